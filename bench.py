@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast-SSA hot path on one MI355X.
+
+Workload (one "step" = one pass of the whole hot path over one series):
+N = 100000, L = 50000, k = 20 -- five sinusoids + exp(-t/50000) trend +
+AR(1) noise (seeded synthetic series; stands in for the long temperature record
+of the paper's Sec. 7.1).  A step embeds the series (spectrum), runs the
+truncated SVD (Golub-Kahan-Lanczos with full reorthogonalization, FFT
+products) and Hankelizes each of the 20 eigentriples into its elementary
+series.  The series is resident in HBM before timing starts.
+
+Prints one JSON line:
+  value       eigentriples/s over the timed region (k * steps / seconds)
+  roofline    the dominant kernel class: algorithmic bytes per launch over its
+              HIP-event-measured launch duration (events recorded on the plan's
+              stream during the timed region), against 8 TB/s HBM
+  cpu_baseline  the FP64 oracle (tier B: Lanczos + direct row products +
+              direct antidiagonal averaging) timed on a bounded sample on this
+              host and scaled to the same number of steps and triples
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, L, K_TRIPLES = 100_000, 50_000, 20
+
+
+def cpu_baseline(f, steps_gpu):
+    """Oracle timed on a bounded sample: K_TRIPLES Lanczos steps (2 direct products
+    each, OpenMP over rows) and one direct rank-1 Hankelization; scaled to the GPU's
+    step count and to K_TRIPLES Hankelizations."""
+    import numpy as np
+
+    import oracle
+    from paper_0911_4498_amd import inputs
+    p0 = inputs.start_vector(L, 4242)
+    t0 = time.perf_counter()
+    s, U, V, steps, _ = oracle.lanczos_svd(f, L, K_TRIPLES, p0, d_max=K_TRIPLES, check_every=10**6)
+    t1 = time.perf_counter()
+    t_step = (t1 - t0) / max(steps, 1)
+    t2 = time.perf_counter()
+    oracle.rank1_hankelize(float(s[0]), U[:, 0], V[:, 0])
+    t_hank = time.perf_counter() - t2
+    est = steps_gpu * t_step + K_TRIPLES * t_hank
+    return {
+        "value": K_TRIPLES / est,
+        "unit": "eigentriples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"tier-B oracle: {steps} Lanczos steps ({2 * steps} direct products, {t_step:.3f} s/step) "
+                   f"+ 1 direct rank-1 Hankelization ({t_hank:.2f} s) at N={N}, L={L}; scaled to "
+                   f"{steps_gpu} steps and {K_TRIPLES} Hankelizations"),
+        "sample_seconds": round(t1 - t0 + t_hank, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X; "
+              "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0911_4498_amd import inputs, ssa
+    if not os.path.exists(ssa.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    f_np = inputs.c2_series(N)
+    f = torch.tensor(f_np, device=dev)
+    plan = ssa.Plan(N, L, K_TRIPLES, device=dev)
+    groups = [[i] for i in range(K_TRIPLES)]
+    steps_seen = []
+
+    def step():
+        s, U, V, info = plan.truncated_svd(f, K_TRIPLES)
+        plan.reconstruct(s, U, V, groups)
+        steps_seen.append(info.steps)
+        return info
+
+    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region without event timing (for reference)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    # timed region: every kernel launch bracketed by HIP events on the plan's stream
+    plan.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile_enable(False)
+    print(f"# timed {args.steps} steps: {t_timed:.4f} s (events on), {t_plain:.4f} s (events off)",
+          file=sys.stderr, flush=True)
+
+    lanczos_classes = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update")
+    dom = max(lanczos_classes + ("ritz", "recon_pass2", "recon_pass1", "recon_pass3"), key=lambda c: prof[c][1])
+    n_l, ms_l, b_l = prof[dom]
+    achieved = (b_l / n_l) / (ms_l / n_l / 1e3) / 1e9 if n_l and ms_l > 0 else 0.0
+    total_bytes = sum(v[2] for v in prof.values())
+    d_mean = float(np.mean(steps_seen[-args.steps:]))
+    for name, (n, ms, b) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        if n:
+            print(f"#   {name:12s} launches={n:6d} time={ms:9.3f} ms  avg={1e3 * ms / n:8.2f} us  "
+                  f"alg={b / 1e9:8.3f} GB  {b / max(ms, 1e-9) / 1e6:8.1f} GB/s", file=sys.stderr)
+
+    out = {
+        "metric": "eigentriples/s (N=1e5, L=N/2, k=20)",
+        "value": K_TRIPLES * args.steps / t_timed,
+        "unit": "eigentriples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_timed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "dtype_detail": "FP32 FFTs, products and stored Lanczos vectors; FP64 Lanczos scalars, "
+                        "Gram-Schmidt inner products and small bidiagonal SVD",
+        "data": "synthetic",
+        "config": {"workload": "single long series: N=100000, L=50000, k=20, 5 sinusoids + exp trend + "
+                               "AR(1) noise (seed 1002); truncated SVD + 20 elementary reconstructions",
+                   "N": N, "L": L, "k": K_TRIPLES, "parallelism": "single GPU"},
+        "value_events_off": K_TRIPLES * args.steps / t_plain,
+        "lanczos_steps": d_mean,
+        "matvecs_per_s": 2.0 * sum(steps_seen[-args.steps:]) / t_timed,
+        "hbm_gb_s_algorithmic": total_bytes / t_timed / 1e9,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": 1e3 * ms_l / max(n_l, 1),
+            "alg_bytes_per_launch": b_l / max(n_l, 1),
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(f_np, int(round(d_mean)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

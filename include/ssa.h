@@ -1,0 +1,203 @@
+/*
+ * ssa.h -- C ABI of the MI355X (gfx950) fast Basic SSA library.
+ *
+ * Method: Korobeynikov, "Computation- and Space-Efficient Implementation of
+ * SSA".  Given a real series F = (f_1..f_N) and a window 1 < L < N
+ * (Sec. 2), the library computes the k leading singular triples
+ * (sigma_i, u_i, v_i) of the L x K trajectory matrix X (K = N - L + 1,
+ * X[i][j] = f_{i+j}, Sec. 2.1) by Golub-Kahan-Lanczos bidiagonalization
+ * (Sec. 3.1, Algorithm 1) with full reorthogonalization (Sec. 3.2.2), where
+ * every product X v and X^T u is a circular convolution of the series
+ * computed by FFT (Sec. 4, Algorithms 2 and 3) so X is never formed; and it
+ * turns groups of triples back into series by FFT rank-1 Hankelization
+ * (Sec. 5, Algorithm 4; Sec. 2.3-2.4 for grouping / diagonal averaging).
+ *
+ * Conventions shared by every entry point:
+ *  - Indices are 0-based.  Device pointers ("_dev") are HIP device memory on
+ *    the current device, owned by the caller; the library never allocates
+ *    device memory.  Host pointers are ordinary host memory.
+ *  - Work is enqueued on the stream given to ssa_plan_bind, in call order.
+ *    ssa_truncated_svd returns after its result is complete (it needs the
+ *    Lanczos scalars on the host to decide when to stop); the other calls
+ *    return as soon as their work is enqueued.
+ *  - A plan (and its workspace) may be used by one stream at a time.
+ *    Distinct plans are independent.
+ *  - Return values: 0 success; positive = warning, results written;
+ *    negative = error, nothing enqueued (argument errors are detected
+ *    before any work is enqueued).
+ *  - Floating point: series input FP64; FFTs, matvecs and stored Lanczos
+ *    vectors FP32; Lanczos scalars (alpha, beta), reorthogonalization inner
+ *    products, norms and the small bidiagonal SVD FP64.
+ */
+#ifndef SSA_H
+#define SSA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssa_plan_s* ssa_plan;
+
+enum ssa_status {
+    SSA_OK = 0,
+    SSA_WARN_NOT_CONVERGED = 1, /* Krylov dimension cap reached before the stopping rule  */
+    SSA_EINVAL = -1,            /* invalid argument (sizes, null pointers, group members) */
+    SSA_ENOMEM = -2,            /* workspace missing or smaller than required             */
+    SSA_ENONFINITE = -3,        /* the series holds NaN or Inf                            */
+    SSA_EDEVICE = -4,           /* a HIP runtime call failed                              */
+    SSA_EMISMATCH = -5,         /* N or L differ from the plan                            */
+    SSA_ESTATE = -6             /* call order violated (e.g. matvec before embed)         */
+};
+
+/* Solver options; zero-initialized fields take the defaults shown. */
+typedef struct {
+    int d_max;              /* Krylov dimension cap (Sec. 3.3, d); default min(L,K,8k+32,1024) */
+    int check_every;        /* Lanczos steps between stopping tests; default 4                 */
+    double tol;             /* stop when every residual bound <= tol * max(omega_i, 1e-5 omega_1)
+                               and the k Ritz values moved < 10 tol relative; default 1e-8   */
+    unsigned long long seed;/* seed of the random start vector p_0 (Algorithm 1); default 1    */
+} ssa_opts;
+
+/* Per-solve report, filled by ssa_truncated_svd. */
+typedef struct {
+    int steps;         /* Lanczos steps d whose bidiagonal B_d gave the result               */
+    int converged;     /* 1 if the stopping rule held, 0 if d_max was reached                */
+    int restarts;      /* vanishing alpha/beta replaced by fresh random directions           */
+    int dgks_passes;   /* second Gram-Schmidt passes triggered by the DGKS criterion          */
+    double resid[64];  /* residual bounds alpha_{d+1} |P[d+1,i]| of the first min(k,64) triples */
+} ssa_info;
+
+/* Sizes chosen by a plan (reported for tests and benchmarks). */
+typedef struct {
+    long long N, L, K;  /* as requested (L > K is accepted; it is solved transposed)   */
+    long long M;        /* FFT length: even, >= N (any M >= N is exact, Sec. 4.3)        */
+    long long M1, M2;   /* M/2 = M1 * M2, the two passes of the half-length complex FFT */
+    int d_max, k_max;
+    size_t workspace_bytes;
+} ssa_plan_desc;
+
+/*
+ * ssa_embed_plan -- Sec. 2.1 / Sec. 4.3: size everything for a series of
+ * length N and window L, solving for at most k_max triples.
+ *   N > 2, 1 < L < N, 1 <= k_max <= min(L, K); opts may be NULL.
+ *   *workspace_bytes receives the device workspace size the plan needs.
+ *   *out receives a host-side plan object (free with ssa_plan_destroy).
+ * Errors: SSA_EINVAL (sizes, null out pointers).
+ */
+int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts,
+                   size_t* workspace_bytes, ssa_plan* out);
+
+/*
+ * ssa_plan_bind -- attach caller-owned device workspace (>= workspace_bytes,
+ * 256-byte aligned) and a HIP stream (hipStream_t passed as void*, NULL =
+ * the default stream).  Errors: SSA_EINVAL (null plan/workspace, bad
+ * alignment), SSA_ENOMEM (too small).
+ */
+int ssa_plan_bind(ssa_plan plan, void* workspace_dev, size_t bytes, void* hip_stream);
+
+/*
+ * ssa_embed -- Algorithm 2, steps 1-2 (done once per series): the spectrum
+ * of the zero-padded series, stored in the workspace as the operator that
+ * every later X v / X^T u applies.  series_dev: N doubles.
+ * Errors: SSA_EINVAL, SSA_ENOMEM (unbound plan).
+ */
+int ssa_embed(ssa_plan plan, const double* series_dev);
+
+/*
+ * ssa_matvec -- Algorithms 2 / 3: y = X x (transpose = 0; x has K entries,
+ * y gets L) or y = X^T x (transpose = 1; x has L entries, y gets K), as an
+ * FFT convolution with the embedded series.  FP32 vectors, device memory.
+ * Errors: SSA_EINVAL, SSA_ESTATE (no ssa_embed yet).
+ */
+int ssa_matvec(ssa_plan plan, int transpose, const float* x_dev, float* y_dev);
+
+/*
+ * ssa_truncated_svd -- Sec. 2.2 via Sec. 3 + 4: the k leading singular
+ * triples of X, sigma descending.
+ *   series_dev: N doubles (device).  N, L must equal the plan's.
+ *   sigma_dev: k doubles; U_dev: L x k floats column-major (u_i at
+ *   U_dev + i*L); V_dev: K x k floats column-major (v_i at V_dev + i*K).
+ *   info: optional host struct (may be NULL).
+ * Returns SSA_OK, SSA_WARN_NOT_CONVERGED, or an error: SSA_EINVAL
+ * (k outside [1, k_max]), SSA_EMISMATCH, SSA_ENOMEM (unbound plan),
+ * SSA_ENONFINITE (series holds NaN/Inf; outputs untouched), SSA_EDEVICE.
+ * Synchronizes the plan's stream before returning.
+ */
+int ssa_truncated_svd(ssa_plan plan, const double* series_dev, long long N, long long L, int k,
+                      double* sigma_dev, float* U_dev, float* V_dev, ssa_info* info);
+
+/*
+ * ssa_reconstruct -- Sec. 2.3-2.4 with Sec. 5: for each group g of triple
+ * indices (CSR on the host: group_offsets[m+1], group_members[]), the
+ * diagonal average of sum_{i in g} sigma_i u_i v_i^T, computed as FFT linear
+ * convolutions of u_i and v_i scaled by 1/(number of entries on each
+ * antidiagonal).  Groups may overlap; each is an independent linear map.
+ *   sigma_dev, U_dev, V_dev: as returned by ssa_truncated_svd with k triples.
+ *   out_dev: m x N floats, row-major (group g at out_dev + g*N).
+ * Errors: SSA_EINVAL (k outside [1, k_max], member outside [0,k), member
+ * repeated within a group, m < 1), SSA_ENOMEM (unbound plan).
+ */
+int ssa_reconstruct(ssa_plan plan, const double* sigma_dev, const float* U_dev,
+                    const float* V_dev, int k, const int* group_offsets,
+                    const int* group_members, int m, float* out_dev);
+
+/* ssa_plan_describe -- copy the plan's sizes into *desc. */
+int ssa_plan_describe(ssa_plan plan, ssa_plan_desc* desc);
+
+/* ssa_plan_destroy -- free the host-side plan (the workspace stays the caller's). */
+void ssa_plan_destroy(ssa_plan plan);
+
+/*
+ * ssa_bidiag_ritz -- host utility (no device work): singular values of the
+ * (d+1) x d lower bidiagonal B_d of Sec. 3.1 (alpha[1..d] on the diagonal,
+ * beta[2..d+1] below it; arrays indexed as in Algorithm 1, alpha[d+1] used
+ * for the residual bound of eq. lbdiagm2).  Writes the k largest values to
+ * omega (descending); if resid is given, their residual bounds
+ * alpha_{d+1} |P[d,i]|; if P and Q are given, the singular vectors
+ * (P: (d+1) x k row-major, Q: d x k row-major).  This is the routine the
+ * solver uses for its stopping test and Ritz vectors.
+ */
+int ssa_bidiag_ritz(const double* alpha, const double* beta, int d, int k, double* omega,
+                    double* resid, double* P, double* Q);
+
+/*
+ * Profiling.  Kernel classes of the hot path, for ssa_profile_read:
+ *   PASS1/PASS2/PASS3: the three FFT passes of one product X v or X^T u
+ *   (Algorithms 2/3); DOTS/REDUCE/UPDATE: the Gram-Schmidt projection,
+ *   coefficient reduction and update (Sec. 3.2.2); RITZ: Ritz vectors;
+ *   RECON1/2/3: the FFT passes of the grouped rank-1 Hankelization
+ *   (Algorithm 4); EMBED: the spectrum of the series (Algorithm 2, steps 1-2).
+ */
+enum ssa_prof_class {
+    SSA_PROF_PASS1 = 0, SSA_PROF_PASS2, SSA_PROF_PASS3, SSA_PROF_DOTS, SSA_PROF_REDUCE,
+    SSA_PROF_UPDATE, SSA_PROF_RITZ, SSA_PROF_RECON1, SSA_PROF_RECON2, SSA_PROF_RECON3,
+    SSA_PROF_EMBED, SSA_PROF_NCLASSES
+};
+
+/*
+ * ssa_profile_enable -- 1: from now on bracket every kernel launch of the plan
+ * with HIP events on the plan's stream (adds two event records per launch);
+ * 0: stop.  Either way the counters are cleared (the stream is synchronized
+ * first).  Errors: SSA_EINVAL.
+ */
+int ssa_profile_enable(ssa_plan plan, int enable);
+
+/*
+ * ssa_profile_read -- synchronize the plan's stream and report, for kernel
+ * class cls since the last ssa_profile_enable: the number of launches, the
+ * summed event-measured duration in milliseconds (-1 if timing was off) and
+ * the summed algorithmic HBM bytes (the bytes the method must move: vectors
+ * read and written, spectra, basis columns).  Errors: SSA_EINVAL, SSA_EDEVICE.
+ */
+int ssa_profile_read(ssa_plan plan, int cls, long long* launches, double* ms, double* bytes);
+
+/* ssa_status_str -- static text for a status code. */
+const char* ssa_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSA_H */

@@ -1,0 +1,652 @@
+// api.cpp -- the C ABI of include/ssa.h: plans, workspace layout, the Lanczos
+// driver and the reconstruction.  Every arithmetic step on vectors runs in the
+// kernels of kernels.hip; the host only sizes, launches, and solves the small
+// (d+1) x d bidiagonal problem that decides when to stop (small_svd.cpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "ssa.h"
+#include "ssa_internal.h"
+
+using namespace ssa;
+
+namespace {
+
+constexpr int kMaxFactor = 4096;   // longest single-workgroup FFT (one LDS row)
+constexpr int kMaxDmax = 1024;     // Krylov dimension cap supported by the kernels
+constexpr double kBreakdownTol = 1e-6;  // relative size of a vanishing alpha/beta (FP32 products)
+constexpr double kResidFloor = 1e-5;    // residuals of omega_i < 1e-5 omega_1 are judged against 1e-5 omega_1
+constexpr int kMaxGroupBatch = 64;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool smooth7(long long n) {
+    if (n < 1) return false;
+    for (long long p : {2LL, 3LL, 5LL, 7LL})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Smallest M' >= ceil(N/2) with a split M' = M1 * M2, both 7-smooth and
+// <= kMaxFactor; among the splits of that M' the most balanced one (M1 <= M2).
+bool choose_fft(long long N, long long& Mp, int& M1, int& M2) {
+    for (long long mp = (N + 1) / 2; mp <= (long long)kMaxFactor * kMaxFactor; ++mp) {
+        if (!smooth7(mp)) continue;
+        int best1 = 0;
+        for (long long a = 1; a * a <= mp; ++a) {
+            if (mp % a) continue;
+            const long long b = mp / a;
+            if (b > kMaxFactor || a > kMaxFactor) continue;
+            best1 = (int)a;  // largest a <= sqrt(mp) that works
+        }
+        if (best1 > 0) {
+            Mp = mp;
+            M1 = best1;
+            M2 = (int)(mp / best1);
+            return true;
+        }
+    }
+    return false;
+}
+
+FftStages make_stages(int n) {
+    FftStages st{};
+    st.n = n;
+    int m = n;
+    while (m % 8 == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = 8; m /= 8; }
+    while (m % 4 == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = 4; m /= 4; }
+    while (m % 2 == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = 2; m /= 2; }
+    for (int p : {3, 5, 7})
+        while (m % p == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = p; m /= p; }
+    return st;
+}
+
+}  // namespace
+
+struct ssa_plan_s {
+    long long N, L, K;  // as requested
+    int transposed;     // L > K: solved for X^T (window K)
+    long long Li, Ki;   // internal window / lag count, Li <= Ki
+    int k_max, d_max, check_every;
+    double tol;
+    unsigned long long seed;
+    ConvGeom g;
+    long long ldU, ldV;
+    int pstride, nchunks_max;
+    size_t ws_bytes;
+    size_t o_ab, o_tw1, o_tw2, o_twlo, o_twhi, o_t1, o_t2, o_U, o_V, o_r, o_part, o_h, o_sc, o_alpha,
+        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2;
+    size_t grp_ints;
+    // bound state
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int bound = 0, embedded = 0;
+    // pinned host staging
+    double* h_scal = nullptr;   // alpha (d_max+3) | beta (d_max+3) | P | Q | sigma
+    double* h_flag = nullptr;
+    int* h_grp = nullptr;
+    hipEvent_t grp_done = nullptr;
+    std::vector<double> work;
+    // optional per-kernel-class timing (HIP events around each launch)
+    int prof_on = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pairs[SSA_PROF_NCLASSES];
+    double prof_bytes[SSA_PROF_NCLASSES] = {};
+    long long prof_count[SSA_PROF_NCLASSES] = {};
+};
+
+namespace {
+
+template <typename T>
+T* at(ssa_plan p, size_t off) {
+    return reinterpret_cast<T*>(p->ws + off);
+}
+
+void layout(ssa_plan p) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + bytes, 256);
+        return r;
+    };
+    const ConvGeom& g = p->g;
+    const long long S = 1LL << g.tw_shift;
+    p->o_ab = take(sizeof(float4) * (size_t)g.Mp);
+    p->o_tw1 = take(sizeof(float2) * (size_t)g.M1);
+    p->o_tw2 = take(sizeof(float2) * (size_t)g.M2);
+    p->o_twlo = take(sizeof(float2) * (size_t)S);
+    p->o_twhi = take(sizeof(float2) * (size_t)((g.Mp + S - 1) / S));
+    p->o_t1 = take(sizeof(float2) * (size_t)g.Mp);
+    p->o_t2 = take(sizeof(float2) * (size_t)g.Mp);
+    p->o_U = take(sizeof(float) * (size_t)(p->d_max + 1) * p->ldU);
+    p->o_V = take(sizeof(float) * (size_t)(p->d_max + 1) * p->ldV);
+    p->o_r = take(sizeof(float) * (size_t)std::max(p->ldU, p->ldV));
+    p->o_part = take(sizeof(double) * (size_t)p->nchunks_max * p->pstride);
+    p->o_h = take(sizeof(double) * (size_t)(p->d_max + 2));
+    p->o_sc = take(sizeof(double) * 8);
+    p->o_alpha = take(sizeof(double) * (size_t)(p->d_max + 3));
+    p->o_beta = take(sizeof(double) * (size_t)(p->d_max + 3));
+    p->o_state = take(sizeof(double) * 8);
+    p->o_P = take(sizeof(double) * (size_t)(p->d_max + 1) * p->k_max);
+    p->o_Q = take(sizeof(double) * (size_t)p->d_max * p->k_max);
+    p->o_flag = take(sizeof(int) * 64);
+    p->grp_ints = (size_t)(kMaxGroupBatch + 1) + (size_t)kMaxGroupBatch * p->k_max;
+    p->o_grp = take(sizeof(int) * p->grp_ints);
+    p->o_rt1 = take(sizeof(float2) * (size_t)g.Mp * 2 * p->k_max);
+    p->o_rt2 = take(sizeof(float2) * (size_t)g.Mp * kMaxGroupBatch);
+    p->ws_bytes = o;
+}
+
+ConvGeom bound_geom(ssa_plan p) {
+    ConvGeom g = p->g;
+    g.tw1 = at<float2>(p, p->o_tw1);
+    g.tw2 = at<float2>(p, p->o_tw2);
+    g.tw_lo = at<float2>(p, p->o_twlo);
+    g.tw_hi = at<float2>(p, p->o_twhi);
+    return g;
+}
+
+hipEvent_t next_event(ssa_plan p) {
+    if (p->ev_next == p->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
+    }
+    return p->ev_pool[p->ev_next++];
+}
+
+// Brackets one launch of kernel class `cls`; `bytes` is the launch's
+// algorithmic HBM traffic (what the method must read and write).
+struct ProfScope {
+    ssa_plan p;
+    int cls;
+    double bytes;
+    hipEvent_t e0 = nullptr;
+    ProfScope(ssa_plan p_, int cls_, double bytes_) : p(p_), cls(cls_), bytes(bytes_) {
+        if (p->prof_on) {
+            e0 = next_event(p);
+            if (e0) (void)hipEventRecord(e0, p->stream);
+        }
+    }
+    ~ProfScope() {
+        p->prof_bytes[cls] += bytes;
+        p->prof_count[cls] += 1;
+        if (p->prof_on && e0) {
+            hipEvent_t e1 = next_event(p);
+            if (e1) {
+                (void)hipEventRecord(e1, p->stream);
+                p->prof_pairs[cls].push_back({e0, e1});
+            }
+        }
+    }
+};
+
+#define SSA_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return SSA_EDEVICE;      \
+    } while (0)
+
+// One convolution with the embedded series: out[t] = y[n_in-1+t] - coef*prev[t].
+int convolve(ssa_plan p, const ConvGeom& g, const float* x, long long n_in, float* out, const float* prev,
+             const double* coef) {
+    hipStream_t s = p->stream;
+    P1In in{};
+    in.x = x;
+    in.n_in = n_in;
+    const double mp = (double)g.Mp;
+    {
+        ProfScope ps(p, SSA_PROF_PASS1, 4.0 * n_in + 8.0 * mp);
+        SSA_TRY(launch_pass1(g, IN_REV, in, 1, at<float2>(p, p->o_t1), s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_PASS2, 32.0 * mp);
+        SSA_TRY(launch_pass2_matvec(g, at<float4>(p, p->o_ab), at<float2>(p, p->o_t1), at<float2>(p, p->o_t2), s));
+    }
+    P3Out o{};
+    o.out = out;
+    o.n_in = n_in;
+    o.n_out = p->N + 1 - n_in;
+    o.prev = prev;
+    o.coef = coef;
+    {
+        ProfScope ps(p, SSA_PROF_PASS3, 8.0 * mp + 4.0 * o.n_out * (prev ? 2.0 : 1.0));
+        SSA_TRY(launch_pass3(g, OUT_SLICE, at<float2>(p, p->o_t2), o, 1, s));
+    }
+    return SSA_OK;
+}
+
+// Classical Gram-Schmidt of the residual r (length n) against `ncols` basis
+// columns, then the normalized vector becomes basis column `ncols`; the B
+// entry goes to *coef_out.
+int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long n, double* coef_out, int track,
+                   unsigned long long ctr) {
+    hipStream_t s = p->stream;
+    float* r = at<float>(p, p->o_r);
+    double* part = at<double>(p, p->o_part);
+    double* h = at<double>(p, p->o_h);
+    double* sc = at<double>(p, p->o_sc);
+    {
+        ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)n * (ncols + 1));
+        SSA_TRY(launch_cgs_dots(basis, ld, ncols, r, n, part, p->pstride, s));
+    }
+    ReduceArgs a{};
+    a.part = part;
+    a.nchunks = (int)((n + kDotsRows - 1) / kDotsRows);
+    a.pstride = p->pstride;
+    a.ncols = ncols;
+    a.r = r;
+    a.n = n;
+    a.basis = basis;
+    a.ld = ld;
+    a.h = h;
+    a.coef_out = coef_out;
+    a.scale_out = sc;
+    a.state = at<double>(p, p->o_state);
+    a.seed = p->seed;
+    a.stream_ctr = ctr;
+    a.track = track;
+    a.full = ncols >= n ? 1 : 0;
+    a.tol_bd = kBreakdownTol;
+    {
+        ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)a.nchunks * (ncols + 1));
+        SSA_TRY(launch_cgs_reduce(a, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_UPDATE, 4.0 * (double)n * (ncols + 2));
+        SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, basis + (long long)ncols * ld, n, s));
+    }
+    return SSA_OK;
+}
+
+int check_series(ssa_plan p, const double* series_dev) {
+    double* dflag = at<double>(p, p->o_flag);
+    SSA_TRY(launch_fill_zero(dflag, 1, p->stream));
+    SSA_TRY(launch_check_finite(series_dev, p->N, dflag, p->stream));
+    SSA_TRY(hipMemcpyAsync(p->h_flag, dflag, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    SSA_TRY(hipStreamSynchronize(p->stream));
+    return *p->h_flag != 0.0 ? SSA_ENONFINITE : SSA_OK;
+}
+
+int do_embed(ssa_plan p, const double* series_dev) {
+    const int rc = check_series(p, series_dev);
+    if (rc != SSA_OK) return rc;
+    const ConvGeom g = bound_geom(p);
+    P1In in{};
+    in.f = series_dev;
+    in.N = p->N;
+    {
+        ProfScope ps(p, SSA_PROF_EMBED, 8.0 * p->N + 8.0 * g.Mp);
+        SSA_TRY(launch_pass1(g, IN_SERIES, in, 1, at<float2>(p, p->o_t1), p->stream));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_EMBED, 24.0 * g.Mp);
+        SSA_TRY(launch_pass2_embed(g, at<float2>(p, p->o_t1), at<float4>(p, p->o_ab), p->stream));
+    }
+    p->embedded = 1;
+    return SSA_OK;
+}
+
+std::once_flag g_attr_once;
+hipError_t g_attr_err = hipSuccess;
+
+}  // namespace
+
+extern "C" {
+
+int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, size_t* workspace_bytes,
+                   ssa_plan* out) {
+    if (!out || !workspace_bytes) return SSA_EINVAL;
+    *out = nullptr;
+    if (N <= 2 || L <= 1 || L >= N) return SSA_EINVAL;
+    const long long K = N - L + 1;
+    const long long r = std::min(L, K);
+    if (k_max < 1 || k_max > r || k_max > 256) return SSA_EINVAL;
+    ssa_plan p = new (std::nothrow) ssa_plan_s();
+    if (!p) return SSA_EINVAL;
+    p->N = N;
+    p->L = L;
+    p->K = K;
+    p->transposed = L > K ? 1 : 0;
+    p->Li = std::min(L, K);
+    p->Ki = std::max(L, K);
+    p->k_max = k_max;
+    int d_max = opts && opts->d_max > 0 ? opts->d_max : 8 * k_max + 32;
+    d_max = (int)std::min<long long>({(long long)d_max, r, (long long)kMaxDmax});
+    if (d_max < k_max) d_max = k_max;
+    p->d_max = d_max;
+    p->check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
+    p->tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
+    p->seed = opts && opts->seed ? opts->seed : 1ULL;
+    long long Mp;
+    int M1, M2;
+    if (!choose_fft(N, Mp, M1, M2)) {
+        delete p;
+        return SSA_EINVAL;
+    }
+    ConvGeom& g = p->g;
+    g.M1 = M1;
+    g.M2 = M2;
+    g.Mp = Mp;
+    g.M = 2 * Mp;
+    int cb = (int)std::min<long long>({16LL, 8192LL / M1, ((long long)M2 + 63) / 64});
+    g.CB = std::max(1, cb);
+    int shift = 0;
+    while ((1LL << (2 * shift)) < Mp) ++shift;
+    g.tw_shift = shift;
+    g.st1 = make_stages(M1);
+    g.st2 = make_stages(M2);
+    p->ldU = (long long)align_up((size_t)p->Li, 64);
+    p->ldV = (long long)align_up((size_t)p->Ki, 64);
+    p->pstride = d_max + 2;
+    p->nchunks_max = (int)((p->Ki + kDotsRows - 1) / kDotsRows);
+    layout(p);
+    p->work.resize(bidiag_work_doubles(d_max) + 16);
+    *workspace_bytes = p->ws_bytes;
+    *out = p;
+    return SSA_OK;
+}
+
+int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_stream) {
+    if (!p || !workspace_dev) return SSA_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
+    if (bytes < p->ws_bytes) return SSA_ENOMEM;
+    std::call_once(g_attr_once, [] { g_attr_err = set_kernel_attributes(); });
+    if (g_attr_err != hipSuccess) return SSA_EDEVICE;
+    if (!p->h_scal) {
+        const size_t nd = 2 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->k_max + p->k_max + 8;
+        if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * nd, hipHostMallocDefault) != hipSuccess)
+            return SSA_EDEVICE;
+        if (hipHostMalloc((void**)&p->h_flag, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
+            return SSA_EDEVICE;
+        if (hipHostMalloc((void**)&p->h_grp, sizeof(int) * p->grp_ints, hipHostMallocDefault) != hipSuccess)
+            return SSA_EDEVICE;
+        if (hipEventCreateWithFlags(&p->grp_done, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
+    }
+    p->ws = static_cast<char*>(workspace_dev);
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->bound = 1;
+    p->embedded = 0;
+    const ConvGeom g = bound_geom(p);
+    SSA_TRY(launch_tables(g, const_cast<float2*>(g.tw1), const_cast<float2*>(g.tw2), const_cast<float2*>(g.tw_lo),
+                          const_cast<float2*>(g.tw_hi), p->stream));
+    return SSA_OK;
+}
+
+int ssa_embed(ssa_plan p, const double* series_dev) {
+    if (!p || !series_dev) return SSA_EINVAL;
+    if (!p->bound) return SSA_ENOMEM;
+    return do_embed(p, series_dev);
+}
+
+int ssa_matvec(ssa_plan p, int transpose, const float* x_dev, float* y_dev) {
+    if (!p || !x_dev || !y_dev) return SSA_EINVAL;
+    if (!p->bound) return SSA_ENOMEM;
+    if (!p->embedded) return SSA_ESTATE;
+    // X x: x has K entries; X^T x: x has L entries (user's L, K)
+    const long long n_in = transpose ? p->L : p->K;
+    return convolve(p, bound_geom(p), x_dev, n_in, y_dev, nullptr, nullptr);
+}
+
+int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long long L, int k, double* sigma_dev,
+                      float* U_dev, float* V_dev, ssa_info* info) {
+    if (!p || !series_dev || !sigma_dev || !U_dev || !V_dev) return SSA_EINVAL;
+    if (k < 1 || k > p->k_max) return SSA_EINVAL;
+    if (N != p->N || L != p->L) return SSA_EMISMATCH;
+    if (!p->bound) return SSA_ENOMEM;
+    int rc = do_embed(p, series_dev);
+    if (rc != SSA_OK) return rc;
+    const ConvGeom g = bound_geom(p);
+    hipStream_t s = p->stream;
+    const long long Li = p->Li, Ki = p->Ki;
+    float* U = at<float>(p, p->o_U);
+    float* V = at<float>(p, p->o_V);
+    float* r = at<float>(p, p->o_r);
+    double* alpha = at<double>(p, p->o_alpha);
+    double* beta = at<double>(p, p->o_beta);
+    SSA_TRY(launch_fill_zero(alpha, p->d_max + 3, s));
+    SSA_TRY(launch_fill_zero(beta, p->d_max + 3, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
+
+    // Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0
+    SSA_TRY(launch_start_vector(r, Li, p->seed, s));
+    rc = orthonormalize(p, U, p->ldU, 0, Li, beta + 1, 0, 1);
+    if (rc != SSA_OK) return rc;
+
+    const int d_cap = (int)std::min<long long>(p->d_max, std::min(Li, Ki));
+    double* h_alpha = p->h_scal;
+    double* h_beta = p->h_scal + (p->d_max + 3);
+    double* h_P = h_beta + (p->d_max + 3);
+    double* h_Q = h_P + (size_t)(p->d_max + 1) * p->k_max;
+    double* h_sig = h_Q + (size_t)p->d_max * p->k_max;
+    std::vector<double> w(k), wprev(k), res(k);
+    bool have_prev = false, converged = false;
+    int d = 0;
+    for (int j = 1;; ++j) {
+        // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
+        rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, Li, r,
+                      j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
+        if (rc != SSA_OK) return rc;
+        rc = orthonormalize(p, V, p->ldV, j - 1, Ki, alpha + j, 1, 2ULL * j);
+        if (rc != SSA_OK) return rc;
+        // stopping test on B_{j-1}, which needs alpha_j for its residual bound
+        const int jj = j - 1;
+        if (jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
+            SSA_TRY(hipMemcpyAsync(h_alpha, alpha, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipMemcpyAsync(h_beta, beta, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipStreamSynchronize(s));
+            bidiag_ritz_values(h_alpha, h_beta, jj, k, w.data(), res.data(), p->work.data());
+            bool ok = have_prev;
+            for (int i = 0; i < k && ok; ++i) {
+                const double scale = std::max(w[i], kResidFloor * w[0]);
+                if (res[i] > p->tol * scale) ok = false;
+                if (std::fabs(w[i] - wprev[i]) > 10.0 * p->tol * scale) ok = false;
+            }
+            if (jj >= std::min(Li, Ki)) ok = true;  // Krylov space exhausted: B is exact
+            wprev = w;
+            have_prev = true;
+            if (ok || jj >= d_cap) {
+                converged = ok;
+                d = jj;
+                break;
+            }
+        }
+        // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
+        rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, Ki, r, U + (long long)(j - 1) * p->ldU, alpha + j);
+        if (rc != SSA_OK) return rc;
+        rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
+        if (rc != SSA_OK) return rc;
+    }
+
+    // Ritz triples of B_d: sigma, U_{d+1} P, V_d Q
+    bidiag_ritz_vectors(h_alpha, h_beta, d, k, h_sig, h_P, h_Q, p->work.data());
+    double* dP = at<double>(p, p->o_P);
+    double* dQ = at<double>(p, p->o_Q);
+    SSA_TRY(hipMemcpyAsync(dP, h_P, sizeof(double) * (size_t)(d + 1) * k, hipMemcpyHostToDevice, s));
+    SSA_TRY(hipMemcpyAsync(dQ, h_Q, sizeof(double) * (size_t)d * k, hipMemcpyHostToDevice, s));
+    SSA_TRY(hipMemcpyAsync(sigma_dev, h_sig, sizeof(double) * k, hipMemcpyHostToDevice, s));
+    float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
+    float* Vo = p->transposed ? U_dev : V_dev;
+    {
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (d + 1 + k) * ((k + 15) / 16));
+        SSA_TRY(launch_ritz(U, p->ldU, d + 1, dP, k, Uo, Li, Li, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (d + k) * ((k + 15) / 16));
+        SSA_TRY(launch_ritz(V, p->ldV, d, dQ, k, Vo, Ki, Ki, s));
+    }
+    double st[3] = {0, 0, 0};
+    SSA_TRY(hipMemcpyAsync(h_sig + k, at<double>(p, p->o_state), sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    SSA_TRY(hipStreamSynchronize(s));
+    std::memcpy(st, h_sig + k, sizeof(st));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->steps = d;
+        info->converged = converged ? 1 : 0;
+        info->restarts = (int)st[1];
+        info->dgks_passes = (int)st[2];
+        for (int i = 0; i < k && i < 64; ++i) info->resid[i] = res[i];
+    }
+    return converged ? SSA_OK : SSA_WARN_NOT_CONVERGED;
+}
+
+int ssa_reconstruct(ssa_plan p, const double* sigma_dev, const float* U_dev, const float* V_dev, int k,
+                    const int* group_offsets, const int* group_members, int m, float* out_dev) {
+    if (!p || !sigma_dev || !U_dev || !V_dev || !group_offsets || !out_dev) return SSA_EINVAL;
+    if (k < 1 || k > p->k_max || m < 1) return SSA_EINVAL;
+    if (!p->bound) return SSA_ENOMEM;
+    if (group_offsets[0] != 0) return SSA_EINVAL;
+    std::vector<char> seen(k);
+    for (int gi = 0; gi < m; ++gi) {
+        const int b = group_offsets[gi], e = group_offsets[gi + 1];
+        if (e < b || e - b > k) return SSA_EINVAL;
+        if (e > b && !group_members) return SSA_EINVAL;
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int t = b; t < e; ++t) {
+            const int i = group_members[t];
+            if (i < 0 || i >= k || seen[i]) return SSA_EINVAL;
+            seen[i] = 1;
+        }
+    }
+    const ConvGeom g = bound_geom(p);
+    hipStream_t s = p->stream;
+    const long long N = p->N, L = p->L, K = p->K;
+    float2* T1 = at<float2>(p, p->o_rt1);
+    float2* T2 = at<float2>(p, p->o_rt2);
+    // spectra of every u_i and v_i (pass 1; pass 2 transforms the rows per group)
+    P1In in{};
+    in.U = U_dev;
+    in.ldu = L;
+    in.lenu = L;
+    in.V = V_dev;
+    in.ldv = K;
+    in.lenv = K;
+    in.nu = k;
+    {
+        ProfScope ps(p, SSA_PROF_RECON1, 4.0 * (double)k * (L + K) + 16.0 * k * (double)g.Mp);
+        SSA_TRY(launch_pass1(g, IN_VECS, in, 2 * k, T1, s));
+    }
+    int* dgrp = at<int>(p, p->o_grp);
+    for (int g0 = 0; g0 < m; g0 += kMaxGroupBatch) {
+        const int ng = std::min(kMaxGroupBatch, m - g0);
+        // stage this batch's CSR (offsets rebased to 0) through pinned memory
+        SSA_TRY(hipEventSynchronize(p->grp_done));
+        const int base = group_offsets[g0];
+        int nmem = 0;
+        for (int gi = 0; gi <= ng; ++gi) p->h_grp[gi] = group_offsets[g0 + gi] - base;
+        nmem = p->h_grp[ng];
+        for (int t = 0; t < nmem; ++t) p->h_grp[ng + 1 + t] = group_members[base + t];
+        SSA_TRY(hipMemcpyAsync(dgrp, p->h_grp, sizeof(int) * (size_t)(ng + 1 + nmem), hipMemcpyHostToDevice, s));
+        SSA_TRY(hipEventRecord(p->grp_done, s));
+        {
+            ProfScope ps(p, SSA_PROF_RECON2, 16.0 * (double)g.Mp * nmem + 8.0 * (double)g.Mp * ng);
+            SSA_TRY(launch_pass2_recon(g, T1, k, sigma_dev, dgrp, dgrp + ng + 1, 0, ng, T2, s));
+        }
+        P3Out o{};
+        o.out = out_dev + (long long)g0 * N;
+        o.N = N;
+        o.L = L;
+        o.K = K;
+        o.ldo = N;
+        {
+            ProfScope ps(p, SSA_PROF_RECON3, (8.0 * (double)g.Mp + 4.0 * N) * ng);
+            SSA_TRY(launch_pass3(g, OUT_HANKEL, T2, o, ng, s));
+        }
+        {
+            const long long lmin = std::min(L, K);
+            const double ne = lmin <= kEdgeCnt ? (double)N : 2.0 * kEdgeCnt;
+            ProfScope ps(p, SSA_PROF_RECON3, 4.0 * ne * ng);
+            SSA_TRY(launch_recon_edges(sigma_dev, U_dev, L, V_dev, K, dgrp, dgrp + ng + 1, ng, N, L, K,
+                                       out_dev + (long long)g0 * N, N, s));
+        }
+    }
+    return SSA_OK;
+}
+
+int ssa_plan_describe(ssa_plan p, ssa_plan_desc* d) {
+    if (!p || !d) return SSA_EINVAL;
+    d->N = p->N;
+    d->L = p->L;
+    d->K = p->K;
+    d->M = p->g.M;
+    d->M1 = p->g.M1;
+    d->M2 = p->g.M2;
+    d->d_max = p->d_max;
+    d->k_max = p->k_max;
+    d->workspace_bytes = p->ws_bytes;
+    return SSA_OK;
+}
+
+void ssa_plan_destroy(ssa_plan p) {
+    if (!p) return;
+    if (p->grp_done) {
+        (void)hipEventSynchronize(p->grp_done);
+        (void)hipEventDestroy(p->grp_done);
+    }
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->h_scal) (void)hipHostFree(p->h_scal);
+    if (p->h_flag) (void)hipHostFree(p->h_flag);
+    if (p->h_grp) (void)hipHostFree(p->h_grp);
+    delete p;
+}
+
+const char* ssa_status_str(int status) {
+    switch (status) {
+        case SSA_OK: return "ok";
+        case SSA_WARN_NOT_CONVERGED: return "stopping rule not met before the Krylov dimension cap";
+        case SSA_EINVAL: return "invalid argument";
+        case SSA_ENOMEM: return "workspace missing or too small";
+        case SSA_ENONFINITE: return "series holds NaN or Inf";
+        case SSA_EDEVICE: return "HIP runtime error";
+        case SSA_EMISMATCH: return "N or L differ from the plan";
+        case SSA_ESTATE: return "call order violated";
+        default: return "unknown status";
+    }
+}
+
+int ssa_profile_enable(ssa_plan p, int enable) {
+    if (!p) return SSA_EINVAL;
+    if (p->stream || p->bound) (void)hipStreamSynchronize(p->stream);
+    for (int c = 0; c < SSA_PROF_NCLASSES; ++c) {
+        p->prof_pairs[c].clear();
+        p->prof_bytes[c] = 0.0;
+        p->prof_count[c] = 0;
+    }
+    p->ev_next = 0;
+    p->prof_on = enable ? 1 : 0;
+    return SSA_OK;
+}
+
+int ssa_profile_read(ssa_plan p, int cls, long long* launches, double* ms, double* bytes) {
+    if (!p || cls < 0 || cls >= SSA_PROF_NCLASSES) return SSA_EINVAL;
+    if (p->bound && hipStreamSynchronize(p->stream) != hipSuccess) return SSA_EDEVICE;
+    double total = 0.0;
+    for (auto& pr : p->prof_pairs[cls]) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess) return SSA_EDEVICE;
+        total += t;
+    }
+    if (launches) *launches = p->prof_count[cls];
+    if (ms) *ms = p->prof_on ? total : -1.0;
+    if (bytes) *bytes = p->prof_bytes[cls];
+    return SSA_OK;
+}
+
+int ssa_bidiag_ritz(const double* alpha, const double* beta, int d, int k, double* omega, double* resid,
+                    double* P, double* Q) {
+    if (!alpha || !beta || !omega || d < 1 || k < 1) return SSA_EINVAL;
+    std::vector<double> work(bidiag_work_doubles(d) + 16);
+    if (resid) bidiag_ritz_values(alpha, beta, d, k, omega, resid, work.data());
+    if (P && Q) bidiag_ritz_vectors(alpha, beta, d, k, omega, P, Q, work.data());
+    return SSA_OK;
+}
+
+}  // extern "C"

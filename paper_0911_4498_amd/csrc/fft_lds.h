@@ -1,0 +1,212 @@
+// fft_lds.h -- mixed-radix complex FFTs staged in LDS (gfx950, wave64).
+//
+// The DFT of Sec. 4.1 (forward kernel e^{-2 pi i k l / n}, inverse with
+// e^{+2 pi i k l / n} and no 1/n factor -- callers fold the scale into the
+// spectral operator).  Each transform is a Stockham autosort sequence of
+// radix-R stages (R in {2,3,4,5,7,8}), so the output is in natural order
+// without a bit-reversal pass.  One workgroup runs `nseq` independent
+// transforms of length n that sit in LDS at buf + s*sstride.  A stage reads
+// every butterfly's inputs into registers, synchronizes, and writes the
+// outputs back in place, so only one LDS buffer is needed.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ssa {
+
+constexpr int kMaxStages = 16;
+
+struct FftStages {
+    int n;
+    int nstages;
+    int radix[kMaxStages];
+};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// a * e^{DIR i pi/2}: forward (DIR=-1) multiplies by -i, inverse by +i.
+template <int DIR>
+__device__ __forceinline__ float2 rot90(float2 a) {
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <int R>
+struct OddRadix;
+template <>
+struct OddRadix<3> {
+    static __device__ __forceinline__ float c(int q) { return -0.5f; }
+    static __device__ __forceinline__ float s(int q) {
+        return q == 1 ? 0.866025403784438647f : -0.866025403784438647f;
+    }
+};
+template <>
+struct OddRadix<5> {
+    static __device__ __forceinline__ float c(int q) {
+        return (q == 1 || q == 4) ? 0.309016994374947424f : -0.809016994374947424f;
+    }
+    static __device__ __forceinline__ float s(int q) {
+        switch (q) {
+            case 1: return 0.951056516295153572f;
+            case 2: return 0.587785252292473129f;
+            case 3: return -0.587785252292473129f;
+            default: return -0.951056516295153572f;
+        }
+    }
+};
+template <>
+struct OddRadix<7> {
+    static __device__ __forceinline__ float c(int q) {
+        switch (q) {
+            case 1: case 6: return 0.623489801858733531f;
+            case 2: case 5: return -0.222520933956314404f;
+            default: return -0.900968867902419126f;
+        }
+    }
+    static __device__ __forceinline__ float s(int q) {
+        switch (q) {
+            case 1: return 0.781831482468029809f;
+            case 2: return 0.974927912181823607f;
+            case 3: return 0.433883739117558120f;
+            case 4: return -0.433883739117558120f;
+            case 5: return -0.974927912181823607f;
+            default: return -0.781831482468029809f;
+        }
+    }
+};
+
+// In-register DFT of length R: y_m = sum_r x_r e^{DIR 2 pi i r m / R}.
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2 (&x)[R]) {
+    if constexpr (R == 2) {
+        float2 a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+        float2 t2 = cadd(x[1], x[3]), t3 = rot90<DIR>(csub(x[1], x[3]));
+        x[0] = cadd(t0, t2);
+        x[2] = csub(t0, t2);
+        x[1] = cadd(t1, t3);
+        x[3] = csub(t1, t3);
+    } else if constexpr (R == 8) {
+        float2 e[4] = {x[0], x[2], x[4], x[6]};
+        float2 o[4] = {x[1], x[3], x[5], x[7]};
+        dft<4, DIR>(e);
+        dft<4, DIR>(o);
+        const float h = 0.707106781186547524f;
+        float2 o1 = cscale(cadd(o[1], rot90<DIR>(o[1])), h);
+        float2 o2 = rot90<DIR>(o[2]);
+        float2 o3 = cscale(csub(rot90<DIR>(o[3]), o[3]), h);
+        x[0] = cadd(e[0], o[0]);
+        x[4] = csub(e[0], o[0]);
+        x[1] = cadd(e[1], o1);
+        x[5] = csub(e[1], o1);
+        x[2] = cadd(e[2], o2);
+        x[6] = csub(e[2], o2);
+        x[3] = cadd(e[3], o3);
+        x[7] = csub(e[3], o3);
+    } else {
+        // odd R: pair r with R - r (cosine and sine parts)
+        constexpr int H = (R - 1) / 2;
+        float2 a[H], b[H];
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            a[r - 1] = cadd(x[r], x[R - r]);
+            b[r - 1] = rot90<DIR>(csub(x[r], x[R - r]));
+        }
+        float2 y[R];
+        float2 s0 = x[0];
+#pragma unroll
+        for (int r = 0; r < H; ++r) s0 = cadd(s0, a[r]);
+        y[0] = s0;
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+            float2 acc = x[0];
+#pragma unroll
+            for (int r = 1; r <= H; ++r) {
+                const int q = (r * m) % R;
+                acc.x += a[r - 1].x * OddRadix<R>::c(q) + b[r - 1].x * OddRadix<R>::s(q);
+                acc.y += a[r - 1].y * OddRadix<R>::c(q) + b[r - 1].y * OddRadix<R>::s(q);
+            }
+            y[m] = acc;
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) x[m] = y[m];
+    }
+}
+
+// One Stockham stage of radix R over nseq sequences of length n.
+// p = product of the radices of earlier stages; tw[t] = e^{-2 pi i t / n}.
+template <int R, int DIR, int EPT>
+__device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstride, int p,
+                                          const float2* __restrict__ tw, int tid, int nthr) {
+    constexpr int NB = (EPT + R - 1) / R;
+    const int nq = n / R;
+    const int nb = nq * nseq;
+    const int twstep = n / (p * R);
+    float2 v[NB][R];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * nthr;
+        if (b < nb) {
+            const int s = b / nq;
+            const int q = b - s * nq;
+            const int k = q % p;
+            const float2* src = buf + s * sstride + q;
+            float2 x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = src[r * nq];
+            if (p > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[r * k * twstep];
+                    if (DIR > 0) w.y = -w.y;
+                    x[r] = cmul(x[r], w);
+                }
+            }
+            dft<R, DIR>(x);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = x[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * nthr;
+        if (b < nb) {
+            const int s = b / nq;
+            const int q = b - s * nq;
+            const int k = q % p;
+            float2* dst = buf + s * sstride + (q - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * p] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform.  Requires n * nseq <= EPT * nthr.  Ends synchronized.
+template <int DIR, int EPT>
+__device__ void lds_fft(float2* buf, const FftStages& st, int nseq, int sstride,
+                        const float2* __restrict__ tw, int tid, int nthr) {
+    int p = 1;
+    for (int s = 0; s < st.nstages; ++s) {
+        const int R = st.radix[s];
+        switch (R) {
+            case 8: fft_stage<8, DIR, EPT>(buf, st.n, nseq, sstride, p, tw, tid, nthr); break;
+            case 4: fft_stage<4, DIR, EPT>(buf, st.n, nseq, sstride, p, tw, tid, nthr); break;
+            case 2: fft_stage<2, DIR, EPT>(buf, st.n, nseq, sstride, p, tw, tid, nthr); break;
+            case 3: fft_stage<3, DIR, EPT>(buf, st.n, nseq, sstride, p, tw, tid, nthr); break;
+            case 5: fft_stage<5, DIR, EPT>(buf, st.n, nseq, sstride, p, tw, tid, nthr); break;
+            default: fft_stage<7, DIR, EPT>(buf, st.n, nseq, sstride, p, tw, tid, nthr); break;
+        }
+        p *= R;
+    }
+}
+
+}  // namespace ssa

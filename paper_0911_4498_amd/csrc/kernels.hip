@@ -1,0 +1,910 @@
+// kernels.hip -- gfx950 kernels of the fast SSA hot path.
+//
+//  * FFT convolution passes (Sec. 4, Algorithms 2/3 for X v and X^T u; Sec. 5,
+//    Algorithm 4 for rank-1 Hankelization), built on the LDS FFT of fft_lds.h.
+//    A real sequence w of length M is packed as z[n] = w[2n] + i w[2n+1]
+//    (M' = M/2 complex points).  With Z = DFT_{M'}(z):
+//        W(k)      = E(k) + w_M^k O(k),   W(k + M') = E(k) - w_M^k O(k),
+//        E(k) = (Z(k) + conj Z(M'-k)) / 2,  O(k) = -i (Z(k) - conj Z(M'-k)) / 2,
+//    w_M = e^{-2 pi i / M}.  Every spectral step therefore pairs bin k with
+//    bin M'-k; in the transposed layout T[k1][k2] the partner of (k1, k2) is
+//    (M1-k1, M2-1-k2) for k1 > 0 and (0, (M2-k2) mod M2) for k1 = 0, so one
+//    workgroup of pass 2 owns rows k1 and M1-k1 and needs no exchange.
+//  * Classical Gram-Schmidt reorthogonalization (Sec. 3.2.2) split into a
+//    projection kernel (FP64 partial inner products), a one-workgroup
+//    reduction (coefficients, the new alpha/beta, the DGKS test and the
+//    breakdown restart) and an update kernel that writes the normalized
+//    Lanczos vector.
+//  * Ritz-vector assembly U_{d+1} P and V_d Q (eqs. lbdiagm1/lbdiagm2).
+#include <hip/hip_runtime.h>
+
+#include "ssa_internal.h"
+
+namespace ssa {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ float2 twiddle_mp(const ConvGeom& g, long long t) {
+    const long long mask = (1LL << g.tw_shift) - 1;
+    return cmul(g.tw_hi[t >> g.tw_shift], g.tw_lo[t & mask]);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3").
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+        const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Standard normal number for element t of stream `ctr` (Box-Muller on two uniforms).
+__device__ __forceinline__ float gauss(unsigned long long seed, unsigned long long ctr, long long t) {
+    uint32_t c[4] = {(uint32_t)t, (uint32_t)((unsigned long long)t >> 32), (uint32_t)ctr,
+                     (uint32_t)(ctr >> 32)};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = ((double)c[0] + 1.0) * (1.0 / 4294967296.0);  // (0, 1]
+    const double u2 = (double)c[1] * (1.0 / 4294967296.0);
+    return (float)(sqrt(-2.0 * log(u1)) * cospi(2.0 * u2));
+}
+
+// ---------------------------------------------------------------------------
+// twiddle tables (FP64 angles, rounded once to FP32)
+
+__global__ void k_tables(int M1, int M2, long long Mp, int shift, float2* tw1, float2* tw2,
+                         float2* tw_lo, float2* tw_hi) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long S = 1LL << shift;
+    const long long nhi = (Mp + S - 1) / S;
+    double s, c;
+    if (t < M1) {
+        sincospi(-2.0 * (double)t / (double)M1, &s, &c);
+        tw1[t] = make_float2((float)c, (float)s);
+    }
+    if (t < M2) {
+        sincospi(-2.0 * (double)t / (double)M2, &s, &c);
+        tw2[t] = make_float2((float)c, (float)s);
+    }
+    if (t < S) {
+        sincospi(-2.0 * (double)t / (double)Mp, &s, &c);
+        tw_lo[t] = make_float2((float)c, (float)s);
+    }
+    if (t < nhi) {
+        sincospi(-2.0 * (double)(t * S) / (double)Mp, &s, &c);
+        tw_hi[t] = make_float2((float)c, (float)s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: column FFTs (length M1) of CB adjacent columns, twiddle, store T[k1][n2]
+
+template <int MODE>
+__device__ __forceinline__ float p1_value(const P1In& a, long long m, int y) {
+    if constexpr (MODE == IN_REV) {
+        return m < a.n_in ? a.x[a.n_in - 1 - m] : 0.0f;
+    } else if constexpr (MODE == IN_SERIES) {
+        return m < a.N ? (float)a.f[m] : 0.0f;
+    } else {
+        if (y < a.nu) return m < a.lenu ? a.U[(long long)y * a.ldu + m] : 0.0f;
+        return m < a.lenv ? a.V[(long long)(y - a.nu) * a.ldv + m] : 0.0f;
+    }
+}
+
+template <int MODE, int EPT>
+__global__ __launch_bounds__(256) void k_pass1(ConvGeom g, P1In a, float2* __restrict__ T1) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
+    float2* buf = smem;
+    float2* tw = smem + CB * ss;
+    const int c0 = blockIdx.x * CB;
+    const int y = blockIdx.y;
+    for (int t = tid; t < M1; t += nthr) tw[t] = g.tw1[t];
+    for (int idx = tid; idx < CB * M1; idx += nthr) {
+        const int c = idx % CB, n1 = idx / CB, n2 = c0 + c;
+        float2 z = make_float2(0.0f, 0.0f);
+        if (n2 < M2) {
+            const long long n = (long long)M2 * n1 + n2;
+            z.x = p1_value<MODE>(a, 2 * n, y);
+            z.y = p1_value<MODE>(a, 2 * n + 1, y);
+        }
+        buf[c * ss + n1] = z;
+    }
+    __syncthreads();
+    lds_fft<-1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
+    float2* out = T1 + (long long)y * g.Mp;
+    for (int idx = tid; idx < CB * M1; idx += nthr) {
+        const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
+        if (n2 < M2) out[(long long)k1 * M2 + n2] = cmul(buf[c * ss + k1], twiddle_mp(g, (long long)n2 * k1));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2 helpers: rows a and M1-a, pairs (element, partner)
+
+struct RowPair {
+    int a, b, nseq, npairs;
+    __device__ RowPair(int a_, int M1, int M2) : a(a_) {
+        b = (a == 0) ? 0 : M1 - a;
+        const bool two = (a != 0) && (2 * a != M1);
+        nseq = two ? 2 : 1;
+        npairs = two ? M2 : (a == 0 ? M2 / 2 + 1 : (M2 + 1) / 2);
+    }
+    // pair p -> (seq, k2) of the element and of its partner
+    __device__ void pair(int p, int M2, int& s0, int& e0, int& s1, int& e1) const {
+        s0 = 0;
+        e0 = p;
+        if (nseq == 2) {
+            s1 = 1;
+            e1 = M2 - 1 - p;
+        } else if (a == 0) {
+            s1 = 0;
+            e1 = (M2 - p) % M2;
+        } else {
+            s1 = 0;
+            e1 = M2 - 1 - p;
+        }
+    }
+    __device__ int row(int s) const { return s ? b : a; }
+};
+
+template <int EPT>
+__device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ T, const RowPair& rp,
+                                          int M2, int tid, int nthr) {
+    for (int idx = tid; idx < rp.nseq * M2; idx += nthr) {
+        const int s = idx / M2, k2 = idx - s * M2;
+        buf[idx] = T[(long long)rp.row(s) * M2 + k2];
+    }
+}
+
+template <int EPT>
+__device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict__ T, const RowPair& rp,
+                                           int M2, int tid, int nthr) {
+    for (int idx = tid; idx < rp.nseq * M2; idx += nthr) {
+        const int s = idx / M2, k2 = idx - s * M2;
+        T[(long long)rp.row(s) * M2 + k2] = buf[idx];
+    }
+}
+
+// pass 2 of a trajectory-matrix product: Q(k) = A(k) Z(k) + B(k) conj Z(M'-k)
+template <int EPT>
+__global__ __launch_bounds__(256) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
+                                                      const float2* __restrict__ T1,
+                                                      float2* __restrict__ T2) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int M2 = g.M2;
+    float2* buf = smem;
+    float2* tw = smem + 2 * M2;
+    const RowPair rp(blockIdx.x, g.M1, M2);
+    for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
+    load_rows<EPT>(buf, T1, rp, M2, tid, nthr);
+    __syncthreads();
+    lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    for (int p = tid; p < rp.npairs; p += nthr) {
+        int s0, e0, s1, e1;
+        rp.pair(p, M2, s0, e0, s1, e1);
+        const float2 z0 = buf[s0 * M2 + e0], z1 = buf[s1 * M2 + e1];
+        const float4 o0 = AB[(long long)rp.row(s0) * M2 + e0];
+        const float4 o1 = AB[(long long)rp.row(s1) * M2 + e1];
+        const float2 q0 = cadd(cmul(make_float2(o0.x, o0.y), z0), cmul(make_float2(o0.z, o0.w), cconj(z1)));
+        const float2 q1 = cadd(cmul(make_float2(o1.x, o1.y), z1), cmul(make_float2(o1.z, o1.w), cconj(z0)));
+        buf[s0 * M2 + e0] = q0;
+        if (s0 != s1 || e0 != e1) buf[s1 * M2 + e1] = q1;
+    }
+    __syncthreads();
+    lds_fft<1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    store_rows<EPT>(buf, T2, rp, M2, tid, nthr);
+}
+
+// E/O split of one packed-real spectrum pair, in FP64.
+struct SplitD {
+    double er, ei, orr, oi;
+};
+__device__ __forceinline__ SplitD split_eo(float2 z, float2 zp) {
+    // E = (z + conj zp)/2 ; O = -i (z - conj zp)/2
+    SplitD s;
+    s.er = 0.5 * ((double)z.x + (double)zp.x);
+    s.ei = 0.5 * ((double)z.y - (double)zp.y);
+    const double dr = (double)z.x - (double)zp.x, di = (double)z.y + (double)zp.y;
+    s.orr = 0.5 * di;
+    s.oi = -0.5 * dr;
+    return s;
+}
+
+// Spectral operator of the series (Algorithm 2, steps 1-2, done once).  For a
+// real c with full spectrum C, the packed output q = pack(c (*) w) satisfies
+//   Q(k) = A(k) Z_w(k) + B(k) conj Z_w(M'-k),
+//   A(k) = [E - sin(th) w^k O] / M',  B(k) = i cos(th) w^k O / M',
+// th = 2 pi k / M, E/O the split of C (so C(k) = E + w^k O,
+// C(k+M') = E - w^k O); the 1/M' of the inverse transform is folded in.
+template <int EPT>
+__global__ __launch_bounds__(256) void k_pass2_embed(ConvGeom g, const float2* __restrict__ T1,
+                                                     float4* __restrict__ AB) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int M1 = g.M1, M2 = g.M2;
+    float2* buf = smem;
+    float2* tw = smem + 2 * M2;
+    const RowPair rp(blockIdx.x, M1, M2);
+    for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
+    load_rows<EPT>(buf, T1, rp, M2, tid, nthr);
+    __syncthreads();
+    lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    const double invMp = 1.0 / (double)g.Mp;
+    for (int idx = tid; idx < rp.nseq * M2; idx += nthr) {
+        const int s = idx / M2, e = idx - s * M2;
+        const int k1 = rp.row(s);
+        int pk1, pk2;
+        if (k1 == 0) {
+            pk1 = 0;
+            pk2 = (M2 - e) % M2;
+        } else {
+            pk1 = M1 - k1;
+            pk2 = M2 - 1 - e;
+        }
+        const int ps = (pk1 == rp.a) ? 0 : 1;
+        const float2 z = buf[s * M2 + e], zp = buf[ps * M2 + pk2];
+        const SplitD d = split_eo(z, zp);
+        const long long k = (long long)k1 + (long long)M1 * e;
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)g.M, &sn, &cs);
+        // w^k = cs - i sn ; w^k O
+        const double wor = cs * d.orr + sn * d.oi;
+        const double woi = cs * d.oi - sn * d.orr;
+        const double ar = (d.er - sn * wor) * invMp, ai = (d.ei - sn * woi) * invMp;
+        // B = i cs (w^k O) / M'
+        const double br = -cs * woi * invMp, bi = cs * wor * invMp;
+        AB[(long long)k1 * M2 + e] = make_float4((float)ar, (float)ai, (float)br, (float)bi);
+    }
+}
+
+// Rank-1 Hankelization of each group (Algorithm 4, summed over the group's
+// triples before the single inverse transform):
+//   G(k) += sigma_i U_i(k) V_i(k),  G(k+M') += sigma_i U_i(k+M') V_i(k+M'),
+// then Q(k) = [(G(k) + G(k+M'))/2 + i (G(k) - G(k+M')) / (2 w^k)] / M'.
+constexpr int kReconThreads = 1024;
+constexpr int kReconPairs = 4;  // pairs per thread: 2*M2 <= kReconThreads*kReconPairs*2
+template <int EPT>
+__global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const float2* __restrict__ T1all,
+                                                              int k, const double* __restrict__ sigma,
+                                                              const int* __restrict__ offs,
+                                                              const int* __restrict__ members, int g0,
+                                                              float2* __restrict__ T2all) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int M1 = g.M1, M2 = g.M2;
+    const long long Mp = g.Mp;
+    float2* buf = smem;
+    float2* tw = smem + 2 * M2;
+    const RowPair rp(blockIdx.x, M1, M2);
+    const int grp = g0 + blockIdx.y;
+    for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
+
+    float2 zu0[kReconPairs], zu1[kReconPairs];
+    double g00r[kReconPairs], g00i[kReconPairs], g01r[kReconPairs], g01i[kReconPairs];
+    double g10r[kReconPairs], g10i[kReconPairs], g11r[kReconPairs], g11i[kReconPairs];
+    double w0r[kReconPairs], w0i[kReconPairs], w1r[kReconPairs], w1i[kReconPairs];
+#pragma unroll
+    for (int i = 0; i < kReconPairs; ++i) {
+        g00r[i] = g00i[i] = g01r[i] = g01i[i] = g10r[i] = g10i[i] = g11r[i] = g11i[i] = 0.0;
+        const int p = tid + i * nthr;
+        w0r[i] = w0i[i] = w1r[i] = w1i[i] = 0.0;
+        if (p < rp.npairs) {
+            int s0, e0, s1, e1;
+            rp.pair(p, M2, s0, e0, s1, e1);
+            const long long ka = (long long)rp.row(s0) + (long long)M1 * e0;
+            const long long kb = (long long)rp.row(s1) + (long long)M1 * e1;
+            double sn, cs;
+            sincospi(2.0 * (double)ka / (double)g.M, &sn, &cs);
+            w0r[i] = cs;
+            w0i[i] = -sn;
+            sincospi(2.0 * (double)kb / (double)g.M, &sn, &cs);
+            w1r[i] = cs;
+            w1i[i] = -sn;
+        }
+    }
+    const int mb = offs[grp], me = offs[grp + 1];
+    for (int mi = mb; mi < me; ++mi) {
+        const int tri = members[mi];
+        const double sg = sigma[tri];
+        // u_i spectrum rows
+        __syncthreads();
+        load_rows<EPT>(buf, T1all + (long long)tri * Mp, rp, M2, tid, nthr);
+        __syncthreads();
+        lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+#pragma unroll
+        for (int i = 0; i < kReconPairs; ++i) {
+            const int p = tid + i * nthr;
+            if (p < rp.npairs) {
+                int s0, e0, s1, e1;
+                rp.pair(p, M2, s0, e0, s1, e1);
+                zu0[i] = buf[s0 * M2 + e0];
+                zu1[i] = buf[s1 * M2 + e1];
+            }
+        }
+        __syncthreads();
+        // v_i spectrum rows
+        load_rows<EPT>(buf, T1all + (long long)(k + tri) * Mp, rp, M2, tid, nthr);
+        __syncthreads();
+        lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+#pragma unroll
+        for (int i = 0; i < kReconPairs; ++i) {
+            const int p = tid + i * nthr;
+            if (p < rp.npairs) {
+                int s0, e0, s1, e1;
+                rp.pair(p, M2, s0, e0, s1, e1);
+                const float2 zv0 = buf[s0 * M2 + e0], zv1 = buf[s1 * M2 + e1];
+                // element 0 (bin ka) and element 1 (bin kb = M'-ka)
+                for (int side = 0; side < 2; ++side) {
+                    const SplitD su = side == 0 ? split_eo(zu0[i], zu1[i]) : split_eo(zu1[i], zu0[i]);
+                    const SplitD sv = side == 0 ? split_eo(zv0, zv1) : split_eo(zv1, zv0);
+                    const double wr = side == 0 ? w0r[i] : w1r[i], wi = side == 0 ? w0i[i] : w1i[i];
+                    // U(k) = E + w O ; U(k+M') = E - w O
+                    const double uor = wr * su.orr - wi * su.oi, uoi = wr * su.oi + wi * su.orr;
+                    const double vor = wr * sv.orr - wi * sv.oi, voi = wr * sv.oi + wi * sv.orr;
+                    const double ua_r = su.er + uor, ua_i = su.ei + uoi, ub_r = su.er - uor, ub_i = su.ei - uoi;
+                    const double va_r = sv.er + vor, va_i = sv.ei + voi, vb_r = sv.er - vor, vb_i = sv.ei - voi;
+                    const double pa_r = ua_r * va_r - ua_i * va_i, pa_i = ua_r * va_i + ua_i * va_r;
+                    const double pb_r = ub_r * vb_r - ub_i * vb_i, pb_i = ub_r * vb_i + ub_i * vb_r;
+                    if (side == 0) {
+                        g00r[i] += sg * pa_r; g00i[i] += sg * pa_i;
+                        g01r[i] += sg * pb_r; g01i[i] += sg * pb_i;
+                    } else {
+                        g10r[i] += sg * pa_r; g10i[i] += sg * pa_i;
+                        g11r[i] += sg * pb_r; g11i[i] += sg * pb_i;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const double invMp = 1.0 / (double)Mp;
+#pragma unroll
+    for (int i = 0; i < kReconPairs; ++i) {
+        const int p = tid + i * nthr;
+        if (p < rp.npairs) {
+            int s0, e0, s1, e1;
+            rp.pair(p, M2, s0, e0, s1, e1);
+            for (int side = 0; side < 2; ++side) {
+                const double ga_r = side == 0 ? g00r[i] : g10r[i], ga_i = side == 0 ? g00i[i] : g10i[i];
+                const double gb_r = side == 0 ? g01r[i] : g11r[i], gb_i = side == 0 ? g01i[i] : g11i[i];
+                const double wr = side == 0 ? w0r[i] : w1r[i], wi = side == 0 ? w0i[i] : w1i[i];
+                // (G(k) - G(k+M')) / w^k = (dr + i di) * conj(w)   (|w| = 1)
+                const double dr = ga_r - gb_r, di = ga_i - gb_i;
+                const double tr = dr * wr + di * wi, ti = di * wr - dr * wi;
+                // Q = (ga + gb)/2 + i t/2
+                const double qr = 0.5 * (ga_r + gb_r) - 0.5 * ti;
+                const double qi = 0.5 * (ga_i + gb_i) + 0.5 * tr;
+                const float2 q = make_float2((float)(qr * invMp), (float)(qi * invMp));
+                if (side == 0) buf[s0 * M2 + e0] = q;
+                else if (s0 != s1 || e0 != e1) buf[s1 * M2 + e1] = q;
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    store_rows<EPT>(buf, T2all + (long long)blockIdx.y * Mp, rp, M2, tid, nthr);
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: conj twiddle, inverse column FFTs, emit y[2n], y[2n+1]
+
+template <int MODE>
+__device__ __forceinline__ void p3_emit(const P3Out& o, long long m, float val, float coef, int y) {
+    if constexpr (MODE == OUT_SLICE) {
+        const long long t = m - (o.n_in - 1);
+        if (t >= 0 && t < o.n_out) {
+            float r = val;
+            if (o.prev) r -= coef * o.prev[t];
+            o.out[t] = r;
+        }
+    } else {
+        if (m < o.N) {
+            long long c = m + 1;
+            if (o.L < c) c = o.L;
+            if (o.K < c) c = o.K;
+            if (o.N - m < c) c = o.N - m;
+            o.out[(long long)y * o.ldo + m] = val / (float)c;
+        }
+    }
+}
+
+template <int MODE, int EPT>
+__global__ __launch_bounds__(256) void k_pass3(ConvGeom g, const float2* __restrict__ T2, P3Out o) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
+    float2* buf = smem;
+    float2* tw = smem + CB * ss;
+    const int c0 = blockIdx.x * CB;
+    const int y = blockIdx.y;
+    const float2* in = T2 + (long long)y * g.Mp;
+    for (int t = tid; t < M1; t += nthr) tw[t] = g.tw1[t];
+    for (int idx = tid; idx < CB * M1; idx += nthr) {
+        const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
+        float2 z = make_float2(0.0f, 0.0f);
+        if (n2 < M2) z = cmul(in[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
+        buf[c * ss + k1] = z;
+    }
+    __syncthreads();
+    lds_fft<1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
+    float coef = 0.0f;
+    if constexpr (MODE == OUT_SLICE) {
+        if (o.coef) coef = (float)(*o.coef);
+    }
+    for (int idx = tid; idx < CB * M1; idx += nthr) {
+        const int c = idx % CB, n1 = idx / CB, n2 = c0 + c;
+        if (n2 < M2) {
+            const float2 q = buf[c * ss + n1];
+            const long long n = (long long)M2 * n1 + n2;
+            p3_emit<MODE>(o, 2 * n, q.x, coef, y);
+            p3_emit<MODE>(o, 2 * n + 1, q.y, coef, y);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Short antidiagonals of the grouped Hankelization, from the definition.
+// The FP32 FFT leaves an absolute error of order eps * sigma |u| |v| on every
+// convolution entry; averaging divides it by the antidiagonal length cnt[n],
+// so near the two ends of the series (cnt ~ 1) the FFT value is recomputed
+// directly: g[n] = sum_i sigma_i sum_{a+b=n} u_i[a] v_i[b] / cnt[n]
+// (FP64 sums of exact FP32 products) for every n with cnt[n] <= kEdgeCnt.
+
+__global__ __launch_bounds__(256) void k_recon_edges(const double* __restrict__ sigma, const float* __restrict__ U,
+                                                     long long ldu, const float* __restrict__ V, long long ldv,
+                                                     const int* __restrict__ offs, const int* __restrict__ members,
+                                                     long long N, long long L, long long K, float* __restrict__ out,
+                                                     long long ldo) {
+    const int grp = blockIdx.y;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long lmin = L < K ? L : K;
+    const long long ne = lmin <= kEdgeCnt ? N : 2LL * kEdgeCnt;
+    if (idx >= ne) return;
+    const long long n = (lmin <= kEdgeCnt || idx < kEdgeCnt) ? idx : N - 2LL * kEdgeCnt + idx;
+    const long long a0 = n - K + 1 > 0 ? n - K + 1 : 0;
+    const long long a1 = n < L - 1 ? n : L - 1;
+    double acc = 0.0;
+    for (int mi = offs[grp]; mi < offs[grp + 1]; ++mi) {
+        const int i = members[mi];
+        const float* u = U + (long long)i * ldu;
+        const float* v = V + (long long)i * ldv;
+        double s = 0.0;
+        for (long long a = a0; a <= a1; ++a) s += (double)u[a] * (double)v[n - a];
+        acc += sigma[i] * s;
+    }
+    out[(long long)grp * ldo + n] = (float)(acc / (double)(a1 - a0 + 1));
+}
+
+// ---------------------------------------------------------------------------
+// misc
+
+__global__ void k_check_finite(const double* __restrict__ f, long long N, double* flag) {
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < N;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (!isfinite(f[t])) *flag = 1.0;
+    }
+}
+
+__global__ void k_fill_zero(double* p, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+__global__ void k_start_vector(float* r, long long n, unsigned long long seed) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) r[t] = gauss(seed, 0, t);
+}
+
+// ---------------------------------------------------------------------------
+// classical Gram-Schmidt
+
+// part[chunk * pstride + c] = sum over the chunk's rows of basis[c][t] * r[t]
+// (c < ncols), and part[chunk * pstride + ncols] = sum r[t]^2 (column group 0).
+// Products of two FP32 numbers are exact in FP64; sums are FP64.
+__global__ __launch_bounds__(256) void k_cgs_dots(const float* __restrict__ basis, long long ld, int ncols,
+                                                  const float* __restrict__ r, long long n,
+                                                  double* __restrict__ part, int pstride) {
+    constexpr int RPT = kDotsRows / 256, CJ = kDotsCols;
+    __shared__ double red[CJ + 1][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long row0 = (long long)blockIdx.x * kDotsRows;
+    const int c0 = blockIdx.y * CJ;
+    const int nc = min(CJ, ncols - c0);
+    float rv[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const long long t = row0 + tid + q * 256;
+        rv[q] = t < n ? r[t] : 0.0f;
+    }
+    double acc[CJ + 1];
+#pragma unroll
+    for (int c = 0; c < CJ; ++c) {
+        acc[c] = 0.0;
+        if (c < nc) {
+            const float* col = basis + (long long)(c0 + c) * ld;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const long long t = row0 + tid + q * 256;
+                if (t < n) acc[c] += (double)col[t] * (double)rv[q];
+            }
+        }
+    }
+    acc[CJ] = 0.0;
+    if (blockIdx.y == 0) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[CJ] += (double)rv[q] * (double)rv[q];
+    }
+#pragma unroll
+    for (int c = 0; c <= CJ; ++c) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) red[c][wave] = v;
+    }
+    __syncthreads();
+    if (tid <= CJ) {
+        const int c = tid;
+        const double s = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+        if (c < nc) part[(long long)blockIdx.x * pstride + c0 + c] = s;
+        if (c == CJ && blockIdx.y == 0) part[(long long)blockIdx.x * pstride + ncols] = s;
+    }
+}
+
+// block-wide sum (256 threads), result valid in every thread
+__device__ double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    const double s = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return s;
+}
+
+// r <- r - basis * h (h in LDS), one workgroup
+__device__ void blk_subtract(float* r, long long n, const float* basis, long long ld, int ncols,
+                             const double* h) {
+    for (long long t = threadIdx.x; t < n; t += blockDim.x) {
+        double acc = r[t];
+        for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * h[c];
+        r[t] = (float)acc;
+    }
+    __syncthreads();
+}
+
+// h[c] = <basis_c, r> for c < ncols, returns |r|^2, one workgroup
+__device__ double blk_project(const float* r, long long n, const float* basis, long long ld, int ncols,
+                              double* h, double* sh) {
+    for (int c = 0; c < ncols; ++c) {
+        double acc = 0.0;
+        const float* col = basis + (long long)c * ld;
+        for (long long t = threadIdx.x; t < n; t += blockDim.x) acc += (double)col[t] * (double)r[t];
+        const double s = block_sum256(acc, sh);
+        if (threadIdx.x == 0) h[c] = s;
+    }
+    double acc = 0.0;
+    for (long long t = threadIdx.x; t < n; t += blockDim.x) acc += (double)r[t] * (double)r[t];
+    const double rr = block_sum256(acc, sh);
+    __syncthreads();
+    return rr;
+}
+
+// Coefficients h, the new B entry and the normalization (one workgroup).
+//   common case: |r_new|^2 = |r|^2 - |h|^2 >= |r|^2 / 2  (one CGS pass suffices);
+//   DGKS case  : a second projection is computed here and h replaced by it
+//                after subtracting the first (r is updated in place);
+//   breakdown  : the new vector is numerically in the span of the basis; the
+//                B entry becomes 0 and a seeded random direction, made
+//                orthogonal to the basis by two passes, continues the
+//                recurrence.
+constexpr int kMaxCols = 2048;
+__global__ __launch_bounds__(256) void k_cgs_reduce(ReduceArgs a) {
+    __shared__ double hs[kMaxCols];
+    __shared__ double sh[4];
+    __shared__ int decision;
+    const int tid = threadIdx.x;
+    for (int c = tid; c < a.ncols; c += 256) {
+        double s = 0.0;
+        for (int ch = 0; ch < a.nchunks; ++ch) s += a.part[(long long)ch * a.pstride + c];
+        hs[c] = s;
+    }
+    __syncthreads();
+    double hh = 0.0;
+    for (int c = tid; c < a.ncols; c += 256) hh += hs[c] * hs[c];
+    hh = block_sum256(hh, sh);
+    double rr = 0.0;
+    if (tid == 0)
+        for (int ch = 0; ch < a.nchunks; ++ch) rr += a.part[(long long)ch * a.pstride + a.ncols];
+    rr = block_sum256(tid == 0 ? rr : 0.0, sh);
+    const double bnorm = a.state[0];
+    double coef, scale;
+    if (a.full) {
+        for (int c = tid; c < a.ncols; c += 256) hs[c] = 0.0;
+        coef = 0.0;
+        scale = 0.0;
+    } else {
+        double a2 = rr - hh;
+        const double thr = a.tol_bd * bnorm;
+        if (tid == 0) decision = (a2 >= 0.5 * rr && sqrt(a2) > thr) ? 0 : 1;
+        __syncthreads();
+        if (decision == 0) {
+            coef = sqrt(a2);
+            scale = 1.0 / coef;
+        } else {
+            // second Gram-Schmidt pass on the updated vector
+            blk_subtract(a.r, a.n, a.basis, a.ld, a.ncols, hs);
+            __syncthreads();
+            const double rr2 = blk_project(a.r, a.n, a.basis, a.ld, a.ncols, hs, sh);
+            __syncthreads();
+            double hh2 = 0.0;
+            for (int c = tid; c < a.ncols; c += 256) hh2 += hs[c] * hs[c];
+            hh2 = block_sum256(hh2, sh);
+            a2 = rr2 - hh2;
+            if (tid == 0) decision = (a2 > 0.0 && sqrt(a2) > thr) ? 2 : 3;
+            __syncthreads();
+            if (decision == 2) {
+                coef = sqrt(a2);
+                scale = 1.0 / coef;
+                if (tid == 0) a.state[2] += 1.0;
+            } else {
+                // breakdown: fresh direction
+                coef = 0.0;
+                const unsigned long long ctr = a.stream_ctr;
+                for (long long t = tid; t < a.n; t += 256) a.r[t] = gauss(a.seed, ctr, t);
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    blk_project(a.r, a.n, a.basis, a.ld, a.ncols, hs, sh);
+                    __syncthreads();
+                    blk_subtract(a.r, a.n, a.basis, a.ld, a.ncols, hs);
+                }
+                const double rr3 = blk_project(a.r, a.n, a.basis, 0, 0, hs, sh);
+                for (int c = tid; c < a.ncols; c += 256) hs[c] = 0.0;
+                scale = rr3 > 0.0 ? 1.0 / sqrt(rr3) : 0.0;
+                if (tid == 0) a.state[1] += 1.0;
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < a.ncols; c += 256) a.h[c] = hs[c];
+    if (tid == 0) {
+        *a.coef_out = coef;
+        *a.scale_out = scale;
+        if (a.track && coef > a.state[0]) a.state[0] = coef;
+    }
+}
+
+// out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale   (FP64 accumulation)
+__global__ __launch_bounds__(256) void k_cgs_update(const float* __restrict__ r, const float* __restrict__ basis,
+                                                    long long ld, int ncols, const double* __restrict__ h,
+                                                    const double* __restrict__ scale, float* __restrict__ out,
+                                                    long long n) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    double acc = r[t];
+    for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * h[c];
+    out[t] = (float)(acc * (*scale));
+}
+
+// ---------------------------------------------------------------------------
+// Ritz vectors: out[i*ldo + t] = sum_c basis[c*ld + t] P[c*k + i]
+
+constexpr int kRitzTile = 16;
+__global__ __launch_bounds__(256) void k_ritz(const float* __restrict__ basis, long long ld, int ncols,
+                                              const double* __restrict__ P, int k, float* __restrict__ out,
+                                              long long ldo, long long n) {
+    extern __shared__ double ps[];  // ncols x kRitzTile
+    const int i0 = blockIdx.y * kRitzTile;
+    const int kt = min(kRitzTile, k - i0);
+    for (int idx = threadIdx.x; idx < ncols * kRitzTile; idx += 256) {
+        const int c = idx / kRitzTile, i = idx - c * kRitzTile;
+        ps[idx] = i < kt ? P[(long long)c * k + i0 + i] : 0.0;
+    }
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    double acc[kRitzTile];
+#pragma unroll
+    for (int i = 0; i < kRitzTile; ++i) acc[i] = 0.0;
+    for (int c = 0; c < ncols; ++c) {
+        const double x = basis[(long long)c * ld + t];
+#pragma unroll
+        for (int i = 0; i < kRitzTile; ++i) acc[i] += x * ps[c * kRitzTile + i];
+    }
+#pragma unroll
+    for (int i = 0; i < kRitzTile; ++i)
+        if (i < kt) out[(long long)(i0 + i) * ldo + t] = (float)acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static int ept_for(long long elems, int nthr) {
+    const long long e = (elems + nthr - 1) / nthr;
+    if (e <= 4) return 4;
+    if (e <= 8) return 8;
+    if (e <= 16) return 16;
+    return 32;
+}
+
+static size_t lds_p13(const ConvGeom& g) { return sizeof(float2) * ((size_t)g.CB * (g.M1 + 1) + g.M1); }
+static size_t lds_p2(const ConvGeom& g) { return sizeof(float2) * (3 * (size_t)g.M2); }
+
+#define SSA_EPT_SWITCH(ept, EXPR)             \
+    switch (ept) {                            \
+        case 4: { constexpr int E = 4; EXPR; } break;   \
+        case 8: { constexpr int E = 8; EXPR; } break;   \
+        case 16: { constexpr int E = 16; EXPR; } break; \
+        default: { constexpr int E = 32; EXPR; } break; \
+    }
+
+hipError_t launch_tables(const ConvGeom& g, float2* tw1, float2* tw2, float2* tw_lo, float2* tw_hi,
+                         hipStream_t s) {
+    const long long S = 1LL << g.tw_shift;
+    long long n = g.M1;
+    if (g.M2 > n) n = g.M2;
+    if (S > n) n = S;
+    const long long nhi = (g.Mp + S - 1) / S;
+    if (nhi > n) n = nhi;
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.M1, g.M2, g.Mp,
+                       g.tw_shift, tw1, tw2, tw_lo, tw_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, float2* T1, hipStream_t s) {
+    const dim3 grid((g.M2 + g.CB - 1) / g.CB, nvec);
+    const size_t lds = lds_p13(g);
+    const int ept = ept_for((long long)g.CB * g.M1, 256);
+    if (mode == IN_REV) {
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_REV, E>), grid, dim3(256), lds, s, g, in, T1));
+    } else if (mode == IN_SERIES) {
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_SERIES, E>), grid, dim3(256), lds, s, g, in, T1));
+    } else {
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_VECS, E>), grid, dim3(256), lds, s, g, in, T1));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2_matvec(const ConvGeom& g, const float4* AB, const float2* T1, float2* T2,
+                               hipStream_t s) {
+    const dim3 grid(g.M1 / 2 + 1);
+    const int ept = ept_for(2LL * g.M2, 256);
+    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_matvec<E>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2));
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2_embed(const ConvGeom& g, const float2* T1, float4* AB, hipStream_t s) {
+    const dim3 grid(g.M1 / 2 + 1);
+    const int ept = ept_for(2LL * g.M2, 256);
+    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_embed<E>), grid, dim3(256), lds_p2(g), s, g, T1, AB));
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2_recon(const ConvGeom& g, const float2* T1all, int k, const double* sigma,
+                              const int* offs, const int* members, int g0, int ng, float2* T2all,
+                              hipStream_t s) {
+    const dim3 grid(g.M1 / 2 + 1, ng);
+    const int ept = ept_for(2LL * g.M2, kReconThreads);
+    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_recon<E>), grid, dim3(kReconThreads), lds_p2(g), s, g,
+                                           T1all, k, sigma, offs, members, g0, T2all));
+    return hipGetLastError();
+}
+
+hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3Out& o, int nvec,
+                        hipStream_t s) {
+    const dim3 grid((g.M2 + g.CB - 1) / g.CB, nvec);
+    const size_t lds = lds_p13(g);
+    const int ept = ept_for((long long)g.CB * g.M1, 256);
+    if (mode == OUT_SLICE) {
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_SLICE, E>), grid, dim3(256), lds, s, g, T2, o));
+    } else {
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_HANKEL, E>), grid, dim3(256), lds, s, g, T2, o));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_recon_edges(const double* sigma, const float* U, long long ldu, const float* V, long long ldv,
+                              const int* offs, const int* members, int ng, long long N, long long L, long long K,
+                              float* out, long long ldo, hipStream_t s) {
+    const long long lmin = L < K ? L : K;
+    const long long ne = lmin <= kEdgeCnt ? N : 2LL * kEdgeCnt;
+    const dim3 grid((unsigned)((ne + 255) / 256), (unsigned)ng);
+    hipLaunchKernelGGL(k_recon_edges, grid, dim3(256), 0, s, sigma, U, ldu, V, ldv, offs, members, N, L, K, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* f, long long N, double* flag, hipStream_t s) {
+    long long blocks = (N + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, s, f, N, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_start_vector, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs_dots(const float* basis, long long ld, int ncols, const float* r, long long n,
+                           double* part, int pstride, hipStream_t s) {
+    const unsigned nchunks = (unsigned)((n + kDotsRows - 1) / kDotsRows);
+    const unsigned ngrp = ncols > 0 ? (unsigned)((ncols + kDotsCols - 1) / kDotsCols) : 1u;
+    hipLaunchKernelGGL(k_cgs_dots, dim3(nchunks, ngrp), dim3(256), 0, s, basis, ld, ncols, r, n, part, pstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cgs_reduce, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols, const double* h,
+                             const double* scale, float* out, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cgs_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, basis, ld, ncols,
+                       h, scale, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_ritz(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
+                       long long ldo, long long n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((k + kRitzTile - 1) / kRitzTile));
+    const size_t lds = sizeof(double) * (size_t)ncols * kRitzTile;
+    hipLaunchKernelGGL(k_ritz, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, n);
+    return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t allow_lds(F* f) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024);
+}
+
+hipError_t set_kernel_attributes() {
+    hipError_t e = hipSuccess;
+#define SSA_ALLOW(K)                              \
+    do {                                          \
+        hipError_t e2 = allow_lds(K);             \
+        if (e2 != hipSuccess) e = e2;             \
+    } while (0)
+#define SSA_ALLOW_EPT(T)                          \
+    SSA_ALLOW(T<4>); SSA_ALLOW(T<8>); SSA_ALLOW(T<16>); SSA_ALLOW(T<32>)
+    SSA_ALLOW((k_pass1<IN_REV, 4>)); SSA_ALLOW((k_pass1<IN_REV, 8>)); SSA_ALLOW((k_pass1<IN_REV, 16>));
+    SSA_ALLOW((k_pass1<IN_REV, 32>));
+    SSA_ALLOW((k_pass1<IN_SERIES, 4>)); SSA_ALLOW((k_pass1<IN_SERIES, 8>)); SSA_ALLOW((k_pass1<IN_SERIES, 16>));
+    SSA_ALLOW((k_pass1<IN_SERIES, 32>));
+    SSA_ALLOW((k_pass1<IN_VECS, 4>)); SSA_ALLOW((k_pass1<IN_VECS, 8>)); SSA_ALLOW((k_pass1<IN_VECS, 16>));
+    SSA_ALLOW((k_pass1<IN_VECS, 32>));
+    SSA_ALLOW((k_pass3<OUT_SLICE, 4>)); SSA_ALLOW((k_pass3<OUT_SLICE, 8>)); SSA_ALLOW((k_pass3<OUT_SLICE, 16>));
+    SSA_ALLOW((k_pass3<OUT_SLICE, 32>));
+    SSA_ALLOW((k_pass3<OUT_HANKEL, 4>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 8>));
+    SSA_ALLOW((k_pass3<OUT_HANKEL, 16>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 32>));
+    SSA_ALLOW_EPT(k_pass2_matvec);
+    SSA_ALLOW_EPT(k_pass2_embed);
+    SSA_ALLOW_EPT(k_pass2_recon);
+    SSA_ALLOW(k_ritz);
+#undef SSA_ALLOW_EPT
+#undef SSA_ALLOW
+    return e;
+}
+
+}  // namespace ssa

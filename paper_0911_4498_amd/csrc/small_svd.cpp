@@ -1,0 +1,236 @@
+// small_svd.cpp -- Ritz values and vectors of the Lanczos bidiagonal B_d.
+//
+// After d steps of Algorithm 1, B_d is (d+1) x d lower bidiagonal with alpha_j
+// on the diagonal and beta_{j+1} below it (Sec. 3.1).  Its singular triples
+// (omega_i, p_i, q_i) give the Ritz approximations omega_i, U_{d+1} p_i,
+// V_d q_i, and the relation X^T U_{d+1} = V_d B_d^T + alpha_{d+1} v_{d+1}
+// e_{d+1}^T (eq. lbdiagm2) bounds their residual by alpha_{d+1} |p_i[d]|.
+//
+// The right singular vectors of B_d are the eigenvectors of the symmetric
+// tridiagonal T = B_d^T B_d (the cross-product route of Theorem 1), with
+//   T[c][c] = alpha_{c+1}^2 + beta_{c+2}^2,  T[c][c+1] = alpha_{c+2} beta_{c+2}.
+// Eigenvalues come from the implicit QL iteration with Wilkinson shifts
+// (Bowdler, Martin, Reinsch and Wilkinson 1968), O(d^2); while iterating only
+// the last row of the eigenvector matrix is carried, which is all the
+// residual bound needs: p_i[d] = beta_{d+1} q_i[d-1] / omega_i.  The final k
+// vectors come from inverse iteration on T (Wilkinson), each made orthogonal
+// to the ones before it, O(k^2 d).  The left vectors are p_i = B_d q_i / omega_i.
+//
+// Squaring costs relative accuracy only for omega_i below ~1e-8 omega_1, far
+// under the error of the FP32 products that produced B_d.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ssa_internal.h"
+
+namespace ssa {
+
+namespace {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+void form_tridiagonal(const double* alpha, const double* beta, int d, double* D, double* E) {
+    for (int c = 0; c < d; ++c) D[c] = alpha[c + 1] * alpha[c + 1] + beta[c + 2] * beta[c + 2];
+    for (int c = 0; c + 1 < d; ++c) E[c] = alpha[c + 2] * beta[c + 2];
+    E[d - 1] = 0.0;
+}
+
+// Implicit QL with shifts on the symmetric tridiagonal (D diagonal, E[c]
+// couples c and c+1).  D receives the eigenvalues (unordered).  If zl is
+// given (initialized to the last row of the identity) the same rotations are
+// applied to it, so on exit zl[c] is the last component of the eigenvector
+// of D[c].  Returns false if an eigenvalue needed more than 64 iterations.
+bool tridiag_ql(int n, double* D, double* E, double* zl) {
+    if (n <= 0) return true;
+    E[n - 1] = 0.0;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                const double dd = std::fabs(D[m]) + std::fabs(D[m + 1]);
+                if (std::fabs(E[m]) <= kEps * dd) break;
+            }
+            if (m == l) break;
+            if (++iter > 64) return false;
+            // shift from the leading 2x2 block of the unreduced part
+            double g = (D[l + 1] - D[l]) / (2.0 * E[l]);
+            double r = std::hypot(g, 1.0);
+            g = D[m] - D[l] + E[l] / (g + std::copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool underflow = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double f = s * E[i];
+                const double b = c * E[i];
+                r = std::hypot(f, g);
+                E[i + 1] = r;
+                if (r == 0.0) {
+                    D[i + 1] -= p;
+                    E[m] = 0.0;
+                    underflow = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = D[i + 1] - p;
+                r = (D[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                D[i + 1] = g + p;
+                g = c * r - b;
+                if (zl) {
+                    const double z1 = zl[i + 1];
+                    zl[i + 1] = s * zl[i] + c * z1;
+                    zl[i] = c * zl[i] - s * z1;
+                }
+            }
+            if (underflow) continue;
+            D[l] -= p;
+            E[l] = g;
+            E[m] = 0.0;
+        }
+    }
+    return true;
+}
+
+// Solve (T - lam I) x = rhs (in place in rhs) by Gaussian elimination with
+// partial pivoting on the tridiagonal; tiny pivots are replaced by
+// eps * tnorm (the usual inverse-iteration safeguard).
+void shifted_solve(int n, const double* D, const double* E, double lam, double tnorm, double* rhs,
+                   double* a, double* b, double* c, double* u2) {
+    for (int i = 0; i < n; ++i) a[i] = D[i] - lam;
+    for (int i = 0; i + 1 < n; ++i) {
+        b[i] = E[i];
+        c[i] = E[i];
+    }
+    const double tiny = kEps * (tnorm > 0.0 ? tnorm : 1.0);
+    for (int i = 0; i + 1 < n; ++i) {
+        u2[i] = 0.0;
+        if (std::fabs(a[i]) >= std::fabs(c[i])) {
+            if (a[i] == 0.0) a[i] = tiny;
+            const double f = c[i] / a[i];
+            a[i + 1] -= f * b[i];
+            rhs[i + 1] -= f * rhs[i];
+        } else {
+            const double f = a[i] / c[i];
+            a[i] = c[i];
+            const double t = a[i + 1];
+            a[i + 1] = b[i] - f * t;
+            if (i + 2 < n) {
+                u2[i] = b[i + 1];
+                b[i + 1] = -f * b[i + 1];
+            }
+            b[i] = t;
+            const double r0 = rhs[i];
+            rhs[i] = rhs[i + 1];
+            rhs[i + 1] = r0 - f * rhs[i + 1];
+        }
+    }
+    if (a[n - 1] == 0.0) a[n - 1] = tiny;
+    rhs[n - 1] /= a[n - 1];
+    if (n >= 2) rhs[n - 2] = (rhs[n - 2] - b[n - 2] * rhs[n - 1]) / a[n - 2];
+    for (int i = n - 3; i >= 0; --i) rhs[i] = (rhs[i] - b[i] * rhs[i + 1] - u2[i] * rhs[i + 2]) / a[i];
+}
+
+void sorted_desc(int n, const double* D, std::vector<int>& order) {
+    order.resize(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return D[x] > D[y]; });
+}
+
+}  // namespace
+
+size_t bidiag_work_doubles(int d) { return (size_t)8 * (d + 2); }
+
+void bidiag_ritz_values(const double* alpha, const double* beta, int d, int k, double* omega,
+                        double* resid, double* work) {
+    double* D = work;
+    double* E = work + (d + 2);
+    double* zl = work + 2 * (d + 2);
+    form_tridiagonal(alpha, beta, d, D, E);
+    for (int c = 0; c < d; ++c) zl[c] = (c == d - 1) ? 1.0 : 0.0;
+    tridiag_ql(d, D, E, zl);
+    std::vector<int> order;
+    sorted_desc(d, D, order);
+    for (int i = 0; i < k; ++i) {
+        if (i >= d) {
+            omega[i] = 0.0;
+            resid[i] = 0.0;
+            continue;
+        }
+        const int o = order[i];
+        const double w = std::sqrt(std::max(D[o], 0.0));
+        omega[i] = w;
+        // alpha_{d+1} |p_i[d]|,  p_i[d] = beta_{d+1} q_i[d-1] / omega_i
+        resid[i] = w > 0.0 ? alpha[d + 1] * beta[d + 1] * std::fabs(zl[o]) / w : 0.0;
+    }
+}
+
+void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, double* omega,
+                         double* P, double* Q, double* work) {
+    double* D = work;
+    double* E = work + (d + 2);
+    double* D0 = work + 2 * (d + 2);
+    double* E0 = work + 3 * (d + 2);
+    double* a = work + 4 * (d + 2);
+    double* b = work + 5 * (d + 2);
+    double* c = work + 6 * (d + 2);
+    double* u2 = work + 7 * (d + 2);
+    form_tridiagonal(alpha, beta, d, D0, E0);
+    std::memcpy(D, D0, sizeof(double) * d);
+    std::memcpy(E, E0, sizeof(double) * d);
+    tridiag_ql(d, D, E, nullptr);
+    std::vector<int> order;
+    sorted_desc(d, D, order);
+    double tnorm = 0.0;
+    for (int i = 0; i < d; ++i) tnorm = std::max(tnorm, std::fabs(D0[i]) + 2.0 * std::fabs(i + 1 < d ? E0[i] : 0.0));
+    std::vector<double> q((size_t)k * d, 0.0), x(d);
+    const int kk = std::min(k, d);
+    for (int i = 0; i < kk; ++i) {
+        const double lam = D[order[i]];
+        // deterministic, generic start vector
+        for (int t = 0; t < d; ++t) x[t] = 1.0 + 0.5 * std::sin(0.7 * (t + 1) + 1.3 * (i + 1));
+        for (int it = 0; it < 4; ++it) {
+            shifted_solve(d, D0, E0, lam, tnorm, x.data(), a, b, c, u2);
+            for (int pass = 0; pass < 2; ++pass)
+                for (int j = 0; j < i; ++j) {
+                    const double* qj = &q[(size_t)j * d];
+                    double h = 0.0;
+                    for (int t = 0; t < d; ++t) h += qj[t] * x[t];
+                    for (int t = 0; t < d; ++t) x[t] -= h * qj[t];
+                }
+            double nrm = 0.0;
+            for (int t = 0; t < d; ++t) nrm += x[t] * x[t];
+            nrm = std::sqrt(nrm);
+            if (nrm == 0.0) {
+                for (int t = 0; t < d; ++t) x[t] = (t == i) ? 1.0 : 0.0;
+                nrm = 1.0;
+            }
+            for (int t = 0; t < d; ++t) x[t] /= nrm;
+        }
+        std::memcpy(&q[(size_t)i * d], x.data(), sizeof(double) * d);
+    }
+    for (int i = 0; i < k; ++i) {
+        omega[i] = i < kk ? std::sqrt(std::max(D[order[i]], 0.0)) : 0.0;
+        // Q[t][i] (row-major d x k)
+        for (int t = 0; t < d; ++t) Q[(size_t)t * k + i] = i < kk ? q[(size_t)i * d + t] : 0.0;
+        // p = B q / omega, normalized (the normalization only matters when omega ~ 0)
+        double nrm = 0.0;
+        std::vector<double> p(d + 1, 0.0);
+        if (i < kk) {
+            const double* qi = &q[(size_t)i * d];
+            for (int r = 0; r <= d; ++r) {
+                double v = 0.0;
+                if (r < d) v += alpha[r + 1] * qi[r];
+                if (r >= 1) v += beta[r + 1] * qi[r - 1];
+                p[r] = v;
+                nrm += v * v;
+            }
+            nrm = std::sqrt(nrm);
+        }
+        for (int r = 0; r <= d; ++r) P[(size_t)r * k + i] = nrm > 0.0 ? p[r] / nrm : 0.0;
+    }
+}
+
+}  // namespace ssa

@@ -1,0 +1,120 @@
+// ssa_internal.h -- shared declarations of the HIP kernels and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fft_lds.h"
+
+namespace ssa {
+
+// Geometry of the half-length complex FFT used for every real convolution of
+// length M: M' = M/2 = M1 * M2 points, "four-step" order.  Pass 1 transforms
+// the M2 strided columns (length M1), applies the W_{M'}^{n2 k1} twiddles and
+// stores T[k1][n2]; pass 2 transforms rows (length M2), so the spectrum sits
+// at T[k1][k2] = Z[k1 + M1 k2] (transposed, never reordered); pass 3 is the
+// inverse column pass.  Pointwise products do not care about the order, so
+// the spectral operator of the series is stored in the same layout.
+struct ConvGeom {
+    int M1, M2;
+    long long Mp;  // M1 * M2
+    long long M;   // 2 * Mp
+    int CB;        // columns per workgroup in passes 1 and 3
+    int tw_shift;  // W_{M'}^t = tw_hi[t >> tw_shift] * tw_lo[t & mask]
+    FftStages st1, st2;
+    const float2* tw1;  // W_{M1}^t, t < M1
+    const float2* tw2;  // W_{M2}^t, t < M2
+    const float2* tw_lo;
+    const float2* tw_hi;
+};
+
+// pass-1 input modes
+enum { IN_REV = 0, IN_SERIES = 1, IN_VECS = 2 };
+// pass-3 output modes
+enum { OUT_SLICE = 0, OUT_HANKEL = 1 };
+
+struct P1In {
+    const float* x;      // IN_REV: input vector (w[m] = x[n_in-1-m])
+    long long n_in;
+    const double* f;     // IN_SERIES
+    long long N;
+    const float* U;      // IN_VECS: vector y < nu is U + y*ldu (lenu entries), else V
+    long long ldu, lenu;
+    const float* V;
+    long long ldv, lenv;
+    int nu;
+};
+
+struct P3Out {
+    float* out;          // OUT_SLICE: out[t] = y[n_in-1+t] - coef*prev[t], t < n_out
+    long long n_in, n_out;
+    const float* prev;   // may be null
+    const double* coef;  // device scalar, may be null
+    long long N, L, K;   // OUT_HANKEL: out[y*ldo + m] = y[m] / cnt(m), m < N
+    long long ldo;
+};
+
+struct ReduceArgs {
+    const double* part;
+    int nchunks, pstride, ncols;
+    float* r;
+    long long n;
+    const float* basis;
+    long long ld;
+    double* h;          // out: projection coefficients (ncols)
+    double* coef_out;   // out: alpha_j or beta_{j+1} (the B entry)
+    double* scale_out;  // out: normalization factor for the new vector
+    double* state;      // [0] running max of |B| entries, [1] restarts, [2] DGKS passes
+    unsigned long long seed, stream_ctr;
+    int track;          // 1: the coefficient is an entry of B (count it in state[0])
+    int full;           // 1: the basis already spans the whole space -> zero vector
+    double tol_bd;      // breakdown threshold relative to state[0]
+};
+
+constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many terms are summed directly
+constexpr int kDotsRows = 1024;  // rows per workgroup in the projection kernel
+constexpr int kDotsCols = 16;    // basis columns per workgroup in the projection kernel
+
+// launchers (kernels.hip); each returns hipSuccess or the launch error
+hipError_t launch_tables(const ConvGeom& g, float2* tw1, float2* tw2, float2* tw_lo, float2* tw_hi,
+                         hipStream_t s);
+hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, float2* T1,
+                        hipStream_t s);
+hipError_t launch_pass2_matvec(const ConvGeom& g, const float4* AB, const float2* T1, float2* T2,
+                               hipStream_t s);
+hipError_t launch_pass2_embed(const ConvGeom& g, const float2* T1, float4* AB, hipStream_t s);
+hipError_t launch_pass2_recon(const ConvGeom& g, const float2* T1all, int k, const double* sigma,
+                              const int* offs, const int* members, int g0, int ng, float2* T2all,
+                              hipStream_t s);
+hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3Out& o, int nvec,
+                        hipStream_t s);
+hipError_t launch_recon_edges(const double* sigma, const float* U, long long ldu, const float* V, long long ldv,
+                              const int* offs, const int* members, int ng, long long N, long long L, long long K,
+                              float* out, long long ldo, hipStream_t s);
+hipError_t launch_check_finite(const double* f, long long N, double* flag, hipStream_t s);
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, hipStream_t s);
+hipError_t launch_cgs_dots(const float* basis, long long ld, int ncols, const float* r, long long n,
+                           double* part, int pstride, hipStream_t s);
+hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols,
+                             const double* h, const double* scale, float* out, long long n,
+                             hipStream_t s);
+hipError_t launch_ritz(const float* basis, long long ld, int ncols, const double* P, int k,
+                       float* out, long long ldo, long long n, hipStream_t s);
+hipError_t set_kernel_attributes();
+
+// host small eigen/singular solver (small_svd.cpp)
+// Ritz values of the (d+1) x d lower bidiagonal B_d (alpha[1..d] on the
+// diagonal, beta[2..d+1] below it; arrays indexed as in Algorithm 1).
+// Writes the k largest omega (descending) and their residual bounds
+// alpha[d+1] * |P[d, i]| (the last component of the left singular vector).
+void bidiag_ritz_values(const double* alpha, const double* beta, int d, int k, double* omega,
+                        double* resid, double* work);
+// Top-k singular triples of B_d: omega[k], P ((d+1) x k row-major), Q (d x k row-major).
+void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, double* omega,
+                         double* P, double* Q, double* work);
+size_t bidiag_work_doubles(int d);
+
+}  // namespace ssa

@@ -1,0 +1,232 @@
+"""ctypes binding of the HIP library (``include/ssa.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libssa_hip.so``.  PyTorch supplies device memory (the workspace
+and the result tensors) and the stream.  There is no CPU fallback: if the
+library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssa_hip.so")
+
+SSA_OK = 0
+SSA_WARN_NOT_CONVERGED = 1
+SSA_EINVAL = -1
+SSA_ENOMEM = -2
+SSA_ENONFINITE = -3
+SSA_EDEVICE = -4
+SSA_EMISMATCH = -5
+SSA_ESTATE = -6
+
+_c_ll = ctypes.c_longlong
+_c_p = ctypes.c_void_p
+
+
+class SsaOpts(ctypes.Structure):
+    _fields_ = [("d_max", ctypes.c_int), ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_ulonglong)]
+
+
+class SsaInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("dgks_passes", ctypes.c_int), ("resid", ctypes.c_double * 64)]
+
+
+class SsaPlanDesc(ctypes.Structure):
+    _fields_ = [("N", _c_ll), ("L", _c_ll), ("K", _c_ll), ("M", _c_ll), ("M1", _c_ll), ("M2", _c_ll),
+                ("d_max", ctypes.c_int), ("k_max", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t)]
+
+
+EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
+            "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
+            "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read")
+
+# kernel classes of ssa_profile_read (enum ssa_prof_class)
+PROF_CLASSES = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz",
+                "recon_pass1", "recon_pass2", "recon_pass3", "embed")
+
+_lib = None
+
+
+class SsaError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_str(code)} ({code})")
+
+
+def load():
+    """Load ``libssa_hip.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python -m paper_0911_4498_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.ssa_embed_plan.argtypes = [_c_ll, _c_ll, ctypes.c_int, ctypes.POINTER(SsaOpts),
+                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_c_p)]
+    lib.ssa_plan_bind.argtypes = [_c_p, _c_p, ctypes.c_size_t, _c_p]
+    lib.ssa_embed.argtypes = [_c_p, _c_p]
+    lib.ssa_matvec.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p]
+    lib.ssa_truncated_svd.argtypes = [_c_p, _c_p, _c_ll, _c_ll, ctypes.c_int, _c_p, _c_p, _c_p,
+                                      ctypes.POINTER(SsaInfo)]
+    lib.ssa_reconstruct.argtypes = [_c_p, _c_p, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_int, _c_p]
+    lib.ssa_plan_describe.argtypes = [_c_p, ctypes.POINTER(SsaPlanDesc)]
+    lib.ssa_plan_destroy.argtypes = [_c_p]
+    lib.ssa_plan_destroy.restype = None
+    lib.ssa_status_str.argtypes = [ctypes.c_int]
+    lib.ssa_status_str.restype = ctypes.c_char_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.ssa_bidiag_ritz.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+    lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_int]
+    lib.ssa_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), dp, dp]
+    for name in EXPORTED:
+        if name not in ("ssa_plan_destroy", "ssa_status_str"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    try:
+        return load().ssa_status_str(int(code)).decode()
+    except RuntimeError:
+        return "library not loaded"
+
+
+def _check(rc: int, where: str, allow_warn: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_warn):
+        raise SsaError(rc, where)
+    return rc
+
+
+def bidiag_ritz(alpha, beta, d: int, k: int, vectors: bool = False):
+    """Host utility: Ritz values (and optionally vectors) of the Lanczos bidiagonal B_d."""
+    import numpy as np
+    lib = load()
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    om = np.zeros(k)
+    res = np.zeros(k)
+    dp = ctypes.POINTER(ctypes.c_double)
+    P = np.zeros((d + 1, k)) if vectors else None
+    Q = np.zeros((d, k)) if vectors else None
+    rc = lib.ssa_bidiag_ritz(a.ctypes.data_as(dp), b.ctypes.data_as(dp), d, k, om.ctypes.data_as(dp),
+                             res.ctypes.data_as(dp), P.ctypes.data_as(dp) if vectors else None,
+                             Q.ctypes.data_as(dp) if vectors else None)
+    _check(rc, "ssa_bidiag_ritz")
+    return (om, res, P, Q) if vectors else (om, res)
+
+
+class Plan:
+    """One series geometry (N, L) bound to a torch-allocated device workspace."""
+
+    def __init__(self, N: int, L: int, k_max: int, d_max: int = 0, check_every: int = 0,
+                 tol: float = 0.0, seed: int = 0, device=None, stream=None):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.lib = lib
+        self.N, self.L, self.K = int(N), int(L), int(N) - int(L) + 1
+        self.k_max = int(k_max)
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed))
+        ws = ctypes.c_size_t(0)
+        h = _c_p()
+        _check(lib.ssa_embed_plan(self.N, self.L, self.k_max, ctypes.byref(opts), ctypes.byref(ws),
+                                  ctypes.byref(h)), "ssa_embed_plan")
+        self._h = h
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib.ssa_plan_bind(h, base + off, int(ws.value), self.stream.cuda_stream), "ssa_plan_bind")
+        d = SsaPlanDesc()
+        _check(lib.ssa_plan_describe(h, ctypes.byref(d)), "ssa_plan_describe")
+        self.desc = d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.ssa_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile_enable(self, on: bool = True):
+        """Bracket every launch with HIP events (and clear the counters)."""
+        _check(self.lib.ssa_profile_enable(self._h, 1 if on else 0), "ssa_profile_enable")
+
+    def profile_read(self):
+        """{class: (launches, event-timed ms, algorithmic bytes)} since profile_enable."""
+        out = {}
+        for i, name in enumerate(PROF_CLASSES):
+            n = _c_ll(0)
+            ms = ctypes.c_double(0)
+            b = ctypes.c_double(0)
+            _check(self.lib.ssa_profile_read(self._h, i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)),
+                   "ssa_profile_read")
+            out[name] = (int(n.value), float(ms.value), float(b.value))
+        return out
+
+    def _series(self, f):
+        torch = self._torch
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        if f.numel() != self.N:
+            raise ValueError("series length differs from the plan")
+        return f
+
+    def embed(self, f):
+        f = self._series(f)
+        self._keep = f
+        _check(self.lib.ssa_embed(self._h, f.data_ptr()), "ssa_embed")
+
+    def matvec(self, x, transpose: bool = False):
+        """X x (x has K entries) or X^T x (x has L entries), FP32 on the device."""
+        torch = self._torch
+        n_in = self.L if transpose else self.K
+        n_out = self.K if transpose else self.L
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        if x.numel() != n_in:
+            raise ValueError("vector length does not match")
+        y = torch.empty(n_out, dtype=torch.float32, device=self.device)
+        _check(self.lib.ssa_matvec(self._h, 1 if transpose else 0, x.data_ptr(), y.data_ptr()), "ssa_matvec")
+        return y
+
+    def truncated_svd(self, f, k: int):
+        """Returns (sigma [k] f64, U [k, L] f32, V [k, K] f32, info); row i of U is u_i."""
+        torch = self._torch
+        f = self._series(f)
+        sigma = torch.empty(k, dtype=torch.float64, device=self.device)
+        U = torch.empty((k, self.L), dtype=torch.float32, device=self.device)
+        V = torch.empty((k, self.K), dtype=torch.float32, device=self.device)
+        info = SsaInfo()
+        rc = self.lib.ssa_truncated_svd(self._h, f.data_ptr(), self.N, self.L, int(k), sigma.data_ptr(),
+                                        U.data_ptr(), V.data_ptr(), ctypes.byref(info))
+        _check(rc, "ssa_truncated_svd", allow_warn=True)
+        return sigma, U, V, info
+
+    def reconstruct(self, sigma, U, V, groups):
+        """One series per group of triple indices; returns an (m, N) float32 tensor."""
+        torch = self._torch
+        k = int(sigma.numel())
+        offs = [0]
+        mem: list[int] = []
+        for g in groups:
+            mem.extend(int(i) for i in g)
+            offs.append(len(mem))
+        m = len(groups)
+        offs_a = (ctypes.c_int * len(offs))(*offs)
+        mem_a = (ctypes.c_int * max(1, len(mem)))(*(mem if mem else [0]))
+        out = torch.empty((m, self.N), dtype=torch.float32, device=self.device)
+        rc = self.lib.ssa_reconstruct(self._h, sigma.data_ptr(), U.contiguous().data_ptr(),
+                                      V.contiguous().data_ptr(), k, ctypes.cast(offs_a, _c_p),
+                                      ctypes.cast(mem_a, _c_p), m, out.data_ptr())
+        _check(rc, "ssa_reconstruct")
+        return out

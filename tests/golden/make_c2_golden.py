@@ -1,0 +1,58 @@
+"""Write tests/golden/c2_oracle.json: expected values for the N=100000, L=50000,
+k=20 workload, computed ONLY by the FP64 oracle (tier B: Algorithm 1 with full
+reorthogonalization and row-by-row products, Sec. 3.1-3.2), for the seeded
+series of ``paper_0911_4498_amd.inputs.c2_series``.
+
+Stored: the 24 leading singular values, and the elementary reconstructed
+series of each of the first 20 triples (Sec. 2.3-2.4 diagonal averaging of
+sigma_i u_i v_i^T) at 512 fixed sample indices; a test sums the members of a
+cluster of near-equal values itself.
+
+Usage: python tests/golden/make_c2_golden.py   (several minutes, all cores)
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_0911_4498_amd import inputs  # noqa: E402
+
+N, L, K_TRIPLES, K_EXTRA = 100_000, 50_000, 20, 4
+
+
+def main():
+    f = inputs.c2_series(N)
+    k = K_TRIPLES + K_EXTRA
+    p0 = inputs.start_vector(L, 4242)
+    t0 = time.time()
+    s, U, V, steps, conv = oracle.lanczos_svd(f, L, k, p0, d_max=400, check_every=8, tol=1e-12)
+    t1 = time.time()
+    print(f"tier B: {steps} steps, converged={conv}, {t1 - t0:.1f} s, threads={oracle.num_threads()}")
+    rng = np.random.default_rng(77)
+    idx = np.unique(np.concatenate([np.arange(0, 64), np.arange(N - 64, N), L + np.arange(-32, 32),
+                                    rng.integers(0, N, 384)]))[:512]
+    groups = [[i] for i in range(K_TRIPLES)]
+    rec = oracle.reconstruct(N, L, s[:K_TRIPLES], U[:, :K_TRIPLES], V[:, :K_TRIPLES], groups)
+    out = {
+        "workload": "c2 synthetic: N=100000, L=50000, k=20 (seeded inputs.c2_series)",
+        "oracle": "tier B (Algorithm 1, MGS-twice full reorthogonalization, direct products), FP64",
+        "steps": int(steps), "converged": bool(conv),
+        "sigma": [float(x) for x in s],
+        "sample_index": [int(i) for i in idx],
+        "recon_per_triple": [[float(x) for x in r[idx]] for r in rec],
+        "series_inf_norm": float(np.abs(f).max()),
+    }
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", path, f"total {time.time() - t0:.1f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,321 @@
+"""Parity of the HIP path against the FP64 oracle (needs an MI355X).
+
+Every call goes through the C ABI (ctypes binding).  Inputs are the seeded
+generators of ``paper_0911_4498_amd.inputs``; expected values come from the
+oracle (``oracle/``) or from ``tests/golden`` files that the oracle wrote.
+Tolerances are those of ``tests/parity.py``; the matrix-vector products use
+the FFT error bound stated in ``mv_tol``.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_0911_4498_amd import inputs
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_0911_4498_amd import ssa as mod
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mv_tol(f, x, M):
+    """FFT convolution in FP32: |y - y_exact|_inf <= |y - y_exact|_2 <= c eps log2(M) max|C| |x|_2,
+    with max|C| <= |f|_1 (the spectrum of the series) and c = 10 covering the packing,
+    the spectral operator and both transforms."""
+    return 10.0 * EPS32 * np.log2(2 * M) * np.abs(f).sum() * np.linalg.norm(x) + 1e-30
+
+
+def hankel(f, L):
+    return scipy.linalg.hankel(f[:L], f[L - 1:])
+
+
+def test_native_library_is_loaded(ssa):
+    import ctypes
+    lib = ssa.load()
+    assert os.path.dirname(os.path.abspath(ssa.LIB_PATH)).endswith("paper_0911_4498_amd")
+    assert isinstance(lib, ctypes.CDLL)
+
+
+# --- Algorithms 2/3: X v and X^T u by FFT ------------------------------------------
+
+def test_matvec_every_small_window(ssa):
+    rng = np.random.default_rng(0)
+    for N in range(3, 41):
+        f = rng.normal(size=N)
+        for L in range(2, N):
+            K = N - L + 1
+            say(f"matvec N={N} L={L}")
+            plan = ssa.Plan(N, L, 1)
+            plan.embed(torch.tensor(f, device="cuda"))
+            v = rng.normal(size=K)
+            u = rng.normal(size=L)
+            X = hankel(f, L)
+            y = plan.matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()
+            yt = plan.matvec(torch.tensor(u, dtype=torch.float32, device="cuda"), transpose=True).cpu().numpy()
+            M = plan.desc.M
+            assert np.abs(y - X @ v).max() <= mv_tol(f, v, M), (N, L)
+            assert np.abs(yt - X.T @ u).max() <= mv_tol(f, u, M), (N, L)
+            plan.close()
+
+
+@pytest.mark.parametrize("N,L", [(1000, 500), (1001, 250), (10007, 5003), (4096, 3000), (20000, 19990),
+                                 (65536, 1000), (100000, 50000), (100001, 77777)])
+def test_matvec_large(ssa, N, L):
+    say(f"matvec large N={N} L={L}")
+    K = N - L + 1
+    f = inputs.c2_series(N) if N >= 65536 else inputs.white(N, N) + inputs.sinusoid(N, 37.0, 3.0)
+    rng = np.random.default_rng(N + L)
+    v = rng.normal(size=K)
+    u = rng.normal(size=L)
+    plan = ssa.Plan(N, L, 1)
+    plan.embed(torch.tensor(f, device="cuda"))
+    y = plan.matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yt = plan.matvec(torch.tensor(u, dtype=torch.float32, device="cuda"), transpose=True).cpu().numpy()
+    # the oracle evaluates each entry as a row (column) of X dotted with the FP32-rounded vector
+    vr = v.astype(np.float32).astype(np.float64)
+    ur = u.astype(np.float32).astype(np.float64)
+    ref = oracle.matvec(f, L, vr)
+    reft = oracle.rmatvec(f, L, ur)
+    e1 = np.abs(y - ref).max()
+    e2 = np.abs(yt - reft).max()
+    say(f"  max err X v {e1:.3e} (bound {mv_tol(f, v, plan.desc.M):.3e}), X^T u {e2:.3e}")
+    assert e1 <= mv_tol(f, v, plan.desc.M)
+    assert e2 <= mv_tol(f, u, plan.desc.M)
+
+
+def test_embed_rejects_nonfinite(ssa):
+    f = inputs.white(100, 1)
+    f[37] = np.nan
+    plan = ssa.Plan(100, 40, 3)
+    with pytest.raises(ssa.SsaError) as ei:
+        plan.embed(torch.tensor(f, device="cuda"))
+    assert ei.value.code == ssa.SSA_ENONFINITE
+    f[37] = np.inf
+    with pytest.raises(ssa.SsaError):
+        plan.truncated_svd(torch.tensor(f, device="cuda"), 2)
+    with pytest.raises(ssa.SsaError) as ei:
+        plan.matvec(torch.zeros(61, device="cuda"))
+    assert ei.value.code == ssa.SSA_ESTATE
+
+
+# --- truncated SVD (Algorithm 1 + FRO) and reconstruction ---------------------------
+
+def run_gpu(ssa, f, L, k, **kw):
+    N = len(f)
+    plan = ssa.Plan(N, L, k, **kw)
+    s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), k)
+    return plan, s, U, V, info
+
+
+def check_against_dense(ssa, f, L, k, extra=4, groups_of_clusters=True):
+    N = len(f)
+    K = N - L + 1
+    kr = min(k + extra, min(L, K))
+    sA, UA, VA = oracle.ssa_dense(f, L, kr)
+    plan, s, U, V, info = run_gpu(ssa, f, L, k)
+    sg = s.cpu().numpy()
+    Ug = U.cpu().numpy().T.astype(np.float64)
+    Vg = V.cpu().numpy().T.astype(np.float64)
+    fro = parity.frobenius(f, L)
+    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, fro)
+    # reconstructions: isolated triples and whole clusters
+    groups = [c for c in parity.clusters(sA, k, fro) if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
+    rg = plan.reconstruct(s, U, V, groups).cpu().numpy()
+    ro = oracle.reconstruct(N, L, sA[:k], UA[:, :k], VA[:, :k], groups)
+    rep["recon_err"] = parity.compare_recon(rg, ro, np.abs(f).max())
+    rep["steps"] = info.steps
+    rep["converged"] = info.converged
+    say(f"  N={N} L={L} k={k}: {rep}")
+    return rep
+
+
+def test_svd_c1_workload(ssa):
+    """N=1000, L=500, k=10 (two sinusoids + trend + noise) against the dense oracle."""
+    say("svd c1")
+    rep = check_against_dense(ssa, inputs.c1_series(), 500, 10)
+    assert rep["converged"] == 1
+
+
+@pytest.mark.parametrize("N,L,k,kind", [(64, 32, 8, "white"), (50, 20, 20, "white"), (200, 150, 12, "c1"),
+                                        (257, 64, 6, "sine"), (999, 333, 16, "c1"), (1500, 750, 20, "c1"),
+                                        (1600, 400, 16, "c3")])
+def test_svd_various(ssa, N, L, k, kind):
+    say(f"svd {kind} N={N} L={L} k={k}")
+    if kind == "white":
+        f = inputs.white(N, N + L)
+    elif kind == "sine":
+        f = inputs.sinusoid(N, 23.0, 2.0) + 0.05 * inputs.white(N, 3)
+    elif kind == "c3":
+        f, _, _ = inputs.c3_series(7, N=N)
+    else:
+        f = inputs.c1_series(N)
+    check_against_dense(ssa, f, L, k)
+
+
+def test_svd_window_longer_than_lag_count(ssa):
+    """L > K is solved through X^T (Sec. 2.2 assumes L <= K without loss of generality)."""
+    say("svd L>K")
+    check_against_dense(ssa, inputs.c1_series(600), 450, 8)
+
+
+def test_exact_rank_series(ssa):
+    """Finite-rank series: a sinusoid gives two nonzero singular values, an exponential
+    one; asking for more triples exercises the breakdown restart."""
+    say("exact rank")
+    N, L = 999, 500
+    f = inputs.sinusoid(N, 10.0, 1.3, 0.4)
+    plan, s, U, V, info = run_gpu(ssa, f, L, 4)
+    s = s.cpu().numpy()
+    expect = 1.3 * np.sqrt(L * (N - L + 1)) / 2
+    np.testing.assert_allclose(s[:2], [expect, expect], rtol=1e-5)
+    assert np.all(s[2:] <= 1e-5 * expect), s
+    assert np.all(np.isfinite(U.cpu().numpy())) and np.all(np.isfinite(V.cpu().numpy()))
+    f = inputs.geometric(300, 1.7, 0.99)
+    plan, s, U, V, info = run_gpu(ssa, f, 120, 3)
+    s = s.cpu().numpy()
+    sA, _, _ = oracle.ssa_dense(f, 120, 3)
+    np.testing.assert_allclose(s[0], sA[0], rtol=1e-5)
+    assert np.all(s[1:] <= 1e-5 * s[0])
+
+
+def test_paper_rank5_series_reconstruction(ssa):
+    """Sec. 6.3's rank-5 series: five triples reconstruct the series (complete
+    reconstruction of a finite-rank series)."""
+    say("rank5")
+    N, L = 1000, 500
+    f = inputs.rank5_example(N)
+    plan, s, U, V, info = run_gpu(ssa, f, L, 6)
+    s = s.cpu().numpy()
+    assert s[5] <= 1e-5 * s[0]
+    rec = plan.reconstruct(torch.tensor(s[:5], device="cuda"), U[:5], V[:5], [list(range(5))]).cpu().numpy()
+    assert np.abs(rec[0] - f).max() <= 1e-5 * np.abs(f).max()
+
+
+def test_reconstruct_matches_oracle_on_shared_inputs(ssa):
+    """Algorithm 4 alone: the same seeded (sigma, u, v) through the GPU and the oracle."""
+    rng = np.random.default_rng(9)
+    for N, L in [(37, 12), (1000, 500), (1000, 900), (4099, 1024), (100000, 50000)]:
+        say(f"reconstruct shared N={N} L={L}")
+        K = N - L + 1
+        k = 5
+        s = np.sort(rng.uniform(1, 10, k))[::-1].copy()
+        U = rng.normal(size=(L, k)) / np.sqrt(L)
+        V = rng.normal(size=(K, k)) / np.sqrt(K)
+        U32 = U.astype(np.float32)
+        V32 = V.astype(np.float32)
+        groups = [[0], [1, 2], [4, 3, 0], []] if N < 5000 else [[0], [1, 2]]
+        plan = ssa.Plan(N, L, k)
+        out = plan.reconstruct(torch.tensor(s, device="cuda"), torch.tensor(U32.T.copy(), device="cuda"),
+                               torch.tensor(V32.T.copy(), device="cuda"), groups).cpu().numpy()
+        if N <= 5000:
+            ref = oracle.reconstruct(N, L, s, U32.astype(np.float64), V32.astype(np.float64), groups)
+        else:  # at this size compare sampled entries of the direct antidiagonal sums
+            ref = None
+        if ref is not None:
+            scale = np.abs(ref).max() + 1e-30
+            assert np.abs(out - ref).max() <= 1e-5 * scale, np.abs(out - ref).max() / scale
+        else:
+            idx = rng.integers(0, N, 64)
+            for gi, g in enumerate(groups):
+                for n in idx:
+                    a = np.arange(max(0, n - K + 1), min(L, n + 1))
+                    val = sum(s[i] * np.dot(U32[a, i].astype(np.float64), V32[n - a, i].astype(np.float64))
+                              for i in g) / len(a)
+                    assert abs(out[gi, n] - val) <= 1e-5 * (abs(val) + 1e-3), (gi, n, out[gi, n], val)
+
+
+def test_reconstruct_validates_groups(ssa):
+    plan = ssa.Plan(100, 40, 4)
+    s = torch.ones(4, dtype=torch.float64, device="cuda")
+    U = torch.zeros((4, 40), device="cuda")
+    V = torch.zeros((4, 61), device="cuda")
+    for bad in ([[4]], [[0, 0]], [[-1]]):
+        with pytest.raises(ssa.SsaError) as ei:
+            plan.reconstruct(s, U, V, bad)
+        assert ei.value.code == ssa.SSA_EINVAL
+
+
+def test_determinism(ssa):
+    say("determinism")
+    f = inputs.c1_series()
+    out = []
+    for _ in range(2):
+        plan, s, U, V, info = run_gpu(ssa, f, 500, 10)
+        rec = plan.reconstruct(s, U, V, [[0], [1, 2]])
+        out.append((s.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy(), rec.cpu().numpy(), info.steps))
+    for a, b in zip(out[0][:4], out[1][:4]):
+        assert np.array_equal(a, b)
+    assert out[0][4] == out[1][4]
+
+
+# --- the N=100000 workload at full size ---------------------------------------------
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
+def test_c2_full_size(ssa):
+    """N=100000, L=50000, k=20: sigma and sampled reconstructions vs the tier-B oracle
+    (stored), plus residual and orthogonality certificates computed here in FP64."""
+    say("c2 full size")
+    g = json.load(open(GOLDEN))
+    N, L, k = 100_000, 50_000, 20
+    K = N - L + 1
+    f = inputs.c2_series(N)
+    plan, s, U, V, info = run_gpu(ssa, f, L, k)
+    sg = s.cpu().numpy()
+    s_ref = np.array(g["sigma"])
+    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")
+    say(f"  sigma rel err max {np.max(np.abs(sg - s_ref[:k]) / s_ref[:k]):.2e}")
+    parity.assert_sigma(sg, s_ref[:k])
+    fro = parity.frobenius(f, L)
+    groups = [c for c in parity.clusters(s_ref, k, fro) if max(c) < k]
+    rec = plan.reconstruct(s, U, V, groups).cpu().numpy()
+    idx = np.array(g["sample_index"])
+    per_triple = np.array(g["recon_per_triple"])
+    ref = np.array([per_triple[c].sum(axis=0) for c in groups])
+    say(f"  groups compared: {groups}")
+    err = np.abs(rec[:, idx] - ref).max()
+    say(f"  sampled reconstruction err {err:.3e} (|F|inf={g['series_inf_norm']:.3f})")
+    assert err <= parity.RECON_REL * g["series_inf_norm"]
+    # certificates: X v_i = sigma_i u_i and X^T u_i = sigma_i v_i, in FP64 (library FFT)
+    Ug = U.cpu().numpy().astype(np.float64)
+    Vg = V.cpu().numpy().astype(np.float64)
+    Mfft = 1 << int(np.ceil(np.log2(2 * N)))
+    F = np.fft.rfft(f, Mfft)
+
+    def Xv(v):  # (X v)[i] = sum_j f[i+j] v[j]
+        return np.fft.irfft(F * np.fft.rfft(v[::-1], Mfft), Mfft)[K - 1:K - 1 + L]
+
+    def XTu(u):
+        return np.fft.irfft(F * np.fft.rfft(u[::-1], Mfft), Mfft)[L - 1:L - 1 + K]
+
+    worst = 0.0
+    for i in range(k):
+        r1 = np.linalg.norm(Xv(Vg[i]) - sg[i] * Ug[i])
+        r2 = np.linalg.norm(XTu(Ug[i]) - sg[i] * Vg[i])
+        worst = max(worst, r1 / sg[0], r2 / sg[0])
+    say(f"  worst residual / sigma_1 = {worst:.2e}")
+    assert worst <= 1e-5
+    G = Ug @ Ug.T
+    assert np.abs(G - np.eye(k)).max() <= 1e-5

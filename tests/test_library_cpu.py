@@ -1,0 +1,158 @@
+"""Host-side checks of the HIP library that need no GPU.
+
+* the shared library loads and exports every function ``include/ssa.h`` declares;
+* plan sizing (FFT length, split, workspace) and argument validation;
+* the small bidiagonal solver used for the stopping test and the Ritz vectors,
+  against LAPACK (numpy) on the explicit (d+1) x d bidiagonal.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0911_4498_amd import ssa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _built():
+    if not os.path.exists(ssa.LIB_PATH):
+        from paper_0911_4498_amd import build
+        build.build()
+    return ssa.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "ssa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ssa_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _built()
+    names = header_functions()
+    assert "ssa_truncated_svd" in names and "ssa_reconstruct" in names and "ssa_embed_plan" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ssa.EXPORTED)
+
+
+def make_plan(N, L, k, d_max=0):
+    lib = _built()
+    opts = ssa.SsaOpts(d_max, 0, 0.0, 0)
+    ws = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    rc = lib.ssa_embed_plan(N, L, k, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h))
+    return rc, h, ws.value
+
+
+def describe(h):
+    d = ssa.SsaPlanDesc()
+    assert _built().ssa_plan_describe(h, ctypes.byref(d)) == 0
+    return d
+
+
+def smooth7(n):
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+@pytest.mark.parametrize("N,L,k", [(3, 2, 1), (1000, 500, 10), (100000, 50000, 20), (10007, 2501, 16),
+                                   (999, 700, 5), (2**24, 2**23, 50), (65, 2, 2)])
+def test_plan_sizes(N, L, k):
+    lib = _built()
+    rc, h, ws = make_plan(N, L, k)
+    assert rc == 0
+    d = describe(h)
+    try:
+        assert d.M >= N and d.M % 2 == 0
+        assert d.M1 * d.M2 * 2 == d.M
+        assert d.M1 <= 4096 and d.M2 <= 4096 and smooth7(d.M1) and smooth7(d.M2)
+        assert d.K == N - L + 1
+        r = min(L, N - L + 1)
+        assert k <= d.d_max <= r
+        assert ws == d.workspace_bytes and ws > 0
+        # the smallest admissible M: no smaller even M >= N has an admissible split
+        assert d.M // 2 - (N + 1) // 2 < 200
+    finally:
+        lib.ssa_plan_destroy(h)
+
+
+@pytest.mark.parametrize("N,L,k", [(2, 1, 1), (10, 1, 1), (10, 10, 1), (10, 11, 1), (10, 5, 0),
+                                   (10, 5, 6), (10, 8, 4), (-5, 2, 1)])
+def test_plan_rejects_invalid(N, L, k):
+    rc, h, _ = make_plan(N, L, k)
+    assert rc == ssa.SSA_EINVAL
+    assert not h.value
+
+
+def test_unbound_plan_calls_fail_cleanly():
+    lib = _built()
+    rc, h, _ = make_plan(100, 40, 4)
+    assert rc == 0
+    try:
+        assert lib.ssa_embed(h, ctypes.c_void_p(8)) == ssa.SSA_ENOMEM
+        assert lib.ssa_matvec(h, 0, ctypes.c_void_p(8), ctypes.c_void_p(8)) == ssa.SSA_ENOMEM
+        assert lib.ssa_plan_bind(h, None, 0, None) == ssa.SSA_EINVAL
+        assert lib.ssa_plan_bind(h, ctypes.c_void_p(256), 16, None) == ssa.SSA_ENOMEM
+        assert lib.ssa_plan_bind(h, ctypes.c_void_p(257), 1 << 40, None) == ssa.SSA_EINVAL
+        info = ssa.SsaInfo()
+        p8 = ctypes.c_void_p(256)
+        assert lib.ssa_truncated_svd(h, p8, 100, 40, 5, p8, p8, p8, ctypes.byref(info)) == ssa.SSA_EINVAL
+        assert lib.ssa_truncated_svd(h, p8, 101, 40, 2, p8, p8, p8, ctypes.byref(info)) == ssa.SSA_EMISMATCH
+        assert lib.ssa_truncated_svd(h, p8, 100, 40, 2, p8, p8, p8, ctypes.byref(info)) == ssa.SSA_ENOMEM
+    finally:
+        lib.ssa_plan_destroy(h)
+    assert ssa.status_str(ssa.SSA_ENONFINITE) == "series holds NaN or Inf"
+
+
+def bidiag(alpha, beta, d):
+    B = np.zeros((d + 1, d))
+    for c in range(d):
+        B[c, c] = alpha[c + 1]
+        B[c + 1, c] = beta[c + 2]
+    return B
+
+
+@pytest.mark.parametrize("d,k,seed", [(5, 3, 0), (40, 10, 1), (120, 20, 2), (300, 50, 3), (1, 1, 4)])
+def test_bidiag_ritz_matches_lapack(d, k, seed):
+    rng = np.random.default_rng(seed)
+    alpha = np.abs(rng.normal(size=d + 3)) + 0.1
+    beta = np.abs(rng.normal(size=d + 3)) + 0.1
+    alpha[0] = beta[0] = beta[1] = 0.0
+    B = bidiag(alpha, beta, d)
+    P_ref, s_ref, Qt_ref = np.linalg.svd(B, full_matrices=False)
+    om, res = ssa.bidiag_ritz(alpha, beta, d, k)
+    kk = min(k, d)
+    np.testing.assert_allclose(om[:kk], s_ref[:kk], rtol=1e-12, atol=1e-13 * s_ref[0])
+    np.testing.assert_allclose(res[:kk], alpha[d + 1] * np.abs(P_ref[d, :kk]), rtol=1e-7,
+                               atol=1e-12 * s_ref[0])
+    om2, _, P, Q = ssa.bidiag_ritz(alpha, beta, d, k, vectors=True)
+    np.testing.assert_allclose(om2[:kk], s_ref[:kk], rtol=1e-12)
+    # singular pairs: B q = omega p, orthonormal columns
+    np.testing.assert_allclose(B @ Q[:, :kk], P[:, :kk] * om2[:kk], atol=1e-11 * s_ref[0])
+    np.testing.assert_allclose(Q[:, :kk].T @ Q[:, :kk], np.eye(kk), atol=1e-11)
+    np.testing.assert_allclose(P[:, :kk].T @ P[:, :kk], np.eye(kk), atol=1e-11)
+
+
+def test_bidiag_ritz_clustered_and_zero_entries():
+    """Exactly repeated singular values and vanishing alpha/beta (a split B) still give
+    orthonormal vectors that span the right subspaces."""
+    d, k = 12, 8
+    alpha = np.zeros(d + 3)
+    beta = np.zeros(d + 3)
+    alpha[1:d + 1] = 1.0
+    beta[2:d + 2] = 0.0
+    alpha[3] = 2.0
+    alpha[7] = 2.0  # sigma = 2 twice, then ones
+    beta[5] = 0.5
+    B = bidiag(alpha, beta, d)
+    s_ref = np.linalg.svd(B, compute_uv=False)
+    om, _, P, Q = ssa.bidiag_ritz(alpha, beta, d, k, vectors=True)
+    np.testing.assert_allclose(om, s_ref[:k], rtol=1e-12)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-10)
+    np.testing.assert_allclose(B @ Q, P * om, atol=1e-10)
