@@ -66,6 +66,8 @@ typedef struct {
     int converged;     /* 1 if the stopping rule held, 0 if d_max was reached                */
     int restarts;      /* vanishing alpha/beta replaced by fresh random directions           */
     int dgks_passes;   /* second Gram-Schmidt passes triggered by the DGKS criterion          */
+    int steps_run;     /* Lanczos steps executed (>= steps: the stopping test of one check
+                          point overlaps the next steps, which are then discarded)           */
     double resid[64];  /* residual bounds alpha_{d+1} |P[d+1,i]| of the first min(k,64) triples */
 } ssa_info;
 

@@ -93,6 +93,7 @@ struct ssa_plan_s {
     double* h_flag = nullptr;
     int* h_grp = nullptr;
     hipEvent_t grp_done = nullptr;
+    hipEvent_t chk_ev[2] = {nullptr, nullptr};
     std::vector<double> work;
     // optional per-kernel-class timing (HIP events around each launch)
     int prof_on = 0;
@@ -231,16 +232,11 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
                    unsigned long long ctr) {
     hipStream_t s = p->stream;
     float* r = at<float>(p, p->o_r);
-    double* part = at<double>(p, p->o_part);
     double* h = at<double>(p, p->o_h);
     double* sc = at<double>(p, p->o_sc);
-    {
-        ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)n * (ncols + 1));
-        SSA_TRY(launch_cgs_dots(basis, ld, ncols, r, n, part, p->pstride, s));
-    }
     ReduceArgs a{};
-    a.part = part;
-    a.nchunks = (int)((n + kDotsRows - 1) / kDotsRows);
+    a.part = at<double>(p, p->o_part);
+    a.nchunks = (int)((n + kProjRows - 1) / kProjRows);
     a.pstride = p->pstride;
     a.ncols = ncols;
     a.r = r;
@@ -256,9 +252,10 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     a.track = track;
     a.full = ncols >= n ? 1 : 0;
     a.tol_bd = kBreakdownTol;
+    a.counter = at<unsigned>(p, p->o_flag) + 16;
     {
-        ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)a.nchunks * (ncols + 1));
-        SSA_TRY(launch_cgs_reduce(a, s));
+        ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)n * (ncols + 1));
+        SSA_TRY(launch_cgs_project(a, s));
     }
     {
         ProfScope ps(p, SSA_PROF_UPDATE, 4.0 * (double)n * (ncols + 2));
@@ -347,7 +344,7 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, si
     p->ldU = (long long)align_up((size_t)p->Li, 64);
     p->ldV = (long long)align_up((size_t)p->Ki, 64);
     p->pstride = d_max + 2;
-    p->nchunks_max = (int)((p->Ki + kDotsRows - 1) / kDotsRows);
+    p->nchunks_max = (int)((p->Ki + kProjRows - 1) / kProjRows);
     layout(p);
     p->work.resize(bidiag_work_doubles(d_max) + 16);
     *workspace_bytes = p->ws_bytes;
@@ -362,7 +359,7 @@ int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_strea
     std::call_once(g_attr_once, [] { g_attr_err = set_kernel_attributes(); });
     if (g_attr_err != hipSuccess) return SSA_EDEVICE;
     if (!p->h_scal) {
-        const size_t nd = 2 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->k_max + p->k_max + 8;
+        const size_t nd = 4 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->k_max + p->k_max + 8;
         if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * nd, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
         if (hipHostMalloc((void**)&p->h_flag, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
@@ -370,6 +367,8 @@ int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_strea
         if (hipHostMalloc((void**)&p->h_grp, sizeof(int) * p->grp_ints, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
         if (hipEventCreateWithFlags(&p->grp_done, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
+        for (hipEvent_t& e : p->chk_ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
     }
     p->ws = static_cast<char*>(workspace_dev);
     p->stream = static_cast<hipStream_t>(hip_stream);
@@ -415,6 +414,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     SSA_TRY(launch_fill_zero(alpha, p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(beta, p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_flag) + 8, 8, s));  // projection ticket counter
 
     // Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0
     SSA_TRY(launch_start_vector(r, Li, p->seed, s));
@@ -422,14 +422,39 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     if (rc != SSA_OK) return rc;
 
     const int d_cap = (int)std::min<long long>(p->d_max, std::min(Li, Ki));
-    double* h_alpha = p->h_scal;
-    double* h_beta = p->h_scal + (p->d_max + 3);
-    double* h_P = h_beta + (p->d_max + 3);
+    const size_t abn = (size_t)(p->d_max + 3);
+    double* h_ab[2] = {p->h_scal, p->h_scal + 2 * abn};  // alpha | beta, double-buffered
+    double* h_P = p->h_scal + 4 * abn;
     double* h_Q = h_P + (size_t)(p->d_max + 1) * p->k_max;
     double* h_sig = h_Q + (size_t)p->d_max * p->k_max;
     std::vector<double> w(k), wprev(k), res(k);
     bool have_prev = false, converged = false;
-    int d = 0;
+    int d = 0, steps_run = 0;
+    const double* fin = nullptr;
+    // Stopping test on B_jj (its residual bound needs alpha_{jj+1}).  The test
+    // of one check point runs on the host while the GPU works through the
+    // steps enqueued after it, so the GPU never waits for the host; if it
+    // stops there, the speculative steps beyond jj are discarded.
+    auto evaluate = [&](int jj, const double* ab) -> bool {
+        bidiag_ritz_values(ab, ab + abn, jj, k, w.data(), res.data(), p->work.data());
+        bool ok = have_prev;
+        for (int i = 0; i < k && ok; ++i) {
+            const double scale = std::max(w[i], kResidFloor * w[0]);
+            if (res[i] > p->tol * scale) ok = false;
+            if (std::fabs(w[i] - wprev[i]) > 10.0 * p->tol * scale) ok = false;
+        }
+        if (jj >= std::min(Li, Ki)) ok = true;  // Krylov space exhausted: B is exact
+        wprev = w;
+        have_prev = true;
+        if (ok || jj >= d_cap) {
+            converged = ok;
+            d = jj;
+            fin = ab;
+            return true;
+        }
+        return false;
+    };
+    int pend_jj = -1, pend_buf = 0, cur_buf = 0;
     for (int j = 1;; ++j) {
         // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
         rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, Li, r,
@@ -437,34 +462,37 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         if (rc != SSA_OK) return rc;
         rc = orthonormalize(p, V, p->ldV, j - 1, Ki, alpha + j, 1, 2ULL * j);
         if (rc != SSA_OK) return rc;
-        // stopping test on B_{j-1}, which needs alpha_j for its residual bound
         const int jj = j - 1;
+        steps_run = jj;
+        bool stop = false;
         if (jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
-            SSA_TRY(hipMemcpyAsync(h_alpha, alpha, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-            SSA_TRY(hipMemcpyAsync(h_beta, beta, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-            SSA_TRY(hipStreamSynchronize(s));
-            bidiag_ritz_values(h_alpha, h_beta, jj, k, w.data(), res.data(), p->work.data());
-            bool ok = have_prev;
-            for (int i = 0; i < k && ok; ++i) {
-                const double scale = std::max(w[i], kResidFloor * w[0]);
-                if (res[i] > p->tol * scale) ok = false;
-                if (std::fabs(w[i] - wprev[i]) > 10.0 * p->tol * scale) ok = false;
+            double* buf = h_ab[cur_buf];
+            SSA_TRY(hipMemcpyAsync(buf, alpha, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipMemcpyAsync(buf + abn, beta, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipEventRecord(p->chk_ev[cur_buf], s));
+            if (pend_jj >= 0) {
+                SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
+                stop = evaluate(pend_jj, h_ab[pend_buf]);
             }
-            if (jj >= std::min(Li, Ki)) ok = true;  // Krylov space exhausted: B is exact
-            wprev = w;
-            have_prev = true;
-            if (ok || jj >= d_cap) {
-                converged = ok;
-                d = jj;
-                break;
+            if (!stop) {
+                pend_jj = jj;
+                pend_buf = cur_buf;
+                cur_buf ^= 1;
+                if (jj >= d_cap) {
+                    SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
+                    stop = evaluate(jj, h_ab[pend_buf]);
+                }
             }
         }
+        if (stop) break;
         // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
         rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, Ki, r, U + (long long)(j - 1) * p->ldU, alpha + j);
         if (rc != SSA_OK) return rc;
         rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
         if (rc != SSA_OK) return rc;
     }
+    const double* h_alpha = fin;
+    const double* h_beta = fin + abn;
 
     // Ritz triples of B_d: sigma, U_{d+1} P, V_d Q
     bidiag_ritz_vectors(h_alpha, h_beta, d, k, h_sig, h_P, h_Q, p->work.data());
@@ -493,6 +521,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         info->converged = converged ? 1 : 0;
         info->restarts = (int)st[1];
         info->dgks_passes = (int)st[2];
+        info->steps_run = steps_run;
         for (int i = 0; i < k && i < 64; ++i) info->resid[i] = res[i];
     }
     return converged ? SSA_OK : SSA_WARN_NOT_CONVERGED;
@@ -592,6 +621,8 @@ void ssa_plan_destroy(ssa_plan p) {
         (void)hipEventDestroy(p->grp_done);
     }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->chk_ev)
+        if (e) (void)hipEventDestroy(e);
     if (p->h_scal) (void)hipHostFree(p->h_scal);
     if (p->h_flag) (void)hipHostFree(p->h_flag);
     if (p->h_grp) (void)hipHostFree(p->h_grp);

@@ -515,54 +515,21 @@ __global__ void k_start_vector(float* r, long long n, unsigned long long seed) {
 // ---------------------------------------------------------------------------
 // classical Gram-Schmidt
 
-// part[chunk * pstride + c] = sum over the chunk's rows of basis[c][t] * r[t]
-// (c < ncols), and part[chunk * pstride + ncols] = sum r[t]^2 (column group 0).
-// Products of two FP32 numbers are exact in FP64; sums are FP64.
-__global__ __launch_bounds__(256) void k_cgs_dots(const float* __restrict__ basis, long long ld, int ncols,
-                                                  const float* __restrict__ r, long long n,
-                                                  double* __restrict__ part, int pstride) {
-    constexpr int RPT = kDotsRows / 256, CJ = kDotsCols;
-    __shared__ double red[CJ + 1][4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long long row0 = (long long)blockIdx.x * kDotsRows;
-    const int c0 = blockIdx.y * CJ;
-    const int nc = min(CJ, ncols - c0);
-    float rv[RPT];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        const long long t = row0 + tid + q * 256;
-        rv[q] = t < n ? r[t] : 0.0f;
+// 4 consecutive rows t..t+3 (t a multiple of 4, t < n) of a column whose
+// allocation is padded to a multiple of 64 floats; rows >= n read as zero.
+__device__ __forceinline__ float4 rows4(const float* __restrict__ col, long long t, long long n) {
+    float4 v = *reinterpret_cast<const float4*>(col + t);
+    if (t + 3 >= n) {
+        if (t + 1 >= n) v.y = 0.0f;
+        if (t + 2 >= n) v.z = 0.0f;
+        if (t + 3 >= n) v.w = 0.0f;
     }
-    double acc[CJ + 1];
-#pragma unroll
-    for (int c = 0; c < CJ; ++c) {
-        acc[c] = 0.0;
-        if (c < nc) {
-            const float* col = basis + (long long)(c0 + c) * ld;
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const long long t = row0 + tid + q * 256;
-                if (t < n) acc[c] += (double)col[t] * (double)rv[q];
-            }
-        }
-    }
-    acc[CJ] = 0.0;
-    if (blockIdx.y == 0) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) acc[CJ] += (double)rv[q] * (double)rv[q];
-    }
-#pragma unroll
-    for (int c = 0; c <= CJ; ++c) {
-        const double v = wave_sum(acc[c]);
-        if (lane == 0) red[c][wave] = v;
-    }
-    __syncthreads();
-    if (tid <= CJ) {
-        const int c = tid;
-        const double s = red[c][0] + red[c][1] + red[c][2] + red[c][3];
-        if (c < nc) part[(long long)blockIdx.x * pstride + c0 + c] = s;
-        if (c == CJ && blockIdx.y == 0) part[(long long)blockIdx.x * pstride + ncols] = s;
-    }
+    return v;
+}
+
+__device__ __forceinline__ double dot4(float4 a, float4 b) {
+    return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
+           (double)a.w * (double)b.w;
 }
 
 // block-wide sum (256 threads), result valid in every thread
@@ -613,14 +580,11 @@ __device__ double blk_project(const float* r, long long n, const float* basis, l
 //                B entry becomes 0 and a seeded random direction, made
 //                orthogonal to the basis by two passes, continues the
 //                recurrence.
-constexpr int kMaxCols = 2048;
-__global__ __launch_bounds__(256) void k_cgs_reduce(ReduceArgs a) {
-    __shared__ double hs[kMaxCols];
-    __shared__ double sh[4];
-    __shared__ int decision;
+__device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& decision) {
     const int tid = threadIdx.x;
     for (int c = tid; c < a.ncols; c += 256) {
         double s = 0.0;
+#pragma unroll 8
         for (int ch = 0; ch < a.nchunks; ++ch) s += a.part[(long long)ch * a.pstride + c];
         hs[c] = s;
     }
@@ -629,9 +593,8 @@ __global__ __launch_bounds__(256) void k_cgs_reduce(ReduceArgs a) {
     for (int c = tid; c < a.ncols; c += 256) hh += hs[c] * hs[c];
     hh = block_sum256(hh, sh);
     double rr = 0.0;
-    if (tid == 0)
-        for (int ch = 0; ch < a.nchunks; ++ch) rr += a.part[(long long)ch * a.pstride + a.ncols];
-    rr = block_sum256(tid == 0 ? rr : 0.0, sh);
+    for (int ch = tid; ch < a.nchunks; ch += 256) rr += a.part[(long long)ch * a.pstride + a.ncols];
+    rr = block_sum256(rr, sh);
     const double bnorm = a.state[0];
     double coef, scale;
     if (a.full) {
@@ -686,19 +649,105 @@ __global__ __launch_bounds__(256) void k_cgs_reduce(ReduceArgs a) {
         *a.coef_out = coef;
         *a.scale_out = scale;
         if (a.track && coef > a.state[0]) a.state[0] = coef;
+        *a.counter = 0u;  // ready for the next projection launch
     }
 }
 
-// out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale   (FP64 accumulation)
+// Projection h = basis^T r and |r|^2 over a (row chunk, column group) tile:
+// part[chunk * pstride + c] for c < ncols and part[chunk * pstride + ncols] =
+// sum r^2 (column group 0).  Products of two FP32 numbers are exact in FP64;
+// sums are FP64.  The workgroup that finishes last (atomic ticket after a
+// device-scope fence) then reduces every partial sum in a fixed order
+// (cgs_finish), so the result does not depend on which tile finished last.
+__global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
+    constexpr int CJ = kProjCols;
+    __shared__ double red[CJ + 1][4];
+    __shared__ double hs[kMaxCols];
+    __shared__ double sh[4];
+    __shared__ int decision;
+    __shared__ int last;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long t = (long long)blockIdx.x * kProjRows + 4 * tid;
+    const int c0 = blockIdx.y * CJ;
+    const int nc = min(CJ, a.ncols - c0);
+    const bool in = t < a.n;
+    const float4 rv = in ? rows4(a.r, t, a.n) : make_float4(0.f, 0.f, 0.f, 0.f);
+    double acc[CJ + 1];
+#pragma unroll
+    for (int c = 0; c < CJ; ++c) {
+        acc[c] = 0.0;
+        if (c < nc && in) acc[c] = dot4(rows4(a.basis + (long long)(c0 + c) * a.ld, t, a.n), rv);
+    }
+    acc[CJ] = blockIdx.y == 0 ? dot4(rv, rv) : 0.0;
+#pragma unroll
+    for (int c = 0; c <= CJ; ++c) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) red[c][wave] = v;
+    }
+    __syncthreads();
+    if (tid <= CJ) {
+        const int c = tid;
+        const double sum = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+        if (c < nc) a.part[(long long)blockIdx.x * a.pstride + c0 + c] = sum;
+        if (c == CJ && blockIdx.y == 0) a.part[(long long)blockIdx.x * a.pstride + a.ncols] = sum;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned total = gridDim.x * gridDim.y;
+        last = atomicAdd(a.counter, 1u) == total - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    cgs_finish(a, hs, sh, decision);
+}
+
+
+
+// out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale, FP64 accumulation.  A
+// workgroup covers 256 rows (4 per lane, float4); its 4 waves split the
+// columns and their partial sums meet in LDS.
 __global__ __launch_bounds__(256) void k_cgs_update(const float* __restrict__ r, const float* __restrict__ basis,
                                                     long long ld, int ncols, const double* __restrict__ h,
                                                     const double* __restrict__ scale, float* __restrict__ out,
                                                     long long n) {
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n) return;
-    double acc = r[t];
-    for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * h[c];
-    out[t] = (float)(acc * (*scale));
+    __shared__ double red[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long t = (long long)blockIdx.x * 256 + 4 * lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (t < n) {
+#pragma unroll 4
+        for (int c = wave; c < ncols; c += 4) {
+            const float4 b = rows4(basis + (long long)c * ld, t, n);
+            const double hc = h[c];
+            a0 += (double)b.x * hc;
+            a1 += (double)b.y * hc;
+            a2 += (double)b.z * hc;
+            a3 += (double)b.w * hc;
+        }
+    }
+    red[wave][4 * lane + 0] = a0;
+    red[wave][4 * lane + 1] = a1;
+    red[wave][4 * lane + 2] = a2;
+    red[wave][4 * lane + 3] = a3;
+    __syncthreads();
+    if (wave == 0 && t < n) {
+        const double sc = *scale;
+        const float4 rv = rows4(r, t, n);
+        double s4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] = red[0][4 * lane + q] + red[1][4 * lane + q] + red[2][4 * lane + q] + red[3][4 * lane + q];
+        const float o0 = (float)(((double)rv.x - s4[0]) * sc), o1 = (float)(((double)rv.y - s4[1]) * sc);
+        const float o2 = (float)(((double)rv.z - s4[2]) * sc), o3 = (float)(((double)rv.w - s4[3]) * sc);
+        if (t + 3 < n) {
+            *reinterpret_cast<float4*>(out + t) = make_float4(o0, o1, o2, o3);
+        } else {
+            out[t] = o0;
+            if (t + 1 < n) out[t + 1] = o1;
+            if (t + 2 < n) out[t + 2] = o2;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -845,16 +894,10 @@ hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, h
     return hipGetLastError();
 }
 
-hipError_t launch_cgs_dots(const float* basis, long long ld, int ncols, const float* r, long long n,
-                           double* part, int pstride, hipStream_t s) {
-    const unsigned nchunks = (unsigned)((n + kDotsRows - 1) / kDotsRows);
-    const unsigned ngrp = ncols > 0 ? (unsigned)((ncols + kDotsCols - 1) / kDotsCols) : 1u;
-    hipLaunchKernelGGL(k_cgs_dots, dim3(nchunks, ngrp), dim3(256), 0, s, basis, ld, ncols, r, n, part, pstride);
-    return hipGetLastError();
-}
-
-hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_cgs_reduce, dim3(1), dim3(256), 0, s, a);
+hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s) {
+    const unsigned nchunks = (unsigned)((a.n + kProjRows - 1) / kProjRows);
+    const unsigned ngrp = a.ncols > 0 ? (unsigned)((a.ncols + kProjCols - 1) / kProjCols) : 1u;
+    hipLaunchKernelGGL(k_cgs_project, dim3(nchunks, ngrp), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

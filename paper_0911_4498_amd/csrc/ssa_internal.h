@@ -56,7 +56,7 @@ struct P3Out {
 };
 
 struct ReduceArgs {
-    const double* part;
+    double* part;
     int nchunks, pstride, ncols;
     float* r;
     long long n;
@@ -70,11 +70,13 @@ struct ReduceArgs {
     int track;          // 1: the coefficient is an entry of B (count it in state[0])
     int full;           // 1: the basis already spans the whole space -> zero vector
     double tol_bd;      // breakdown threshold relative to state[0]
+    unsigned* counter;  // tile tickets of the projection launch (0 between launches)
 };
 
 constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many terms are summed directly
-constexpr int kDotsRows = 1024;  // rows per workgroup in the projection kernel
-constexpr int kDotsCols = 16;    // basis columns per workgroup in the projection kernel
+constexpr int kProjRows = 1024;  // rows per workgroup in the projection kernel (256 x float4)
+constexpr int kProjCols = 8;     // basis columns per workgroup in the projection kernel
+constexpr int kMaxCols = 2048;   // most basis columns one projection handles
 
 // launchers (kernels.hip); each returns hipSuccess or the launch error
 hipError_t launch_tables(const ConvGeom& g, float2* tw1, float2* tw2, float2* tw_lo, float2* tw_hi,
@@ -95,9 +97,7 @@ hipError_t launch_recon_edges(const double* sigma, const float* U, long long ldu
 hipError_t launch_check_finite(const double* f, long long N, double* flag, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, hipStream_t s);
-hipError_t launch_cgs_dots(const float* basis, long long ld, int ncols, const float* r, long long n,
-                           double* part, int pstride, hipStream_t s);
-hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols,
                              const double* h, const double* scale, float* out, long long n,
                              hipStream_t s);
