@@ -179,17 +179,19 @@ enum ssa_prof_class {
 };
 
 /*
- * ssa_profile_enable -- 1: from now on bracket every kernel launch of the plan
- * with HIP events on the plan's stream (adds two event records per launch);
- * 0: stop.  Either way the counters are cleared (the stream is synchronized
- * first).  Errors: SSA_EINVAL.
+ * ssa_profile_enable -- class_mask != 0: from now on count the launches and
+ * algorithmic bytes of every kernel class, and bracket each launch of the
+ * classes whose bit (1u << class) is set with HIP events on the plan's stream
+ * (two event records per timed launch); 0: stop.  Either way the counters are
+ * cleared (the stream is synchronized first).  Errors: SSA_EINVAL.
  */
-int ssa_profile_enable(ssa_plan plan, int enable);
+int ssa_profile_enable(ssa_plan plan, unsigned class_mask);
 
 /*
  * ssa_profile_read -- synchronize the plan's stream and report, for kernel
  * class cls since the last ssa_profile_enable: the number of launches, the
- * summed event-measured duration in milliseconds (-1 if timing was off) and
+ * summed event-measured duration in milliseconds (-1 if the class was not
+ * timed) and
  * the summed algorithmic HBM bytes (the bytes the method must move: vectors
  * read and written, spectra, basis columns).  Errors: SSA_EINVAL, SSA_EDEVICE.
  */

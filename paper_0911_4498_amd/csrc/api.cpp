@@ -95,8 +95,10 @@ struct ssa_plan_s {
     hipEvent_t grp_done = nullptr;
     hipEvent_t chk_ev[2] = {nullptr, nullptr};
     std::vector<double> work;
-    // optional per-kernel-class timing (HIP events around each launch)
+    // optional per-kernel-class timing (HIP events around the launches of the
+    // classes in prof_mask; launch counts and bytes are kept for all classes)
     int prof_on = 0;
+    unsigned prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pairs[SSA_PROF_NCLASSES];
@@ -130,7 +132,7 @@ void layout(ssa_plan p) {
     p->o_U = take(sizeof(float) * (size_t)(p->d_max + 1) * p->ldU);
     p->o_V = take(sizeof(float) * (size_t)(p->d_max + 1) * p->ldV);
     p->o_r = take(sizeof(float) * (size_t)std::max(p->ldU, p->ldV));
-    p->o_part = take(sizeof(double) * (size_t)p->nchunks_max * p->pstride);
+    p->o_part = take(sizeof(double) * (size_t)(p->d_max + 2) * p->pstride);
     p->o_h = take(sizeof(double) * (size_t)(p->d_max + 2));
     p->o_sc = take(sizeof(double) * 8);
     p->o_alpha = take(sizeof(double) * (size_t)(p->d_max + 3));
@@ -172,7 +174,7 @@ struct ProfScope {
     double bytes;
     hipEvent_t e0 = nullptr;
     ProfScope(ssa_plan p_, int cls_, double bytes_) : p(p_), cls(cls_), bytes(bytes_) {
-        if (p->prof_on) {
+        if (p->prof_on && (p->prof_mask >> cls & 1u)) {
             e0 = next_event(p);
             if (e0) (void)hipEventRecord(e0, p->stream);
         }
@@ -252,10 +254,13 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     a.track = track;
     a.full = ncols >= n ? 1 : 0;
     a.tol_bd = kBreakdownTol;
-    a.counter = at<unsigned>(p, p->o_flag) + 16;
     {
         ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)n * (ncols + 1));
         SSA_TRY(launch_cgs_project(a, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)a.nchunks * (ncols + 1));
+        SSA_TRY(launch_cgs_reduce(a, s));
     }
     {
         ProfScope ps(p, SSA_PROF_UPDATE, 4.0 * (double)n * (ncols + 2));
@@ -343,8 +348,8 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, si
     g.st2 = make_stages(M2);
     p->ldU = (long long)align_up((size_t)p->Li, 64);
     p->ldV = (long long)align_up((size_t)p->Ki, 64);
-    p->pstride = d_max + 2;
     p->nchunks_max = (int)((p->Ki + kProjRows - 1) / kProjRows);
+    p->pstride = p->nchunks_max;
     layout(p);
     p->work.resize(bidiag_work_doubles(d_max) + 16);
     *workspace_bytes = p->ws_bytes;
@@ -414,7 +419,6 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     SSA_TRY(launch_fill_zero(alpha, p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(beta, p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
-    SSA_TRY(launch_fill_zero(at<double>(p, p->o_flag) + 8, 8, s));  // projection ticket counter
 
     // Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0
     SSA_TRY(launch_start_vector(r, Li, p->seed, s));
@@ -643,7 +647,7 @@ const char* ssa_status_str(int status) {
     }
 }
 
-int ssa_profile_enable(ssa_plan p, int enable) {
+int ssa_profile_enable(ssa_plan p, unsigned class_mask) {
     if (!p) return SSA_EINVAL;
     if (p->stream || p->bound) (void)hipStreamSynchronize(p->stream);
     for (int c = 0; c < SSA_PROF_NCLASSES; ++c) {
@@ -652,7 +656,8 @@ int ssa_profile_enable(ssa_plan p, int enable) {
         p->prof_count[c] = 0;
     }
     p->ev_next = 0;
-    p->prof_on = enable ? 1 : 0;
+    p->prof_on = class_mask ? 1 : 0;
+    p->prof_mask = class_mask;
     return SSA_OK;
 }
 
@@ -666,7 +671,7 @@ int ssa_profile_read(ssa_plan p, int cls, long long* launches, double* ms, doubl
         total += t;
     }
     if (launches) *launches = p->prof_count[cls];
-    if (ms) *ms = p->prof_on ? total : -1.0;
+    if (ms) *ms = (p->prof_on && (p->prof_mask >> cls & 1u)) ? total : -1.0;
     if (bytes) *bytes = p->prof_bytes[cls];
     return SSA_OK;
 }

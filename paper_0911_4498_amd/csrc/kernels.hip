@@ -125,12 +125,25 @@ __global__ __launch_bounds__(256) void k_pass1(ConvGeom g, P1In a, float2* __res
         }
         buf[c * ss + n1] = z;
     }
+    // output twiddles W_{M'}^{n2 k1} of this thread's first kPre stores, fetched before the FFT
+    constexpr int kPre = 4;
+    float2 wpre[kPre];
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+        const int idx = tid + i * nthr;
+        const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
+        wpre[i] = (idx < CB * M1 && n2 < M2) ? twiddle_mp(g, (long long)n2 * k1) : make_float2(1.0f, 0.0f);
+    }
     __syncthreads();
     lds_fft<-1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
     float2* out = T1 + (long long)y * g.Mp;
-    for (int idx = tid; idx < CB * M1; idx += nthr) {
+    int i = 0;
+    for (int idx = tid; idx < CB * M1; idx += nthr, ++i) {
         const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
-        if (n2 < M2) out[(long long)k1 * M2 + n2] = cmul(buf[c * ss + k1], twiddle_mp(g, (long long)n2 * k1));
+        if (n2 < M2) {
+            const float2 w = i < kPre ? wpre[i < kPre ? i : 0] : twiddle_mp(g, (long long)n2 * k1);
+            out[(long long)k1 * M2 + n2] = cmul(buf[c * ss + k1], w);
+        }
     }
 }
 
@@ -194,14 +207,28 @@ __global__ __launch_bounds__(256) void k_pass2_matvec(ConvGeom g, const float4* 
     const RowPair rp(blockIdx.x, g.M1, M2);
     for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
     load_rows<EPT>(buf, T1, rp, M2, tid, nthr);
+    // operator values of this thread's first kPre pairs, fetched before the FFT
+    constexpr int kPre = 2;
+    float4 pre0[kPre], pre1[kPre];
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+        const int p = tid + i * nthr;
+        if (p < rp.npairs) {
+            int s0, e0, s1, e1;
+            rp.pair(p, M2, s0, e0, s1, e1);
+            pre0[i] = AB[(long long)rp.row(s0) * M2 + e0];
+            pre1[i] = AB[(long long)rp.row(s1) * M2 + e1];
+        }
+    }
     __syncthreads();
     lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
-    for (int p = tid; p < rp.npairs; p += nthr) {
+    int i = 0;
+    for (int p = tid; p < rp.npairs; p += nthr, ++i) {
         int s0, e0, s1, e1;
         rp.pair(p, M2, s0, e0, s1, e1);
         const float2 z0 = buf[s0 * M2 + e0], z1 = buf[s1 * M2 + e1];
-        const float4 o0 = AB[(long long)rp.row(s0) * M2 + e0];
-        const float4 o1 = AB[(long long)rp.row(s1) * M2 + e1];
+        const float4 o0 = i < kPre ? pre0[i < kPre ? i : 0] : AB[(long long)rp.row(s0) * M2 + e0];
+        const float4 o1 = i < kPre ? pre1[i < kPre ? i : 0] : AB[(long long)rp.row(s1) * M2 + e1];
         const float2 q0 = cadd(cmul(make_float2(o0.x, o0.y), z0), cmul(make_float2(o0.z, o0.w), cconj(z1)));
         const float2 q1 = cadd(cmul(make_float2(o1.x, o1.y), z1), cmul(make_float2(o1.z, o1.w), cconj(z0)));
         buf[s0 * M2 + e0] = q0;
@@ -532,14 +559,15 @@ __device__ __forceinline__ double dot4(float4 a, float4 b) {
            (double)a.w * (double)b.w;
 }
 
-// block-wide sum (256 threads), result valid in every thread
-__device__ double block_sum256(double v, double* sh) {
+// block-wide sum (any block of up to 1024 threads), fixed order, valid in every thread
+__device__ double block_sum(double v, double* sh) {
     v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     __syncthreads();
     if (lane == 0) sh[wave] = v;
     __syncthreads();
-    const double s = sh[0] + sh[1] + sh[2] + sh[3];
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
     __syncthreads();
     return s;
 }
@@ -562,12 +590,12 @@ __device__ double blk_project(const float* r, long long n, const float* basis, l
         double acc = 0.0;
         const float* col = basis + (long long)c * ld;
         for (long long t = threadIdx.x; t < n; t += blockDim.x) acc += (double)col[t] * (double)r[t];
-        const double s = block_sum256(acc, sh);
+        const double s = block_sum(acc, sh);
         if (threadIdx.x == 0) h[c] = s;
     }
     double acc = 0.0;
     for (long long t = threadIdx.x; t < n; t += blockDim.x) acc += (double)r[t] * (double)r[t];
-    const double rr = block_sum256(acc, sh);
+    const double rr = block_sum(acc, sh);
     __syncthreads();
     return rr;
 }
@@ -581,24 +609,17 @@ __device__ double blk_project(const float* r, long long n, const float* basis, l
 //                orthogonal to the basis by two passes, continues the
 //                recurrence.
 __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& decision) {
-    const int tid = threadIdx.x;
-    for (int c = tid; c < a.ncols; c += 256) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int ch = 0; ch < a.nchunks; ++ch) s += a.part[(long long)ch * a.pstride + c];
-        hs[c] = s;
-    }
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int c = tid; c < a.ncols; c += nt) hs[c] = a.h[c];
     __syncthreads();
     double hh = 0.0;
-    for (int c = tid; c < a.ncols; c += 256) hh += hs[c] * hs[c];
-    hh = block_sum256(hh, sh);
-    double rr = 0.0;
-    for (int ch = tid; ch < a.nchunks; ch += 256) rr += a.part[(long long)ch * a.pstride + a.ncols];
-    rr = block_sum256(rr, sh);
+    for (int c = tid; c < a.ncols; c += nt) hh += hs[c] * hs[c];
+    hh = block_sum(hh, sh);
+    const double rr = a.h[a.ncols];
     const double bnorm = a.state[0];
     double coef, scale;
     if (a.full) {
-        for (int c = tid; c < a.ncols; c += 256) hs[c] = 0.0;
+        for (int c = tid; c < a.ncols; c += nt) hs[c] = 0.0;
         coef = 0.0;
         scale = 0.0;
     } else {
@@ -616,8 +637,8 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
             const double rr2 = blk_project(a.r, a.n, a.basis, a.ld, a.ncols, hs, sh);
             __syncthreads();
             double hh2 = 0.0;
-            for (int c = tid; c < a.ncols; c += 256) hh2 += hs[c] * hs[c];
-            hh2 = block_sum256(hh2, sh);
+            for (int c = tid; c < a.ncols; c += nt) hh2 += hs[c] * hs[c];
+            hh2 = block_sum(hh2, sh);
             a2 = rr2 - hh2;
             if (tid == 0) decision = (a2 > 0.0 && sqrt(a2) > thr) ? 2 : 3;
             __syncthreads();
@@ -629,7 +650,7 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
                 // breakdown: fresh direction
                 coef = 0.0;
                 const unsigned long long ctr = a.stream_ctr;
-                for (long long t = tid; t < a.n; t += 256) a.r[t] = gauss(a.seed, ctr, t);
+                for (long long t = tid; t < a.n; t += nt) a.r[t] = gauss(a.seed, ctr, t);
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
                     blk_project(a.r, a.n, a.basis, a.ld, a.ncols, hs, sh);
@@ -637,35 +658,27 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
                     blk_subtract(a.r, a.n, a.basis, a.ld, a.ncols, hs);
                 }
                 const double rr3 = blk_project(a.r, a.n, a.basis, 0, 0, hs, sh);
-                for (int c = tid; c < a.ncols; c += 256) hs[c] = 0.0;
+                for (int c = tid; c < a.ncols; c += nt) hs[c] = 0.0;
                 scale = rr3 > 0.0 ? 1.0 / sqrt(rr3) : 0.0;
                 if (tid == 0) a.state[1] += 1.0;
             }
         }
     }
     __syncthreads();
-    for (int c = tid; c < a.ncols; c += 256) a.h[c] = hs[c];
+    for (int c = tid; c < a.ncols; c += nt) a.h[c] = hs[c];
     if (tid == 0) {
         *a.coef_out = coef;
         *a.scale_out = scale;
         if (a.track && coef > a.state[0]) a.state[0] = coef;
-        *a.counter = 0u;  // ready for the next projection launch
     }
 }
 
-// Projection h = basis^T r and |r|^2 over a (row chunk, column group) tile:
-// part[chunk * pstride + c] for c < ncols and part[chunk * pstride + ncols] =
-// sum r^2 (column group 0).  Products of two FP32 numbers are exact in FP64;
-// sums are FP64.  The workgroup that finishes last (atomic ticket after a
-// device-scope fence) then reduces every partial sum in a fixed order
-// (cgs_finish), so the result does not depend on which tile finished last.
+// Projection h = basis^T r and |r|^2, FP64 sums of exact FP32 products, in
+// (row chunk, column group) tiles: part[c * pstride + chunk] for c < ncols,
+// and part[ncols * pstride + chunk] = the chunk's |r|^2 (column group 0).
 __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
     constexpr int CJ = kProjCols;
     __shared__ double red[CJ + 1][4];
-    __shared__ double hs[kMaxCols];
-    __shared__ double sh[4];
-    __shared__ int decision;
-    __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long t = (long long)blockIdx.x * kProjRows + 4 * tid;
     const int c0 = blockIdx.y * CJ;
@@ -688,22 +701,30 @@ __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
     if (tid <= CJ) {
         const int c = tid;
         const double sum = red[c][0] + red[c][1] + red[c][2] + red[c][3];
-        if (c < nc) a.part[(long long)blockIdx.x * a.pstride + c0 + c] = sum;
-        if (c == CJ && blockIdx.y == 0) a.part[(long long)blockIdx.x * a.pstride + a.ncols] = sum;
+        if (c < nc) a.part[(long long)(c0 + c) * a.pstride + blockIdx.x] = sum;
+        if (c == CJ && blockIdx.y == 0) a.part[(long long)a.ncols * a.pstride + blockIdx.x] = sum;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned total = gridDim.x * gridDim.y;
-        last = atomicAdd(a.counter, 1u) == total - 1 ? 1 : 0;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    cgs_finish(a, hs, sh, decision);
 }
 
-
+// One workgroup (1024 threads): h[c] = sum over chunks of part[c][chunk]
+// (32 lanes per column, chunks contiguous, fixed order), then cgs_finish.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
+    __shared__ double hs[kMaxCols];
+    __shared__ double sh[16];
+    __shared__ int decision;
+    const int tid = threadIdx.x;
+    for (int c = tid >> 5; c <= a.ncols; c += kReduceThreads / 32) {
+        const double* row = a.part + (long long)c * a.pstride;
+        double sum = 0.0;
+        for (int ch = tid & 31; ch < a.nchunks; ch += 32) sum += row[ch];
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) sum += __shfl_down(sum, off, 32);
+        if ((tid & 31) == 0) a.h[c] = sum;
+    }
+    __syncthreads();
+    cgs_finish(a, hs, sh, decision);
+}
 
 // out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale, FP64 accumulation.  A
 // workgroup covers 256 rows (4 per lane, float4); its 4 waves split the
@@ -898,6 +919,11 @@ hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s) {
     const unsigned nchunks = (unsigned)((a.n + kProjRows - 1) / kProjRows);
     const unsigned ngrp = a.ncols > 0 ? (unsigned)((a.ncols + kProjCols - 1) / kProjCols) : 1u;
     hipLaunchKernelGGL(k_cgs_project, dim3(nchunks, ngrp), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cgs_reduce, dim3(1), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();
 }
 

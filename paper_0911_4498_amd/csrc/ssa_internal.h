@@ -70,7 +70,6 @@ struct ReduceArgs {
     int track;          // 1: the coefficient is an entry of B (count it in state[0])
     int full;           // 1: the basis already spans the whole space -> zero vector
     double tol_bd;      // breakdown threshold relative to state[0]
-    unsigned* counter;  // tile tickets of the projection launch (0 between launches)
 };
 
 constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many terms are summed directly
@@ -98,6 +97,7 @@ hipError_t launch_check_finite(const double* f, long long N, double* flag, hipSt
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols,
                              const double* h, const double* scale, float* out, long long n,
                              hipStream_t s);

@@ -81,7 +81,7 @@ def load():
     lib.ssa_status_str.restype = ctypes.c_char_p
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ssa_bidiag_ritz.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
-    lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_int]
+    lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_uint]
     lib.ssa_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), dp, dp]
     for name in EXPORTED:
         if name not in ("ssa_plan_destroy", "ssa_status_str"):
@@ -159,9 +159,18 @@ class Plan:
         except Exception:
             pass
 
-    def profile_enable(self, on: bool = True):
-        """Bracket every launch with HIP events (and clear the counters)."""
-        _check(self.lib.ssa_profile_enable(self._h, 1 if on else 0), "ssa_profile_enable")
+    def profile_enable(self, classes=None, on: bool = True):
+        """Count launches/bytes of every class and time the listed classes (all if None)
+        with HIP events; on=False stops.  Clears the counters."""
+        if not on:
+            mask = 0
+        elif classes is None:
+            mask = (1 << len(PROF_CLASSES)) - 1
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << PROF_CLASSES.index(c)
+        _check(self.lib.ssa_profile_enable(self._h, mask), "ssa_profile_enable")
 
     def profile_read(self):
         """{class: (launches, event-timed ms, algorithmic bytes)} since profile_enable."""
