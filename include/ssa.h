@@ -145,6 +145,51 @@ int ssa_reconstruct(ssa_plan plan, const double* sigma_dev, const float* U_dev,
                     const float* V_dev, int k, const int* group_offsets,
                     const int* group_members, int m, float* out_dev);
 
+/*
+ * Many independent series in one launch ("batched" path).  One persistent
+ * kernel: each workgroup takes the next series from a work counter and runs
+ * the whole method on it -- spectrum, Algorithm 1 with classical Gram-Schmidt
+ * reorthogonalization and FFT products held in LDS, the stopping test and Ritz
+ * vectors on the device, then the rank-1 Hankelization (Algorithm 4) of each
+ * of the k triples.  A series' result does not depend on the other series in
+ * the batch or on which workgroup ran it.
+ */
+typedef struct ssa_batch_s* ssa_batch;
+
+/*
+ * ssa_batch_plan -- size a batch engine: nslots workgroups (0 = 256), series of
+ * length 3 <= N <= n_max (n_max <= 20480), up to k_max <= 32 triples, up to
+ * max_series series per solve.  opts as for ssa_embed_plan (d_max capped at
+ * 320).  Errors: SSA_EINVAL.
+ */
+int ssa_batch_plan(int nslots, long long n_max, int k_max, int max_series, const ssa_opts* opts,
+                   size_t* workspace_bytes, ssa_batch* out);
+
+/* ssa_batch_bind -- as ssa_plan_bind, for a batch engine. */
+int ssa_batch_bind(ssa_batch batch, void* workspace_dev, size_t bytes, void* hip_stream);
+
+/*
+ * ssa_batch_solve -- the k_s leading triples (and, if recon_dev is not NULL,
+ * the k_s elementary reconstructed series) of every series s.
+ *   series_dev: all series concatenated (FP64, device); offsets (host,
+ *   nseries+1, offsets[0] = 0): series s is series_dev[offsets[s] ..
+ *   offsets[s+1]); L (host, nseries) window lengths, 1 < L[s] < N_s; k (host,
+ *   nseries) triples, 1 <= k[s] <= min(k_max, L[s], K_s).
+ *   Outputs (device), one block per series in input order:
+ *     sigma_dev: k_s doubles;
+ *     U_dev: L_s*k_s floats (u_i at + i*L_s);
+ *     V_dev: K_s*k_s floats (v_i at + i*K_s);
+ *     recon_dev: N_s*k_s floats (elementary series i at + i*N_s);
+ *     info_dev: 4 ints per series (steps, converged, restarts, DGKS passes).
+ * Asynchronous on the bound stream.  Errors: SSA_EINVAL, SSA_ENOMEM, SSA_EDEVICE.
+ */
+int ssa_batch_solve(ssa_batch batch, int nseries, const double* series_dev, const long long* offsets,
+                    const int* L, const int* k, double* sigma_dev, float* U_dev, float* V_dev,
+                    float* recon_dev, int* info_dev);
+
+/* ssa_batch_destroy -- free the host-side batch engine. */
+void ssa_batch_destroy(ssa_batch batch);
+
 /* ssa_plan_describe -- copy the plan's sizes into *desc. */
 int ssa_plan_describe(ssa_plan plan, ssa_plan_desc* desc);
 

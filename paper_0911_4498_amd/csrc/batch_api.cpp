@@ -1,0 +1,203 @@
+// batch_api.cpp -- C ABI of the many-series path (ssa_batch_*): sizes the
+// per-workgroup slots, validates and uploads the series table, launches the
+// persistent kernel of batch.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ssa.h"
+#include "ssa_batch.h"
+#include "ssa_internal.h"
+
+using namespace ssa;
+
+namespace {
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+}  // namespace
+
+struct ssa_batch_s {
+    int nslots, k_max, d_max, check_every, max_series;
+    long long n_max, ld;
+    double tol;
+    unsigned long long seed;
+    size_t slot_bytes, o_ab, o_u, o_v, o_scratch, o_p, o_q;
+    size_t t_offs, t_ls, t_ks, t_soff, t_uoff, t_voff, t_roff, t_queue, slots_off, ws_bytes;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int bound = 0;
+    long long* h_tab = nullptr;  // pinned staging: offs | soff | uoff | voff | roff | Ls, ks (int)
+    hipEvent_t tab_done = nullptr;
+};
+
+extern "C" {
+
+int ssa_batch_plan(int nslots, long long n_max, int k_max, int max_series, const ssa_opts* opts,
+                   size_t* workspace_bytes, ssa_batch* out) {
+    if (!out || !workspace_bytes) return SSA_EINVAL;
+    *out = nullptr;
+    if (n_max < 3 || n_max > 2LL * batch::kMaxMp || k_max < 1 || k_max > batch::kMaxK || max_series < 1)
+        return SSA_EINVAL;
+    if (nslots <= 0) nslots = 256;
+    ssa_batch b = new (std::nothrow) ssa_batch_s();
+    if (!b) return SSA_EINVAL;
+    b->nslots = nslots;
+    b->n_max = n_max;
+    b->k_max = k_max;
+    b->max_series = max_series;
+    int d_max = opts && opts->d_max > 0 ? opts->d_max : 8 * k_max + 32;
+    b->d_max = std::max(k_max, std::min(d_max, batch::kDmax));
+    b->check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
+    b->tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
+    b->seed = opts && opts->seed ? opts->seed : 1ULL;
+    b->ld = (long long)align_up((size_t)n_max, 64);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + bytes, 256);
+        return r;
+    };
+    b->o_ab = take(sizeof(float4) * (size_t)batch::kMaxMp);
+    b->o_u = take(sizeof(float) * (size_t)(b->d_max + 1) * b->ld);
+    b->o_v = take(sizeof(float) * (size_t)(b->d_max + 1) * b->ld);
+    b->o_scratch = take(std::max(sizeof(double) * (size_t)k_max * 6 * (batch::kDmax + 2),
+                                 sizeof(float2) * (size_t)batch::kMaxMp));
+    b->o_p = take(sizeof(double) * (size_t)(b->d_max + 1) * k_max);
+    b->o_q = take(sizeof(double) * (size_t)b->d_max * k_max);
+    b->slot_bytes = o;
+    o = 0;
+    b->t_offs = take(sizeof(long long) * (size_t)(max_series + 1));
+    b->t_ls = take(sizeof(int) * (size_t)max_series);
+    b->t_ks = take(sizeof(int) * (size_t)max_series);
+    b->t_soff = take(sizeof(long long) * (size_t)max_series);
+    b->t_uoff = take(sizeof(long long) * (size_t)max_series);
+    b->t_voff = take(sizeof(long long) * (size_t)max_series);
+    b->t_roff = take(sizeof(long long) * (size_t)max_series);
+    b->t_queue = take(256);
+    b->slots_off = o;
+    b->ws_bytes = o + b->slot_bytes * (size_t)nslots;
+    *workspace_bytes = b->ws_bytes;
+    *out = b;
+    return SSA_OK;
+}
+
+int ssa_batch_bind(ssa_batch b, void* workspace_dev, size_t bytes, void* hip_stream) {
+    if (!b || !workspace_dev) return SSA_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
+    if (bytes < b->ws_bytes) return SSA_ENOMEM;
+    if (!b->h_tab) {
+        if (hipHostMalloc((void**)&b->h_tab, sizeof(long long) * (7 * (size_t)b->max_series + 8),
+                          hipHostMallocDefault) != hipSuccess)
+            return SSA_EDEVICE;
+        if (hipEventCreateWithFlags(&b->tab_done, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
+    }
+    b->ws = static_cast<char*>(workspace_dev);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->bound = 1;
+    return SSA_OK;
+}
+
+int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const long long* offsets, const int* L,
+                    const int* k, double* sigma_dev, float* U_dev, float* V_dev, float* recon_dev, int* info_dev) {
+    if (!b || !series_dev || !offsets || !L || !k || !sigma_dev || !U_dev || !V_dev) return SSA_EINVAL;
+    if (nseries < 1 || nseries > b->max_series) return SSA_EINVAL;
+    if (!b->bound) return SSA_ENOMEM;
+    if (offsets[0] != 0) return SSA_EINVAL;
+    for (int s = 0; s < nseries; ++s) {
+        const long long N = offsets[s + 1] - offsets[s];
+        if (N < 3 || N > b->n_max) return SSA_EINVAL;
+        if (L[s] <= 1 || L[s] >= N) return SSA_EINVAL;
+        const long long K = N - L[s] + 1;
+        if (k[s] < 1 || k[s] > b->k_max || k[s] > std::min<long long>(L[s], K)) return SSA_EINVAL;
+    }
+    if (hipEventSynchronize(b->tab_done) != hipSuccess) return SSA_EDEVICE;
+    long long* h_offs = b->h_tab;
+    long long* h_soff = h_offs + (nseries + 1);
+    long long* h_uoff = h_soff + nseries;
+    long long* h_voff = h_uoff + nseries;
+    long long* h_roff = h_voff + nseries;
+    int* h_ls = reinterpret_cast<int*>(h_roff + nseries);
+    int* h_ks = h_ls + nseries;
+    long long so = 0, uo = 0, vo = 0, ro = 0;
+    for (int s = 0; s < nseries; ++s) {
+        const long long N = offsets[s + 1] - offsets[s];
+        const long long K = N - L[s] + 1;
+        h_offs[s] = offsets[s];
+        h_soff[s] = so;
+        h_uoff[s] = uo;
+        h_voff[s] = vo;
+        h_roff[s] = ro;
+        h_ls[s] = L[s];
+        h_ks[s] = k[s];
+        so += k[s];
+        uo += (long long)L[s] * k[s];
+        vo += K * k[s];
+        ro += N * k[s];
+    }
+    h_offs[nseries] = offsets[nseries];
+    hipStream_t st = b->stream;
+    auto cp = [&](size_t dst_off, const void* src, size_t bytes) {
+        return hipMemcpyAsync(b->ws + dst_off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    if (cp(b->t_offs, h_offs, sizeof(long long) * (nseries + 1)) != hipSuccess ||
+        cp(b->t_soff, h_soff, sizeof(long long) * nseries) != hipSuccess ||
+        cp(b->t_uoff, h_uoff, sizeof(long long) * nseries) != hipSuccess ||
+        cp(b->t_voff, h_voff, sizeof(long long) * nseries) != hipSuccess ||
+        cp(b->t_roff, h_roff, sizeof(long long) * nseries) != hipSuccess ||
+        cp(b->t_ls, h_ls, sizeof(int) * nseries) != hipSuccess ||
+        cp(b->t_ks, h_ks, sizeof(int) * nseries) != hipSuccess)
+        return SSA_EDEVICE;
+    if (hipEventRecord(b->tab_done, st) != hipSuccess) return SSA_EDEVICE;
+    if (launch_fill_zero(reinterpret_cast<double*>(b->ws + b->t_queue), 1, st) != hipSuccess) return SSA_EDEVICE;
+    BatchArgs a{};
+    a.nseries = nseries;
+    a.series = series_dev;
+    a.offs = reinterpret_cast<const long long*>(b->ws + b->t_offs);
+    a.Ls = reinterpret_cast<const int*>(b->ws + b->t_ls);
+    a.ks = reinterpret_cast<const int*>(b->ws + b->t_ks);
+    a.soff = reinterpret_cast<const long long*>(b->ws + b->t_soff);
+    a.d_max = b->d_max;
+    a.check_every = b->check_every;
+    a.tol = b->tol;
+    a.seed = b->seed;
+    a.sigma = sigma_dev;
+    a.U = U_dev;
+    a.uoff = reinterpret_cast<const long long*>(b->ws + b->t_uoff);
+    a.V = V_dev;
+    a.voff = reinterpret_cast<const long long*>(b->ws + b->t_voff);
+    a.recon = recon_dev;
+    a.roff = reinterpret_cast<const long long*>(b->ws + b->t_roff);
+    a.info = info_dev;
+    a.slots = b->ws + b->slots_off;
+    a.slot_bytes = b->slot_bytes;
+    a.o_ab = b->o_ab;
+    a.o_u = b->o_u;
+    a.o_v = b->o_v;
+    a.o_scratch = b->o_scratch;
+    a.o_p = b->o_p;
+    a.o_q = b->o_q;
+    a.ld = b->ld;
+    a.queue = reinterpret_cast<unsigned*>(b->ws + b->t_queue);
+    const int nslots = std::min(b->nslots, nseries);
+    if (launch_batch(a, nslots, st) != hipSuccess) return SSA_EDEVICE;
+    return SSA_OK;
+}
+
+void ssa_batch_destroy(ssa_batch b) {
+    if (!b) return;
+    if (b->tab_done) {
+        (void)hipEventSynchronize(b->tab_done);
+        (void)hipEventDestroy(b->tab_done);
+    }
+    if (b->h_tab) (void)hipHostFree(b->h_tab);
+    delete b;
+}
+
+}  // extern "C"
+
+static_assert(sizeof(ssa::batch::Shared) <= 160 * 1024, "batch workgroup LDS exceeds the 160 KB of a CU");
+static_assert(2 * ssa::batch::kMaxMp <= ssa::batch::kEpt * ssa::batch::kThreads * 2,
+              "in-LDS FFT needs M' <= EPT * threads");

@@ -140,11 +140,26 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
     }
 }
 
+// Twiddle sources: W(t) = e^{-2 pi i t / n}.
+struct TableTw {  // full table of n entries
+    const float2* tw;
+    __device__ __forceinline__ float2 operator()(int t) const { return tw[t]; }
+};
+struct TwoLevelTw {  // W(t) = hi[t >> shift] * lo[t & mask]; two tables of ~sqrt(n) entries
+    const float2* hi;
+    const float2* lo;
+    int shift;
+    __device__ __forceinline__ float2 operator()(int t) const {
+        const float2 a = hi[t >> shift], b = lo[t & ((1 << shift) - 1)];
+        return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    }
+};
+
 // One Stockham stage of radix R over nseq sequences of length n.
-// p = product of the radices of earlier stages; tw[t] = e^{-2 pi i t / n}.
-template <int R, int DIR, int EPT>
+// p = product of the radices of earlier stages; tw(t) = e^{-2 pi i t / n}.
+template <int R, int DIR, int EPT, typename TW>
 __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstride, int p,
-                                          const float2* __restrict__ tw, int tid, int nthr) {
+                                          const TW& tw, int tid, int nthr) {
     constexpr int NB = (EPT + R - 1) / R;
     const int nq = n / R;
     const int nb = nq * nseq;
@@ -164,7 +179,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstr
             if (p > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    float2 w = tw[r * k * twstep];
+                    float2 w = tw(r * k * twstep);
                     if (DIR > 0) w.y = -w.y;
                     x[r] = cmul(x[r], w);
                 }
@@ -191,9 +206,9 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstr
 }
 
 // Full transform.  Requires n * nseq <= EPT * nthr.  Ends synchronized.
-template <int DIR, int EPT>
-__device__ void lds_fft(float2* buf, const FftStages& st, int nseq, int sstride,
-                        const float2* __restrict__ tw, int tid, int nthr) {
+template <int DIR, int EPT, typename TW>
+__device__ void lds_fft_tw(float2* buf, const FftStages& st, int nseq, int sstride, const TW& tw,
+                           int tid, int nthr) {
     int p = 1;
     for (int s = 0; s < st.nstages; ++s) {
         const int R = st.radix[s];
@@ -207,6 +222,12 @@ __device__ void lds_fft(float2* buf, const FftStages& st, int nseq, int sstride,
         }
         p *= R;
     }
+}
+
+template <int DIR, int EPT>
+__device__ void lds_fft(float2* buf, const FftStages& st, int nseq, int sstride,
+                        const float2* __restrict__ tw, int tid, int nthr) {
+    lds_fft_tw<DIR, EPT>(buf, st, nseq, sstride, TableTw{tw}, tid, nthr);
 }
 
 }  // namespace ssa

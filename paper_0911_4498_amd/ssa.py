@@ -43,7 +43,8 @@ class SsaPlanDesc(ctypes.Structure):
 
 EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
-            "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read")
+            "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read",
+            "ssa_batch_plan", "ssa_batch_bind", "ssa_batch_solve", "ssa_batch_destroy")
 
 # kernel classes of ssa_profile_read (enum ssa_prof_class)
 PROF_CLASSES = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz",
@@ -83,8 +84,14 @@ def load():
     lib.ssa_bidiag_ritz.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
     lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_uint]
     lib.ssa_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), dp, dp]
+    lib.ssa_batch_plan.argtypes = [ctypes.c_int, _c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts),
+                                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_c_p)]
+    lib.ssa_batch_bind.argtypes = [_c_p, _c_p, ctypes.c_size_t, _c_p]
+    lib.ssa_batch_solve.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
+    lib.ssa_batch_destroy.argtypes = [_c_p]
+    lib.ssa_batch_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("ssa_plan_destroy", "ssa_status_str"):
+        if name not in ("ssa_plan_destroy", "ssa_status_str", "ssa_batch_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -238,4 +245,78 @@ class Plan:
                                       V.contiguous().data_ptr(), k, ctypes.cast(offs_a, _c_p),
                                       ctypes.cast(mem_a, _c_p), m, out.data_ptr())
         _check(rc, "ssa_reconstruct")
+        return out
+
+
+class Batch:
+    """Many independent series solved by one persistent launch (``ssa_batch_*``)."""
+
+    def __init__(self, n_max: int, k_max: int, max_series: int, nslots: int = 0, d_max: int = 0,
+                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.lib = lib
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed))
+        ws = ctypes.c_size_t(0)
+        h = _c_p()
+        _check(lib.ssa_batch_plan(int(nslots), int(n_max), int(k_max), int(max_series), ctypes.byref(opts),
+                                  ctypes.byref(ws), ctypes.byref(h)), "ssa_batch_plan")
+        self._h = h
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib.ssa_batch_bind(h, base + off, int(ws.value), self.stream.cuda_stream), "ssa_batch_bind")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.ssa_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, series, L, k, recon: bool = True):
+        """series: list of 1-D arrays/tensors (or one concatenated FP64 device tensor with
+        ``offsets``); L, k: per-series lists.  Returns a dict of per-series views:
+        sigma[s] (k_s,), U[s] (k_s, L_s), V[s] (k_s, K_s), recon[s] (k_s, N_s) and
+        info (nseries, 4): steps, converged, restarts, DGKS passes."""
+        import numpy as np
+        torch = self._torch
+        parts = [torch.as_tensor(x, dtype=torch.float64, device=self.device).reshape(-1) for x in series]
+        ns = len(parts)
+        lens = np.array([int(p.numel()) for p in parts], dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        flat = torch.cat(parts).contiguous()
+        L = np.asarray(L, dtype=np.int32).reshape(ns)
+        k = np.asarray(k, dtype=np.int32).reshape(ns)
+        K = lens - L + 1
+        sig = torch.empty(int(k.sum()), dtype=torch.float64, device=self.device)
+        U = torch.empty(int((L * k).sum()), dtype=torch.float32, device=self.device)
+        V = torch.empty(int((K * k).sum()), dtype=torch.float32, device=self.device)
+        R = torch.empty(int((lens * k).sum()), dtype=torch.float32, device=self.device) if recon else None
+        info = torch.zeros((ns, 4), dtype=torch.int32, device=self.device)
+        rc = self.lib.ssa_batch_solve(self._h, ns, flat.data_ptr(), offs.ctypes.data, L.ctypes.data, k.ctypes.data,
+                                      sig.data_ptr(), U.data_ptr(), V.data_ptr(), R.data_ptr() if recon else None,
+                                      info.data_ptr())
+        _check(rc, "ssa_batch_solve")
+        self._keep = (flat, offs, L, k)
+        out = {"sigma": [], "U": [], "V": [], "recon": [] if recon else None, "info": info}
+        so = uo = vo = ro = 0
+        for s in range(ns):
+            ks, Ls, Ks, Ns = int(k[s]), int(L[s]), int(K[s]), int(lens[s])
+            out["sigma"].append(sig[so:so + ks])
+            out["U"].append(U[uo:uo + Ls * ks].view(ks, Ls))
+            out["V"].append(V[vo:vo + Ks * ks].view(ks, Ks))
+            if recon:
+                out["recon"].append(R[ro:ro + Ns * ks].view(ks, Ns))
+            so += ks
+            uo += Ls * ks
+            vo += Ks * ks
+            ro += Ns * ks
         return out

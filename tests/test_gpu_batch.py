@@ -1,0 +1,120 @@
+"""The many-series path (one persistent launch) against the FP64 oracle.
+
+Each series of a batch is compared with the oracle exactly as the single-series
+path is (``tests/parity.py``): sigma, vector subspaces per cluster, and the
+elementary reconstructions (summed over a cluster).  A series must give the
+same bits alone and inside a batch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0911_4498_amd import inputs
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_0911_4498_amd import ssa as mod
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_one(f, L, k, sig, U, V, rec, dense=True):
+    N = len(f)
+    K = N - L + 1
+    sg = sig.cpu().numpy()
+    Ug = U.cpu().numpy().T.astype(np.float64)
+    Vg = V.cpu().numpy().T.astype(np.float64)
+    kr = min(k + 4, min(L, K))
+    if dense:
+        sA, UA, VA = oracle.ssa_dense(f, L, kr)
+    else:
+        p0 = inputs.start_vector(L, 7)
+        sA, UA, VA, _, conv = oracle.lanczos_svd(f, L, kr, p0, tol=1e-12)
+        assert conv
+    fro = parity.frobenius(f, L)
+    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, fro)
+    groups = [c for c in parity.clusters(sA, k, fro) if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
+    rg = rec.cpu().numpy().astype(np.float64)
+    ref = oracle.reconstruct(N, L, sA[:k], UA[:, :k], VA[:, :k], groups)
+    got = np.array([rg[c].sum(axis=0) for c in groups])
+    rep["recon_err"] = parity.compare_recon(got, ref, np.abs(f).max())
+    return rep
+
+
+def small_batch(n):
+    rng = np.random.default_rng(2024)
+    series, Ls, ks = [], [], []
+    for s in range(n):
+        N = int(rng.integers(60, 1500))
+        kind = s % 4
+        if kind == 0:
+            f, _, _ = inputs.c3_series(s, N=N)
+        elif kind == 1:
+            f = inputs.c1_series(N)
+        elif kind == 2:
+            f = inputs.sinusoid(N, 17.0, 2.0) + 0.05 * inputs.white(N, s)
+        else:
+            f = inputs.white(N, s)
+        L = N // 2 if s % 5 else (3 * N) // 4  # some windows longer than the lag count
+        k = int(rng.integers(4, 17))
+        series.append(f)
+        Ls.append(L)
+        ks.append(min(k, L, N - L + 1))
+    return series, Ls, ks
+
+
+def test_batch_small_series_match_oracle(ssa):
+    series, Ls, ks = small_batch(12)
+    b = ssa.Batch(n_max=1500, k_max=16, max_series=64)
+    out = b.solve(series, Ls, ks)
+    info = out["info"].cpu().numpy()
+    for s, (f, L, k) in enumerate(zip(series, Ls, ks)):
+        say(f"batch series {s}: N={len(f)} L={L} k={k} steps={info[s, 0]} conv={info[s, 1]}")
+        rep = compare_one(f, L, k, out["sigma"][s], out["U"][s], out["V"][s], out["recon"][s])
+        say(f"   {rep}")
+        assert info[s, 1] == 1
+
+
+def test_batch_alone_equals_in_the_mix(ssa):
+    series, Ls, ks = small_batch(32)
+    b = ssa.Batch(n_max=1500, k_max=16, max_series=64, nslots=8)
+    mixed = b.solve(series, Ls, ks)
+    torch.cuda.synchronize()
+    for s in (0, 5, 17, 31):
+        alone = b.solve([series[s]], [Ls[s]], [ks[s]])
+        torch.cuda.synchronize()
+        for key in ("sigma", "U", "V", "recon"):
+            a = alone[key][0].cpu().numpy()
+            m = mixed[key][s].cpu().numpy()
+            assert np.array_equal(a, m), (s, key)
+
+
+@pytest.mark.parametrize("s", [3, 11])
+def test_batch_c3_series_match_oracle(ssa, s):
+    """Series of the many-series workload (N up to 20000, L = N/2, k = 16) against the
+    tier-B oracle (direct products), one series in a batch of four."""
+    f, N, L = inputs.c3_series(s)
+    N = min(N, 12000)
+    f, N, L = inputs.c3_series(s, N=N)
+    others = [inputs.c3_series(t, N=2000)[0] for t in range(3)]
+    b = ssa.Batch(n_max=20480, k_max=16, max_series=8)
+    out = b.solve([f] + others, [L] + [1000] * 3, [16] * 4)
+    info = out["info"].cpu().numpy()
+    say(f"c3 series {s}: N={N} steps={info[0, 0]} conv={info[0, 1]}")
+    rep = compare_one(f, L, 16, out["sigma"][0], out["U"][0], out["V"][0], out["recon"][0], dense=False)
+    say(f"   {rep}")
+    assert info[0, 1] == 1
