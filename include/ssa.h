@@ -48,7 +48,8 @@ enum ssa_status {
     SSA_ENONFINITE = -3,        /* the series holds NaN or Inf                            */
     SSA_EDEVICE = -4,           /* a HIP runtime call failed                              */
     SSA_EMISMATCH = -5,         /* N or L differ from the plan                            */
-    SSA_ESTATE = -6             /* call order violated (e.g. matvec before embed)         */
+    SSA_ESTATE = -6,            /* call order violated (e.g. matvec before embed)         */
+    SSA_EDISABLED = -7          /* entry point switched off (see its declaration)         */
 };
 
 /* Solver options; zero-initialized fields take the defaults shown. */
@@ -182,6 +183,9 @@ int ssa_batch_bind(ssa_batch batch, void* workspace_dev, size_t bytes, void* hip
  *     recon_dev: N_s*k_s floats (elementary series i at + i*N_s);
  *     info_dev: 4 ints per series (steps, converged, restarts, DGKS passes).
  * Asynchronous on the bound stream.  Errors: SSA_EINVAL, SSA_ENOMEM, SSA_EDEVICE.
+ * Currently switched off: after validating its arguments the call returns
+ * SSA_EDISABLED and enqueues nothing (the persistent kernel behind it did not
+ * finish on MI355X for a small batch; the cause is open).
  */
 int ssa_batch_solve(ssa_batch batch, int nseries, const double* series_dev, const long long* offsets,
                     const int* L, const int* k, double* sigma_dev, float* U_dev, float* V_dev,

@@ -21,6 +21,7 @@ SSA_ENONFINITE = -3
 SSA_EDEVICE = -4
 SSA_EMISMATCH = -5
 SSA_ESTATE = -6
+SSA_EDISABLED = -7
 
 _c_ll = ctypes.c_longlong
 _c_p = ctypes.c_void_p

@@ -14,7 +14,12 @@ import oracle
 from paper_0911_4498_amd import inputs
 from tests import parity
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="ssa_batch_solve is switched off (returns SSA_EDISABLED): the persistent "
+                            "many-series kernel did not finish on MI355X for a 12-series batch and the "
+                            "cause is not identified; the kernel stays off the GPU until it is"),
+]
 
 torch = pytest.importorskip("torch")
 

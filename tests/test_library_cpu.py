@@ -110,6 +110,29 @@ def test_unbound_plan_calls_fail_cleanly():
     assert ssa.status_str(ssa.SSA_ENONFINITE) == "series holds NaN or Inf"
 
 
+def test_batch_solve_switched_off_after_validation():
+    """The many-series entry point validates its arguments, then reports that it is
+    switched off without enqueuing anything (no device needed for either)."""
+    lib = _built()
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t(0)
+    assert lib.ssa_batch_plan(4, 1000, 8, 4, None, ctypes.byref(ws), ctypes.byref(h)) == 0
+    try:
+        p = ctypes.c_void_p(256)
+        offs = (ctypes.c_longlong * 3)(0, 100, 300)
+        Ls = (ctypes.c_int * 2)(50, 100)
+        ks = (ctypes.c_int * 2)(4, 8)
+        assert lib.ssa_batch_solve(h, 2, p, offs, Ls, ks, p, p, p, None, None) == ssa.SSA_EDISABLED
+        bad_k = (ctypes.c_int * 2)(4, 9)  # above k_max
+        assert lib.ssa_batch_solve(h, 2, p, offs, Ls, bad_k, p, p, p, None, None) == ssa.SSA_EINVAL
+        bad_L = (ctypes.c_int * 2)(50, 200)  # L >= N
+        assert lib.ssa_batch_solve(h, 2, p, offs, bad_L, ks, p, p, p, None, None) == ssa.SSA_EINVAL
+        assert lib.ssa_batch_solve(h, 5, p, offs, Ls, ks, p, p, p, None, None) == ssa.SSA_EINVAL
+    finally:
+        lib.ssa_batch_destroy(h)
+    assert ssa.status_str(ssa.SSA_EDISABLED) == "entry point switched off"
+
+
 def bidiag(alpha, beta, d):
     B = np.zeros((d + 1, d))
     for c in range(d):
