@@ -17,7 +17,11 @@ Prints one JSON line:
   cpu_baseline  the FP64 oracle (tier B: Lanczos + direct row products +
               direct antidiagonal averaging) timed on a bounded sample on this
               host and scaled to the same number of steps and triples
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  roofline.traffic  HBM bytes per launch of that kernel from two rocprofv3
+              counter runs (FETCH_SIZE, WRITE_SIZE; see
+              paper_0911_4498_amd/pmc_traffic.py), null unless the summary in
+              profiles/ was taken from the current library sources
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--pmc-copy]
 """
 import argparse
 import json
@@ -30,6 +34,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 N, L, K_TRIPLES = 100_000, 50_000, 20
+# kernel-name substring (as rocprofv3 prints it) of each profiled kernel class
+CLASS_KERNEL = {"pass1": "k_pass1<0", "pass2": "k_pass2_matvec", "pass3": "k_pass3<0",
+                "cgs_dots": "k_cgs_project", "cgs_reduce": "k_cgs_reduce", "cgs_update": "k_cgs_update",
+                "ritz": "k_ritz", "recon_pass1": "k_pass1<2", "recon_pass2": "k_pass2_recon",
+                "recon_pass3": "k_pass3<1"}
+
+
+def traffic_summary_path(cls):
+    return os.path.join(ROOT, "profiles", f"c2_{cls}_traffic.txt")
+
+
+def traffic_per_launch(cls):
+    """HBM bytes per launch of the class's kernel from the committed counter summary,
+    or None if there is none or the library sources changed since it was taken."""
+    from paper_0911_4498_amd import pmc_traffic
+    s = pmc_traffic.load_summary(traffic_summary_path(cls))
+    if not s or s.get("source_sha256") != pmc_traffic.source_hash():
+        return None
+    return float(s["traffic_bytes_per_launch"])
+
+
+def copy_calibration():
+    """A plain copy of known size (256 MiB read, 256 MiB written) for scaling the
+    FETCH_SIZE / WRITE_SIZE counters; only useful under rocprofv3 --pmc."""
+    import torch
+    n = 64 * 1024 * 1024  # floats
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_baseline(f, steps_gpu):
@@ -67,6 +103,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -82,6 +119,8 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     dev = torch.device("cuda:0")
+    if args.pmc_copy:
+        copy_calibration()
     f_np = inputs.c2_series(N)
     f = torch.tensor(f_np, device=dev)
     plan = ssa.Plan(N, L, K_TRIPLES, device=dev)
@@ -160,7 +199,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_per_launch(dom),
             "avg_launch_us": 1e3 * ms_l / max(n_l, 1),
             "alg_bytes_per_launch": b_l / max(n_l, 1),
         },
