@@ -59,6 +59,9 @@ typedef struct {
     double tol;             /* stop when every residual bound <= tol * max(omega_i, 1e-5 omega_1)
                                and the k Ritz values moved < 10 tol relative; default 1e-8   */
     unsigned long long seed;/* seed of the random start vector p_0 (Algorithm 1); default 1    */
+    int fft_m1;             /* FFT schedule override: first factor M1 of M/2 = M1*M2 (must
+                               divide M/2, both factors <= 4096); 0 = automatic              */
+    int fft_cb;             /* columns per workgroup in FFT passes 1 and 3 (1..64); 0 = auto */
 } ssa_opts;
 
 /* Per-solve report, filled by ssa_truncated_svd. */

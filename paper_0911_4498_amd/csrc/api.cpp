@@ -334,12 +334,32 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, si
         delete p;
         return SSA_EINVAL;
     }
+    if (opts && opts->fft_m1 > 0) {  // schedule override: M1 must split M' into factors <= kMaxFactor
+        const long long m1 = opts->fft_m1;
+        if (Mp % m1 != 0 || m1 > kMaxFactor || Mp / m1 > kMaxFactor) {
+            delete p;
+            return SSA_EINVAL;
+        }
+        M1 = (int)m1;
+        M2 = (int)(Mp / m1);
+    }
     ConvGeom& g = p->g;
     g.M1 = M1;
     g.M2 = M2;
     g.Mp = Mp;
     g.M = 2 * Mp;
-    int cb = (int)std::min<long long>({16LL, 8192LL / M1, ((long long)M2 + 63) / 64});
+    // columns per workgroup of passes 1 and 3: enough workgroups (~M2/CB >= 256) comes first;
+    // at N = 1e5 (M1 x M2 = 200 x 250) CB = 1 beats CB = 4 by 10% per product although the
+    // wider blocks fetch fewer partial lines (measured over every split of M' = 50000)
+    int cb = (int)std::min<long long>({16LL, 8192LL / M1, std::max(1LL, ((long long)M2 + 255) / 256)});
+    if (opts && opts->fft_cb > 0) {
+        // passes 1 and 3 hold CB columns of M1 points: at most 32 per thread of 256
+        if (opts->fft_cb > 64 || (long long)opts->fft_cb * M1 > 8192) {
+            delete p;
+            return SSA_EINVAL;
+        }
+        cb = opts->fft_cb;
+    }
     g.CB = std::max(1, cb);
     int shift = 0;
     while ((1LL << (2 * shift)) < Mp) ++shift;

@@ -29,7 +29,7 @@ _c_p = ctypes.c_void_p
 
 class SsaOpts(ctypes.Structure):
     _fields_ = [("d_max", ctypes.c_int), ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
-                ("seed", ctypes.c_ulonglong)]
+                ("seed", ctypes.c_ulonglong), ("fft_m1", ctypes.c_int), ("fft_cb", ctypes.c_int)]
 
 
 class SsaInfo(ctypes.Structure):
@@ -133,14 +133,14 @@ class Plan:
     """One series geometry (N, L) bound to a torch-allocated device workspace."""
 
     def __init__(self, N: int, L: int, k_max: int, d_max: int = 0, check_every: int = 0,
-                 tol: float = 0.0, seed: int = 0, device=None, stream=None):
+                 tol: float = 0.0, seed: int = 0, device=None, stream=None, fft_m1: int = 0, fft_cb: int = 0):
         import torch
         self._torch = torch
         lib = load()
         self.lib = lib
         self.N, self.L, self.K = int(N), int(L), int(N) - int(L) + 1
         self.k_max = int(k_max)
-        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed))
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), int(fft_m1), int(fft_cb))
         ws = ctypes.c_size_t(0)
         h = _c_p()
         _check(lib.ssa_embed_plan(self.N, self.L, self.k_max, ctypes.byref(opts), ctypes.byref(ws),

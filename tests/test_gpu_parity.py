@@ -103,6 +103,28 @@ def test_matvec_large(ssa, N, L):
     assert e2 <= mv_tol(f, u, plan.desc.M)
 
 
+@pytest.mark.parametrize("N,L,m1,cb", [(100000, 50000, 16, 1), (100000, 50000, 400, 16), (100000, 50000, 3125, 2),
+                                       (100000, 50000, 1000, 8), (20000, 10000, 100, 32), (1000, 500, 25, 8)])
+def test_matvec_fft_schedules(ssa, N, L, m1, cb):
+    """Every FFT schedule (split M' = M1 M2, columns per workgroup) gives the same products."""
+    say(f"matvec schedule N={N} L={L} M1={m1} CB={cb}")
+    K = N - L + 1
+    f = inputs.c2_series(N)
+    rng = np.random.default_rng(N + m1 + cb)
+    v = rng.normal(size=K)
+    u = rng.normal(size=L)
+    plan = ssa.Plan(N, L, 1, fft_m1=m1, fft_cb=cb)
+    assert plan.desc.M1 == m1
+    plan.embed(torch.tensor(f, device="cuda"))
+    y = plan.matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()
+    yt = plan.matvec(torch.tensor(u, dtype=torch.float32, device="cuda"), transpose=True).cpu().numpy()
+    ref = oracle.matvec(f, L, v.astype(np.float32).astype(np.float64))
+    reft = oracle.rmatvec(f, L, u.astype(np.float32).astype(np.float64))
+    assert np.abs(y - ref).max() <= mv_tol(f, v, plan.desc.M)
+    assert np.abs(yt - reft).max() <= mv_tol(f, u, plan.desc.M)
+    plan.close()
+
+
 def test_embed_rejects_nonfinite(ssa):
     f = inputs.white(100, 1)
     f[37] = np.nan

@@ -110,6 +110,32 @@ def test_unbound_plan_calls_fail_cleanly():
     assert ssa.status_str(ssa.SSA_ENONFINITE) == "series holds NaN or Inf"
 
 
+def test_fft_schedule_override():
+    """ssa_opts.fft_m1 / fft_cb select the split of M' = M1*M2 and the columns per workgroup;
+    invalid overrides are rejected."""
+    lib = _built()
+
+    def plan(m1, cb):
+        opts = ssa.SsaOpts(0, 0, 0.0, 0, m1, cb)
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        rc = lib.ssa_embed_plan(100000, 50000, 20, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h))
+        d = ssa.SsaPlanDesc()
+        if rc == 0:
+            assert lib.ssa_plan_describe(h, ctypes.byref(d)) == 0
+            lib.ssa_plan_destroy(h)
+        return rc, d
+
+    rc, d = plan(0, 0)
+    assert rc == 0 and d.M1 * d.M2 == 50000
+    rc, d = plan(400, 16)
+    assert rc == 0 and (d.M1, d.M2) == (400, 125)
+    assert plan(300, 0)[0] == ssa.SSA_EINVAL      # does not divide M' = 50000
+    assert plan(10, 0)[0] == ssa.SSA_EINVAL       # M2 = 5000 > 4096
+    assert plan(1000, 16)[0] == ssa.SSA_EINVAL    # 16 columns of 1000 points exceed 32 per thread
+    assert plan(200, 65)[0] == ssa.SSA_EINVAL
+
+
 def test_batch_solve_switched_off_after_validation():
     """The many-series entry point validates its arguments, then reports that it is
     switched off without enqueuing anything (no device needed for either)."""
