@@ -64,6 +64,9 @@ def _bind(lib):
     lib.oracle_ssa_dense.argtypes = [_D, _L, _L, ctypes.c_int, _D, _D, _D]
     lib.oracle_matvec.argtypes = [_D, _L, _L, _D, _D]
     lib.oracle_rmatvec.argtypes = [_D, _L, _L, _D, _D]
+    _LP = ctypes.POINTER(ctypes.c_long)
+    lib.oracle_matvec_rows.argtypes = [_D, _L, _L, ctypes.c_int, _D, _LP, _L, _D]
+    lib.oracle_hankelize_at.argtypes = [ctypes.c_double, _D, _L, _D, _L, _LP, _L, _D]
     lib.oracle_lanczos_svd.argtypes = [_D, _L, _L, ctypes.c_int, ctypes.c_int, _D, _D,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        _D, _D, _D, _I]
@@ -192,6 +195,35 @@ def rmatvec(f, L: int, u) -> np.ndarray:
     u = _f64(u)
     out = np.empty(f.size - L + 1)
     _load().oracle_rmatvec(_dp(f), f.size, L, _dp(u), _dp(out))
+    return out
+
+
+def _lp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+
+
+def matvec_rows(f, L: int, x, rows, transpose: bool = False) -> np.ndarray:
+    """Selected entries of X x (rows of X) or of X^T x (columns), each a plain dot product."""
+    f = _f64(f)
+    x = _f64(x)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty(rows.size)
+    rc = _load().oracle_matvec_rows(_dp(f), f.size, L, 1 if transpose else 0, _dp(x), _lp(rows), rows.size,
+                                     _dp(out))
+    if rc != 0:
+        raise ValueError("invalid arguments")
+    return out
+
+
+def hankelize_at(sigma: float, u, v, pos) -> np.ndarray:
+    """Sec. 2.4 at selected positions: mean of sigma u[a] v[b] over a + b = n, n in pos."""
+    u = _f64(u)
+    v = _f64(v)
+    pos = np.ascontiguousarray(pos, dtype=np.int64)
+    out = np.empty(pos.size)
+    rc = _load().oracle_hankelize_at(float(sigma), _dp(u), u.size, _dp(v), v.size, _lp(pos), pos.size, _dp(out))
+    if rc != 0:
+        raise ValueError("invalid arguments")
     return out
 
 

@@ -271,6 +271,42 @@ int oracle_rmatvec(const double* f, long N, long L, const double* u, double* out
     return 0;
 }
 
+/* Selected entries of a product with the trajectory matrix (Sec. 2.1), for
+ * sizes where a whole product is too slow ("tier C" certificates):
+ *   transpose = 0: out[q] = (X x)[rows[q]]   = sum_j f[rows[q] + j] x[j], x of length K;
+ *   transpose = 1: out[q] = (X^T x)[rows[q]] = sum_i f[i + rows[q]] x[i], x of length L.
+ * Each entry is the plain dot product of one row (column) of X with x. */
+int oracle_matvec_rows(const double* f, long N, long L, int transpose, const double* x,
+                       const long* rows, long nrows, double* out) {
+    if (N <= 2 || L <= 1 || L >= N || nrows < 0) return -1;
+    long K = N - L + 1;
+    long lim = transpose ? K : L, len = transpose ? L : K;
+    for (long q = 0; q < nrows; ++q)
+        if (rows[q] < 0 || rows[q] >= lim) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long q = 0; q < nrows; ++q) out[q] = dot(f + rows[q], x, len);
+    return 0;
+}
+
+/* Sec. 2.4 (eq. hankelization) at selected positions only: the mean of
+ * sigma * u[a] * v[b] over the antidiagonal a + b = n of sigma u v^T, for each
+ * n = pos[q] (0 <= n < L + K - 1). */
+int oracle_hankelize_at(double sigma, const double* u, long L, const double* v, long K,
+                        const long* pos, long npos, double* out) {
+    if (L <= 0 || K <= 0 || npos < 0) return -1;
+    for (long q = 0; q < npos; ++q)
+        if (pos[q] < 0 || pos[q] >= L + K - 1) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long q = 0; q < npos; ++q) {
+        long n = pos[q];
+        long a0 = n - (K - 1) > 0 ? n - (K - 1) : 0, a1 = n < L - 1 ? n : L - 1;
+        double acc = 0.0;
+        for (long a = a0; a <= a1; ++a) acc += u[a] * v[n - a];
+        out[q] = sigma * acc / (double)(a1 - a0 + 1);
+    }
+    return 0;
+}
+
 /* Modified Gram-Schmidt of x (length n) against ncol orthonormal columns
  * stored contiguously in Q (column c at Q + c*n). */
 static void mgs(double* x, const double* Q, long ncol, long n) {

@@ -1,0 +1,174 @@
+"""The other workload shapes as parity cases of the single-series path.
+
+* many-series workload: series of N in [2000, 20000], L = N/2, k = 16; the
+  dense oracle (tier A) where N <= 4000, else tier B (Lanczos with direct
+  products);
+* served stream: requests with N log-uniform in [1e3, 1e6], L in {N/4, N/2},
+  k in [8, 32]; tier B up to N = 20000, above it certificates;
+* very long series: N = 2^24, L = N/2, certificates only (k = 8 here; see the test).
+
+Certificates (tier C) at sizes the oracle cannot solve: residuals
+|X v_i - sigma_i u_i| and |X^T u_i - sigma_i v_i| in FP64 (from the library FFT
+or from sampled rows of X, oracle.matvec_rows), orthonormality of the
+vectors, ordering of sigma, the energy bound sum sigma_i^2 <= |X|_F^2, and the
+elementary reconstructed series at sampled positions against the definition
+(oracle.hankelize_at, with the GPU's own triples).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0911_4498_amd import inputs
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_0911_4498_amd import ssa as mod
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def solve(ssa, f, L, k, groups=None, d_max=0):
+    N = len(f)
+    plan = ssa.Plan(N, L, k, d_max=d_max)
+    s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), k)
+    rec = plan.reconstruct(s, U, V, groups) if groups is not None else None
+    return plan, s, U, V, info, rec
+
+
+def parity_vs_oracle(ssa, f, L, k, tier):
+    """sigma, cluster subspaces and grouped reconstructions against tier A or B."""
+    N = len(f)
+    K = N - L + 1
+    kr = min(k + 4, min(L, K))
+    if tier == "A":
+        sA, UA, VA = oracle.ssa_dense(f, L, kr)
+    else:
+        sA, UA, VA, steps, conv = oracle.lanczos_svd(f, L, kr, inputs.start_vector(L, 11), tol=1e-12)
+        assert conv
+    fro = parity.frobenius(f, L)
+    groups = [c for c in parity.clusters(sA, k, fro) if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
+    plan, s, U, V, info, rec = solve(ssa, f, L, k, groups)
+    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")
+    sg = s.cpu().numpy()
+    Ug = U.cpu().numpy().T.astype(np.float64)
+    Vg = V.cpu().numpy().T.astype(np.float64)
+    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, fro)
+    ref = oracle.reconstruct(N, L, sA[:k], UA[:, :k], VA[:, :k], groups)
+    rep["recon_err"] = parity.compare_recon(rec.cpu().numpy().astype(np.float64), ref, np.abs(f).max())
+    say(f"  {rep}")
+    plan.close()
+
+
+def certify(ssa, f, L, k, sampled_rows=0, recon_positions=256, d_max=0):
+    """Tier C certificates of a GPU solve (see the module docstring)."""
+    N = len(f)
+    K = N - L + 1
+    plan, s, U, V, info, _ = solve(ssa, f, L, k, d_max=d_max)
+    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")
+    sg = s.cpu().numpy()
+    assert np.all(sg > 0) and np.all(np.diff(sg) <= 1e-12 * sg[0])
+    assert np.sum(sg ** 2) <= parity.frobenius(f, L) ** 2 * (1 + 1e-6)
+    rng = np.random.default_rng(N + L + k)
+    worst = 0.0
+    Ug = U.cpu().numpy()
+    Vg = V.cpu().numpy()
+    if sampled_rows:
+        rows = np.sort(rng.choice(L, sampled_rows, replace=False))
+        cols = np.sort(rng.choice(K, sampled_rows, replace=False))
+    else:
+        Mfft = 1 << int(np.ceil(np.log2(2 * N)))
+        F = np.fft.rfft(f, Mfft)
+    for i in range(k):
+        u = Ug[i].astype(np.float64)
+        v = Vg[i].astype(np.float64)
+        if sampled_rows:
+            e1 = oracle.matvec_rows(f, L, v, rows) - sg[i] * u[rows]
+            e2 = oracle.matvec_rows(f, L, u, cols, transpose=True) - sg[i] * v[cols]
+            r1 = np.sqrt(L / rows.size * np.sum(e1 ** 2))
+            r2 = np.sqrt(K / cols.size * np.sum(e2 ** 2))
+        else:
+            y = np.fft.irfft(F * np.fft.rfft(v[::-1], Mfft), Mfft)[K - 1:K - 1 + L]
+            r1 = np.linalg.norm(y - sg[i] * u)
+            y = np.fft.irfft(F * np.fft.rfft(u[::-1], Mfft), Mfft)[L - 1:L - 1 + K]
+            r2 = np.linalg.norm(y - sg[i] * v)
+        worst = max(worst, r1 / sg[0], r2 / sg[0])
+    say(f"  worst residual / sigma_1 = {worst:.2e}")
+    assert worst <= 1e-5
+    for B in (Ug, Vg):
+        G = B.astype(np.float64) @ B.astype(np.float64).T
+        assert np.abs(G - np.eye(k)).max() <= 1e-5
+    # elementary series at sampled positions (both ends, where the counts are small, and inside)
+    pos = np.unique(np.concatenate([np.arange(8), N - 1 - np.arange(8), rng.choice(N, recon_positions, replace=False)]))
+    fmax = np.abs(f).max()
+    worst_r = 0.0
+    groups = [[i] for i in range(k)]
+    rec = plan.reconstruct(s, U, V, groups)
+    for i in range(k):
+        got = rec[i][torch.as_tensor(pos, device="cuda")].cpu().numpy().astype(np.float64)
+        ref = oracle.hankelize_at(sg[i], Ug[i].astype(np.float64), Vg[i].astype(np.float64), pos)
+        worst_r = max(worst_r, np.abs(got - ref).max())
+    say(f"  sampled elementary-series error {worst_r:.2e} (|F|inf {fmax:.3f})")
+    assert worst_r <= parity.RECON_REL * fmax
+    del rec
+    plan.close()
+
+
+def c3_pick():
+    """Seeded series of the many-series workload: the first with N <= 4000, the first with
+    N >= 16000, and series 0."""
+    small = next(s for s in range(200) if inputs.c3_shape(s)[0] <= 4000)
+    large = next(s for s in range(200) if inputs.c3_shape(s)[0] >= 16000)
+    return [(small, "A"), (large, "B"), (0, "A" if inputs.c3_shape(0)[0] <= 4000 else "B")]
+
+
+@pytest.mark.parametrize("s,tier", c3_pick())
+def test_many_series_workload_members(ssa, s, tier):
+    f, N, L = inputs.c3_series(s)
+    say(f"c3 series {s}: N={N} L={L} k=16 tier {tier}")
+    parity_vs_oracle(ssa, f, L, 16, tier)
+
+
+def c4_pick():
+    """Requests of the served stream: two with N <= 20000 (tier B), the first with
+    N in [2e5, 4e5] and the largest of the first 200 (certificates)."""
+    shapes = [inputs.c4_request(r)[1:] for r in range(200)]
+    small = [r for r, (N, L, k) in enumerate(shapes) if N <= 20000][:2]
+    mid = next(r for r, (N, L, k) in enumerate(shapes) if 2e5 <= N <= 4e5)
+    big = int(np.argmax([N for N, L, k in shapes]))
+    return [(r, "B") for r in small] + [(mid, "C"), (big, "C")]
+
+
+@pytest.mark.parametrize("r,tier", c4_pick())
+def test_served_stream_requests(ssa, r, tier):
+    f, N, L, k = inputs.c4_request(r)
+    say(f"c4 request {r}: N={N} L={L} k={k} tier {tier}")
+    if tier == "B":
+        parity_vs_oracle(ssa, f, L, k, "B")
+    else:
+        certify(ssa, f, L, k)
+
+
+def test_very_long_series(ssa):
+    """The full-length series (N = 2^24, L = N/2) with its leading k = 8 triples and at most
+    40 Lanczos steps.  Full reorthogonalization reads the whole basis every step, so the
+    workload's k = 50 (d ~ 200: ~2.7 TB of Gram-Schmidt traffic) is a measurement, not a
+    test case."""
+    N = 2 ** 24
+    L, k = N // 2, 8
+    say(f"c5 series: N={N} L={L} k={k} d_max=40 (certificates, sampled rows)")
+    f = inputs.c5_series(N)
+    certify(ssa, f, L, k, sampled_rows=128, recon_positions=128, d_max=40)

@@ -264,6 +264,42 @@ def test_direct_products_match_explicit(N, L):
     np.testing.assert_allclose(oracle.rmatvec(f, L, u), X.T @ u, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("N,L", [(3, 2), (10, 3), (10, 8), (64, 32), (101, 7)])
+def test_sampled_rows_match_explicit(N, L):
+    """Tier C: selected rows (columns) of X times a vector, against the explicit matrix."""
+    f = inputs.white(N, N * 5 + L)
+    X = hankel_lib(f, L)
+    K = N - L + 1
+    rng = np.random.default_rng(N + 1)
+    v = rng.normal(size=K)
+    u = rng.normal(size=L)
+    rows = np.array(sorted(set(rng.integers(0, L, size=5).tolist()) | {0, L - 1}))
+    cols = np.array(sorted(set(rng.integers(0, K, size=5).tolist()) | {0, K - 1}))
+    np.testing.assert_allclose(oracle.matvec_rows(f, L, v, rows), (X @ v)[rows], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(oracle.matvec_rows(f, L, u, cols, transpose=True), (X.T @ u)[cols],
+                               rtol=1e-13, atol=1e-13)
+    with pytest.raises(ValueError):
+        oracle.matvec_rows(f, L, v, np.array([L]))
+    with pytest.raises(ValueError):
+        oracle.matvec_rows(f, L, u, np.array([-1]), transpose=True)
+
+
+def test_hankelize_at_matches_explicit_antidiagonals():
+    """Sec. 2.4 at sampled positions: the mean over each antidiagonal of the explicit sigma u v^T."""
+    rng = np.random.default_rng(7)
+    for L, K in [(5, 9), (9, 5), (13, 13), (2, 30), (1, 4)]:
+        u = rng.normal(size=L)
+        v = rng.normal(size=K)
+        Y = 2.5 * np.outer(u, v)
+        N = L + K - 1
+        flipped = np.fliplr(Y)  # antidiagonal a + b = n is the diagonal with offset (K - 1) - n
+        expect = np.array([np.diagonal(flipped, offset=(K - 1) - n).mean() for n in range(N)])
+        pos = np.arange(N)[::-1].copy()
+        np.testing.assert_allclose(oracle.hankelize_at(2.5, u, v, pos), expect[pos], atol=1e-13)
+    with pytest.raises(ValueError):
+        oracle.hankelize_at(1.0, u, v, np.array([L + K - 1]))
+
+
 # --- tier B: Lanczos with full reorthogonalization -------------------------------
 
 def test_gkl_relations():

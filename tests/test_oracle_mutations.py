@@ -32,6 +32,12 @@ MUTATIONS = {
     "bidiagonal_wrong_beta": (
         "B[(long)(c + 1) * jj + c] = beta[c + 2];", "B[(long)(c + 1) * jj + c] = beta[c + 1];",
         [lambda: pins.test_tier_b_matches_tier_a(300, 150, 10)]),
+    "sampled_rows_off_by_one": (
+        "out[q] = dot(f + rows[q], x, len);", "out[q] = dot(f + rows[q] + 1, x, len - 1);",
+        [lambda: pins.test_sampled_rows_match_explicit(64, 32)]),
+    "hankelize_at_count_dropped_end": (
+        "out[q] = sigma * acc / (double)(a1 - a0 + 1);", "out[q] = sigma * acc / (double)(a1 - a0);",
+        [pins.test_hankelize_at_matches_explicit_antidiagonals]),
     "trajectory_shifted": (
         "X[i * K + j] = f[i + j];", "X[i * K + j] = f[i + j + (i + j + 1 < N)];",
         [pins.test_trajectory_matches_library_hankel]),
