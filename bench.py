@@ -21,7 +21,12 @@ Prints one JSON line:
               counter runs (FETCH_SIZE, WRITE_SIZE; see
               paper_0911_4498_amd/pmc_traffic.py), null unless the summary in
               profiles/ was taken from the current library sources
+With --workload many: the many-series workload instead (4096 series, N uniform
+in [2000, 20000], L = N/2, k = 16, seeded), solved together by the batched
+engine (ssa_batch_*); the JSON line also reports the single-series path on a
+sample of the same series, one series at a time, on the same GPU.
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--pmc-copy]
+                       [--workload single|many] [--series S] [--sample S1]
 """
 import argparse
 import json
@@ -97,6 +102,87 @@ def cpu_baseline(f, steps_gpu):
     }
 
 
+def bench_many(args):
+    """Many-series workload: batched engine vs one series at a time (eigentriples/s)."""
+    import numpy as np
+    import torch
+
+    from paper_0911_4498_amd import inputs, ssa
+    dev = torch.device("cuda:0")
+    ns, k = args.series, 16
+    print(f"# generating {ns} series", file=sys.stderr, flush=True)
+    host = [inputs.c3_series(s) for s in range(ns)]
+    series = [torch.tensor(f, device=dev) for f, _, _ in host]
+    Ls = [L for _, _, L in host]
+    Ns = np.array([N for _, N, _ in host])
+    keys = list(range(ns))
+    eng = ssa.Batch(n_max=20000, k_max=k, max_series=ns)
+    steps = []
+
+    def step():
+        out = eng.solve(series, Ls, [k] * ns, keys=keys)
+        steps.append(out["info"])
+        return out
+
+    print(f"# warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    info = steps[-1].cpu().numpy()
+    rate_b = ns * k * args.steps / t_b
+    print(f"# batched: {t_b / args.steps * 1e3:.1f} ms per batch, {rate_b:.0f} eigentriples/s, "
+          f"mean d {info[:, 0].mean():.1f}, converged {info[:, 1].mean():.3f}", file=sys.stderr, flush=True)
+    # one series at a time with the single-series path (plans built untimed)
+    m = min(args.sample, ns)
+    plans = [ssa.Plan(int(Ns[s]), Ls[s], k, device=dev) for s in range(m)]
+    groups = [[i] for i in range(k)]
+
+    def one(s):
+        sg, U, V, inf = plans[s].truncated_svd(series[s], k)
+        plans[s].reconstruct(sg, U, V, groups)
+        return inf
+
+    for s in range(min(4, m)):
+        one(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d1 = [one(s).steps for s in range(m)]
+    torch.cuda.synchronize()
+    t_1 = time.perf_counter() - t0
+    rate_1 = m * k / t_1
+    print(f"# one at a time: {m} series in {t_1:.3f} s, {rate_1:.0f} eigentriples/s, mean d {np.mean(d1):.1f}",
+          file=sys.stderr, flush=True)
+    out = {
+        "metric": "eigentriples/s (many-series workload)",
+        "value": rate_b,
+        "unit": "eigentriples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_b / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{ns} series, N uniform in [2000, 20000], L = N/2, k = 16, two sinusoids + "
+                               "trend + N(0, 0.1^2) (seeded); truncated SVD + 16 elementary reconstructions each",
+                   "series": ns, "k": k, "parallelism": "single GPU"},
+        "lanczos_steps_mean": float(info[:, 0].mean()),
+        "converged_fraction": float(info[:, 1].mean()),
+        "one_at_a_time": {"value": rate_1, "unit": "eigentriples/s", "series_timed": m,
+                          "lanczos_steps_mean": float(np.mean(d1)),
+                          "path": "single-series plans (ssa_truncated_svd + ssa_reconstruct), one series after another"},
+        "speedup_vs_one_at_a_time": rate_b / rate_1,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,12 +190,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
+    ap.add_argument("--workload", choices=("single", "many"), default="single")
+    ap.add_argument("--series", type=int, default=4096, help="series of the many-series workload")
+    ap.add_argument("--sample", type=int, default=256, help="series timed one at a time (many-series workload)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X; "
               "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "many":
+        from paper_0911_4498_amd import ssa as _ssa
+        if not os.path.exists(_ssa.LIB_PATH):
+            import __graft_entry__
+            __graft_entry__.build()
+        return bench_many(args)
 
     import numpy as np
     import torch

@@ -48,8 +48,7 @@ enum ssa_status {
     SSA_ENONFINITE = -3,        /* the series holds NaN or Inf                            */
     SSA_EDEVICE = -4,           /* a HIP runtime call failed                              */
     SSA_EMISMATCH = -5,         /* N or L differ from the plan                            */
-    SSA_ESTATE = -6,            /* call order violated (e.g. matvec before embed)         */
-    SSA_EDISABLED = -7          /* entry point switched off (see its declaration)         */
+    SSA_ESTATE = -6             /* call order violated (e.g. matvec before embed)         */
 };
 
 /* Solver options; zero-initialized fields take the defaults shown. */
@@ -150,49 +149,66 @@ int ssa_reconstruct(ssa_plan plan, const double* sigma_dev, const float* U_dev,
                     const int* group_members, int m, float* out_dev);
 
 /*
- * Many independent series in one launch ("batched" path).  One persistent
- * kernel: each workgroup takes the next series from a work counter and runs
- * the whole method on it -- spectrum, Algorithm 1 with classical Gram-Schmidt
- * reorthogonalization and FFT products held in LDS, the stopping test and Ritz
- * vectors on the device, then the rank-1 Hankelization (Algorithm 4) of each
- * of the k triples.  A series' result does not depend on the other series in
- * the batch or on which workgroup ran it.
+ * Many independent series solved together (the batched path).  The series
+ * advance in lockstep, one launch per Lanczos half-step for the whole batch
+ * with one workgroup per series.  Each workgroup runs Algorithm 1 for its
+ * series: the FFT products of Algorithms 2/3 and classical Gram-Schmidt
+ * reorthogonalization (Sec. 3.2.2), all in LDS.  At check points the stopping
+ * test on B_j runs on the device (eqs. lbdiagm1/lbdiagm2).  At the end come the
+ * Ritz triples and the rank-1 Hankelization of every triple (Algorithm 4).
+ * A series' result depends only on the series, its key and the seed: it is
+ * the same alone and inside any batch.
  */
 typedef struct ssa_batch_s* ssa_batch;
 
 /*
- * ssa_batch_plan -- size a batch engine: nslots workgroups (0 = 256), series of
- * length 3 <= N <= n_max (n_max <= 20480), up to k_max <= 32 triples, up to
- * max_series series per solve.  opts as for ssa_embed_plan (d_max capped at
- * 320).  Errors: SSA_EINVAL.
+ * ssa_batch_plan -- host-side engine for up to max_series series per solve.
+ * Each series has length 3 <= N <= n_max (n_max <= 20480) and up to
+ * k_max <= 32 triples.  opts as for ssa_embed_plan; d_max is capped at 320;
+ * fft_m1/fft_cb do not apply (each series' FFT is one workgroup's).
+ * *workspace_bytes: enough for max_series series of length n_max with
+ * L = n_max/2 and k = k_max.  ssa_batch_workspace gives the exact figure for
+ * given series.  Errors: SSA_EINVAL.
  */
-int ssa_batch_plan(int nslots, long long n_max, int k_max, int max_series, const ssa_opts* opts,
+int ssa_batch_plan(long long n_max, int k_max, int max_series, const ssa_opts* opts,
                    size_t* workspace_bytes, ssa_batch* out);
 
-/* ssa_batch_bind -- as ssa_plan_bind, for a batch engine. */
+/*
+ * ssa_batch_workspace -- device workspace bytes that ssa_batch_solve needs for
+ * these series (same host arrays as ssa_batch_solve).  Errors: SSA_EINVAL.
+ */
+int ssa_batch_workspace(ssa_batch batch, int nseries, const long long* offsets, const int* L,
+                        const int* k, size_t* bytes);
+
+/* ssa_batch_bind -- as ssa_plan_bind, for a batch engine (workspace 256-byte aligned). */
 int ssa_batch_bind(ssa_batch batch, void* workspace_dev, size_t bytes, void* hip_stream);
 
 /*
- * ssa_batch_solve -- the k_s leading triples (and, if recon_dev is not NULL,
- * the k_s elementary reconstructed series) of every series s.
- *   series_dev: all series concatenated (FP64, device); offsets (host,
- *   nseries+1, offsets[0] = 0): series s is series_dev[offsets[s] ..
- *   offsets[s+1]); L (host, nseries) window lengths, 1 < L[s] < N_s; k (host,
- *   nseries) triples, 1 <= k[s] <= min(k_max, L[s], K_s).
+ * ssa_batch_solve -- the k_s leading triples of every series s and, if
+ * recon_dev is not NULL, its k_s elementary reconstructed series.
+ *   series_dev: all series concatenated (FP64, device).
+ *   offsets (host, nseries+1, offsets[0] = 0): series s is
+ *     series_dev[offsets[s] .. offsets[s+1]).
+ *   L (host, nseries): window lengths, 1 < L[s] < N_s.
+ *   k (host, nseries): triples, 1 <= k[s] <= min(k_max, L[s], K_s).
+ *   keys (host, nseries, may be NULL = 0..nseries-1): seed the start and
+ *     restart vectors of each series.  A series with the same key gives the
+ *     same bits alone and in any batch.
  *   Outputs (device), one block per series in input order:
- *     sigma_dev: k_s doubles;
+ *     sigma_dev: k_s doubles, descending;
  *     U_dev: L_s*k_s floats (u_i at + i*L_s);
  *     V_dev: K_s*k_s floats (v_i at + i*K_s);
  *     recon_dev: N_s*k_s floats (elementary series i at + i*N_s);
- *     info_dev: 4 ints per series (steps, converged, restarts, DGKS passes).
- * Asynchronous on the bound stream.  Errors: SSA_EINVAL, SSA_ENOMEM, SSA_EDEVICE.
- * Currently switched off: after validating its arguments the call returns
- * SSA_EDISABLED and enqueues nothing (the persistent kernel behind it did not
- * finish on MI355X for a small batch; the cause is open).
+ *     info_dev (may be NULL): 4 ints per series (steps d, converged,
+ *       restarts, DGKS passes).
+ * Asynchronous on the bound stream.  The host returns once every series has
+ * finished its steps; the outputs are valid after the stream synchronizes.
+ * Errors: SSA_EINVAL, SSA_ENOMEM (unbound, or the bound workspace is smaller
+ * than ssa_batch_workspace), SSA_EDEVICE.
  */
 int ssa_batch_solve(ssa_batch batch, int nseries, const double* series_dev, const long long* offsets,
-                    const int* L, const int* k, double* sigma_dev, float* U_dev, float* V_dev,
-                    float* recon_dev, int* info_dev);
+                    const int* L, const int* k, const unsigned long long* keys, double* sigma_dev,
+                    float* U_dev, float* V_dev, float* recon_dev, int* info_dev);
 
 /* ssa_batch_destroy -- free the host-side batch engine. */
 void ssa_batch_destroy(ssa_batch batch);

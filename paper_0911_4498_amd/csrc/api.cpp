@@ -663,7 +663,6 @@ const char* ssa_status_str(int status) {
         case SSA_EDEVICE: return "HIP runtime error";
         case SSA_EMISMATCH: return "N or L differ from the plan";
         case SSA_ESTATE: return "call order violated";
-        case SSA_EDISABLED: return "entry point switched off";
         default: return "unknown status";
     }
 }

@@ -1,33 +1,35 @@
-// batch.hip -- many independent series in one persistent launch.
+// batch.hip -- many independent series advanced in lockstep.
 //
-// Every workgroup (1024 threads, one per CU) repeatedly takes the next series
-// from a work counter and runs the whole hot path for it: the spectrum of the
-// series (Algorithm 2, steps 1-2), Golub-Kahan-Lanczos bidiagonalization with
-// full classical Gram-Schmidt reorthogonalization (Algorithm 1, Sec. 3.2.2)
-// whose products X v / X^T u are FFT convolutions done entirely in LDS
-// (Algorithms 2/3), the stopping test on B_j (eqs. lbdiagm1/lbdiagm2), the Ritz
-// triples, and the rank-1 Hankelization of every triple (Algorithm 4).  A
-// series' result depends only on the series, its index and the seed -- never
-// on which workgroup ran it or what ran beside it -- and no workgroup waits
-// for another (the only shared state is the work counter).
+// Every launch has one workgroup (512 threads) per series of the batch, and a
+// series' result depends only on the series and its seed, never on what runs
+// beside it.  Per Lanczos step the host enqueues
+//   kb_half(j, side 0): r_j = X^T u_j - beta_j v_{j-1}, Gram-Schmidt against V,
+//                       alpha_j, v_j                    (Algorithm 1; Algorithm 3)
+//   kb_check(j):        stopping test on B_{j-1}         (eqs. lbdiagm1/lbdiagm2)
+//   kb_half(j, side 1): p_j = X v_j - alpha_j u_j, Gram-Schmidt against U,
+//                       beta_{j+1}, u_{j+1}             (Algorithm 1; Algorithm 2)
+// and after the last step kb_ritz (Ritz triples) and kb_hankel (rank-1
+// Hankelization of every triple, Algorithm 4).  A series whose stopping rule
+// held is skipped by every later launch.
 //
-// Sizes: the FFT of a series has M' = M/2 <= kMaxMp complex points (M >= N the
-// smallest even length with a 7-smooth half), held in LDS with two small
-// twiddle tables.  The Lanczos bases of the series live in the workgroup's
-// slot of HBM.
+// Inside a workgroup the product is the circular convolution of the
+// zero-padded series with the reversed input vector (Sec. 4.2-4.3), done as a
+// packed-real FFT of M' = M/2 complex points entirely in LDS; Gram-Schmidt is
+// classical with FP64 sums of exact FP32 products, a second pass by the DGKS
+// criterion and a seeded random restart on breakdown (Sec. 3.2.2).
 //
-// The stopping test and the Ritz vectors use T = B_j^T B_j (symmetric
-// tridiagonal, T[c][c] = alpha_{c+1}^2 + beta_{c+2}^2, T[c][c+1] =
-// alpha_{c+2} beta_{c+2}):
-//  * eigenvalues by multisection: each of the k largest is bracketed by
-//    Sturm counts of the pivots d_c(x) of T - x I, many shifts per round in
-//    parallel;
-//  * the last component of each eigenvector from q[n-1]^2 = -1 / d'_{n-1}(lambda),
-//    where d' follows by differentiating the pivot recurrence (det(T - x I) =
-//    prod d_c(x), and the adjugate of T - lambda I at a simple eigenvalue);
-//  * the residual bound alpha_{j+1} beta_{j+1} |q[n-1]| / omega (eq. lbdiagm2);
-//  * final vectors by inverse iteration (one thread per vector) followed by
-//    modified Gram-Schmidt across the k vectors.
+// The stopping test works on T = B^T B (symmetric tridiagonal, T[c][c] =
+// alpha_{c+1}^2 + beta_{c+2}^2, T[c][c+1] = alpha_{c+2} beta_{c+2}):
+//  * its k largest eigenvalues by multisection on Sturm counts of the pivots
+//    d_c(x) of T - x I;
+//  * the last component of each eigenvector from the twisted factorization of
+//    T - lambda I (products of pivot ratios, accurate for the tiny tails of
+//    converged Ritz vectors);
+//  * the residual bound alpha_{j+1} beta_{j+1} |q[n-1]| / omega (eq. lbdiagm2).
+// The Ritz coefficients come from inverse iteration on T (one thread per
+// triple) followed by modified Gram-Schmidt across the k vectors.
+//
+// All helpers are inlined into the kernels, so LDS is addressed directly.
 #include <hip/hip_runtime.h>
 
 #include "ssa_batch.h"
@@ -35,13 +37,57 @@
 namespace ssa {
 namespace batch {
 
-__device__ __forceinline__ double wsum(double v) {
+#define SSA_INLINE __device__ __attribute__((always_inline)) inline
+
+struct Lds {
+    float2 buf[kMaxMp];
+    float2 tw_hi[kTwTab];
+    float2 tw_lo[kTwTab];
+    double red[kWaves][kDmax + 2];
+    double h[kDmax + 2];
+    double ab[2 * (kDmax + 3)];  // alpha | beta
+    double tri[2 * (kDmax + 2)];
+    double lo[kMaxK], hi[kMaxK], lam[kMaxK], qlast[kMaxK];
+    double xs[kThreads];
+    int cnt[kThreads];
+    double misc[kWaves];
+    double dmisc[8];
+    int imisc[8];
+};
+
+SSA_INLINE double wsum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
 }
 
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+SSA_INLINE double block_sum(Lds* sh, double v, int tid) {
+    v = wsum(v);
+    __syncthreads();
+    if ((tid & 63) == 0) sh->misc[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += sh->misc[w];
+    __syncthreads();
+    return s;
+}
+
+SSA_INLINE double block_max(Lds* sh, double v, int tid) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) sh->misc[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s = fmax(s, sh->misc[w]);
+    __syncthreads();
+    return s;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): counter (t, ctr), key = seed.
+SSA_INLINE void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -57,7 +103,8 @@ __device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) 
     }
 }
 
-__device__ __forceinline__ float gaussian(unsigned long long seed, unsigned long long ctr, long long t) {
+// standard normal by Box-Muller from one Philox block
+SSA_INLINE float gaussian(unsigned long long seed, unsigned long long ctr, long long t) {
     uint32_t c[4] = {(uint32_t)t, (uint32_t)((unsigned long long)t >> 32), (uint32_t)ctr, (uint32_t)(ctr >> 32)};
     philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
     const double u1 = ((double)c[0] + 1.0) * (1.0 / 4294967296.0);
@@ -65,126 +112,297 @@ __device__ __forceinline__ float gaussian(unsigned long long seed, unsigned long
     return (float)(sqrt(-2.0 * log(u1)) * cospi(2.0 * u2));
 }
 
-// ---------------------------------------------------------------------------
-// workgroup helpers
-
-struct Ctx {
-    Shared* sh;
-    int tid;
-    // series
-    long long N, Li, Ki;  // internal window Li <= Ki
-    int Mp, tw_shift;
-    unsigned long long seed;
-    // slot
-    float* Ub;
-    float* Vb;
-    long long ld;
-    float4* AB;
-    double* scratch;  // inverse-iteration work, k * 6 * (kDmax + 2) doubles
-    double* P;
-    double* Q;
-};
-
-__device__ double block_sum(Ctx& c, double v) {
-    v = wsum(v);
-    const int lane = c.tid & 63, wave = c.tid >> 6;
-    __syncthreads();
-    if (lane == 0) c.sh->misc[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += c.sh->misc[w];
-    __syncthreads();
-    return s;
-}
-
-__device__ double block_max(Ctx& c, double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-    const int lane = c.tid & 63, wave = c.tid >> 6;
-    __syncthreads();
-    if (lane == 0) c.sh->misc[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) s = fmax(s, c.sh->misc[w]);
-    __syncthreads();
-    return s;
-}
-
-__device__ void fft(Ctx& c, int dir) {
-    const TwoLevelTw tw{c.sh->tw_hi, c.sh->tw_lo, c.tw_shift};
-    if (dir < 0)
-        lds_fft_tw<-1, kEpt>(c.sh->buf, c.sh->st, 1, c.Mp, tw, c.tid, kThreads);
-    else
-        lds_fft_tw<1, kEpt>(c.sh->buf, c.sh->st, 1, c.Mp, tw, c.tid, kThreads);
-}
-
-// element m of the real sequence packed in buf (w[2n] + i w[2n+1] at buf[n])
-__device__ __forceinline__ float getr(const float2* buf, long long m) {
+// real element m of the sequence packed in buf (w[2n] + i w[2n+1] at buf[n])
+SSA_INLINE float getr(const float2* buf, long long m) {
     const float2 z = buf[m >> 1];
     return (m & 1) ? z.y : z.x;
 }
-__device__ __forceinline__ void setr(float2* buf, long long m, float v) {
+SSA_INLINE void setr(float2* buf, long long m, float v) {
     if (m & 1)
         buf[m >> 1].y = v;
     else
         buf[m >> 1].x = v;
 }
 
-// FFT length, radix plan and twiddle tables of one series
-__device__ void setup_series_fft(Ctx& c) {
-    long long mp = (c.N + 1) / 2;
-    for (;; ++mp) {
-        long long m = mp;
-        for (int p : {2, 3, 5, 7})
-            while (m % p == 0) m /= p;
-        if (m == 1) break;
-    }
-    c.Mp = (int)mp;
-    if (c.tid == 0) {
-        FftStages& st = c.sh->st;
-        st.n = c.Mp;
-        st.nstages = 0;
-        int m = c.Mp;
-        while (m % 8 == 0) { st.radix[st.nstages++] = 8; m /= 8; }
-        while (m % 4 == 0) { st.radix[st.nstages++] = 4; m /= 4; }
-        while (m % 2 == 0) { st.radix[st.nstages++] = 2; m /= 2; }
-        for (int p : {3, 5, 7})
-            while (m % p == 0) { st.radix[st.nstages++] = p; m /= p; }
-    }
-    int shift = 0;
-    while ((1LL << (2 * shift)) < c.Mp) ++shift;
-    c.tw_shift = shift;
-    const int S = 1 << shift, nhi = (c.Mp + S - 1) / S;
-    for (int t = c.tid; t < S || t < nhi; t += kThreads) {
-        double sn, cs;
-        if (t < S) {
-            sincospi(-2.0 * (double)t / (double)c.Mp, &sn, &cs);
-            c.sh->tw_lo[t] = make_float2((float)cs, (float)sn);
+// Per-series constants of one launch.
+struct Ser {
+    long long N, Li, Ki, ldu, ldv;
+    int k, dcap, Mp, tw_shift;
+    unsigned long long seed;
+    const FftStages* st;  // radix plan (in the series table)
+    float4* AB;
+    float2* tw;  // hi | lo tables, kTwTab each
+    float* U;
+    float* V;
+    double* alpha;
+    double* beta;
+    double* state;
+    double* P;
+    double* Q;
+    double* scr;
+};
+
+SSA_INLINE Ser load_series(const BatchArgs& a, int s) {
+    const BSeries& b = a.tab[s];
+    Ser r;
+    r.N = b.N;
+    r.Li = b.Li;
+    r.Ki = b.Ki;
+    r.ldu = b.ldu;
+    r.ldv = b.ldv;
+    r.k = b.k;
+    r.dcap = b.dcap;
+    r.Mp = b.Mp;
+    r.tw_shift = b.tw_shift;
+    r.seed = b.seed;
+    r.st = &b.st;
+    char* base = a.ws + b.reg;
+    r.AB = reinterpret_cast<float4*>(base + b.o_ab);
+    r.tw = reinterpret_cast<float2*>(base + b.o_tw);
+    r.U = reinterpret_cast<float*>(base + b.o_u);
+    r.V = reinterpret_cast<float*>(base + b.o_v);
+    r.alpha = reinterpret_cast<double*>(base + b.o_alpha);
+    r.beta = reinterpret_cast<double*>(base + b.o_beta);
+    r.state = reinterpret_cast<double*>(base + b.o_state);
+    r.P = reinterpret_cast<double*>(base + b.o_p);
+    r.Q = reinterpret_cast<double*>(base + b.o_q);
+    r.scr = reinterpret_cast<double*>(base + b.o_scr);
+    return r;
+}
+
+// M'-point complex FFT of buf in LDS (forward DIR = -1, inverse +1, no scaling)
+template <int DIR>
+SSA_INLINE void fft(Lds* sh, const Ser& q, int tid) {
+    const TwoLevelTw tw{sh->tw_hi, sh->tw_lo, q.tw_shift};
+    int p = 1;
+    const int ns = q.st->nstages;
+    for (int s = 0; s < ns; ++s) {
+        const int R = q.st->radix[s];
+        switch (R) {
+            case 8: fft_stage<8, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
+            case 4: fft_stage<4, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
+            case 2: fft_stage<2, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
+            case 3: fft_stage<3, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
+            case 5: fft_stage<5, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
+            default: fft_stage<7, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
         }
-        if (t < nhi) {
-            sincospi(-2.0 * (double)((long long)t * S) / (double)c.Mp, &sn, &cs);
-            c.sh->tw_hi[t] = make_float2((float)cs, (float)sn);
+        p *= R;
+    }
+}
+
+SSA_INLINE void load_twiddles(Lds* sh, const Ser& q, int tid) {
+    for (int t = tid; t < kTwTab; t += kThreads) {
+        sh->tw_hi[t] = q.tw[t];
+        sh->tw_lo[t] = q.tw[kTwTab + t];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// products (Algorithms 2 and 3)
+
+// r = X x or X^T x (x: n_in entries in HBM) minus coef * prev; r[t] stays in
+// buf at real position n_in - 1 + t.
+SSA_INLINE void convolve(Lds* sh, const Ser& q, const float* x, long long n_in, long long n_out, const float* prev,
+                         double coef, int tid) {
+    float2* buf = sh->buf;
+    for (int n = tid; n < q.Mp; n += kThreads) {
+        const long long m0 = 2LL * n, m1 = m0 + 1;
+        buf[n] = make_float2(m0 < n_in ? x[n_in - 1 - m0] : 0.0f, m1 < n_in ? x[n_in - 1 - m1] : 0.0f);
+    }
+    __syncthreads();
+    fft<-1>(sh, q, tid);
+    // Q(k) = A(k) Z(k) + B(k) conj Z(M'-k), for the bin pair (k, M'-k) owned by one thread
+    for (int k = tid; k <= q.Mp / 2; k += kThreads) {
+        const int kp = k == 0 ? 0 : q.Mp - k;
+        const float2 z0 = buf[k], z1 = buf[kp];
+        const float4 o0 = q.AB[k], o1 = q.AB[kp];
+        const float2 q0 = cadd(cmul(make_float2(o0.x, o0.y), z0), cmul(make_float2(o0.z, o0.w), cconj(z1)));
+        const float2 q1 = cadd(cmul(make_float2(o1.x, o1.y), z1), cmul(make_float2(o1.z, o1.w), cconj(z0)));
+        buf[k] = q0;
+        if (kp != k) buf[kp] = q1;
+    }
+    __syncthreads();
+    fft<1>(sh, q, tid);
+    if (prev) {
+        const float cf = (float)coef;
+        for (long long t = tid; t < n_out; t += kThreads) {
+            const long long m = n_in - 1 + t;
+            setr(buf, m, getr(buf, m) - cf * prev[t]);
         }
     }
     __syncthreads();
 }
 
-// Spectral operator of the series: packed output Q(k) = A Z(k) + B conj Z(M'-k)
-// for the circular convolution with the zero-padded series (natural order here).
-__device__ void embed(Ctx& c, const double* f) {
-    float2* buf = c.sh->buf;
-    for (int n = c.tid; n < c.Mp; n += kThreads) {
-        const long long m0 = 2LL * n, m1 = m0 + 1;
-        buf[n] = make_float2(m0 < c.N ? (float)f[m0] : 0.0f, m1 < c.N ? (float)f[m1] : 0.0f);
+// ---------------------------------------------------------------------------
+// classical Gram-Schmidt (Sec. 3.2.2)
+
+// h[c] = <basis_c, r> for c < ncols and h[ncols] = |r|^2, FP64 sums of exact
+// FP32 products in a fixed order; r[t] at real position pos0 + t of buf.
+SSA_INLINE void project(Lds* sh, const float* basis, long long ld, int ncols, long long n, long long pos0, int tid) {
+    const float2* buf = sh->buf;
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int G = 8;
+    for (int c0 = 0; c0 <= ncols; c0 += G) {
+        double acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = 0.0;
+        for (long long t = tid; t < n; t += kThreads) {
+            const double r = (double)getr(buf, pos0 + t);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int c = c0 + g;
+                if (c < ncols)
+                    acc[g] += (double)basis[(long long)c * ld + t] * r;
+                else if (c == ncols)
+                    acc[g] += r * r;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double v = wsum(acc[g]);
+            if (lane == 0 && c0 + g <= ncols) sh->red[wave][c0 + g] = v;
+        }
     }
     __syncthreads();
-    fft(c, -1);
-    const double invMp = 1.0 / (double)c.Mp;
-    const double M = 2.0 * c.Mp;
-    for (int k = c.tid; k < c.Mp; k += kThreads) {
-        const int kp = k == 0 ? 0 : c.Mp - k;
+    for (int c = tid; c <= ncols; c += kThreads) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += sh->red[w][c];
+        sh->h[c] = s;
+    }
+    __syncthreads();
+}
+
+// r -= basis h
+SSA_INLINE void subtract(Lds* sh, const float* basis, long long ld, int ncols, long long n, long long pos0, int tid) {
+    float2* buf = sh->buf;
+    for (long long t = tid; t < n; t += kThreads) {
+        double acc = (double)getr(buf, pos0 + t);
+        for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * sh->h[c];
+        setr(buf, pos0 + t, (float)acc);
+    }
+    __syncthreads();
+}
+
+SSA_INLINE double sum_h2(Lds* sh, int ncols, int tid) {
+    double hh = 0.0;
+    for (int c = tid; c < ncols; c += kThreads) hh += sh->h[c] * sh->h[c];
+    return block_sum(sh, hh, tid);
+}
+
+// New basis column ncols from r (in buf): one Gram-Schmidt pass with
+// |r_new|^2 = |r|^2 - |h|^2, a second pass if |r_new|^2 < |r|^2 / 2 (DGKS),
+// a seeded random direction if the vector vanishes (|r_new| <= tol * max B).
+// Returns the B entry (0 after a restart); updates the series state.
+SSA_INLINE double orthonormalize(Lds* sh, const Ser& q, float* basis, long long ld, int ncols, long long n,
+                                 long long pos0, unsigned long long ctr, int tid) {
+    float2* buf = sh->buf;
+    const double bnorm = q.state[kStBnorm];
+    project(sh, basis, ld, ncols, n, pos0, tid);
+    double coef = 0.0, scale = 0.0;
+    int event = 0;  // 1: DGKS pass, 2: restart
+    if (ncols >= n) {  // the basis already spans the space
+        for (int c = tid; c < ncols; c += kThreads) sh->h[c] = 0.0;
+        __syncthreads();
+    } else {
+        const double hh = sum_h2(sh, ncols, tid);
+        const double rr = sh->h[ncols];
+        double a2 = rr - hh;
+        const double thr = kBreakdownTol * bnorm;
+        if (a2 >= 0.5 * rr && sqrt(a2) > thr) {
+            coef = sqrt(a2);
+            scale = 1.0 / coef;
+        } else {
+            subtract(sh, basis, ld, ncols, n, pos0, tid);
+            project(sh, basis, ld, ncols, n, pos0, tid);
+            const double hh2 = sum_h2(sh, ncols, tid);
+            a2 = sh->h[ncols] - hh2;
+            if (a2 > 0.0 && sqrt(a2) > thr) {
+                coef = sqrt(a2);
+                scale = 1.0 / coef;
+                event = 1;
+            } else {
+                for (long long t = tid; t < n; t += kThreads) setr(buf, pos0 + t, gaussian(q.seed, ctr, t));
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    project(sh, basis, ld, ncols, n, pos0, tid);
+                    subtract(sh, basis, ld, ncols, n, pos0, tid);
+                }
+                project(sh, basis, ld, 0, n, pos0, tid);
+                const double r3 = sh->h[0];
+                for (int c = tid; c < ncols; c += kThreads) sh->h[c] = 0.0;
+                __syncthreads();
+                scale = r3 > 0.0 ? 1.0 / sqrt(r3) : 0.0;
+                event = 2;
+            }
+        }
+    }
+    float* out = basis + (long long)ncols * ld;
+    for (long long t = tid; t < n; t += kThreads) {
+        double acc = (double)getr(buf, pos0 + t);
+        for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * sh->h[c];
+        out[t] = (float)(acc * scale);
+    }
+    if (tid == 0) {
+        if (coef > bnorm) q.state[kStBnorm] = coef;
+        if (event == 1) q.state[kStDgks] += 1.0;
+        if (event == 2) q.state[kStRestarts] += 1.0;
+    }
+    __syncthreads();
+    return coef;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+// Spectral operator of each series (Algorithm 2, steps 1-2; packed form
+// Q(k) = A Z(k) + B conj Z(M'-k), the 1/M' of the inverse folded in), the
+// twiddle tables, the cleared state, and u_1 = p_0 / |p_0| for a seeded
+// Gaussian p_0 (Algorithm 1, first line).
+__global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
+    extern __shared__ char lds[];
+    Lds* sh = reinterpret_cast<Lds*>(lds);
+    const int tid = threadIdx.x, s = blockIdx.x;
+    const Ser q = load_series(a, s);
+    const BSeries& b = a.tab[s];
+    // twiddles W(t) = e^{-2 pi i t / M'}: lo[t] = W(t), hi[t] = W(t << shift)
+    const int S = 1 << q.tw_shift;
+    for (int t = tid; t < kTwTab; t += kThreads) {
+        double sn, cs;
+        float2 lo = make_float2(1.0f, 0.0f), hi = make_float2(1.0f, 0.0f);
+        if (t < S) {
+            sincospi(-2.0 * (double)t / (double)q.Mp, &sn, &cs);
+            lo = make_float2((float)cs, (float)sn);
+        }
+        if ((long long)t * S < q.Mp) {
+            sincospi(-2.0 * (double)((long long)t * S) / (double)q.Mp, &sn, &cs);
+            hi = make_float2((float)cs, (float)sn);
+        }
+        q.tw[t] = hi;
+        q.tw[kTwTab + t] = lo;
+        sh->tw_hi[t] = hi;
+        sh->tw_lo[t] = lo;
+    }
+    for (int i = tid; i < kDmax + 3; i += kThreads) {
+        if (i <= q.dcap + 2) {
+            q.alpha[i] = 0.0;
+            q.beta[i] = 0.0;
+        }
+    }
+    for (int i = tid; i < kStDoubles; i += kThreads) q.state[i] = 0.0;
+    const double* f = a.series + b.f_off;
+    float2* buf = sh->buf;
+    for (int n = tid; n < q.Mp; n += kThreads) {
+        const long long m0 = 2LL * n, m1 = m0 + 1;
+        buf[n] = make_float2(m0 < q.N ? (float)f[m0] : 0.0f, m1 < q.N ? (float)f[m1] : 0.0f);
+    }
+    __syncthreads();
+    fft<-1>(sh, q, tid);
+    const double invMp = 1.0 / (double)q.Mp;
+    const double M = 2.0 * q.Mp;
+    for (int k = tid; k < q.Mp; k += kThreads) {
+        const int kp = k == 0 ? 0 : q.Mp - k;
         const float2 z = buf[k], zp = buf[kp];
         const double er = 0.5 * ((double)z.x + (double)zp.x), ei = 0.5 * ((double)z.y - (double)zp.y);
         const double orr = 0.5 * ((double)z.y + (double)zp.y), oi = -0.5 * ((double)z.x - (double)zp.x);
@@ -193,264 +411,218 @@ __device__ void embed(Ctx& c, const double* f) {
         const double wor = cs * orr + sn * oi, woi = cs * oi - sn * orr;
         const double ar = (er - sn * wor) * invMp, ai = (ei - sn * woi) * invMp;
         const double br = -cs * woi * invMp, bi = cs * wor * invMp;
-        c.AB[k] = make_float4((float)ar, (float)ai, (float)br, (float)bi);
+        q.AB[k] = make_float4((float)ar, (float)ai, (float)br, (float)bi);
     }
     __syncthreads();
+    // start vector
+    double ss = 0.0;
+    for (long long t = tid; t < q.Li; t += kThreads) {
+        const float g = gaussian(q.seed, 0, t);
+        q.U[t] = g;
+        ss += (double)g * (double)g;
+    }
+    ss = block_sum(sh, ss, tid);
+    const double nrm = sqrt(ss);
+    const float sc = (float)(1.0 / nrm);
+    for (long long t = tid; t < q.Li; t += kThreads) q.U[t] *= sc;
+    if (tid == 0) {
+        q.beta[1] = nrm;
+        q.state[kStBnorm] = nrm;
+    }
 }
 
-// r = X x or X^T x as a convolution (x: n_in entries in global memory), minus
-// coef * prev; r stays in buf, r[t] at real position n_in - 1 + t.
-__device__ void convolve(Ctx& c, const float* x, long long n_in, long long n_out, const float* prev, double coef) {
-    float2* buf = c.sh->buf;
-    for (int n = c.tid; n < c.Mp; n += kThreads) {
-        const long long m0 = 2LL * n, m1 = m0 + 1;
-        buf[n] = make_float2(m0 < n_in ? x[n_in - 1 - m0] : 0.0f, m1 < n_in ? x[n_in - 1 - m1] : 0.0f);
-    }
-    __syncthreads();
-    fft(c, -1);
-    for (int k = c.tid; k <= c.Mp / 2; k += kThreads) {
-        const int kp = k == 0 ? 0 : c.Mp - k;
-        const float2 z0 = buf[k], z1 = buf[kp];
-        const float4 o0 = c.AB[k], o1 = c.AB[kp];
-        const float2 q0 = cadd(cmul(make_float2(o0.x, o0.y), z0), cmul(make_float2(o0.z, o0.w), cconj(z1)));
-        const float2 q1 = cadd(cmul(make_float2(o1.x, o1.y), z1), cmul(make_float2(o1.z, o1.w), cconj(z0)));
-        buf[k] = q0;
-        if (kp != k) buf[kp] = q1;
-    }
-    __syncthreads();
-    fft(c, 1);
-    if (prev) {
-        const float cf = (float)coef;
-        for (long long t = c.tid; t < n_out; t += kThreads) {
-            const long long m = n_in - 1 + t;
-            setr(buf, m, getr(buf, m) - cf * prev[t]);
-        }
-    }
-    __syncthreads();
-}
-
-// h[cc] = <basis_cc, r> for cc < ncols and h[ncols] = |r|^2, FP64 (exact
-// FP32 x FP32 products), fixed reduction order.  r[t] = buf real position pos0 + t.
-__device__ void project(Ctx& c, const float* basis, int ncols, long long n, long long pos0) {
-    const float2* buf = c.sh->buf;
-    const int lane = c.tid & 63, wave = c.tid >> 6;
-    constexpr int G = 8;
-    for (int c0 = 0; c0 <= ncols; c0 += G) {
-        double acc[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = 0.0;
-        for (long long t = c.tid; t < n; t += kThreads) {
-            const double r = (double)getr(buf, pos0 + t);
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int cc = c0 + g;
-                if (cc < ncols)
-                    acc[g] += (double)basis[(long long)cc * c.ld + t] * r;
-                else if (cc == ncols)
-                    acc[g] += r * r;
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const double v = wsum(acc[g]);
-            if (lane == 0 && c0 + g <= ncols) c.sh->red[wave][c0 + g] = v;
-        }
-    }
-    __syncthreads();
-    for (int cc = c.tid; cc <= ncols; cc += kThreads) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) s += c.sh->red[w][cc];
-        c.sh->h[cc] = s;
-    }
-    __syncthreads();
-}
-
-// r -= basis h (in buf)
-__device__ void subtract(Ctx& c, const float* basis, int ncols, long long n, long long pos0) {
-    float2* buf = c.sh->buf;
-    for (long long t = c.tid; t < n; t += kThreads) {
-        double acc = (double)getr(buf, pos0 + t);
-        for (int cc = 0; cc < ncols; ++cc) acc -= (double)basis[(long long)cc * c.ld + t] * c.sh->h[cc];
-        setr(buf, pos0 + t, (float)acc);
-    }
-    __syncthreads();
-}
-
-// Coefficients and normalization of the new basis vector (r in buf); returns
-// the B entry.  Same rules as the single-series path: one classical
-// Gram-Schmidt pass with |r_new|^2 = |r|^2 - |h|^2, a second pass by the DGKS
-// criterion, and a seeded random restart on breakdown.
-__device__ double orthonormalize(Ctx& c, float* basis, int ncols, long long n, long long pos0,
-                                 unsigned long long ctr, double* bnorm, int* restarts, int* dgks) {
-    float2* buf = c.sh->buf;
-    project(c, basis, ncols, n, pos0);
-    double coef = 0.0, scale = 0.0;
-    if (ncols >= n) {  // the basis already spans the space
-        for (int cc = c.tid; cc < ncols; cc += kThreads) c.sh->h[cc] = 0.0;
-        __syncthreads();
+// One half of Lanczos step j for every unfinished series:
+//   side 0: r = X^T u_j - beta_j v_{j-1}, v_j = orthonormalized r, alpha_j;
+//   side 1: p = X v_j - alpha_j u_j,      u_{j+1} = orthonormalized p, beta_{j+1}.
+__global__ __launch_bounds__(kThreads) void kb_half(BatchArgs a, int j, int side) {
+    extern __shared__ char lds[];
+    Lds* sh = reinterpret_cast<Lds*>(lds);
+    const int tid = threadIdx.x, s = blockIdx.x;
+    const Ser q = load_series(a, s);
+    if (q.state[kStDone] != 0.0) return;
+    if (j - 1 > q.dcap) return;
+    load_twiddles(sh, q, tid);
+    if (side == 0) {
+        convolve(sh, q, q.U + (long long)(j - 1) * q.ldu, q.Li, q.Ki,
+                 j >= 2 ? q.V + (long long)(j - 2) * q.ldv : nullptr, q.beta[j], tid);
+        const double aj = orthonormalize(sh, q, q.V, q.ldv, j - 1, q.Ki, q.Li - 1, 2ULL * j, tid);
+        if (tid == 0) q.alpha[j] = aj;
     } else {
-        double hh = 0.0;
-        for (int cc = c.tid; cc < ncols; cc += kThreads) hh += c.sh->h[cc] * c.sh->h[cc];
-        hh = block_sum(c, hh);
-        const double rr = c.sh->h[ncols];
-        double a2 = rr - hh;
-        const double thr = kBreakdownTol * *bnorm;
-        if (a2 >= 0.5 * rr && sqrt(a2) > thr) {
-            coef = sqrt(a2);
-            scale = 1.0 / coef;
-        } else {
-            subtract(c, basis, ncols, n, pos0);
-            project(c, basis, ncols, n, pos0);
-            double hh2 = 0.0;
-            for (int cc = c.tid; cc < ncols; cc += kThreads) hh2 += c.sh->h[cc] * c.sh->h[cc];
-            hh2 = block_sum(c, hh2);
-            a2 = c.sh->h[ncols] - hh2;
-            if (a2 > 0.0 && sqrt(a2) > thr) {
-                coef = sqrt(a2);
-                scale = 1.0 / coef;
-                ++*dgks;
-            } else {
-                for (long long t = c.tid; t < n; t += kThreads) setr(buf, pos0 + t, gaussian(c.seed, ctr, t));
-                __syncthreads();
-                for (int pass = 0; pass < 2; ++pass) {
-                    project(c, basis, ncols, n, pos0);
-                    subtract(c, basis, ncols, n, pos0);
-                }
-                project(c, basis, 0, n, pos0);
-                const double r3 = c.sh->h[0];
-                for (int cc = c.tid; cc < ncols; cc += kThreads) c.sh->h[cc] = 0.0;
-                __syncthreads();
-                scale = r3 > 0.0 ? 1.0 / sqrt(r3) : 0.0;
-                ++*restarts;
-            }
-        }
+        convolve(sh, q, q.V + (long long)(j - 1) * q.ldv, q.Ki, q.Li, q.U + (long long)(j - 1) * q.ldu,
+                 q.alpha[j], tid);
+        const double bj = orthonormalize(sh, q, q.U, q.ldu, j, q.Li, q.Ki - 1, 2ULL * j + 1, tid);
+        if (tid == 0) q.beta[j + 1] = bj;
     }
-    // v = (r - basis h) * scale -> basis column ncols
-    float* out = basis + (long long)ncols * c.ld;
-    for (long long t = c.tid; t < n; t += kThreads) {
-        double acc = (double)getr(buf, pos0 + t);
-        for (int cc = 0; cc < ncols; ++cc) acc -= (double)basis[(long long)cc * c.ld + t] * c.sh->h[cc];
-        out[t] = (float)(acc * scale);
-    }
-    if (coef > *bnorm) *bnorm = coef;
-    __syncthreads();
-    return coef;
 }
 
-// Sturm count of T - x I: number of eigenvalues < x
-__device__ int sturm_count(const double* D, const double* E2, int n, double x, double pivmin) {
-    double q = D[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = q < 0.0 ? 1 : 0;
+// The k largest eigenvalues of T_n by multisection (sh->lam); D, E2 in sh->tri,
+// the pivot floor in sh->dmisc[0].
+SSA_INLINE int sturm_count(const double* D, const double* E2, int n, double x, double pivmin) {
+    double d = D[0] - x;
+    if (fabs(d) < pivmin) d = -pivmin;
+    int cnt = d < 0.0 ? 1 : 0;
     for (int i = 1; i < n; ++i) {
-        q = D[i] - x - E2[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0 ? 1 : 0;
+        d = D[i] - x - E2[i - 1] / d;
+        if (fabs(d) < pivmin) d = -pivmin;
+        cnt += d < 0.0 ? 1 : 0;
     }
     return cnt;
 }
 
-// The k largest eigenvalues of T_n (= omega^2) by multisection, and the squared
-// last components of their eigenvectors; results in sh->lam[i], sh->qlast[i].
-__device__ void tridiag_top(Ctx& c, int n, int k) {
-    Shared* sh = c.sh;
+SSA_INLINE void tridiag_top(Lds* sh, int n, int k, int tid) {
+    const double* al = sh->ab;
+    const double* be = sh->ab + (kDmax + 3);
     double* D = sh->tri;
     double* E2 = sh->tri + kDmax + 2;
-    for (int i = c.tid; i < n; i += kThreads) {
-        const double a = sh->alpha[i + 1], b = sh->beta[i + 2];
-        D[i] = a * a + b * b;
+    for (int i = tid; i < n; i += kThreads) {
+        const double x = al[i + 1], y = be[i + 2];
+        D[i] = x * x + y * y;
         if (i + 1 < n) {
-            const double e = sh->alpha[i + 2] * sh->beta[i + 2];
+            const double e = al[i + 2] * be[i + 2];
             E2[i] = e * e;
         }
     }
     __syncthreads();
     double g = 0.0, e2max = 0.0;
-    for (int i = c.tid; i < n; i += kThreads) {
+    for (int i = tid; i < n; i += kThreads) {
         const double el = i > 0 ? sqrt(E2[i - 1]) : 0.0, er = i + 1 < n ? sqrt(E2[i]) : 0.0;
         g = fmax(g, D[i] + el + er);
         if (i + 1 < n) e2max = fmax(e2max, E2[i]);
     }
-    const double gmax = block_max(c, g);
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, block_max(c, e2max));
+    const double gmax = block_max(sh, g, tid);
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, block_max(sh, e2max, tid));
     const int P = kThreads / k;  // shifts per eigenvalue per round
-    for (int i = c.tid; i < k; i += kThreads) {
+    for (int i = tid; i < k; i += kThreads) {
         sh->lo[i] = 0.0;
         sh->hi[i] = gmax * (1.0 + 1e-12) + 1e-300;
     }
     __syncthreads();
-    const int ei = c.tid / P, p = c.tid % P;
+    const int ei = tid / P, p = tid % P;
     for (int round = 0; round < 14; ++round) {
         if (ei < k) {
-            const double a = sh->lo[ei], b = sh->hi[ei];
-            const double x = a + (b - a) * (double)(p + 1) / (double)(P + 1);
-            sh->cnt[c.tid] = sturm_count(D, E2, n, x, pivmin);
-            sh->xs[c.tid] = x;
+            const double lo = sh->lo[ei], hi = sh->hi[ei];
+            const double x = lo + (hi - lo) * (double)(p + 1) / (double)(P + 1);
+            sh->cnt[tid] = sturm_count(D, E2, n, x, pivmin);
+            sh->xs[tid] = x;
         }
         __syncthreads();
         if (ei < k && p == 0) {
             const int m = n - 1 - ei;  // the eigenvalue is the m-th smallest
-            double a = sh->lo[ei], b = sh->hi[ei];
-            for (int q = 0; q < P; ++q) {
-                const int idx = ei * P + q;
+            double lo = sh->lo[ei], hi = sh->hi[ei];
+            for (int t = 0; t < P; ++t) {
+                const int idx = ei * P + t;
                 if (sh->cnt[idx] <= m) {
-                    a = sh->xs[idx];
+                    lo = sh->xs[idx];
                 } else {
-                    b = sh->xs[idx];
+                    hi = sh->xs[idx];
                     break;
                 }
             }
-            sh->lo[ei] = a;
-            sh->hi[ei] = b;
+            sh->lo[ei] = lo;
+            sh->hi[ei] = hi;
         }
         __syncthreads();
     }
-    for (int i = c.tid; i < k; i += kThreads) {
-        const double lam = 0.5 * (sh->lo[i] + sh->hi[i]);
-        sh->lam[i] = lam;
-        // q[n-1]^2 = -1 / d'_{n-1}(lambda)
-        double d = D[0] - lam, dp = -1.0;
-        if (fabs(d) < pivmin) d = -pivmin;
-        for (int j = 1; j < n; ++j) {
-            const double t = E2[j - 1] / d;
-            dp = -1.0 + t * dp / d;
-            d = D[j] - lam - t;
-            if (fabs(d) < pivmin) d = -pivmin;
-        }
-        sh->qlast[i] = dp < 0.0 ? fmin(1.0, -1.0 / dp) : 1.0;
-    }
+    for (int i = tid; i < k; i += kThreads) sh->lam[i] = 0.5 * (sh->lo[i] + sh->hi[i]);
+    if (tid == 0) sh->dmisc[0] = pivmin;
     __syncthreads();
 }
 
-// Stopping test on B_jj (alpha[1..jj+1], beta[2..jj+1] in LDS); thread 0 decides.
-__device__ bool stopping_test(Ctx& c, int jj, int k, double tol, bool& have_prev, bool exhausted) {
-    Shared* sh = c.sh;
-    tridiag_top(c, jj, k);
-    if (c.tid == 0) {
-        const double w0 = sqrt(fmax(sh->lam[0], 0.0));
-        bool ok = have_prev;
-        for (int i = 0; i < k; ++i) {
-            const double w = sqrt(fmax(sh->lam[i], 0.0));
-            const double res = w > 0.0 ? sh->alpha[jj + 1] * sh->beta[jj + 1] * sqrt(sh->qlast[i]) / w : 0.0;
-            const double sc = fmax(w, kResidFloor * w0);
-            if (res > tol * sc) ok = false;
-            if (fabs(w - sh->wprev[i]) > 10.0 * tol * sc) ok = false;
-            sh->wprev[i] = w;
-            sh->resid[i] = res;
+// Squared last component of the unit eigenvector of T_n at eigenvalue lam, from
+// the twisted factorization of T - lam I (Dhillon and Parlett): backward pivots
+// dm, forward pivots dp, twist index r minimizing |dp_r + dm_r - (D_r - lam)|,
+// then z_r = 1 and z spreads both ways by products of pivot ratios, which keeps
+// the tiny tail components of converged Ritz vectors to relative accuracy.
+// dm and dp (n doubles each) live in the caller's scratch.
+SSA_INLINE double twisted_qlast(const double* D, const double* E2, int n, double lam, double pivmin, double* dm,
+                                double* dp) {
+    if (n == 1) return 1.0;
+    dm[n - 1] = D[n - 1] - lam;
+    for (int c = n - 2; c >= 0; --c) {
+        const double x = fabs(dm[c + 1]) >= pivmin ? dm[c + 1] : -pivmin;
+        dm[c] = D[c] - lam - E2[c] / x;
+    }
+    double best = 0.0;
+    int r = 0;
+    for (int c = 0; c < n; ++c) {
+        if (c == 0) {
+            dp[0] = D[0] - lam;
+        } else {
+            const double x = fabs(dp[c - 1]) >= pivmin ? dp[c - 1] : -pivmin;
+            dp[c] = D[c] - lam - E2[c - 1] / x;
         }
-        if (exhausted) ok = true;
-        sh->imisc[1] = ok ? 1 : 0;
+        const double g = fabs(dp[c] + dm[c] - (D[c] - lam));
+        if (c == 0 || g < best) {
+            best = g;
+            r = c;
+        }
+    }
+    double z = 1.0, zz = 1.0;
+    for (int c = r - 1; c >= 0; --c) {
+        const double x = fabs(dp[c]) >= pivmin ? dp[c] : -pivmin;
+        z = -(sqrt(E2[c]) / x) * z;
+        zz += z * z;
+    }
+    z = 1.0;
+    for (int c = r + 1; c < n; ++c) {
+        const double x = fabs(dm[c]) >= pivmin ? dm[c] : -pivmin;
+        z = -(sqrt(E2[c - 1]) / x) * z;
+        zz += z * z;
+    }
+    const double zl = r == n - 1 ? 1.0 : z;
+    return zl * zl / zz;
+}
+
+// Stopping test of step j on B_{j-1} for the series whose check point it is:
+// every residual bound <= tol * max(omega_i, 1e-5 omega_1) and the k Ritz
+// values within 10 tol (relative) of the previous check's; or the Krylov cap.
+__global__ __launch_bounds__(kThreads) void kb_check(BatchArgs a, int j) {
+    extern __shared__ char lds[];
+    Lds* sh = reinterpret_cast<Lds*>(lds);
+    const int tid = threadIdx.x, s = blockIdx.x;
+    const Ser q = load_series(a, s);
+    if (q.state[kStDone] != 0.0) return;
+    const int jj = j - 1, k = q.k;
+    if (!(jj >= k && (jj % a.check_every == 0 || jj >= q.dcap))) return;
+    for (int i = tid; i <= jj + 1; i += kThreads) {
+        sh->ab[i] = q.alpha[i];
+        sh->ab[kDmax + 3 + i] = q.beta[i];
     }
     __syncthreads();
-    have_prev = true;
-    const bool ok = sh->imisc[1] != 0;
+    tridiag_top(sh, jj, k, tid);
+    if (tid < k) {
+        double* dm = q.scr + (long long)tid * 2 * (q.dcap + 2);
+        sh->qlast[tid] = twisted_qlast(sh->tri, sh->tri + kDmax + 2, jj, sh->lam[tid], sh->dmisc[0], dm,
+                                       dm + (q.dcap + 2));
+    }
     __syncthreads();
-    return ok;
+    if (tid == 0) {
+        const double w0 = sqrt(fmax(sh->lam[0], 0.0));
+        bool ok = q.state[kStHavePrev] != 0.0;
+        const double ab = sh->ab[jj + 1] * sh->ab[kDmax + 3 + jj + 1];
+        for (int i = 0; i < k; ++i) {
+            const double w = sqrt(fmax(sh->lam[i], 0.0));
+            const double res = w > 0.0 ? ab * sqrt(sh->qlast[i]) / w : 0.0;
+            const double sc = fmax(w, kResidFloor * w0);
+            if (res > a.tol * sc) ok = false;
+            if (fabs(w - q.state[kStWprev + i]) > 10.0 * a.tol * sc) ok = false;
+            q.state[kStWprev + i] = w;
+            q.state[kStResid + i] = res;
+            q.state[kStLam + i] = sh->lam[i];
+        }
+        q.state[kStHavePrev] = 1.0;
+        const bool exhausted = jj >= q.Li;  // the Krylov space is exhausted: B is exact
+        if (ok || exhausted || jj >= q.dcap) {
+            q.state[kStDone] = 1.0;
+            q.state[kStD] = (double)jj;
+            q.state[kStConv] = (ok || exhausted) ? 1.0 : 0.0;
+            atomicAdd(a.ndone, 1u);
+        }
+    }
 }
 
 // Solve (T - lam I) x = x in place (partial pivoting; tiny pivots replaced).
-__device__ void shifted_solve(const double* D, const double* E, int n, double lam, double tnorm, double* x,
+SSA_INLINE void shifted_solve(const double* D, const double* E, int n, double lam, double tnorm, double* x,
                               double* a, double* b, double* cc, double* u2) {
     for (int i = 0; i < n; ++i) a[i] = D[i] - lam;
     for (int i = 0; i + 1 < n; ++i) {
@@ -486,32 +658,75 @@ __device__ void shifted_solve(const double* D, const double* E, int n, double la
     for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - b[i] * x[i + 1] - u2[i] * x[i + 2]) / a[i];
 }
 
-// Ritz coefficient matrices of B_d: Q (d x k) and P ((d+1) x k), row-major in
-// global scratch, from the eigenvalues left in sh->lam by the last test.
-__device__ void ritz_coefficients(Ctx& c, int d, int k) {
-    Shared* sh = c.sh;
+// out[i*ldo + t] = sum_{c < ncols} basis[c][t] coef[c*k + i], i < k
+SSA_INLINE void ritz_vectors(Lds* sh, const float* basis, long long ld, int ncols, const double* coef, int k,
+                             float* out, long long ldo, long long n, int tid) {
+    constexpr int T = 8;
+    double* cs = &sh->red[0][0];  // ncols x T coefficients
+    for (int i0 = 0; i0 < k; i0 += T) {
+        for (int idx = tid; idx < ncols * T; idx += kThreads) {
+            const int c = idx / T, i = idx % T;
+            cs[idx] = i0 + i < k ? coef[(long long)c * k + i0 + i] : 0.0;
+        }
+        __syncthreads();
+        for (long long t = tid; t < n; t += kThreads) {
+            double acc[T];
+#pragma unroll
+            for (int i = 0; i < T; ++i) acc[i] = 0.0;
+            for (int c = 0; c < ncols; ++c) {
+                const double x = basis[(long long)c * ld + t];
+#pragma unroll
+                for (int i = 0; i < T; ++i) acc[i] += x * cs[c * T + i];
+            }
+#pragma unroll
+            for (int i = 0; i < T; ++i)
+                if (i0 + i < k) out[(long long)(i0 + i) * ldo + t] = (float)acc[i];
+        }
+        __syncthreads();
+    }
+}
+
+// Ritz triples of B_d: Q (d x k) by inverse iteration on T at the eigenvalues
+// of the last check plus modified Gram-Schmidt, P = B Q / |B Q|; then sigma,
+// U_{d+1} P and V_d Q in the caller's layout, and the per-series report.
+__global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
+    extern __shared__ char lds[];
+    Lds* sh = reinterpret_cast<Lds*>(lds);
+    const int tid = threadIdx.x, s = blockIdx.x;
+    const Ser q = load_series(a, s);
+    const BSeries& b = a.tab[s];
+    const int k = q.k;
+    const int d = (int)q.state[kStD];
+    for (int i = tid; i <= d + 1; i += kThreads) {
+        sh->ab[i] = q.alpha[i];
+        sh->ab[kDmax + 3 + i] = q.beta[i];
+    }
+    for (int i = tid; i < k; i += kThreads) sh->lam[i] = q.state[kStLam + i];
+    __syncthreads();
+    const double* al = sh->ab;
+    const double* be = sh->ab + (kDmax + 3);
     double* D = sh->tri;
-    double* E = sh->tri + kDmax + 2;  // off-diagonal (not squared) for the solves
-    for (int i = c.tid; i < d; i += kThreads) {
-        const double a = sh->alpha[i + 1], b = sh->beta[i + 2];
-        D[i] = a * a + b * b;
-        if (i + 1 < d) E[i] = sh->alpha[i + 2] * sh->beta[i + 2];
+    double* E = sh->tri + kDmax + 2;  // off-diagonal (not squared)
+    for (int i = tid; i < d; i += kThreads) {
+        const double x = al[i + 1], y = be[i + 2];
+        D[i] = x * x + y * y;
+        if (i + 1 < d) E[i] = al[i + 2] * be[i + 2];
     }
     __syncthreads();
     double g = 0.0;
-    for (int i = c.tid; i < d; i += kThreads) g = fmax(g, fabs(D[i]) + 2.0 * (i + 1 < d ? fabs(E[i]) : 0.0));
-    const double tnorm = block_max(c, g);
-    const long long stride = kDmax + 2;
-    if (c.tid < k && c.tid < d) {
-        const int i = c.tid;
-        double* x = c.scratch + (long long)i * 6 * stride;
-        double* a = x + stride;
-        double* b = a + stride;
-        double* cc = b + stride;
-        double* u2 = cc + stride;
+    for (int i = tid; i < d; i += kThreads) g = fmax(g, fabs(D[i]) + 2.0 * (i + 1 < d ? fabs(E[i]) : 0.0));
+    const double tnorm = block_max(sh, g, tid);
+    const long long stride = q.dcap + 2;
+    if (tid < k && tid < d) {
+        const int i = tid;
+        double* x = q.scr + (long long)i * 5 * stride;
+        double* wa = x + stride;
+        double* wb = wa + stride;
+        double* wc = wb + stride;
+        double* wu = wc + stride;
         for (int t = 0; t < d; ++t) x[t] = 1.0 + 0.5 * sin(0.7 * (t + 1) + 1.3 * (i + 1));
         for (int it = 0; it < 4; ++it) {
-            shifted_solve(D, E, d, sh->lam[i], tnorm, x, a, b, cc, u2);
+            shifted_solve(D, E, d, sh->lam[i], tnorm, x, wa, wb, wc, wu);
             double nrm = 0.0;
             for (int t = 0; t < d; ++t) nrm += x[t] * x[t];
             nrm = sqrt(nrm);
@@ -522,276 +737,193 @@ __device__ void ritz_coefficients(Ctx& c, int d, int k) {
             for (int t = 0; t < d; ++t) x[t] /= nrm;
         }
     }
-    __threadfence_block();
     __syncthreads();
-    // modified Gram-Schmidt across the k vectors (handles equal eigenvalues)
     const int kk = k < d ? k : d;
     for (int i = 0; i < kk; ++i) {
-        double* xi = c.scratch + (long long)i * 6 * stride;
+        double* xi = q.scr + (long long)i * 5 * stride;
         for (int p = 0; p < i; ++p) {
-            const double* xp = c.scratch + (long long)p * 6 * stride;
-            double dot = 0.0;
-            for (int t = c.tid; t < d; t += kThreads) dot += xp[t] * xi[t];
-            dot = block_sum(c, dot);
-            for (int t = c.tid; t < d; t += kThreads) xi[t] -= dot * xp[t];
-            __threadfence_block();
+            const double* xp = q.scr + (long long)p * 5 * stride;
+            double dt = 0.0;
+            for (int t = tid; t < d; t += kThreads) dt += xp[t] * xi[t];
+            dt = block_sum(sh, dt, tid);
+            for (int t = tid; t < d; t += kThreads) xi[t] -= dt * xp[t];
             __syncthreads();
         }
         double nrm = 0.0;
-        for (int t = c.tid; t < d; t += kThreads) nrm += xi[t] * xi[t];
-        nrm = sqrt(block_sum(c, nrm));
-        for (int t = c.tid; t < d; t += kThreads) {
+        for (int t = tid; t < d; t += kThreads) nrm += xi[t] * xi[t];
+        nrm = sqrt(block_sum(sh, nrm, tid));
+        for (int t = tid; t < d; t += kThreads) {
             xi[t] = nrm > 0.0 ? xi[t] / nrm : 0.0;
-            c.Q[(long long)t * k + i] = xi[t];
+            q.Q[(long long)t * k + i] = xi[t];
         }
-        __threadfence_block();
         __syncthreads();
-        // p = B q / |B q|
         double pn = 0.0;
-        for (int r = c.tid; r <= d; r += kThreads) {
+        for (int r = tid; r <= d; r += kThreads) {
             double v = 0.0;
-            if (r < d) v += sh->alpha[r + 1] * xi[r];
-            if (r >= 1) v += sh->beta[r + 1] * xi[r - 1];
-            c.P[(long long)r * k + i] = v;
+            if (r < d) v += al[r + 1] * xi[r];
+            if (r >= 1) v += be[r + 1] * xi[r - 1];
+            q.P[(long long)r * k + i] = v;
             pn += v * v;
         }
-        pn = sqrt(block_sum(c, pn));
-        for (int r = c.tid; r <= d; r += kThreads) c.P[(long long)r * k + i] = pn > 0.0 ? c.P[(long long)r * k + i] / pn : 0.0;
-        __threadfence_block();
+        pn = sqrt(block_sum(sh, pn, tid));
+        for (int r = tid; r <= d; r += kThreads) q.P[(long long)r * k + i] = pn > 0.0 ? q.P[(long long)r * k + i] / pn : 0.0;
         __syncthreads();
     }
     for (int i = kk; i < k; ++i) {
-        for (int t = c.tid; t < d; t += kThreads) c.Q[(long long)t * k + i] = 0.0;
-        for (int r = c.tid; r <= d; r += kThreads) c.P[(long long)r * k + i] = 0.0;
-    }
-    __threadfence_block();
-    __syncthreads();
-}
-
-// out[i*ldo + t] = sum_{cc < ncols} basis[cc][t] coef[cc*k + i], i < k
-__device__ void ritz_vectors(Ctx& c, const float* basis, int ncols, const double* coef, int k, float* out,
-                             long long ldo, long long n) {
-    constexpr int T = 8;
-    double* cs = &c.sh->red[0][0];  // ncols x T coefficients
-    for (int i0 = 0; i0 < k; i0 += T) {
-        for (int idx = c.tid; idx < ncols * T; idx += kThreads) {
-            const int cc = idx / T, i = idx % T;
-            cs[idx] = i0 + i < k ? coef[(long long)cc * k + i0 + i] : 0.0;
-        }
-        __syncthreads();
-        for (long long t = c.tid; t < n; t += kThreads) {
-            double acc[T];
-#pragma unroll
-            for (int i = 0; i < T; ++i) acc[i] = 0.0;
-            for (int cc = 0; cc < ncols; ++cc) {
-                const double x = basis[(long long)cc * c.ld + t];
-#pragma unroll
-                for (int i = 0; i < T; ++i) acc[i] += x * cs[cc * T + i];
-            }
-#pragma unroll
-            for (int i = 0; i < T; ++i)
-                if (i0 + i < k) out[(long long)(i0 + i) * ldo + t] = (float)acc[i];
-        }
-        __syncthreads();
-    }
-}
-
-// Elementary series of one triple (Algorithm 4): g = sigma (u * v) / cnt.
-// The packed spectrum of u waits in the slot's HBM scratch while v is
-// transformed; each bin pair (k, M'-k) belongs to one thread, which reads both
-// spectra there and writes the packed product back in place.
-__device__ void hankelize(Ctx& c, double sigma, const float* u, long long lu, const float* v, long long lv,
-                          float* out) {
-    Shared* sh = c.sh;
-    float2* buf = sh->buf;
-    float2* zu = reinterpret_cast<float2*>(c.scratch);
-    const long long N = c.N;
-    const int Mp = c.Mp;
-    const double M = 2.0 * Mp;
-    for (int n = c.tid; n < Mp; n += kThreads) {
-        const long long m0 = 2LL * n, m1 = m0 + 1;
-        buf[n] = make_float2(m0 < lu ? u[m0] : 0.0f, m1 < lu ? u[m1] : 0.0f);
+        for (int t = tid; t < d; t += kThreads) q.Q[(long long)t * k + i] = 0.0;
+        for (int r = tid; r <= d; r += kThreads) q.P[(long long)r * k + i] = 0.0;
     }
     __syncthreads();
-    fft(c, -1);
-    for (int n = c.tid; n < Mp; n += kThreads) zu[n] = buf[n];
-    __syncthreads();
-    for (int n = c.tid; n < Mp; n += kThreads) {
-        const long long m0 = 2LL * n, m1 = m0 + 1;
-        buf[n] = make_float2(m0 < lv ? v[m0] : 0.0f, m1 < lv ? v[m1] : 0.0f);
-    }
-    __syncthreads();
-    fft(c, -1);
-    const double sc = sigma / (double)Mp;
-    for (int k = c.tid; k <= Mp / 2; k += kThreads) {
-        const int kp = k == 0 ? 0 : Mp - k;
-        const float2 zu0 = zu[k], zu1 = zu[kp];
-        const float2 zv0 = buf[k], zv1 = buf[kp];
-        for (int side = 0; side < 2; ++side) {
-            if (side == 1 && kp == k) break;
-            const float2 a = side == 0 ? zu0 : zu1, ap = side == 0 ? zu1 : zu0;
-            const float2 b = side == 0 ? zv0 : zv1, bp = side == 0 ? zv1 : zv0;
-            const int kk = side == 0 ? k : kp;
-            double sn, cs;
-            sincospi(2.0 * (double)kk / M, &sn, &cs);
-            const double wr = cs, wi = -sn;
-            // E/O split, then the full spectra at kk and kk + M'
-            const double uer = 0.5 * ((double)a.x + (double)ap.x), uei = 0.5 * ((double)a.y - (double)ap.y);
-            const double uor = 0.5 * ((double)a.y + (double)ap.y), uoi = -0.5 * ((double)a.x - (double)ap.x);
-            const double ver = 0.5 * ((double)b.x + (double)bp.x), vei = 0.5 * ((double)b.y - (double)bp.y);
-            const double vor = 0.5 * ((double)b.y + (double)bp.y), voi = -0.5 * ((double)b.x - (double)bp.x);
-            const double uwr = wr * uor - wi * uoi, uwi = wr * uoi + wi * uor;
-            const double vwr = wr * vor - wi * voi, vwi = wr * voi + wi * vor;
-            const double uar = uer + uwr, uai = uei + uwi, ubr = uer - uwr, ubi = uei - uwi;
-            const double var_ = ver + vwr, vai = vei + vwi, vbr = ver - vwr, vbi = vei - vwi;
-            const double gar = uar * var_ - uai * vai, gai = uar * vai + uai * var_;
-            const double gbr = ubr * vbr - ubi * vbi, gbi = ubr * vbi + ubi * vbr;
-            const double dr = gar - gbr, di = gai - gbi;
-            const double tr = dr * wr + di * wi, ti = di * wr - dr * wi;
-            const double qr = 0.5 * (gar + gbr) - 0.5 * ti, qi = 0.5 * (gai + gbi) + 0.5 * tr;
-            buf[kk] = make_float2((float)(qr * sc), (float)(qi * sc));
-        }
-    }
-    __syncthreads();
-    fft(c, 1);
-    const long long L = lu, K = lv;
-    for (long long m = c.tid; m < N; m += kThreads) {
-        long long cnt = m + 1;
-        if (L < cnt) cnt = L;
-        if (K < cnt) cnt = K;
-        if (N - m < cnt) cnt = N - m;
-        if (cnt <= kEdge) {
-            const long long a0 = m - K + 1 > 0 ? m - K + 1 : 0, a1 = m < L - 1 ? m : L - 1;
-            double s = 0.0;
-            for (long long aa = a0; aa <= a1; ++aa) s += (double)u[aa] * (double)v[m - aa];
-            out[m] = (float)(sigma * s / (double)cnt);
-        } else {
-            out[m] = getr(buf, m) / (float)cnt;
-        }
-    }
-    __syncthreads();
-}
-
-__device__ void solve_series(const BatchArgs& a, int s, Ctx& c) {
-    Shared* sh = c.sh;
-    const long long off = a.offs[s];
-    const long long N = a.offs[s + 1] - off;
-    const long long L = a.Ls[s], K = N - L + 1;
-    const int k = a.ks[s];
-    const bool transposed = L > K;
-    c.N = N;
-    c.Li = transposed ? K : L;
-    c.Ki = transposed ? L : K;
-    c.seed = a.seed ^ (0x9E3779B97F4A7C15ULL * (unsigned long long)(s + 1));
-    setup_series_fft(c);
-    embed(c, a.series + off);
-    const long long Li = c.Li, Ki = c.Ki;
-    for (int i = c.tid; i < kDmax + 3; i += kThreads) {
-        sh->alpha[i] = 0.0;
-        sh->beta[i] = 0.0;
-    }
-    for (int i = c.tid; i < kMaxK; i += kThreads) sh->wprev[i] = 0.0;
-    double bnorm = 0.0;
-    int restarts = 0, dgks = 0;
-    // start vector (Algorithm 1, first line)
-    for (long long t = c.tid; t < Li; t += kThreads) setr(sh->buf, t, gaussian(c.seed, 0, t));
-    __syncthreads();
-    {
-        double dummy = 0.0;
-        const double b1 = orthonormalize(c, c.Ub, 0, Li, 0, 1, &dummy, &restarts, &dgks);
-        if (c.tid == 0) sh->beta[1] = b1;
-    }
-    const long long r_ = Li < Ki ? Li : Ki;
-    const int d_cap = (int)(a.d_max < r_ ? a.d_max : r_);
-    bool have_prev = false;
-    int d = 0;
-    bool conv = false;
-    for (int j = 1;; ++j) {
-        __syncthreads();
-        convolve(c, c.Ub + (long long)(j - 1) * c.ld, Li, Ki, j >= 2 ? c.Vb + (long long)(j - 2) * c.ld : nullptr,
-                 sh->beta[j]);
-        const double aj = orthonormalize(c, c.Vb, j - 1, Ki, Li - 1, 2ULL * j, &bnorm, &restarts, &dgks);
-        if (c.tid == 0) sh->alpha[j] = aj;
-        __syncthreads();
-        const int jj = j - 1;
-        if (jj >= k && (jj % a.check_every == 0 || jj >= d_cap)) {
-            const bool exhausted = jj >= r_;
-            const bool ok = stopping_test(c, jj, k, a.tol, have_prev, exhausted);
-            if (ok || jj >= d_cap) {
-                d = jj;
-                conv = ok;
-                break;
-            }
-        }
-        convolve(c, c.Vb + (long long)(j - 1) * c.ld, Ki, Li, c.Ub + (long long)(j - 1) * c.ld, sh->alpha[j]);
-        const double bj = orthonormalize(c, c.Ub, j, Li, Ki - 1, 2ULL * j + 1, &bnorm, &restarts, &dgks);
-        if (c.tid == 0) sh->beta[j + 1] = bj;
-        __syncthreads();
-    }
-    // Ritz triples
-    ritz_coefficients(c, d, k);
-    float* Uo = a.U + a.uoff[s];
-    float* Vo = a.V + a.voff[s];
-    float* Ui = transposed ? Vo : Uo;  // internal U has Li entries
-    float* Vi = transposed ? Uo : Vo;
-    ritz_vectors(c, c.Ub, d + 1, c.P, k, Ui, Li, Li);
-    ritz_vectors(c, c.Vb, d, c.Q, k, Vi, Ki, Ki);
-    for (int i = c.tid; i < k; i += kThreads) a.sigma[a.soff[s] + i] = sqrt(fmax(sh->lam[i], 0.0));
-    if (c.tid == 0 && a.info) {
+    float* Uo = a.U + b.u_off;
+    float* Vo = a.V + b.v_off;
+    float* Ui = b.transposed ? Vo : Uo;  // the internal U has Li entries
+    float* Vi = b.transposed ? Uo : Vo;
+    ritz_vectors(sh, q.U, q.ldu, d + 1, q.P, k, Ui, q.Li, q.Li, tid);
+    ritz_vectors(sh, q.V, q.ldv, d, q.Q, k, Vi, q.Ki, q.Ki, tid);
+    for (int i = tid; i < k; i += kThreads) a.sigma[b.s_off + i] = sqrt(fmax(sh->lam[i], 0.0));
+    if (tid == 0 && a.info) {
         int* inf = a.info + 4LL * s;
         inf[0] = d;
-        inf[1] = conv ? 1 : 0;
-        inf[2] = restarts;
-        inf[3] = dgks;
-    }
-    __threadfence_block();
-    __syncthreads();
-    if (a.recon) {
-        for (int i = 0; i < k; ++i) {
-            const double sg = sqrt(fmax(sh->lam[i], 0.0));
-            hankelize(c, sg, Uo + (long long)i * L, L, Vo + (long long)i * K, K, a.recon + a.roff[s] + (long long)i * N);
-        }
+        inf[1] = (int)q.state[kStConv];
+        inf[2] = (int)q.state[kStRestarts];
+        inf[3] = (int)q.state[kStDgks];
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch(BatchArgs a) {
+// Elementary series of every triple (Algorithm 4): g = sigma (u * v) / cnt,
+// the linear convolution by a packed-real FFT; the spectrum of u waits in the
+// region's scratch while v is transformed.  Entries whose antidiagonal has at
+// most kEdge terms are summed directly (FP64 sums of exact FP32 products).
+__global__ __launch_bounds__(kThreads) void kb_hankel(BatchArgs a) {
     extern __shared__ char lds[];
-    Ctx c;
-    c.sh = reinterpret_cast<Shared*>(lds);
-    c.tid = threadIdx.x;
-    char* slot = a.slots + (size_t)blockIdx.x * a.slot_bytes;
-    c.ld = a.ld;
-    c.AB = reinterpret_cast<float4*>(slot + a.o_ab);
-    c.Ub = reinterpret_cast<float*>(slot + a.o_u);
-    c.Vb = reinterpret_cast<float*>(slot + a.o_v);
-    c.scratch = reinterpret_cast<double*>(slot + a.o_scratch);
-    c.P = reinterpret_cast<double*>(slot + a.o_p);
-    c.Q = reinterpret_cast<double*>(slot + a.o_q);
-    for (;;) {
-        if (c.tid == 0) c.sh->imisc[0] = (int)atomicAdd(a.queue, 1u);
+    Lds* sh = reinterpret_cast<Lds*>(lds);
+    const int tid = threadIdx.x, s = blockIdx.x;
+    const Ser q = load_series(a, s);
+    const BSeries& b = a.tab[s];
+    load_twiddles(sh, q, tid);
+    float2* buf = sh->buf;
+    float2* zu = reinterpret_cast<float2*>(q.scr);
+    const long long N = q.N, L = b.L, K = N - b.L + 1;
+    const int Mp = q.Mp;
+    const double M = 2.0 * Mp;
+    for (int i = 0; i < q.k; ++i) {
+        const double sigma = a.sigma[b.s_off + i];
+        const float* u = a.U + b.u_off + (long long)i * L;
+        const float* v = a.V + b.v_off + (long long)i * K;
+        float* out = a.recon + b.r_off + (long long)i * N;
+        for (int n = tid; n < Mp; n += kThreads) {
+            const long long m0 = 2LL * n, m1 = m0 + 1;
+            buf[n] = make_float2(m0 < L ? u[m0] : 0.0f, m1 < L ? u[m1] : 0.0f);
+        }
         __syncthreads();
-        const int s = c.sh->imisc[0];
+        fft<-1>(sh, q, tid);
+        for (int n = tid; n < Mp; n += kThreads) zu[n] = buf[n];
         __syncthreads();
-        if (s >= a.nseries) break;
-        solve_series(a, s, c);
+        for (int n = tid; n < Mp; n += kThreads) {
+            const long long m0 = 2LL * n, m1 = m0 + 1;
+            buf[n] = make_float2(m0 < K ? v[m0] : 0.0f, m1 < K ? v[m1] : 0.0f);
+        }
+        __syncthreads();
+        fft<-1>(sh, q, tid);
+        const double sc = sigma / (double)Mp;
+        for (int k = tid; k <= Mp / 2; k += kThreads) {
+            const int kp = k == 0 ? 0 : Mp - k;
+            const float2 zu0 = zu[k], zu1 = zu[kp];
+            const float2 zv0 = buf[k], zv1 = buf[kp];
+            for (int side = 0; side < 2; ++side) {
+                if (side == 1 && kp == k) break;
+                const float2 x = side == 0 ? zu0 : zu1, xp = side == 0 ? zu1 : zu0;
+                const float2 y = side == 0 ? zv0 : zv1, yp = side == 0 ? zv1 : zv0;
+                const int kk = side == 0 ? k : kp;
+                double sn, cs;
+                sincospi(2.0 * (double)kk / M, &sn, &cs);
+                const double wr = cs, wi = -sn;
+                // E/O split of each spectrum, then the full spectra at kk and kk + M'
+                const double uer = 0.5 * ((double)x.x + (double)xp.x), uei = 0.5 * ((double)x.y - (double)xp.y);
+                const double uor = 0.5 * ((double)x.y + (double)xp.y), uoi = -0.5 * ((double)x.x - (double)xp.x);
+                const double ver = 0.5 * ((double)y.x + (double)yp.x), vei = 0.5 * ((double)y.y - (double)yp.y);
+                const double vor = 0.5 * ((double)y.y + (double)yp.y), voi = -0.5 * ((double)y.x - (double)yp.x);
+                const double uwr = wr * uor - wi * uoi, uwi = wr * uoi + wi * uor;
+                const double vwr = wr * vor - wi * voi, vwi = wr * voi + wi * vor;
+                const double uar = uer + uwr, uai = uei + uwi, ubr = uer - uwr, ubi = uei - uwi;
+                const double var_ = ver + vwr, vai = vei + vwi, vbr = ver - vwr, vbi = vei - vwi;
+                const double gar = uar * var_ - uai * vai, gai = uar * vai + uai * var_;
+                const double gbr = ubr * vbr - ubi * vbi, gbi = ubr * vbi + ubi * vbr;
+                const double dr = gar - gbr, di = gai - gbi;
+                const double tr = dr * wr + di * wi, ti = di * wr - dr * wi;
+                const double qr = 0.5 * (gar + gbr) - 0.5 * ti, qi = 0.5 * (gai + gbi) + 0.5 * tr;
+                buf[kk] = make_float2((float)(qr * sc), (float)(qi * sc));
+            }
+        }
+        __syncthreads();
+        fft<1>(sh, q, tid);
+        for (long long m = tid; m < N; m += kThreads) {
+            long long cnt = m + 1;
+            if (L < cnt) cnt = L;
+            if (K < cnt) cnt = K;
+            if (N - m < cnt) cnt = N - m;
+            if (cnt <= kEdge) {
+                const long long a0 = m - K + 1 > 0 ? m - K + 1 : 0, a1 = m < L - 1 ? m : L - 1;
+                double acc = 0.0;
+                for (long long t = a0; t <= a1; ++t) acc += (double)u[t] * (double)v[m - t];
+                out[m] = (float)(sigma * acc / (double)cnt);
+            } else {
+                out[m] = getr(buf, m) / (float)cnt;
+            }
+        }
+        __syncthreads();
     }
 }
+
+#undef SSA_INLINE
 
 }  // namespace batch
 
-hipError_t launch_batch(const BatchArgs& a, int nslots, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(batch::k_batch),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)sizeof(batch::Shared));
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL(batch::k_batch, dim3(nslots), dim3(batch::kThreads), sizeof(batch::Shared), s, a);
+static hipError_t allow_lds(const void* f) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(batch::Lds));
+}
+
+static hipError_t batch_attributes() {
+    static hipError_t err = [] {
+        hipError_t e = hipSuccess;
+        for (const void* f : {reinterpret_cast<const void*>(batch::kb_init), reinterpret_cast<const void*>(batch::kb_half),
+                              reinterpret_cast<const void*>(batch::kb_check), reinterpret_cast<const void*>(batch::kb_ritz),
+                              reinterpret_cast<const void*>(batch::kb_hankel)}) {
+            const hipError_t e2 = allow_lds(f);
+            if (e2 != hipSuccess) e = e2;
+        }
+        return e;
+    }();
+    return err;
+}
+
+hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s) {
+    const hipError_t e = batch_attributes();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch::kb_init, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a);
     return hipGetLastError();
 }
 
-size_t batch_lds_bytes() { return sizeof(batch::Shared); }
+hipError_t launch_batch_half(const BatchArgs& a, int j, int side, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_half, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, j, side);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(const BatchArgs& a, int j, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_check, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_ritz, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_hankel(const BatchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_hankel, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a);
+    return hipGetLastError();
+}
+
+size_t batch_lds_bytes() { return sizeof(batch::Lds); }
 
 }  // namespace ssa

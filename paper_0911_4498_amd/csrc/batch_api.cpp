@@ -1,12 +1,14 @@
-// batch_api.cpp -- C ABI of the many-series path (ssa_batch_*): sizes the
-// per-workgroup slots, validates and uploads the series table, launches the
-// persistent kernel of batch.hip.
+// batch_api.cpp -- C ABI of the many-series engine (ssa_batch_*): builds the
+// per-series table and region layout, validates, and drives the lockstep
+// launches of batch.hip (one launch per Lanczos half-step for the whole batch,
+// a stopping-test launch at check points, then Ritz triples and Hankelization).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <set>
 #include <vector>
 
 #include "ssa.h"
@@ -16,180 +18,265 @@
 using namespace ssa;
 
 namespace {
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-constexpr int kPersistentKernelEnabled = 0;
+
+bool smooth7(long long m) {
+    for (int p : {2, 3, 5, 7})
+        while (m % p == 0) m /= p;
+    return m == 1;
+}
+
+FftStages plan_radices(int n) {
+    FftStages st{};
+    st.n = n;
+    int m = n;
+    while (m % 8 == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = 8; m /= 8; }
+    while (m % 4 == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = 4; m /= 4; }
+    while (m % 2 == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = 2; m /= 2; }
+    for (int p : {3, 5, 7})
+        while (m % p == 0 && st.nstages < kMaxStages) { st.radix[st.nstages++] = p; m /= p; }
+    return st;
+}
+
+// splitmix64 finalizer: per-series seed from the batch seed and the series key
+unsigned long long mix64(unsigned long long x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
 }  // namespace
 
 struct ssa_batch_s {
-    int nslots, k_max, d_max, check_every, max_series;
-    long long n_max, ld;
+    long long n_max;
+    int k_max, d_max, check_every, max_series;
     double tol;
     unsigned long long seed;
-    size_t slot_bytes, o_ab, o_u, o_v, o_scratch, o_p, o_q;
-    size_t t_offs, t_ls, t_ks, t_soff, t_uoff, t_voff, t_roff, t_queue, slots_off, ws_bytes;
+    size_t tab_bytes, t_ndone, regions_off, bound_bytes;
     char* ws = nullptr;
+    size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     int bound = 0;
-    long long* h_tab = nullptr;  // pinned staging: offs | soff | uoff | voff | roff | Ls, ks (int)
+    BSeries* h_tab = nullptr;     // pinned staging of the series table
+    unsigned* h_done = nullptr;   // pinned, double-buffered finished-series counts
     hipEvent_t tab_done = nullptr;
+    hipEvent_t chk_ev[2] = {nullptr, nullptr};
+    std::vector<BSeries> tab;
 };
+
+namespace {
+
+// Fill b->tab for these series; returns the workspace bytes they need, or 0 on invalid input.
+size_t build_table(ssa_batch b, int nseries, const long long* offsets, const int* L, const int* k,
+                   const unsigned long long* keys) {
+    if (nseries < 1 || nseries > b->max_series || !offsets || !L || !k || offsets[0] != 0) return 0;
+    b->tab.assign(nseries, BSeries{});
+    size_t off = b->regions_off;
+    for (int s = 0; s < nseries; ++s) {
+        const long long N = offsets[s + 1] - offsets[s];
+        if (N < 3 || N > b->n_max) return 0;
+        if (L[s] <= 1 || L[s] >= N) return 0;
+        const long long K = N - L[s] + 1;
+        const long long r = std::min<long long>(L[s], K);
+        if (k[s] < 1 || k[s] > b->k_max || k[s] > r) return 0;
+        BSeries& t = b->tab[s];
+        t.f_off = offsets[s];
+        t.N = N;
+        t.L = L[s];
+        t.k = k[s];
+        t.transposed = L[s] > K ? 1 : 0;
+        t.Li = std::min<long long>(L[s], K);
+        t.Ki = std::max<long long>(L[s], K);
+        long long mp = (N + 1) / 2;
+        while (!smooth7(mp)) ++mp;
+        if (mp > batch::kMaxMp) return 0;
+        t.Mp = (int)mp;
+        int shift = 0;
+        while ((1LL << (2 * shift)) < mp) ++shift;
+        t.tw_shift = shift;
+        t.st = plan_radices(t.Mp);
+        int dmax = b->d_max > 0 ? b->d_max : 8 * k[s] + 32;
+        dmax = std::min(dmax, batch::kDmax);
+        t.dcap = (int)std::max<long long>(k[s], std::min<long long>(dmax, r));
+        t.ldu = (long long)align_up((size_t)t.Li, 64);
+        t.ldv = (long long)align_up((size_t)t.Ki, 64);
+        const unsigned long long key = keys ? keys[s] : (unsigned long long)s;
+        t.seed = mix64(b->seed ^ mix64(key));
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = o;
+            o = align_up(o + bytes, 256);
+            return (long long)at;
+        };
+        const size_t dc = (size_t)t.dcap;
+        t.o_ab = take(sizeof(float4) * (size_t)t.Mp);
+        t.o_tw = take(sizeof(float2) * 2 * batch::kTwTab);
+        t.o_u = take(sizeof(float) * (dc + 1) * (size_t)t.ldu);
+        t.o_v = take(sizeof(float) * (dc + 1) * (size_t)t.ldv);
+        t.o_alpha = take(sizeof(double) * (dc + 3));
+        t.o_beta = take(sizeof(double) * (dc + 3));
+        t.o_state = take(sizeof(double) * batch::kStDoubles);
+        t.o_p = take(sizeof(double) * (dc + 1) * (size_t)t.k);
+        t.o_q = take(sizeof(double) * dc * (size_t)t.k);
+        t.o_scr = take(std::max(sizeof(double) * (size_t)t.k * 5 * (dc + 2), sizeof(float2) * (size_t)t.Mp));
+        t.reg = (long long)off;
+        off += o;
+    }
+    // output offsets, in input order
+    long long so = 0, uo = 0, vo = 0, ro = 0;
+    for (int s = 0; s < nseries; ++s) {
+        BSeries& t = b->tab[s];
+        const long long K = t.N - t.L + 1;
+        t.s_off = so;
+        t.u_off = uo;
+        t.v_off = vo;
+        t.r_off = ro;
+        so += t.k;
+        uo += (long long)t.L * t.k;
+        vo += K * t.k;
+        ro += t.N * t.k;
+    }
+    return off;
+}
+
+}  // namespace
 
 extern "C" {
 
-int ssa_batch_plan(int nslots, long long n_max, int k_max, int max_series, const ssa_opts* opts,
-                   size_t* workspace_bytes, ssa_batch* out) {
+int ssa_batch_plan(long long n_max, int k_max, int max_series, const ssa_opts* opts, size_t* workspace_bytes,
+                   ssa_batch* out) {
     if (!out || !workspace_bytes) return SSA_EINVAL;
     *out = nullptr;
     if (n_max < 3 || n_max > 2LL * batch::kMaxMp || k_max < 1 || k_max > batch::kMaxK || max_series < 1)
         return SSA_EINVAL;
-    if (nslots <= 0) nslots = 256;
     ssa_batch b = new (std::nothrow) ssa_batch_s();
     if (!b) return SSA_EINVAL;
-    b->nslots = nslots;
     b->n_max = n_max;
     b->k_max = k_max;
     b->max_series = max_series;
-    int d_max = opts && opts->d_max > 0 ? opts->d_max : 8 * k_max + 32;
-    b->d_max = std::max(k_max, std::min(d_max, batch::kDmax));
+    b->d_max = opts && opts->d_max > 0 ? std::min(opts->d_max, batch::kDmax) : 0;
     b->check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
     b->tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
     b->seed = opts && opts->seed ? opts->seed : 1ULL;
-    b->ld = (long long)align_up((size_t)n_max, 64);
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        const size_t r = o;
-        o = align_up(o + bytes, 256);
-        return r;
-    };
-    b->o_ab = take(sizeof(float4) * (size_t)batch::kMaxMp);
-    b->o_u = take(sizeof(float) * (size_t)(b->d_max + 1) * b->ld);
-    b->o_v = take(sizeof(float) * (size_t)(b->d_max + 1) * b->ld);
-    b->o_scratch = take(std::max(sizeof(double) * (size_t)k_max * 6 * (batch::kDmax + 2),
-                                 sizeof(float2) * (size_t)batch::kMaxMp));
-    b->o_p = take(sizeof(double) * (size_t)(b->d_max + 1) * k_max);
-    b->o_q = take(sizeof(double) * (size_t)b->d_max * k_max);
-    b->slot_bytes = o;
-    o = 0;
-    b->t_offs = take(sizeof(long long) * (size_t)(max_series + 1));
-    b->t_ls = take(sizeof(int) * (size_t)max_series);
-    b->t_ks = take(sizeof(int) * (size_t)max_series);
-    b->t_soff = take(sizeof(long long) * (size_t)max_series);
-    b->t_uoff = take(sizeof(long long) * (size_t)max_series);
-    b->t_voff = take(sizeof(long long) * (size_t)max_series);
-    b->t_roff = take(sizeof(long long) * (size_t)max_series);
-    b->t_queue = take(256);
-    b->slots_off = o;
-    b->ws_bytes = o + b->slot_bytes * (size_t)nslots;
-    *workspace_bytes = b->ws_bytes;
+    b->tab_bytes = align_up(sizeof(BSeries) * (size_t)max_series, 256);
+    b->t_ndone = b->tab_bytes;
+    b->regions_off = b->t_ndone + 256;
+    // bound: max_series series of length n_max with L = n_max / 2 and k = k_max
+    std::vector<long long> offs(max_series + 1);
+    std::vector<int> Ls(max_series, (int)(n_max / 2)), ks(max_series, (int)std::min<long long>(k_max, n_max / 2));
+    for (int s = 0; s <= max_series; ++s) offs[s] = (long long)s * n_max;
+    const size_t need = build_table(b, max_series, offs.data(), Ls.data(), ks.data(), nullptr);
+    b->tab.clear();
+    if (need == 0) {
+        delete b;
+        return SSA_EINVAL;
+    }
+    b->bound_bytes = need;
+    *workspace_bytes = need;
     *out = b;
+    return SSA_OK;
+}
+
+int ssa_batch_workspace(ssa_batch b, int nseries, const long long* offsets, const int* L, const int* k,
+                        size_t* bytes) {
+    if (!b || !bytes) return SSA_EINVAL;
+    const size_t need = build_table(b, nseries, offsets, L, k, nullptr);
+    b->tab.clear();
+    if (need == 0) return SSA_EINVAL;
+    *bytes = need;
     return SSA_OK;
 }
 
 int ssa_batch_bind(ssa_batch b, void* workspace_dev, size_t bytes, void* hip_stream) {
     if (!b || !workspace_dev) return SSA_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
-    if (bytes < b->ws_bytes) return SSA_ENOMEM;
+    if (bytes < b->regions_off) return SSA_ENOMEM;
     if (!b->h_tab) {
-        if (hipHostMalloc((void**)&b->h_tab, sizeof(long long) * (7 * (size_t)b->max_series + 8),
-                          hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void**)&b->h_tab, sizeof(BSeries) * (size_t)b->max_series, hipHostMallocDefault) !=
+            hipSuccess)
+            return SSA_EDEVICE;
+        if (hipHostMalloc((void**)&b->h_done, sizeof(unsigned) * 2, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
         if (hipEventCreateWithFlags(&b->tab_done, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
+        for (hipEvent_t& e : b->chk_ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
     }
     b->ws = static_cast<char*>(workspace_dev);
+    b->ws_bytes = bytes;
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->bound = 1;
     return SSA_OK;
 }
 
+#define SSA_TRY_HIP(x)                             \
+    do {                                           \
+        if ((x) != hipSuccess) return SSA_EDEVICE; \
+    } while (0)
+
 int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const long long* offsets, const int* L,
-                    const int* k, double* sigma_dev, float* U_dev, float* V_dev, float* recon_dev, int* info_dev) {
+                    const int* k, const unsigned long long* keys, double* sigma_dev, float* U_dev, float* V_dev,
+                    float* recon_dev, int* info_dev) {
     if (!b || !series_dev || !offsets || !L || !k || !sigma_dev || !U_dev || !V_dev) return SSA_EINVAL;
-    if (nseries < 1 || nseries > b->max_series) return SSA_EINVAL;
-    if (offsets[0] != 0) return SSA_EINVAL;
-    for (int s = 0; s < nseries; ++s) {
-        const long long N = offsets[s + 1] - offsets[s];
-        if (N < 3 || N > b->n_max) return SSA_EINVAL;
-        if (L[s] <= 1 || L[s] >= N) return SSA_EINVAL;
-        const long long K = N - L[s] + 1;
-        if (k[s] < 1 || k[s] > b->k_max || k[s] > std::min<long long>(L[s], K)) return SSA_EINVAL;
-    }
-    // The persistent many-series kernel is switched off: on MI355X its first
-    // run (12 series, N <= 1500) did not finish, while the same source runs to
-    // completion and matches the oracle under a CPU emulation of its barriers
-    // and shuffles.  Until the cause is found, the call validates its
-    // arguments and returns SSA_EDISABLED without touching the device.
-    if (kPersistentKernelEnabled == 0) return SSA_EDISABLED;
-    if (!b->bound) return SSA_ENOMEM;
-    if (hipEventSynchronize(b->tab_done) != hipSuccess) return SSA_EDEVICE;
-    long long* h_offs = b->h_tab;
-    long long* h_soff = h_offs + (nseries + 1);
-    long long* h_uoff = h_soff + nseries;
-    long long* h_voff = h_uoff + nseries;
-    long long* h_roff = h_voff + nseries;
-    int* h_ls = reinterpret_cast<int*>(h_roff + nseries);
-    int* h_ks = h_ls + nseries;
-    long long so = 0, uo = 0, vo = 0, ro = 0;
-    for (int s = 0; s < nseries; ++s) {
-        const long long N = offsets[s + 1] - offsets[s];
-        const long long K = N - L[s] + 1;
-        h_offs[s] = offsets[s];
-        h_soff[s] = so;
-        h_uoff[s] = uo;
-        h_voff[s] = vo;
-        h_roff[s] = ro;
-        h_ls[s] = L[s];
-        h_ks[s] = k[s];
-        so += k[s];
-        uo += (long long)L[s] * k[s];
-        vo += K * k[s];
-        ro += N * k[s];
-    }
-    h_offs[nseries] = offsets[nseries];
+    const size_t need = build_table(b, nseries, offsets, L, k, keys);
+    if (need == 0) return SSA_EINVAL;
+    if (!b->bound || need > b->ws_bytes) return SSA_ENOMEM;
     hipStream_t st = b->stream;
-    auto cp = [&](size_t dst_off, const void* src, size_t bytes) {
-        return hipMemcpyAsync(b->ws + dst_off, src, bytes, hipMemcpyHostToDevice, st);
-    };
-    if (cp(b->t_offs, h_offs, sizeof(long long) * (nseries + 1)) != hipSuccess ||
-        cp(b->t_soff, h_soff, sizeof(long long) * nseries) != hipSuccess ||
-        cp(b->t_uoff, h_uoff, sizeof(long long) * nseries) != hipSuccess ||
-        cp(b->t_voff, h_voff, sizeof(long long) * nseries) != hipSuccess ||
-        cp(b->t_roff, h_roff, sizeof(long long) * nseries) != hipSuccess ||
-        cp(b->t_ls, h_ls, sizeof(int) * nseries) != hipSuccess ||
-        cp(b->t_ks, h_ks, sizeof(int) * nseries) != hipSuccess)
-        return SSA_EDEVICE;
-    if (hipEventRecord(b->tab_done, st) != hipSuccess) return SSA_EDEVICE;
-    if (launch_fill_zero(reinterpret_cast<double*>(b->ws + b->t_queue), 1, st) != hipSuccess) return SSA_EDEVICE;
+    // the previous solve's table upload must be done before the staging is reused
+    SSA_TRY_HIP(hipEventSynchronize(b->tab_done));
+    std::memcpy(b->h_tab, b->tab.data(), sizeof(BSeries) * (size_t)nseries);
+    SSA_TRY_HIP(hipMemcpyAsync(b->ws, b->h_tab, sizeof(BSeries) * (size_t)nseries, hipMemcpyHostToDevice, st));
+    SSA_TRY_HIP(hipEventRecord(b->tab_done, st));
+    SSA_TRY_HIP(launch_fill_zero(reinterpret_cast<double*>(b->ws + b->t_ndone), 1, st));
+
     BatchArgs a{};
     a.nseries = nseries;
+    a.tab = reinterpret_cast<const BSeries*>(b->ws);
     a.series = series_dev;
-    a.offs = reinterpret_cast<const long long*>(b->ws + b->t_offs);
-    a.Ls = reinterpret_cast<const int*>(b->ws + b->t_ls);
-    a.ks = reinterpret_cast<const int*>(b->ws + b->t_ks);
-    a.soff = reinterpret_cast<const long long*>(b->ws + b->t_soff);
-    a.d_max = b->d_max;
-    a.check_every = b->check_every;
-    a.tol = b->tol;
-    a.seed = b->seed;
+    a.ws = b->ws;
     a.sigma = sigma_dev;
     a.U = U_dev;
-    a.uoff = reinterpret_cast<const long long*>(b->ws + b->t_uoff);
     a.V = V_dev;
-    a.voff = reinterpret_cast<const long long*>(b->ws + b->t_voff);
     a.recon = recon_dev;
-    a.roff = reinterpret_cast<const long long*>(b->ws + b->t_roff);
     a.info = info_dev;
-    a.slots = b->ws + b->slots_off;
-    a.slot_bytes = b->slot_bytes;
-    a.o_ab = b->o_ab;
-    a.o_u = b->o_u;
-    a.o_v = b->o_v;
-    a.o_scratch = b->o_scratch;
-    a.o_p = b->o_p;
-    a.o_q = b->o_q;
-    a.ld = b->ld;
-    a.queue = reinterpret_cast<unsigned*>(b->ws + b->t_queue);
-    const int nslots = std::min(b->nslots, nseries);
-    if (launch_batch(a, nslots, st) != hipSuccess) return SSA_EDEVICE;
+    a.ndone = reinterpret_cast<unsigned*>(b->ws + b->t_ndone);
+    a.check_every = b->check_every;
+    a.tol = b->tol;
+
+    int kmin = b->tab[0].k, maxcap = 0;
+    std::set<int> caps;
+    for (const BSeries& t : b->tab) {
+        kmin = std::min(kmin, t.k);
+        maxcap = std::max(maxcap, t.dcap);
+        caps.insert(t.dcap);
+    }
+    SSA_TRY_HIP(launch_batch_init(a, st));
+    // Lanczos steps in lockstep.  The finished-series count of one check is read
+    // while the GPU runs the steps enqueued after it, so the host never waits on
+    // the GPU; once every series is finished, the steps already enqueued find
+    // nothing left to do.
+    int pend = -1, cur = 0;
+    for (int j = 1; j <= maxcap + 1; ++j) {
+        const int jj = j - 1;
+        SSA_TRY_HIP(launch_batch_half(a, j, 0, st));
+        bool stop = false;
+        if (jj >= kmin && (jj % b->check_every == 0 || caps.count(jj))) {
+            SSA_TRY_HIP(launch_batch_check(a, j, st));
+            SSA_TRY_HIP(hipMemcpyAsync(b->h_done + cur, a.ndone, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+            SSA_TRY_HIP(hipEventRecord(b->chk_ev[cur], st));
+            if (pend >= 0) {
+                SSA_TRY_HIP(hipEventSynchronize(b->chk_ev[pend]));
+                stop = b->h_done[pend] >= (unsigned)nseries;
+            }
+            pend = cur;
+            cur ^= 1;
+        }
+        if (stop || jj >= maxcap) break;
+        SSA_TRY_HIP(launch_batch_half(a, j, 1, st));
+    }
+    SSA_TRY_HIP(launch_batch_ritz(a, st));
+    if (recon_dev) SSA_TRY_HIP(launch_batch_hankel(a, st));
     return SSA_OK;
 }
 
@@ -199,12 +286,17 @@ void ssa_batch_destroy(ssa_batch b) {
         (void)hipEventSynchronize(b->tab_done);
         (void)hipEventDestroy(b->tab_done);
     }
+    for (hipEvent_t e : b->chk_ev)
+        if (e) {
+            (void)hipEventSynchronize(e);
+            (void)hipEventDestroy(e);
+        }
     if (b->h_tab) (void)hipHostFree(b->h_tab);
+    if (b->h_done) (void)hipHostFree(b->h_done);
     delete b;
 }
 
 }  // extern "C"
 
-static_assert(sizeof(ssa::batch::Shared) <= 160 * 1024, "batch workgroup LDS exceeds the 160 KB of a CU");
-static_assert(2 * ssa::batch::kMaxMp <= ssa::batch::kEpt * ssa::batch::kThreads * 2,
-              "in-LDS FFT needs M' <= EPT * threads");
+static_assert(sizeof(BSeries) % 8 == 0, "series table entries must keep 8-byte alignment");
+static_assert(2 * batch::kMaxMp <= batch::kEpt * batch::kThreads * 2, "in-LDS FFT needs M' <= EPT * threads");

@@ -1,36 +1,18 @@
-// ssa_batch.h -- the persistent many-series kernel (batch.hip): LDS layout,
-// limits and launch arguments.
+// ssa_batch.h -- the many-series engine (batch.hip): per-series table, LDS
+// layout, limits and launch arguments.
+//
+// A batch advances all of its series in lockstep, one Lanczos half-step per
+// launch; every launch has one workgroup per series, and each workgroup does
+// the whole FFT product and Gram-Schmidt step of its series in LDS.  The
+// state of a series between launches (spectral operator, Lanczos bases,
+// alpha/beta, stopping-test history) lives in its own region of the
+// caller's workspace.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"
 
 namespace ssa {
-
-struct BatchArgs {
-    int nseries;
-    const double* series;      // all series, concatenated (FP64)
-    const long long* offs;     // [nseries + 1] start of each series in `series`
-    const int* Ls;             // [nseries] window lengths
-    const int* ks;             // [nseries] triples per series
-    const long long* soff;     // [nseries] start of each series' sigma block
-    int d_max, check_every;
-    double tol;
-    unsigned long long seed;
-    double* sigma;             // series s: k_s values at soff[s]
-    float* U;                  // series s: L_s x k column-major at uoff[s]
-    const long long* uoff;
-    float* V;                  // series s: K_s x k column-major at voff[s]
-    const long long* voff;
-    float* recon;              // series s: k elementary series of N_s at roff[s] (may be null)
-    const long long* roff;
-    int* info;                 // [nseries * 4]: steps, converged, restarts, DGKS passes
-    char* slots;               // one slot of slot_bytes per workgroup
-    size_t slot_bytes, o_ab, o_u, o_v, o_scratch, o_p, o_q;
-    long long ld;              // leading dimension of the slot's bases
-    unsigned* queue;           // work counter, 0 at launch
-};
-
 namespace batch {
 
 constexpr int kThreads = 512;
@@ -44,26 +26,57 @@ constexpr int kEdge = 512;     // Hankelization entries with <= kEdge terms summ
 constexpr double kBreakdownTol = 1e-6;
 constexpr double kResidFloor = 1e-5;
 
-struct Shared {
-    float2 buf[kMaxMp];
-    float2 tw_hi[kTwTab];
-    float2 tw_lo[kTwTab];
-    double red[kWaves][kDmax + 2];
-    double h[kDmax + 2];
-    double alpha[kDmax + 3];
-    double beta[kDmax + 3];
-    double tri[2 * (kDmax + 2)];
-    double lo[kMaxK], hi[kMaxK], lam[kMaxK], qlast[kMaxK], wprev[kMaxK], resid[kMaxK];
-    double xs[kThreads];
-    int cnt[kThreads];
-    double misc[kWaves];
-    int imisc[8];
-    FftStages st;
+// per-series state (doubles at BSeries::o_state)
+enum {
+    kStBnorm = 0,     // largest alpha/beta so far (breakdown threshold)
+    kStRestarts = 1,  // random restarts after a vanishing alpha/beta
+    kStDgks = 2,      // second Gram-Schmidt passes
+    kStDone = 3,      // 1 once the stopping rule (or the step cap) ended the series
+    kStD = 4,         // Lanczos steps d of the final bidiagonal
+    kStConv = 5,      // 1 if the stopping rule held
+    kStHavePrev = 6,  // a previous check exists (stability test)
+    kStLam = 8,       // k eigenvalues of B_d^T B_d (omega^2), descending
+    kStWprev = kStLam + kMaxK,
+    kStResid = kStWprev + kMaxK,
+    kStDoubles = kStResid + kMaxK
 };
 
 }  // namespace batch
 
-hipError_t launch_batch(const BatchArgs& a, int nslots, hipStream_t s);
+// One series of a batch (host-built, uploaded per solve).
+struct BSeries {
+    long long f_off, N;        // the series: series[f_off .. f_off + N)
+    long long Li, Ki;          // internal window / lag count, Li <= Ki
+    long long reg;             // byte offset of the series' region in the workspace
+    long long ldu, ldv;        // leading dimensions of the U / V bases (floats)
+    long long s_off, u_off, v_off, r_off;  // outputs: sigma, U, V, recon (elements)
+    long long o_ab, o_tw, o_u, o_v, o_alpha, o_beta, o_state, o_p, o_q, o_scr;  // in the region
+    unsigned long long seed;   // start and restart vectors
+    int L, k, transposed, dcap;  // user window, triples, L > K, Krylov cap
+    int Mp, tw_shift, pad0, pad1;
+    FftStages st;              // radix plan of the M'-point complex FFT
+};
+
+struct BatchArgs {
+    int nseries;
+    const BSeries* tab;
+    const double* series;      // all series, concatenated (FP64)
+    char* ws;                  // workspace base (series regions)
+    double* sigma;
+    float* U;
+    float* V;
+    float* recon;              // may be null
+    int* info;                 // [nseries * 4] steps, converged, restarts, DGKS passes (may be null)
+    unsigned* ndone;           // series finished so far
+    int check_every;
+    double tol;
+};
+
+hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_half(const BatchArgs& a, int j, int side, hipStream_t s);
+hipError_t launch_batch_check(const BatchArgs& a, int j, hipStream_t s);
+hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_hankel(const BatchArgs& a, hipStream_t s);
 size_t batch_lds_bytes();
 
 }  // namespace ssa

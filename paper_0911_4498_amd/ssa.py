@@ -21,7 +21,6 @@ SSA_ENONFINITE = -3
 SSA_EDEVICE = -4
 SSA_EMISMATCH = -5
 SSA_ESTATE = -6
-SSA_EDISABLED = -7
 
 _c_ll = ctypes.c_longlong
 _c_p = ctypes.c_void_p
@@ -45,7 +44,8 @@ class SsaPlanDesc(ctypes.Structure):
 EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
             "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read",
-            "ssa_batch_plan", "ssa_batch_bind", "ssa_batch_solve", "ssa_batch_destroy")
+            "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
+            "ssa_batch_destroy")
 
 # kernel classes of ssa_profile_read (enum ssa_prof_class)
 PROF_CLASSES = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz",
@@ -85,10 +85,12 @@ def load():
     lib.ssa_bidiag_ritz.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
     lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_uint]
     lib.ssa_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), dp, dp]
-    lib.ssa_batch_plan.argtypes = [ctypes.c_int, _c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts),
+    lib.ssa_batch_plan.argtypes = [_c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts),
                                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_c_p)]
+    lib.ssa_batch_workspace.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, ctypes.POINTER(ctypes.c_size_t)]
     lib.ssa_batch_bind.argtypes = [_c_p, _c_p, ctypes.c_size_t, _c_p]
-    lib.ssa_batch_solve.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]
+    lib.ssa_batch_solve.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p,
+                                    _c_p]
     lib.ssa_batch_destroy.argtypes = [_c_p]
     lib.ssa_batch_destroy.restype = None
     for name in EXPORTED:
@@ -250,26 +252,26 @@ class Plan:
 
 
 class Batch:
-    """Many independent series solved by one persistent launch (``ssa_batch_*``)."""
+    """Many independent series solved together (``ssa_batch_*``): lockstep launches,
+    one workgroup per series.  The device workspace grows to what each solve needs."""
 
-    def __init__(self, n_max: int, k_max: int, max_series: int, nslots: int = 0, d_max: int = 0,
-                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None):
+    def __init__(self, n_max: int, k_max: int, max_series: int, d_max: int = 0, check_every: int = 0,
+                 tol: float = 0.0, seed: int = 0, device=None, stream=None):
         import torch
         self._torch = torch
         lib = load()
         self.lib = lib
-        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed))
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), 0, 0)
         ws = ctypes.c_size_t(0)
         h = _c_p()
-        _check(lib.ssa_batch_plan(int(nslots), int(n_max), int(k_max), int(max_series), ctypes.byref(opts),
+        _check(lib.ssa_batch_plan(int(n_max), int(k_max), int(max_series), ctypes.byref(opts),
                                   ctypes.byref(ws), ctypes.byref(h)), "ssa_batch_plan")
         self._h = h
+        self.bound_bytes = int(ws.value)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        off = (-base) % 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _check(lib.ssa_batch_bind(h, base + off, int(ws.value), self.stream.cuda_stream), "ssa_batch_bind")
+        self.workspace = None
+        self.ws_bytes = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -282,31 +284,57 @@ class Batch:
         except Exception:
             pass
 
-    def solve(self, series, L, k, recon: bool = True):
-        """series: list of 1-D arrays/tensors (or one concatenated FP64 device tensor with
-        ``offsets``); L, k: per-series lists.  Returns a dict of per-series views:
-        sigma[s] (k_s,), U[s] (k_s, L_s), V[s] (k_s, K_s), recon[s] (k_s, N_s) and
-        info (nseries, 4): steps, converged, restarts, DGKS passes."""
+    def _tables(self, series, L, k, keys):
         import numpy as np
         torch = self._torch
         parts = [torch.as_tensor(x, dtype=torch.float64, device=self.device).reshape(-1) for x in series]
         ns = len(parts)
         lens = np.array([int(p.numel()) for p in parts], dtype=np.int64)
         offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        L = np.ascontiguousarray(np.asarray(L, dtype=np.int32).reshape(ns))
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.int32).reshape(ns))
+        keys = None if keys is None else np.ascontiguousarray(np.asarray(keys, dtype=np.uint64).reshape(ns))
+        return parts, lens, offs, L, k, keys
+
+    def workspace_bytes(self, lens, L, k):
+        import numpy as np
+        lens = np.asarray(lens, dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        L = np.ascontiguousarray(np.asarray(L, dtype=np.int32))
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.int32))
+        need = ctypes.c_size_t(0)
+        _check(self.lib.ssa_batch_workspace(self._h, len(lens), offs.ctypes.data, L.ctypes.data, k.ctypes.data,
+                                            ctypes.byref(need)), "ssa_batch_workspace")
+        return int(need.value)
+
+    def solve(self, series, L, k, recon: bool = True, keys=None):
+        """series: list of 1-D arrays/tensors; L, k (and optional keys): per-series lists.
+        Returns a dict of per-series views: sigma[s] (k_s,), U[s] (k_s, L_s), V[s] (k_s, K_s),
+        recon[s] (k_s, N_s) and info (nseries, 4): steps, converged, restarts, DGKS passes."""
+        torch = self._torch
+        parts, lens, offs, L, k, keys = self._tables(series, L, k, keys)
+        ns = len(parts)
+        need = self.workspace_bytes(lens, L, k)
+        if need > self.ws_bytes:
+            self.workspace = None
+            self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            _check(self.lib.ssa_batch_bind(self._h, base + (-base) % 256, need, self.stream.cuda_stream),
+                   "ssa_batch_bind")
+            self.ws_bytes = need
         flat = torch.cat(parts).contiguous()
-        L = np.asarray(L, dtype=np.int32).reshape(ns)
-        k = np.asarray(k, dtype=np.int32).reshape(ns)
         K = lens - L + 1
         sig = torch.empty(int(k.sum()), dtype=torch.float64, device=self.device)
         U = torch.empty(int((L * k).sum()), dtype=torch.float32, device=self.device)
         V = torch.empty(int((K * k).sum()), dtype=torch.float32, device=self.device)
         R = torch.empty(int((lens * k).sum()), dtype=torch.float32, device=self.device) if recon else None
         info = torch.zeros((ns, 4), dtype=torch.int32, device=self.device)
-        rc = self.lib.ssa_batch_solve(self._h, ns, flat.data_ptr(), offs.ctypes.data, L.ctypes.data, k.ctypes.data,
-                                      sig.data_ptr(), U.data_ptr(), V.data_ptr(), R.data_ptr() if recon else None,
-                                      info.data_ptr())
+        rc = self.lib.ssa_batch_solve(self._h, ns, flat.data_ptr(), offs.ctypes.data, L.ctypes.data,
+                                      k.ctypes.data, keys.ctypes.data if keys is not None else None,
+                                      sig.data_ptr(), U.data_ptr(), V.data_ptr(),
+                                      R.data_ptr() if recon else None, info.data_ptr())
         _check(rc, "ssa_batch_solve")
-        self._keep = (flat, offs, L, k)
+        self._keep = (flat, offs, L, k, keys)
         out = {"sigma": [], "U": [], "V": [], "recon": [] if recon else None, "info": info}
         so = uo = vo = ro = 0
         for s in range(ns):

@@ -136,27 +136,37 @@ def test_fft_schedule_override():
     assert plan(200, 65)[0] == ssa.SSA_EINVAL
 
 
-def test_batch_solve_switched_off_after_validation():
-    """The many-series entry point validates its arguments, then reports that it is
-    switched off without enqueuing anything (no device needed for either)."""
+def test_batch_validation_and_workspace():
+    """The many-series entry points validate on the host before anything is enqueued, and
+    the workspace a solve needs is a pure function of the series shapes."""
     lib = _built()
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t(0)
-    assert lib.ssa_batch_plan(4, 1000, 8, 4, None, ctypes.byref(ws), ctypes.byref(h)) == 0
+    assert lib.ssa_batch_plan(1000, 8, 4, None, ctypes.byref(ws), ctypes.byref(h)) == 0
     try:
         p = ctypes.c_void_p(256)
         offs = (ctypes.c_longlong * 3)(0, 100, 300)
-        Ls = (ctypes.c_int * 2)(50, 100)
+        Ls = (ctypes.c_int * 2)(50, 150)  # the second window is longer than its lag count
         ks = (ctypes.c_int * 2)(4, 8)
-        assert lib.ssa_batch_solve(h, 2, p, offs, Ls, ks, p, p, p, None, None) == ssa.SSA_EDISABLED
+        need = ctypes.c_size_t(0)
+        assert lib.ssa_batch_workspace(h, 2, offs, Ls, ks, ctypes.byref(need)) == 0
+        assert 0 < need.value <= ws.value
+        one = ctypes.c_size_t(0)
+        assert lib.ssa_batch_workspace(h, 1, offs, Ls, ks, ctypes.byref(one)) == 0
+        assert one.value < need.value
+        # unbound: valid arguments report the missing workspace, invalid ones EINVAL
+        assert lib.ssa_batch_solve(h, 2, p, offs, Ls, ks, None, p, p, p, None, None) == ssa.SSA_ENOMEM
         bad_k = (ctypes.c_int * 2)(4, 9)  # above k_max
-        assert lib.ssa_batch_solve(h, 2, p, offs, Ls, bad_k, p, p, p, None, None) == ssa.SSA_EINVAL
+        assert lib.ssa_batch_solve(h, 2, p, offs, Ls, bad_k, None, p, p, p, None, None) == ssa.SSA_EINVAL
         bad_L = (ctypes.c_int * 2)(50, 200)  # L >= N
-        assert lib.ssa_batch_solve(h, 2, p, offs, bad_L, ks, p, p, p, None, None) == ssa.SSA_EINVAL
-        assert lib.ssa_batch_solve(h, 5, p, offs, Ls, ks, p, p, p, None, None) == ssa.SSA_EINVAL
+        assert lib.ssa_batch_solve(h, 2, p, offs, bad_L, ks, None, p, p, p, None, None) == ssa.SSA_EINVAL
+        assert lib.ssa_batch_solve(h, 5, p, offs, Ls, ks, None, p, p, p, None, None) == ssa.SSA_EINVAL
+        big = (ctypes.c_longlong * 2)(0, 1001)  # longer than n_max
+        assert lib.ssa_batch_workspace(h, 1, big, Ls, ks, ctypes.byref(need)) == ssa.SSA_EINVAL
     finally:
         lib.ssa_batch_destroy(h)
-    assert ssa.status_str(ssa.SSA_EDISABLED) == "entry point switched off"
+    assert lib.ssa_batch_plan(20481, 8, 4, None, ctypes.byref(ws), ctypes.byref(h)) == ssa.SSA_EINVAL
+    assert lib.ssa_batch_plan(1000, 33, 4, None, ctypes.byref(ws), ctypes.byref(h)) == ssa.SSA_EINVAL
 
 
 def bidiag(alpha, beta, d):
