@@ -128,13 +128,27 @@ def bench_many(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    eng.profile_enable()  # every kernel class bracketed by HIP events on the engine's stream
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
+    prof = eng.profile_read()
+    eng.profile_enable(on=False)
     info = steps[-1].cpu().numpy()
     rate_b = ns * k * args.steps / t_b
+    for name, (n_l, ms_l) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        print(f"#   {name:7s} launches={n_l:5d} time={ms_l:9.2f} ms", file=sys.stderr)
+    # algorithmic bytes of the Gram-Schmidt launches: a projection against ncols columns reads
+    # (ncols + 1) n floats (columns and r), the update (ncols + 1) n and writes n; side 0 runs
+    # for j = 1..d+1 with ncols = j-1 over Ki entries, side 1 for j = 1..d with ncols = j over Li
+    Li = np.minimum(np.array(Ls), Ns - np.array(Ls) + 1).astype(np.float64)
+    Ki = np.maximum(np.array(Ls), Ns - np.array(Ls) + 1).astype(np.float64)
+    d = info[:, 0].astype(np.float64)
+    cgs_bytes = args.steps * float(np.sum(4.0 * Ki * (d + 1) * (d + 3) + 4.0 * Li * d * (d + 4)))
+    n_cgs, ms_cgs = prof["cgs"]
+    dom = max(prof, key=lambda c: prof[c][1])
     print(f"# batched: {t_b / args.steps * 1e3:.1f} ms per batch, {rate_b:.0f} eigentriples/s, "
           f"mean d {info[:, 0].mean():.1f}, converged {info[:, 1].mean():.3f}", file=sys.stderr, flush=True)
     # one series at a time with the single-series path (plans built untimed)
@@ -179,6 +193,19 @@ def bench_many(args):
                           "lanczos_steps_mean": float(np.mean(d1)),
                           "path": "single-series plans (ssa_truncated_svd + ssa_reconstruct), one series after another"},
         "speedup_vs_one_at_a_time": rate_b / rate_1,
+        "kernel_ms_per_batch": {c: v[1] / args.steps for c, v in prof.items()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "cgs (kb_cgs)" if dom == "cgs" else dom,
+            "achieved": cgs_bytes / (ms_cgs / 1e3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": cgs_bytes / (ms_cgs / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": 1e3 * ms_cgs / max(n_cgs, 1),
+            "alg_bytes_per_launch": cgs_bytes / max(n_cgs, 1),
+            "note": "Gram-Schmidt launches (one per half-step, all series); bytes from each series' d",
+        },
     }
     print(json.dumps(out), flush=True)
 

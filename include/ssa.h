@@ -210,6 +210,31 @@ int ssa_batch_solve(ssa_batch batch, int nseries, const double* series_dev, cons
                     const int* L, const int* k, const unsigned long long* keys, double* sigma_dev,
                     float* U_dev, float* V_dev, float* recon_dev, int* info_dev);
 
+/* Kernel classes of the batch engine's optional timing. */
+enum ssa_batch_prof_class {
+    SSA_BPROF_INIT = 0,  /* spectra, twiddles, start vectors                      */
+    SSA_BPROF_CONV,      /* FFT products (Algorithms 2/3), one launch per half-step */
+    SSA_BPROF_CGS,       /* Gram-Schmidt steps (Sec. 3.2.2), one per half-step   */
+    SSA_BPROF_CHECK,     /* stopping tests (eqs. lbdiagm1/lbdiagm2)              */
+    SSA_BPROF_RITZ,      /* Ritz triples                                         */
+    SSA_BPROF_HANKEL,    /* rank-1 Hankelization (Algorithm 4)                   */
+    SSA_BPROF_NCLASSES
+};
+
+/*
+ * ssa_batch_profile_enable -- from now on, bracket every launch of the classes
+ * in class_mask (bit c = class c) with HIP events on the bound stream; clears
+ * earlier counts.  0 stops timing.  Synchronizes the bound stream.
+ */
+int ssa_batch_profile_enable(ssa_batch batch, unsigned class_mask);
+
+/*
+ * ssa_batch_profile_read -- launches of class cls since the last enable and,
+ * if the class is timed, the summed event-measured milliseconds (else -1).
+ * Synchronizes the bound stream.  Errors: SSA_EINVAL, SSA_EDEVICE.
+ */
+int ssa_batch_profile_read(ssa_batch batch, int cls, long long* launches, double* ms);
+
 /* ssa_batch_destroy -- free the host-side batch engine. */
 void ssa_batch_destroy(ssa_batch batch);
 

@@ -3,20 +3,21 @@
 // Every launch has one workgroup (512 threads) per series of the batch, and a
 // series' result depends only on the series and its seed, never on what runs
 // beside it.  Per Lanczos step the host enqueues
-//   kb_half(j, side 0): r_j = X^T u_j - beta_j v_{j-1}, Gram-Schmidt against V,
-//                       alpha_j, v_j                    (Algorithm 1; Algorithm 3)
+//   kb_conv, kb_cgs (j, side 0): r_j = X^T u_j - beta_j v_{j-1}, Gram-Schmidt
+//                       against V, alpha_j, v_j         (Algorithm 1; Algorithm 3)
 //   kb_check(j):        stopping test on B_{j-1}         (eqs. lbdiagm1/lbdiagm2)
-//   kb_half(j, side 1): p_j = X v_j - alpha_j u_j, Gram-Schmidt against U,
-//                       beta_{j+1}, u_{j+1}             (Algorithm 1; Algorithm 2)
+//   kb_conv, kb_cgs (j, side 1): p_j = X v_j - alpha_j u_j, Gram-Schmidt
+//                       against U, beta_{j+1}, u_{j+1}  (Algorithm 1; Algorithm 2)
 // and after the last step kb_ritz (Ritz triples) and kb_hankel (rank-1
 // Hankelization of every triple, Algorithm 4).  A series whose stopping rule
 // held is skipped by every later launch.
 //
-// Inside a workgroup the product is the circular convolution of the
-// zero-padded series with the reversed input vector (Sec. 4.2-4.3), done as a
-// packed-real FFT of M' = M/2 complex points entirely in LDS; Gram-Schmidt is
-// classical with FP64 sums of exact FP32 products, a second pass by the DGKS
-// criterion and a seeded random restart on breakdown (Sec. 3.2.2).
+// The product is the circular convolution of the zero-padded series with the
+// reversed input vector (Sec. 4.2-4.3), done as a packed-real FFT of M' = M/2
+// complex points entirely in one workgroup's LDS.  The Gram-Schmidt step runs
+// in a second launch with small workgroups (several per CU, float4 rows from
+// HBM): classical, FP64 sums of exact FP32 products, a second pass by the
+// DGKS criterion and a seeded random restart on breakdown (Sec. 3.2.2).
 //
 // The stopping test works on T = B^T B (symmetric tridiagonal, T[c][c] =
 // alpha_{c+1}^2 + beta_{c+2}^2, T[c][c+1] = alpha_{c+2} beta_{c+2}):
@@ -39,12 +40,16 @@ namespace batch {
 
 #define SSA_INLINE __device__ __attribute__((always_inline)) inline
 
-struct Lds {
+struct Lds {  // FFT-product, set-up and Hankelization kernels
     float2 buf[kMaxMp];
     float2 tw_hi[kTwTab];
     float2 tw_lo[kTwTab];
+    double misc[kWaves];
+};
+
+// LDS of the stopping-test and Ritz kernels (no FFT buffer: several workgroups per CU)
+struct SmallLds {
     double red[kWaves][kDmax + 2];
-    double h[kDmax + 2];
     double ab[2 * (kDmax + 3)];  // alpha | beta
     double tri[2 * (kDmax + 2)];
     double lo[kMaxK], hi[kMaxK], lam[kMaxK], qlast[kMaxK];
@@ -52,7 +57,6 @@ struct Lds {
     int cnt[kThreads];
     double misc[kWaves];
     double dmisc[8];
-    int imisc[8];
 };
 
 SSA_INLINE double wsum(double v) {
@@ -61,7 +65,8 @@ SSA_INLINE double wsum(double v) {
     return v;
 }
 
-SSA_INLINE double block_sum(Lds* sh, double v, int tid) {
+template <class S>
+SSA_INLINE double block_sum(S* sh, double v, int tid) {
     v = wsum(v);
     __syncthreads();
     if ((tid & 63) == 0) sh->misc[tid >> 6] = v;
@@ -73,7 +78,8 @@ SSA_INLINE double block_sum(Lds* sh, double v, int tid) {
     return s;
 }
 
-SSA_INLINE double block_max(Lds* sh, double v, int tid) {
+template <class S>
+SSA_INLINE double block_max(S* sh, double v, int tid) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
     __syncthreads();
@@ -134,6 +140,7 @@ struct Ser {
     float2* tw;  // hi | lo tables, kTwTab each
     float* U;
     float* V;
+    float* r;
     double* alpha;
     double* beta;
     double* state;
@@ -161,6 +168,7 @@ SSA_INLINE Ser load_series(const BatchArgs& a, int s) {
     r.tw = reinterpret_cast<float2*>(base + b.o_tw);
     r.U = reinterpret_cast<float*>(base + b.o_u);
     r.V = reinterpret_cast<float*>(base + b.o_v);
+    r.r = reinterpret_cast<float*>(base + b.o_r);
     r.alpha = reinterpret_cast<double*>(base + b.o_alpha);
     r.beta = reinterpret_cast<double*>(base + b.o_beta);
     r.state = reinterpret_cast<double*>(base + b.o_state);
@@ -201,10 +209,10 @@ SSA_INLINE void load_twiddles(Lds* sh, const Ser& q, int tid) {
 // ---------------------------------------------------------------------------
 // products (Algorithms 2 and 3)
 
-// r = X x or X^T x (x: n_in entries in HBM) minus coef * prev; r[t] stays in
-// buf at real position n_in - 1 + t.
+// r = X x or X^T x (x: n_in entries in HBM) minus coef * prev, written to r_out
+// (n_out entries); the product is y[n_in - 1 + t] of the circular convolution.
 SSA_INLINE void convolve(Lds* sh, const Ser& q, const float* x, long long n_in, long long n_out, const float* prev,
-                         double coef, int tid) {
+                         double coef, float* r_out, int tid) {
     float2* buf = sh->buf;
     for (int n = tid; n < q.Mp; n += kThreads) {
         const long long m0 = 2LL * n, m1 = m0 + 1;
@@ -224,89 +232,132 @@ SSA_INLINE void convolve(Lds* sh, const Ser& q, const float* x, long long n_in, 
     }
     __syncthreads();
     fft<1>(sh, q, tid);
-    if (prev) {
-        const float cf = (float)coef;
-        for (long long t = tid; t < n_out; t += kThreads) {
-            const long long m = n_in - 1 + t;
-            setr(buf, m, getr(buf, m) - cf * prev[t]);
-        }
+    const float cf = (float)coef;
+    for (long long t = tid; t < n_out; t += kThreads) {
+        const float y = getr(buf, n_in - 1 + t);
+        r_out[t] = prev ? y - cf * prev[t] : y;
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// classical Gram-Schmidt (Sec. 3.2.2)
+// classical Gram-Schmidt (Sec. 3.2.2), one workgroup of kCgsThreads per series;
+// r and the basis stream from HBM in float4 rows (ld is a multiple of 64)
 
-// h[c] = <basis_c, r> for c < ncols and h[ncols] = |r|^2, FP64 sums of exact
-// FP32 products in a fixed order; r[t] at real position pos0 + t of buf.
-SSA_INLINE void project(Lds* sh, const float* basis, long long ld, int ncols, long long n, long long pos0, int tid) {
-    const float2* buf = sh->buf;
+struct CgsLds {
+    double h[kDmax + 2];
+    double red[kCgsWaves][kCgsCols + 1];
+    double misc[kCgsWaves];
+};
+
+SSA_INLINE float4 rows4(const float* col, long long t, long long n) {
+    float4 v = *reinterpret_cast<const float4*>(col + t);
+    if (t + 3 >= n) {
+        if (t + 1 >= n) v.y = 0.0f;
+        if (t + 2 >= n) v.z = 0.0f;
+        if (t + 3 >= n) v.w = 0.0f;
+    }
+    return v;
+}
+
+SSA_INLINE double dot4(float4 a, float4 b) {
+    return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
+           (double)a.w * (double)b.w;
+}
+
+SSA_INLINE double cgs_sum(CgsLds* sh, double v, int tid) {
+    v = wsum(v);
+    __syncthreads();
+    if ((tid & 63) == 0) sh->misc[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCgsWaves; ++w) s += sh->misc[w];
+    __syncthreads();
+    return s;
+}
+
+// h[c] = <basis_c, r> for c < ncols and h[ncols] = |r|^2: FP64 sums of exact
+// FP32 products in a fixed order, kCgsCols columns per pass over r.
+SSA_INLINE void cgs_project(CgsLds* sh, const float* r, const float* basis, long long ld, int ncols, long long n,
+                            int tid) {
     const int lane = tid & 63, wave = tid >> 6;
-    constexpr int G = 8;
-    for (int c0 = 0; c0 <= ncols; c0 += G) {
-        double acc[G];
+    for (int c0 = 0; c0 <= ncols; c0 += kCgsCols) {
+        double acc[kCgsCols + 1];
 #pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = 0.0;
-        for (long long t = tid; t < n; t += kThreads) {
-            const double r = (double)getr(buf, pos0 + t);
+        for (int g = 0; g <= kCgsCols; ++g) acc[g] = 0.0;
+        for (long long t = 4LL * tid; t < n; t += 4LL * kCgsThreads) {
+            const float4 rv = rows4(r, t, n);
+            if (c0 == 0) acc[kCgsCols] += dot4(rv, rv);
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int c = c0 + g;
-                if (c < ncols)
-                    acc[g] += (double)basis[(long long)c * ld + t] * r;
-                else if (c == ncols)
-                    acc[g] += r * r;
-            }
+            for (int g = 0; g < kCgsCols; ++g)
+                if (c0 + g < ncols) acc[g] += dot4(rows4(basis + (long long)(c0 + g) * ld, t, n), rv);
         }
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g <= kCgsCols; ++g) {
             const double v = wsum(acc[g]);
-            if (lane == 0 && c0 + g <= ncols) sh->red[wave][c0 + g] = v;
+            if (lane == 0) sh->red[wave][g] = v;
+        }
+        __syncthreads();
+        if (tid <= kCgsCols) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kCgsWaves; ++w) s += sh->red[w][tid];
+            if (tid < kCgsCols && c0 + tid < ncols) sh->h[c0 + tid] = s;
+            if (tid == kCgsCols && c0 == 0) sh->h[ncols] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// out = (r - basis h) * scale, FP64 accumulation (out may be r)
+SSA_INLINE void cgs_update(const CgsLds* sh, const float* r, const float* basis, long long ld, int ncols,
+                           long long n, double scale, float* out, int tid) {
+    for (long long t = 4LL * tid; t < n; t += 4LL * kCgsThreads) {
+        const float4 rv = rows4(r, t, n);
+        double a0 = rv.x, a1 = rv.y, a2 = rv.z, a3 = rv.w;
+#pragma unroll 8
+        for (int c = 0; c < ncols; ++c) {
+            const float4 b = rows4(basis + (long long)c * ld, t, n);
+            const double hc = sh->h[c];
+            a0 -= (double)b.x * hc;
+            a1 -= (double)b.y * hc;
+            a2 -= (double)b.z * hc;
+            a3 -= (double)b.w * hc;
+        }
+        const float4 o = make_float4((float)(a0 * scale), (float)(a1 * scale), (float)(a2 * scale),
+                                     (float)(a3 * scale));
+        if (t + 3 < n) {
+            *reinterpret_cast<float4*>(out + t) = o;
+        } else {
+            out[t] = o.x;
+            if (t + 1 < n) out[t + 1] = o.y;
+            if (t + 2 < n) out[t + 2] = o.z;
         }
     }
     __syncthreads();
-    for (int c = tid; c <= ncols; c += kThreads) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) s += sh->red[w][c];
-        sh->h[c] = s;
-    }
-    __syncthreads();
 }
 
-// r -= basis h
-SSA_INLINE void subtract(Lds* sh, const float* basis, long long ld, int ncols, long long n, long long pos0, int tid) {
-    float2* buf = sh->buf;
-    for (long long t = tid; t < n; t += kThreads) {
-        double acc = (double)getr(buf, pos0 + t);
-        for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * sh->h[c];
-        setr(buf, pos0 + t, (float)acc);
-    }
-    __syncthreads();
-}
-
-SSA_INLINE double sum_h2(Lds* sh, int ncols, int tid) {
+SSA_INLINE double cgs_h2(CgsLds* sh, int ncols, int tid) {
     double hh = 0.0;
-    for (int c = tid; c < ncols; c += kThreads) hh += sh->h[c] * sh->h[c];
-    return block_sum(sh, hh, tid);
+    for (int c = tid; c < ncols; c += kCgsThreads) hh += sh->h[c] * sh->h[c];
+    return cgs_sum(sh, hh, tid);
 }
 
-// New basis column ncols from r (in buf): one Gram-Schmidt pass with
+// New basis column ncols from r: one Gram-Schmidt pass with
 // |r_new|^2 = |r|^2 - |h|^2, a second pass if |r_new|^2 < |r|^2 / 2 (DGKS),
 // a seeded random direction if the vector vanishes (|r_new| <= tol * max B).
 // Returns the B entry (0 after a restart); updates the series state.
-SSA_INLINE double orthonormalize(Lds* sh, const Ser& q, float* basis, long long ld, int ncols, long long n,
-                                 long long pos0, unsigned long long ctr, int tid) {
-    float2* buf = sh->buf;
+SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basis, long long ld, int ncols,
+                                 long long n, unsigned long long ctr, int tid) {
     const double bnorm = q.state[kStBnorm];
-    project(sh, basis, ld, ncols, n, pos0, tid);
+    cgs_project(sh, r, basis, ld, ncols, n, tid);
     double coef = 0.0, scale = 0.0;
     int event = 0;  // 1: DGKS pass, 2: restart
     if (ncols >= n) {  // the basis already spans the space
-        for (int c = tid; c < ncols; c += kThreads) sh->h[c] = 0.0;
+        for (int c = tid; c < ncols; c += kCgsThreads) sh->h[c] = 0.0;
         __syncthreads();
     } else {
-        const double hh = sum_h2(sh, ncols, tid);
+        const double hh = cgs_h2(sh, ncols, tid);
         const double rr = sh->h[ncols];
         double a2 = rr - hh;
         const double thr = kBreakdownTol * bnorm;
@@ -314,42 +365,36 @@ SSA_INLINE double orthonormalize(Lds* sh, const Ser& q, float* basis, long long 
             coef = sqrt(a2);
             scale = 1.0 / coef;
         } else {
-            subtract(sh, basis, ld, ncols, n, pos0, tid);
-            project(sh, basis, ld, ncols, n, pos0, tid);
-            const double hh2 = sum_h2(sh, ncols, tid);
+            cgs_update(sh, r, basis, ld, ncols, n, 1.0, r, tid);
+            cgs_project(sh, r, basis, ld, ncols, n, tid);
+            const double hh2 = cgs_h2(sh, ncols, tid);
             a2 = sh->h[ncols] - hh2;
             if (a2 > 0.0 && sqrt(a2) > thr) {
                 coef = sqrt(a2);
                 scale = 1.0 / coef;
                 event = 1;
             } else {
-                for (long long t = tid; t < n; t += kThreads) setr(buf, pos0 + t, gaussian(q.seed, ctr, t));
+                for (long long t = tid; t < n; t += kCgsThreads) r[t] = gaussian(q.seed, ctr, t);
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
-                    project(sh, basis, ld, ncols, n, pos0, tid);
-                    subtract(sh, basis, ld, ncols, n, pos0, tid);
+                    cgs_project(sh, r, basis, ld, ncols, n, tid);
+                    cgs_update(sh, r, basis, ld, ncols, n, 1.0, r, tid);
                 }
-                project(sh, basis, ld, 0, n, pos0, tid);
+                cgs_project(sh, r, basis, ld, 0, n, tid);
                 const double r3 = sh->h[0];
-                for (int c = tid; c < ncols; c += kThreads) sh->h[c] = 0.0;
+                for (int c = tid; c < ncols; c += kCgsThreads) sh->h[c] = 0.0;
                 __syncthreads();
                 scale = r3 > 0.0 ? 1.0 / sqrt(r3) : 0.0;
                 event = 2;
             }
         }
     }
-    float* out = basis + (long long)ncols * ld;
-    for (long long t = tid; t < n; t += kThreads) {
-        double acc = (double)getr(buf, pos0 + t);
-        for (int c = 0; c < ncols; ++c) acc -= (double)basis[(long long)c * ld + t] * sh->h[c];
-        out[t] = (float)(acc * scale);
-    }
+    cgs_update(sh, r, basis, ld, ncols, n, scale, basis + (long long)ncols * ld, tid);
     if (tid == 0) {
         if (coef > bnorm) q.state[kStBnorm] = coef;
         if (event == 1) q.state[kStDgks] += 1.0;
         if (event == 2) q.state[kStRestarts] += 1.0;
     }
-    __syncthreads();
     return coef;
 }
 
@@ -431,26 +476,35 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
     }
 }
 
-// One half of Lanczos step j for every unfinished series:
-//   side 0: r = X^T u_j - beta_j v_{j-1}, v_j = orthonormalized r, alpha_j;
-//   side 1: p = X v_j - alpha_j u_j,      u_{j+1} = orthonormalized p, beta_{j+1}.
-__global__ __launch_bounds__(kThreads) void kb_half(BatchArgs a, int j, int side) {
+// One half of Lanczos step j for every unfinished series, product part:
+//   side 0: r = X^T u_j - beta_j v_{j-1};   side 1: r = X v_j - alpha_j u_j.
+__global__ __launch_bounds__(kThreads) void kb_conv(BatchArgs a, int j, int side) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
     const int tid = threadIdx.x, s = blockIdx.x;
     const Ser q = load_series(a, s);
-    if (q.state[kStDone] != 0.0) return;
-    if (j - 1 > q.dcap) return;
+    if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
     load_twiddles(sh, q, tid);
-    if (side == 0) {
+    if (side == 0)
         convolve(sh, q, q.U + (long long)(j - 1) * q.ldu, q.Li, q.Ki,
-                 j >= 2 ? q.V + (long long)(j - 2) * q.ldv : nullptr, q.beta[j], tid);
-        const double aj = orthonormalize(sh, q, q.V, q.ldv, j - 1, q.Ki, q.Li - 1, 2ULL * j, tid);
+                 j >= 2 ? q.V + (long long)(j - 2) * q.ldv : nullptr, q.beta[j], q.r, tid);
+    else
+        convolve(sh, q, q.V + (long long)(j - 1) * q.ldv, q.Ki, q.Li, q.U + (long long)(j - 1) * q.ldu,
+                 q.alpha[j], q.r, tid);
+}
+
+// Gram-Schmidt part: side 0: v_j and alpha_j;  side 1: u_{j+1} and beta_{j+1}.
+__global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int j, int side) {
+    extern __shared__ char lds[];
+    CgsLds* sh = reinterpret_cast<CgsLds*>(lds);
+    const int tid = threadIdx.x, s = blockIdx.x;
+    const Ser q = load_series(a, s);
+    if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
+    if (side == 0) {
+        const double aj = orthonormalize(sh, q, q.r, q.V, q.ldv, j - 1, q.Ki, 2ULL * j, tid);
         if (tid == 0) q.alpha[j] = aj;
     } else {
-        convolve(sh, q, q.V + (long long)(j - 1) * q.ldv, q.Ki, q.Li, q.U + (long long)(j - 1) * q.ldu,
-                 q.alpha[j], tid);
-        const double bj = orthonormalize(sh, q, q.U, q.ldu, j, q.Li, q.Ki - 1, 2ULL * j + 1, tid);
+        const double bj = orthonormalize(sh, q, q.r, q.U, q.ldu, j, q.Li, 2ULL * j + 1, tid);
         if (tid == 0) q.beta[j + 1] = bj;
     }
 }
@@ -469,7 +523,7 @@ SSA_INLINE int sturm_count(const double* D, const double* E2, int n, double x, d
     return cnt;
 }
 
-SSA_INLINE void tridiag_top(Lds* sh, int n, int k, int tid) {
+SSA_INLINE void tridiag_top(SmallLds* sh, int n, int k, int tid) {
     const double* al = sh->ab;
     const double* be = sh->ab + (kDmax + 3);
     double* D = sh->tri;
@@ -578,7 +632,7 @@ SSA_INLINE double twisted_qlast(const double* D, const double* E2, int n, double
 // values within 10 tol (relative) of the previous check's; or the Krylov cap.
 __global__ __launch_bounds__(kThreads) void kb_check(BatchArgs a, int j) {
     extern __shared__ char lds[];
-    Lds* sh = reinterpret_cast<Lds*>(lds);
+    SmallLds* sh = reinterpret_cast<SmallLds*>(lds);
     const int tid = threadIdx.x, s = blockIdx.x;
     const Ser q = load_series(a, s);
     if (q.state[kStDone] != 0.0) return;
@@ -659,7 +713,7 @@ SSA_INLINE void shifted_solve(const double* D, const double* E, int n, double la
 }
 
 // out[i*ldo + t] = sum_{c < ncols} basis[c][t] coef[c*k + i], i < k
-SSA_INLINE void ritz_vectors(Lds* sh, const float* basis, long long ld, int ncols, const double* coef, int k,
+SSA_INLINE void ritz_vectors(SmallLds* sh, const float* basis, long long ld, int ncols, const double* coef, int k,
                              float* out, long long ldo, long long n, int tid) {
     constexpr int T = 8;
     double* cs = &sh->red[0][0];  // ncols x T coefficients
@@ -691,7 +745,7 @@ SSA_INLINE void ritz_vectors(Lds* sh, const float* basis, long long ld, int ncol
 // U_{d+1} P and V_d Q in the caller's layout, and the per-series report.
 __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
     extern __shared__ char lds[];
-    Lds* sh = reinterpret_cast<Lds*>(lds);
+    SmallLds* sh = reinterpret_cast<SmallLds*>(lds);
     const int tid = threadIdx.x, s = blockIdx.x;
     const Ser q = load_series(a, s);
     const BSeries& b = a.tab[s];
@@ -886,7 +940,7 @@ static hipError_t allow_lds(const void* f) {
 static hipError_t batch_attributes() {
     static hipError_t err = [] {
         hipError_t e = hipSuccess;
-        for (const void* f : {reinterpret_cast<const void*>(batch::kb_init), reinterpret_cast<const void*>(batch::kb_half),
+        for (const void* f : {reinterpret_cast<const void*>(batch::kb_init), reinterpret_cast<const void*>(batch::kb_conv),
                               reinterpret_cast<const void*>(batch::kb_check), reinterpret_cast<const void*>(batch::kb_ritz),
                               reinterpret_cast<const void*>(batch::kb_hankel)}) {
             const hipError_t e2 = allow_lds(f);
@@ -904,18 +958,24 @@ hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_half(const BatchArgs& a, int j, int side, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_half, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, j, side);
+hipError_t launch_batch_conv(const BatchArgs& a, int j, int side, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_conv, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, j, side);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_cgs(const BatchArgs& a, int j, int side, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_cgs, dim3(a.nseries), dim3(batch::kCgsThreads), sizeof(batch::CgsLds), s, a, j,
+                       side);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_check(const BatchArgs& a, int j, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_check, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, j);
+    hipLaunchKernelGGL(batch::kb_check, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::SmallLds), s, a, j);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_ritz, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a);
+    hipLaunchKernelGGL(batch::kb_ritz, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::SmallLds), s, a);
     return hipGetLastError();
 }
 

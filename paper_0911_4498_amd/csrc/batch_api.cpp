@@ -64,6 +64,12 @@ struct ssa_batch_s {
     hipEvent_t tab_done = nullptr;
     hipEvent_t chk_ev[2] = {nullptr, nullptr};
     std::vector<BSeries> tab;
+    // optional HIP-event timing of the kernel classes in prof_mask
+    unsigned prof_mask = 0;
+    std::vector<hipEvent_t> prof_events;
+    size_t prof_used = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pairs[SSA_BPROF_NCLASSES];
+    long long prof_count[SSA_BPROF_NCLASSES] = {};
 };
 
 namespace {
@@ -115,6 +121,7 @@ size_t build_table(ssa_batch b, int nseries, const long long* offsets, const int
         t.o_tw = take(sizeof(float2) * 2 * batch::kTwTab);
         t.o_u = take(sizeof(float) * (dc + 1) * (size_t)t.ldu);
         t.o_v = take(sizeof(float) * (dc + 1) * (size_t)t.ldv);
+        t.o_r = take(sizeof(float) * (size_t)t.ldv);  // product / Gram-Schmidt vector (Ki >= Li entries)
         t.o_alpha = take(sizeof(double) * (dc + 3));
         t.o_beta = take(sizeof(double) * (dc + 3));
         t.o_state = take(sizeof(double) * batch::kStDoubles);
@@ -139,6 +146,31 @@ size_t build_table(ssa_batch b, int nseries, const long long* offsets, const int
         ro += t.N * t.k;
     }
     return off;
+}
+
+hipEvent_t prof_event(ssa_batch b) {
+    if (b->prof_used == b->prof_events.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        b->prof_events.push_back(e);
+    }
+    return b->prof_events[b->prof_used++];
+}
+
+// Enqueue one launch of class cls, bracketed by events when that class is timed.
+template <typename F>
+hipError_t timed(ssa_batch b, int cls, F&& launch) {
+    hipEvent_t e0 = (b->prof_mask >> cls & 1u) ? prof_event(b) : nullptr;
+    if (e0 && hipEventRecord(e0, b->stream) != hipSuccess) return hipErrorUnknown;
+    const hipError_t e = launch();
+    if (e != hipSuccess) return e;
+    b->prof_count[cls] += 1;
+    if (e0) {
+        hipEvent_t e1 = prof_event(b);
+        if (!e1 || hipEventRecord(e1, b->stream) != hipSuccess) return hipErrorUnknown;
+        b->prof_pairs[cls].push_back({e0, e1});
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -251,7 +283,7 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
         maxcap = std::max(maxcap, t.dcap);
         caps.insert(t.dcap);
     }
-    SSA_TRY_HIP(launch_batch_init(a, st));
+    SSA_TRY_HIP(timed(b, SSA_BPROF_INIT, [&] { return launch_batch_init(a, st); }));
     // Lanczos steps in lockstep.  The finished-series count of one check is read
     // while the GPU runs the steps enqueued after it, so the host never waits on
     // the GPU; once every series is finished, the steps already enqueued find
@@ -259,10 +291,11 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
     int pend = -1, cur = 0;
     for (int j = 1; j <= maxcap + 1; ++j) {
         const int jj = j - 1;
-        SSA_TRY_HIP(launch_batch_half(a, j, 0, st));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CONV, [&] { return launch_batch_conv(a, j, 0, st); }));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CGS, [&] { return launch_batch_cgs(a, j, 0, st); }));
         bool stop = false;
         if (jj >= kmin && (jj % b->check_every == 0 || caps.count(jj))) {
-            SSA_TRY_HIP(launch_batch_check(a, j, st));
+            SSA_TRY_HIP(timed(b, SSA_BPROF_CHECK, [&] { return launch_batch_check(a, j, st); }));
             SSA_TRY_HIP(hipMemcpyAsync(b->h_done + cur, a.ndone, sizeof(unsigned), hipMemcpyDeviceToHost, st));
             SSA_TRY_HIP(hipEventRecord(b->chk_ev[cur], st));
             if (pend >= 0) {
@@ -273,10 +306,37 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
             cur ^= 1;
         }
         if (stop || jj >= maxcap) break;
-        SSA_TRY_HIP(launch_batch_half(a, j, 1, st));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CONV, [&] { return launch_batch_conv(a, j, 1, st); }));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CGS, [&] { return launch_batch_cgs(a, j, 1, st); }));
     }
-    SSA_TRY_HIP(launch_batch_ritz(a, st));
-    if (recon_dev) SSA_TRY_HIP(launch_batch_hankel(a, st));
+    SSA_TRY_HIP(timed(b, SSA_BPROF_RITZ, [&] { return launch_batch_ritz(a, st); }));
+    if (recon_dev) SSA_TRY_HIP(timed(b, SSA_BPROF_HANKEL, [&] { return launch_batch_hankel(a, st); }));
+    return SSA_OK;
+}
+
+int ssa_batch_profile_enable(ssa_batch b, unsigned class_mask) {
+    if (!b) return SSA_EINVAL;
+    if (b->bound && hipStreamSynchronize(b->stream) != hipSuccess) return SSA_EDEVICE;
+    for (int c = 0; c < SSA_BPROF_NCLASSES; ++c) {
+        b->prof_pairs[c].clear();
+        b->prof_count[c] = 0;
+    }
+    b->prof_used = 0;
+    b->prof_mask = class_mask;
+    return SSA_OK;
+}
+
+int ssa_batch_profile_read(ssa_batch b, int cls, long long* launches, double* ms) {
+    if (!b || cls < 0 || cls >= SSA_BPROF_NCLASSES) return SSA_EINVAL;
+    if (b->bound && hipStreamSynchronize(b->stream) != hipSuccess) return SSA_EDEVICE;
+    double total = 0.0;
+    for (auto& pr : b->prof_pairs[cls]) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess) return SSA_EDEVICE;
+        total += t;
+    }
+    if (launches) *launches = b->prof_count[cls];
+    if (ms) *ms = (b->prof_mask >> cls & 1u) ? total : -1.0;
     return SSA_OK;
 }
 
@@ -291,6 +351,7 @@ void ssa_batch_destroy(ssa_batch b) {
             (void)hipEventSynchronize(e);
             (void)hipEventDestroy(e);
         }
+    for (hipEvent_t e : b->prof_events) (void)hipEventDestroy(e);
     if (b->h_tab) (void)hipHostFree(b->h_tab);
     if (b->h_done) (void)hipHostFree(b->h_done);
     delete b;

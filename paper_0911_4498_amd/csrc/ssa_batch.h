@@ -1,9 +1,9 @@
 // ssa_batch.h -- the many-series engine (batch.hip): per-series table, LDS
 // layout, limits and launch arguments.
 //
-// A batch advances all of its series in lockstep, one Lanczos half-step per
-// launch; every launch has one workgroup per series, and each workgroup does
-// the whole FFT product and Gram-Schmidt step of its series in LDS.  The
+// A batch advances all of its series in lockstep; every launch has one
+// workgroup per series.  A Lanczos half-step is two launches: the FFT product
+// of each series in its workgroup's LDS, then its Gram-Schmidt step.  The
 // state of a series between launches (spectral operator, Lanczos bases,
 // alpha/beta, stopping-test history) lives in its own region of the
 // caller's workspace.
@@ -15,8 +15,11 @@
 namespace ssa {
 namespace batch {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 512;     // FFT-product, check, Ritz and Hankelization kernels
 constexpr int kWaves = kThreads / 64;
+constexpr int kCgsThreads = 256;  // Gram-Schmidt kernel (small LDS, several workgroups per CU)
+constexpr int kCgsWaves = kCgsThreads / 64;
+constexpr int kCgsCols = 16;      // basis columns per projection pass
 constexpr int kEpt = 32;
 constexpr int kMaxMp = 10240;  // largest half-length FFT held in LDS (N <= 20480)
 constexpr int kTwTab = 128;    // two-level twiddle tables, each <= sqrt(kMaxMp) rounded up
@@ -50,7 +53,7 @@ struct BSeries {
     long long reg;             // byte offset of the series' region in the workspace
     long long ldu, ldv;        // leading dimensions of the U / V bases (floats)
     long long s_off, u_off, v_off, r_off;  // outputs: sigma, U, V, recon (elements)
-    long long o_ab, o_tw, o_u, o_v, o_alpha, o_beta, o_state, o_p, o_q, o_scr;  // in the region
+    long long o_ab, o_tw, o_u, o_v, o_r, o_alpha, o_beta, o_state, o_p, o_q, o_scr;  // in the region
     unsigned long long seed;   // start and restart vectors
     int L, k, transposed, dcap;  // user window, triples, L > K, Krylov cap
     int Mp, tw_shift, pad0, pad1;
@@ -73,7 +76,8 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);
-hipError_t launch_batch_half(const BatchArgs& a, int j, int side, hipStream_t s);
+hipError_t launch_batch_conv(const BatchArgs& a, int j, int side, hipStream_t s);
+hipError_t launch_batch_cgs(const BatchArgs& a, int j, int side, hipStream_t s);
 hipError_t launch_batch_check(const BatchArgs& a, int j, hipStream_t s);
 hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_hankel(const BatchArgs& a, hipStream_t s);

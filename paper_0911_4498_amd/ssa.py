@@ -45,7 +45,10 @@ EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_t
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
             "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
-            "ssa_batch_destroy")
+            "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy")
+
+# kernel classes of ssa_batch_profile_read (enum ssa_batch_prof_class)
+BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
 
 # kernel classes of ssa_profile_read (enum ssa_prof_class)
 PROF_CLASSES = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz",
@@ -91,6 +94,8 @@ def load():
     lib.ssa_batch_bind.argtypes = [_c_p, _c_p, ctypes.c_size_t, _c_p]
     lib.ssa_batch_solve.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p, _c_p,
                                     _c_p]
+    lib.ssa_batch_profile_enable.argtypes = [_c_p, ctypes.c_uint]
+    lib.ssa_batch_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), ctypes.POINTER(ctypes.c_double)]
     lib.ssa_batch_destroy.argtypes = [_c_p]
     lib.ssa_batch_destroy.restype = None
     for name in EXPORTED:
@@ -295,6 +300,29 @@ class Batch:
         k = np.ascontiguousarray(np.asarray(k, dtype=np.int32).reshape(ns))
         keys = None if keys is None else np.ascontiguousarray(np.asarray(keys, dtype=np.uint64).reshape(ns))
         return parts, lens, offs, L, k, keys
+
+    def profile_enable(self, classes=None, on: bool = True):
+        """Time the listed kernel classes (all if None) with HIP events; on=False stops."""
+        if not on:
+            mask = 0
+        elif classes is None:
+            mask = (1 << len(BATCH_PROF_CLASSES)) - 1
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << BATCH_PROF_CLASSES.index(c)
+        _check(self.lib.ssa_batch_profile_enable(self._h, mask), "ssa_batch_profile_enable")
+
+    def profile_read(self):
+        """{class: (launches, ms or -1)} since the last profile_enable."""
+        out = {}
+        for i, c in enumerate(BATCH_PROF_CLASSES):
+            n = _c_ll(0)
+            ms = ctypes.c_double(0.0)
+            _check(self.lib.ssa_batch_profile_read(self._h, i, ctypes.byref(n), ctypes.byref(ms)),
+                   "ssa_batch_profile_read")
+            out[c] = (int(n.value), float(ms.value))
+        return out
 
     def workspace_bytes(self, lens, L, k):
         import numpy as np
