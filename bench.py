@@ -25,8 +25,14 @@ With --workload many: the many-series workload instead (4096 series, N uniform
 in [2000, 20000], L = N/2, k = 16, seeded), solved together by the batched
 engine (ssa_batch_*); the JSON line also reports the single-series path on a
 sample of the same series, one series at a time, on the same GPU.
+With --workload served: a Poisson stream of requests (N log-uniform in
+[1e3, 1e6], L in {N/4, N/2}, k in [8, 32], seeded) at each of --rates;
+requests with N <= 20480 go to the continuous-batching server (ssa_server_*),
+longer ones to single-series plans on two worker streams; reports p50/p99
+latency from arrival to complete outputs, and throughput.
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--pmc-copy]
-                       [--workload single|many] [--series S] [--sample S1]
+                       [--workload single|many|served] [--series S] [--sample S1]
+                       [--rates R1,R2] [--requests Q] [--slots S] [--pool-gb G]
 """
 import argparse
 import json
@@ -210,6 +216,128 @@ def bench_many(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_served(args):
+    """Served stream: continuous batching for short requests, single-series plans for long ones."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_0911_4498_amd import inputs, ssa
+    dev = torch.device("cuda:0")
+    nreq = args.requests
+    n_small_max = 20480
+    print(f"# generating {nreq} requests", file=sys.stderr, flush=True)
+    reqs = []
+    for r in range(nreq):
+        f, N, L, k = inputs.c4_request(r)
+        reqs.append((torch.tensor(f, device=dev), N, L, k))
+    small = [r for r in range(nreq) if reqs[r][1] <= n_small_max]
+    torch.cuda.synchronize()  # request series resident before any stream uses them
+    srv = ssa.Server(n_max=n_small_max, k_max=32, slots=args.slots, pool_bytes=int(args.pool_gb * 2**30), device=dev)
+    done_at = {}
+    lock = threading.Lock()
+    work = queue.Queue()
+
+    def worker():
+        stream = torch.cuda.Stream(device=dev)
+        groups_cache = {}
+        while True:
+            item = work.get()
+            if item is None:
+                return
+            r, t0 = item
+            f, N, L, k = reqs[r]
+            with torch.cuda.stream(stream):
+                plan = ssa.Plan(N, L, k, device=dev, stream=stream)
+                sg, U, V, info = plan.truncated_svd(f, k)
+                g = groups_cache.setdefault(k, [[i] for i in range(k)])
+                plan.reconstruct(sg, U, V, g)
+                stream.synchronize()
+                plan.close()
+            with lock:
+                done_at[r] = time.perf_counter() - t0
+
+    workers = [threading.Thread(target=worker, daemon=True) for _ in range(2)]
+    for w in workers:
+        w.start()
+
+    def run_stream(rate, ids):
+        arrivals = inputs.c4_arrivals(rate, len(ids))
+        done_at.clear()
+        t0 = time.perf_counter()
+        nxt = 0
+        keep = {}
+        while len(done_at) < len(ids):
+            now = time.perf_counter() - t0
+            while nxt < len(ids) and arrivals[nxt] <= now:
+                r = ids[nxt]
+                f, N, L, k = reqs[r]
+                if N <= n_small_max:
+                    keep[r] = srv.submit(r, f, L, k, key=r)
+                else:
+                    work.put((r, t0))
+                nxt += 1
+            st = srv.status()
+            if st["queued"] + st["active"] + st["finalizing"]:
+                for r, _ in srv.step():
+                    with lock:
+                        done_at[r] = time.perf_counter() - t0
+                    keep.pop(r, None)
+            else:
+                time.sleep(min(1e-3, max(0.0, (arrivals[nxt] - now) if nxt < len(ids) else 1e-3)))
+        lat = np.array([done_at[r] - arrivals[i] for i, r in enumerate(ids)])
+        span = max(done_at.values()) - arrivals[0]
+        is_small = np.array([reqs[r][1] <= n_small_max for r in ids])
+        triples = sum(reqs[r][3] for r in ids)
+
+        def pct(x, q):
+            return float(np.percentile(x, q)) if len(x) else None
+
+        return {"rate_req_s": rate, "requests": len(ids), "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+                "p50_short_s": pct(lat[is_small], 50), "p99_short_s": pct(lat[is_small], 99),
+                "p50_long_s": pct(lat[~is_small], 50), "p99_long_s": pct(lat[~is_small], 99),
+                "short_requests": int(is_small.sum()), "makespan_s": span,
+                "eigentriples_per_s": triples / span}
+
+    # warm-up: a few short and long requests, untimed
+    print("# warmup", file=sys.stderr, flush=True)
+    run_stream(1000.0, small[:8] + [r for r in range(nreq) if r not in small][:2])
+    results = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        print(f"# rate {rate:.0f} req/s", file=sys.stderr, flush=True)
+        res = run_stream(rate, list(range(nreq)))
+        print(f"#   p50 {res['p50_s']:.3f} s  p99 {res['p99_s']:.3f} s  short p50 {res['p50_short_s']:.3f} s "
+              f"p99 {res['p99_short_s']:.3f} s  {res['eigentriples_per_s']:.0f} eigentriples/s", file=sys.stderr,
+              flush=True)
+        results.append(res)
+    for _ in workers:
+        work.put(None)
+    best = results[-1]
+    out = {
+        "metric": "p50/p99 served-SSA latency",
+        "value": best["p99_s"],
+        "unit": "s (p99, highest rate)",
+        "n_gpus": 1,
+        "steps": len(results),
+        "warmup": 1,
+        "ms_per_step": None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson stream of {nreq} requests per rate: N log-uniform in [1e3, 1e6], "
+                               "L in {N/4, N/2}, k in [8, 32], c3 signals (seeded)",
+                   "short_path": f"continuous batching, N <= {n_small_max}, {args.slots} slots, "
+                                 f"{args.pool_gb} GiB pool",
+                   "long_path": "single-series plans, 2 worker streams", "parallelism": "single GPU"},
+        "rates": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +345,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
-    ap.add_argument("--workload", choices=("single", "many"), default="single")
+    ap.add_argument("--workload", choices=("single", "many", "served"), default="single")
+    ap.add_argument("--rates", default="100,1000", help="request rates of the served stream (req/s)")
+    ap.add_argument("--requests", type=int, default=200, help="requests per rate (served stream)")
+    ap.add_argument("--slots", type=int, default=256, help="server slots (served stream)")
+    ap.add_argument("--pool-gb", type=float, default=24.0, help="server pool GiB (served stream)")
     ap.add_argument("--series", type=int, default=4096, help="series of the many-series workload")
     ap.add_argument("--sample", type=int, default=256, help="series timed one at a time (many-series workload)")
     args = ap.parse_args()
@@ -227,12 +359,12 @@ def main():
               "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "many":
+    if args.workload in ("many", "served"):
         from paper_0911_4498_amd import ssa as _ssa
         if not os.path.exists(_ssa.LIB_PATH):
             import __graft_entry__
             __graft_entry__.build()
-        return bench_many(args)
+        return bench_many(args) if args.workload == "many" else bench_served(args)
 
     import numpy as np
     import torch

@@ -238,6 +238,59 @@ int ssa_batch_profile_read(ssa_batch batch, int cls, long long* launches, double
 /* ssa_batch_destroy -- free the host-side batch engine. */
 void ssa_batch_destroy(ssa_batch batch);
 
+/*
+ * Continuous batching of SSA requests (served form).  A server owns a pool of
+ * device memory (the caller's workspace, its HBM budget) and a number of
+ * slots.  Submitted requests wait in a first-come-first-served queue and are
+ * admitted, at the start of a tick, while a slot is free and the pool holds
+ * their region.  A tick enqueues one Lanczos step (Algorithm 1 with the FFT
+ * products and Gram-Schmidt of the batched path) for every admitted request,
+ * sets up the newly admitted ones and finishes (Ritz triples, Algorithm 4) the
+ * ones whose stopping test held in the previous tick.  Each request's Lanczos
+ * state stays on the device between ticks.  A request gives the same result
+ * whatever else is in flight (its key seeds its start vector).
+ */
+typedef struct ssa_server_s* ssa_server;
+
+/*
+ * ssa_server_create -- requests of length 3 <= N <= n_max (n_max <= 20480),
+ * k <= k_max <= 32, at most `slots` in flight; opts as for ssa_batch_plan.
+ * workspace_dev (256-byte aligned, `bytes` long) is the device pool; the
+ * library allocates no device memory.  Errors: SSA_EINVAL, SSA_ENOMEM (pool
+ * too small for the slot tables).
+ */
+int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opts, void* workspace_dev,
+                      size_t bytes, void* hip_stream, ssa_server* out);
+
+/* ssa_server_request_bytes -- pool bytes a request of this shape occupies. */
+int ssa_server_request_bytes(ssa_server server, long long N, long long L, int k, size_t* bytes);
+
+/*
+ * ssa_server_submit -- queue a request.  series_dev (N FP64 values) and the
+ * outputs (sigma_dev: k doubles; U_dev: L*k floats, u_i at + i*L; V_dev:
+ * K*k floats; recon_dev: N*k floats or NULL; info_dev: 4 ints or NULL: steps,
+ * converged, restarts, DGKS passes) are device memory that must stay valid
+ * until `id` is reported complete by ssa_server_step.  Errors: SSA_EINVAL,
+ * SSA_ENOMEM (the request alone exceeds the pool).
+ */
+int ssa_server_submit(ssa_server server, long long id, unsigned long long key, const double* series_dev,
+                      long long N, long long L, int k, double* sigma_dev, float* U_dev, float* V_dev,
+                      float* recon_dev, int* info_dev);
+
+/*
+ * ssa_server_step -- one tick (see above); returns when the tick's work is
+ * done on the device.  completed[0 .. *ncompleted) receives the ids of
+ * requests whose outputs are complete (at most max_completed; the others are
+ * reported by later ticks).  Errors: SSA_EINVAL, SSA_EDEVICE.
+ */
+int ssa_server_step(ssa_server server, long long* completed, int max_completed, int* ncompleted);
+
+/* ssa_server_status -- requests queued, being solved, being finished; free pool bytes. */
+int ssa_server_status(ssa_server server, int* queued, int* active, int* finalizing, size_t* pool_free_bytes);
+
+/* ssa_server_destroy -- free the host-side server (waits for its stream). */
+void ssa_server_destroy(ssa_server server);
+
 /* ssa_plan_describe -- copy the plan's sizes into *desc. */
 int ssa_plan_describe(ssa_plan plan, ssa_plan_desc* desc);
 

@@ -408,7 +408,7 @@ SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basi
 __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
-    const int tid = threadIdx.x, s = blockIdx.x;
+    const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
     const BSeries& b = a.tab[s];
     // twiddles W(t) = e^{-2 pi i t / M'}: lo[t] = W(t), hi[t] = W(t << shift)
@@ -435,8 +435,9 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
             q.beta[i] = 0.0;
         }
     }
-    for (int i = tid; i < kStDoubles; i += kThreads) q.state[i] = 0.0;
-    const double* f = a.series + b.f_off;
+    for (int i = tid; i < kStDoubles; i += kThreads) q.state[i] = i == kStJ ? 1.0 : 0.0;
+    if (tid == 0 && a.done_flags) a.done_flags[s] = 0;
+    const double* f = b.f;
     float2* buf = sh->buf;
     for (int n = tid; n < q.Mp; n += kThreads) {
         const long long m0 = 2LL * n, m1 = m0 + 1;
@@ -478,11 +479,12 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
 
 // One half of Lanczos step j for every unfinished series, product part:
 //   side 0: r = X^T u_j - beta_j v_{j-1};   side 1: r = X v_j - alpha_j u_j.
-__global__ __launch_bounds__(kThreads) void kb_conv(BatchArgs a, int j, int side) {
+__global__ __launch_bounds__(kThreads) void kb_conv(BatchArgs a, int side) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
-    const int tid = threadIdx.x, s = blockIdx.x;
+    const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
+    const int j = (int)q.state[kStJ];
     if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
     load_twiddles(sh, q, tid);
     if (side == 0)
@@ -494,18 +496,22 @@ __global__ __launch_bounds__(kThreads) void kb_conv(BatchArgs a, int j, int side
 }
 
 // Gram-Schmidt part: side 0: v_j and alpha_j;  side 1: u_{j+1} and beta_{j+1}.
-__global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int j, int side) {
+__global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int side) {
     extern __shared__ char lds[];
     CgsLds* sh = reinterpret_cast<CgsLds*>(lds);
-    const int tid = threadIdx.x, s = blockIdx.x;
+    const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
+    const int j = (int)q.state[kStJ];
     if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
     if (side == 0) {
         const double aj = orthonormalize(sh, q, q.r, q.V, q.ldv, j - 1, q.Ki, 2ULL * j, tid);
         if (tid == 0) q.alpha[j] = aj;
     } else {
         const double bj = orthonormalize(sh, q, q.r, q.U, q.ldu, j, q.Li, 2ULL * j + 1, tid);
-        if (tid == 0) q.beta[j + 1] = bj;
+        if (tid == 0) {
+            q.beta[j + 1] = bj;
+            q.state[kStJ] = (double)(j + 1);  // the series' next Lanczos step
+        }
     }
 }
 
@@ -630,12 +636,13 @@ SSA_INLINE double twisted_qlast(const double* D, const double* E2, int n, double
 // Stopping test of step j on B_{j-1} for the series whose check point it is:
 // every residual bound <= tol * max(omega_i, 1e-5 omega_1) and the k Ritz
 // values within 10 tol (relative) of the previous check's; or the Krylov cap.
-__global__ __launch_bounds__(kThreads) void kb_check(BatchArgs a, int j) {
+__global__ __launch_bounds__(kThreads) void kb_check(BatchArgs a) {
     extern __shared__ char lds[];
     SmallLds* sh = reinterpret_cast<SmallLds*>(lds);
-    const int tid = threadIdx.x, s = blockIdx.x;
+    const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
     if (q.state[kStDone] != 0.0) return;
+    const int j = (int)q.state[kStJ];
     const int jj = j - 1, k = q.k;
     if (!(jj >= k && (jj % a.check_every == 0 || jj >= q.dcap))) return;
     for (int i = tid; i <= jj + 1; i += kThreads) {
@@ -670,7 +677,8 @@ __global__ __launch_bounds__(kThreads) void kb_check(BatchArgs a, int j) {
             q.state[kStDone] = 1.0;
             q.state[kStD] = (double)jj;
             q.state[kStConv] = (ok || exhausted) ? 1.0 : 0.0;
-            atomicAdd(a.ndone, 1u);
+            if (a.ndone) atomicAdd(a.ndone, 1u);
+            if (a.done_flags) a.done_flags[s] = 1;
         }
     }
 }
@@ -746,7 +754,7 @@ SSA_INLINE void ritz_vectors(SmallLds* sh, const float* basis, long long ld, int
 __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
     extern __shared__ char lds[];
     SmallLds* sh = reinterpret_cast<SmallLds*>(lds);
-    const int tid = threadIdx.x, s = blockIdx.x;
+    const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
     const BSeries& b = a.tab[s];
     const int k = q.k;
@@ -828,15 +836,15 @@ __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
         for (int r = tid; r <= d; r += kThreads) q.P[(long long)r * k + i] = 0.0;
     }
     __syncthreads();
-    float* Uo = a.U + b.u_off;
-    float* Vo = a.V + b.v_off;
+    float* Uo = b.U;
+    float* Vo = b.V;
     float* Ui = b.transposed ? Vo : Uo;  // the internal U has Li entries
     float* Vi = b.transposed ? Uo : Vo;
     ritz_vectors(sh, q.U, q.ldu, d + 1, q.P, k, Ui, q.Li, q.Li, tid);
     ritz_vectors(sh, q.V, q.ldv, d, q.Q, k, Vi, q.Ki, q.Ki, tid);
-    for (int i = tid; i < k; i += kThreads) a.sigma[b.s_off + i] = sqrt(fmax(sh->lam[i], 0.0));
-    if (tid == 0 && a.info) {
-        int* inf = a.info + 4LL * s;
+    for (int i = tid; i < k; i += kThreads) b.sigma[i] = sqrt(fmax(sh->lam[i], 0.0));
+    if (tid == 0 && b.info) {
+        int* inf = b.info;
         inf[0] = d;
         inf[1] = (int)q.state[kStConv];
         inf[2] = (int)q.state[kStRestarts];
@@ -851,9 +859,10 @@ __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
 __global__ __launch_bounds__(kThreads) void kb_hankel(BatchArgs a) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
-    const int tid = threadIdx.x, s = blockIdx.x;
+    const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
     const BSeries& b = a.tab[s];
+    if (!b.recon) return;
     load_twiddles(sh, q, tid);
     float2* buf = sh->buf;
     float2* zu = reinterpret_cast<float2*>(q.scr);
@@ -861,10 +870,10 @@ __global__ __launch_bounds__(kThreads) void kb_hankel(BatchArgs a) {
     const int Mp = q.Mp;
     const double M = 2.0 * Mp;
     for (int i = 0; i < q.k; ++i) {
-        const double sigma = a.sigma[b.s_off + i];
-        const float* u = a.U + b.u_off + (long long)i * L;
-        const float* v = a.V + b.v_off + (long long)i * K;
-        float* out = a.recon + b.r_off + (long long)i * N;
+        const double sigma = b.sigma[i];
+        const float* u = b.U + (long long)i * L;
+        const float* v = b.V + (long long)i * K;
+        float* out = b.recon + (long long)i * N;
         for (int n = tid; n < Mp; n += kThreads) {
             const long long m0 = 2LL * n, m1 = m0 + 1;
             buf[n] = make_float2(m0 < L ? u[m0] : 0.0f, m1 < L ? u[m1] : 0.0f);
@@ -958,19 +967,19 @@ hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_conv(const BatchArgs& a, int j, int side, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_conv, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, j, side);
+hipError_t launch_batch_conv(const BatchArgs& a, int side, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_conv, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, side);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_cgs(const BatchArgs& a, int j, int side, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_cgs, dim3(a.nseries), dim3(batch::kCgsThreads), sizeof(batch::CgsLds), s, a, j,
+hipError_t launch_batch_cgs(const BatchArgs& a, int side, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_cgs, dim3(a.nseries), dim3(batch::kCgsThreads), sizeof(batch::CgsLds), s, a,
                        side);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_check(const BatchArgs& a, int j, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_check, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::SmallLds), s, a, j);
+hipError_t launch_batch_check(const BatchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(batch::kb_check, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::SmallLds), s, a);
     return hipGetLastError();
 }
 

@@ -1,12 +1,18 @@
-// batch_api.cpp -- C ABI of the many-series engine (ssa_batch_*): builds the
-// per-series table and region layout, validates, and drives the lockstep
-// launches of batch.hip (one launch per Lanczos half-step for the whole batch,
-// a stopping-test launch at check points, then Ritz triples and Hankelization).
+// batch_api.cpp -- C ABI of the many-series engine (ssa_batch_*) and of the
+// continuous-batching server built on the same kernels (ssa_server_*).
+//
+// Both lay out one region per series in the caller's workspace (spectral
+// operator, twiddles, Lanczos bases, alpha/beta, stopping-test state) and
+// describe it to the kernels of batch.hip in a table of BSeries.  Every
+// launch covers a list of series with one workgroup each; each series carries
+// its own Lanczos step, so series can start and finish at different launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <new>
 #include <set>
 #include <vector>
@@ -39,7 +45,7 @@ FftStages plan_radices(int n) {
     return st;
 }
 
-// splitmix64 finalizer: per-series seed from the batch seed and the series key
+// splitmix64 finalizer: per-series seed from the engine seed and the series key
 unsigned long long mix64(unsigned long long x) {
     x += 0x9E3779B97F4A7C15ULL;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -47,14 +53,91 @@ unsigned long long mix64(unsigned long long x) {
     return x ^ (x >> 31);
 }
 
-}  // namespace
-
-struct ssa_batch_s {
+struct EngineCfg {
     long long n_max;
-    int k_max, d_max, check_every, max_series;
+    int k_max, d_max, check_every;
     double tol;
     unsigned long long seed;
-    size_t tab_bytes, t_ndone, regions_off, bound_bytes;
+};
+
+// Geometry and region layout of one series; returns its region bytes (offsets
+// relative to the region), or 0 if the series is invalid for this engine.
+size_t layout_series(const EngineCfg& c, long long N, long long L, int k, unsigned long long key, BSeries& t) {
+    if (N < 3 || N > c.n_max || L <= 1 || L >= N) return 0;
+    const long long K = N - L + 1;
+    const long long r = std::min(L, K);
+    if (k < 1 || k > c.k_max || k > r) return 0;
+    t = BSeries{};
+    t.N = N;
+    t.L = (int)L;
+    t.k = k;
+    t.transposed = L > K ? 1 : 0;
+    t.Li = std::min(L, K);
+    t.Ki = std::max(L, K);
+    long long mp = (N + 1) / 2;
+    while (!smooth7(mp)) ++mp;
+    if (mp > batch::kMaxMp) return 0;
+    t.Mp = (int)mp;
+    int shift = 0;
+    while ((1LL << (2 * shift)) < mp) ++shift;
+    t.tw_shift = shift;
+    t.st = plan_radices(t.Mp);
+    int dmax = c.d_max > 0 ? c.d_max : 8 * k + 32;
+    dmax = std::min(dmax, batch::kDmax);
+    t.dcap = (int)std::max<long long>(k, std::min<long long>(dmax, r));
+    t.ldu = (long long)align_up((size_t)t.Li, 64);
+    t.ldv = (long long)align_up((size_t)t.Ki, 64);
+    t.seed = mix64(c.seed ^ mix64(key));
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, 256);
+        return (long long)at;
+    };
+    const size_t dc = (size_t)t.dcap;
+    t.o_ab = take(sizeof(float4) * (size_t)t.Mp);
+    t.o_tw = take(sizeof(float2) * 2 * batch::kTwTab);
+    t.o_u = take(sizeof(float) * (dc + 1) * (size_t)t.ldu);
+    t.o_v = take(sizeof(float) * (dc + 1) * (size_t)t.ldv);
+    t.o_r = take(sizeof(float) * (size_t)t.ldv);  // product / Gram-Schmidt vector (Ki >= Li entries)
+    t.o_alpha = take(sizeof(double) * (dc + 3));
+    t.o_beta = take(sizeof(double) * (dc + 3));
+    t.o_state = take(sizeof(double) * batch::kStDoubles);
+    t.o_p = take(sizeof(double) * (dc + 1) * (size_t)t.k);
+    t.o_q = take(sizeof(double) * dc * (size_t)t.k);
+    t.o_scr = take(std::max(sizeof(double) * (size_t)t.k * 5 * (dc + 2), sizeof(float2) * (size_t)t.Mp));
+    return o;
+}
+
+EngineCfg make_cfg(long long n_max, int k_max, const ssa_opts* opts) {
+    EngineCfg c{};
+    c.n_max = n_max;
+    c.k_max = k_max;
+    c.d_max = opts && opts->d_max > 0 ? std::min(opts->d_max, batch::kDmax) : 0;
+    c.check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
+    c.tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
+    c.seed = opts && opts->seed ? opts->seed : 1ULL;
+    return c;
+}
+
+bool cfg_valid(long long n_max, int k_max) {
+    return n_max >= 3 && n_max <= 2LL * batch::kMaxMp && k_max >= 1 && k_max <= batch::kMaxK;
+}
+
+#define SSA_TRY_HIP(x)                             \
+    do {                                           \
+        if ((x) != hipSuccess) return SSA_EDEVICE; \
+    } while (0)
+
+}  // namespace
+
+// ===========================================================================
+// batch engine: a fixed set of series solved to completion by one call
+
+struct ssa_batch_s {
+    EngineCfg cfg;
+    int max_series;
+    size_t tab_bytes, t_ndone, regions_off;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -82,68 +165,10 @@ size_t build_table(ssa_batch b, int nseries, const long long* offsets, const int
     size_t off = b->regions_off;
     for (int s = 0; s < nseries; ++s) {
         const long long N = offsets[s + 1] - offsets[s];
-        if (N < 3 || N > b->n_max) return 0;
-        if (L[s] <= 1 || L[s] >= N) return 0;
-        const long long K = N - L[s] + 1;
-        const long long r = std::min<long long>(L[s], K);
-        if (k[s] < 1 || k[s] > b->k_max || k[s] > r) return 0;
-        BSeries& t = b->tab[s];
-        t.f_off = offsets[s];
-        t.N = N;
-        t.L = L[s];
-        t.k = k[s];
-        t.transposed = L[s] > K ? 1 : 0;
-        t.Li = std::min<long long>(L[s], K);
-        t.Ki = std::max<long long>(L[s], K);
-        long long mp = (N + 1) / 2;
-        while (!smooth7(mp)) ++mp;
-        if (mp > batch::kMaxMp) return 0;
-        t.Mp = (int)mp;
-        int shift = 0;
-        while ((1LL << (2 * shift)) < mp) ++shift;
-        t.tw_shift = shift;
-        t.st = plan_radices(t.Mp);
-        int dmax = b->d_max > 0 ? b->d_max : 8 * k[s] + 32;
-        dmax = std::min(dmax, batch::kDmax);
-        t.dcap = (int)std::max<long long>(k[s], std::min<long long>(dmax, r));
-        t.ldu = (long long)align_up((size_t)t.Li, 64);
-        t.ldv = (long long)align_up((size_t)t.Ki, 64);
-        const unsigned long long key = keys ? keys[s] : (unsigned long long)s;
-        t.seed = mix64(b->seed ^ mix64(key));
-        size_t o = 0;
-        auto take = [&](size_t bytes) {
-            const size_t at = o;
-            o = align_up(o + bytes, 256);
-            return (long long)at;
-        };
-        const size_t dc = (size_t)t.dcap;
-        t.o_ab = take(sizeof(float4) * (size_t)t.Mp);
-        t.o_tw = take(sizeof(float2) * 2 * batch::kTwTab);
-        t.o_u = take(sizeof(float) * (dc + 1) * (size_t)t.ldu);
-        t.o_v = take(sizeof(float) * (dc + 1) * (size_t)t.ldv);
-        t.o_r = take(sizeof(float) * (size_t)t.ldv);  // product / Gram-Schmidt vector (Ki >= Li entries)
-        t.o_alpha = take(sizeof(double) * (dc + 3));
-        t.o_beta = take(sizeof(double) * (dc + 3));
-        t.o_state = take(sizeof(double) * batch::kStDoubles);
-        t.o_p = take(sizeof(double) * (dc + 1) * (size_t)t.k);
-        t.o_q = take(sizeof(double) * dc * (size_t)t.k);
-        t.o_scr = take(std::max(sizeof(double) * (size_t)t.k * 5 * (dc + 2), sizeof(float2) * (size_t)t.Mp));
-        t.reg = (long long)off;
-        off += o;
-    }
-    // output offsets, in input order
-    long long so = 0, uo = 0, vo = 0, ro = 0;
-    for (int s = 0; s < nseries; ++s) {
-        BSeries& t = b->tab[s];
-        const long long K = t.N - t.L + 1;
-        t.s_off = so;
-        t.u_off = uo;
-        t.v_off = vo;
-        t.r_off = ro;
-        so += t.k;
-        uo += (long long)t.L * t.k;
-        vo += K * t.k;
-        ro += t.N * t.k;
+        const size_t bytes = layout_series(b->cfg, N, L[s], k[s], keys ? keys[s] : (unsigned long long)s, b->tab[s]);
+        if (bytes == 0) return 0;
+        b->tab[s].reg = (long long)off;
+        off += bytes;
     }
     return off;
 }
@@ -181,17 +206,11 @@ int ssa_batch_plan(long long n_max, int k_max, int max_series, const ssa_opts* o
                    ssa_batch* out) {
     if (!out || !workspace_bytes) return SSA_EINVAL;
     *out = nullptr;
-    if (n_max < 3 || n_max > 2LL * batch::kMaxMp || k_max < 1 || k_max > batch::kMaxK || max_series < 1)
-        return SSA_EINVAL;
+    if (!cfg_valid(n_max, k_max) || max_series < 1) return SSA_EINVAL;
     ssa_batch b = new (std::nothrow) ssa_batch_s();
     if (!b) return SSA_EINVAL;
-    b->n_max = n_max;
-    b->k_max = k_max;
+    b->cfg = make_cfg(n_max, k_max, opts);
     b->max_series = max_series;
-    b->d_max = opts && opts->d_max > 0 ? std::min(opts->d_max, batch::kDmax) : 0;
-    b->check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
-    b->tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
-    b->seed = opts && opts->seed ? opts->seed : 1ULL;
     b->tab_bytes = align_up(sizeof(BSeries) * (size_t)max_series, 256);
     b->t_ndone = b->tab_bytes;
     b->regions_off = b->t_ndone + 256;
@@ -205,7 +224,6 @@ int ssa_batch_plan(long long n_max, int k_max, int max_series, const ssa_opts* o
         delete b;
         return SSA_EINVAL;
     }
-    b->bound_bytes = need;
     *workspace_bytes = need;
     *out = b;
     return SSA_OK;
@@ -242,11 +260,6 @@ int ssa_batch_bind(ssa_batch b, void* workspace_dev, size_t bytes, void* hip_str
     return SSA_OK;
 }
 
-#define SSA_TRY_HIP(x)                             \
-    do {                                           \
-        if ((x) != hipSuccess) return SSA_EDEVICE; \
-    } while (0)
-
 int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const long long* offsets, const int* L,
                     const int* k, const unsigned long long* keys, double* sigma_dev, float* U_dev, float* V_dev,
                     float* recon_dev, int* info_dev) {
@@ -254,6 +267,22 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
     const size_t need = build_table(b, nseries, offsets, L, k, keys);
     if (need == 0) return SSA_EINVAL;
     if (!b->bound || need > b->ws_bytes) return SSA_ENOMEM;
+    // outputs: one block per series in input order
+    long long so = 0, uo = 0, vo = 0, ro = 0;
+    for (int s = 0; s < nseries; ++s) {
+        BSeries& t = b->tab[s];
+        const long long K = t.N - t.L + 1;
+        t.f = series_dev + offsets[s];
+        t.sigma = sigma_dev + so;
+        t.U = U_dev + uo;
+        t.V = V_dev + vo;
+        t.recon = recon_dev ? recon_dev + ro : nullptr;
+        t.info = info_dev ? info_dev + 4LL * s : nullptr;
+        so += t.k;
+        uo += (long long)t.L * t.k;
+        vo += K * t.k;
+        ro += t.N * t.k;
+    }
     hipStream_t st = b->stream;
     // the previous solve's table upload must be done before the staging is reused
     SSA_TRY_HIP(hipEventSynchronize(b->tab_done));
@@ -264,17 +293,13 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
 
     BatchArgs a{};
     a.nseries = nseries;
+    a.list = nullptr;
     a.tab = reinterpret_cast<const BSeries*>(b->ws);
-    a.series = series_dev;
     a.ws = b->ws;
-    a.sigma = sigma_dev;
-    a.U = U_dev;
-    a.V = V_dev;
-    a.recon = recon_dev;
-    a.info = info_dev;
     a.ndone = reinterpret_cast<unsigned*>(b->ws + b->t_ndone);
-    a.check_every = b->check_every;
-    a.tol = b->tol;
+    a.done_flags = nullptr;
+    a.check_every = b->cfg.check_every;
+    a.tol = b->cfg.tol;
 
     int kmin = b->tab[0].k, maxcap = 0;
     std::set<int> caps;
@@ -284,18 +309,18 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
         caps.insert(t.dcap);
     }
     SSA_TRY_HIP(timed(b, SSA_BPROF_INIT, [&] { return launch_batch_init(a, st); }));
-    // Lanczos steps in lockstep.  The finished-series count of one check is read
-    // while the GPU runs the steps enqueued after it, so the host never waits on
-    // the GPU; once every series is finished, the steps already enqueued find
-    // nothing left to do.
+    // Lanczos steps in lockstep (every series starts at step 1).  The
+    // finished-series count of one check is read while the GPU runs the steps
+    // enqueued after it, so the host never waits on the GPU; once every series
+    // is finished, the steps already enqueued find nothing left to do.
     int pend = -1, cur = 0;
     for (int j = 1; j <= maxcap + 1; ++j) {
         const int jj = j - 1;
-        SSA_TRY_HIP(timed(b, SSA_BPROF_CONV, [&] { return launch_batch_conv(a, j, 0, st); }));
-        SSA_TRY_HIP(timed(b, SSA_BPROF_CGS, [&] { return launch_batch_cgs(a, j, 0, st); }));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CONV, [&] { return launch_batch_conv(a, 0, st); }));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CGS, [&] { return launch_batch_cgs(a, 0, st); }));
         bool stop = false;
-        if (jj >= kmin && (jj % b->check_every == 0 || caps.count(jj))) {
-            SSA_TRY_HIP(timed(b, SSA_BPROF_CHECK, [&] { return launch_batch_check(a, j, st); }));
+        if (jj >= kmin && (jj % b->cfg.check_every == 0 || caps.count(jj))) {
+            SSA_TRY_HIP(timed(b, SSA_BPROF_CHECK, [&] { return launch_batch_check(a, st); }));
             SSA_TRY_HIP(hipMemcpyAsync(b->h_done + cur, a.ndone, sizeof(unsigned), hipMemcpyDeviceToHost, st));
             SSA_TRY_HIP(hipEventRecord(b->chk_ev[cur], st));
             if (pend >= 0) {
@@ -306,8 +331,8 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
             cur ^= 1;
         }
         if (stop || jj >= maxcap) break;
-        SSA_TRY_HIP(timed(b, SSA_BPROF_CONV, [&] { return launch_batch_conv(a, j, 1, st); }));
-        SSA_TRY_HIP(timed(b, SSA_BPROF_CGS, [&] { return launch_batch_cgs(a, j, 1, st); }));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CONV, [&] { return launch_batch_conv(a, 1, st); }));
+        SSA_TRY_HIP(timed(b, SSA_BPROF_CGS, [&] { return launch_batch_cgs(a, 1, st); }));
     }
     SSA_TRY_HIP(timed(b, SSA_BPROF_RITZ, [&] { return launch_batch_ritz(a, st); }));
     if (recon_dev) SSA_TRY_HIP(timed(b, SSA_BPROF_HANKEL, [&] { return launch_batch_hankel(a, st); }));
@@ -355,6 +380,265 @@ void ssa_batch_destroy(ssa_batch b) {
     if (b->h_tab) (void)hipHostFree(b->h_tab);
     if (b->h_done) (void)hipHostFree(b->h_done);
     delete b;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// continuous-batching server: requests join and leave between ticks
+
+namespace {
+
+struct Request {
+    long long id;
+    unsigned long long key;
+    const double* f;
+    long long N, L;
+    int k;
+    double* sigma;
+    float* U;
+    float* V;
+    float* recon;
+    int* info;
+};
+
+// First-fit allocator of byte ranges of the region pool (256-byte multiples).
+struct Pool {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> bytes
+    void init(size_t base, size_t bytes) {
+        size = bytes;
+        free_.clear();
+        if (bytes) free_[base] = bytes;
+    }
+    bool alloc(size_t bytes, size_t* at) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *at = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t off = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[off] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t at, size_t bytes) {
+        auto it = free_.emplace(at, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t free_bytes() const {
+        size_t s = 0;
+        for (auto& kv : free_) s += kv.second;
+        return s;
+    }
+};
+
+enum SlotState { kFree = 0, kActive = 1, kFinalizing = 2 };
+
+}  // namespace
+
+struct ssa_server_s {
+    EngineCfg cfg;
+    int slots;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    size_t o_tab, o_flags, o_lists;  // table, done flags, launch lists (device)
+    Pool pool;
+    std::deque<Request> queue;
+    std::vector<int> state;            // SlotState per slot
+    std::vector<Request> req;          // request per slot
+    std::vector<size_t> reg, reg_bytes;
+    BSeries* h_tab = nullptr;          // pinned: table staging (one entry per slot)
+    int* h_flags = nullptr;            // pinned: done flags read back after each tick
+    int* h_lists = nullptr;            // pinned: launch lists (set-up | active | finalize)
+    long long ticks = 0;
+};
+
+extern "C" {
+
+int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opts, void* workspace_dev, size_t bytes,
+                      void* hip_stream, ssa_server* out) {
+    if (!out) return SSA_EINVAL;
+    *out = nullptr;
+    if (!cfg_valid(n_max, k_max) || slots < 1 || !workspace_dev) return SSA_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
+    ssa_server v = new (std::nothrow) ssa_server_s();
+    if (!v) return SSA_EINVAL;
+    v->cfg = make_cfg(n_max, k_max, opts);
+    v->slots = slots;
+    v->o_tab = 0;
+    v->o_flags = align_up(sizeof(BSeries) * (size_t)slots, 256);
+    v->o_lists = v->o_flags + align_up(sizeof(int) * (size_t)slots, 256);
+    const size_t head = v->o_lists + align_up(sizeof(int) * 3 * (size_t)slots, 256);
+    if (bytes <= head) {
+        delete v;
+        return SSA_ENOMEM;
+    }
+    v->ws = static_cast<char*>(workspace_dev);
+    v->ws_bytes = bytes;
+    v->stream = static_cast<hipStream_t>(hip_stream);
+    v->pool.init(head, (bytes - head) / 256 * 256);
+    v->state.assign(slots, kFree);
+    v->req.assign(slots, Request{});
+    v->reg.assign(slots, 0);
+    v->reg_bytes.assign(slots, 0);
+    *out = v;
+    return SSA_OK;
+}
+
+int ssa_server_request_bytes(ssa_server v, long long N, long long L, int k, size_t* bytes) {
+    if (!v || !bytes) return SSA_EINVAL;
+    BSeries t;
+    const size_t b = layout_series(v->cfg, N, L, k, 0, t);
+    if (b == 0) return SSA_EINVAL;
+    *bytes = b;
+    return SSA_OK;
+}
+
+int ssa_server_submit(ssa_server v, long long id, unsigned long long key, const double* series_dev, long long N,
+                      long long L, int k, double* sigma_dev, float* U_dev, float* V_dev, float* recon_dev,
+                      int* info_dev) {
+    if (!v || !series_dev || !sigma_dev || !U_dev || !V_dev) return SSA_EINVAL;
+    BSeries t;
+    const size_t bytes = layout_series(v->cfg, N, L, k, key, t);
+    if (bytes == 0) return SSA_EINVAL;
+    if (bytes > v->pool.size) return SSA_ENOMEM;  // could never be admitted
+    v->queue.push_back(Request{id, key, series_dev, N, L, k, sigma_dev, U_dev, V_dev, recon_dev, info_dev});
+    return SSA_OK;
+}
+
+int ssa_server_step(ssa_server v, long long* completed, int max_completed, int* ncompleted) {
+    if (!v || !ncompleted || max_completed < 0 || (max_completed > 0 && !completed)) return SSA_EINVAL;
+    *ncompleted = 0;
+    hipStream_t st = v->stream;
+    if (!v->h_tab) {  // pinned staging, allocated at the first tick
+        if (hipHostMalloc((void**)&v->h_tab, sizeof(BSeries) * (size_t)v->slots, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&v->h_flags, sizeof(int) * (size_t)v->slots, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&v->h_lists, sizeof(int) * 3 * (size_t)v->slots, hipHostMallocDefault) !=
+                hipSuccess)
+            return SSA_EDEVICE;
+        std::memset(v->h_flags, 0, sizeof(int) * (size_t)v->slots);
+    }
+    // 1. requests finalized in the previous tick are complete (every tick ends synchronized)
+    for (int s = 0; s < v->slots; ++s) {
+        if (v->state[s] != kFinalizing) continue;
+        if (*ncompleted >= max_completed) break;  // the rest are reported next time
+        completed[(*ncompleted)++] = v->req[s].id;
+        v->pool.release(v->reg[s], v->reg_bytes[s]);
+        v->state[s] = kFree;
+    }
+    BatchArgs a{};
+    a.tab = reinterpret_cast<const BSeries*>(v->ws + v->o_tab);
+    a.ws = v->ws;
+    a.ndone = nullptr;
+    a.done_flags = reinterpret_cast<int*>(v->ws + v->o_flags);
+    a.check_every = v->cfg.check_every;
+    a.tol = v->cfg.tol;
+    int* d_lists = reinterpret_cast<int*>(v->ws + v->o_lists);
+    int* l_init = v->h_lists;
+    int* l_act = v->h_lists + v->slots;
+    int* l_fin = v->h_lists + 2 * v->slots;
+    int n_init = 0, n_act = 0, n_fin = 0;
+    // 2. series the previous tick's stopping test finished: Ritz triples and Hankelization
+    for (int s = 0; s < v->slots; ++s)
+        if (v->state[s] == kActive && v->h_flags[s]) l_fin[n_fin++] = s;
+    // 3. admission, first come first served, while a slot and pool memory are free
+    while (!v->queue.empty()) {
+        int s = -1;
+        for (int c = 0; c < v->slots; ++c)
+            if (v->state[c] == kFree) {
+                s = c;
+                break;
+            }
+        if (s < 0) break;
+        const Request r = v->queue.front();
+        BSeries t;
+        const size_t bytes = layout_series(v->cfg, r.N, r.L, r.k, r.key, t);
+        size_t at = 0;
+        if (!v->pool.alloc(bytes, &at)) break;
+        t.reg = (long long)at;
+        t.f = r.f;
+        t.sigma = r.sigma;
+        t.U = r.U;
+        t.V = r.V;
+        t.recon = r.recon;
+        t.info = r.info;
+        v->h_tab[s] = t;
+        SSA_TRY_HIP(hipMemcpyAsync(v->ws + v->o_tab + sizeof(BSeries) * (size_t)s, &v->h_tab[s], sizeof(BSeries),
+                                   hipMemcpyHostToDevice, st));
+        v->req[s] = r;
+        v->reg[s] = at;
+        v->reg_bytes[s] = bytes;
+        v->state[s] = kActive;
+        v->h_flags[s] = 0;
+        l_init[n_init++] = s;
+        v->queue.pop_front();
+    }
+    for (int s = 0; s < v->slots; ++s)
+        if (v->state[s] == kActive && !v->h_flags[s]) l_act[n_act++] = s;
+    SSA_TRY_HIP(hipMemcpyAsync(d_lists, v->h_lists, sizeof(int) * 3 * (size_t)v->slots, hipMemcpyHostToDevice, st));
+    if (n_fin) {
+        a.list = d_lists + 2 * v->slots;
+        a.nseries = n_fin;
+        SSA_TRY_HIP(launch_batch_ritz(a, st));
+        SSA_TRY_HIP(launch_batch_hankel(a, st));
+        for (int i = 0; i < n_fin; ++i) v->state[l_fin[i]] = kFinalizing;
+    }
+    if (n_init) {
+        a.list = d_lists;
+        a.nseries = n_init;
+        SSA_TRY_HIP(launch_batch_init(a, st));
+    }
+    // 4. one Lanczos step of every active series; the stopping test runs where it is due
+    if (n_act) {
+        a.list = d_lists + v->slots;
+        a.nseries = n_act;
+        SSA_TRY_HIP(launch_batch_conv(a, 0, st));
+        SSA_TRY_HIP(launch_batch_cgs(a, 0, st));
+        SSA_TRY_HIP(launch_batch_check(a, st));
+        SSA_TRY_HIP(launch_batch_conv(a, 1, st));
+        SSA_TRY_HIP(launch_batch_cgs(a, 1, st));
+    }
+    SSA_TRY_HIP(hipMemcpyAsync(v->h_flags, a.done_flags, sizeof(int) * (size_t)v->slots, hipMemcpyDeviceToHost, st));
+    SSA_TRY_HIP(hipStreamSynchronize(st));
+    ++v->ticks;
+    return SSA_OK;
+}
+
+int ssa_server_status(ssa_server v, int* queued, int* active, int* finalizing, size_t* pool_free_bytes) {
+    if (!v) return SSA_EINVAL;
+    int na = 0, nf = 0;
+    for (int s = 0; s < v->slots; ++s) {
+        na += v->state[s] == kActive;
+        nf += v->state[s] == kFinalizing;
+    }
+    if (queued) *queued = (int)v->queue.size();
+    if (active) *active = na;
+    if (finalizing) *finalizing = nf;
+    if (pool_free_bytes) *pool_free_bytes = v->pool.free_bytes();
+    return SSA_OK;
+}
+
+void ssa_server_destroy(ssa_server v) {
+    if (!v) return;
+    if (v->h_tab) (void)hipStreamSynchronize(v->stream);
+    if (v->h_tab) (void)hipHostFree(v->h_tab);
+    if (v->h_flags) (void)hipHostFree(v->h_flags);
+    if (v->h_lists) (void)hipHostFree(v->h_lists);
+    delete v;
 }
 
 }  // extern "C"

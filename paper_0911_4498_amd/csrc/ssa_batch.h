@@ -38,6 +38,7 @@ enum {
     kStD = 4,         // Lanczos steps d of the final bidiagonal
     kStConv = 5,      // 1 if the stopping rule held
     kStHavePrev = 6,  // a previous check exists (stability test)
+    kStJ = 7,         // the series' current Lanczos step j (1 after set-up)
     kStLam = 8,       // k eigenvalues of B_d^T B_d (omega^2), descending
     kStWprev = kStLam + kMaxK,
     kStResid = kStWprev + kMaxK,
@@ -48,11 +49,16 @@ enum {
 
 // One series of a batch (host-built, uploaded per solve).
 struct BSeries {
-    long long f_off, N;        // the series: series[f_off .. f_off + N)
+    const double* f;           // the series (device, N values)
+    long long N;
     long long Li, Ki;          // internal window / lag count, Li <= Ki
     long long reg;             // byte offset of the series' region in the workspace
     long long ldu, ldv;        // leading dimensions of the U / V bases (floats)
-    long long s_off, u_off, v_off, r_off;  // outputs: sigma, U, V, recon (elements)
+    double* sigma;             // outputs (device): k values, descending
+    float* U;                  // L x k, u_i at + i*L
+    float* V;                  // K x k, v_i at + i*K
+    float* recon;              // N x k, elementary series i at + i*N (may be null: no Hankelization)
+    int* info;                 // 4 ints: steps, converged, restarts, DGKS passes (may be null)
     long long o_ab, o_tw, o_u, o_v, o_r, o_alpha, o_beta, o_state, o_p, o_q, o_scr;  // in the region
     unsigned long long seed;   // start and restart vectors
     int L, k, transposed, dcap;  // user window, triples, L > K, Krylov cap
@@ -61,24 +67,20 @@ struct BSeries {
 };
 
 struct BatchArgs {
-    int nseries;
+    int nseries;               // workgroups of the launch (entries of list, if any)
+    const int* list;           // series (table slots) of the launch; null = 0 .. nseries-1
     const BSeries* tab;
-    const double* series;      // all series, concatenated (FP64)
     char* ws;                  // workspace base (series regions)
-    double* sigma;
-    float* U;
-    float* V;
-    float* recon;              // may be null
-    int* info;                 // [nseries * 4] steps, converged, restarts, DGKS passes (may be null)
-    unsigned* ndone;           // series finished so far
+    unsigned* ndone;           // series finished so far (may be null)
+    int* done_flags;           // per table slot: 1 once the series is finished (may be null)
     int check_every;
     double tol;
 };
 
 hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s);
-hipError_t launch_batch_conv(const BatchArgs& a, int j, int side, hipStream_t s);
-hipError_t launch_batch_cgs(const BatchArgs& a, int j, int side, hipStream_t s);
-hipError_t launch_batch_check(const BatchArgs& a, int j, hipStream_t s);
+hipError_t launch_batch_conv(const BatchArgs& a, int side, hipStream_t s);
+hipError_t launch_batch_cgs(const BatchArgs& a, int side, hipStream_t s);
+hipError_t launch_batch_check(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_hankel(const BatchArgs& a, hipStream_t s);
 size_t batch_lds_bytes();

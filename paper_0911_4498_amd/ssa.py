@@ -45,7 +45,9 @@ EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_t
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
             "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
-            "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy")
+            "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
+            "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
+            "ssa_server_status", "ssa_server_destroy")
 
 # kernel classes of ssa_batch_profile_read (enum ssa_batch_prof_class)
 BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
@@ -98,8 +100,18 @@ def load():
     lib.ssa_batch_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), ctypes.POINTER(ctypes.c_double)]
     lib.ssa_batch_destroy.argtypes = [_c_p]
     lib.ssa_batch_destroy.restype = None
+    lib.ssa_server_create.argtypes = [_c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts), _c_p,
+                                      ctypes.c_size_t, _c_p, ctypes.POINTER(_c_p)]
+    lib.ssa_server_request_bytes.argtypes = [_c_p, _c_ll, _c_ll, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ssa_server_submit.argtypes = [_c_p, _c_ll, ctypes.c_ulonglong, _c_p, _c_ll, _c_ll, ctypes.c_int, _c_p, _c_p,
+                                      _c_p, _c_p, _c_p]
+    lib.ssa_server_step.argtypes = [_c_p, ctypes.POINTER(_c_ll), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.ssa_server_status.argtypes = [_c_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]
+    lib.ssa_server_destroy.argtypes = [_c_p]
+    lib.ssa_server_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("ssa_plan_destroy", "ssa_status_str", "ssa_batch_destroy"):
+        if name not in ("ssa_plan_destroy", "ssa_status_str", "ssa_batch_destroy", "ssa_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -377,3 +389,79 @@ class Batch:
             vo += Ks * ks
             ro += Ns * ks
         return out
+
+
+class Server:
+    """Continuous batching of SSA requests (``ssa_server_*``): a device pool of
+    ``pool_bytes`` (the HBM budget), ``slots`` requests in flight, one Lanczos step of
+    every admitted request per tick."""
+
+    def __init__(self, n_max: int, k_max: int, slots: int, pool_bytes: int, d_max: int = 0,
+                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.lib = lib
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.pool.data_ptr()
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), 0, 0)
+        h = _c_p()
+        _check(lib.ssa_server_create(int(n_max), int(k_max), int(slots), ctypes.byref(opts), base + (-base) % 256,
+                                     int(pool_bytes), self.stream.cuda_stream, ctypes.byref(h)), "ssa_server_create")
+        self._h = h
+        self.slots = int(slots)
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.ssa_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def request_bytes(self, N: int, L: int, k: int) -> int:
+        b = ctypes.c_size_t(0)
+        _check(self.lib.ssa_server_request_bytes(self._h, int(N), int(L), int(k), ctypes.byref(b)),
+               "ssa_server_request_bytes")
+        return int(b.value)
+
+    def submit(self, rid: int, f, L: int, k: int, key: int | None = None, recon: bool = True):
+        """Queue request ``rid``; returns its output tensors (valid once it completes)."""
+        torch = self._torch
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        N = int(f.numel())
+        K = N - int(L) + 1
+        out = {
+            "f": f,
+            "sigma": torch.empty(k, dtype=torch.float64, device=self.device),
+            "U": torch.empty((k, int(L)), dtype=torch.float32, device=self.device),
+            "V": torch.empty((k, K), dtype=torch.float32, device=self.device),
+            "recon": torch.empty((k, N), dtype=torch.float32, device=self.device) if recon else None,
+            "info": torch.zeros(4, dtype=torch.int32, device=self.device),
+        }
+        _check(self.lib.ssa_server_submit(self._h, int(rid), int(rid if key is None else key), f.data_ptr(), N,
+                                          int(L), int(k), out["sigma"].data_ptr(), out["U"].data_ptr(),
+                                          out["V"].data_ptr(), out["recon"].data_ptr() if recon else None,
+                                          out["info"].data_ptr()), "ssa_server_submit")
+        self._live[int(rid)] = out
+        return out
+
+    def step(self):
+        """One tick; returns the list of (id, outputs) completed."""
+        buf = (_c_ll * self.slots)()
+        n = ctypes.c_int(0)
+        _check(self.lib.ssa_server_step(self._h, buf, self.slots, ctypes.byref(n)), "ssa_server_step")
+        return [(int(buf[i]), self._live.pop(int(buf[i]))) for i in range(n.value)]
+
+    def status(self):
+        q, a, f = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        free = ctypes.c_size_t(0)
+        _check(self.lib.ssa_server_status(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(f),
+                                          ctypes.byref(free)), "ssa_server_status")
+        return {"queued": q.value, "active": a.value, "finalizing": f.value, "pool_free": int(free.value)}
