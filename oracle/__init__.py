@@ -67,6 +67,7 @@ def _bind(lib):
     _LP = ctypes.POINTER(ctypes.c_long)
     lib.oracle_matvec_rows.argtypes = [_D, _L, _L, ctypes.c_int, _D, _LP, _L, _D]
     lib.oracle_hankelize_at.argtypes = [ctypes.c_double, _D, _L, _D, _L, _LP, _L, _D]
+    lib.oracle_hmatrix.argtypes = [_D, _L, _L, _L, _L, _I, ctypes.c_int, _D]
     lib.oracle_lanczos_svd.argtypes = [_D, _L, _L, ctypes.c_int, ctypes.c_int, _D, _D,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        _D, _D, _D, _I]
@@ -225,6 +226,19 @@ def hankelize_at(sigma: float, u, v, pos) -> np.ndarray:
     if rc != 0:
         raise ValueError("invalid arguments")
     return out
+
+
+def hmatrix(f, B: int, T: int, L: int, I) -> np.ndarray:
+    """Structural-change detection: the H-matrix of heterogeneity indices g(base window i,
+    test window j), base windows of length B, test windows of length T, window L, I 1-based."""
+    f = _f64(f)
+    N = f.size
+    I = np.ascontiguousarray(I, dtype=np.int32)
+    G = np.empty((N - B + 1, N - T + 1))
+    rc = _load().oracle_hmatrix(_dp(f), N, B, T, L, I.ctypes.data_as(_I), I.size, _dp(G))
+    if rc < 0:
+        raise ValueError("invalid arguments")
+    return G
 
 
 def lanczos_svd(f, L: int, k: int, p0, d_max: int | None = None, restart=None,

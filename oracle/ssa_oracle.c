@@ -307,6 +307,61 @@ int oracle_hankelize_at(double sigma, const double* u, long L, const double* v, 
     return 0;
 }
 
+/*
+ * Structural-change detection (Sec. "Detection of Structural Changes", eq. g):
+ * the heterogeneity index of a test series F2 against a base series F1 is
+ *   g = sum_j dist^2(X2_j, span{U1_i, i in I}) / sum_j |X2_j|^2,
+ * over the L-lagged vectors X2_j of F2 (j < T - L + 1), with U1_i the
+ * eigenvectors of the trajectory matrix of F1 (window L).  The H-matrix holds
+ * g for base windows f[i .. i+B-1] and test windows f[j .. j+T-1] (0-based
+ * starts i < N-B+1, j < N-T+1), row-major, G[i * (N-T+1) + j].  I holds
+ * 1-based triple indices.  A test window with no energy gets g = 0.
+ * Each dist^2 is ||X - sum_i (U_i^T X) U_i||^2 evaluated as written.
+ */
+int oracle_hmatrix(const double* f, long N, long B, long T, long L, const int* I, int nI, double* G) {
+    if (nI < 1 || B > N || T > N || L <= 1 || L >= B - 1 || L > T) return -1;
+    int k = 0;
+    for (int q = 0; q < nI; ++q) {
+        if (I[q] < 1 || I[q] > L) return -1;
+        if (I[q] > k) k = I[q];
+    }
+    const long MB = N - B + 1, MT = N - T + 1, K2 = T - L + 1;
+    if (k > (B - L + 1 < L ? B - L + 1 : L)) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < MB; ++i) {
+        double* sg = (double*)malloc(sizeof(double) * k);
+        double* U = (double*)malloc(sizeof(double) * L * k);
+        double* V = (double*)malloc(sizeof(double) * (B - L + 1) * k);
+        double* x = (double*)malloc(sizeof(double) * L);
+        if (!sg || !U || !V || !x || oracle_ssa_dense(f + i, B, L, k, sg, U, V) < 0) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+            for (long j = 0; j < MT; ++j) {
+                double num = 0.0, den = 0.0;
+                for (long m = 0; m < K2; ++m) {
+                    const double* X = f + j + m;  /* lagged vector m of the test window */
+                    for (long l = 0; l < L; ++l) x[l] = X[l];
+                    for (int q = 0; q < nI; ++q) {
+                        const int c = I[q] - 1;
+                        double p = 0.0;
+                        for (long l = 0; l < L; ++l) p += U[l * k + c] * X[l];
+                        for (long l = 0; l < L; ++l) x[l] -= p * U[l * k + c];
+                    }
+                    for (long l = 0; l < L; ++l) {
+                        num += x[l] * x[l];
+                        den += X[l] * X[l];
+                    }
+                }
+                G[i * MT + j] = den > 0.0 ? num / den : 0.0;
+            }
+        }
+        free(sg); free(U); free(V); free(x);
+    }
+    return bad ? -3 : 0;
+}
+
 /* Modified Gram-Schmidt of x (length n) against ncol orthonormal columns
  * stored contiguously in Q (column c at Q + c*n). */
 static void mgs(double* x, const double* Q, long ncol, long n) {

@@ -129,6 +129,15 @@ def c5_series(N: int = 2**24, seed: int = SEED_C5) -> np.ndarray:
     return f
 
 
+def hmatrix_series(N: int = 400, Q: int = 200, seed: int = 1006) -> np.ndarray:
+    """The structural-change example series: sin(2 pi n / 10) before n = Q, sin(2 pi n / 10.5)
+    from n = Q on, plus 0.01 white noise (n = 1..N)."""
+    rng = np.random.default_rng(seed)
+    n = _t(N)
+    f = np.where(n < Q, np.sin(2 * np.pi * n / 10.0), np.sin(2 * np.pi * n / 10.5))
+    return f + 0.01 * rng.normal(0.0, 1.0, N)
+
+
 # --- structured test signals -------------------------------------------------
 
 def sinusoid(N: int, period: float, amp: float = 1.0, phase: float = 0.0) -> np.ndarray:

@@ -300,6 +300,59 @@ def test_hankelize_at_matches_explicit_antidiagonals():
         oracle.hankelize_at(1.0, u, v, np.array([L + K - 1]))
 
 
+# --- structural-change detection: heterogeneity index and H-matrix ---------------
+
+def _hmatrix_numpy(f, B, T, L, I):
+    """Independent statement of eq. g: numpy's SVD of each base trajectory matrix, the
+    test window's lagged vectors as columns, projections by matrix products."""
+    N = len(f)
+    G = np.zeros((N - B + 1, N - T + 1))
+    for i in range(N - B + 1):
+        Xb = hankel_lib(f[i:i + B], L)
+        Ub = np.linalg.svd(Xb)[0][:, [c - 1 for c in I]]
+        for j in range(N - T + 1):
+            Xt = hankel_lib(f[j:j + T], L)
+            R = Xt - Ub @ (Ub.T @ Xt)
+            den = (Xt ** 2).sum()
+            G[i, j] = (R ** 2).sum() / den if den > 0 else 0.0
+    return G
+
+
+@pytest.mark.parametrize("N,B,T,L,I", [(30, 12, 9, 5, [1, 3]), (25, 10, 10, 4, [2]), (40, 20, 6, 6, [1, 2, 4])])
+def test_hmatrix_matches_numpy(N, B, T, L, I):
+    f = inputs.white(N, N + B) + inputs.sinusoid(N, 7.0, 2.0)
+    np.testing.assert_allclose(oracle.hmatrix(f, B, T, L, I), _hmatrix_numpy(f, B, T, L, I), atol=1e-12)
+
+
+def test_hmatrix_closed_forms():
+    """No change in structure: a pure sinusoid lies in its own 2-D lagged subspace, so g = 0;
+    the full index set spans R^L, so g = 0 for any series; 0 <= g <= 1 always."""
+    N = 120
+    f = inputs.sinusoid(N, 10.0, 1.5, 0.3)
+    G = oracle.hmatrix(f, 40, 30, 12, [1, 2])
+    assert np.abs(G).max() < 1e-20
+    w = inputs.white(N, 3)
+    G = oracle.hmatrix(w, 40, 30, 12, list(range(1, 13)))
+    assert np.abs(G).max() < 1e-20
+    G = oracle.hmatrix(w, 40, 30, 12, [1])
+    assert G.min() >= 0.0 and G.max() <= 1.0
+    z = np.zeros(N)
+    z[:50] = w[:50]
+    G = oracle.hmatrix(z, 40, 30, 12, [1])  # test windows of zeros have g = 0 by convention
+    assert np.all(G[:, 60:] == 0.0)
+    with pytest.raises(ValueError):
+        oracle.hmatrix(w, 40, 30, 39, [1])  # L must be below B - 1
+
+
+def test_hmatrix_detects_the_change_point():
+    """The paper's example: a frequency change at Q = 200 makes g large exactly for pairs of
+    windows on opposite sides of the change and small on the same side."""
+    f = inputs.hmatrix_series(400, 200, 5)
+    G = oracle.hmatrix(f, 100, 100, 50, [1, 2])
+    assert G[0, 0] < 1e-3 and G[-1, -1] < 1e-3
+    assert G[0, -1] > 0.1 and G[-1, 0] > 0.1
+
+
 # --- tier B: Lanczos with full reorthogonalization -------------------------------
 
 def test_gkl_relations():

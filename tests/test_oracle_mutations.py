@@ -38,6 +38,9 @@ MUTATIONS = {
     "hankelize_at_count_dropped_end": (
         "out[q] = sigma * acc / (double)(a1 - a0 + 1);", "out[q] = sigma * acc / (double)(a1 - a0);",
         [pins.test_hankelize_at_matches_explicit_antidiagonals]),
+    "hmatrix_lagged_vectors_of_base": (
+        "const double* X = f + j + m;", "const double* X = f + i + m;",
+        [lambda: pins.test_hmatrix_matches_numpy(30, 12, 9, 5, [1, 3])]),
     "trajectory_shifted": (
         "X[i * K + j] = f[i + j];", "X[i * K + j] = f[i + j + (i + j + 1 < N)];",
         [pins.test_trajectory_matches_library_hankel]),
