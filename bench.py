@@ -338,6 +338,55 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_hmatrix(args):
+    """Structural-change detection: H-matrix time on the GPU (base-window SSAs on the batched
+    path) against the CPU oracle, for the paper's comparison shape Q = N/2, B = T = N/4,
+    L = B/2, I = {1, 2}."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_0911_4498_amd import inputs, ssa
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in args.hm_sizes.split(",")]
+    rows = []
+    for N in sizes:
+        B = T = N // 4
+        L = B // 2
+        f = inputs.hmatrix_series(N, N // 2, 5)
+        fd = torch.tensor(f, device=dev)
+        ssa.hmatrix(fd, B, T, L, [1, 2])  # warm-up
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G = ssa.hmatrix(fd, B, T, L, [1, 2])
+        torch.cuda.synchronize()
+        t_gpu = (time.perf_counter() - t0) / reps
+        row = {"N": N, "B": B, "T": T, "L": L, "windows": N - B + 1, "gpu_s": t_gpu}
+        if N <= args.hm_oracle_max:
+            t0 = time.perf_counter()
+            ref = oracle.hmatrix(f, B, T, L, [1, 2])
+            row["oracle_s"] = time.perf_counter() - t0
+            row["oracle_cores"] = oracle.num_threads()
+            row["max_abs_err_vs_oracle"] = float(np.abs(G.cpu().numpy() - ref).max())
+        print(f"# N={N}: {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+    out = {
+        "metric": "H-matrix time (structural-change detection)",
+        "value": rows[-1]["gpu_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "frequency change at Q = N/2 (period 10 -> 10.5) + 0.01 white noise; "
+                               "B = T = N/4, L = B/2, I = {1, 2}"},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,7 +394,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
-    ap.add_argument("--workload", choices=("single", "many", "served"), default="single")
+    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix"), default="single")
+    ap.add_argument("--hm-sizes", default="400,1000,4000,8000", help="series lengths of the H-matrix workload")
+    ap.add_argument("--hm-oracle-max", type=int, default=1000, help="largest N timed with the CPU oracle")
     ap.add_argument("--rates", default="100,1000", help="request rates of the served stream (req/s)")
     ap.add_argument("--requests", type=int, default=200, help="requests per rate (served stream)")
     ap.add_argument("--slots", type=int, default=256, help="server slots (served stream)")
@@ -359,12 +410,12 @@ def main():
               "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload in ("many", "served"):
+    if args.workload in ("many", "served", "hmatrix"):
         from paper_0911_4498_amd import ssa as _ssa
         if not os.path.exists(_ssa.LIB_PATH):
             import __graft_entry__
             __graft_entry__.build()
-        return bench_many(args) if args.workload == "many" else bench_served(args)
+        return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix}[args.workload](args)
 
     import numpy as np
     import torch

@@ -291,6 +291,28 @@ int ssa_server_status(ssa_server server, int* queued, int* active, int* finalizi
 /* ssa_server_destroy -- free the host-side server (waits for its stream). */
 void ssa_server_destroy(ssa_server server);
 
+/*
+ * Structural-change detection (the H-matrix of Sec. "Detection of Structural
+ * Changes", eq. g).  G[i * (N-T+1) + j] (row-major, FP64) is the
+ * heterogeneity index of test window f[j .. j+T-1] against the eigenvector
+ * span {U_i, i in I} of base window f[i .. i+B-1] (window length L): the share
+ * of the test window's lagged-vector energy outside that span.  The base
+ * windows' SSAs run together on the batched path.  I: host array of nI
+ * 1-based triple indices, each <= 32.  Limits: L < B - 1, L <= T,
+ * B <= 20480, B, T <= N, nI*L + L + 256 <= 40960.
+ */
+int ssa_hmatrix_workspace(long long N, long long B, long long T, long long L, const int* I, int nI,
+                          size_t* bytes);
+
+/*
+ * ssa_hmatrix -- the H-matrix of series_dev (N FP64 values, device) into G_dev
+ * ((N-B+1) x (N-T+1) doubles, device).  workspace_dev: 256-byte aligned, at
+ * least ssa_hmatrix_workspace bytes.  Returns when G is complete.  Errors:
+ * SSA_EINVAL, SSA_ENOMEM (workspace too small), SSA_EDEVICE.
+ */
+int ssa_hmatrix(const double* series_dev, long long N, long long B, long long T, long long L, const int* I,
+                int nI, void* workspace_dev, size_t bytes, void* hip_stream, double* G_dev);
+
 /* ssa_plan_describe -- copy the plan's sizes into *desc. */
 int ssa_plan_describe(ssa_plan plan, ssa_plan_desc* desc);
 

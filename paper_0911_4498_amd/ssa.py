@@ -47,7 +47,7 @@ EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_t
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
             "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
             "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
-            "ssa_server_status", "ssa_server_destroy")
+            "ssa_server_status", "ssa_server_destroy", "ssa_hmatrix_workspace", "ssa_hmatrix")
 
 # kernel classes of ssa_batch_profile_read (enum ssa_batch_prof_class)
 BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
@@ -108,6 +108,10 @@ def load():
     lib.ssa_server_step.argtypes = [_c_p, ctypes.POINTER(_c_ll), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.ssa_server_status.argtypes = [_c_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]
+    lib.ssa_hmatrix_workspace.argtypes = [_c_ll, _c_ll, _c_ll, _c_ll, _c_p, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+    lib.ssa_hmatrix.argtypes = [_c_p, _c_ll, _c_ll, _c_ll, _c_ll, _c_p, ctypes.c_int, _c_p, ctypes.c_size_t, _c_p,
+                                _c_p]
     lib.ssa_server_destroy.argtypes = [_c_p]
     lib.ssa_server_destroy.restype = None
     for name in EXPORTED:
@@ -465,3 +469,26 @@ class Server:
         _check(self.lib.ssa_server_status(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(f),
                                           ctypes.byref(free)), "ssa_server_status")
         return {"queued": q.value, "active": a.value, "finalizing": f.value, "pool_free": int(free.value)}
+
+
+def hmatrix(f, B: int, T: int, L: int, I, device=None, stream=None):
+    """H-matrix of heterogeneity indices (structural-change detection) of a series on the
+    GPU: base windows of length B, test windows of length T, window L, 1-based index set I.
+    Returns an (N-B+1, N-T+1) FP64 tensor."""
+    import numpy as np
+    import torch
+    lib = load()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    f = torch.as_tensor(f, dtype=torch.float64, device=dev).reshape(-1).contiguous()
+    N = int(f.numel())
+    Ia = np.ascontiguousarray(np.asarray(I, dtype=np.int32))
+    need = ctypes.c_size_t(0)
+    _check(lib.ssa_hmatrix_workspace(N, int(B), int(T), int(L), Ia.ctypes.data, Ia.size, ctypes.byref(need)),
+           "ssa_hmatrix_workspace")
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    G = torch.empty((N - int(B) + 1, N - int(T) + 1), dtype=torch.float64, device=dev)
+    _check(lib.ssa_hmatrix(f.data_ptr(), N, int(B), int(T), int(L), Ia.ctypes.data, Ia.size, base + (-base) % 256,
+                           int(need.value), st.cuda_stream, G.data_ptr()), "ssa_hmatrix")
+    return G

@@ -215,3 +215,22 @@ def test_bidiag_ritz_clustered_and_zero_entries():
     np.testing.assert_allclose(om, s_ref[:k], rtol=1e-12)
     np.testing.assert_allclose(Q.T @ Q, np.eye(k), atol=1e-10)
     np.testing.assert_allclose(B @ Q, P * om, atol=1e-10)
+
+
+def test_hmatrix_workspace_validation():
+    """The H-matrix entry point checks its window sizes and index set on the host."""
+    lib = _built()
+    need = ctypes.c_size_t(0)
+
+    def ws(N, B, T, L, I):
+        Ia = (ctypes.c_int * len(I))(*I)
+        return lib.ssa_hmatrix_workspace(N, B, T, L, Ia, len(I), ctypes.byref(need))
+
+    assert ws(400, 100, 100, 50, [1, 2]) == 0 and need.value > 0
+    small = need.value
+    assert ws(800, 200, 200, 100, [1, 2]) == 0 and need.value > small
+    assert ws(400, 100, 100, 99, [1, 2]) == ssa.SSA_EINVAL   # L must be below B - 1
+    assert ws(400, 100, 40, 50, [1, 2]) == ssa.SSA_EINVAL    # L must not exceed T
+    assert ws(400, 100, 100, 50, [0]) == ssa.SSA_EINVAL      # 1-based indices
+    assert ws(400, 100, 100, 50, [33]) == ssa.SSA_EINVAL     # at most 32 triples
+    assert ws(400, 500, 100, 50, [1]) == ssa.SSA_EINVAL      # base window longer than the series
