@@ -68,6 +68,7 @@ def _bind(lib):
     lib.oracle_matvec_rows.argtypes = [_D, _L, _L, ctypes.c_int, _D, _LP, _L, _D]
     lib.oracle_hankelize_at.argtypes = [ctypes.c_double, _D, _L, _D, _L, _LP, _L, _D]
     lib.oracle_hmatrix.argtypes = [_D, _L, _L, _L, _L, _I, ctypes.c_int, _D]
+    lib.oracle_realization_stats.argtypes = [_D, _L, _L, _L, ctypes.c_int, _D, _D, _D, _D]
     lib.oracle_lanczos_svd.argtypes = [_D, _L, _L, ctypes.c_int, ctypes.c_int, _D, _D,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        _D, _D, _D, _I]
@@ -239,6 +240,22 @@ def hmatrix(f, B: int, T: int, L: int, I) -> np.ndarray:
     if rc < 0:
         raise ValueError("invalid arguments")
     return G
+
+
+def realization_stats(F, L: int, d: int, truth=None):
+    """Repeated realizations: per point mean and (R-1)-normalized variance of the rank-d
+    reconstructions of the rows of F, and their mean square error against truth."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    R, N = F.shape
+    mean = np.empty(N)
+    var = np.empty(N)
+    mse = np.empty(N) if truth is not None else None
+    tr = _f64(truth) if truth is not None else None
+    rc = _load().oracle_realization_stats(_dp(F), R, N, L, d, _dp(tr) if tr is not None else None, _dp(mean),
+                                          _dp(var), _dp(mse) if mse is not None else None)
+    if rc < 0:
+        raise ValueError("invalid arguments")
+    return mean, var, mse
 
 
 def lanczos_svd(f, L: int, k: int, p0, d_max: int | None = None, restart=None,

@@ -362,6 +362,62 @@ int oracle_hmatrix(const double* f, long N, long B, long T, long L, const int* I
     return bad ? -3 : 0;
 }
 
+/*
+ * Repeated realizations (Sec. "Bootstrap Confidence Intervals Construction"):
+ * each of the R series F_r (row r of F_all, N values) is reconstructed from
+ * its first d eigentriples (window L, Sec. 2.3-2.4 with the group {1..d}),
+ * G_r; then per point n
+ *   mean[n] = (1/R) sum_r G_r[n],
+ *   var[n]  = (1/(R-1)) sum_r (G_r[n] - mean[n])^2   (0 when R = 1),
+ *   mse[n]  = (1/R) sum_r (G_r[n] - truth[n])^2      (if truth and mse are given).
+ */
+int oracle_realization_stats(const double* F_all, long R, long N, long L, int d, const double* truth,
+                             double* mean, double* var, double* mse) {
+    if (R < 1 || N <= 2 || L <= 1 || L >= N || d < 1) return -1;
+    const long K = N - L + 1;
+    if (d > (L < K ? L : K)) return -1;
+    double* G = (double*)malloc(sizeof(double) * R * N);
+    if (!G) return -3;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long r = 0; r < R; ++r) {
+        double* sg = (double*)malloc(sizeof(double) * d);
+        double* U = (double*)malloc(sizeof(double) * L * d);
+        double* V = (double*)malloc(sizeof(double) * K * d);
+        int offs[2] = {0, d};
+        int* mem = (int*)malloc(sizeof(int) * d);
+        if (!sg || !U || !V || !mem || oracle_ssa_dense(F_all + r * N, N, L, d, sg, U, V) < 0) {
+#pragma omp atomic write
+            bad = 1;
+        } else {
+            for (int c = 0; c < d; ++c) mem[c] = c;
+            if (oracle_reconstruct(N, L, d, sg, U, V, offs, mem, 1, G + r * N) < 0) {
+#pragma omp atomic write
+                bad = 1;
+            }
+        }
+        free(sg); free(U); free(V); free(mem);
+    }
+    if (!bad) {
+        for (long n = 0; n < N; ++n) {
+            double m = 0.0;
+            for (long r = 0; r < R; ++r) m += G[r * N + n];
+            m /= (double)R;
+            double v = 0.0, e = 0.0;
+            for (long r = 0; r < R; ++r) {
+                const double x = G[r * N + n];
+                v += (x - m) * (x - m);
+                if (truth) e += (x - truth[n]) * (x - truth[n]);
+            }
+            mean[n] = m;
+            var[n] = R > 1 ? v / (double)(R - 1) : 0.0;
+            if (truth && mse) mse[n] = e / (double)R;
+        }
+    }
+    free(G);
+    return bad ? -3 : 0;
+}
+
 /* Modified Gram-Schmidt of x (length n) against ncol orthonormal columns
  * stored contiguously in Q (column c at Q + c*n). */
 static void mgs(double* x, const double* Q, long ncol, long n) {

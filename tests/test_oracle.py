@@ -353,6 +353,42 @@ def test_hmatrix_detects_the_change_point():
     assert G[0, -1] > 0.1 and G[-1, 0] > 0.1
 
 
+# --- repeated realizations ------------------------------------------------------
+
+def test_realization_stats_match_numpy():
+    """Independent statement: numpy SVD of each explicit trajectory matrix, the rank-d part
+    averaged over antidiagonals with numpy, then numpy's mean and (ddof=1) variance."""
+    rng = np.random.default_rng(12)
+    N, L, d, R = 60, 25, 3, 5
+    F = inputs.rank5_example(N) + 0.5 * rng.normal(size=(R, N))
+    G = []
+    for r in range(R):
+        X = hankel_lib(F[r], L)
+        Uu, s, Vt = np.linalg.svd(X, full_matrices=False)
+        Y = (Uu[:, :d] * s[:d]) @ Vt[:d]
+        flipped = np.fliplr(Y)
+        G.append([np.diagonal(flipped, offset=(N - L) - n).mean() for n in range(N)])
+    G = np.array(G)
+    truth = inputs.rank5_example(N)
+    mean, var, mse = oracle.realization_stats(F, L, d, truth)
+    np.testing.assert_allclose(mean, G.mean(axis=0), atol=1e-11)
+    np.testing.assert_allclose(var, G.var(axis=0, ddof=1), atol=1e-11)
+    np.testing.assert_allclose(mse, ((G - truth) ** 2).mean(axis=0), atol=1e-11)
+
+
+def test_realization_stats_noise_free_finite_rank():
+    """Noise-free copies of a rank-5 series reconstructed from 5 triples give the series
+    itself: zero variance and zero error (the paper's finite-rank setting)."""
+    N, L = 200, 100
+    f = inputs.rank5_example(N)
+    F = np.tile(f, (4, 1))
+    mean, var, mse = oracle.realization_stats(F, L, 5, f)
+    np.testing.assert_allclose(mean, f, atol=1e-10)
+    assert np.abs(var).max() < 1e-20 and np.abs(mse).max() < 1e-20
+    with pytest.raises(ValueError):
+        oracle.realization_stats(F, L, 0)
+
+
 # --- tier B: Lanczos with full reorthogonalization -------------------------------
 
 def test_gkl_relations():

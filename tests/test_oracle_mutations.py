@@ -41,6 +41,9 @@ MUTATIONS = {
     "hmatrix_lagged_vectors_of_base": (
         "const double* X = f + j + m;", "const double* X = f + i + m;",
         [lambda: pins.test_hmatrix_matches_numpy(30, 12, 9, 5, [1, 3])]),
+    "realization_variance_biased": (
+        "var[n] = R > 1 ? v / (double)(R - 1) : 0.0;", "var[n] = R > 1 ? v / (double)R : 0.0;",
+        [pins.test_realization_stats_match_numpy]),
     "trajectory_shifted": (
         "X[i * K + j] = f[i + j];", "X[i * K + j] = f[i + j + (i + j + 1 < N)];",
         [pins.test_trajectory_matches_library_hankel]),
