@@ -387,6 +387,53 @@ def bench_hmatrix(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_realizations(args):
+    """Repeated realizations (the paper's bootstrap setting): rank-5 series, sigma = 5 white
+    noise, L = N/2, rank-5 reconstructions of R realizations; GPU time against the CPU oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_0911_4498_amd import inputs, ssa
+    dev = torch.device("cuda:0")
+    rows = []
+    R = args.realizations
+    for N in [int(x) for x in args.rs_sizes.split(",")]:
+        L = N // 2
+        f = inputs.rank5_example(N)
+        F = f + 5.0 * np.stack([inputs.white(N, 100 + r) for r in range(R)])
+        Fd = torch.tensor(F, device=dev)
+        ssa.realizations(Fd, L, 5, truth=f)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mean, var, mse = ssa.realizations(Fd, L, 5, truth=f)
+        torch.cuda.synchronize()
+        row = {"N": N, "L": L, "R": R, "gpu_s": time.perf_counter() - t0,
+               "mean_abs_bias": float(np.abs(mean.cpu().numpy() - f).mean()),
+               "mean_var": float(var.mean().item()), "mean_mse": float(mse.mean().item())}
+        if N <= args.rs_oracle_max:
+            t0 = time.perf_counter()
+            rm, rv, re = oracle.realization_stats(F, L, 5, f)
+            row["oracle_s"] = time.perf_counter() - t0
+            row["oracle_cores"] = oracle.num_threads()
+            row["max_mean_diff_vs_oracle"] = float(np.abs(mean.cpu().numpy() - rm).max())
+        print(f"# N={N}: {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+    out = {
+        "metric": "repeated-realization SSA time",
+        "value": rows[-1]["gpu_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{R} realizations of the rank-5 series + N(0, 5^2) noise, L = N/2, "
+                               "rank-5 reconstruction, per-point mean / variance / MSE"},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,7 +441,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
-    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix"), default="single")
+    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix", "realizations"), default="single")
+    ap.add_argument("--realizations", type=int, default=64, help="realizations per size (realizations workload)")
+    ap.add_argument("--rs-sizes", default="1000,4000,16000", help="series lengths (realizations workload)")
+    ap.add_argument("--rs-oracle-max", type=int, default=1000, help="largest N timed with the CPU oracle")
     ap.add_argument("--hm-sizes", default="400,1000,4000,8000", help="series lengths of the H-matrix workload")
     ap.add_argument("--hm-oracle-max", type=int, default=1000, help="largest N timed with the CPU oracle")
     ap.add_argument("--rates", default="100,1000", help="request rates of the served stream (req/s)")
@@ -410,12 +460,13 @@ def main():
               "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload in ("many", "served", "hmatrix"):
+    if args.workload in ("many", "served", "hmatrix", "realizations"):
         from paper_0911_4498_amd import ssa as _ssa
         if not os.path.exists(_ssa.LIB_PATH):
             import __graft_entry__
             __graft_entry__.build()
-        return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix}[args.workload](args)
+        return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix,
+                "realizations": bench_realizations}[args.workload](args)
 
     import numpy as np
     import torch

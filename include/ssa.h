@@ -313,6 +313,23 @@ int ssa_hmatrix_workspace(long long N, long long B, long long T, long long L, co
 int ssa_hmatrix(const double* series_dev, long long N, long long B, long long T, long long L, const int* I,
                 int nI, void* workspace_dev, size_t bytes, void* hip_stream, double* G_dev);
 
+/*
+ * Repeated realizations (Sec. "Bootstrap Confidence Intervals Construction").
+ * series_dev holds R realizations of length N (row r at + r*N, FP64, device).
+ * Each is reconstructed from its first d eigentriples, with window L
+ * (Sec. 2.3-2.4, group {1..d}), on the batched path.  Per point n:
+ *   mean_dev[n] = mean over r of G_r[n];
+ *   var_dev[n]  = (R-1)-normalized variance;
+ *   mse_dev[n]  = mean square error against truth_dev (optional: both NULL or both given).
+ * A bootstrap confidence interval for the mean reconstruction follows as
+ * mean +- z sqrt(var / R).  Limits: N <= 20480, d <= 32, d <= min(L, K).
+ * Returns when the statistics are complete.
+ */
+int ssa_realizations_workspace(long long R, long long N, long long L, int d, size_t* bytes);
+int ssa_realizations(const double* series_dev, long long R, long long N, long long L, int d,
+                     const double* truth_dev, void* workspace_dev, size_t bytes, void* hip_stream,
+                     double* mean_dev, double* var_dev, double* mse_dev);
+
 /* ssa_plan_describe -- copy the plan's sizes into *desc. */
 int ssa_plan_describe(ssa_plan plan, ssa_plan_desc* desc);
 

@@ -47,7 +47,8 @@ EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_t
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
             "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
             "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
-            "ssa_server_status", "ssa_server_destroy", "ssa_hmatrix_workspace", "ssa_hmatrix")
+            "ssa_server_status", "ssa_server_destroy", "ssa_hmatrix_workspace", "ssa_hmatrix",
+            "ssa_realizations_workspace", "ssa_realizations")
 
 # kernel classes of ssa_batch_profile_read (enum ssa_batch_prof_class)
 BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
@@ -112,6 +113,9 @@ def load():
                                           ctypes.POINTER(ctypes.c_size_t)]
     lib.ssa_hmatrix.argtypes = [_c_p, _c_ll, _c_ll, _c_ll, _c_ll, _c_p, ctypes.c_int, _c_p, ctypes.c_size_t, _c_p,
                                 _c_p]
+    lib.ssa_realizations_workspace.argtypes = [_c_ll, _c_ll, _c_ll, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ssa_realizations.argtypes = [_c_p, _c_ll, _c_ll, _c_ll, ctypes.c_int, _c_p, _c_p, ctypes.c_size_t, _c_p,
+                                     _c_p, _c_p, _c_p]
     lib.ssa_server_destroy.argtypes = [_c_p]
     lib.ssa_server_destroy.restype = None
     for name in EXPORTED:
@@ -492,3 +496,26 @@ def hmatrix(f, B: int, T: int, L: int, I, device=None, stream=None):
     _check(lib.ssa_hmatrix(f.data_ptr(), N, int(B), int(T), int(L), Ia.ctypes.data, Ia.size, base + (-base) % 256,
                            int(need.value), st.cuda_stream, G.data_ptr()), "ssa_hmatrix")
     return G
+
+
+def realizations(F, L: int, d: int, truth=None, device=None, stream=None):
+    """Repeated realizations on the GPU: rows of F (R x N) reconstructed from their first d
+    eigentriples; returns (mean, var, mse or None) per point as FP64 tensors."""
+    import torch
+    lib = load()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    F = torch.as_tensor(F, dtype=torch.float64, device=dev).contiguous()
+    R, N = F.shape
+    need = ctypes.c_size_t(0)
+    _check(lib.ssa_realizations_workspace(R, N, int(L), int(d), ctypes.byref(need)), "ssa_realizations_workspace")
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    mean = torch.empty(N, dtype=torch.float64, device=dev)
+    var = torch.empty(N, dtype=torch.float64, device=dev)
+    tr = torch.as_tensor(truth, dtype=torch.float64, device=dev).contiguous() if truth is not None else None
+    mse = torch.empty(N, dtype=torch.float64, device=dev) if truth is not None else None
+    _check(lib.ssa_realizations(F.data_ptr(), R, N, int(L), int(d), tr.data_ptr() if tr is not None else None,
+                                base + (-base) % 256, int(need.value), st.cuda_stream, mean.data_ptr(),
+                                var.data_ptr(), mse.data_ptr() if mse is not None else None), "ssa_realizations")
+    return mean, var, mse

@@ -234,3 +234,13 @@ def test_hmatrix_workspace_validation():
     assert ws(400, 100, 100, 50, [0]) == ssa.SSA_EINVAL      # 1-based indices
     assert ws(400, 100, 100, 50, [33]) == ssa.SSA_EINVAL     # at most 32 triples
     assert ws(400, 500, 100, 50, [1]) == ssa.SSA_EINVAL      # base window longer than the series
+
+
+def test_realizations_workspace_validation():
+    lib = _built()
+    need = ctypes.c_size_t(0)
+    assert lib.ssa_realizations_workspace(64, 1000, 500, 5, ctypes.byref(need)) == 0 and need.value > 0
+    assert lib.ssa_realizations_workspace(64, 1000, 500, 0, ctypes.byref(need)) == ssa.SSA_EINVAL
+    assert lib.ssa_realizations_workspace(64, 1000, 1000, 5, ctypes.byref(need)) == ssa.SSA_EINVAL
+    assert lib.ssa_realizations_workspace(64, 30000, 500, 5, ctypes.byref(need)) == ssa.SSA_EINVAL
+    assert lib.ssa_realizations_workspace(0, 1000, 500, 5, ctypes.byref(need)) == ssa.SSA_EINVAL
