@@ -61,17 +61,31 @@ typedef struct {
     int fft_m1;             /* FFT schedule override: first factor M1 of M/2 = M1*M2 (must
                                divide M/2, both factors <= 4096); 0 = automatic              */
     int fft_cb;             /* columns per workgroup in FFT passes 1 and 3 (1..64); 0 = auto */
+    int restart_keep;       /* thick restart (Sec. 3.3, restarting schemes): when the basis
+                               reaches d_max columns without convergence, keep this many
+                               Ritz pairs and continue, at most 64 times.  Needs
+                               k_max <= restart_keep <= d_max - 2 and d_max <= 512 (unless
+                               d_max >= min(L, K), when no restart can occur); 0 = off,
+                               the plain Algorithm 1 that stops at d_max.  Single-series
+                               solver only.                                               */
+    int reorth;             /* 0: full reorthogonalization of both bases (Sec. 3.2, FRO);
+                               1: one-sided (Simon and Zha): only the basis of length
+                               min(L, K) is reorthogonalized, the other keeps the
+                               three-term recurrence alone (half the Gram-Schmidt traffic).
+                               One-sided cannot be combined with restart_keep.            */
 } ssa_opts;
 
 /* Per-solve report, filled by ssa_truncated_svd. */
 typedef struct {
-    int steps;         /* Lanczos steps d whose bidiagonal B_d gave the result               */
+    int steps;         /* Lanczos steps d whose bidiagonal B_d gave the result (with thick
+                          restarts: all steps of all cycles)                                */
     int converged;     /* 1 if the stopping rule held, 0 if d_max was reached                */
     int restarts;      /* vanishing alpha/beta replaced by fresh random directions           */
     int dgks_passes;   /* second Gram-Schmidt passes triggered by the DGKS criterion          */
     int steps_run;     /* Lanczos steps executed (>= steps: the stopping test of one check
                           point overlaps the next steps, which are then discarded)           */
     double resid[64];  /* residual bounds alpha_{d+1} |P[d+1,i]| of the first min(k,64) triples */
+    int thick_restarts;/* restart cycles performed (ssa_opts.restart_keep)                   */
 } ssa_info;
 
 /* Sizes chosen by a plan (reported for tests and benchmarks). */
@@ -165,7 +179,8 @@ typedef struct ssa_batch_s* ssa_batch;
  * ssa_batch_plan -- host-side engine for up to max_series series per solve.
  * Each series has length 3 <= N <= n_max (n_max <= 20480) and up to
  * k_max <= 32 triples.  opts as for ssa_embed_plan; d_max is capped at 320;
- * fft_m1/fft_cb do not apply (each series' FFT is one workgroup's).
+ * fft_m1/fft_cb do not apply (each series' FFT is one workgroup's); reorth
+ * applies to every series; restart_keep must be 0.
  * *workspace_bytes: enough for max_series series of length n_max with
  * L = n_max/2 and k = k_max.  ssa_batch_workspace gives the exact figure for
  * given series.  Errors: SSA_EINVAL.
@@ -348,6 +363,17 @@ void ssa_plan_destroy(ssa_plan plan);
  */
 int ssa_bidiag_ritz(const double* alpha, const double* beta, int d, int k, double* omega,
                     double* resid, double* P, double* Q);
+
+/*
+ * ssa_dense_ritz -- host utility (no device work): the k largest singular
+ * triples of a dense nr x nc matrix A (row-major, nr >= nc >= 1, k >= 1):
+ * omega (k, descending), P (nr x k row-major, left vectors), Q (nc x k
+ * row-major, right vectors); entries beyond min(k, nc) are zero.  Householder
+ * reduction to bidiagonal form, then the routine of ssa_bidiag_ritz.  The
+ * thick-restarted solver uses it for its projected matrix (an arrow block
+ * followed by a bidiagonal one).  Errors: SSA_EINVAL.
+ */
+int ssa_dense_ritz(const double* A, int nr, int nc, int k, double* omega, double* P, double* Q);
 
 /*
  * Profiling.  Kernel classes of the hot path, for ssa_profile_read:

@@ -24,6 +24,8 @@ constexpr int kMaxDmax = 1024;     // Krylov dimension cap supported by the kern
 constexpr double kBreakdownTol = 1e-6;  // relative size of a vanishing alpha/beta (FP32 products)
 constexpr double kResidFloor = 1e-5;    // residuals of omega_i < 1e-5 omega_1 are judged against 1e-5 omega_1
 constexpr int kMaxGroupBatch = 64;
+constexpr int kMaxRestartDmax = 512;  // basis cap of the restarted solver (host dense SVD per cycle)
+constexpr int kMaxCycles = 64;        // thick restarts before the solver gives up
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -75,6 +77,9 @@ struct ssa_plan_s {
     int transposed;     // L > K: solved for X^T (window K)
     long long Li, Ki;   // internal window / lag count, Li <= Ki
     int k_max, d_max, check_every;
+    int keep;   // thick restart: Ritz pairs kept per cycle (0: no restart)
+    int onesided;  // 1: only the length-Li basis (U) is reorthogonalized
+    int kcols;  // columns of the P/Q coefficient buffers: max(k_max, keep)
     double tol;
     unsigned long long seed;
     ConvGeom g;
@@ -82,7 +87,7 @@ struct ssa_plan_s {
     int pstride, nchunks_max;
     size_t ws_bytes;
     size_t o_ab, o_tw1, o_tw2, o_twlo, o_twhi, o_t1, o_t2, o_U, o_V, o_r, o_part, o_h, o_sc, o_alpha,
-        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2;
+        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2, o_rot;
     size_t grp_ints;
     // bound state
     char* ws = nullptr;
@@ -138,13 +143,14 @@ void layout(ssa_plan p) {
     p->o_alpha = take(sizeof(double) * (size_t)(p->d_max + 3));
     p->o_beta = take(sizeof(double) * (size_t)(p->d_max + 3));
     p->o_state = take(sizeof(double) * 8);
-    p->o_P = take(sizeof(double) * (size_t)(p->d_max + 1) * p->k_max);
-    p->o_Q = take(sizeof(double) * (size_t)p->d_max * p->k_max);
+    p->o_P = take(sizeof(double) * (size_t)(p->d_max + 1) * p->kcols);
+    p->o_Q = take(sizeof(double) * (size_t)p->d_max * p->kcols);
     p->o_flag = take(sizeof(int) * 64);
     p->grp_ints = (size_t)(kMaxGroupBatch + 1) + (size_t)kMaxGroupBatch * p->k_max;
     p->o_grp = take(sizeof(int) * p->grp_ints);
     p->o_rt1 = take(sizeof(float2) * (size_t)g.Mp * 2 * p->k_max);
     p->o_rt2 = take(sizeof(float2) * (size_t)g.Mp * kMaxGroupBatch);
+    p->o_rot = take(sizeof(float) * (size_t)p->keep * std::max(p->ldU, p->ldV));
     p->ws_bytes = o;
 }
 
@@ -228,10 +234,10 @@ int convolve(ssa_plan p, const ConvGeom& g, const float* x, long long n_in, floa
 }
 
 // Classical Gram-Schmidt of the residual r (length n) against `ncols` basis
-// columns, then the normalized vector becomes basis column `ncols`; the B
-// entry goes to *coef_out.
+// columns, then the normalized vector becomes basis column `out_col` (ncols
+// if negative); the B entry goes to *coef_out.
 int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long n, double* coef_out, int track,
-                   unsigned long long ctr) {
+                   unsigned long long ctr, int out_col = -1) {
     hipStream_t s = p->stream;
     float* r = at<float>(p, p->o_r);
     double* h = at<double>(p, p->o_h);
@@ -264,7 +270,8 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     }
     {
         ProfScope ps(p, SSA_PROF_UPDATE, 4.0 * (double)n * (ncols + 2));
-        SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, basis + (long long)ncols * ld, n, s));
+        SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, basis + (long long)(out_col < 0 ? ncols : out_col) * ld,
+                                  n, s));
     }
     return SSA_OK;
 }
@@ -328,6 +335,24 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, si
     p->check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
     p->tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
     p->seed = opts && opts->seed ? opts->seed : 1ULL;
+    p->keep = 0;
+    if (opts && opts->restart_keep > 0) {
+        // the whole Krylov space fits under the cap: no restart is ever needed
+        if (opts->restart_keep < k_max || (d_max < r && (opts->restart_keep + 2 > d_max || d_max > kMaxRestartDmax))) {
+            delete p;
+            return SSA_EINVAL;
+        }
+        if (d_max < r) p->keep = opts->restart_keep;
+    }
+    p->kcols = std::max(k_max, p->keep);
+    p->onesided = 0;
+    if (opts && opts->reorth != 0) {
+        if (opts->reorth != 1 || (opts->restart_keep > 0)) {
+            delete p;
+            return SSA_EINVAL;
+        }
+        p->onesided = 1;
+    }
     long long Mp;
     int M1, M2;
     if (!choose_fft(N, Mp, M1, M2)) {
@@ -384,7 +409,7 @@ int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_strea
     std::call_once(g_attr_once, [] { g_attr_err = set_kernel_attributes(); });
     if (g_attr_err != hipSuccess) return SSA_EDEVICE;
     if (!p->h_scal) {
-        const size_t nd = 4 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->k_max + p->k_max + 8;
+        const size_t nd = 4 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->kcols + p->k_max + 8;
         if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * nd, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
         if (hipHostMalloc((void**)&p->h_flag, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
@@ -449,8 +474,8 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     const size_t abn = (size_t)(p->d_max + 3);
     double* h_ab[2] = {p->h_scal, p->h_scal + 2 * abn};  // alpha | beta, double-buffered
     double* h_P = p->h_scal + 4 * abn;
-    double* h_Q = h_P + (size_t)(p->d_max + 1) * p->k_max;
-    double* h_sig = h_Q + (size_t)p->d_max * p->k_max;
+    double* h_Q = h_P + (size_t)(p->d_max + 1) * p->kcols;
+    double* h_sig = h_Q + (size_t)p->d_max * p->kcols;
     std::vector<double> w(k), wprev(k), res(k);
     bool have_prev = false, converged = false;
     int d = 0, steps_run = 0;
@@ -484,7 +509,8 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, Li, r,
                       j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
         if (rc != SSA_OK) return rc;
-        rc = orthonormalize(p, V, p->ldV, j - 1, Ki, alpha + j, 1, 2ULL * j);
+        // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
+        rc = orthonormalize(p, V, p->ldV, p->onesided ? 0 : j - 1, Ki, alpha + j, 1, 2ULL * j, j - 1);
         if (rc != SSA_OK) return rc;
         const int jj = j - 1;
         steps_run = jj;
@@ -517,23 +543,139 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     }
     const double* h_alpha = fin;
     const double* h_beta = fin + abn;
-
-    // Ritz triples of B_d: sigma, U_{d+1} P, V_d Q
-    bidiag_ritz_vectors(h_alpha, h_beta, d, k, h_sig, h_P, h_Q, p->work.data());
     double* dP = at<double>(p, p->o_P);
     double* dQ = at<double>(p, p->o_Q);
-    SSA_TRY(hipMemcpyAsync(dP, h_P, sizeof(double) * (size_t)(d + 1) * k, hipMemcpyHostToDevice, s));
-    SSA_TRY(hipMemcpyAsync(dQ, h_Q, sizeof(double) * (size_t)d * k, hipMemcpyHostToDevice, s));
+    int nu = d + 1, nc = d;  // the result is U_{nu} P (nu x k) and V_{nc} Q (nc x k)
+    int cycles = 0;
+
+    if (!converged && p->keep > 0 && d >= d_cap && d_cap < std::min(Li, Ki)) {
+        // Thick restart (augmented Lanczos bidiagonalization, Sec. 3.3 on restarting).
+        // With B = P Omega Q^T the SVD of the projected matrix and a the coefficient
+        // of the newest V column, the m leading Ritz vectors satisfy
+        //   X (V Q_m) = (U P_m) Omega_m,   X^T (U P_m) = (V Q_m) Omega_m + v_new rho^T,
+        // rho_i = a P[last, i].  The bases restart as U' = U P_m, V' = [V Q_m, v_new]; the
+        // projected matrix becomes diag(Omega_m) with rho as column m, and the recurrence
+        // continues from v_new (its first product's component along U' is rho, which the
+        // Gram-Schmidt step removes).  Every later step adds one bidiagonal pair, so each
+        // cycle ends with a square nc x nc problem, solved densely on the host.
+        const int m = p->keep;
+        const size_t cap = (size_t)p->d_max + 1;
+        const int kk = std::max(k, m);
+        std::vector<double> Bm(cap * cap, 0.0), Bc, om(kk), PA, QA;
+        for (int c = 0; c < d; ++c) {
+            Bm[(size_t)c * cap + c] = h_alpha[c + 1];
+            Bm[(size_t)(c + 1) * cap + c] = h_beta[c + 2];
+        }
+        double a_last = h_alpha[d + 1];
+        float* rot = at<float>(p, p->o_rot);
+        unsigned long long ctr = 2ULL * (unsigned long long)p->d_max + 8ULL;
+        struct Fill { int row, col, from_beta, idx; };
+        std::vector<Fill> fills;
+        for (;;) {
+            Bc.assign((size_t)nu * nc, 0.0);
+            for (int r0 = 0; r0 < nu; ++r0)
+                for (int c = 0; c < nc; ++c) Bc[(size_t)r0 * nc + c] = Bm[(size_t)r0 * cap + c];
+            PA.assign((size_t)nu * kk, 0.0);
+            QA.assign((size_t)nc * kk, 0.0);
+            dense_ritz(Bc.data(), nu, nc, kk, om.data(), PA.data(), QA.data());
+            if (cycles > 0) {  // cycle 0 is B_d, which the stopping test above has just rejected
+                bool ok = have_prev;
+                for (int i = 0; i < k; ++i) {
+                    w[i] = om[i];
+                    res[i] = std::fabs(a_last * PA[(size_t)(nu - 1) * kk + i]);
+                    const double scale = std::max(w[i], kResidFloor * om[0]);
+                    if (res[i] > p->tol * scale) ok = false;
+                    if (std::fabs(w[i] - wprev[i]) > 10.0 * p->tol * scale) ok = false;
+                }
+                wprev = w;
+                have_prev = true;
+                if (ok || cycles >= kMaxCycles) {
+                    converged = ok;
+                    break;
+                }
+            }
+            // rotate the bases: U' = U_{nu} P_m, V' = [V_{nc} Q_m, v_{nc+1}]
+            for (int r0 = 0; r0 < nu; ++r0)
+                for (int i = 0; i < m; ++i) h_P[(size_t)r0 * m + i] = PA[(size_t)r0 * kk + i];
+            for (int r0 = 0; r0 < nc; ++r0)
+                for (int i = 0; i < m; ++i) h_Q[(size_t)r0 * m + i] = QA[(size_t)r0 * kk + i];
+            SSA_TRY(hipMemcpyAsync(dP, h_P, sizeof(double) * (size_t)nu * m, hipMemcpyHostToDevice, s));
+            SSA_TRY(hipMemcpyAsync(dQ, h_Q, sizeof(double) * (size_t)nc * m, hipMemcpyHostToDevice, s));
+            {
+                ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + m) * ((m + 15) / 16));
+                SSA_TRY(launch_ritz(U, p->ldU, nu, dP, m, rot, p->ldU, Li, s));
+            }
+            SSA_TRY(hipMemcpyAsync(U, rot, sizeof(float) * (size_t)m * p->ldU, hipMemcpyDeviceToDevice, s));
+            {
+                ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + m) * ((m + 15) / 16));
+                SSA_TRY(launch_ritz(V, p->ldV, nc, dQ, m, rot, p->ldV, Ki, s));
+            }
+            // nc >= m + 2 (keep + 2 <= d_max), so columns nc and m are distinct
+            SSA_TRY(hipMemcpyAsync(V + (long long)m * p->ldV, V + (long long)nc * p->ldV, sizeof(float) * Ki,
+                                   hipMemcpyDeviceToDevice, s));
+            SSA_TRY(hipMemcpyAsync(V, rot, sizeof(float) * (size_t)m * p->ldV, hipMemcpyDeviceToDevice, s));
+            std::fill(Bm.begin(), Bm.end(), 0.0);
+            for (int i = 0; i < m; ++i) {
+                Bm[(size_t)i * cap + i] = om[i];
+                Bm[(size_t)i * cap + m] = a_last * PA[(size_t)(nu - 1) * kk + i];
+            }
+            ++cycles;
+            // one cycle of the recurrence from v_{m+1}, until V holds d_cap + 1 columns
+            nu = m;
+            int nv = m + 1;
+            fills.clear();
+            bool first = true;
+            while (nv - 1 < d_cap) {
+                // p = X v_nv - alpha_nv u_nu (first step: the Gram-Schmidt step removes U' rho)
+                rc = convolve(p, g, V + (long long)(nv - 1) * p->ldV, Ki, r,
+                              first ? nullptr : U + (long long)(nu - 1) * p->ldU, first ? nullptr : alpha + nv);
+                if (rc != SSA_OK) return rc;
+                rc = orthonormalize(p, U, p->ldU, nu, Li, beta + nu + 1, 1, ctr++);
+                if (rc != SSA_OK) return rc;
+                fills.push_back({nu, nv - 1, 1, nu + 1});
+                ++nu;
+                first = false;
+                // r = X^T u_nu - beta_nu v_nv
+                rc = convolve(p, g, U + (long long)(nu - 1) * p->ldU, Li, r, V + (long long)(nv - 1) * p->ldV,
+                              beta + nu);
+                if (rc != SSA_OK) return rc;
+                rc = orthonormalize(p, V, p->ldV, nv, Ki, alpha + nv + 1, 1, ctr++);
+                if (rc != SSA_OK) return rc;
+                fills.push_back({nu - 1, nv, 0, nv + 1});
+                ++nv;
+                ++steps_run;
+            }
+            double* ha = h_ab[0];
+            double* hb = h_ab[0] + abn;
+            SSA_TRY(hipMemcpyAsync(ha, alpha, sizeof(double) * (size_t)(nv + 1), hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipMemcpyAsync(hb, beta, sizeof(double) * (size_t)(nu + 1), hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipStreamSynchronize(s));
+            for (const Fill& f : fills) Bm[(size_t)f.row * cap + f.col] = (f.from_beta ? hb : ha)[f.idx];
+            nc = nv - 1;
+            a_last = ha[nv];
+        }
+        for (int i = 0; i < k; ++i) h_sig[i] = om[i];
+        for (int r0 = 0; r0 < nu; ++r0)
+            for (int i = 0; i < k; ++i) h_P[(size_t)r0 * k + i] = PA[(size_t)r0 * kk + i];
+        for (int r0 = 0; r0 < nc; ++r0)
+            for (int i = 0; i < k; ++i) h_Q[(size_t)r0 * k + i] = QA[(size_t)r0 * kk + i];
+        d = steps_run;
+    } else {
+        // Ritz triples of B_d: sigma, U_{d+1} P, V_d Q
+        bidiag_ritz_vectors(h_alpha, h_beta, d, k, h_sig, h_P, h_Q, p->work.data());
+    }
+    SSA_TRY(hipMemcpyAsync(dP, h_P, sizeof(double) * (size_t)nu * k, hipMemcpyHostToDevice, s));
+    SSA_TRY(hipMemcpyAsync(dQ, h_Q, sizeof(double) * (size_t)nc * k, hipMemcpyHostToDevice, s));
     SSA_TRY(hipMemcpyAsync(sigma_dev, h_sig, sizeof(double) * k, hipMemcpyHostToDevice, s));
     float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
     float* Vo = p->transposed ? U_dev : V_dev;
     {
-        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (d + 1 + k) * ((k + 15) / 16));
-        SSA_TRY(launch_ritz(U, p->ldU, d + 1, dP, k, Uo, Li, Li, s));
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + k) * ((k + 15) / 16));
+        SSA_TRY(launch_ritz(U, p->ldU, nu, dP, k, Uo, Li, Li, s));
     }
     {
-        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (d + k) * ((k + 15) / 16));
-        SSA_TRY(launch_ritz(V, p->ldV, d, dQ, k, Vo, Ki, Ki, s));
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + k) * ((k + 15) / 16));
+        SSA_TRY(launch_ritz(V, p->ldV, nc, dQ, k, Vo, Ki, Ki, s));
     }
     double st[3] = {0, 0, 0};
     SSA_TRY(hipMemcpyAsync(h_sig + k, at<double>(p, p->o_state), sizeof(double) * 3, hipMemcpyDeviceToHost, s));
@@ -546,6 +688,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         info->restarts = (int)st[1];
         info->dgks_passes = (int)st[2];
         info->steps_run = steps_run;
+        info->thick_restarts = cycles;
         for (int i = 0; i < k && i < 64; ++i) info->resid[i] = res[i];
     }
     return converged ? SSA_OK : SSA_WARN_NOT_CONVERGED;
@@ -702,6 +845,12 @@ int ssa_bidiag_ritz(const double* alpha, const double* beta, int d, int k, doubl
     std::vector<double> work(bidiag_work_doubles(d) + 16);
     if (resid) bidiag_ritz_values(alpha, beta, d, k, omega, resid, work.data());
     if (P && Q) bidiag_ritz_vectors(alpha, beta, d, k, omega, P, Q, work.data());
+    return SSA_OK;
+}
+
+int ssa_dense_ritz(const double* A, int nr, int nc, int k, double* omega, double* P, double* Q) {
+    if (!A || !omega || !P || !Q || nc < 1 || nr < nc || k < 1) return SSA_EINVAL;
+    dense_ritz(A, nr, nc, k, omega, P, Q);
     return SSA_OK;
 }
 

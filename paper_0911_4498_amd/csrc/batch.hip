@@ -348,7 +348,7 @@ SSA_INLINE double cgs_h2(CgsLds* sh, int ncols, int tid) {
 // a seeded random direction if the vector vanishes (|r_new| <= tol * max B).
 // Returns the B entry (0 after a restart); updates the series state.
 SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basis, long long ld, int ncols,
-                                 long long n, unsigned long long ctr, int tid) {
+                                 long long n, unsigned long long ctr, int tid, int out_col) {
     const double bnorm = q.state[kStBnorm];
     cgs_project(sh, r, basis, ld, ncols, n, tid);
     double coef = 0.0, scale = 0.0;
@@ -389,7 +389,7 @@ SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basi
             }
         }
     }
-    cgs_update(sh, r, basis, ld, ncols, n, scale, basis + (long long)ncols * ld, tid);
+    cgs_update(sh, r, basis, ld, ncols, n, scale, basis + (long long)out_col * ld, tid);
     if (tid == 0) {
         if (coef > bnorm) q.state[kStBnorm] = coef;
         if (event == 1) q.state[kStDgks] += 1.0;
@@ -504,10 +504,11 @@ __global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int side) {
     const int j = (int)q.state[kStJ];
     if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
     if (side == 0) {
-        const double aj = orthonormalize(sh, q, q.r, q.V, q.ldv, j - 1, q.Ki, 2ULL * j, tid);
+        // one-sided: V (length Ki >= Li) keeps only the three-term recurrence
+        const double aj = orthonormalize(sh, q, q.r, q.V, q.ldv, a.onesided ? 0 : j - 1, q.Ki, 2ULL * j, tid, j - 1);
         if (tid == 0) q.alpha[j] = aj;
     } else {
-        const double bj = orthonormalize(sh, q, q.r, q.U, q.ldu, j, q.Li, 2ULL * j + 1, tid);
+        const double bj = orthonormalize(sh, q, q.r, q.U, q.ldu, j, q.Li, 2ULL * j + 1, tid, j);
         if (tid == 0) {
             q.beta[j + 1] = bj;
             q.state[kStJ] = (double)(j + 1);  // the series' next Lanczos step

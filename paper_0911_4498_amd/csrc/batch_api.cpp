@@ -58,6 +58,7 @@ struct EngineCfg {
     int k_max, d_max, check_every;
     double tol;
     unsigned long long seed;
+    int onesided;
 };
 
 // Geometry and region layout of one series; returns its region bytes (offsets
@@ -117,10 +118,13 @@ EngineCfg make_cfg(long long n_max, int k_max, const ssa_opts* opts) {
     c.check_every = opts && opts->check_every > 0 ? opts->check_every : 4;
     c.tol = opts && opts->tol > 0.0 ? opts->tol : 1e-8;
     c.seed = opts && opts->seed ? opts->seed : 1ULL;
+    c.onesided = opts && opts->reorth == 1 ? 1 : 0;
     return c;
 }
 
-bool cfg_valid(long long n_max, int k_max) {
+// thick restart is a single-series option; reorth is 0 (full) or 1 (one-sided)
+bool cfg_valid(long long n_max, int k_max, const ssa_opts* opts) {
+    if (opts && (opts->restart_keep != 0 || (opts->reorth != 0 && opts->reorth != 1))) return false;
     return n_max >= 3 && n_max <= 2LL * batch::kMaxMp && k_max >= 1 && k_max <= batch::kMaxK;
 }
 
@@ -206,7 +210,7 @@ int ssa_batch_plan(long long n_max, int k_max, int max_series, const ssa_opts* o
                    ssa_batch* out) {
     if (!out || !workspace_bytes) return SSA_EINVAL;
     *out = nullptr;
-    if (!cfg_valid(n_max, k_max) || max_series < 1) return SSA_EINVAL;
+    if (!cfg_valid(n_max, k_max, opts) || max_series < 1) return SSA_EINVAL;
     ssa_batch b = new (std::nothrow) ssa_batch_s();
     if (!b) return SSA_EINVAL;
     b->cfg = make_cfg(n_max, k_max, opts);
@@ -299,6 +303,7 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
     a.ndone = reinterpret_cast<unsigned*>(b->ws + b->t_ndone);
     a.done_flags = nullptr;
     a.check_every = b->cfg.check_every;
+    a.onesided = b->cfg.onesided;
     a.tol = b->cfg.tol;
 
     int kmin = b->tab[0].k, maxcap = 0;
@@ -473,7 +478,7 @@ int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opt
                       void* hip_stream, ssa_server* out) {
     if (!out) return SSA_EINVAL;
     *out = nullptr;
-    if (!cfg_valid(n_max, k_max) || slots < 1 || !workspace_dev) return SSA_EINVAL;
+    if (!cfg_valid(n_max, k_max, opts) || slots < 1 || !workspace_dev) return SSA_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
     ssa_server v = new (std::nothrow) ssa_server_s();
     if (!v) return SSA_EINVAL;
@@ -546,6 +551,7 @@ int ssa_server_step(ssa_server v, long long* completed, int max_completed, int* 
     a.ndone = nullptr;
     a.done_flags = reinterpret_cast<int*>(v->ws + v->o_flags);
     a.check_every = v->cfg.check_every;
+    a.onesided = v->cfg.onesided;
     a.tol = v->cfg.tol;
     int* d_lists = reinterpret_cast<int*>(v->ws + v->o_lists);
     int* l_init = v->h_lists;

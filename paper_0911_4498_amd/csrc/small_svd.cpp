@@ -233,4 +233,95 @@ void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, 
     }
 }
 
+// Householder vector of x[0..n) (stride sx): on return v[0..n) with v[0] = 1
+// and tau such that (I - tau v v^T) x = beta e_0; returns beta.
+static double householder(int n, const double* x, long long sx, double* v, double& tau) {
+    double s2 = 0.0;
+    for (int i = 1; i < n; ++i) s2 += x[(long long)i * sx] * x[(long long)i * sx];
+    const double x0 = x[0];
+    v[0] = 1.0;
+    if (s2 == 0.0) {
+        tau = 0.0;
+        for (int i = 1; i < n; ++i) v[i] = 0.0;
+        return x0;
+    }
+    const double nrm = std::sqrt(x0 * x0 + s2);
+    const double beta = x0 <= 0.0 ? nrm : -nrm;
+    const double v0 = x0 - beta;
+    for (int i = 1; i < n; ++i) v[i] = x[(long long)i * sx] / v0;
+    tau = (beta - x0) / beta;
+    return beta;
+}
+
+void dense_ritz(const double* A, int nr, int nc, int k, double* omega, double* P, double* Q) {
+    // W = A; Golub-Kahan reduction W = Hl [Bu; 0] Hr^T, Bu upper bidiagonal (nc x nc)
+    std::vector<double> W(A, A + (size_t)nr * nc);
+    std::vector<double> vl((size_t)nc * nr, 0.0), tl(nc, 0.0), vr((size_t)nc * nc, 0.0), tr(nc, 0.0);
+    std::vector<double> dg(nc, 0.0), sup(nc, 0.0), tmp(std::max(nr, nc));
+    for (int j = 0; j < nc; ++j) {
+        double* v = &vl[(size_t)j * nr];
+        dg[j] = householder(nr - j, &W[(size_t)j * nc + j], nc, v, tl[j]);
+        if (tl[j] != 0.0)
+            for (int c = j; c < nc; ++c) {
+                double s = 0.0;
+                for (int i = j; i < nr; ++i) s += v[i - j] * W[(size_t)i * nc + c];
+                s *= tl[j];
+                for (int i = j; i < nr; ++i) W[(size_t)i * nc + c] -= s * v[i - j];
+            }
+        if (j + 1 < nc) {
+            double* w = &vr[(size_t)j * nc];
+            sup[j] = householder(nc - j - 1, &W[(size_t)j * nc + j + 1], 1, w, tr[j]);
+            if (tr[j] != 0.0)
+                for (int r = j; r < nr; ++r) {
+                    double* row = &W[(size_t)r * nc + j + 1];
+                    double s = 0.0;
+                    for (int c = 0; c < nc - j - 1; ++c) s += row[c] * w[c];
+                    s *= tr[j];
+                    for (int c = 0; c < nc - j - 1; ++c) row[c] -= s * w[c];
+                }
+        }
+    }
+    // Bu^T is lower bidiagonal: alpha[1..nc] = diagonal, beta[2..nc] = superdiagonal of Bu,
+    // beta[nc+1] = 0 (an (nc+1) x nc matrix with a zero last row).
+    std::vector<double> al(nc + 3, 0.0), be(nc + 3, 0.0);
+    for (int j = 0; j < nc; ++j) al[j + 1] = dg[j];
+    for (int j = 0; j + 1 < nc; ++j) be[j + 2] = sup[j];
+    const int kk = std::min(k, nc);
+    std::vector<double> Pb((size_t)(nc + 1) * kk), Qb((size_t)nc * kk), work(bidiag_work_doubles(nc) + 16);
+    bidiag_ritz_vectors(al.data(), be.data(), nc, kk, omega, Pb.data(), Qb.data(), work.data());
+    // Bu = Qb diag(omega) Pb[0..nc)^T, so the left vectors of A are Hl [Qb; 0] and the right
+    // ones Hr Pb[0..nc); the reflectors are applied last-first to those small blocks.
+    std::vector<double> Lft((size_t)nr * kk, 0.0), Rgt((size_t)nc * kk, 0.0);
+    for (int i = 0; i < nc; ++i)
+        for (int c = 0; c < kk; ++c) {
+            Lft[(size_t)i * kk + c] = Qb[(size_t)i * kk + c];
+            Rgt[(size_t)i * kk + c] = Pb[(size_t)i * kk + c];
+        }
+    for (int j = nc - 1; j >= 0; --j) {
+        if (tl[j] != 0.0) {
+            const double* v = &vl[(size_t)j * nr];
+            for (int c = 0; c < kk; ++c) {
+                double s = 0.0;
+                for (int i = j; i < nr; ++i) s += v[i - j] * Lft[(size_t)i * kk + c];
+                s *= tl[j];
+                for (int i = j; i < nr; ++i) Lft[(size_t)i * kk + c] -= s * v[i - j];
+            }
+        }
+        if (j + 1 < nc && tr[j] != 0.0) {
+            const double* w = &vr[(size_t)j * nc];
+            for (int c = 0; c < kk; ++c) {
+                double s = 0.0;
+                for (int i = j + 1; i < nc; ++i) s += w[i - j - 1] * Rgt[(size_t)i * kk + c];
+                s *= tr[j];
+                for (int i = j + 1; i < nc; ++i) Rgt[(size_t)i * kk + c] -= s * w[i - j - 1];
+            }
+        }
+    }
+    for (int i = 0; i < k; ++i) {
+        if (i >= kk) omega[i] = 0.0;
+        for (int r = 0; r < nr; ++r) P[(size_t)r * k + i] = i < kk ? Lft[(size_t)r * kk + i] : 0.0;
+        for (int r = 0; r < nc; ++r) Q[(size_t)r * k + i] = i < kk ? Rgt[(size_t)r * kk + i] : 0.0;
+    }
+}
+
 }  // namespace ssa

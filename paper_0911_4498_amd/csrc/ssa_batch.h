@@ -74,6 +74,7 @@ struct BatchArgs {
     unsigned* ndone;           // series finished so far (may be null)
     int* done_flags;           // per table slot: 1 once the series is finished (may be null)
     int check_every;
+    int onesided;              // 1: the V basis (length Ki) is not reorthogonalized
     double tol;
 };
 

@@ -116,5 +116,10 @@ void bidiag_ritz_values(const double* alpha, const double* beta, int d, int k, d
 void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, double* omega,
                          double* P, double* Q, double* work);
 size_t bidiag_work_doubles(int d);
+// Top-k singular triples of a dense nr x nc matrix A (row-major, nr >= nc):
+// omega[k] descending, P (nr x k row-major, left vectors), Q (nc x k, right).
+// Used for the projected matrix of a restarted bidiagonalization, which is
+// no longer bidiagonal.
+void dense_ritz(const double* A, int nr, int nc, int k, double* omega, double* P, double* Q);
 
 }  // namespace ssa

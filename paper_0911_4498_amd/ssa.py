@@ -28,12 +28,14 @@ _c_p = ctypes.c_void_p
 
 class SsaOpts(ctypes.Structure):
     _fields_ = [("d_max", ctypes.c_int), ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
-                ("seed", ctypes.c_ulonglong), ("fft_m1", ctypes.c_int), ("fft_cb", ctypes.c_int)]
+                ("seed", ctypes.c_ulonglong), ("fft_m1", ctypes.c_int), ("fft_cb", ctypes.c_int),
+                ("restart_keep", ctypes.c_int), ("reorth", ctypes.c_int)]
 
 
 class SsaInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int), ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("dgks_passes", ctypes.c_int), ("steps_run", ctypes.c_int), ("resid", ctypes.c_double * 64)]
+                ("dgks_passes", ctypes.c_int), ("steps_run", ctypes.c_int), ("resid", ctypes.c_double * 64),
+                ("thick_restarts", ctypes.c_int)]
 
 
 class SsaPlanDesc(ctypes.Structure):
@@ -43,7 +45,7 @@ class SsaPlanDesc(ctypes.Structure):
 
 EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
-            "ssa_bidiag_ritz", "ssa_profile_enable", "ssa_profile_read",
+            "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
             "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
             "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
@@ -89,6 +91,7 @@ def load():
     lib.ssa_status_str.restype = ctypes.c_char_p
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ssa_bidiag_ritz.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+    lib.ssa_dense_ritz.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
     lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_uint]
     lib.ssa_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), dp, dp]
     lib.ssa_batch_plan.argtypes = [_c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts),
@@ -156,18 +159,35 @@ def bidiag_ritz(alpha, beta, d: int, k: int, vectors: bool = False):
     return (om, res, P, Q) if vectors else (om, res)
 
 
+def dense_ritz(A, k: int):
+    """Host utility: the k largest singular triples of a dense matrix (rows >= columns)."""
+    import numpy as np
+    lib = load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    nr, nc = A.shape
+    om = np.zeros(k)
+    P = np.zeros((nr, k))
+    Q = np.zeros((nc, k))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.ssa_dense_ritz(A.ctypes.data_as(dp), nr, nc, k, om.ctypes.data_as(dp), P.ctypes.data_as(dp),
+                              Q.ctypes.data_as(dp)), "ssa_dense_ritz")
+    return om, P, Q
+
+
 class Plan:
     """One series geometry (N, L) bound to a torch-allocated device workspace."""
 
     def __init__(self, N: int, L: int, k_max: int, d_max: int = 0, check_every: int = 0,
-                 tol: float = 0.0, seed: int = 0, device=None, stream=None, fft_m1: int = 0, fft_cb: int = 0):
+                 tol: float = 0.0, seed: int = 0, device=None, stream=None, fft_m1: int = 0, fft_cb: int = 0,
+                 restart_keep: int = 0, reorth: int = 0):
         import torch
         self._torch = torch
         lib = load()
         self.lib = lib
         self.N, self.L, self.K = int(N), int(L), int(N) - int(L) + 1
         self.k_max = int(k_max)
-        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), int(fft_m1), int(fft_cb))
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), int(fft_m1), int(fft_cb),
+                       int(restart_keep), int(reorth))
         ws = ctypes.c_size_t(0)
         h = _c_p()
         _check(lib.ssa_embed_plan(self.N, self.L, self.k_max, ctypes.byref(opts), ctypes.byref(ws),
@@ -281,12 +301,12 @@ class Batch:
     one workgroup per series.  The device workspace grows to what each solve needs."""
 
     def __init__(self, n_max: int, k_max: int, max_series: int, d_max: int = 0, check_every: int = 0,
-                 tol: float = 0.0, seed: int = 0, device=None, stream=None):
+                 tol: float = 0.0, seed: int = 0, device=None, stream=None, reorth: int = 0):
         import torch
         self._torch = torch
         lib = load()
         self.lib = lib
-        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), 0, 0)
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), 0, 0, 0, int(reorth))
         ws = ctypes.c_size_t(0)
         h = _c_p()
         _check(lib.ssa_batch_plan(int(n_max), int(k_max), int(max_series), ctypes.byref(opts),
@@ -405,7 +425,7 @@ class Server:
     every admitted request per tick."""
 
     def __init__(self, n_max: int, k_max: int, slots: int, pool_bytes: int, d_max: int = 0,
-                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None):
+                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None, reorth: int = 0):
         import torch
         self._torch = torch
         lib = load()
@@ -414,7 +434,7 @@ class Server:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
         base = self.pool.data_ptr()
-        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), 0, 0)
+        opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), 0, 0, 0, int(reorth))
         h = _c_p()
         _check(lib.ssa_server_create(int(n_max), int(k_max), int(slots), ctypes.byref(opts), base + (-base) % 256,
                                      int(pool_bytes), self.stream.cuda_stream, ctypes.byref(h)), "ssa_server_create")

@@ -92,6 +92,25 @@ def test_batch_small_series_match_oracle(ssa):
         say(f"   {rep}")
 
 
+def test_batch_one_sided_reorth_matches_oracle(ssa):
+    """reorth=1: only the length-min(L,K) basis is reorthogonalized; same tolerances."""
+    series, Ls, ks = small_batch(12)
+    say("batch of 12 series, one-sided: solving")
+    b = ssa.Batch(n_max=1500, k_max=16, max_series=64, reorth=1)
+    out = b.solve(series, Ls, ks)
+    info = out["info"].cpu().numpy()
+    for s, (f, L, k) in enumerate(zip(series, Ls, ks)):
+        say(f"batch one-sided series {s}: N={len(f)} L={L} k={k} steps={info[s, 0]} conv={info[s, 1]}")
+        rep = compare_one(f, L, k, out["sigma"][s], out["U"][s], out["V"][s], out["recon"][s])
+        say(f"   {rep}")
+    f, N, L = inputs.c3_series(5, N=12000)
+    say("c3 series 5, one-sided: solving")
+    b2 = ssa.Batch(n_max=20480, k_max=16, max_series=4, reorth=1)
+    out = b2.solve([f], [L], [16])
+    rep = compare_one(f, L, 16, out["sigma"][0], out["U"][0], out["V"][0], out["recon"][0], dense=False)
+    say(f"   {rep}")
+
+
 def test_batch_alone_equals_in_the_mix(ssa):
     series, Ls, ks = small_batch(32)
     keys = [7000 + s for s in range(32)]

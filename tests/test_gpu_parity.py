@@ -149,12 +149,12 @@ def run_gpu(ssa, f, L, k, **kw):
     return plan, s, U, V, info
 
 
-def check_against_dense(ssa, f, L, k, extra=4, groups_of_clusters=True):
+def check_against_dense(ssa, f, L, k, extra=4, groups_of_clusters=True, **kw):
     N = len(f)
     K = N - L + 1
     kr = min(k + extra, min(L, K))
     sA, UA, VA = oracle.ssa_dense(f, L, kr)
-    plan, s, U, V, info = run_gpu(ssa, f, L, k)
+    plan, s, U, V, info = run_gpu(ssa, f, L, k, **kw)
     sg = s.cpu().numpy()
     Ug = U.cpu().numpy().T.astype(np.float64)
     Vg = V.cpu().numpy().T.astype(np.float64)
@@ -167,6 +167,7 @@ def check_against_dense(ssa, f, L, k, extra=4, groups_of_clusters=True):
     rep["recon_err"] = parity.compare_recon(rg, ro, np.abs(f).max())
     rep["steps"] = info.steps
     rep["converged"] = info.converged
+    rep["thick_restarts"] = info.thick_restarts
     say(f"  N={N} L={L} k={k}: {rep}")
     return rep
 
@@ -192,6 +193,47 @@ def test_svd_various(ssa, N, L, k, kind):
     else:
         f = inputs.c1_series(N)
     check_against_dense(ssa, f, L, k)
+
+
+@pytest.mark.parametrize("N,L,k,d_max,keep,kind", [(1000, 500, 10, 24, 14, "c1"), (600, 300, 8, 30, 16, "white"),
+                                                   (900, 700, 6, 12, 8, "c1"), (1500, 750, 20, 30, 22, "c1"),
+                                                   (2000, 1000, 12, 16, 12, "sine")])
+def test_svd_thick_restart(ssa, N, L, k, d_max, keep, kind):
+    """Thick-restarted bidiagonalization (basis capped at d_max, keep Ritz pairs per cycle)
+    against the dense oracle.  With check_every above d_max the first stopping test comes
+    at the cap, where it cannot pass (the rule needs two tests), so every case restarts."""
+    say(f"svd thick restart {kind} N={N} L={L} k={k} d_max={d_max} keep={keep}")
+    if kind == "white":
+        f = inputs.white(N, 5)
+    elif kind == "sine":
+        f = inputs.sinusoid(N, 23.0, 2.0) + inputs.sinusoid(N, 61.0, 1.0) + 0.05 * inputs.white(N, 3)
+    else:
+        f = inputs.c1_series(N)
+    rep = check_against_dense(ssa, f, L, k, d_max=d_max, restart_keep=keep, check_every=64)
+    assert rep["converged"] == 1
+    assert rep["thick_restarts"] >= 1
+
+
+@pytest.mark.parametrize("N,L,k,kind", [(1000, 500, 10, "c1"), (600, 300, 8, "white"), (900, 700, 6, "c1"),
+                                        (1500, 750, 20, "c1"), (64, 32, 8, "white")])
+def test_svd_one_sided_reorth(ssa, N, L, k, kind):
+    """One-sided reorthogonalization (Simon and Zha): only the basis of length min(L, K)
+    is reorthogonalized; the same tolerances against the dense oracle."""
+    say(f"svd one-sided {kind} N={N} L={L} k={k}")
+    f = inputs.white(N, 5) if kind == "white" else inputs.c1_series(N)
+    rep = check_against_dense(ssa, f, L, k, reorth=1)
+    assert rep["converged"] == 1
+
+
+def test_thick_restart_off_is_plain_algorithm(ssa):
+    """restart_keep with a cap that the solve never reaches leaves the result bitwise equal
+    to the plain solver's."""
+    say("thick restart unused")
+    f = inputs.c1_series(1000)
+    _, s0, U0, V0, i0 = run_gpu(ssa, f, 500, 10)
+    _, s1, U1, V1, i1 = run_gpu(ssa, f, 500, 10, d_max=200, restart_keep=20)
+    assert i0.thick_restarts == 0 and i1.thick_restarts == 0 and i0.steps == i1.steps
+    assert torch.equal(s0, s1) and torch.equal(U0, U1) and torch.equal(V0, V1)
 
 
 def test_svd_window_longer_than_lag_count(ssa):
@@ -296,18 +338,25 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
-def test_c2_full_size(ssa):
+@pytest.mark.parametrize("d_max,keep,reorth", [(0, 0, 0), (60, 30, 0), (0, 0, 1)])
+def test_c2_full_size(ssa, d_max, keep, reorth):
     """N=100000, L=50000, k=20: sigma and sampled reconstructions vs the tier-B oracle
-    (stored), plus residual and orthogonality certificates computed here in FP64."""
-    say("c2 full size")
+    (stored), plus residual and orthogonality certificates computed here in FP64: the plain
+    solver, the basis capped at 60 columns (thick restart keeping 30), and one-sided
+    reorthogonalization."""
+    say(f"c2 full size d_max={d_max} keep={keep} reorth={reorth}")
     g = json.load(open(GOLDEN))
     N, L, k = 100_000, 50_000, 20
     K = N - L + 1
     f = inputs.c2_series(N)
-    plan, s, U, V, info = run_gpu(ssa, f, L, k)
+    plan, s, U, V, info = run_gpu(ssa, f, L, k, d_max=d_max, restart_keep=keep, reorth=reorth)
     sg = s.cpu().numpy()
     s_ref = np.array(g["sigma"])
-    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")
+    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes} "
+        f"thick_restarts={info.thick_restarts}")
+    assert info.converged == 1
+    if keep:
+        assert info.thick_restarts >= 1
     say(f"  sigma rel err max {np.max(np.abs(sg - s_ref[:k]) / s_ref[:k]):.2e}")
     parity.assert_sigma(sg, s_ref[:k])
     fro = parity.frobenius(f, L)

@@ -217,6 +217,113 @@ def test_bidiag_ritz_clustered_and_zero_entries():
     np.testing.assert_allclose(B @ Q, P * om, atol=1e-10)
 
 
+def arrow(omega, rho, a, b):
+    """Projected matrix of a restarted bidiagonalization: diag(omega) with rho as column m,
+    then b on the diagonal and a on the superdiagonal of the bidiagonal tail."""
+    m = len(omega)
+    n = m + len(b)
+    B = np.zeros((n, n))
+    B[np.arange(m), np.arange(m)] = omega
+    B[:m, m] = rho
+    for t in range(len(b)):
+        B[m + t, m + t] = b[t]
+        if t + 1 < len(b):
+            B[m + t, m + t + 1] = a[t]
+    return B
+
+
+@pytest.mark.parametrize("shape,k,seed", [((7, 5), 3, 0), ((41, 40), 10, 1), ((60, 60), 20, 2),
+                                          ((130, 90), 30, 3), ((1, 1), 1, 4), ((9, 4), 6, 5)])
+def test_dense_ritz_matches_lapack(shape, k, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=shape)
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    om, P, Q = ssa.dense_ritz(A, k)
+    kk = min(k, shape[1])
+    np.testing.assert_allclose(om[:kk], s_ref[:kk], rtol=1e-10, atol=1e-12 * s_ref[0])
+    assert np.all(om[kk:] == 0) and np.all(P[:, kk:] == 0) and np.all(Q[:, kk:] == 0)
+    np.testing.assert_allclose(A @ Q[:, :kk], P[:, :kk] * om[:kk], atol=1e-10 * s_ref[0])
+    np.testing.assert_allclose(A.T @ P[:, :kk], Q[:, :kk] * om[:kk], atol=1e-10 * s_ref[0])
+    np.testing.assert_allclose(Q[:, :kk].T @ Q[:, :kk], np.eye(kk), atol=1e-10)
+    np.testing.assert_allclose(P[:, :kk].T @ P[:, :kk], np.eye(kk), atol=1e-10)
+
+
+def test_dense_ritz_on_restart_shapes():
+    """The two projected matrices of the restarted solver: the first cycle's (d+1) x d
+    bidiagonal (same triples as the bidiagonal routine) and the arrow form of later
+    cycles, whose last left-vector row gives the residual bound."""
+    rng = np.random.default_rng(7)
+    d, k = 30, 12
+    alpha = np.abs(rng.normal(size=d + 3)) + 0.1
+    beta = np.abs(rng.normal(size=d + 3)) + 0.1
+    alpha[0] = beta[0] = beta[1] = 0.0
+    B = bidiag(alpha, beta, d)
+    om, P, Q = ssa.dense_ritz(B, k)
+    om_b, res_b, P_b, Q_b = ssa.bidiag_ritz(alpha, beta, d, k, vectors=True)
+    np.testing.assert_allclose(om, om_b, rtol=1e-12)
+    np.testing.assert_allclose(alpha[d + 1] * np.abs(P[d]), res_b, rtol=1e-7, atol=1e-13 * om[0])
+    for i in range(k):  # vectors agree up to sign
+        sgn = np.sign(Q[:, i] @ Q_b[:, i])
+        np.testing.assert_allclose(sgn * Q[:, i], Q_b[:, i], atol=1e-9)
+        np.testing.assert_allclose(sgn * P[:, i], P_b[:, i], atol=1e-9)
+    m = 14
+    Ba = arrow(np.sort(rng.uniform(1, 10, m))[::-1], rng.normal(size=m) * 1e-3,
+               np.abs(rng.normal(size=20)), np.abs(rng.normal(size=21)))
+    U_ref, s_ref, _ = np.linalg.svd(Ba)
+    om, P, Q = ssa.dense_ritz(Ba, m)
+    np.testing.assert_allclose(om, s_ref[:m], rtol=1e-11)
+    np.testing.assert_allclose(np.abs(P[-1]), np.abs(U_ref[-1, :m]), atol=1e-11)
+    np.testing.assert_allclose(Ba @ Q, P * om, atol=1e-11 * s_ref[0])
+
+
+def test_restart_keep_validation():
+    lib = _built()
+
+    def rc_of(N, L, k, d_max, keep):
+        opts = ssa.SsaOpts(d_max, 0, 0.0, 0, 0, 0, keep)
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        rc = lib.ssa_embed_plan(N, L, k, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h))
+        if rc == 0:
+            lib.ssa_plan_destroy(h)
+        return rc, ws.value
+
+    assert rc_of(10000, 5000, 10, 40, 16)[0] == 0
+    assert rc_of(10000, 5000, 10, 40, 9)[0] == ssa.SSA_EINVAL       # keep < k_max
+    assert rc_of(10000, 5000, 10, 40, 39)[0] == ssa.SSA_EINVAL      # keep + 2 > d_max
+    assert rc_of(10000, 5000, 10, 600, 16)[0] == ssa.SSA_EINVAL     # basis cap above 512
+    assert rc_of(100, 20, 5, 64, 80)[0] == 0                        # whole Krylov space fits
+    # the rotation scratch (keep columns of the longer basis) is part of the workspace
+    assert rc_of(10000, 5000, 10, 40, 16)[1] > rc_of(10000, 5000, 10, 40, 0)[1] + 4 * 16 * 5000
+
+
+def test_reorth_option_validation():
+    lib = _built()
+
+    def rc_of(keep, reorth):
+        opts = ssa.SsaOpts(40, 0, 0.0, 0, 0, 0, keep, reorth)
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        rc = lib.ssa_embed_plan(10000, 5000, 10, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h))
+        if rc == 0:
+            lib.ssa_plan_destroy(h)
+        return rc
+
+    assert rc_of(0, 1) == 0
+    assert rc_of(0, 2) == ssa.SSA_EINVAL
+    assert rc_of(16, 1) == ssa.SSA_EINVAL  # one-sided bases cannot be restarted
+    for keep, reorth in ((16, 0), (0, 3)):  # the batch engine has no restart
+        opts = ssa.SsaOpts(0, 0, 0.0, 0, 0, 0, keep, reorth)
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        assert lib.ssa_batch_plan(2000, 8, 4, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h)) == ssa.SSA_EINVAL
+    opts = ssa.SsaOpts(0, 0, 0.0, 0, 0, 0, 0, 1)
+    ws = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    assert lib.ssa_batch_plan(2000, 8, 4, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h)) == 0
+    lib.ssa_batch_destroy(h)
+
+
 def test_hmatrix_workspace_validation():
     """The H-matrix entry point checks its window sizes and index set on the host."""
     lib = _built()
