@@ -30,9 +30,14 @@ With --workload served: a Poisson stream of requests (N log-uniform in
 requests with N <= 20480 go to the continuous-batching server (ssa_server_*),
 longer ones to single-series plans on two worker streams; reports p50/p99
 latency from arrival to complete outputs, and throughput.
+With --workload long: the very long series (N = 2^24, L = N/2, k = 50) through
+the single-series path with the basis capped by thick restart (--d-max,
+--restart-keep); suggested --steps 2 --warmup 1.
+--reorth 1 selects one-sided reorthogonalization (single, many, served).
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--pmc-copy]
-                       [--workload single|many|served] [--series S] [--sample S1]
-                       [--rates R1,R2] [--requests Q] [--slots S] [--pool-gb G]
+                       [--workload single|many|served|hmatrix|realizations|long] [--reorth 0|1]
+                       [--series S] [--sample S1] [--rates R1,R2] [--requests Q] [--slots S]
+                       [--pool-gb G] [--d-max D] [--restart-keep M]
 """
 import argparse
 import json
@@ -122,7 +127,7 @@ def bench_many(args):
     Ls = [L for _, _, L in host]
     Ns = np.array([N for _, N, _ in host])
     keys = list(range(ns))
-    eng = ssa.Batch(n_max=20000, k_max=k, max_series=ns)
+    eng = ssa.Batch(n_max=20000, k_max=k, max_series=ns, reorth=args.reorth)
     steps = []
 
     def step():
@@ -152,14 +157,16 @@ def bench_many(args):
     Li = np.minimum(np.array(Ls), Ns - np.array(Ls) + 1).astype(np.float64)
     Ki = np.maximum(np.array(Ls), Ns - np.array(Ls) + 1).astype(np.float64)
     d = info[:, 0].astype(np.float64)
-    cgs_bytes = args.steps * float(np.sum(4.0 * Ki * (d + 1) * (d + 3) + 4.0 * Li * d * (d + 4)))
+    # (one-sided: side 0 projects against no columns, 3 Ki floats per launch)
+    side0 = 12.0 * Ki * (d + 1) if args.reorth else 4.0 * Ki * (d + 1) * (d + 3)
+    cgs_bytes = args.steps * float(np.sum(side0 + 4.0 * Li * d * (d + 4)))
     n_cgs, ms_cgs = prof["cgs"]
     dom = max(prof, key=lambda c: prof[c][1])
     print(f"# batched: {t_b / args.steps * 1e3:.1f} ms per batch, {rate_b:.0f} eigentriples/s, "
           f"mean d {info[:, 0].mean():.1f}, converged {info[:, 1].mean():.3f}", file=sys.stderr, flush=True)
     # one series at a time with the single-series path (plans built untimed)
     m = min(args.sample, ns)
-    plans = [ssa.Plan(int(Ns[s]), Ls[s], k, device=dev) for s in range(m)]
+    plans = [ssa.Plan(int(Ns[s]), Ls[s], k, device=dev, reorth=args.reorth) for s in range(m)]
     groups = [[i] for i in range(k)]
 
     def one(s):
@@ -192,7 +199,8 @@ def bench_many(args):
         "data": "synthetic",
         "config": {"workload": f"{ns} series, N uniform in [2000, 20000], L = N/2, k = 16, two sinusoids + "
                                "trend + N(0, 0.1^2) (seeded); truncated SVD + 16 elementary reconstructions each",
-                   "series": ns, "k": k, "parallelism": "single GPU"},
+                   "series": ns, "k": k, "reorth": "one-sided" if args.reorth else "full",
+                   "parallelism": "single GPU"},
         "lanczos_steps_mean": float(info[:, 0].mean()),
         "converged_fraction": float(info[:, 1].mean()),
         "one_at_a_time": {"value": rate_1, "unit": "eigentriples/s", "series_timed": m,
@@ -235,7 +243,8 @@ def bench_served(args):
         reqs.append((torch.tensor(f, device=dev), N, L, k))
     small = [r for r in range(nreq) if reqs[r][1] <= n_small_max]
     torch.cuda.synchronize()  # request series resident before any stream uses them
-    srv = ssa.Server(n_max=n_small_max, k_max=32, slots=args.slots, pool_bytes=int(args.pool_gb * 2**30), device=dev)
+    srv = ssa.Server(n_max=n_small_max, k_max=32, slots=args.slots, pool_bytes=int(args.pool_gb * 2**30), device=dev,
+                     reorth=args.reorth)
     done_at = {}
     lock = threading.Lock()
     work = queue.Queue()
@@ -250,7 +259,7 @@ def bench_served(args):
             r, t0 = item
             f, N, L, k = reqs[r]
             with torch.cuda.stream(stream):
-                plan = ssa.Plan(N, L, k, device=dev, stream=stream)
+                plan = ssa.Plan(N, L, k, device=dev, stream=stream, reorth=args.reorth)
                 sg, U, V, info = plan.truncated_svd(f, k)
                 g = groups_cache.setdefault(k, [[i] for i in range(k)])
                 plan.reconstruct(sg, U, V, g)
@@ -332,7 +341,8 @@ def bench_served(args):
                                "L in {N/4, N/2}, k in [8, 32], c3 signals (seeded)",
                    "short_path": f"continuous batching, N <= {n_small_max}, {args.slots} slots, "
                                  f"{args.pool_gb} GiB pool",
-                   "long_path": "single-series plans, 2 worker streams", "parallelism": "single GPU"},
+                   "long_path": "single-series plans, 2 worker streams",
+                   "reorth": "one-sided" if args.reorth else "full", "parallelism": "single GPU"},
         "rates": results,
     }
     print(json.dumps(out), flush=True)
@@ -441,7 +451,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
-    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix", "realizations"), default="single")
+    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix", "realizations", "long"),
+                    default="single")
+    ap.add_argument("--reorth", type=int, choices=(0, 1), default=0,
+                    help="0: full reorthogonalization, 1: one-sided (single, many and served workloads)")
+    ap.add_argument("--d-max", type=int, default=0, help="basis cap (long workload; default 125)")
+    ap.add_argument("--restart-keep", type=int, default=0, help="Ritz pairs kept per restart (long; default 75)")
     ap.add_argument("--realizations", type=int, default=64, help="realizations per size (realizations workload)")
     ap.add_argument("--rs-sizes", default="1000,4000,16000", help="series lengths (realizations workload)")
     ap.add_argument("--rs-oracle-max", type=int, default=1000, help="largest N timed with the CPU oracle")
@@ -468,28 +483,51 @@ def main():
         return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix,
                 "realizations": bench_realizations}[args.workload](args)
 
-    import numpy as np
-    import torch
-
-    from paper_0911_4498_amd import inputs, ssa
+    from paper_0911_4498_amd import ssa
     if not os.path.exists(ssa.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
-    dev = torch.device("cuda:0")
     if args.pmc_copy:
         copy_calibration()
+    if args.workload == "long":
+        return bench_long(args)
+    from paper_0911_4498_amd import inputs
     f_np = inputs.c2_series(N)
+    config = {"workload": "single long series: N=100000, L=50000, k=20, 5 sinusoids + exp trend + "
+                          "AR(1) noise (seed 1002); truncated SVD + 20 elementary reconstructions",
+              "N": N, "L": L, "k": K_TRIPLES, "reorth": "one-sided" if args.reorth else "full",
+              "parallelism": "single GPU"}
+    out = bench_plan(args, f_np, L, K_TRIPLES, {"reorth": args.reorth}, "eigentriples/s (N=1e5, L=N/2, k=20)",
+                     config, traffic_per_launch)
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(f_np, int(round(out["lanczos_steps"])))
+    print(json.dumps(out), flush=True)
+
+
+def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
+    """One series through the single-series path: warm-up, one calibration solve with every
+    kernel class event-timed (picks the dominant class), then the timed solves with the
+    dominant class bracketed by HIP events on the plan's stream."""
+    import numpy as np
+    import torch
+
+    from paper_0911_4498_amd import ssa
+    dev = torch.device("cuda:0")
+    Nw = len(f_np)
     f = torch.tensor(f_np, device=dev)
-    plan = ssa.Plan(N, L, K_TRIPLES, device=dev)
-    groups = [[i] for i in range(K_TRIPLES)]
+    plan = ssa.Plan(Nw, Lw, k, device=dev, **plan_kw)
+    groups = [[i] for i in range(k)]
     steps_seen = []
     steps_run = []
+    cycles = []
 
     def step():
-        s, U, V, info = plan.truncated_svd(f, K_TRIPLES)
+        s, U, V, info = plan.truncated_svd(f, k)
         plan.reconstruct(s, U, V, groups)
         steps_seen.append(info.steps)
         steps_run.append(info.steps_run)
+        cycles.append(info.thick_restarts)
         return info
 
     print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
@@ -497,7 +535,6 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # one extra untimed solve with every kernel class event-timed: picks the dominant class
     plan.profile_enable()
     step()
     calib = plan.profile_read()
@@ -511,12 +548,13 @@ def main():
                   f"alg={b / 1e6:9.3f} MB  {b / max(ms, 1e-9) / 1e6:8.1f} GB/s", file=sys.stderr)
     print(f"# dominant kernel class: {dom}", file=sys.stderr, flush=True)
 
-    # timed region: launches of the dominant class bracketed by HIP events on the plan's stream
     plan.profile_enable([dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
+        if Nw > 10**6:
+            print(f"# timed step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_timed = time.perf_counter() - t0
     prof = plan.profile_read()
@@ -525,11 +563,9 @@ def main():
     n_l, ms_l, b_l = prof[dom]
     achieved = (b_l / n_l) / (ms_l / n_l / 1e3) / 1e9 if n_l and ms_l > 0 else 0.0
     total_bytes = sum(v[2] for v in prof.values())
-    d_mean = float(np.mean(steps_seen[-args.steps:]))
-
-    out = {
-        "metric": "eigentriples/s (N=1e5, L=N/2, k=20)",
-        "value": K_TRIPLES * args.steps / t_timed,
+    return {
+        "metric": metric,
+        "value": k * args.steps / t_timed,
         "unit": "eigentriples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -542,11 +578,10 @@ def main():
         "dtype_detail": "FP32 FFTs, products and stored Lanczos vectors; FP64 Lanczos scalars, "
                         "Gram-Schmidt inner products and small bidiagonal SVD",
         "data": "synthetic",
-        "config": {"workload": "single long series: N=100000, L=50000, k=20, 5 sinusoids + exp trend + "
-                               "AR(1) noise (seed 1002); truncated SVD + 20 elementary reconstructions",
-                   "N": N, "L": L, "k": K_TRIPLES, "parallelism": "single GPU"},
-        "lanczos_steps": d_mean,
+        "config": config,
+        "lanczos_steps": float(np.mean(steps_seen[-args.steps:])),
         "lanczos_steps_run": float(np.mean(steps_run[-args.steps:])),
+        "thick_restarts": float(np.mean(cycles[-args.steps:])),
         "matvecs_per_s": 2.0 * sum(steps_run[-args.steps:]) / t_timed,
         "hbm_gb_s_algorithmic": total_bytes / t_timed / 1e9,
         "roofline": {
@@ -556,14 +591,68 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_per_launch(dom),
+            "traffic": traffic_fn(dom),
             "avg_launch_us": 1e3 * ms_l / max(n_l, 1),
             "alg_bytes_per_launch": b_l / max(n_l, 1),
         },
     }
+
+
+def cpu_baseline_long(f, Lw, k, steps_gpu):
+    """Oracle on a bounded sample of the N = 2^24 workload: direct row products of X and
+    X^T and direct antidiagonal means at sampled positions, scaled to the GPU's steps
+    (two products each) and to k Hankelizations of all N positions."""
+    import numpy as np
+
+    import oracle
+    Nw = len(f)
+    Kw = Nw - Lw + 1
+    rng = np.random.default_rng(77)
+    x = rng.normal(size=Kw)
+    y = rng.normal(size=Lw)
+    nrow = 8192  # about 10 s of direct products on 16 cores
+    rows = np.sort(rng.choice(Lw, nrow, replace=False))
+    cols = np.sort(rng.choice(Kw, nrow, replace=False))
+    t0 = time.perf_counter()
+    oracle.matvec_rows(f, Lw, x, rows)
+    oracle.matvec_rows(f, Lw, y, cols, transpose=True)
+    t_rows = time.perf_counter() - t0
+    t_step = t_rows / (2 * nrow) * (Lw + Kw)
+    pos = rng.choice(Nw, 2048, replace=False)
+    t1 = time.perf_counter()
+    oracle.hankelize_at(1.0, y, x, pos)
+    t_pos = (time.perf_counter() - t1) / pos.size
+    est = steps_gpu * t_step + k * Nw * t_pos
+    return {
+        "value": k / est,
+        "unit": "eigentriples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"direct products: {nrow} rows of X v and {nrow} of X^T u ({t_rows:.2f} s) scaled to "
+                   f"{steps_gpu} steps of L + K rows; direct antidiagonal means at {pos.size} random positions "
+                   f"({t_pos * 1e3:.2f} ms each) scaled to {k} x {Nw} positions"),
+        "sample_seconds": round(t_rows + t_pos * pos.size, 2),
+    }
+
+
+def bench_long(args):
+    """The very long series (N = 2^24, L = N/2, k = 50) with the basis capped by thick restart."""
+    from paper_0911_4498_amd import inputs
+    Nw = 2 ** 24
+    Lw, k = Nw // 2, 50
+    d_max = args.d_max or 125
+    keep = args.restart_keep or 75
+    print(f"# generating the N={Nw} series", file=sys.stderr, flush=True)
+    f_np = inputs.c5_series(Nw)
+    config = {"workload": f"very long series: N=2^24, L=N/2, k=50, 8 sinusoids + quadratic trend + "
+                          f"N(0, 0.5^2) noise (seeded); thick restart with a {d_max}-column basis keeping "
+                          f"{keep} Ritz pairs; truncated SVD + 50 elementary reconstructions",
+              "N": Nw, "L": Lw, "k": k, "d_max": d_max, "restart_keep": keep, "parallelism": "single GPU"}
+    out = bench_plan(args, f_np, Lw, k, {"d_max": d_max, "restart_keep": keep},
+                     "eigentriples/s (N=2^24, L=N/2, k=50)", config, lambda cls: None)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(f_np, int(round(d_mean)))
+        out["cpu_baseline"] = cpu_baseline_long(f_np, Lw, k, int(round(out["lanczos_steps_run"])))
     print(json.dumps(out), flush=True)
 
 
