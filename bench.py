@@ -57,15 +57,15 @@ CLASS_KERNEL = {"pass1": "k_pass1<0", "pass2": "k_pass2_matvec", "pass3": "k_pas
                 "recon_pass3": "k_pass3<1"}
 
 
-def traffic_summary_path(cls):
-    return os.path.join(ROOT, "profiles", f"c2_{cls}_traffic.txt")
+def traffic_summary_path(cls, workload="c2"):
+    return os.path.join(ROOT, "profiles", f"{workload}_{cls}_traffic.txt")
 
 
-def traffic_per_launch(cls):
+def traffic_per_launch(cls, workload="c2"):
     """HBM bytes per launch of the class's kernel from the committed counter summary,
     or None if there is none or the library sources changed since it was taken."""
     from paper_0911_4498_amd import pmc_traffic
-    s = pmc_traffic.load_summary(traffic_summary_path(cls))
+    s = pmc_traffic.load_summary(traffic_summary_path(cls, workload))
     if not s or s.get("source_sha256") != pmc_traffic.source_hash():
         return None
     return float(s["traffic_bytes_per_launch"])
@@ -215,7 +215,7 @@ def bench_many(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": cgs_bytes / (ms_cgs / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_per_launch("kb_cgs", "c3") if not args.reorth else None,
             "avg_launch_us": 1e3 * ms_cgs / max(n_cgs, 1),
             "alg_bytes_per_launch": cgs_bytes / max(n_cgs, 1),
             "note": "Gram-Schmidt launches (one per half-step, all series); bytes from each series' d",
@@ -475,20 +475,15 @@ def main():
               "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if args.workload in ("many", "served", "hmatrix", "realizations"):
-        from paper_0911_4498_amd import ssa as _ssa
-        if not os.path.exists(_ssa.LIB_PATH):
-            import __graft_entry__
-            __graft_entry__.build()
-        return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix,
-                "realizations": bench_realizations}[args.workload](args)
-
     from paper_0911_4498_amd import ssa
     if not os.path.exists(ssa.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
     if args.pmc_copy:
         copy_calibration()
+    if args.workload in ("many", "served", "hmatrix", "realizations"):
+        return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix,
+                "realizations": bench_realizations}[args.workload](args)
     if args.workload == "long":
         return bench_long(args)
     from paper_0911_4498_amd import inputs
@@ -649,7 +644,7 @@ def bench_long(args):
                           f"{keep} Ritz pairs; truncated SVD + 50 elementary reconstructions",
               "N": Nw, "L": Lw, "k": k, "d_max": d_max, "restart_keep": keep, "parallelism": "single GPU"}
     out = bench_plan(args, f_np, Lw, k, {"d_max": d_max, "restart_keep": keep},
-                     "eigentriples/s (N=2^24, L=N/2, k=50)", config, lambda cls: None)
+                     "eigentriples/s (N=2^24, L=N/2, k=50)", config, lambda cls: traffic_per_launch(cls, "c5"))
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_long(f_np, Lw, k, int(round(out["lanczos_steps_run"])))
