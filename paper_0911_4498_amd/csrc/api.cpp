@@ -264,8 +264,13 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
         ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)n * (ncols + 1));
         SSA_TRY(launch_cgs_project(a, s));
     }
-    {
+    a.presummed = a.nchunks > kColsumChunks ? 1 : 0;
+    if (a.presummed) {
         ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)a.nchunks * (ncols + 1));
+        SSA_TRY(launch_cgs_colsum(a, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_REDUCE, a.presummed ? 8.0 * (ncols + 1) : 8.0 * (double)a.nchunks * (ncols + 1));
         SSA_TRY(launch_cgs_reduce(a, s));
     }
     {

@@ -105,8 +105,14 @@ __device__ __forceinline__ float p1_value(const P1In& a, long long m, int y) {
     }
 }
 
-template <int MODE, int EPT>
-__global__ __launch_bounds__(256) void k_pass1(ConvGeom g, P1In a, float2* __restrict__ T1) {
+// Threads of a workgroup of the FFT passes whose rows hold more than 2048
+// points in total (up to 8192: 8 per thread).  Such a workgroup needs 64-96
+// KB of LDS, so it is alone on its CU; the 16 waves are what hides the
+// memory latency (256 threads with 32 points each reach a third less).
+constexpr int kBigThreads = 1024;
+
+template <int MODE, int EPT, int NT = 256>
+__global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __restrict__ T1) {
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
@@ -195,8 +201,8 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 }
 
 // pass 2 of a trajectory-matrix product: Q(k) = A(k) Z(k) + B(k) conj Z(M'-k)
-template <int EPT>
-__global__ __launch_bounds__(256) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
+template <int EPT, int NT = 256>
+__global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
                                                       const float2* __restrict__ T1,
                                                       float2* __restrict__ T2) {
     extern __shared__ float2 smem[];
@@ -260,8 +266,8 @@ __device__ __forceinline__ SplitD split_eo(float2 z, float2 zp) {
 //   A(k) = [E - sin(th) w^k O] / M',  B(k) = i cos(th) w^k O / M',
 // th = 2 pi k / M, E/O the split of C (so C(k) = E + w^k O,
 // C(k+M') = E - w^k O); the 1/M' of the inverse transform is folded in.
-template <int EPT>
-__global__ __launch_bounds__(256) void k_pass2_embed(ConvGeom g, const float2* __restrict__ T1,
+template <int EPT, int NT = 256>
+__global__ __launch_bounds__(NT) void k_pass2_embed(ConvGeom g, const float2* __restrict__ T1,
                                                      float4* __restrict__ AB) {
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -452,8 +458,8 @@ __device__ __forceinline__ void p3_emit(const P3Out& o, long long m, float val, 
     }
 }
 
-template <int MODE, int EPT>
-__global__ __launch_bounds__(256) void k_pass3(ConvGeom g, const float2* __restrict__ T2, P3Out o) {
+template <int MODE, int EPT, int NT = 256>
+__global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restrict__ T2, P3Out o) {
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
@@ -706,21 +712,35 @@ __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
     }
 }
 
+// Column sums for long vectors (many chunks): workgroup c adds part[c][chunk]
+// over all chunks (thread-strided, then the block sum: a fixed order) into h[c].
+__global__ __launch_bounds__(256) void k_cgs_colsum(ReduceArgs a) {
+    __shared__ double sh[16];
+    const double* row = a.part + (long long)blockIdx.x * a.pstride;
+    double sum = 0.0;
+    for (int ch = threadIdx.x; ch < a.nchunks; ch += 256) sum += row[ch];
+    sum = block_sum(sum, sh);
+    if (threadIdx.x == 0) a.h[blockIdx.x] = sum;
+}
+
 // One workgroup (1024 threads): h[c] = sum over chunks of part[c][chunk]
-// (32 lanes per column, chunks contiguous, fixed order), then cgs_finish.
+// (32 lanes per column, chunks contiguous, fixed order) unless k_cgs_colsum
+// has already formed it, then cgs_finish.
 constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
     __shared__ double hs[kMaxCols];
     __shared__ double sh[16];
     __shared__ int decision;
     const int tid = threadIdx.x;
-    for (int c = tid >> 5; c <= a.ncols; c += kReduceThreads / 32) {
-        const double* row = a.part + (long long)c * a.pstride;
-        double sum = 0.0;
-        for (int ch = tid & 31; ch < a.nchunks; ch += 32) sum += row[ch];
+    if (!a.presummed) {
+        for (int c = tid >> 5; c <= a.ncols; c += kReduceThreads / 32) {
+            const double* row = a.part + (long long)c * a.pstride;
+            double sum = 0.0;
+            for (int ch = tid & 31; ch < a.nchunks; ch += 32) sum += row[ch];
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) sum += __shfl_down(sum, off, 32);
-        if ((tid & 31) == 0) a.h[c] = sum;
+            for (int off = 16; off > 0; off >>= 1) sum += __shfl_down(sum, off, 32);
+            if ((tid & 31) == 0) a.h[c] = sum;
+        }
     }
     __syncthreads();
     cgs_finish(a, hs, sh, decision);
@@ -812,6 +832,11 @@ static int ept_for(long long elems, int nthr) {
     return 32;
 }
 
+// An FFT-pass workgroup holding more than 2048 points (up to 8192) runs
+// kBigThreads threads with 8 points each (its own instantiation, NT =
+// kBigThreads); smaller ones run 256 threads.
+static bool pass_big(long long elems) { return elems > 2048; }
+
 static size_t lds_p13(const ConvGeom& g) { return sizeof(float2) * ((size_t)g.CB * (g.M1 + 1) + g.M1); }
 static size_t lds_p2(const ConvGeom& g) { return sizeof(float2) * (3 * (size_t)g.M2); }
 
@@ -839,13 +864,24 @@ hipError_t launch_tables(const ConvGeom& g, float2* tw1, float2* tw2, float2* tw
 hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, float2* T1, hipStream_t s) {
     const dim3 grid((g.M2 + g.CB - 1) / g.CB, nvec);
     const size_t lds = lds_p13(g);
-    const int ept = ept_for((long long)g.CB * g.M1, 256);
+    const long long elems = (long long)g.CB * g.M1;
+    const int ept = ept_for(elems, 256);
+    const dim3 big(kBigThreads);
     if (mode == IN_REV) {
-        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_REV, E>), grid, dim3(256), lds, s, g, in, T1));
+        if (pass_big(elems))
+            hipLaunchKernelGGL((k_pass1<IN_REV, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
+        else
+            SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_REV, E>), grid, dim3(256), lds, s, g, in, T1));
     } else if (mode == IN_SERIES) {
-        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_SERIES, E>), grid, dim3(256), lds, s, g, in, T1));
+        if (pass_big(elems))
+            hipLaunchKernelGGL((k_pass1<IN_SERIES, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
+        else
+            SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_SERIES, E>), grid, dim3(256), lds, s, g, in, T1));
     } else {
-        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_VECS, E>), grid, dim3(256), lds, s, g, in, T1));
+        if (pass_big(elems))
+            hipLaunchKernelGGL((k_pass1<IN_VECS, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
+        else
+            SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_VECS, E>), grid, dim3(256), lds, s, g, in, T1));
     }
     return hipGetLastError();
 }
@@ -854,14 +890,20 @@ hipError_t launch_pass2_matvec(const ConvGeom& g, const float4* AB, const float2
                                hipStream_t s) {
     const dim3 grid(g.M1 / 2 + 1);
     const int ept = ept_for(2LL * g.M2, 256);
-    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_matvec<E>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2));
+    if (pass_big(2LL * g.M2))
+        hipLaunchKernelGGL((k_pass2_matvec<8, kBigThreads>), grid, dim3(kBigThreads), lds_p2(g), s, g, AB, T1, T2);
+    else
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_matvec<E>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2));
     return hipGetLastError();
 }
 
 hipError_t launch_pass2_embed(const ConvGeom& g, const float2* T1, float4* AB, hipStream_t s) {
     const dim3 grid(g.M1 / 2 + 1);
     const int ept = ept_for(2LL * g.M2, 256);
-    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_embed<E>), grid, dim3(256), lds_p2(g), s, g, T1, AB));
+    if (pass_big(2LL * g.M2))
+        hipLaunchKernelGGL((k_pass2_embed<8, kBigThreads>), grid, dim3(kBigThreads), lds_p2(g), s, g, T1, AB);
+    else
+        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_embed<E>), grid, dim3(256), lds_p2(g), s, g, T1, AB));
     return hipGetLastError();
 }
 
@@ -879,11 +921,19 @@ hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3O
                         hipStream_t s) {
     const dim3 grid((g.M2 + g.CB - 1) / g.CB, nvec);
     const size_t lds = lds_p13(g);
-    const int ept = ept_for((long long)g.CB * g.M1, 256);
+    const long long elems = (long long)g.CB * g.M1;
+    const int ept = ept_for(elems, 256);
+    const dim3 big(kBigThreads);
     if (mode == OUT_SLICE) {
-        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_SLICE, E>), grid, dim3(256), lds, s, g, T2, o));
+        if (pass_big(elems))
+            hipLaunchKernelGGL((k_pass3<OUT_SLICE, 8, kBigThreads>), grid, big, lds, s, g, T2, o);
+        else
+            SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_SLICE, E>), grid, dim3(256), lds, s, g, T2, o));
     } else {
-        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_HANKEL, E>), grid, dim3(256), lds, s, g, T2, o));
+        if (pass_big(elems))
+            hipLaunchKernelGGL((k_pass3<OUT_HANKEL, 8, kBigThreads>), grid, big, lds, s, g, T2, o);
+        else
+            SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_HANKEL, E>), grid, dim3(256), lds, s, g, T2, o));
     }
     return hipGetLastError();
 }
@@ -919,6 +969,11 @@ hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s) {
     const unsigned nchunks = (unsigned)((a.n + kProjRows - 1) / kProjRows);
     const unsigned ngrp = a.ncols > 0 ? (unsigned)((a.ncols + kProjCols - 1) / kProjCols) : 1u;
     hipLaunchKernelGGL(k_cgs_project, dim3(nchunks, ngrp), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs_colsum(const ReduceArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cgs_colsum, dim3((unsigned)(a.ncols + 1)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -967,6 +1022,10 @@ hipError_t set_kernel_attributes() {
     SSA_ALLOW((k_pass3<OUT_SLICE, 32>));
     SSA_ALLOW((k_pass3<OUT_HANKEL, 4>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 8>));
     SSA_ALLOW((k_pass3<OUT_HANKEL, 16>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 32>));
+    SSA_ALLOW((k_pass1<IN_REV, 8, kBigThreads>)); SSA_ALLOW((k_pass1<IN_SERIES, 8, kBigThreads>));
+    SSA_ALLOW((k_pass1<IN_VECS, 8, kBigThreads>));
+    SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads>));
+    SSA_ALLOW((k_pass2_matvec<8, kBigThreads>)); SSA_ALLOW((k_pass2_embed<8, kBigThreads>));
     SSA_ALLOW_EPT(k_pass2_matvec);
     SSA_ALLOW_EPT(k_pass2_embed);
     SSA_ALLOW_EPT(k_pass2_recon);

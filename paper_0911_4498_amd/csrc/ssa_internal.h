@@ -69,6 +69,7 @@ struct ReduceArgs {
     unsigned long long seed, stream_ctr;
     int track;          // 1: the coefficient is an entry of B (count it in state[0])
     int full;           // 1: the basis already spans the whole space -> zero vector
+    int presummed;      // 1: h[0..ncols] already holds the column sums (k_cgs_colsum)
     double tol_bd;      // breakdown threshold relative to state[0]
 };
 
@@ -76,6 +77,7 @@ constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many term
 constexpr int kProjRows = 1024;  // rows per workgroup in the projection kernel (256 x float4)
 constexpr int kProjCols = 8;     // basis columns per workgroup in the projection kernel
 constexpr int kMaxCols = 2048;   // most basis columns one projection handles
+constexpr int kColsumChunks = 256;  // above this many row chunks the column sums get their own launch
 
 // launchers (kernels.hip); each returns hipSuccess or the launch error
 hipError_t launch_tables(const ConvGeom& g, float2* tw1, float2* tw2, float2* tw_lo, float2* tw_hi,
@@ -97,6 +99,7 @@ hipError_t launch_check_finite(const double* f, long long N, double* flag, hipSt
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_cgs_colsum(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols,
                              const double* h, const double* scale, float* out, long long n,
