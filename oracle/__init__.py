@@ -22,6 +22,9 @@ part of the paper it follows:
                                the explicit matrix does not fit.
 * :func:`gkl_raw`           -- the raw Lanczos quantities, for the relations
                                of eqs. lbdiagm1 / lbdiagm2.
+* :func:`trajectory_2d`, :func:`hankelize_2d`, :func:`ssa2d_dense`,
+  :func:`reconstruct_2d`    -- 2D-SSA (the Hankel-with-Hankel-blocks case of
+                               Sec. 1 and Sec. 3.3) from the definition.
 
 Index convention: 0-based, ``X[i, j] = f[i + j]``, ``K = N - L + 1``.
 """
@@ -73,6 +76,10 @@ def _bind(lib):
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        _D, _D, _D, _I]
     lib.oracle_gkl_raw.argtypes = [_D, _L, _L, ctypes.c_int, _D, _D, _D, _D, _D]
+    lib.oracle_trajectory_2d.argtypes = [_D, _L, _L, _L, _L, _D]
+    lib.oracle_hankelize_2d.argtypes = [_D, _L, _L, _L, _L, _D]
+    lib.oracle_ssa2d_dense.argtypes = [_D, _L, _L, _L, _L, ctypes.c_int, _D, _D, _D]
+    lib.oracle_reconstruct_2d.argtypes = [_L, _L, _L, _L, ctypes.c_int, _D, _D, _D, _I, _I, ctypes.c_int, _D]
     for name in ("oracle_trajectory", "oracle_jacobi_svd", "oracle_hankelize",
                  "oracle_rank1_hankelize", "oracle_reconstruct", "oracle_ssa_dense",
                  "oracle_matvec", "oracle_rmatvec", "oracle_lanczos_svd", "oracle_gkl_raw"):
@@ -304,3 +311,58 @@ def gkl_raw(f, L: int, d: int, p0):
     if rc < 0:
         raise ValueError("invalid arguments")
     return Ub, Vb, a, b
+
+
+def _groups_csr(groups):
+    offs = [0]
+    mem: list[int] = []
+    for g in groups:
+        mem.extend(int(i) for i in g)
+        offs.append(len(mem))
+    return np.asarray(offs, dtype=np.int32), np.asarray(mem if mem else [0], dtype=np.int32)
+
+
+def trajectory_2d(F, Lx: int, Ly: int) -> np.ndarray:
+    """2D-SSA trajectory matrix X[(a, b), (c, d)] = F[a + c, b + d]; rows a*Ly + b, columns c*Ky + d."""
+    F = _f64(F)
+    Nx, Ny = F.shape
+    X = np.empty((Lx * Ly, (Nx - Lx + 1) * (Ny - Ly + 1)))
+    if _load().oracle_trajectory_2d(_dp(F), Nx, Ny, Lx, Ly, _dp(X)) < 0:
+        raise ValueError("invalid shape or window")
+    return X
+
+
+def hankelize_2d(Y, Nx: int, Ny: int, Lx: int, Ly: int) -> np.ndarray:
+    """2D diagonal averaging of an (Lx Ly) x (Kx Ky) matrix into an Nx x Ny array."""
+    Y = _f64(Y)
+    G = np.empty((Nx, Ny))
+    if _load().oracle_hankelize_2d(_dp(Y), Nx, Ny, Lx, Ly, _dp(G)) < 0:
+        raise ValueError("invalid shape or window")
+    return G
+
+
+def ssa2d_dense(F, Lx: int, Ly: int, k: int):
+    """2D-SSA from the definition: the k leading triples of the explicit 2D trajectory matrix."""
+    F = _f64(F)
+    Nx, Ny = F.shape
+    L, K = Lx * Ly, (Nx - Lx + 1) * (Ny - Ly + 1)
+    s = np.empty(k)
+    U = np.empty((L, k))
+    V = np.empty((K, k))
+    if _load().oracle_ssa2d_dense(_dp(F), Nx, Ny, Lx, Ly, k, _dp(s), _dp(U), _dp(V)) < 0:
+        raise ValueError("invalid arguments")
+    return s, U, V
+
+
+def reconstruct_2d(Nx: int, Ny: int, Lx: int, Ly: int, sigma, U, V, groups) -> np.ndarray:
+    """2D grouping + diagonal averaging: one Nx x Ny array per group of triple indices."""
+    sigma = _f64(sigma)
+    U = _f64(U)
+    V = _f64(V)
+    offs, mem = _groups_csr(groups)
+    out = np.empty((len(groups), Nx, Ny))
+    rc = _load().oracle_reconstruct_2d(Nx, Ny, Lx, Ly, sigma.size, _dp(sigma), _dp(U), _dp(V),
+                                       offs.ctypes.data_as(_I), mem.ctypes.data_as(_I), len(groups), _dp(out))
+    if rc < 0:
+        raise ValueError("invalid arguments")
+    return out

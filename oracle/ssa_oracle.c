@@ -15,6 +15,11 @@
  *   - diagonal averaging (Hankelization)         (Sec. 2.4, eq. hankelization)
  *   - rank-1 Hankelization as antidiagonal sums  (Sec. 5, eq. hankelization1)
  *   - grouping                                   (Sec. 2.3)
+ * and for two-dimensional arrays (2D-SSA, named in Sec. 1 and Sec. 3.3 as the
+ * case whose trajectory matrix is Hankel with Hankel blocks):
+ *   - the 2D trajectory matrix, its SVD and the 2D diagonal averaging,
+ *     from the definition (explicit matrix, the same Jacobi SVD, direct
+ *     averaging over the index sets a + c = i, b + d = j);
  * and, for sizes where the explicit L x K matrix is too large ("tier B"):
  *   - Golub-Kahan-Lanczos bidiagonalization      (Sec. 3.1, Algorithm 1) with
  *     full reorthogonalization by modified Gram-Schmidt applied twice
@@ -617,5 +622,121 @@ int oracle_gkl_raw(const double* f, long N, long L, int d, const double* p0, dou
         for (long i = 0; i < L; ++i) Ub[(long)j * L + i] = x[i] / b;
     }
     free(x);
+    return 0;
+}
+
+/*
+ * 2D-SSA.  An Nx x Ny array F (row-major, F[i][j] at i * Ny + j) with window
+ * Lx x Ly; Kx = Nx - Lx + 1, Ky = Ny - Ly + 1.  Each column of the trajectory
+ * matrix is one Lx x Ly sub-array of F, read row by row:
+ *   X[(a, b), (c, d)] = F[a + c][b + d],
+ * row index a * Ly + b (a < Lx, b < Ly), column index c * Ky + d (c < Kx,
+ * d < Ky); X is (Lx Ly) x (Kx Ky), Hankel with Hankel blocks.
+ */
+static int check_2d(long Nx, long Ny, long Lx, long Ly) {
+    if (Nx < 1 || Ny < 1 || Lx < 1 || Ly < 1 || Lx > Nx || Ly > Ny) return -1;
+    if (Lx * Ly < 2 || (Nx - Lx + 1) * (Ny - Ly + 1) < 2) return -1;
+    return 0;
+}
+
+int oracle_trajectory_2d(const double* F, long Nx, long Ny, long Lx, long Ly, double* X) {
+    if (check_2d(Nx, Ny, Lx, Ly)) return -1;
+    long Kx = Nx - Lx + 1, Ky = Ny - Ly + 1, ncol = Kx * Ky;
+    for (long a = 0; a < Lx; ++a)
+        for (long b = 0; b < Ly; ++b)
+            for (long c = 0; c < Kx; ++c)
+                for (long d = 0; d < Ky; ++d)
+                    X[(a * Ly + b) * ncol + c * Ky + d] = F[(a + c) * Ny + (b + d)];
+    return 0;
+}
+
+/*
+ * 2D diagonal averaging of an (Lx Ly) x (Kx Ky) matrix Y: G[i][j] is the
+ * mean of Y[(a, b), (c, d)] over all a + c = i, b + d = j (G is Nx x Ny).
+ */
+int oracle_hankelize_2d(const double* Y, long Nx, long Ny, long Lx, long Ly, double* G) {
+    if (check_2d(Nx, Ny, Lx, Ly)) return -1;
+    long Kx = Nx - Lx + 1, Ky = Ny - Ly + 1, ncol = Kx * Ky;
+    for (long i = 0; i < Nx; ++i)
+        for (long j = 0; j < Ny; ++j) {
+            double s = 0.0;
+            long cnt = 0;
+            for (long a = 0; a < Lx; ++a) {
+                long c = i - a;
+                if (c < 0 || c >= Kx) continue;
+                for (long b = 0; b < Ly; ++b) {
+                    long d = j - b;
+                    if (d < 0 || d >= Ky) continue;
+                    s += Y[(a * Ly + b) * ncol + c * Ky + d];
+                    ++cnt;
+                }
+            }
+            G[i * Ny + j] = s / (double)cnt;
+        }
+    return 0;
+}
+
+/*
+ * 2D-SSA from the definition: the k leading triples of the explicit 2D
+ * trajectory matrix (Jacobi SVD): sigma[k], U ((Lx Ly) x k row-major; column
+ * i reshaped row by row is the Lx x Ly eigen-array), V ((Kx Ky) x k).
+ */
+int oracle_ssa2d_dense(const double* F, long Nx, long Ny, long Lx, long Ly, int k, double* sigma,
+                       double* U, double* V) {
+    if (check_2d(Nx, Ny, Lx, Ly)) return -1;
+    long L = Lx * Ly, K = (Nx - Lx + 1) * (Ny - Ly + 1);
+    long r = L < K ? L : K;
+    if (k < 1 || k > r) return -1;
+    double* X = (double*)malloc(sizeof(double) * L * K);
+    double* s = (double*)malloc(sizeof(double) * r);
+    double* UU = (double*)malloc(sizeof(double) * L * r);
+    double* VV = (double*)malloc(sizeof(double) * K * r);
+    if (!X || !s || !UU || !VV) { free(X); free(s); free(UU); free(VV); return -3; }
+    oracle_trajectory_2d(F, Nx, Ny, Lx, Ly, X);
+    int sweeps = oracle_jacobi_svd(X, L, K, 1e-15, 60, s, UU, VV);
+    for (int c = 0; c < k; ++c) sigma[c] = s[c];
+    for (long i = 0; i < L; ++i)
+        for (int c = 0; c < k; ++c) U[i * k + c] = UU[i * r + c];
+    for (long i = 0; i < K; ++i)
+        for (int c = 0; c < k; ++c) V[i * k + c] = VV[i * r + c];
+    free(X); free(s); free(UU); free(VV);
+    return sweeps < 0 ? 1 : 0;
+}
+
+/*
+ * Grouping + 2D diagonal averaging: out[g] (Nx x Ny) is the 2D averaging of
+ * sum_{i in I_g} sigma_i U_i V_i^T, each term averaged directly:
+ * G[i][j] = sigma / cnt * sum_{a + c = i, b + d = j} U[(a, b)] V[(c, d)].
+ */
+int oracle_reconstruct_2d(long Nx, long Ny, long Lx, long Ly, int k, const double* sigma,
+                          const double* U, const double* V, const int* offsets, const int* members,
+                          int m, double* out) {
+    if (check_2d(Nx, Ny, Lx, Ly) || k <= 0 || m <= 0) return -1;
+    long Kx = Nx - Lx + 1, Ky = Ny - Ly + 1;
+    for (int grp = 0; grp < m; ++grp) {
+        for (int t = offsets[grp]; t < offsets[grp + 1]; ++t)
+            if (members[t] < 0 || members[t] >= k) return -1;
+        double* o = out + (long)grp * Nx * Ny;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < Nx; ++i)
+            for (long j = 0; j < Ny; ++j) {
+                double acc = 0.0;
+                long cnt = 0;
+                for (long a = 0; a < Lx; ++a) {
+                    long c = i - a;
+                    if (c < 0 || c >= Kx) continue;
+                    for (long b = 0; b < Ly; ++b) {
+                        long d = j - b;
+                        if (d < 0 || d >= Ky) continue;
+                        ++cnt;
+                        for (int t = offsets[grp]; t < offsets[grp + 1]; ++t) {
+                            int q = members[t];
+                            acc += sigma[q] * U[(a * Ly + b) * k + q] * V[(c * Ky + d) * k + q];
+                        }
+                    }
+                }
+                o[i * Ny + j] = acc / (double)cnt;
+            }
+    }
     return 0;
 }

@@ -140,6 +140,25 @@ def hmatrix_series(N: int = 400, Q: int = 200, seed: int = 1006) -> np.ndarray:
 
 # --- structured test signals -------------------------------------------------
 
+def array2d(Nx: int, Ny: int, seed: int = 1007) -> np.ndarray:
+    """2D-SSA input (Nx x Ny): three plane waves cos(2 pi (i / px + j / py) + phi) with periods
+    log-uniform in [8, 200] along each axis and amplitudes U[0.5, 2], a smooth bilinear trend
+    and N(0, 0.1^2) noise.  The paper has no 2D workload; this stands in for an image with a
+    few periodic textures."""
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(Nx, dtype=np.float64), np.arange(Ny, dtype=np.float64), indexing="ij")
+    F = np.zeros((Nx, Ny))
+    for _ in range(3):
+        px, py = np.exp(rng.uniform(np.log(8.0), np.log(200.0), 2))
+        amp = rng.uniform(0.5, 2.0)
+        phi = rng.uniform(0.0, 2 * np.pi)
+        F += amp * np.cos(2 * np.pi * (i / px + j / py) + phi)
+    c = rng.uniform(-1.0, 1.0, 3)
+    F += c[0] + c[1] * i / Nx + c[2] * j / Ny
+    F += rng.normal(0.0, 0.1, (Nx, Ny))
+    return F
+
+
 def sinusoid(N: int, period: float, amp: float = 1.0, phase: float = 0.0) -> np.ndarray:
     t = _t(N)
     return amp * np.cos(2 * np.pi * t / period + phase)

@@ -454,3 +454,89 @@ def test_tier_b_exact_rank_restarts():
     sA, _, _ = oracle.ssa_dense(f, L, 4)
     np.testing.assert_allclose(sB[:2], sA[:2], rtol=1e-11)
     assert np.all(np.abs(sB[2:]) < 1e-9 * sA[0])
+
+
+# --- 2D-SSA (Hankel-with-Hankel-blocks trajectory matrix) -----------------------------
+
+def _hankel1(g, L):
+    return scipy.linalg.hankel(g[:L], g[L - 1:])
+
+
+@pytest.mark.parametrize("Nx,Ny,Lx,Ly", [(6, 9, 3, 4), (5, 5, 2, 3), (8, 4, 5, 2)])
+def test_trajectory_2d_of_separable_array_is_kronecker(Nx, Ny, Lx, Ly):
+    """F = g h^T gives X[(a,b),(c,d)] = g[a+c] h[b+d] = kron(X_g, X_h) with the library Hankel
+    matrices of g and h (rows a*Ly+b, columns c*Ky+d)."""
+    rng = np.random.default_rng(Nx * 100 + Ny)
+    g, h = rng.normal(size=Nx), rng.normal(size=Ny)
+    X = oracle.trajectory_2d(np.outer(g, h), Lx, Ly)
+    np.testing.assert_array_equal(X, np.kron(_hankel1(g, Lx), _hankel1(h, Ly)))
+
+
+def test_ssa2d_separable_singular_values_are_products():
+    """Singular values of a Kronecker product are the products of the factors' values."""
+    rng = np.random.default_rng(3)
+    Nx, Ny, Lx, Ly = 9, 11, 4, 5
+    g, h = rng.normal(size=Nx), rng.normal(size=Ny)
+    sg = np.linalg.svd(_hankel1(g, Lx), compute_uv=False)
+    sh = np.linalg.svd(_hankel1(h, Ly), compute_uv=False)
+    ref = np.sort(np.outer(sg, sh).ravel())[::-1]
+    k = min(Lx * Ly, (Nx - Lx + 1) * (Ny - Ly + 1))
+    s, U, V = oracle.ssa2d_dense(np.outer(g, h), Lx, Ly, k)
+    np.testing.assert_allclose(s, ref[:k], rtol=1e-11, atol=1e-12 * ref[0])
+
+
+@pytest.mark.parametrize("Nx,Ny,Lx,Ly,k", [(7, 8, 3, 4, 6), (10, 6, 6, 2, 5), (12, 12, 5, 7, 9)])
+def test_ssa2d_dense_matches_lapack(Nx, Ny, Lx, Ly, k):
+    rng = np.random.default_rng(Nx + 7 * Ny)
+    F = rng.normal(size=(Nx, Ny))
+    X = oracle.trajectory_2d(F, Lx, Ly)
+    Ur, sr, Vrt = np.linalg.svd(X, full_matrices=False)
+    s, U, V = oracle.ssa2d_dense(F, Lx, Ly, k)
+    np.testing.assert_allclose(s, sr[:k], rtol=1e-11)
+    np.testing.assert_allclose(X @ V, U * s, atol=1e-10 * sr[0])
+    np.testing.assert_allclose(np.abs(np.sum(U * Ur[:, :k], axis=0)), 1.0, atol=1e-9)
+
+
+def test_ssa2d_one_row_is_basic_ssa():
+    """A 1 x N array with a 1 x L window is Basic SSA of the row."""
+    f = np.cos(0.37 * np.arange(40)) + 0.1 * np.random.default_rng(1).normal(size=40)
+    s2, U2, V2 = oracle.ssa2d_dense(f[None, :], 1, 15, 6)
+    s1, U1, V1 = oracle.ssa_dense(f, 15, 6)
+    np.testing.assert_allclose(s2, s1, rtol=1e-12)
+    np.testing.assert_allclose(np.abs(np.sum(U2 * U1, axis=0)), 1.0, atol=1e-10)
+
+
+def test_ssa2d_plane_wave_has_rank_two():
+    """F[i,j] = cos(w1 i + w2 j + phi) = Re(z1^i z2^j e^{i phi}): two nonzero singular values;
+    a product of two cosines in i and j: four."""
+    i, j = np.meshgrid(np.arange(12), np.arange(14), indexing="ij")
+    s, _, _ = oracle.ssa2d_dense(np.cos(0.4 * i + 0.9 * j + 0.3), 5, 6, 8)
+    assert s[1] > 1e-3 * s[0] and np.all(s[2:] < 1e-10 * s[0])
+    s, _, _ = oracle.ssa2d_dense(np.cos(0.4 * i) * np.cos(0.9 * j + 0.2), 5, 6, 8)
+    assert s[3] > 1e-3 * s[0] and np.all(s[4:] < 1e-10 * s[0])
+
+
+def test_hankelize_2d_of_kronecker_factorizes():
+    """For Y = kron(Y1, Y2) the 2D means over a+c=i, b+d=j factor into the 1D means of Y1 and Y2."""
+    rng = np.random.default_rng(5)
+    Nx, Ny, Lx, Ly = 7, 9, 3, 4
+    Y1 = rng.normal(size=(Lx, Nx - Lx + 1))
+    Y2 = rng.normal(size=(Ly, Ny - Ly + 1))
+    G = oracle.hankelize_2d(np.kron(Y1, Y2), Nx, Ny, Lx, Ly)
+    np.testing.assert_allclose(G, np.outer(oracle.hankelize(Y1), oracle.hankelize(Y2)), rtol=1e-12, atol=1e-14)
+
+
+def test_reconstruct_2d_sums_back_to_the_array():
+    """All triples in one group give back F; two groups add up to it; each group equals the
+    2D averaging of its explicit low-rank matrix."""
+    rng = np.random.default_rng(8)
+    Nx, Ny, Lx, Ly = 8, 10, 3, 4
+    F = rng.normal(size=(Nx, Ny))
+    r = min(Lx * Ly, (Nx - Lx + 1) * (Ny - Ly + 1))
+    s, U, V = oracle.ssa2d_dense(F, Lx, Ly, r)
+    whole = oracle.reconstruct_2d(Nx, Ny, Lx, Ly, s, U, V, [list(range(r))])[0]
+    np.testing.assert_allclose(whole, F, atol=1e-11)
+    parts = oracle.reconstruct_2d(Nx, Ny, Lx, Ly, s, U, V, [[0, 2], [1] + list(range(3, r))])
+    np.testing.assert_allclose(parts.sum(axis=0), F, atol=1e-11)
+    Y = (U[:, [0, 2]] * s[[0, 2]]) @ V[:, [0, 2]].T
+    np.testing.assert_allclose(parts[0], oracle.hankelize_2d(Y, Nx, Ny, Lx, Ly), atol=1e-12)

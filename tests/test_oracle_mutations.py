@@ -44,6 +44,17 @@ MUTATIONS = {
     "realization_variance_biased": (
         "var[n] = R > 1 ? v / (double)(R - 1) : 0.0;", "var[n] = R > 1 ? v / (double)R : 0.0;",
         [pins.test_realization_stats_match_numpy]),
+    "trajectory_2d_window_reversed": (
+        "X[(a * Ly + b) * ncol + c * Ky + d] = F[(a + c) * Ny + (b + d)];",
+        "X[(a * Ly + b) * ncol + c * Ky + d] = F[(a + c) * Ny + (Ly - 1 - b + d)];",
+        [lambda: pins.test_trajectory_2d_of_separable_array_is_kronecker(6, 9, 3, 4)]),
+    "hankelize_2d_count_off_by_one": (
+        "G[i * Ny + j] = s / (double)cnt;", "G[i * Ny + j] = s / (double)(cnt + 1);",
+        [pins.test_hankelize_2d_of_kronecker_factorizes]),
+    "reconstruct_2d_v_transposed": (
+        "acc += sigma[q] * U[(a * Ly + b) * k + q] * V[(c * Ky + d) * k + q];",
+        "acc += sigma[q] * U[(a * Ly + b) * k + q] * V[(d * Kx + c) * k + q];",
+        [pins.test_reconstruct_2d_sums_back_to_the_array]),
     "trajectory_shifted": (
         "X[i * K + j] = f[i + j];", "X[i * K + j] = f[i + j + (i + j + 1 < N)];",
         [pins.test_trajectory_matches_library_hankel]),
