@@ -109,6 +109,27 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts,
                    size_t* workspace_bytes, ssa_plan* out);
 
 /*
+ * ssa_embed_plan_2d -- 2D-SSA (named in Sec. 1 and Sec. 3.3 as the case whose
+ * trajectory matrix is Hankel with Hankel blocks): an Nx x Ny array F
+ * (row-major, F[i][j] at i * Ny + j) with an Lx x Ly window.  The trajectory
+ * matrix is X[(a, b), (c, d)] = F[a + c][b + d], rows a * Ly + b (a < Lx,
+ * b < Ly), columns c * Ky + d (c < Kx = Nx - Lx + 1, d < Ky = Ny - Ly + 1).
+ * The plan is then used like a 1D plan of N = Nx Ny, L = Lx Ly, K = Kx Ky:
+ * ssa_truncated_svd takes that N and L (the array flattened row by row) and
+ * returns U ((Lx Ly) x k: each u_i an Lx x Ly array row by row) and V
+ * ((Kx Ky) x k); ssa_matvec takes and returns such compressed vectors;
+ * ssa_reconstruct writes m arrays of Nx x Ny (row-major), the 2D diagonal
+ * averaging (mean over a + c = i, b + d = j).  Products and averaging run on
+ * the row-pitch-Ny flattening, where X is a row/column selection of the 1D
+ * Hankel matrix of the flattened array, so the FFT length covers Nx Ny.
+ *   1 <= Lx <= Nx, 1 <= Ly <= Ny, Lx Ly >= 2, Kx Ky >= 2,
+ *   1 <= k_max <= min(Lx Ly, Kx Ky).
+ * Errors: SSA_EINVAL.
+ */
+int ssa_embed_plan_2d(long long Nx, long long Ny, long long Lx, long long Ly, int k_max, const ssa_opts* opts,
+                      size_t* workspace_bytes, ssa_plan* out);
+
+/*
  * ssa_plan_bind -- attach caller-owned device workspace (>= workspace_bytes,
  * 256-byte aligned) and a HIP stream (hipStream_t passed as void*, NULL =
  * the default stream).  Errors: SSA_EINVAL (null plan/workspace, bad

@@ -73,9 +73,12 @@ FftStages make_stages(int n) {
 }  // namespace
 
 struct ssa_plan_s {
-    long long N, L, K;  // as requested
+    long long N, L, K;  // as requested (2D: N = Nx Ny, L = Lx Ly, K = Kx Ky)
     int transposed;     // L > K: solved for X^T (window K)
     long long Li, Ki;   // internal window / lag count, Li <= Ki
+    int is2d;           // 2D-SSA: an Nx x Ny array with an Lx x Ly window, flattened row by row
+    long long Nx, Ny, Lx, Ly, Kx, Ky;
+    long long rows[2], width[2];  // shape of the internal U-side (0) and V-side (1) vectors
     int k_max, d_max, check_every;
     int keep;   // thick restart: Ritz pairs kept per cycle (0: no restart)
     int onesided;  // 1: only the length-Li basis (U) is reorthogonalized
@@ -204,16 +207,27 @@ struct ProfScope {
         if (e_ != hipSuccess) return SSA_EDEVICE;      \
     } while (0)
 
-// One convolution with the embedded series: out[t] = y[n_in-1+t] - coef*prev[t].
-int convolve(ssa_plan p, const ConvGeom& g, const float* x, long long n_in, float* out, const float* prev,
+// One convolution with the embedded series: out[t] = y[n_in-1+t] - coef*prev[t],
+// for an input vector of side `side` (0: U side, 1: V side).  A 2D plan works
+// in the padded row-pitch coordinates (n_in = (rows - 1) Ny + width) and
+// scatters the input / gathers the output there, so X of 2D-SSA is the
+// row/column selection of the 1D Hankel matrix of the flattened array.
+int convolve(ssa_plan p, const ConvGeom& g, const float* x, int side, float* out, const float* prev,
              const double* coef) {
     hipStream_t s = p->stream;
+    const long long n_in = p->is2d ? (p->rows[side] - 1) * p->Ny + p->width[side] : p->width[side];
+    const double len_in = (double)p->rows[side] * p->width[side];
+    const double len_out = (double)p->rows[1 - side] * p->width[1 - side];
     P1In in{};
     in.x = x;
     in.n_in = n_in;
+    if (p->is2d) {
+        in.pitch = p->Ny;
+        in.win = (int)p->width[side];
+    }
     const double mp = (double)g.Mp;
     {
-        ProfScope ps(p, SSA_PROF_PASS1, 4.0 * n_in + 8.0 * mp);
+        ProfScope ps(p, SSA_PROF_PASS1, 4.0 * len_in + 8.0 * mp);
         SSA_TRY(launch_pass1(g, IN_REV, in, 1, at<float2>(p, p->o_t1), s));
     }
     {
@@ -226,8 +240,12 @@ int convolve(ssa_plan p, const ConvGeom& g, const float* x, long long n_in, floa
     o.n_out = p->N + 1 - n_in;
     o.prev = prev;
     o.coef = coef;
+    if (p->is2d) {
+        o.pitch = p->Ny;
+        o.wout = (int)p->width[1 - side];
+    }
     {
-        ProfScope ps(p, SSA_PROF_PASS3, 8.0 * mp + 4.0 * o.n_out * (prev ? 2.0 : 1.0));
+        ProfScope ps(p, SSA_PROF_PASS3, 8.0 * mp + 4.0 * len_out * (prev ? 2.0 : 1.0));
         SSA_TRY(launch_pass3(g, OUT_SLICE, at<float2>(p, p->o_t2), o, 1, s));
     }
     return SSA_OK;
@@ -316,12 +334,10 @@ hipError_t g_attr_err = hipSuccess;
 
 extern "C" {
 
-int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, size_t* workspace_bytes,
-                   ssa_plan* out) {
-    if (!out || !workspace_bytes) return SSA_EINVAL;
-    *out = nullptr;
-    if (N <= 2 || L <= 1 || L >= N) return SSA_EINVAL;
-    const long long K = N - L + 1;
+// A plan for a series of N values whose trajectory matrix is L x K; for 2D
+// plans (is2d) N = Nx Ny, L = Lx Ly, K = Kx Ky.
+static int plan_create(long long N, long long L, long long K, int is2d, long long Nx, long long Ny, long long Lx,
+                       long long Ly, int k_max, const ssa_opts* opts, size_t* workspace_bytes, ssa_plan* out) {
     const long long r = std::min(L, K);
     if (k_max < 1 || k_max > r || k_max > 256) return SSA_EINVAL;
     ssa_plan p = new (std::nothrow) ssa_plan_s();
@@ -332,6 +348,25 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, si
     p->transposed = L > K ? 1 : 0;
     p->Li = std::min(L, K);
     p->Ki = std::max(L, K);
+    p->is2d = is2d;
+    if (is2d) {
+        p->Nx = Nx;
+        p->Ny = Ny;
+        p->Lx = Lx;
+        p->Ly = Ly;
+        p->Kx = Nx - Lx + 1;
+        p->Ky = Ny - Ly + 1;
+        // internal window: the smaller of the two shapes (the transpose uses window Kx x Ky)
+        const int sL = p->transposed ? 1 : 0;
+        p->rows[sL] = Lx;
+        p->width[sL] = Ly;
+        p->rows[1 - sL] = p->Kx;
+        p->width[1 - sL] = p->Ky;
+    } else {
+        p->rows[0] = p->rows[1] = 1;
+        p->width[0] = p->Li;
+        p->width[1] = p->Ki;
+    }
     p->k_max = k_max;
     int d_max = opts && opts->d_max > 0 ? opts->d_max : 8 * k_max + 32;
     d_max = (int)std::min<long long>({(long long)d_max, r, (long long)kMaxDmax});
@@ -407,6 +442,25 @@ int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, si
     return SSA_OK;
 }
 
+int ssa_embed_plan(long long N, long long L, int k_max, const ssa_opts* opts, size_t* workspace_bytes,
+                   ssa_plan* out) {
+    if (!out || !workspace_bytes) return SSA_EINVAL;
+    *out = nullptr;
+    if (N <= 2 || L <= 1 || L >= N) return SSA_EINVAL;
+    return plan_create(N, L, N - L + 1, 0, 0, 0, 0, 0, k_max, opts, workspace_bytes, out);
+}
+
+int ssa_embed_plan_2d(long long Nx, long long Ny, long long Lx, long long Ly, int k_max, const ssa_opts* opts,
+                      size_t* workspace_bytes, ssa_plan* out) {
+    if (!out || !workspace_bytes) return SSA_EINVAL;
+    *out = nullptr;
+    if (Nx < 1 || Ny < 1 || Lx < 1 || Ly < 1 || Lx > Nx || Ly > Ny) return SSA_EINVAL;
+    if (Ny > (1LL << 30) || Nx > (1LL << 40) / Ny) return SSA_EINVAL;
+    const long long L = Lx * Ly, K = (Nx - Lx + 1) * (Ny - Ly + 1);
+    if (L < 2 || K < 2) return SSA_EINVAL;
+    return plan_create(Nx * Ny, L, K, 1, Nx, Ny, Lx, Ly, k_max, opts, workspace_bytes, out);
+}
+
 int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_stream) {
     if (!p || !workspace_dev) return SSA_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
@@ -445,9 +499,9 @@ int ssa_matvec(ssa_plan p, int transpose, const float* x_dev, float* y_dev) {
     if (!p || !x_dev || !y_dev) return SSA_EINVAL;
     if (!p->bound) return SSA_ENOMEM;
     if (!p->embedded) return SSA_ESTATE;
-    // X x: x has K entries; X^T x: x has L entries (user's L, K)
-    const long long n_in = transpose ? p->L : p->K;
-    return convolve(p, bound_geom(p), x_dev, n_in, y_dev, nullptr, nullptr);
+    // X x: x has K entries; X^T x: x has L entries (user's L, K; side 0 is the shorter one)
+    const int side = transpose ? (p->transposed ? 1 : 0) : (p->transposed ? 0 : 1);
+    return convolve(p, bound_geom(p), x_dev, side, y_dev, nullptr, nullptr);
 }
 
 int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long long L, int k, double* sigma_dev,
@@ -511,7 +565,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     int pend_jj = -1, pend_buf = 0, cur_buf = 0;
     for (int j = 1;; ++j) {
         // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
-        rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, Li, r,
+        rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, 0, r,
                       j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
         if (rc != SSA_OK) return rc;
         // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
@@ -541,7 +595,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         }
         if (stop) break;
         // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
-        rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, Ki, r, U + (long long)(j - 1) * p->ldU, alpha + j);
+        rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, 1, r, U + (long long)(j - 1) * p->ldU, alpha + j);
         if (rc != SSA_OK) return rc;
         rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
         if (rc != SSA_OK) return rc;
@@ -632,7 +686,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
             bool first = true;
             while (nv - 1 < d_cap) {
                 // p = X v_nv - alpha_nv u_nu (first step: the Gram-Schmidt step removes U' rho)
-                rc = convolve(p, g, V + (long long)(nv - 1) * p->ldV, Ki, r,
+                rc = convolve(p, g, V + (long long)(nv - 1) * p->ldV, 1, r,
                               first ? nullptr : U + (long long)(nu - 1) * p->ldU, first ? nullptr : alpha + nv);
                 if (rc != SSA_OK) return rc;
                 rc = orthonormalize(p, U, p->ldU, nu, Li, beta + nu + 1, 1, ctr++);
@@ -641,7 +695,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
                 ++nu;
                 first = false;
                 // r = X^T u_nu - beta_nu v_nv
-                rc = convolve(p, g, U + (long long)(nu - 1) * p->ldU, Li, r, V + (long long)(nv - 1) * p->ldV,
+                rc = convolve(p, g, U + (long long)(nu - 1) * p->ldU, 0, r, V + (long long)(nv - 1) * p->ldV,
                               beta + nu);
                 if (rc != SSA_OK) return rc;
                 rc = orthonormalize(p, V, p->ldV, nv, Ki, alpha + nv + 1, 1, ctr++);
@@ -731,6 +785,13 @@ int ssa_reconstruct(ssa_plan p, const double* sigma_dev, const float* U_dev, con
     in.ldv = K;
     in.lenv = K;
     in.nu = k;
+    if (p->is2d) {  // U_i is Lx x Ly and V_i is Kx x Ky, row by row, scattered with row pitch Ny
+        in.pitch = p->Ny;
+        in.wu = (int)p->Ly;
+        in.wv = (int)p->Ky;
+        in.lenu = (p->Lx - 1) * p->Ny + p->Ly;
+        in.lenv = (p->Kx - 1) * p->Ny + p->Ky;
+    }
     {
         ProfScope ps(p, SSA_PROF_RECON1, 4.0 * (double)k * (L + K) + 16.0 * k * (double)g.Mp);
         SSA_TRY(launch_pass1(g, IN_VECS, in, 2 * k, T1, s));
@@ -757,11 +818,23 @@ int ssa_reconstruct(ssa_plan p, const double* sigma_dev, const float* U_dev, con
         o.L = L;
         o.K = K;
         o.ldo = N;
+        if (p->is2d) {  // counts cnt_x(i) cnt_y(j)
+            o.pitch = p->Ny;
+            o.L = p->Ly;
+            o.K = p->Ky;
+            o.Nx = p->Nx;
+            o.Lx = p->Lx;
+            o.Kx = p->Kx;
+        }
         {
             ProfScope ps(p, SSA_PROF_RECON3, (8.0 * (double)g.Mp + 4.0 * N) * ng);
             SSA_TRY(launch_pass3(g, OUT_HANKEL, T2, o, ng, s));
         }
-        {
+        if (p->is2d) {
+            ProfScope ps(p, SSA_PROF_RECON3, 4.0 * (double)N * ng);
+            SSA_TRY(launch_recon_edges_2d(sigma_dev, U_dev, L, V_dev, K, dgrp, dgrp + ng + 1, ng, p->Nx, p->Ny, p->Lx,
+                                          p->Ly, out_dev + (long long)g0 * N, N, s));
+        } else {
             const long long lmin = std::min(L, K);
             const double ne = lmin <= kEdgeCnt ? (double)N : 2.0 * kEdgeCnt;
             ProfScope ps(p, SSA_PROF_RECON3, 4.0 * ne * ng);

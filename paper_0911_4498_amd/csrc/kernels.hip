@@ -93,15 +93,34 @@ __global__ void k_tables(int M1, int M2, long long Mp, int shift, float2* tw1, f
 // ---------------------------------------------------------------------------
 // pass 1: column FFTs (length M1) of CB adjacent columns, twiddle, store T[k1][n2]
 
+// Position m of the padded coordinates of a width-w array (pitch > 0): its
+// compressed index, or -1 in the gap between rows.
+__device__ __forceinline__ long long compress_index(long long m, long long pitch, int w) {
+    const long long r = m / pitch, c = m - r * pitch;
+    return c < w ? r * w + c : -1;
+}
+
 template <int MODE>
 __device__ __forceinline__ float p1_value(const P1In& a, long long m, int y) {
     if constexpr (MODE == IN_REV) {
-        return m < a.n_in ? a.x[a.n_in - 1 - m] : 0.0f;
+        if (m >= a.n_in) return 0.0f;
+        long long j = a.n_in - 1 - m;
+        if (a.pitch) {
+            j = compress_index(j, a.pitch, a.win);
+            if (j < 0) return 0.0f;
+        }
+        return a.x[j];
     } else if constexpr (MODE == IN_SERIES) {
         return m < a.N ? (float)a.f[m] : 0.0f;
     } else {
-        if (y < a.nu) return m < a.lenu ? a.U[(long long)y * a.ldu + m] : 0.0f;
-        return m < a.lenv ? a.V[(long long)(y - a.nu) * a.ldv + m] : 0.0f;
+        const bool isu = y < a.nu;
+        if (m >= (isu ? a.lenu : a.lenv)) return 0.0f;
+        long long j = m;
+        if (a.pitch) {
+            j = compress_index(m, a.pitch, isu ? a.wu : a.wv);
+            if (j < 0) return 0.0f;
+        }
+        return isu ? a.U[(long long)y * a.ldu + j] : a.V[(long long)(y - a.nu) * a.ldv + j];
     }
 }
 
@@ -438,21 +457,37 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
 // ---------------------------------------------------------------------------
 // pass 3: conj twiddle, inverse column FFTs, emit y[2n], y[2n+1]
 
+// antidiagonal length of position n of a length-n_all series with window L
+__device__ __forceinline__ long long count1(long long n, long long n_all, long long L, long long K) {
+    long long c = n + 1;
+    if (L < c) c = L;
+    if (K < c) c = K;
+    if (n_all - n < c) c = n_all - n;
+    return c;
+}
+
 template <int MODE>
 __device__ __forceinline__ void p3_emit(const P3Out& o, long long m, float val, float coef, int y) {
     if constexpr (MODE == OUT_SLICE) {
-        const long long t = m - (o.n_in - 1);
+        long long t = m - (o.n_in - 1);
         if (t >= 0 && t < o.n_out) {
+            if (o.pitch) {
+                t = compress_index(t, o.pitch, o.wout);
+                if (t < 0) return;
+            }
             float r = val;
             if (o.prev) r -= coef * o.prev[t];
             o.out[t] = r;
         }
     } else {
         if (m < o.N) {
-            long long c = m + 1;
-            if (o.L < c) c = o.L;
-            if (o.K < c) c = o.K;
-            if (o.N - m < c) c = o.N - m;
+            long long c;
+            if (o.pitch) {
+                const long long i = m / o.pitch, j = m - i * o.pitch;
+                c = count1(i, o.Nx, o.Lx, o.Kx) * count1(j, o.pitch, o.L, o.K);
+            } else {
+                c = count1(m, o.N, o.L, o.K);
+            }
             o.out[(long long)y * o.ldo + m] = val / (float)c;
         }
     }
@@ -523,6 +558,36 @@ __global__ __launch_bounds__(256) void k_recon_edges(const double* __restrict__ 
         acc += sigma[i] * s;
     }
     out[(long long)grp * ldo + n] = (float)(acc / (double)(a1 - a0 + 1));
+}
+
+// The same for a 2D array (Nx x Ny, window Lx x Ly, U and V compressed row by
+// row): every position whose count cnt_x(i) cnt_y(j) is at most kEdgeCnt is
+// recomputed as sum_i sigma_i sum_{a+c=i, b+d=j} U_i[a, b] V_i[c, d] / count.
+__global__ __launch_bounds__(256) void k_recon_edges_2d(const double* __restrict__ sigma, const float* __restrict__ U,
+                                                        long long ldu, const float* __restrict__ V, long long ldv,
+                                                        const int* __restrict__ offs, const int* __restrict__ members,
+                                                        long long Nx, long long Ny, long long Lx, long long Ly,
+                                                        float* __restrict__ out, long long ldo) {
+    const int grp = blockIdx.y;
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Nx * Ny) return;
+    const long long Kx = Nx - Lx + 1, Ky = Ny - Ly + 1;
+    const long long i = m / Ny, j = m - i * Ny;
+    const long long a0 = i - Kx + 1 > 0 ? i - Kx + 1 : 0, a1 = i < Lx - 1 ? i : Lx - 1;
+    const long long b0 = j - Ky + 1 > 0 ? j - Ky + 1 : 0, b1 = j < Ly - 1 ? j : Ly - 1;
+    const long long cnt = (a1 - a0 + 1) * (b1 - b0 + 1);
+    if (cnt > kEdgeCnt) return;
+    double acc = 0.0;
+    for (int mi = offs[grp]; mi < offs[grp + 1]; ++mi) {
+        const int q = members[mi];
+        const float* u = U + (long long)q * ldu;
+        const float* v = V + (long long)q * ldv;
+        double s = 0.0;
+        for (long long a = a0; a <= a1; ++a)
+            for (long long b = b0; b <= b1; ++b) s += (double)u[a * Ly + b] * (double)v[(i - a) * Ky + (j - b)];
+        acc += sigma[q] * s;
+    }
+    out[(long long)grp * ldo + m] = (float)(acc / (double)cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -935,6 +1000,17 @@ hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3O
         else
             SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_HANKEL, E>), grid, dim3(256), lds, s, g, T2, o));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_recon_edges_2d(const double* sigma, const float* U, long long ldu, const float* V,
+                                 long long ldv, const int* offs, const int* members, int ng, long long Nx,
+                                 long long Ny, long long Lx, long long Ly, float* out, long long ldo,
+                                 hipStream_t s) {
+    const long long n = Nx * Ny;
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)ng);
+    hipLaunchKernelGGL(k_recon_edges_2d, grid, dim3(256), 0, s, sigma, U, ldu, V, ldv, offs, members, Nx, Ny, Lx,
+                       Ly, out, ldo);
     return hipGetLastError();
 }
 

@@ -34,16 +34,22 @@ enum { IN_REV = 0, IN_SERIES = 1, IN_VECS = 2 };
 // pass-3 output modes
 enum { OUT_SLICE = 0, OUT_HANKEL = 1 };
 
+// Two-dimensional arrays (2D-SSA) are flattened row by row with row pitch
+// `pitch` (= Ny).  A compressed vector of shape rows x width (an Lx x Ly or
+// Kx x Ky sub-array, row by row) sits in the padded coordinates at
+// r * pitch + c (c < width), zeros elsewhere; pitch = 0 means a plain series.
 struct P1In {
-    const float* x;      // IN_REV: input vector (w[m] = x[n_in-1-m])
+    const float* x;      // IN_REV: input vector (w[m] = x[n_in-1-m]), padded length n_in
     long long n_in;
     const double* f;     // IN_SERIES
     long long N;
-    const float* U;      // IN_VECS: vector y < nu is U + y*ldu (lenu entries), else V
+    const float* U;      // IN_VECS: vector y < nu is U + y*ldu (padded length lenu), else V
     long long ldu, lenu;
     const float* V;
     long long ldv, lenv;
     int nu;
+    long long pitch;     // 0: 1D
+    int win, wu, wv;     // widths of x, U and V arrays (pitch > 0)
 };
 
 struct P3Out {
@@ -53,6 +59,9 @@ struct P3Out {
     const double* coef;  // device scalar, may be null
     long long N, L, K;   // OUT_HANKEL: out[y*ldo + m] = y[m] / cnt(m), m < N
     long long ldo;
+    long long pitch;     // 0: 1D; else OUT_SLICE keeps t with t % pitch < wout (compressed),
+    int wout;            //   OUT_HANKEL divides by cnt_x(m / pitch) cnt_y(m % pitch) with
+    long long Nx, Lx, Kx;  // the y-dimension in (pitch, L, K) and the x-dimension here
 };
 
 struct ReduceArgs {
@@ -95,6 +104,10 @@ hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3O
 hipError_t launch_recon_edges(const double* sigma, const float* U, long long ldu, const float* V, long long ldv,
                               const int* offs, const int* members, int ng, long long N, long long L, long long K,
                               float* out, long long ldo, hipStream_t s);
+hipError_t launch_recon_edges_2d(const double* sigma, const float* U, long long ldu, const float* V,
+                                 long long ldv, const int* offs, const int* members, int ng, long long Nx,
+                                 long long Ny, long long Lx, long long Ly, float* out, long long ldo,
+                                 hipStream_t s);
 hipError_t launch_check_finite(const double* f, long long N, double* flag, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, hipStream_t s);

@@ -43,7 +43,7 @@ class SsaPlanDesc(ctypes.Structure):
                 ("d_max", ctypes.c_int), ("k_max", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t)]
 
 
-EXPORTED = ("ssa_embed_plan", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
+EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
             "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
@@ -78,6 +78,8 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     lib.ssa_embed_plan.argtypes = [_c_ll, _c_ll, ctypes.c_int, ctypes.POINTER(SsaOpts),
                                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_c_p)]
+    lib.ssa_embed_plan_2d.argtypes = [_c_ll, _c_ll, _c_ll, _c_ll, ctypes.c_int, ctypes.POINTER(SsaOpts),
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_c_p)]
     lib.ssa_plan_bind.argtypes = [_c_p, _c_p, ctypes.c_size_t, _c_p]
     lib.ssa_embed.argtypes = [_c_p, _c_p]
     lib.ssa_matvec.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p]
@@ -190,8 +192,7 @@ class Plan:
                        int(restart_keep), int(reorth))
         ws = ctypes.c_size_t(0)
         h = _c_p()
-        _check(lib.ssa_embed_plan(self.N, self.L, self.k_max, ctypes.byref(opts), ctypes.byref(ws),
-                                  ctypes.byref(h)), "ssa_embed_plan")
+        _check(self._create(opts, ws, h), "ssa_embed_plan")
         self._h = h
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device=self.device)
@@ -202,6 +203,10 @@ class Plan:
         d = SsaPlanDesc()
         _check(lib.ssa_plan_describe(h, ctypes.byref(d)), "ssa_plan_describe")
         self.desc = d
+
+    def _create(self, opts, ws, h):
+        return self.lib.ssa_embed_plan(self.N, self.L, self.k_max, ctypes.byref(opts), ctypes.byref(ws),
+                                       ctypes.byref(h))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -294,6 +299,26 @@ class Plan:
                                       ctypes.cast(mem_a, _c_p), m, out.data_ptr())
         _check(rc, "ssa_reconstruct")
         return out
+
+
+class Plan2D(Plan):
+    """2D-SSA of an Nx x Ny array with an Lx x Ly window (``ssa_embed_plan_2d``).  The array
+    (row-major, any shape with Nx*Ny values) is the series; row i of U is the i-th Lx x Ly
+    eigen-array, row i of V a Kx x Ky one, both flattened row by row; ``reconstruct`` returns
+    (m, Nx, Ny)."""
+
+    def __init__(self, Nx: int, Ny: int, Lx: int, Ly: int, k_max: int, **kw):
+        self.Nx, self.Ny, self.Lx, self.Ly = int(Nx), int(Ny), int(Lx), int(Ly)
+        self.Kx, self.Ky = self.Nx - self.Lx + 1, self.Ny - self.Ly + 1
+        super().__init__(self.Nx * self.Ny, self.Lx * self.Ly, k_max, **kw)
+        self.K = self.Kx * self.Ky
+
+    def _create(self, opts, ws, h):
+        return self.lib.ssa_embed_plan_2d(self.Nx, self.Ny, self.Lx, self.Ly, self.k_max, ctypes.byref(opts),
+                                          ctypes.byref(ws), ctypes.byref(h))
+
+    def reconstruct(self, sigma, U, V, groups):
+        return super().reconstruct(sigma, U, V, groups).view(len(groups), self.Nx, self.Ny)
 
 
 class Batch:

@@ -351,3 +351,25 @@ def test_realizations_workspace_validation():
     assert lib.ssa_realizations_workspace(64, 1000, 1000, 5, ctypes.byref(need)) == ssa.SSA_EINVAL
     assert lib.ssa_realizations_workspace(64, 30000, 500, 5, ctypes.byref(need)) == ssa.SSA_EINVAL
     assert lib.ssa_realizations_workspace(0, 1000, 500, 5, ctypes.byref(need)) == ssa.SSA_EINVAL
+
+
+def test_plan_2d_sizes_and_validation():
+    lib = _built()
+
+    def plan2d(Nx, Ny, Lx, Ly, k):
+        opts = ssa.SsaOpts()
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        rc = lib.ssa_embed_plan_2d(Nx, Ny, Lx, Ly, k, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h))
+        d = describe(h) if rc == 0 else None
+        if rc == 0:
+            lib.ssa_plan_destroy(h)
+        return rc, d
+
+    rc, d = plan2d(40, 50, 20, 25, 8)
+    assert rc == 0 and d.N == 2000 and d.L == 500 and d.K == 21 * 26 and d.M >= 2000
+    assert plan2d(1, 100, 1, 30, 5)[0] == 0        # one row: Basic SSA of the row
+    assert plan2d(30, 7, 30, 1, 1)[0] == 0         # full-height window: Kx = 1
+    for bad in ((40, 50, 0, 25, 8), (40, 50, 41, 25, 8), (40, 50, 20, 51, 8), (1, 1, 1, 1, 1),
+                (40, 50, 40, 50, 1), (5, 5, 2, 2, 5), (40, 50, 20, 25, 0)):
+        assert plan2d(*bad)[0] == ssa.SSA_EINVAL, bad
