@@ -34,6 +34,8 @@ With --workload long: the very long series (N = 2^24, L = N/2, k = 50) through
 the single-series path with the basis capped by thick restart (--d-max,
 --restart-keep); suggested --steps 2 --warmup 1.
 --reorth 1 selects one-sided reorthogonalization (single, many, served).
+With --workload 2d: 2D-SSA of seeded plane-wave arrays (--s2-sizes), window half the
+array, k = 16.
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--pmc-copy]
                        [--workload single|many|served|hmatrix|realizations|long] [--reorth 0|1]
                        [--series S] [--sample S1] [--rates R1,R2] [--requests Q] [--slots S]
@@ -444,6 +446,69 @@ def bench_realizations(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_2d(args):
+    """2D-SSA: seeded plane-wave arrays (three textures + trend + noise), window about half the
+    array, k = 16 triples and 16 elementary reconstructions, at each of --s2-sizes; GPU time
+    per solve, and the dense 2D oracle timed at the smallest size."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_0911_4498_amd import inputs, ssa
+    dev = torch.device("cuda:0")
+    k = 16
+    rows = []
+    sizes = [tuple(int(v) for v in x.split("x")) for x in args.s2_sizes.split(",")]
+    for Nx, Ny in sizes:
+        Lx, Ly = Nx // 2, Ny // 2
+        F = inputs.array2d(Nx, Ny, seed=Nx + 7 * Ny)
+        Fd = torch.tensor(F, device=dev)
+        plan = ssa.Plan2D(Nx, Ny, Lx, Ly, k, device=dev)
+        groups = [[i] for i in range(k)]
+
+        def solve():
+            s, U, V, info = plan.truncated_svd(Fd, k)
+            plan.reconstruct(s, U, V, groups)
+            return s, U, V, info
+
+        for _ in range(max(1, args.warmup)):
+            solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s, U, V, info = solve()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        row = {"Nx": Nx, "Ny": Ny, "Lx": Lx, "Ly": Ly, "k": k, "gpu_s_per_solve": dt,
+               "eigentriples_per_s": k / dt, "lanczos_steps": info.steps, "converged": info.converged,
+               "trajectory_matrix": f"{Lx * Ly} x {(Nx - Lx + 1) * (Ny - Ly + 1)}"}
+        if Lx * Ly <= args.s2_oracle_max:
+            t0 = time.perf_counter()
+            sA, UA, VA = oracle.ssa2d_dense(F, Lx, Ly, k)
+            oracle.reconstruct_2d(Nx, Ny, Lx, Ly, sA, UA, VA, groups)
+            row["oracle_s"] = time.perf_counter() - t0
+            row["oracle_cores"] = oracle.num_threads()
+            row["max_sigma_rel_diff_vs_oracle"] = float(np.max(np.abs(s.cpu().numpy() - sA) / sA))
+        print(f"# {Nx}x{Ny}: {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+        plan.close()
+    out = {
+        "metric": "eigentriples/s (2D-SSA)",
+        "value": rows[-1]["eigentriples_per_s"],
+        "unit": "eigentriples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D arrays of three plane waves + bilinear trend + N(0, 0.1^2), window "
+                               "(Nx/2) x (Ny/2), k = 16 triples and 16 elementary reconstructions"},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,8 +516,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-copy", action="store_true", help="run the 256 MiB copy calibration first")
-    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix", "realizations", "long"),
+    ap.add_argument("--workload", choices=("single", "many", "served", "hmatrix", "realizations", "long", "2d"),
                     default="single")
+    ap.add_argument("--s2-sizes", default="48x48,256x256,1024x1024", help="array sizes (2d workload)")
+    ap.add_argument("--s2-oracle-max", type=int, default=600, help="largest Lx*Ly timed with the dense oracle")
     ap.add_argument("--reorth", type=int, choices=(0, 1), default=0,
                     help="0: full reorthogonalization, 1: one-sided (single, many and served workloads)")
     ap.add_argument("--d-max", type=int, default=0, help="basis cap (long workload; default 125)")
@@ -481,9 +548,9 @@ def main():
         __graft_entry__.build()
     if args.pmc_copy:
         copy_calibration()
-    if args.workload in ("many", "served", "hmatrix", "realizations"):
+    if args.workload in ("many", "served", "hmatrix", "realizations", "2d"):
         return {"many": bench_many, "served": bench_served, "hmatrix": bench_hmatrix,
-                "realizations": bench_realizations}[args.workload](args)
+                "realizations": bench_realizations, "2d": bench_2d}[args.workload](args)
     if args.workload == "long":
         return bench_long(args)
     from paper_0911_4498_amd import inputs

@@ -5,7 +5,8 @@
   products);
 * served stream: requests with N log-uniform in [1e3, 1e6], L in {N/4, N/2},
   k in [8, 32]; tier B up to N = 20000, above it certificates;
-* very long series: N = 2^24, L = N/2, certificates only (k = 8 here; see the test).
+* very long series: N = 2^24, L = N/2, certificates only: k = 8 within 40 steps, and
+  the workload's k = 50 with thick restart (the benchmark's configuration).
 
 Certificates (tier C) at sizes the oracle cannot solve: residuals
 |X v_i - sigma_i u_i| and |X^T u_i - sigma_i v_i| in FP64 (from the library FFT
@@ -41,9 +42,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def solve(ssa, f, L, k, groups=None, d_max=0):
+def solve(ssa, f, L, k, groups=None, d_max=0, **kw):
     N = len(f)
-    plan = ssa.Plan(N, L, k, d_max=d_max)
+    plan = ssa.Plan(N, L, k, d_max=d_max, **kw)
     s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), k)
     rec = plan.reconstruct(s, U, V, groups) if groups is not None else None
     return plan, s, U, V, info, rec
@@ -73,12 +74,15 @@ def parity_vs_oracle(ssa, f, L, k, tier):
     plan.close()
 
 
-def certify(ssa, f, L, k, sampled_rows=0, recon_positions=256, d_max=0):
+def certify(ssa, f, L, k, sampled_rows=0, recon_positions=256, d_max=0, **kw):
     """Tier C certificates of a GPU solve (see the module docstring)."""
     N = len(f)
     K = N - L + 1
-    plan, s, U, V, info, _ = solve(ssa, f, L, k, d_max=d_max)
-    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")
+    plan, s, U, V, info, _ = solve(ssa, f, L, k, d_max=d_max, **kw)
+    say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes} "
+        f"thick_restarts={info.thick_restarts}")
+    if kw.get("restart_keep"):
+        assert info.converged == 1 and info.thick_restarts >= 1
     sg = s.cpu().numpy()
     assert np.all(sg > 0) and np.all(np.diff(sg) <= 1e-12 * sg[0])
     assert np.sum(sg ** 2) <= parity.frobenius(f, L) ** 2 * (1 + 1e-6)
@@ -172,3 +176,14 @@ def test_very_long_series(ssa):
     say(f"c5 series: N={N} L={L} k={k} d_max=40 (certificates, sampled rows)")
     f = inputs.c5_series(N)
     certify(ssa, f, L, k, sampled_rows=128, recon_positions=128, d_max=40)
+
+
+def test_very_long_series_full_k_thick_restart(ssa):
+    """The same series at the workload's k = 50, in the configuration the benchmark times:
+    thick restart with a 125-column basis keeping 75 Ritz pairs (certificates on 32 sampled
+    rows of each product and 64 sampled positions of each elementary series)."""
+    N = 2 ** 24
+    L, k = N // 2, 50
+    say(f"c5 series: N={N} L={L} k={k} d_max=125 keep=75 (certificates, sampled rows)")
+    f = inputs.c5_series(N)
+    certify(ssa, f, L, k, sampled_rows=32, recon_positions=64, d_max=125, restart_keep=75)
