@@ -287,6 +287,9 @@ int ssa_batch_solve(ssa_batch b, int nseries, const double* series_dev, const lo
         vo += K * t.k;
         ro += t.N * t.k;
     }
+    // one workgroup per table entry: the longest series first, so that the short ones fill
+    // the tail of every launch (each entry carries its own region and output pointers)
+    std::stable_sort(b->tab.begin(), b->tab.end(), [](const BSeries& x, const BSeries& y) { return x.N > y.N; });
     hipStream_t st = b->stream;
     // the previous solve's table upload must be done before the staging is reused
     SSA_TRY_HIP(hipEventSynchronize(b->tab_done));
