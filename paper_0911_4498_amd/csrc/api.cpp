@@ -26,6 +26,7 @@ constexpr double kResidFloor = 1e-5;    // residuals of omega_i < 1e-5 omega_1 a
 constexpr int kMaxGroupBatch = 64;
 constexpr int kMaxRestartDmax = 512;  // basis cap of the restarted solver (host dense SVD per cycle)
 constexpr int kMaxCycles = 64;        // thick restarts before the solver gives up
+constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 16 row chunks (16384 rows)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -283,6 +284,14 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
         SSA_TRY(launch_cgs_project(a, s));
     }
     a.presummed = a.nchunks > kColsumChunks ? 1 : 0;
+    // A DGKS second pass inside the one-workgroup finish reads the whole basis through one
+    // CU: fine while rare and short, ruinous for long vectors (an N = 2^24 pass would take
+    // minutes) and for the reorthogonalized side of the one-sided scheme, where it is
+    // frequent.  There the finish hands it to four gated launches over the whole grid,
+    // which return at once when no second pass was needed.
+    const bool grid2 = ncols > 0 && a.nchunks > (p->onesided ? kGrid2ChunksOneSided : kColsumChunks);
+    int* flag2 = at<int>(p, p->o_flag) + 8;
+    a.dgks_flag = grid2 ? flag2 : nullptr;
     if (a.presummed) {
         ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)a.nchunks * (ncols + 1));
         SSA_TRY(launch_cgs_colsum(a, s));
@@ -291,10 +300,33 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
         ProfScope ps(p, SSA_PROF_REDUCE, a.presummed ? 8.0 * (ncols + 1) : 8.0 * (double)a.nchunks * (ncols + 1));
         SSA_TRY(launch_cgs_reduce(a, s));
     }
+    float* out = basis + (long long)(out_col < 0 ? ncols : out_col) * ld;
     {
         ProfScope ps(p, SSA_PROF_UPDATE, 4.0 * (double)n * (ncols + 2));
-        SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, basis + (long long)(out_col < 0 ? ncols : out_col) * ld,
-                                  n, s));
+        SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, out, n, nullptr, s));
+    }
+    if (grid2) {
+        // second pass on out = r - basis h (in place); no algorithmic bytes unless it runs
+        ReduceArgs b = a;
+        b.r = out;
+        b.dgks_flag = nullptr;
+        b.gate = flag2;
+        {
+            ProfScope ps(p, SSA_PROF_DOTS, 0.0);
+            SSA_TRY(launch_cgs_project(b, s));
+        }
+        if (b.presummed) {
+            ProfScope ps(p, SSA_PROF_REDUCE, 0.0);
+            SSA_TRY(launch_cgs_colsum(b, s));
+        }
+        {
+            ProfScope ps(p, SSA_PROF_REDUCE, 0.0);
+            SSA_TRY(launch_cgs_reduce(b, s));
+        }
+        {
+            ProfScope ps(p, SSA_PROF_UPDATE, 0.0);
+            SSA_TRY(launch_cgs_update(out, basis, ld, ncols, h, sc, out, n, flag2, s));
+        }
     }
     return SSA_OK;
 }

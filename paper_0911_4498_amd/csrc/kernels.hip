@@ -693,6 +693,7 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
         for (int c = tid; c < a.ncols; c += nt) hs[c] = 0.0;
         coef = 0.0;
         scale = 0.0;
+        if (a.dgks_flag && tid == 0) *a.dgks_flag = 0;
     } else {
         double a2 = rr - hh;
         const double thr = a.tol_bd * bnorm;
@@ -701,6 +702,16 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
         if (decision == 0) {
             coef = sqrt(a2);
             scale = 1.0 / coef;
+            if (a.dgks_flag && tid == 0) *a.dgks_flag = 0;
+        } else if (a.dgks_flag) {
+            // long vectors: the update writes r - basis h unscaled and the second pass runs
+            // over the whole grid (the gated launches that follow); h stays in a.h
+            if (tid == 0) {
+                *a.dgks_flag = 1;
+                *a.scale_out = 1.0;
+                a.state[2] += 1.0;
+            }
+            return;
         } else {
             // second Gram-Schmidt pass on the updated vector
             blk_subtract(a.r, a.n, a.basis, a.ld, a.ncols, hs);
@@ -748,6 +759,7 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
 // (row chunk, column group) tiles: part[c * pstride + chunk] for c < ncols,
 // and part[ncols * pstride + chunk] = the chunk's |r|^2 (column group 0).
 __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
+    if (a.gate && *a.gate == 0) return;
     constexpr int CJ = kProjCols;
     __shared__ double red[CJ + 1][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -780,6 +792,7 @@ __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
 // Column sums for long vectors (many chunks): workgroup c adds part[c][chunk]
 // over all chunks (thread-strided, then the block sum: a fixed order) into h[c].
 __global__ __launch_bounds__(256) void k_cgs_colsum(ReduceArgs a) {
+    if (a.gate && *a.gate == 0) return;
     __shared__ double sh[16];
     const double* row = a.part + (long long)blockIdx.x * a.pstride;
     double sum = 0.0;
@@ -793,6 +806,7 @@ __global__ __launch_bounds__(256) void k_cgs_colsum(ReduceArgs a) {
 // has already formed it, then cgs_finish.
 constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
+    if (a.gate && *a.gate == 0) return;
     __shared__ double hs[kMaxCols];
     __shared__ double sh[16];
     __shared__ int decision;
@@ -814,10 +828,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
 // out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale, FP64 accumulation.  A
 // workgroup covers 256 rows (4 per lane, float4); its 4 waves split the
 // columns and their partial sums meet in LDS.
-__global__ __launch_bounds__(256) void k_cgs_update(const float* __restrict__ r, const float* __restrict__ basis,
+__global__ __launch_bounds__(256) void k_cgs_update(const float* r, const float* __restrict__ basis,
                                                     long long ld, int ncols, const double* __restrict__ h,
-                                                    const double* __restrict__ scale, float* __restrict__ out,
-                                                    long long n) {
+                                                    const double* __restrict__ scale, float* out,
+                                                    long long n, const int* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ double red[4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long t = (long long)blockIdx.x * 256 + 4 * lane;
@@ -1059,9 +1074,9 @@ hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols, const double* h,
-                             const double* scale, float* out, long long n, hipStream_t s) {
+                             const double* scale, float* out, long long n, const int* gate, hipStream_t s) {
     hipLaunchKernelGGL(k_cgs_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r, basis, ld, ncols,
-                       h, scale, out, n);
+                       h, scale, out, n, gate);
     return hipGetLastError();
 }
 

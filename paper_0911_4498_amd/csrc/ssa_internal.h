@@ -79,6 +79,8 @@ struct ReduceArgs {
     int track;          // 1: the coefficient is an entry of B (count it in state[0])
     int full;           // 1: the basis already spans the whole space -> zero vector
     int presummed;      // 1: h[0..ncols] already holds the column sums (k_cgs_colsum)
+    int* dgks_flag;     // non-null: a second pass is left to the gated launches (flag set to 1)
+    const int* gate;    // non-null: the launch does nothing unless *gate != 0
     double tol_bd;      // breakdown threshold relative to state[0]
 };
 
@@ -116,7 +118,7 @@ hipError_t launch_cgs_colsum(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, int ncols,
                              const double* h, const double* scale, float* out, long long n,
-                             hipStream_t s);
+                             const int* gate, hipStream_t s);
 hipError_t launch_ritz(const float* basis, long long ld, int ncols, const double* P, int k,
                        float* out, long long ldo, long long n, hipStream_t s);
 hipError_t set_kernel_attributes();

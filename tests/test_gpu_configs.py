@@ -129,6 +129,7 @@ def certify(ssa, f, L, k, sampled_rows=0, recon_positions=256, d_max=0, **kw):
     assert worst_r <= parity.RECON_REL * fmax
     del rec
     plan.close()
+    return info
 
 
 def c3_pick():
@@ -187,3 +188,14 @@ def test_very_long_series_full_k_thick_restart(ssa):
     say(f"c5 series: N={N} L={L} k={k} d_max=125 keep=75 (certificates, sampled rows)")
     f = inputs.c5_series(N)
     certify(ssa, f, L, k, sampled_rows=32, recon_positions=64, d_max=125, restart_keep=75)
+
+
+def test_one_sided_second_passes_run_on_the_whole_grid(ssa):
+    """Request 6 of the served stream (N = 241251, L = N/2, k = 13) with one-sided
+    reorthogonalization: the U-side Gram-Schmidt often removes most of the vector, so DGKS
+    second passes fire; for bases this long they run as the gated full-grid launches.  The
+    result must still pass the certificates."""
+    f, N, L, k = inputs.c4_request(6)
+    say(f"served request 6 one-sided: N={N} L={L} k={k}")
+    info = certify(ssa, f, L, k, reorth=1)
+    assert info.dgks_passes > 0
