@@ -330,9 +330,11 @@ __global__ __launch_bounds__(NT) void k_pass2_embed(ConvGeom g, const float2* __
 // triples before the single inverse transform):
 //   G(k) += sigma_i U_i(k) V_i(k),  G(k+M') += sigma_i U_i(k+M') V_i(k+M'),
 // then Q(k) = [(G(k) + G(k+M'))/2 + i (G(k) - G(k+M')) / (2 w^k)] / M'.
+// NP = bin pairs per thread (M2 <= kReconThreads * NP): the FP64 accumulators of NP
+// pairs live in registers, so NP is the smallest that covers the row (1 for rows of up
+// to 1024 points) rather than the largest (4 would spill them to scratch memory).
 constexpr int kReconThreads = 1024;
-constexpr int kReconPairs = 4;  // pairs per thread: 2*M2 <= kReconThreads*kReconPairs*2
-template <int EPT>
+template <int EPT, int NP>
 __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const float2* __restrict__ T1all,
                                                               int k, const double* __restrict__ sigma,
                                                               const int* __restrict__ offs,
@@ -348,12 +350,12 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
     const int grp = g0 + blockIdx.y;
     for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
 
-    float2 zu0[kReconPairs], zu1[kReconPairs];
-    double g00r[kReconPairs], g00i[kReconPairs], g01r[kReconPairs], g01i[kReconPairs];
-    double g10r[kReconPairs], g10i[kReconPairs], g11r[kReconPairs], g11i[kReconPairs];
-    double w0r[kReconPairs], w0i[kReconPairs], w1r[kReconPairs], w1i[kReconPairs];
+    float2 zu0[NP], zu1[NP];
+    double g00r[NP], g00i[NP], g01r[NP], g01i[NP];
+    double g10r[NP], g10i[NP], g11r[NP], g11i[NP];
+    double w0r[NP], w0i[NP], w1r[NP], w1i[NP];
 #pragma unroll
-    for (int i = 0; i < kReconPairs; ++i) {
+    for (int i = 0; i < NP; ++i) {
         g00r[i] = g00i[i] = g01r[i] = g01i[i] = g10r[i] = g10i[i] = g11r[i] = g11i[i] = 0.0;
         const int p = tid + i * nthr;
         w0r[i] = w0i[i] = w1r[i] = w1i[i] = 0.0;
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         __syncthreads();
         lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
-        for (int i = 0; i < kReconPairs; ++i) {
+        for (int i = 0; i < NP; ++i) {
             const int p = tid + i * nthr;
             if (p < rp.npairs) {
                 int s0, e0, s1, e1;
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         __syncthreads();
         lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
-        for (int i = 0; i < kReconPairs; ++i) {
+        for (int i = 0; i < NP; ++i) {
             const int p = tid + i * nthr;
             if (p < rp.npairs) {
                 int s0, e0, s1, e1;
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
     __syncthreads();
     const double invMp = 1.0 / (double)Mp;
 #pragma unroll
-    for (int i = 0; i < kReconPairs; ++i) {
+    for (int i = 0; i < NP; ++i) {
         const int p = tid + i * nthr;
         if (p < rp.npairs) {
             int s0, e0, s1, e1;
@@ -992,8 +994,18 @@ hipError_t launch_pass2_recon(const ConvGeom& g, const float2* T1all, int k, con
                               hipStream_t s) {
     const dim3 grid(g.M1 / 2 + 1, ng);
     const int ept = ept_for(2LL * g.M2, kReconThreads);
-    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_recon<E>), grid, dim3(kReconThreads), lds_p2(g), s, g,
-                                           T1all, k, sigma, offs, members, g0, T2all));
+    const int np = (g.M2 + kReconThreads - 1) / kReconThreads;  // M2 <= 4096
+#define SSA_RECON(NPV)                                                                                  \
+    SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_recon<E, NPV>), grid, dim3(kReconThreads), lds_p2(g), s, g, \
+                                           T1all, k, sigma, offs, members, g0, T2all))
+    if (np <= 1) {
+        SSA_RECON(1);
+    } else if (np <= 2) {
+        SSA_RECON(2);
+    } else {
+        SSA_RECON(4);
+    }
+#undef SSA_RECON
     return hipGetLastError();
 }
 
@@ -1119,7 +1131,13 @@ hipError_t set_kernel_attributes() {
     SSA_ALLOW((k_pass2_matvec<8, kBigThreads>)); SSA_ALLOW((k_pass2_embed<8, kBigThreads>));
     SSA_ALLOW_EPT(k_pass2_matvec);
     SSA_ALLOW_EPT(k_pass2_embed);
-    SSA_ALLOW_EPT(k_pass2_recon);
+#define SSA_ALLOW_RECON(NPV)                                                                   \
+    SSA_ALLOW((k_pass2_recon<4, NPV>)); SSA_ALLOW((k_pass2_recon<8, NPV>));                      \
+    SSA_ALLOW((k_pass2_recon<16, NPV>)); SSA_ALLOW((k_pass2_recon<32, NPV>))
+    SSA_ALLOW_RECON(1);
+    SSA_ALLOW_RECON(2);
+    SSA_ALLOW_RECON(4);
+#undef SSA_ALLOW_RECON
     SSA_ALLOW(k_ritz);
 #undef SSA_ALLOW_EPT
 #undef SSA_ALLOW
