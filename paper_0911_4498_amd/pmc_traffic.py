@@ -10,7 +10,7 @@ reports the traffic only while the sources still hash to it.
 
 Usage:
   python -m paper_0911_4498_amd.pmc_traffic FETCH_CSV WRITE_CSV KERNEL_SUBSTRING OUT_TXT \\
-      --command "..." [--workload "..."]
+      --command "..." [--workload "..."] [--skip-idle]
 """
 from __future__ import annotations
 
@@ -55,7 +55,14 @@ def per_dispatch(rows, needle: str) -> list[float]:
     return [v for k, v in rows if needle in k]
 
 
-def summarize(fetch_csv: str, write_csv: str, kernel: str) -> dict:
+def drop_idle(values: list[float]) -> list[float]:
+    """Dispatches that moved under 1/1000 of the kernel's largest one: launches that returned
+    at once (e.g. a gated second Gram-Schmidt pass that was not needed)."""
+    top = max(values) if values else 0.0
+    return [v for v in values if v >= 1e-3 * top]
+
+
+def summarize(fetch_csv: str, write_csv: str, kernel: str, skip_idle: bool = False) -> dict:
     fr = read_counter(fetch_csv, "FETCH_SIZE")
     wr = read_counter(write_csv, "WRITE_SIZE")
     copy_f = [v for v in per_dispatch(fr, COPY_KERNEL) if v * 1024 > COPY_BYTES / 4]
@@ -68,12 +75,16 @@ def summarize(fetch_csv: str, write_csv: str, kernel: str) -> dict:
     kw = per_dispatch(wr, kernel)
     if not kf or not kw:
         raise ValueError(f"kernel {kernel!r} not found in the counter files")
+    n_all = len(kf)
+    if skip_idle:
+        kf, kw = drop_idle(kf), drop_idle(kw)
     fetch_b = statistics.mean(kf) * 1024.0 * f_fetch
     write_b = statistics.mean(kw) * 1024.0 * f_write
     return {
         "kernel": kernel,
         "dispatches_fetch": len(kf),
         "dispatches_write": len(kw),
+        "idle_dispatches_skipped": n_all - len(kf),
         "fetch_kib_per_dispatch": statistics.mean(kf),
         "write_kib_per_dispatch": statistics.mean(kw),
         "copy_fetch_kib": statistics.median(copy_f),
@@ -122,8 +133,9 @@ def main():
     ap.add_argument("out")
     ap.add_argument("--command", default="")
     ap.add_argument("--workload", default="")
+    ap.add_argument("--skip-idle", action="store_true", help="ignore dispatches that returned at once")
     a = ap.parse_args()
-    s = summarize(a.fetch_csv, a.write_csv, a.kernel)
+    s = summarize(a.fetch_csv, a.write_csv, a.kernel, a.skip_idle)
     write_summary(a.out, s, a.command, a.workload)
     for k, v in s.items():
         print(f"{k}: {v}")

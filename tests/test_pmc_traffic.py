@@ -39,3 +39,16 @@ def test_summary_needs_the_copy(tmp_path):
     _write(tmp_path / "w.csv", "WRITE_SIZE", [("k", 1.0)])
     with pytest.raises(ValueError):
         pmc_traffic.summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "k")
+
+
+def test_idle_dispatches_can_be_skipped(tmp_path):
+    """Gated launches that return at once count only with skip_idle off."""
+    copy = "neg_kernel"
+    kern = "ssa::k_cgs_project(ssa::ReduceArgs)"
+    _write(tmp_path / "f.csv", "FETCH_SIZE", [(copy, 131072.0), (kern, 1000.0), (kern, 0.1), (kern, 3000.0), (kern, 0.0)])
+    _write(tmp_path / "w.csv", "WRITE_SIZE", [(copy, 262144.0), (kern, 50.0), (kern, 0.0), (kern, 50.0), (kern, 0.0)])
+    s = pmc_traffic.summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "k_cgs_project", skip_idle=True)
+    assert s["idle_dispatches_skipped"] == 2 and s["dispatches_fetch"] == 2
+    assert s["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024 * 2.0)
+    s_all = pmc_traffic.summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "k_cgs_project")
+    assert s_all["dispatches_fetch"] == 4 and s_all["fetch_bytes_per_launch"] < s["fetch_bytes_per_launch"]
