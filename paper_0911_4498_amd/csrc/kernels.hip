@@ -758,11 +758,12 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
 }
 
 // Projection h = basis^T r and |r|^2, FP64 sums of exact FP32 products, in
-// (row chunk, column group) tiles: part[c * pstride + chunk] for c < ncols,
-// and part[ncols * pstride + chunk] = the chunk's |r|^2 (column group 0).
+// (row chunk, column group of CJ columns) tiles: part[c * pstride + chunk] for
+// c < ncols, and part[ncols * pstride + chunk] = the chunk's |r|^2 (column
+// group 0).
+template <int CJ>
 __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
     if (a.gate && *a.gate == 0) return;
-    constexpr int CJ = kProjCols;
     __shared__ double red[CJ + 1][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long t = (long long)blockIdx.x * kProjRows + 4 * tid;
@@ -1068,10 +1069,17 @@ hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, h
     return hipGetLastError();
 }
 
+// Columns per projection workgroup: short vectors (few row chunks) are latency-bound and
+// gain from more, smaller workgroups; long ones re-read r once per column group, so they
+// take wider groups.
 hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s) {
     const unsigned nchunks = (unsigned)((a.n + kProjRows - 1) / kProjRows);
-    const unsigned ngrp = a.ncols > 0 ? (unsigned)((a.ncols + kProjCols - 1) / kProjCols) : 1u;
-    hipLaunchKernelGGL(k_cgs_project, dim3(nchunks, ngrp), dim3(256), 0, s, a);
+    const int cj = nchunks <= kProjNarrowChunks ? kProjColsNarrow : kProjCols;
+    const unsigned ngrp = a.ncols > 0 ? (unsigned)((a.ncols + cj - 1) / cj) : 1u;
+    if (cj == kProjColsNarrow)
+        hipLaunchKernelGGL((k_cgs_project<kProjColsNarrow>), dim3(nchunks, ngrp), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_cgs_project<kProjCols>), dim3(nchunks, ngrp), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -87,6 +87,8 @@ struct ReduceArgs {
 constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many terms are summed directly
 constexpr int kProjRows = 1024;  // rows per workgroup in the projection kernel (256 x float4)
 constexpr int kProjCols = 8;     // basis columns per workgroup in the projection kernel
+constexpr int kProjColsNarrow = 4;    // ... for vectors of at most kProjNarrowChunks row chunks
+constexpr int kProjNarrowChunks = 64;
 constexpr int kMaxCols = 2048;   // most basis columns one projection handles
 constexpr int kColsumChunks = 256;  // above this many row chunks the column sums get their own launch
 
