@@ -143,3 +143,49 @@ def test_batch_c3_series_match_oracle(ssa, s):
     say(f"c3 series {s}: N={N} steps={info[0, 0]} conv={info[0, 1]}")
     rep = compare_one(f, L, 16, out["sigma"][0], out["U"][0], out["V"][0], out["recon"][0], dense=False)
     say(f"   {rep}")
+
+
+def test_batch_full_many_series_workload(ssa):
+    """The many-series workload exactly as the benchmark launches it: 4096 series (N uniform in
+    [2000, 20000], L = N/2, k = 16) in one batch.  Three sampled series against the oracle
+    (dense where N <= 4000, else tier B), residual and orthonormality certificates (FP64,
+    numpy FFT) for 64 sampled series, and ordering / convergence for all of them."""
+    ns, k = 4096, 16
+    say(f"full many-series workload: generating {ns} series")
+    host = [inputs.c3_series(s) for s in range(ns)]
+    series = [torch.tensor(f, device="cuda") for f, _, _ in host]
+    Ls = [L for _, _, L in host]
+    b = ssa.Batch(n_max=20000, k_max=k, max_series=ns)
+    say("full many-series workload: solving")
+    out = b.solve(series, Ls, [k] * ns, keys=list(range(ns)))
+    info = out["info"].cpu().numpy()
+    say(f"  mean steps {info[:, 0].mean():.1f}, converged {info[:, 1].mean():.4f}")
+    assert info[:, 1].mean() >= 0.99
+    for s in range(ns):
+        sg = out["sigma"][s].cpu().numpy()
+        assert np.all(np.diff(sg) <= 1e-12 * sg[0]) and sg[-1] > 0, s
+    rng = np.random.default_rng(4096)
+    for s in sorted(rng.choice(ns, 3, replace=False)):
+        f, N, L = host[s]
+        say(f"  series {s}: N={N} oracle comparison")
+        rep = compare_one(f, L, k, out["sigma"][s], out["U"][s], out["V"][s], out["recon"][s], dense=N <= 4000)
+        say(f"     {rep}")
+    worst = 0.0
+    for s in sorted(rng.choice(ns, 64, replace=False)):
+        f, N, L = host[s]
+        K = N - L + 1
+        sg = out["sigma"][s].cpu().numpy()
+        U = out["U"][s].cpu().numpy().astype(np.float64)
+        V = out["V"][s].cpu().numpy().astype(np.float64)
+        M = 1 << int(np.ceil(np.log2(2 * N)))
+        F = np.fft.rfft(f, M)
+        for i in range(k):
+            y = np.fft.irfft(F * np.fft.rfft(V[i][::-1], M), M)[K - 1:K - 1 + L]
+            r1 = np.linalg.norm(y - sg[i] * U[i])
+            y = np.fft.irfft(F * np.fft.rfft(U[i][::-1], M), M)[L - 1:L - 1 + K]
+            r2 = np.linalg.norm(y - sg[i] * V[i])
+            worst = max(worst, r1 / sg[0], r2 / sg[0])
+        for B in (U, V):
+            assert np.abs(B @ B.T - np.eye(k)).max() <= 1e-5, s
+    say(f"  worst residual / sigma_1 over 64 sampled series: {worst:.2e}")
+    assert worst <= 1e-5
