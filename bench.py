@@ -28,7 +28,7 @@ sample of the same series, one series at a time, on the same GPU.
 With --workload served: a Poisson stream of requests (N log-uniform in
 [1e3, 1e6], L in {N/4, N/2}, k in [8, 32], seeded) at each of --rates;
 requests with N <= 20480 go to the continuous-batching server (ssa_server_*),
-longer ones to single-series plans on two worker streams; reports p50/p99
+longer ones to single-series plans on --long-workers (4) worker streams; reports p50/p99
 latency from arrival to complete outputs, and throughput.
 With --workload long: the very long series (N = 2^24, L = N/2, k = 50) through
 the single-series path with the basis capped by thick restart (--d-max,
@@ -305,7 +305,7 @@ def bench_served(args):
             with lock:
                 done_at[r] = time.perf_counter() - t0
 
-    workers = [threading.Thread(target=worker, daemon=True) for _ in range(2)]
+    workers = [threading.Thread(target=worker, daemon=True) for _ in range(args.long_workers)]
     for w in workers:
         w.start()
 
@@ -378,7 +378,7 @@ def bench_served(args):
                                "L in {N/4, N/2}, k in [8, 32], c3 signals (seeded)",
                    "short_path": f"continuous batching, N <= {n_small_max}, {args.slots} slots, "
                                  f"{args.pool_gb} GiB pool",
-                   "long_path": "single-series plans, 2 worker streams",
+                   "long_path": f"single-series plans, {args.long_workers} worker streams",
                    "reorth": "one-sided" if args.reorth else "full", "parallelism": "single GPU"},
         "rates": results,
     }
@@ -568,6 +568,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="requests per rate (served stream)")
     ap.add_argument("--slots", type=int, default=256, help="server slots (served stream)")
     ap.add_argument("--pool-gb", type=float, default=24.0, help="server pool GiB (served stream)")
+    ap.add_argument("--long-workers", type=int, default=4,
+                    help="host threads, each with its own stream, for the long requests (served stream)")
     ap.add_argument("--series", type=int, default=4096, help="series of the many-series workload")
     ap.add_argument("--sample", type=int, default=256, help="series timed one at a time (many-series workload)")
     args = ap.parse_args()
