@@ -647,7 +647,9 @@ def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
                   f"alg={b / 1e6:9.3f} MB  {b / max(ms, 1e-9) / 1e6:8.1f} GB/s", file=sys.stderr)
     print(f"# dominant kernel class: {dom}", file=sys.stderr, flush=True)
 
-    plan.profile_enable([dom])
+    # one launch in eight of the dominant class bracketed by events: its mean duration is
+    # measured live while the stream is disturbed as little as possible
+    plan.profile_enable([dom], every=8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     starts = []

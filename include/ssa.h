@@ -423,11 +423,19 @@ int ssa_profile_enable(ssa_plan plan, unsigned class_mask);
  * ssa_profile_read -- synchronize the plan's stream and report, for kernel
  * class cls since the last ssa_profile_enable: the number of launches, the
  * summed event-measured duration in milliseconds (-1 if the class was not
- * timed) and
+ * timed; with ssa_profile_sample, the timed launches' mean times the count) and
  * the summed algorithmic HBM bytes (the bytes the method must move: vectors
  * read and written, spectra, basis columns).  Errors: SSA_EINVAL, SSA_EDEVICE.
  */
 int ssa_profile_read(ssa_plan plan, int cls, long long* launches, double* ms, double* bytes);
+
+/*
+ * ssa_profile_sample -- bracket only one launch in `every` (>= 1; default 1) of
+ * each timed class with events, from the next launch on; ssa_profile_read then
+ * reports the mean of the timed launches times the number of launches.  Fewer
+ * event records disturb the stream less.  Errors: SSA_EINVAL.
+ */
+int ssa_profile_sample(ssa_plan plan, int every);
 
 /* ssa_status_str -- static text for a status code. */
 const char* ssa_status_str(int status);

@@ -111,6 +111,8 @@ struct ssa_plan_s {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pairs[SSA_PROF_NCLASSES];
+    int prof_every = 1;                        // time one launch in prof_every of a timed class
+    long long prof_seen[SSA_PROF_NCLASSES] = {};
     double prof_bytes[SSA_PROF_NCLASSES] = {};
     long long prof_count[SSA_PROF_NCLASSES] = {};
 };
@@ -184,7 +186,7 @@ struct ProfScope {
     double bytes;
     hipEvent_t e0 = nullptr;
     ProfScope(ssa_plan p_, int cls_, double bytes_) : p(p_), cls(cls_), bytes(bytes_) {
-        if (p->prof_on && (p->prof_mask >> cls & 1u)) {
+        if (p->prof_on && (p->prof_mask >> cls & 1u) && p->prof_seen[cls]++ % p->prof_every == 0) {
             e0 = next_event(p);
             if (e0) (void)hipEventRecord(e0, p->stream);
         }
@@ -927,6 +929,7 @@ int ssa_profile_enable(ssa_plan p, unsigned class_mask) {
         p->prof_pairs[c].clear();
         p->prof_bytes[c] = 0.0;
         p->prof_count[c] = 0;
+        p->prof_seen[c] = 0;
     }
     p->ev_next = 0;
     p->prof_on = class_mask ? 1 : 0;
@@ -943,9 +946,18 @@ int ssa_profile_read(ssa_plan p, int cls, long long* launches, double* ms, doubl
         if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess) return SSA_EDEVICE;
         total += t;
     }
+    // sampled timing: the mean of the timed launches stands for every launch of the class
+    const size_t timed = p->prof_pairs[cls].size();
+    if (timed) total *= (double)p->prof_count[cls] / (double)timed;
     if (launches) *launches = p->prof_count[cls];
     if (ms) *ms = (p->prof_on && (p->prof_mask >> cls & 1u)) ? total : -1.0;
     if (bytes) *bytes = p->prof_bytes[cls];
+    return SSA_OK;
+}
+
+int ssa_profile_sample(ssa_plan p, int every) {
+    if (!p || every < 1) return SSA_EINVAL;
+    p->prof_every = every;
     return SSA_OK;
 }
 

@@ -45,7 +45,7 @@ class SsaPlanDesc(ctypes.Structure):
 
 EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
-            "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read",
+            "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read", "ssa_profile_sample",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
             "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
             "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
@@ -96,6 +96,7 @@ def load():
     lib.ssa_dense_ritz.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
     lib.ssa_profile_enable.argtypes = [_c_p, ctypes.c_uint]
     lib.ssa_profile_read.argtypes = [_c_p, ctypes.c_int, ctypes.POINTER(_c_ll), dp, dp]
+    lib.ssa_profile_sample.argtypes = [_c_p, ctypes.c_int]
     lib.ssa_batch_plan.argtypes = [_c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts),
                                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_c_p)]
     lib.ssa_batch_workspace.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p, _c_p, ctypes.POINTER(ctypes.c_size_t)]
@@ -219,9 +220,10 @@ class Plan:
         except Exception:
             pass
 
-    def profile_enable(self, classes=None, on: bool = True):
+    def profile_enable(self, classes=None, on: bool = True, every: int = 1):
         """Count launches/bytes of every class and time the listed classes (all if None)
-        with HIP events; on=False stops.  Clears the counters."""
+        with HIP events, one launch in `every`; on=False stops.  Clears the counters."""
+        _check(self.lib.ssa_profile_sample(self._h, int(every)), "ssa_profile_sample")
         if not on:
             mask = 0
         elif classes is None:
