@@ -557,6 +557,9 @@ def main():
     ap.add_argument("--s2-oracle-max", type=int, default=600, help="largest Lx*Ly timed with the dense oracle")
     ap.add_argument("--reorth", type=int, choices=(0, 1), default=0,
                     help="0: full reorthogonalization, 1: one-sided (single, many and served workloads)")
+    ap.add_argument("--schedule", choices=("table", "tune", "auto"), default="table",
+                    help="FFT schedule of the single-series products: the stored tuner table, a tuner "
+                         "run before the measurement, or the plan's automatic choice")
     ap.add_argument("--d-max", type=int, default=0, help="basis cap (long workload; default 125)")
     ap.add_argument("--restart-keep", type=int, default=0, help="Ritz pairs kept per restart (long; default 75)")
     ap.add_argument("--realizations", type=int, default=64, help="realizations per size (realizations workload)")
@@ -604,6 +607,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def fft_schedule(args, Nw, Lw, f_dev):
+    """Plan keywords of the products' FFT schedule and where they came from: the stored
+    tuner table (default), a tuner run now (untimed), or the plan's automatic choice."""
+    if args.schedule == "auto":
+        return {}, "automatic"
+    from paper_0911_4498_amd import autotune
+    if args.schedule == "tune":
+        e = autotune.tune(Nw, Lw, f_dev)
+        print(f"# tuner: {e['candidates']} candidates in {e['tune_s']} s, best {e['us_per_pair']} us per "
+              f"product pair, automatic {e['auto']['us_per_pair']}", file=sys.stderr, flush=True)
+        return {key: e[key] for key in ("fft_mp", "fft_m1", "fft_cb")}, "tuned in this run (ssa_tune_fft)"
+    sched = autotune.lookup(Nw, Lw)
+    if sched is None:
+        return {}, "automatic (no tuner table entry)"
+    return sched, "tuner table (paper_0911_4498_amd/fft_schedules.json, ssa_tune_fft)"
+
+
 def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
     """One series through the single-series path: warm-up, one calibration solve with every
     kernel class event-timed (picks the dominant class), then the timed solves with the
@@ -615,7 +635,13 @@ def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
     dev = torch.device("cuda:0")
     Nw = len(f_np)
     f = torch.tensor(f_np, device=dev)
-    plan = ssa.Plan(Nw, Lw, k, device=dev, **plan_kw)
+    sched, sched_src = fft_schedule(args, Nw, Lw, f)
+    plan = ssa.Plan(Nw, Lw, k, device=dev, **plan_kw, **sched)
+    d = plan.desc
+    config = {**config, "fft": {"M_half": int(d.M) // 2, "M1": int(d.M1), "M2": int(d.M2), "CB": int(d.cb),
+                                "schedule": sched_src}}
+    print(f"# FFT schedule: M' = {d.M // 2} = {d.M1} x {d.M2}, CB = {d.cb} ({sched_src})", file=sys.stderr,
+          flush=True)
     groups = [[i] for i in range(k)]
     steps_seen = []
     steps_run = []

@@ -73,6 +73,11 @@ typedef struct {
                                min(L, K) is reorthogonalized, the other keeps the
                                three-term recurrence alone (half the Gram-Schmidt traffic).
                                One-sided cannot be combined with restart_keep.            */
+    long long fft_mp;       /* FFT length override: M/2 = M' for the products and the
+                               Hankelization (Sec. 4.2: any M >= N gives the exact
+                               correlation).  Must be >= ceil(N/2), 7-smooth and split
+                               into two factors <= 4096; 0 = the smallest such M'.  The
+                               schedule tuner (ssa_tune_fft) picks it by measurement.    */
 } ssa_opts;
 
 /* Per-solve report, filled by ssa_truncated_svd. */
@@ -95,6 +100,7 @@ typedef struct {
     long long M1, M2;   /* M/2 = M1 * M2, the two passes of the half-length complex FFT */
     int d_max, k_max;
     size_t workspace_bytes;
+    int cb;             /* columns per workgroup of FFT passes 1 and 3                   */
 } ssa_plan_desc;
 
 /*
@@ -200,7 +206,7 @@ typedef struct ssa_batch_s* ssa_batch;
  * ssa_batch_plan -- host-side engine for up to max_series series per solve.
  * Each series has length 3 <= N <= n_max (n_max <= 20480) and up to
  * k_max <= 32 triples.  opts as for ssa_embed_plan; d_max is capped at 320;
- * fft_m1/fft_cb do not apply (each series' FFT is one workgroup's); reorth
+ * fft_m1/fft_cb/fft_mp do not apply (each series' FFT is one workgroup's); reorth
  * applies to every series; restart_keep must be 0.
  * *workspace_bytes: enough for max_series series of length n_max with
  * L = n_max/2 and k = k_max.  ssa_batch_workspace gives the exact figure for
@@ -365,6 +371,42 @@ int ssa_realizations_workspace(long long R, long long N, long long L, int d, siz
 int ssa_realizations(const double* series_dev, long long R, long long N, long long L, int d,
                      const double* truth_dev, void* workspace_dev, size_t bytes, void* hip_stream,
                      double* mean_dev, double* var_dev, double* mse_dev);
+
+/*
+ * ssa_tune_workspace -- device bytes that ssa_tune_fft needs for a series of
+ * length N with window L: the largest candidate plan (k_max = 1, d_max = 2)
+ * plus four product vectors.  Errors: SSA_EINVAL (sizes, null bytes).
+ */
+int ssa_tune_workspace(long long N, long long L, size_t* bytes);
+
+/*
+ * ssa_tune_fft -- choose the FFT schedule of the products X v and X^T u
+ * (Algorithms 2 and 3) by measurement.  Any M >= N gives the exact correlation
+ * (Sec. 4.2), so the transform length M' = M/2 is free above ceil(N/2), and so
+ * are its split M' = M1 * M2 and the columns per workgroup CB of passes 1 and 3.
+ * Candidates: the automatic schedule; the 8 smallest 7-smooth M' in
+ * [ceil(N/2), 1.25 ceil(N/2)] that split into factors in [16, 4096], each with
+ * its 6 most balanced splits and CB in {1, 2, 4, 8} (CB * M1 <= 8192, CB <= M2).
+ * Each candidate: a plan is created and bound to workspace_dev, series_dev is
+ * embedded, 2 product pairs warm up, then 3 runs of reps pairs are timed with
+ * HIP events on hip_stream (hipStream_t as void*, NULL = default stream); the
+ * candidate's time is its fastest run per pair.  The product time does not
+ * depend on the series' values.
+ *   series_dev: N doubles on the device (read only).
+ *   workspace_dev: >= ssa_tune_workspace bytes, 256-byte aligned, overwritten.
+ *   best: its fft_mp, fft_m1 and fft_cb receive the fastest schedule (explicit
+ *     values, never 0); its other fields are left as they are.
+ *   us_best (may be NULL): microseconds per product pair of that schedule.
+ *   rows/us (may be NULL when max_rows = 0): the first max_rows candidates
+ *     timed, as {M', M1, CB} triples in rows and microseconds per pair in us;
+ *     *nrows (may be NULL) receives the number of candidates timed.
+ * Synchronizes hip_stream.  Errors: SSA_EINVAL (sizes, null pointers),
+ * SSA_ENOMEM (workspace too small or misaligned), SSA_ENONFINITE (series),
+ * SSA_EDEVICE.
+ */
+int ssa_tune_fft(long long N, long long L, const double* series_dev, void* workspace_dev, size_t bytes,
+                 void* hip_stream, int reps, ssa_opts* best, double* us_best, int max_rows, long long* rows,
+                 double* us, int* nrows);
 
 /* ssa_plan_describe -- copy the plan's sizes into *desc. */
 int ssa_plan_describe(ssa_plan plan, ssa_plan_desc* desc);

@@ -37,18 +37,25 @@ bool smooth7(long long n) {
     return n == 1;
 }
 
+// The most balanced split M' = M1 * M2 (M1 <= M2, both <= kMaxFactor) of a
+// 7-smooth M', or 0 if M' has none.
+int balanced_m1(long long mp) {
+    if (!smooth7(mp)) return 0;
+    int best1 = 0;
+    for (long long a = 1; a * a <= mp; ++a) {
+        if (mp % a) continue;
+        const long long b = mp / a;
+        if (b > kMaxFactor || a > kMaxFactor) continue;
+        best1 = (int)a;  // largest a <= sqrt(mp) that works
+    }
+    return best1;
+}
+
 // Smallest M' >= ceil(N/2) with a split M' = M1 * M2, both 7-smooth and
 // <= kMaxFactor; among the splits of that M' the most balanced one (M1 <= M2).
 bool choose_fft(long long N, long long& Mp, int& M1, int& M2) {
     for (long long mp = (N + 1) / 2; mp <= (long long)kMaxFactor * kMaxFactor; ++mp) {
-        if (!smooth7(mp)) continue;
-        int best1 = 0;
-        for (long long a = 1; a * a <= mp; ++a) {
-            if (mp % a) continue;
-            const long long b = mp / a;
-            if (b > kMaxFactor || a > kMaxFactor) continue;
-            best1 = (int)a;  // largest a <= sqrt(mp) that works
-        }
+        const int best1 = balanced_m1(mp);
         if (best1 > 0) {
             Mp = mp;
             M1 = best1;
@@ -432,6 +439,17 @@ static int plan_create(long long N, long long L, long long K, int is2d, long lon
     if (!choose_fft(N, Mp, M1, M2)) {
         delete p;
         return SSA_EINVAL;
+    }
+    if (opts && opts->fft_mp > 0) {  // a longer transform: any M >= N gives the exact correlation
+        const long long mp = opts->fft_mp;
+        const int m1 = mp >= Mp && mp <= (long long)kMaxFactor * kMaxFactor ? balanced_m1(mp) : 0;
+        if (m1 == 0) {
+            delete p;
+            return SSA_EINVAL;
+        }
+        Mp = mp;
+        M1 = m1;
+        M2 = (int)(mp / m1);
     }
     if (opts && opts->fft_m1 > 0) {  // schedule override: M1 must split M' into factors <= kMaxFactor
         const long long m1 = opts->fft_m1;
@@ -890,6 +908,7 @@ int ssa_plan_describe(ssa_plan p, ssa_plan_desc* d) {
     d->d_max = p->d_max;
     d->k_max = p->k_max;
     d->workspace_bytes = p->ws_bytes;
+    d->cb = p->g.CB;
     return SSA_OK;
 }
 

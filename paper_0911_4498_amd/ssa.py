@@ -29,7 +29,7 @@ _c_p = ctypes.c_void_p
 class SsaOpts(ctypes.Structure):
     _fields_ = [("d_max", ctypes.c_int), ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
                 ("seed", ctypes.c_ulonglong), ("fft_m1", ctypes.c_int), ("fft_cb", ctypes.c_int),
-                ("restart_keep", ctypes.c_int), ("reorth", ctypes.c_int)]
+                ("restart_keep", ctypes.c_int), ("reorth", ctypes.c_int), ("fft_mp", ctypes.c_longlong)]
 
 
 class SsaInfo(ctypes.Structure):
@@ -40,7 +40,8 @@ class SsaInfo(ctypes.Structure):
 
 class SsaPlanDesc(ctypes.Structure):
     _fields_ = [("N", _c_ll), ("L", _c_ll), ("K", _c_ll), ("M", _c_ll), ("M1", _c_ll), ("M2", _c_ll),
-                ("d_max", ctypes.c_int), ("k_max", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t)]
+                ("d_max", ctypes.c_int), ("k_max", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
+                ("cb", ctypes.c_int)]
 
 
 EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
@@ -50,7 +51,7 @@ EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed",
             "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
             "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
             "ssa_server_status", "ssa_server_destroy", "ssa_hmatrix_workspace", "ssa_hmatrix",
-            "ssa_realizations_workspace", "ssa_realizations")
+            "ssa_realizations_workspace", "ssa_realizations", "ssa_tune_workspace", "ssa_tune_fft")
 
 # kernel classes of ssa_batch_profile_read (enum ssa_batch_prof_class)
 BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
@@ -124,6 +125,10 @@ def load():
                                      _c_p, _c_p, _c_p]
     lib.ssa_server_destroy.argtypes = [_c_p]
     lib.ssa_server_destroy.restype = None
+    lib.ssa_tune_workspace.argtypes = [_c_ll, _c_ll, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ssa_tune_fft.argtypes = [_c_ll, _c_ll, _c_p, _c_p, ctypes.c_size_t, _c_p, ctypes.c_int,
+                                 ctypes.POINTER(SsaOpts), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                 ctypes.POINTER(_c_ll), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     for name in EXPORTED:
         if name not in ("ssa_plan_destroy", "ssa_status_str", "ssa_batch_destroy", "ssa_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
@@ -182,7 +187,7 @@ class Plan:
 
     def __init__(self, N: int, L: int, k_max: int, d_max: int = 0, check_every: int = 0,
                  tol: float = 0.0, seed: int = 0, device=None, stream=None, fft_m1: int = 0, fft_cb: int = 0,
-                 restart_keep: int = 0, reorth: int = 0):
+                 restart_keep: int = 0, reorth: int = 0, fft_mp: int = 0):
         import torch
         self._torch = torch
         lib = load()
@@ -190,7 +195,7 @@ class Plan:
         self.N, self.L, self.K = int(N), int(L), int(N) - int(L) + 1
         self.k_max = int(k_max)
         opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), int(fft_m1), int(fft_cb),
-                       int(restart_keep), int(reorth))
+                       int(restart_keep), int(reorth), int(fft_mp))
         ws = ctypes.c_size_t(0)
         h = _c_p()
         _check(self._create(opts, ws, h), "ssa_embed_plan")
@@ -301,6 +306,43 @@ class Plan:
                                       ctypes.cast(mem_a, _c_p), m, out.data_ptr())
         _check(rc, "ssa_reconstruct")
         return out
+
+
+def tune_fft(N: int, L: int, series=None, reps: int = 20, max_rows: int = 512, device=None, stream=None):
+    """Time the FFT schedules of the products for (N, L) with ``ssa_tune_fft``.
+
+    ``series`` (N values; zeros if None) is embedded for every candidate; the time per
+    product pair does not depend on its values.  Returns (best, us_best, table): best is
+    {"fft_mp", "fft_m1", "fft_cb"} to pass to Plan, us_best its microseconds per pair
+    (X v and X^T u), and table a list of (M', M1, CB, us) for every candidate timed."""
+    import torch
+    lib = load()
+    N, L = int(N), int(L)
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    need = ctypes.c_size_t(0)
+    _check(lib.ssa_tune_workspace(N, L, ctypes.byref(need)), "ssa_tune_workspace")
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    off = (-base) % 256
+    if series is None:
+        f = torch.zeros(N, dtype=torch.float64, device=dev)
+    else:
+        f = torch.as_tensor(series, dtype=torch.float64, device=dev).contiguous()
+        if f.numel() != N:
+            raise ValueError("series length differs from N")
+    best = SsaOpts()
+    us_best = ctypes.c_double(0)
+    rows = (_c_ll * (3 * max(1, max_rows)))()
+    us = (ctypes.c_double * max(1, max_rows))()
+    nrows = ctypes.c_int(0)
+    _check(lib.ssa_tune_fft(N, L, _c_p(f.data_ptr()), _c_p(base + off), int(need.value),
+                            _c_p(st.cuda_stream), int(reps), ctypes.byref(best), ctypes.byref(us_best),
+                            int(max_rows), rows, us, ctypes.byref(nrows)), "ssa_tune_fft")
+    n = min(int(nrows.value), max_rows)
+    table = [(int(rows[3 * i]), int(rows[3 * i + 1]), int(rows[3 * i + 2]), float(us[i])) for i in range(n)]
+    return ({"fft_mp": int(best.fft_mp), "fft_m1": int(best.fft_m1), "fft_cb": int(best.fft_cb)},
+            float(us_best.value), table)
 
 
 class Plan2D(Plan):

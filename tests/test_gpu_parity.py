@@ -103,18 +103,26 @@ def test_matvec_large(ssa, N, L):
     assert e2 <= mv_tol(f, u, plan.desc.M)
 
 
-@pytest.mark.parametrize("N,L,m1,cb", [(100000, 50000, 16, 1), (100000, 50000, 400, 16), (100000, 50000, 3125, 2),
-                                       (100000, 50000, 1000, 8), (20000, 10000, 100, 32), (1000, 500, 25, 8)])
-def test_matvec_fft_schedules(ssa, N, L, m1, cb):
-    """Every FFT schedule (split M' = M1 M2, columns per workgroup) gives the same products."""
-    say(f"matvec schedule N={N} L={L} M1={m1} CB={cb}")
+@pytest.mark.parametrize("N,L,m1,cb,mp", [(100000, 50000, 16, 1, 0), (100000, 50000, 400, 16, 0),
+                                          (100000, 50000, 3125, 2, 0), (100000, 50000, 1000, 8, 0),
+                                          (20000, 10000, 100, 32, 0), (1000, 500, 25, 8, 0),
+                                          (100000, 50000, 200, 1, 51200), (100000, 50000, 224, 2, 50176),
+                                          (100000, 50000, 256, 4, 65536), (1000, 500, 25, 1, 625),
+                                          (99999, 33333, 0, 0, 54000), (7, 3, 0, 0, 256)])
+def test_matvec_fft_schedules(ssa, N, L, m1, cb, mp):
+    """Every FFT schedule (transform length M' >= ceil(N/2), split M' = M1 M2, columns per
+    workgroup) gives the same products."""
+    say(f"matvec schedule N={N} L={L} M1={m1} CB={cb} M'={mp}")
     K = N - L + 1
     f = inputs.c2_series(N)
     rng = np.random.default_rng(N + m1 + cb)
     v = rng.normal(size=K)
     u = rng.normal(size=L)
-    plan = ssa.Plan(N, L, 1, fft_m1=m1, fft_cb=cb)
-    assert plan.desc.M1 == m1
+    plan = ssa.Plan(N, L, 1, fft_m1=m1, fft_cb=cb, fft_mp=mp)
+    if m1:
+        assert plan.desc.M1 == m1
+    if mp:
+        assert plan.desc.M == 2 * mp
     plan.embed(torch.tensor(f, device="cuda"))
     y = plan.matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()
     yt = plan.matvec(torch.tensor(u, dtype=torch.float32, device="cuda"), transpose=True).cpu().numpy()
@@ -338,18 +346,27 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
-@pytest.mark.parametrize("d_max,keep,reorth", [(0, 0, 0), (60, 30, 0), (0, 0, 1)])
-def test_c2_full_size(ssa, d_max, keep, reorth):
+@pytest.mark.parametrize("d_max,keep,reorth,sched", [(0, 0, 0, "auto"), (60, 30, 0, "auto"), (0, 0, 1, "auto"),
+                                                     (0, 0, 0, "table")])
+def test_c2_full_size(ssa, d_max, keep, reorth, sched):
     """N=100000, L=50000, k=20: sigma and sampled reconstructions vs the tier-B oracle
     (stored), plus residual and orthogonality certificates computed here in FP64: the plain
-    solver, the basis capped at 60 columns (thick restart keeping 30), and one-sided
-    reorthogonalization."""
-    say(f"c2 full size d_max={d_max} keep={keep} reorth={reorth}")
+    solver, the basis capped at 60 columns (thick restart keeping 30), one-sided
+    reorthogonalization, and the FFT schedule of the tuner table (what the benchmark runs)."""
+    say(f"c2 full size d_max={d_max} keep={keep} reorth={reorth} schedule={sched}")
     g = json.load(open(GOLDEN))
     N, L, k = 100_000, 50_000, 20
     K = N - L + 1
     f = inputs.c2_series(N)
-    plan, s, U, V, info = run_gpu(ssa, f, L, k, d_max=d_max, restart_keep=keep, reorth=reorth)
+    kw = {}
+    if sched == "table":
+        from paper_0911_4498_amd import autotune
+        kw = autotune.lookup(N, L) or {}
+        if not kw:
+            pytest.skip("no tuner table entry for N=100000, L=50000")
+    plan, s, U, V, info = run_gpu(ssa, f, L, k, d_max=d_max, restart_keep=keep, reorth=reorth, **kw)
+    if kw:
+        assert plan.desc.M == 2 * kw["fft_mp"] and plan.desc.M1 == kw["fft_m1"] and plan.desc.cb == kw["fft_cb"]
     sg = s.cpu().numpy()
     s_ref = np.array(g["sigma"])
     say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes} "

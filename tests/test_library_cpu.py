@@ -136,6 +136,96 @@ def test_fft_schedule_override():
     assert plan(200, 65)[0] == ssa.SSA_EINVAL
 
 
+def _plan_mp(N, L, mp, m1=0, cb=0):
+    lib = _built()
+    opts = ssa.SsaOpts(0, 0, 0.0, 0, m1, cb, 0, 0, mp)
+    ws = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    rc = lib.ssa_embed_plan(N, L, 4, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h))
+    d = ssa.SsaPlanDesc()
+    if rc == 0:
+        assert lib.ssa_plan_describe(h, ctypes.byref(d)) == 0
+        lib.ssa_plan_destroy(h)
+    return rc, d
+
+
+def test_fft_length_override():
+    """ssa_opts.fft_mp picks a longer transform (any M >= N is exact): it must be 7-smooth,
+    at least the smallest admissible M' and split into factors <= 4096."""
+    rc, d = _plan_mp(100000, 50000, 51200)
+    assert rc == 0 and d.M == 102400 and d.M1 * d.M2 == 51200 and d.M1 <= d.M2
+    rc, d = _plan_mp(100000, 50000, 51200, 256, 2)
+    assert rc == 0 and (d.M1, d.M2, d.cb) == (256, 200, 2)
+    rc, d = _plan_mp(1000, 500, 512)
+    assert rc == 0 and d.M == 1024
+    assert _plan_mp(100000, 50000, 49152)[0] == ssa.SSA_EINVAL   # M = 98304 < N
+    assert _plan_mp(100000, 50000, 50001)[0] == ssa.SSA_EINVAL   # not 7-smooth
+    assert _plan_mp(100000, 50000, 50000 * 11)[0] == ssa.SSA_EINVAL
+    assert _plan_mp(1000, 500, 8192 * 4096)[0] == ssa.SSA_EINVAL  # no split into factors <= 4096
+    assert _plan_mp(100000, 50000, 51200, 300)[0] == ssa.SSA_EINVAL  # 300 does not divide 51200
+
+
+def test_tuner_host_checks():
+    """ssa_tune_workspace covers every candidate plan; ssa_tune_fft validates its arguments
+    and the workspace before it touches the device."""
+    lib = _built()
+    b = ctypes.c_size_t(0)
+    assert lib.ssa_tune_workspace(100000, 50000, ctypes.byref(b)) == 0
+    rc, h, ws_auto = make_plan(100000, 50000, 1, 2)
+    lib.ssa_plan_destroy(h)
+    assert rc == 0 and b.value >= ws_auto + 4 * 2 * 100001
+    opts = ssa.SsaOpts(2, 0, 0.0, 0, 0, 0, 0, 0, 51200)  # a candidate length above the smallest
+    ws = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    assert lib.ssa_embed_plan(100000, 50000, 1, ctypes.byref(opts), ctypes.byref(ws), ctypes.byref(h)) == 0
+    lib.ssa_plan_destroy(h)
+    assert b.value >= ws.value + 4 * 2 * 100001
+    assert lib.ssa_tune_workspace(100, 100, ctypes.byref(b)) == ssa.SSA_EINVAL
+    assert lib.ssa_tune_workspace(2, 1, ctypes.byref(b)) == ssa.SSA_EINVAL
+    assert lib.ssa_tune_workspace(100, 40, None) == ssa.SSA_EINVAL
+    best = ssa.SsaOpts()
+    fake = ctypes.c_void_p(1 << 20)
+    args = (1000, 500, fake, fake)
+    need = ctypes.c_size_t(0)
+    assert lib.ssa_tune_workspace(1000, 500, ctypes.byref(need)) == 0
+    n = ctypes.c_int(0)
+    assert lib.ssa_tune_fft(*args, need.value - 1, None, 5, ctypes.byref(best), None, 0, None, None,
+                            ctypes.byref(n)) == ssa.SSA_ENOMEM
+    assert lib.ssa_tune_fft(1000, 500, fake, ctypes.c_void_p((1 << 20) + 4), need.value, None, 5,
+                            ctypes.byref(best), None, 0, None, None, None) == ssa.SSA_ENOMEM  # misaligned
+    assert lib.ssa_tune_fft(*args, need.value, None, 0, ctypes.byref(best), None, 0, None, None,
+                            None) == ssa.SSA_EINVAL  # reps
+    assert lib.ssa_tune_fft(*args, need.value, None, 5, None, None, 0, None, None, None) == ssa.SSA_EINVAL
+    assert lib.ssa_tune_fft(*args, need.value, None, 5, ctypes.byref(best), None, 4, None, None,
+                            None) == ssa.SSA_EINVAL  # rows missing
+    assert lib.ssa_tune_fft(1000, 500, None, fake, need.value, None, 5, ctypes.byref(best), None, 0, None, None,
+                            None) == ssa.SSA_EINVAL
+    assert (best.fft_mp, best.fft_m1, best.fft_cb) == (0, 0, 0)  # untouched on error
+
+
+def test_schedule_table(tmp_path):
+    """The tuner table: store/lookup round trip, and every stored entry is a valid schedule
+    for its (N, L)."""
+    from paper_0911_4498_amd import autotune
+    path = str(tmp_path / "t.json")
+    assert autotune.lookup(1000, 500, path) is None
+    autotune.store(1000, 500, {"fft_mp": 512, "fft_m1": 16, "fft_cb": 2, "us_per_pair": 1.0}, path)
+    autotune.store(100000, 50000, {"fft_mp": 51200, "fft_m1": 200, "fft_cb": 1}, path)
+    assert autotune.lookup(1000, 500, path) == {"fft_mp": 512, "fft_m1": 16, "fft_cb": 2}
+    assert autotune.lookup(1000, 501, path) is None
+    assert list(autotune.load_table(path)) == ["1000:500", "100000:50000"]
+    with open(path, "w") as fh:
+        fh.write("[1, 2]")
+    with pytest.raises(ValueError):
+        autotune.load_table(path)
+    for key, e in autotune.load_table(autotune.TABLE).items():
+        N, L = (int(x) for x in key.split(":"))
+        rc, d = _plan_mp(N, L, e["fft_mp"], e["fft_m1"], e["fft_cb"])
+        assert rc == 0, key
+        assert (d.M // 2, d.M1, d.cb) == (e["fft_mp"], e["fft_m1"], e["fft_cb"])
+        assert e["us_per_pair"] <= e["auto"]["us_per_pair"]
+
+
 def test_batch_validation_and_workspace():
     """The many-series entry points validate on the host before anything is enqueued, and
     the workspace a solve needs is a pure function of the series shapes."""
