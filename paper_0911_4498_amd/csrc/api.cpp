@@ -713,12 +713,12 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
             SSA_TRY(hipMemcpyAsync(dP, h_P, sizeof(double) * (size_t)nu * m, hipMemcpyHostToDevice, s));
             SSA_TRY(hipMemcpyAsync(dQ, h_Q, sizeof(double) * (size_t)nc * m, hipMemcpyHostToDevice, s));
             {
-                ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + m) * ((m + 15) / 16));
+                ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + m));
                 SSA_TRY(launch_ritz(U, p->ldU, nu, dP, m, rot, p->ldU, Li, s));
             }
             SSA_TRY(hipMemcpyAsync(U, rot, sizeof(float) * (size_t)m * p->ldU, hipMemcpyDeviceToDevice, s));
             {
-                ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + m) * ((m + 15) / 16));
+                ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + m));
                 SSA_TRY(launch_ritz(V, p->ldV, nc, dQ, m, rot, p->ldV, Ki, s));
             }
             // nc >= m + 2 (keep + 2 <= d_max), so columns nc and m are distinct
@@ -781,11 +781,11 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
     float* Vo = p->transposed ? U_dev : V_dev;
     {
-        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + k) * ((k + 15) / 16));
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + k));
         SSA_TRY(launch_ritz(U, p->ldU, nu, dP, k, Uo, Li, Li, s));
     }
     {
-        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + k) * ((k + 15) / 16));
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + k));
         SSA_TRY(launch_ritz(V, p->ldV, nc, dQ, k, Vo, Ki, Ki, s));
     }
     double st[3] = {0, 0, 0};

@@ -877,6 +877,7 @@ __global__ __launch_bounds__(256) void k_cgs_update(const float* r, const float*
 // ---------------------------------------------------------------------------
 // Ritz vectors: out[i*ldo + t] = sum_c basis[c*ld + t] P[c*k + i]
 
+// Short vectors: kRitzTile triples per workgroup with their coefficients staged in LDS.
 constexpr int kRitzTile = 16;
 __global__ __launch_bounds__(256) void k_ritz(const float* __restrict__ basis, long long ld, int ncols,
                                               const double* __restrict__ P, int k, float* __restrict__ out,
@@ -901,6 +902,44 @@ __global__ __launch_bounds__(256) void k_ritz(const float* __restrict__ basis, l
     }
 #pragma unroll
     for (int i = 0; i < kRitzTile; ++i)
+        if (i < kt) out[(long long)(i0 + i) * ldo + t] = (float)acc[i];
+}
+
+// Long vectors: one row per thread and kRitzWideTile triples per workgroup.  The
+// coefficients of a column are the same for every lane, so they are read with a
+// wave-uniform address (scalar loads, scalar operands of the FP64 FMAs) instead of
+// LDS; fewer tiles also mean fewer passes over the basis.  Needs many waves per
+// SIMD to hide the scalar-load latency of each column, hence long vectors only.
+constexpr int kRitzWideTile = 32;
+__global__ __launch_bounds__(256) void k_ritz_long(const float* __restrict__ basis, long long ld, int ncols,
+                                              const double* __restrict__ P, int k, float* __restrict__ out,
+                                              long long ldo, long long n) {
+    const int i0 = blockIdx.y * kRitzWideTile;
+    const int kt = min(kRitzWideTile, k - i0);
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    double acc[kRitzWideTile];
+#pragma unroll
+    for (int i = 0; i < kRitzWideTile; ++i) acc[i] = 0.0;
+    if (kt == kRitzWideTile) {
+#pragma unroll 2
+        for (int c = 0; c < ncols; ++c) {
+            const double x = basis[(long long)c * ld + t];
+            const double* pc = P + (long long)c * k + i0;
+#pragma unroll
+            for (int i = 0; i < kRitzWideTile; ++i) acc[i] += x * pc[i];
+        }
+    } else {
+        for (int c = 0; c < ncols; ++c) {
+            const double x = basis[(long long)c * ld + t];
+            const double* pc = P + (long long)c * k + i0;
+#pragma unroll
+            for (int i = 0; i < kRitzWideTile; ++i)
+                if (i < kt) acc[i] += x * pc[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kRitzWideTile; ++i)
         if (i < kt) out[(long long)(i0 + i) * ldo + t] = (float)acc[i];
 }
 
@@ -1102,9 +1141,14 @@ hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, i
 
 hipError_t launch_ritz(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
                        long long ldo, long long n, hipStream_t s) {
-    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((k + kRitzTile - 1) / kRitzTile));
-    const size_t lds = sizeof(double) * (size_t)ncols * kRitzTile;
-    hipLaunchKernelGGL(k_ritz, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, n);
+    if (n >= kRitzWideRows) {
+        const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((k + kRitzWideTile - 1) / kRitzWideTile));
+        hipLaunchKernelGGL(k_ritz_long, grid, dim3(256), 0, s, basis, ld, ncols, P, k, out, ldo, n);
+    } else {
+        const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((k + kRitzTile - 1) / kRitzTile));
+        const size_t lds = sizeof(double) * (size_t)ncols * kRitzTile;
+        hipLaunchKernelGGL(k_ritz, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, n);
+    }
     return hipGetLastError();
 }
 

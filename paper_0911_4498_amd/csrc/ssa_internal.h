@@ -89,6 +89,7 @@ constexpr int kProjRows = 1024;  // rows per workgroup in the projection kernel 
 constexpr int kProjCols = 8;     // basis columns per workgroup in the projection kernel
 constexpr int kProjColsNarrow = 4;    // ... for vectors of at most kProjNarrowChunks row chunks
 constexpr int kProjNarrowChunks = 64;
+constexpr long long kRitzWideRows = 1LL << 20;  // Ritz rotations of longer vectors use the scalar-load kernel
 constexpr int kMaxCols = 2048;   // most basis columns one projection handles
 constexpr int kColsumChunks = 256;  // above this many row chunks the column sums get their own launch
 
