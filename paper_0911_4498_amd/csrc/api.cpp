@@ -26,7 +26,7 @@ constexpr double kResidFloor = 1e-5;    // residuals of omega_i < 1e-5 omega_1 a
 constexpr int kMaxGroupBatch = 64;
 constexpr int kMaxRestartDmax = 512;  // basis cap of the restarted solver (host dense SVD per cycle)
 constexpr int kMaxCycles = 64;        // thick restarts before the solver gives up
-constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 16 row chunks (16384 rows)
+constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 16 x 1024 = 16384 rows
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -272,7 +272,8 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     double* sc = at<double>(p, p->o_sc);
     ReduceArgs a{};
     a.part = at<double>(p, p->o_part);
-    a.nchunks = (int)((n + kProjRows - 1) / kProjRows);
+    a.chunk_rows = proj_chunk_rows(n);
+    a.nchunks = (int)((n + a.chunk_rows - 1) / a.chunk_rows);
     a.pstride = p->pstride;
     a.ncols = ncols;
     a.r = r;
@@ -298,7 +299,8 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     // minutes) and for the reorthogonalized side of the one-sided scheme, where it is
     // frequent.  There the finish hands it to four gated launches over the whole grid,
     // which return at once when no second pass was needed.
-    const bool grid2 = ncols > 0 && a.nchunks > (p->onesided ? kGrid2ChunksOneSided : kColsumChunks);
+    const long long grid2_rows = (long long)(p->onesided ? kGrid2ChunksOneSided : kColsumChunks) * kProjRows;
+    const bool grid2 = ncols > 0 && n > grid2_rows;
     int* flag2 = at<int>(p, p->o_flag) + 8;
     a.dgks_flag = grid2 ? flag2 : nullptr;
     if (a.presummed) {

@@ -760,24 +760,26 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
 // Projection h = basis^T r and |r|^2, FP64 sums of exact FP32 products, in
 // (row chunk, column group of CJ columns) tiles: part[c * pstride + chunk] for
 // c < ncols, and part[ncols * pstride + chunk] = the chunk's |r|^2 (column
-// group 0).
+// group 0).  A chunk is a.chunk_rows rows, summed in steps of kProjRows (one
+// float4 row per thread) before the workgroup's reduction.
 template <int CJ>
 __global__ __launch_bounds__(256) void k_cgs_project(ReduceArgs a) {
     if (a.gate && *a.gate == 0) return;
     __shared__ double red[CJ + 1][4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long long t = (long long)blockIdx.x * kProjRows + 4 * tid;
     const int c0 = blockIdx.y * CJ;
     const int nc = min(CJ, a.ncols - c0);
-    const bool in = t < a.n;
-    const float4 rv = in ? rows4(a.r, t, a.n) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const long long tend = min(a.n, (long long)(blockIdx.x + 1) * a.chunk_rows);
     double acc[CJ + 1];
 #pragma unroll
-    for (int c = 0; c < CJ; ++c) {
-        acc[c] = 0.0;
-        if (c < nc && in) acc[c] = dot4(rows4(a.basis + (long long)(c0 + c) * a.ld, t, a.n), rv);
+    for (int c = 0; c <= CJ; ++c) acc[c] = 0.0;
+    for (long long t = (long long)blockIdx.x * a.chunk_rows + 4 * tid; t < tend; t += kProjRows) {
+        const float4 rv = rows4(a.r, t, a.n);
+#pragma unroll
+        for (int c = 0; c < CJ; ++c)
+            if (c < nc) acc[c] += dot4(rows4(a.basis + (long long)(c0 + c) * a.ld, t, a.n), rv);
+        if (blockIdx.y == 0) acc[CJ] += dot4(rv, rv);
     }
-    acc[CJ] = blockIdx.y == 0 ? dot4(rv, rv) : 0.0;
 #pragma unroll
     for (int c = 0; c <= CJ; ++c) {
         const double v = wave_sum(acc[c]);
@@ -1112,7 +1114,7 @@ hipError_t launch_start_vector(float* r, long long n, unsigned long long seed, h
 // gain from more, smaller workgroups; long ones re-read r once per column group, so they
 // take wider groups.
 hipError_t launch_cgs_project(const ReduceArgs& a, hipStream_t s) {
-    const unsigned nchunks = (unsigned)((a.n + kProjRows - 1) / kProjRows);
+    const unsigned nchunks = (unsigned)a.nchunks;
     const int cj = nchunks <= kProjNarrowChunks ? kProjColsNarrow : kProjCols;
     const unsigned ngrp = a.ncols > 0 ? (unsigned)((a.ncols + cj - 1) / cj) : 1u;
     if (cj == kProjColsNarrow)

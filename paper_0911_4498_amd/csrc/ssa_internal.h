@@ -82,6 +82,7 @@ struct ReduceArgs {
     int* dgks_flag;     // non-null: a second pass is left to the gated launches (flag set to 1)
     const int* gate;    // non-null: the launch does nothing unless *gate != 0
     double tol_bd;      // breakdown threshold relative to state[0]
+    long long chunk_rows;  // rows per projection workgroup (a multiple of kProjRows); nchunks of them
 };
 
 constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many terms are summed directly
@@ -90,6 +91,13 @@ constexpr int kProjCols = 8;     // basis columns per workgroup in the projectio
 constexpr int kProjColsNarrow = 4;    // ... for vectors of at most kProjNarrowChunks row chunks
 constexpr int kProjNarrowChunks = 64;
 constexpr long long kRitzWideRows = 1LL << 20;  // Ritz rotations of longer vectors use the scalar-load kernel
+constexpr int kProjLongChunks = 8;  // row chunks per projection workgroup for vectors longer than ...
+constexpr long long kProjLongRows = 1LL << 20;  // ... this many rows (fewer reductions and partial sums)
+
+// Rows that one projection workgroup sums before its reduction.
+inline long long proj_chunk_rows(long long n) {
+    return n > kProjLongRows ? (long long)kProjRows * kProjLongChunks : (long long)kProjRows;
+}
 constexpr int kMaxCols = 2048;   // most basis columns one projection handles
 constexpr int kColsumChunks = 256;  // above this many row chunks the column sums get their own launch
 
