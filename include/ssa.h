@@ -444,12 +444,15 @@ int ssa_dense_ritz(const double* A, int nr, int nc, int k, double* omega, double
  *   (Algorithms 2/3); DOTS/REDUCE/UPDATE: the Gram-Schmidt projection,
  *   coefficient reduction and update (Sec. 3.2.2); RITZ: Ritz vectors;
  *   RECON1/2/3: the FFT passes of the grouped rank-1 Hankelization
- *   (Algorithm 4); EMBED: the spectrum of the series (Algorithm 2, steps 1-2).
+ *   (Algorithm 4); EMBED: the spectrum of the series (Algorithm 2, steps 1-2);
+ *   DGKS2: the launches of a DGKS second Gram-Schmidt pass over the whole grid
+ *   (long vectors), which return at once unless the criterion fired on the
+ *   device; their algorithmic bytes are counted as 0.
  */
 enum ssa_prof_class {
     SSA_PROF_PASS1 = 0, SSA_PROF_PASS2, SSA_PROF_PASS3, SSA_PROF_DOTS, SSA_PROF_REDUCE,
     SSA_PROF_UPDATE, SSA_PROF_RITZ, SSA_PROF_RECON1, SSA_PROF_RECON2, SSA_PROF_RECON3,
-    SSA_PROF_EMBED, SSA_PROF_NCLASSES
+    SSA_PROF_EMBED, SSA_PROF_DGKS2, SSA_PROF_NCLASSES
 };
 
 /*

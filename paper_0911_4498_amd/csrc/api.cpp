@@ -317,25 +317,27 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
         SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, out, n, nullptr, s));
     }
     if (grid2) {
-        // second pass on out = r - basis h (in place); no algorithmic bytes unless it runs
+        // second pass on out = r - basis h (in place), a profiling class of its own: these
+        // launches return at once unless the finish asked for the pass, so they would
+        // distort the per-launch times of the first-pass classes
         ReduceArgs b = a;
         b.r = out;
         b.dgks_flag = nullptr;
         b.gate = flag2;
         {
-            ProfScope ps(p, SSA_PROF_DOTS, 0.0);
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
             SSA_TRY(launch_cgs_project(b, s));
         }
         if (b.presummed) {
-            ProfScope ps(p, SSA_PROF_REDUCE, 0.0);
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
             SSA_TRY(launch_cgs_colsum(b, s));
         }
         {
-            ProfScope ps(p, SSA_PROF_REDUCE, 0.0);
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
             SSA_TRY(launch_cgs_reduce(b, s));
         }
         {
-            ProfScope ps(p, SSA_PROF_UPDATE, 0.0);
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
             SSA_TRY(launch_cgs_update(out, basis, ld, ncols, h, sc, out, n, flag2, s));
         }
     }

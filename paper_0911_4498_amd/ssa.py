@@ -58,7 +58,7 @@ BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
 
 # kernel classes of ssa_profile_read (enum ssa_prof_class)
 PROF_CLASSES = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz",
-                "recon_pass1", "recon_pass2", "recon_pass3", "embed")
+                "recon_pass1", "recon_pass2", "recon_pass3", "embed", "dgks2")
 
 _lib = None
 

@@ -407,3 +407,33 @@ def test_c2_full_size(ssa, d_max, keep, reorth, sched):
     assert worst <= 1e-5
     G = Ug @ Ug.T
     assert np.abs(G - np.eye(k)).max() <= 1e-5
+
+
+def test_profile_classes(ssa):
+    """Profiling counters: every class of the path is counted, the gated second-pass
+    launches of long one-sided bases are a class of their own (no bytes), and sampling one
+    launch in three still gives a time for the sampled classes."""
+    say("profile classes")
+    f = inputs.c1_series(1000)
+    plan = ssa.Plan(1000, 500, 10)
+    plan.profile_enable(every=3)
+    s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 10)
+    plan.reconstruct(s, U, V, [[0, 1], [2]])
+    pr = plan.profile_read()
+    for c in ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz", "recon_pass2"):
+        n, ms, b = pr[c]
+        assert n > 0 and ms > 0 and b > 0, (c, pr[c])
+    assert pr["pass2"][0] >= 2 * info.steps_run - 1
+    assert pr["dgks2"][0] == 0  # short vectors: the second pass stays in the finish
+    plan.close()
+    # one-sided with U longer than 16384 rows: every U-side step adds three gated launches
+    N, L = 40000, 20000
+    f = inputs.c2_series(N)
+    plan = ssa.Plan(N, L, 8, reorth=1)
+    plan.profile_enable(every=3)
+    s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 8)
+    pr = plan.profile_read()
+    say(f"  steps_run={info.steps_run} dgks={info.dgks_passes} dgks2 launches={pr['dgks2'][0]}")
+    assert pr["dgks2"][0] >= 3 * (info.steps_run - 1) and pr["dgks2"][2] == 0.0
+    assert pr["cgs_dots"][2] > 0
+    plan.close()
