@@ -1,8 +1,8 @@
 // batch.hip -- many independent series advanced in lockstep.
 //
-// Every launch has one workgroup (512 threads) per series of the batch, and a
-// series' result depends only on the series and its seed, never on what runs
-// beside it.  Per Lanczos step the host enqueues
+// Every launch has one workgroup per series of the batch (1024 threads for the
+// kernels that hold an FFT in LDS, 512 for the others), and a series' result
+// depends only on the series and its seed, never on what runs beside it.  Per Lanczos step the host enqueues
 //   kb_conv, kb_cgs (j, side 0): r_j = X^T u_j - beta_j v_{j-1}, Gram-Schmidt
 //                       against V, alpha_j, v_j         (Algorithm 1; Algorithm 3)
 //   kb_check(j):        stopping test on B_{j-1}         (eqs. lbdiagm1/lbdiagm2)
@@ -44,7 +44,7 @@ struct Lds {  // FFT-product, set-up and Hankelization kernels
     float2 buf[kMaxMp];
     float2 tw_hi[kTwTab];
     float2 tw_lo[kTwTab];
-    double misc[kWaves];
+    double misc[kFftWaves];
 };
 
 // LDS of the stopping-test and Ritz kernels (no FFT buffer: several workgroups per CU)
@@ -65,7 +65,7 @@ SSA_INLINE double wsum(double v) {
     return v;
 }
 
-template <class S>
+template <int W = kWaves, class S>
 SSA_INLINE double block_sum(S* sh, double v, int tid) {
     v = wsum(v);
     __syncthreads();
@@ -73,7 +73,7 @@ SSA_INLINE double block_sum(S* sh, double v, int tid) {
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += sh->misc[w];
+    for (int w = 0; w < W; ++w) s += sh->misc[w];
     __syncthreads();
     return s;
 }
@@ -187,19 +187,19 @@ SSA_INLINE void fft(Lds* sh, const Ser& q, int tid) {
     for (int s = 0; s < ns; ++s) {
         const int R = q.st->radix[s];
         switch (R) {
-            case 8: fft_stage<8, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
-            case 4: fft_stage<4, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
-            case 2: fft_stage<2, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
-            case 3: fft_stage<3, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
-            case 5: fft_stage<5, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
-            default: fft_stage<7, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kThreads); break;
+            case 8: fft_stage<8, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kFftThreads); break;
+            case 4: fft_stage<4, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kFftThreads); break;
+            case 2: fft_stage<2, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kFftThreads); break;
+            case 3: fft_stage<3, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kFftThreads); break;
+            case 5: fft_stage<5, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kFftThreads); break;
+            default: fft_stage<7, DIR, kEpt>(sh->buf, q.Mp, 1, q.Mp, p, tw, tid, kFftThreads); break;
         }
         p *= R;
     }
 }
 
 SSA_INLINE void load_twiddles(Lds* sh, const Ser& q, int tid) {
-    for (int t = tid; t < kTwTab; t += kThreads) {
+    for (int t = tid; t < kTwTab; t += kFftThreads) {
         sh->tw_hi[t] = q.tw[t];
         sh->tw_lo[t] = q.tw[kTwTab + t];
     }
@@ -214,14 +214,14 @@ SSA_INLINE void load_twiddles(Lds* sh, const Ser& q, int tid) {
 SSA_INLINE void convolve(Lds* sh, const Ser& q, const float* x, long long n_in, long long n_out, const float* prev,
                          double coef, float* r_out, int tid) {
     float2* buf = sh->buf;
-    for (int n = tid; n < q.Mp; n += kThreads) {
+    for (int n = tid; n < q.Mp; n += kFftThreads) {
         const long long m0 = 2LL * n, m1 = m0 + 1;
         buf[n] = make_float2(m0 < n_in ? x[n_in - 1 - m0] : 0.0f, m1 < n_in ? x[n_in - 1 - m1] : 0.0f);
     }
     __syncthreads();
     fft<-1>(sh, q, tid);
     // Q(k) = A(k) Z(k) + B(k) conj Z(M'-k), for the bin pair (k, M'-k) owned by one thread
-    for (int k = tid; k <= q.Mp / 2; k += kThreads) {
+    for (int k = tid; k <= q.Mp / 2; k += kFftThreads) {
         const int kp = k == 0 ? 0 : q.Mp - k;
         const float2 z0 = buf[k], z1 = buf[kp];
         const float4 o0 = q.AB[k], o1 = q.AB[kp];
@@ -233,7 +233,7 @@ SSA_INLINE void convolve(Lds* sh, const Ser& q, const float* x, long long n_in, 
     __syncthreads();
     fft<1>(sh, q, tid);
     const float cf = (float)coef;
-    for (long long t = tid; t < n_out; t += kThreads) {
+    for (long long t = tid; t < n_out; t += kFftThreads) {
         const float y = getr(buf, n_in - 1 + t);
         r_out[t] = prev ? y - cf * prev[t] : y;
     }
@@ -405,7 +405,7 @@ SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basi
 // Q(k) = A Z(k) + B conj Z(M'-k), the 1/M' of the inverse folded in), the
 // twiddle tables, the cleared state, and u_1 = p_0 / |p_0| for a seeded
 // Gaussian p_0 (Algorithm 1, first line).
-__global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
+__global__ __launch_bounds__(kFftThreads) void kb_init(BatchArgs a) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
     const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
     const BSeries& b = a.tab[s];
     // twiddles W(t) = e^{-2 pi i t / M'}: lo[t] = W(t), hi[t] = W(t << shift)
     const int S = 1 << q.tw_shift;
-    for (int t = tid; t < kTwTab; t += kThreads) {
+    for (int t = tid; t < kTwTab; t += kFftThreads) {
         double sn, cs;
         float2 lo = make_float2(1.0f, 0.0f), hi = make_float2(1.0f, 0.0f);
         if (t < S) {
@@ -429,17 +429,17 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
         sh->tw_hi[t] = hi;
         sh->tw_lo[t] = lo;
     }
-    for (int i = tid; i < kDmax + 3; i += kThreads) {
+    for (int i = tid; i < kDmax + 3; i += kFftThreads) {
         if (i <= q.dcap + 2) {
             q.alpha[i] = 0.0;
             q.beta[i] = 0.0;
         }
     }
-    for (int i = tid; i < kStDoubles; i += kThreads) q.state[i] = i == kStJ ? 1.0 : 0.0;
+    for (int i = tid; i < kStDoubles; i += kFftThreads) q.state[i] = i == kStJ ? 1.0 : 0.0;
     if (tid == 0 && a.done_flags) a.done_flags[s] = 0;
     const double* f = b.f;
     float2* buf = sh->buf;
-    for (int n = tid; n < q.Mp; n += kThreads) {
+    for (int n = tid; n < q.Mp; n += kFftThreads) {
         const long long m0 = 2LL * n, m1 = m0 + 1;
         buf[n] = make_float2(m0 < q.N ? (float)f[m0] : 0.0f, m1 < q.N ? (float)f[m1] : 0.0f);
     }
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
     fft<-1>(sh, q, tid);
     const double invMp = 1.0 / (double)q.Mp;
     const double M = 2.0 * q.Mp;
-    for (int k = tid; k < q.Mp; k += kThreads) {
+    for (int k = tid; k < q.Mp; k += kFftThreads) {
         const int kp = k == 0 ? 0 : q.Mp - k;
         const float2 z = buf[k], zp = buf[kp];
         const double er = 0.5 * ((double)z.x + (double)zp.x), ei = 0.5 * ((double)z.y - (double)zp.y);
@@ -462,15 +462,15 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
     __syncthreads();
     // start vector
     double ss = 0.0;
-    for (long long t = tid; t < q.Li; t += kThreads) {
+    for (long long t = tid; t < q.Li; t += kFftThreads) {
         const float g = gaussian(q.seed, 0, t);
         q.U[t] = g;
         ss += (double)g * (double)g;
     }
-    ss = block_sum(sh, ss, tid);
+    ss = block_sum<kFftWaves>(sh, ss, tid);
     const double nrm = sqrt(ss);
     const float sc = (float)(1.0 / nrm);
-    for (long long t = tid; t < q.Li; t += kThreads) q.U[t] *= sc;
+    for (long long t = tid; t < q.Li; t += kFftThreads) q.U[t] *= sc;
     if (tid == 0) {
         q.beta[1] = nrm;
         q.state[kStBnorm] = nrm;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void kb_init(BatchArgs a) {
 
 // One half of Lanczos step j for every unfinished series, product part:
 //   side 0: r = X^T u_j - beta_j v_{j-1};   side 1: r = X v_j - alpha_j u_j.
-__global__ __launch_bounds__(kThreads) void kb_conv(BatchArgs a, int side) {
+__global__ __launch_bounds__(kFftThreads) void kb_conv(BatchArgs a, int side) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
     const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
 // the linear convolution by a packed-real FFT; the spectrum of u waits in the
 // region's scratch while v is transformed.  Entries whose antidiagonal has at
 // most kEdge terms are summed directly (FP64 sums of exact FP32 products).
-__global__ __launch_bounds__(kThreads) void kb_hankel(BatchArgs a) {
+__global__ __launch_bounds__(kFftThreads) void kb_hankel(BatchArgs a) {
     extern __shared__ char lds[];
     Lds* sh = reinterpret_cast<Lds*>(lds);
     const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
@@ -875,22 +875,22 @@ __global__ __launch_bounds__(kThreads) void kb_hankel(BatchArgs a) {
         const float* u = b.U + (long long)i * L;
         const float* v = b.V + (long long)i * K;
         float* out = b.recon + (long long)i * N;
-        for (int n = tid; n < Mp; n += kThreads) {
+        for (int n = tid; n < Mp; n += kFftThreads) {
             const long long m0 = 2LL * n, m1 = m0 + 1;
             buf[n] = make_float2(m0 < L ? u[m0] : 0.0f, m1 < L ? u[m1] : 0.0f);
         }
         __syncthreads();
         fft<-1>(sh, q, tid);
-        for (int n = tid; n < Mp; n += kThreads) zu[n] = buf[n];
+        for (int n = tid; n < Mp; n += kFftThreads) zu[n] = buf[n];
         __syncthreads();
-        for (int n = tid; n < Mp; n += kThreads) {
+        for (int n = tid; n < Mp; n += kFftThreads) {
             const long long m0 = 2LL * n, m1 = m0 + 1;
             buf[n] = make_float2(m0 < K ? v[m0] : 0.0f, m1 < K ? v[m1] : 0.0f);
         }
         __syncthreads();
         fft<-1>(sh, q, tid);
         const double sc = sigma / (double)Mp;
-        for (int k = tid; k <= Mp / 2; k += kThreads) {
+        for (int k = tid; k <= Mp / 2; k += kFftThreads) {
             const int kp = k == 0 ? 0 : Mp - k;
             const float2 zu0 = zu[k], zu1 = zu[kp];
             const float2 zv0 = buf[k], zv1 = buf[kp];
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(kThreads) void kb_hankel(BatchArgs a) {
         }
         __syncthreads();
         fft<1>(sh, q, tid);
-        for (long long m = tid; m < N; m += kThreads) {
+        for (long long m = tid; m < N; m += kFftThreads) {
             long long cnt = m + 1;
             if (L < cnt) cnt = L;
             if (K < cnt) cnt = K;
@@ -964,12 +964,12 @@ static hipError_t batch_attributes() {
 hipError_t launch_batch_init(const BatchArgs& a, hipStream_t s) {
     const hipError_t e = batch_attributes();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch::kb_init, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a);
+    hipLaunchKernelGGL(batch::kb_init, dim3(a.nseries), dim3(batch::kFftThreads), sizeof(batch::Lds), s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_conv(const BatchArgs& a, int side, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_conv, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a, side);
+    hipLaunchKernelGGL(batch::kb_conv, dim3(a.nseries), dim3(batch::kFftThreads), sizeof(batch::Lds), s, a, side);
     return hipGetLastError();
 }
 
@@ -990,7 +990,7 @@ hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_batch_hankel(const BatchArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_hankel, dim3(a.nseries), dim3(batch::kThreads), sizeof(batch::Lds), s, a);
+    hipLaunchKernelGGL(batch::kb_hankel, dim3(a.nseries), dim3(batch::kFftThreads), sizeof(batch::Lds), s, a);
     return hipGetLastError();
 }
 

@@ -653,4 +653,4 @@ void ssa_server_destroy(ssa_server v) {
 }  // extern "C"
 
 static_assert(sizeof(BSeries) % 8 == 0, "series table entries must keep 8-byte alignment");
-static_assert(2 * batch::kMaxMp <= batch::kEpt * batch::kThreads * 2, "in-LDS FFT needs M' <= EPT * threads");
+static_assert(batch::kMaxMp <= batch::kEpt * batch::kFftThreads, "in-LDS FFT needs M' <= EPT * threads");

@@ -15,12 +15,14 @@
 namespace ssa {
 namespace batch {
 
-constexpr int kThreads = 512;     // FFT-product, check, Ritz and Hankelization kernels
+constexpr int kFftThreads = 1024;  // set-up, FFT-product and Hankelization kernels (FFT in LDS)
+constexpr int kFftWaves = kFftThreads / 64;
+constexpr int kThreads = 512;     // stopping-test and Ritz kernels
 constexpr int kWaves = kThreads / 64;
-constexpr int kCgsThreads = 256;  // Gram-Schmidt kernel (small LDS, several workgroups per CU)
+constexpr int kCgsThreads = 512;  // Gram-Schmidt kernel (small LDS)
 constexpr int kCgsWaves = kCgsThreads / 64;
 constexpr int kCgsCols = 16;      // basis columns per projection pass
-constexpr int kEpt = 32;
+constexpr int kEpt = 16;          // points per thread of one LDS FFT stage
 constexpr int kMaxMp = 10240;  // largest half-length FFT held in LDS (N <= 20480)
 constexpr int kTwTab = 128;    // two-level twiddle tables, each <= sqrt(kMaxMp) rounded up
 constexpr int kDmax = 320;     // Krylov dimension cap of the batched path
