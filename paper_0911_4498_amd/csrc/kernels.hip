@@ -130,6 +130,16 @@ __device__ __forceinline__ float p1_value(const P1In& a, long long m, int y) {
 // memory latency (256 threads with 32 points each reach a third less).
 constexpr int kBigThreads = 1024;
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), and each
+// XCD has its own L2.  Column blocks of passes 1 and 3 read and write runs of CB
+// complex values, so neighbouring blocks share 128-byte lines: give each XCD a
+// contiguous run of blocks so that those neighbours meet in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    if (nb % kXcds != 0) return b;
+    return (b % kXcds) * (nb / kXcds) + b / kXcds;
+}
+
 template <int MODE, int EPT, int NT = 256>
 __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __restrict__ T1) {
     extern __shared__ float2 smem[];
@@ -137,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
     float2* buf = smem;
     float2* tw = smem + CB * ss;
-    const int c0 = blockIdx.x * CB;
+    const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
     const int y = blockIdx.y;
     for (int t = tid; t < M1; t += nthr) tw[t] = g.tw1[t];
     for (int idx = tid; idx < CB * M1; idx += nthr) {
@@ -502,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restri
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
     float2* buf = smem;
     float2* tw = smem + CB * ss;
-    const int c0 = blockIdx.x * CB;
+    const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
     const int y = blockIdx.y;
     const float2* in = T2 + (long long)y * g.Mp;
     for (int t = tid; t < M1; t += nthr) tw[t] = g.tw1[t];
