@@ -578,8 +578,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X; "
-              "how it would shard across GPUs is described in DESIGN.md. Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X, and no "
+              "multi-GPU path is built. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     from paper_0911_4498_amd import ssa
