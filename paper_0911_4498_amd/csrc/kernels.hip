@@ -161,8 +161,9 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
         buf[c * ss + n1] = z;
     }
     // output twiddles W_{M'}^{n2 k1} of this thread's first kPre stores, fetched before the FFT
-    constexpr int kPre = 4;
-    float2 wpre[kPre];
+    // (not in the 1024-thread instantiations: capped at 128 VGPRs, they would spill)
+    constexpr int kPre = NT >= 1024 ? 0 : 4;
+    float2 wpre[kPre > 0 ? kPre : 1];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
         const int idx = tid + i * nthr;
@@ -242,9 +243,10 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
     const RowPair rp(blockIdx.x, g.M1, M2);
     for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
     load_rows<EPT>(buf, T1, rp, M2, tid, nthr);
-    // operator values of this thread's first kPre pairs, fetched before the FFT
-    constexpr int kPre = 2;
-    float4 pre0[kPre], pre1[kPre];
+    // operator values of this thread's first kPre pairs, fetched before the FFT (not in the
+    // 1024-thread instantiation: capped at 128 VGPRs, it would spill)
+    constexpr int kPre = NT >= 1024 ? 0 : 2;
+    float4 pre0[kPre > 0 ? kPre : 1], pre1[kPre > 0 ? kPre : 1];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
         const int p = tid + i * nthr;
