@@ -190,6 +190,20 @@ def test_very_long_series_full_k_thick_restart(ssa):
     certify(ssa, f, L, k, sampled_rows=32, recon_positions=64, d_max=125, restart_keep=75)
 
 
+def test_ragged_long_series_tails(ssa):
+    """An odd length just below 2^22 (N = 4194001, L = N/2) with the schedule M' = 2^21 =
+    2048 x 1024, CB = 4.  Both bases are longer than 2^20 rows with ragged ends: the
+    projection sums several row chunks per workgroup with a partial last one, the
+    long-vector Ritz rotation has a partial last workgroup, and the column passes run their
+    1024-thread instantiations over 256 blocks in the XCD-aware order.  Certificates on
+    sampled rows."""
+    N = 4_194_001
+    L, k = N // 2, 6
+    say(f"ragged long series: N={N} L={L} k={k} d_max=40 M'=2^21 (2048 x 1024) CB=4")
+    f = inputs.c5_series(N)
+    certify(ssa, f, L, k, sampled_rows=128, recon_positions=128, d_max=40, fft_mp=2 ** 21, fft_m1=2048, fft_cb=4)
+
+
 def test_one_sided_second_passes_run_on_the_whole_grid(ssa):
     """Request 6 of the served stream (N = 241251, L = N/2, k = 13) with one-sided
     reorthogonalization: the U-side Gram-Schmidt often removes most of the vector, so DGKS
