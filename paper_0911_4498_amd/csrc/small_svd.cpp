@@ -143,8 +143,120 @@ void sorted_desc(int n, const double* D, std::vector<int>& order) {
 
 size_t bidiag_work_doubles(int d) { return (size_t)8 * (d + 2); }
 
+namespace {
+
+// Number of eigenvalues below x[i] of the tridiagonal with diagonal D and squared
+// off-diagonal E2, for the m shifts at once: the m pivot recurrences are advanced
+// together, so their divisions overlap instead of forming one long chain.
+void sturm_counts(const double* D, const double* E2, int n, const double* x, int m, double pivmin, double* dd,
+                  int* cnt) {
+    for (int i = 0; i < m; ++i) {
+        double v = D[0] - x[i];
+        if (std::fabs(v) < pivmin) v = -pivmin;
+        dd[i] = v;
+        cnt[i] = v < 0.0 ? 1 : 0;
+    }
+    for (int t = 1; t < n; ++t) {
+        const double dt = D[t], et = E2[t - 1];
+        for (int i = 0; i < m; ++i) {
+            double v = dt - x[i] - et / dd[i];
+            if (std::fabs(v) < pivmin) v = -pivmin;
+            dd[i] = v;
+            cnt[i] += v < 0.0 ? 1 : 0;
+        }
+    }
+}
+
+// Squared last component of the unit eigenvector of the tridiagonal at its
+// eigenvalue lam, from the twisted factorization of T - lam I (Dhillon and
+// Parlett): pivots from the bottom (dm) and from the top (dp), the twist index r
+// where |dp_r + dm_r - (D_r - lam)| is least, z_r = 1, and z spread both ways by
+// products of pivot ratios.  The tiny last components of converged Ritz vectors
+// keep their relative accuracy this way.
+double twisted_last2(const double* D, const double* E2, int n, double lam, double pivmin, double* dm, double* dp) {
+    if (n == 1) return 1.0;
+    auto guard = [pivmin](double x) { return std::fabs(x) < pivmin ? -pivmin : x; };
+    dm[n - 1] = D[n - 1] - lam;
+    for (int c = n - 2; c >= 0; --c) dm[c] = D[c] - lam - E2[c] / guard(dm[c + 1]);
+    double best = 0.0;
+    int r = 0;
+    for (int c = 0; c < n; ++c) {
+        dp[c] = c == 0 ? D[0] - lam : D[c] - lam - E2[c - 1] / guard(dp[c - 1]);
+        const double g = std::fabs(dp[c] + dm[c] - (D[c] - lam));
+        if (c == 0 || g < best) {
+            best = g;
+            r = c;
+        }
+    }
+    double z = 1.0, zz = 1.0;
+    for (int c = r - 1; c >= 0; --c) {
+        z = -(std::sqrt(E2[c]) / guard(dp[c])) * z;
+        zz += z * z;
+    }
+    z = 1.0;
+    for (int c = r + 1; c < n; ++c) {
+        z = -(std::sqrt(E2[c - 1]) / guard(dm[c])) * z;
+        zz += z * z;
+    }
+    const double zl = r == n - 1 ? 1.0 : z;
+    return zl * zl / zz;
+}
+
+}  // namespace
+
 void bidiag_ritz_values(const double* alpha, const double* beta, int d, int k, double* omega,
                         double* resid, double* work) {
+    if (d >= kBisectMinSteps) {
+        // The k largest eigenvalues by bisection on Sturm counts (all k together), their
+        // last eigenvector components by twisted factorizations: O(k d) per halving
+        // instead of the O(d^2) serial rotations of the full QL iteration.
+        double* D = work;
+        double* E2 = work + (d + 2);
+        double* dm = work + 2 * (d + 2);
+        double* dp = work + 3 * (d + 2);
+        form_tridiagonal(alpha, beta, d, D, E2);
+        double gmin = 0.0, gmax = 0.0, e2max = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double el = c > 0 ? std::fabs(E2[c - 1]) : 0.0, er = c + 1 < d ? std::fabs(E2[c]) : 0.0;
+            gmin = c == 0 ? D[c] - el - er : std::min(gmin, D[c] - el - er);
+            gmax = c == 0 ? D[c] + el + er : std::max(gmax, D[c] + el + er);
+        }
+        for (int c = 0; c + 1 < d; ++c) {
+            E2[c] = E2[c] * E2[c];
+            e2max = std::max(e2max, E2[c]);
+        }
+        const double pivmin = 2.2250738585072014e-308 * std::max(1.0, e2max);
+        const int kk = std::min(k, d);
+        std::vector<double> lo(kk, gmin), hi(kk, gmax), x(kk), dd(kk);
+        std::vector<int> cnt(kk);
+        const double tolabs = 2.0 * kEps * std::max(std::fabs(gmin), std::fabs(gmax)) + pivmin;
+        int rounds = 1;
+        for (double w = gmax - gmin; w > tolabs && rounds < 200; w *= 0.5) ++rounds;
+        for (int it = 0; it < rounds; ++it) {
+            for (int i = 0; i < kk; ++i) x[i] = 0.5 * (lo[i] + hi[i]);
+            sturm_counts(D, E2, d, x.data(), kk, pivmin, dd.data(), cnt.data());
+            for (int i = 0; i < kk; ++i) {
+                // the i-th largest eigenvalue is the (d-1-i)-th smallest
+                if (cnt[i] <= d - 1 - i)
+                    lo[i] = x[i];
+                else
+                    hi[i] = x[i];
+            }
+        }
+        for (int i = 0; i < k; ++i) {
+            if (i >= d) {
+                omega[i] = 0.0;
+                resid[i] = 0.0;
+                continue;
+            }
+            const double lam = 0.5 * (lo[i] + hi[i]);
+            const double w = std::sqrt(std::max(lam, 0.0));
+            omega[i] = w;
+            const double zl = std::sqrt(twisted_last2(D, E2, d, lam, pivmin, dm, dp));
+            resid[i] = w > 0.0 ? alpha[d + 1] * beta[d + 1] * zl / w : 0.0;
+        }
+        return;
+    }
     double* D = work;
     double* E = work + (d + 2);
     double* zl = work + 2 * (d + 2);

@@ -91,6 +91,7 @@ constexpr int kProjCols = 8;     // basis columns per workgroup in the projectio
 constexpr int kProjColsNarrow = 4;    // ... for vectors of at most kProjNarrowChunks row chunks
 constexpr int kProjNarrowChunks = 64;
 constexpr long long kRitzWideRows = 1LL << 20;  // Ritz rotations of longer vectors use the scalar-load kernel
+constexpr int kBisectMinSteps = 48;  // stopping tests on B_d with d >= this use bisection, not QL
 constexpr int kProjLongChunks = 8;  // row chunks per projection workgroup for vectors longer than ...
 constexpr long long kProjLongRows = 1LL << 20;  // ... this many rows (fewer reductions and partial sums)
 
