@@ -202,6 +202,41 @@ double twisted_last2(const double* D, const double* E2, int n, double lam, doubl
     return zl * zl / zz;
 }
 
+// The kk largest eigenvalues (descending, into lam) of the tridiagonal with diagonal D
+// and off-diagonal E (E[c] couples c and c+1) by bisection on Sturm counts, all kk
+// advanced together.  E is replaced by its squares; returns the pivot floor.
+double top_eigs_bisect(const double* D, double* E, int n, int kk, double* lam) {
+    double gmin = 0.0, gmax = 0.0, e2max = 0.0;
+    for (int c = 0; c < n; ++c) {
+        const double el = c > 0 ? std::fabs(E[c - 1]) : 0.0, er = c + 1 < n ? std::fabs(E[c]) : 0.0;
+        gmin = c == 0 ? D[c] - el - er : std::min(gmin, D[c] - el - er);
+        gmax = c == 0 ? D[c] + el + er : std::max(gmax, D[c] + el + er);
+    }
+    for (int c = 0; c + 1 < n; ++c) {
+        E[c] = E[c] * E[c];
+        e2max = std::max(e2max, E[c]);
+    }
+    const double pivmin = 2.2250738585072014e-308 * std::max(1.0, e2max);
+    std::vector<double> lo(kk, gmin), hi(kk, gmax), x(kk), dd(kk);
+    std::vector<int> cnt(kk);
+    const double tolabs = 2.0 * kEps * std::max(std::fabs(gmin), std::fabs(gmax)) + pivmin;
+    int rounds = 1;
+    for (double w = gmax - gmin; w > tolabs && rounds < 200; w *= 0.5) ++rounds;
+    for (int it = 0; it < rounds; ++it) {
+        for (int i = 0; i < kk; ++i) x[i] = 0.5 * (lo[i] + hi[i]);
+        sturm_counts(D, E, n, x.data(), kk, pivmin, dd.data(), cnt.data());
+        for (int i = 0; i < kk; ++i) {
+            // the i-th largest eigenvalue is the (n-1-i)-th smallest
+            if (cnt[i] <= n - 1 - i)
+                lo[i] = x[i];
+            else
+                hi[i] = x[i];
+        }
+    }
+    for (int i = 0; i < kk; ++i) lam[i] = 0.5 * (lo[i] + hi[i]);
+    return pivmin;
+}
+
 }  // namespace
 
 void bidiag_ritz_values(const double* alpha, const double* beta, int d, int k, double* omega,
@@ -215,41 +250,16 @@ void bidiag_ritz_values(const double* alpha, const double* beta, int d, int k, d
         double* dm = work + 2 * (d + 2);
         double* dp = work + 3 * (d + 2);
         form_tridiagonal(alpha, beta, d, D, E2);
-        double gmin = 0.0, gmax = 0.0, e2max = 0.0;
-        for (int c = 0; c < d; ++c) {
-            const double el = c > 0 ? std::fabs(E2[c - 1]) : 0.0, er = c + 1 < d ? std::fabs(E2[c]) : 0.0;
-            gmin = c == 0 ? D[c] - el - er : std::min(gmin, D[c] - el - er);
-            gmax = c == 0 ? D[c] + el + er : std::max(gmax, D[c] + el + er);
-        }
-        for (int c = 0; c + 1 < d; ++c) {
-            E2[c] = E2[c] * E2[c];
-            e2max = std::max(e2max, E2[c]);
-        }
-        const double pivmin = 2.2250738585072014e-308 * std::max(1.0, e2max);
         const int kk = std::min(k, d);
-        std::vector<double> lo(kk, gmin), hi(kk, gmax), x(kk), dd(kk);
-        std::vector<int> cnt(kk);
-        const double tolabs = 2.0 * kEps * std::max(std::fabs(gmin), std::fabs(gmax)) + pivmin;
-        int rounds = 1;
-        for (double w = gmax - gmin; w > tolabs && rounds < 200; w *= 0.5) ++rounds;
-        for (int it = 0; it < rounds; ++it) {
-            for (int i = 0; i < kk; ++i) x[i] = 0.5 * (lo[i] + hi[i]);
-            sturm_counts(D, E2, d, x.data(), kk, pivmin, dd.data(), cnt.data());
-            for (int i = 0; i < kk; ++i) {
-                // the i-th largest eigenvalue is the (d-1-i)-th smallest
-                if (cnt[i] <= d - 1 - i)
-                    lo[i] = x[i];
-                else
-                    hi[i] = x[i];
-            }
-        }
+        std::vector<double> lams(kk);
+        const double pivmin = top_eigs_bisect(D, E2, d, kk, lams.data());
         for (int i = 0; i < k; ++i) {
             if (i >= d) {
                 omega[i] = 0.0;
                 resid[i] = 0.0;
                 continue;
             }
-            const double lam = 0.5 * (lo[i] + hi[i]);
+            const double lam = lams[i];
             const double w = std::sqrt(std::max(lam, 0.0));
             omega[i] = w;
             const double zl = std::sqrt(twisted_last2(D, E2, d, lam, pivmin, dm, dp));
@@ -292,9 +302,19 @@ void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, 
     form_tridiagonal(alpha, beta, d, D0, E0);
     std::memcpy(D, D0, sizeof(double) * d);
     std::memcpy(E, E0, sizeof(double) * d);
-    tridiag_ql(d, D, E, nullptr);
     std::vector<int> order;
-    sorted_desc(d, D, order);
+    if (d >= kBisectMinSteps) {
+        // only the k largest eigenvalues are needed: bisection, stored in D[0..k) descending
+        const int kq = std::min(k, d);
+        std::vector<double> lams(kq);
+        top_eigs_bisect(D0, E, d, kq, lams.data());
+        for (int i = 0; i < kq; ++i) D[i] = lams[i];
+        order.resize(kq);
+        for (int i = 0; i < kq; ++i) order[i] = i;
+    } else {
+        tridiag_ql(d, D, E, nullptr);
+        sorted_desc(d, D, order);
+    }
     double tnorm = 0.0;
     for (int i = 0; i < d; ++i) tnorm = std::max(tnorm, std::fabs(D0[i]) + 2.0 * std::fabs(i + 1 < d ? E0[i] : 0.0));
     std::vector<double> q((size_t)k * d, 0.0), x(d);
