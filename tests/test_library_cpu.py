@@ -288,6 +288,59 @@ def test_bidiag_ritz_matches_lapack(d, k, seed):
     np.testing.assert_allclose(P[:, :kk].T @ P[:, :kk], np.eye(kk), atol=1e-11)
 
 
+def lanczos_bidiag(f, L, d, seed=1):
+    """alpha, beta of d steps of Golub-Kahan-Lanczos in FP64 with full reorthogonalization
+    on the explicit trajectory matrix (a test fixture, not the oracle)."""
+    import scipy.linalg
+    X = scipy.linalg.hankel(f[:L], f[L - 1:])
+    Lh, K = X.shape
+    U = np.zeros((Lh, d + 2))
+    V = np.zeros((K, d + 1))
+    al = np.zeros(d + 3)
+    be = np.zeros(d + 3)
+    p = np.random.default_rng(seed).normal(size=Lh)
+    be[1] = np.linalg.norm(p)
+    U[:, 0] = p / be[1]
+    for j in range(1, d + 2):
+        r = X.T @ U[:, j - 1] - (be[j] * V[:, j - 2] if j >= 2 else 0.0)
+        for _ in range(2):
+            r -= V[:, :j - 1] @ (V[:, :j - 1].T @ r)
+        al[j] = np.linalg.norm(r)
+        if j == d + 1:
+            break
+        V[:, j - 1] = r / al[j]
+        q = X @ V[:, j - 1] - al[j] * U[:, j - 1]
+        for _ in range(2):
+            q -= U[:, :j] @ (U[:, :j].T @ q)
+        be[j + 1] = np.linalg.norm(q)
+        U[:, j] = q / be[j + 1]
+    return al, be
+
+
+@pytest.mark.parametrize("kind,d", [("c1", 80), ("c1", 120), ("white", 100), ("sine", 60)])
+def test_stopping_test_on_lanczos_bidiagonals(kind, d):
+    """The stopping test for d >= 48 (bisection and twisted factorizations) on bidiagonals
+    from real Lanczos runs, where converged triples have eigenvector tails near 1e-20:
+    Ritz values and residual bounds alpha_{d+1} |p_i[d]| against LAPACK."""
+    from paper_0911_4498_amd import inputs
+    if kind == "c1":
+        f, L = inputs.c1_series(1000), 500
+    elif kind == "white":
+        f, L = inputs.white(800, 3), 400
+    else:
+        f, L = inputs.sinusoid(600, 23.0, 2.0) + 0.001 * inputs.white(600, 5), 300
+    al, be = lanczos_bidiag(f, L, d)
+    k = 16
+    B = bidiag(al, be, d)
+    P, s_ref, _ = np.linalg.svd(B, full_matrices=False)
+    om, res = ssa.bidiag_ritz(al, be, d, k)
+    np.testing.assert_allclose(om, s_ref[:k], rtol=1e-8)
+    ref = al[d + 1] * np.abs(P[d, :k])
+    big = ref > 1e-10 * s_ref[0]
+    np.testing.assert_allclose(res[big], ref[big], rtol=1e-4)
+    assert np.all(np.abs(res[~big] - ref[~big]) <= 1e-10 * s_ref[0])
+
+
 def test_bidiag_ritz_clustered_and_zero_entries():
     """Exactly repeated singular values and vanishing alpha/beta (a split B) still give
     orthonormal vectors that span the right subspaces."""
