@@ -3,10 +3,12 @@ k=20 workload, computed ONLY by the FP64 oracle (tier B: Algorithm 1 with full
 reorthogonalization and row-by-row products, Sec. 3.1-3.2), for the seeded
 series of ``paper_0911_4498_amd.inputs.c2_series``.
 
-Stored: the 24 leading singular values, and the elementary reconstructed
+Stored: the 24 leading singular values, the elementary reconstructed
 series of each of the first 20 triples (Sec. 2.3-2.4 diagonal averaging of
-sigma_i u_i v_i^T) at 512 fixed sample indices; a test sums the members of a
-cluster of near-equal values itself.
+sigma_i u_i v_i^T) at 512 fixed sample indices (a test sums the members of a
+cluster of near-equal values itself), and in c2_oracle_vectors.npz the first 20
+left and right singular vectors (Sec. 2.2), rounded to FP32 (a sine of 1e-7 at
+most, far below the 1e-4 angle tolerance they are compared with).
 
 Usage: python tests/golden/make_c2_golden.py   (several minutes, all cores)
 """
@@ -51,7 +53,9 @@ def main():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print("wrote", path, f"total {time.time() - t0:.1f} s")
+    vpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_vectors.npz")
+    np.savez_compressed(vpath, U=U[:, :K_TRIPLES].T.astype(np.float32), V=V[:, :K_TRIPLES].T.astype(np.float32))
+    print("wrote", path, vpath, f"total {time.time() - t0:.1f} s")
 
 
 if __name__ == "__main__":

@@ -6,17 +6,32 @@ Tolerances (FP32 products, FP64 Lanczos scalars):
     product X v, which bounds what any FP32 matvec can resolve);
   * vectors: largest principal-angle sine <= 1e-4 per cluster, because
     individual vectors inside a cluster are not unique.  Two neighbouring
-    values belong to one cluster when their gap is below
-        max(1e-3 sigma_i, DELTA / 1e-4),   DELTA = 16 u |X|_F,  u = 2^-24,
-    i.e. when Wedin's bound sin(theta) <= |E| / gap cannot certify 1e-4 for a
-    perturbation E of the size the FP32 path itself introduces (rounding the
-    series to FP32 alone is a Hankel perturbation with |E| <= u |X|_F; the FFT
-    products and FP32 vector storage add errors of the same order);
+    oracle values belong to one cluster when their relative gap
+    (sigma_i - sigma_{i+1}) / sigma_i is below 1e-3.  The perturbations the FP32
+    path introduces (rounding the series, FFT products, FP32 vector storage)
+    act like a perturbation E of norm ~1e-7 |X|_2 with no preferred direction,
+    so the rotation of an isolated singular subspace, to first order
+    |U_perp^T E V_c| / gap, stays far below 1e-4 at these gaps; the tests measure
+    it rather than assume a worst case;
   * reconstructions: max-abs error <= 1e-5 |F|_inf per isolated triple, and per
     cluster (sum over the cluster) otherwise.
 A cluster that straddles k (its last member beyond k) is compared by its
-singular values only.
+singular values only, and so are exactly zero triples (sigma <= 1e-6 sigma_1:
+their vectors span an arbitrary part of the null space).
+
+FP32 resolution (resolved_clusters).  The method computes its products with
+FP32 FFTs, and for noise-floor triples whose relative gaps are ~1e-3 those
+products alone rotate a subspace by ~1e-4 (a CPU model with float32 library
+FFTs reproduces the GPU's figures, e.g. 1.40e-4 against 1.39e-4).  So the
+clusters are refined by measurement: fp32_model runs Algorithm 1 on the CPU
+with float32 FFT products, FP32 vector storage and FP64 Gram-Schmidt, and every
+relative-gap cluster that this model itself does not reproduce to half the
+angle tolerance is merged with its neighbour across the smaller gap (and the
+test repeats).  The merged cluster is still compared at 1e-4 (or by sigma only
+if it then reaches past k).  Clusters the FP32 method resolves keep the 1e-4
+check; none is exempted by a worst-case bound.
 """
+import scipy.fft
 import numpy as np
 
 SIGMA_REL = 1e-5
@@ -24,8 +39,6 @@ SIGMA_FLOOR = 1e-7
 ANGLE_SIN = 1e-4
 RECON_REL = 1e-5
 CLUSTER_GAP = 1e-3
-U32 = 2.0 ** -24
-BACKWARD = 16.0 * U32
 
 
 def frobenius(f, L):
@@ -40,18 +53,107 @@ def frobenius(f, L):
 
 def clusters(s_ref, k, fro=None):
     """Index groups of near-equal oracle singular values among the first k
-    (s_ref may hold more than k values so straddling clusters are visible).
-    fro = |X|_F enables the FP32-conditioning part of the rule."""
-    wedin_gap = 0.0 if fro is None else BACKWARD * fro / ANGLE_SIN
+    (s_ref may hold more than k values so straddling clusters are visible):
+    neighbours join while their relative gap is below CLUSTER_GAP.  fro is
+    accepted for the callers' convenience and not used."""
     out, i = [], 0
     while i < k:
         j = i + 1
         while (j < len(s_ref) and s_ref[j - 1] > 0
-               and (s_ref[j - 1] - s_ref[j]) < max(CLUSTER_GAP * s_ref[j - 1], wedin_gap)):
+               and (s_ref[j - 1] - s_ref[j]) < CLUSTER_GAP * s_ref[j - 1]):
             j += 1
         out.append(list(range(i, min(j, len(s_ref)))))
         i = j
     return out
+
+
+def fp32_model(f, L, k, d=None, seed=1, dtype=np.float32):
+    """The k leading triples of Algorithm 1 run with float32 FFT products (library FFT),
+    FP32 storage of the Lanczos vectors and FP64 Gram-Schmidt (two passes, full
+    reorthogonalization), the Ritz triples taken from an FP64 SVD of B_d.  A model of the
+    arithmetic of the FP32 method, used only to measure what that arithmetic resolves."""
+    f = np.asarray(f, dtype=np.float64)
+    N = f.size
+    K = N - L + 1
+    Li, Ki = min(L, K), max(L, K)
+    r = min(Li, Ki)
+    d = min(r, d if d else 8 * k + 32)
+    M = 2 * ((N + 1) // 2)
+    F = scipy.fft.rfft(np.pad(f.astype(dtype), (0, M - N)))
+
+    def conv(x, off, n_out):  # y[off + i] of the circular convolution with the reversed x
+        w = np.zeros(M, dtype)
+        w[:len(x)] = x[::-1]
+        return scipy.fft.irfft(F * scipy.fft.rfft(w), M)[off:off + n_out].astype(np.float64)
+
+    def st(v):
+        return v.astype(dtype).astype(np.float64)
+
+    rng = np.random.default_rng(seed)
+    U = np.zeros((Li, d + 1))
+    V = np.zeros((Ki, d))
+    al = np.zeros(d + 2)
+    be = np.zeros(d + 2)
+    p = rng.standard_normal(Li)
+    be[1] = np.linalg.norm(p)
+    U[:, 0] = st(p / be[1])
+    for j in range(1, d + 1):
+        x = st(conv(U[:, j - 1], Li - 1, Ki) - (be[j] * V[:, j - 2] if j >= 2 else 0.0))
+        for _ in range(2):
+            x = x - V[:, :j - 1] @ (V[:, :j - 1].T @ x)
+        al[j] = np.linalg.norm(x)
+        V[:, j - 1] = st(x / al[j])
+        y = st(conv(V[:, j - 1], Ki - 1, Li) - al[j] * U[:, j - 1])
+        for _ in range(2):
+            y = y - U[:, :j] @ (U[:, :j].T @ y)
+        be[j + 1] = np.linalg.norm(y)
+        U[:, j] = st(y / be[j + 1])
+    B = np.zeros((d + 1, d))
+    for c in range(d):
+        B[c, c] = al[c + 1]
+        B[c + 1, c] = be[c + 2]
+    P, om, Qt = np.linalg.svd(B, full_matrices=False)
+    Um, Vm = U @ P[:, :k], V @ Qt[:k].T
+    if L > K:
+        Um, Vm = Vm, Um
+    return om[:k], Um, Vm
+
+
+def resolved_clusters(s_ref, U_ref, V_ref, k, model):
+    """Relative-gap clusters of the first k oracle triples, each merged with its nearer
+    neighbour while the FP32 model (sigma, U, V with >= k columns) does not reproduce its
+    subspace to ANGLE_SIN / 2.  U_ref, V_ref: (n, >= k) oracle vectors as columns."""
+    _, Um, Vm = model
+    km = Um.shape[1]
+    cl = clusters(s_ref, k)
+    changed = True
+    while changed:
+        changed = False
+        for idx, c in enumerate(cl):
+            if max(c) >= min(k, km) or s_ref[c[0]] <= 1e-6 * s_ref[0]:
+                continue
+            sm = max(subspace_sin(U_ref[:, c], Um[:, c]), subspace_sin(V_ref[:, c], Vm[:, c]))
+            if sm <= ANGLE_SIN / 2:
+                continue
+            lo_gap = s_ref[c[0] - 1] - s_ref[c[0]] if c[0] > 0 else np.inf
+            hi_gap = s_ref[c[-1]] - s_ref[c[-1] + 1] if c[-1] + 1 < len(s_ref) else np.inf
+            if lo_gap < hi_gap:
+                cl[idx - 1] = cl[idx - 1] + c
+                del cl[idx]
+            elif idx + 1 < len(cl):
+                cl[idx] = c + cl[idx + 1]
+                del cl[idx + 1]
+            else:  # the next cluster lies beyond k
+                cl[idx] = c + [c[-1] + 1]
+            changed = True
+            break
+    return cl
+
+
+def reference_clusters(f, L, k, s_ref, U_ref, V_ref):
+    """The clusters a test compares for the series f: relative-gap clusters refined by
+    the FP32 model (resolved_clusters); the model gets as many triples as U_ref has."""
+    return resolved_clusters(s_ref, U_ref, V_ref, k, fp32_model(f, L, U_ref.shape[1]))
 
 
 def sigma_errors(s_gpu, s_ref):
@@ -76,11 +178,12 @@ def subspace_sin(A, B):
     return float(np.linalg.norm(qb - qa @ (qa.T @ qb), 2))
 
 
-def compare_svd(s_gpu, U_gpu, V_gpu, s_ref, U_ref, V_ref, k, fro=None, min_rel=1e-6):
-    """U/V as (n, k) arrays (columns = vectors).  Returns a report dict; asserts."""
+def compare_svd(s_gpu, U_gpu, V_gpu, s_ref, U_ref, V_ref, k, fro=None, min_rel=1e-6, cl=None):
+    """U/V as (n, k) arrays (columns = vectors).  cl: the clusters to compare (default:
+    the relative-gap clusters).  Returns a report dict; asserts."""
     worst_sin = 0.0
     rel = assert_sigma(s_gpu[:k], s_ref[:k])
-    for c in clusters(s_ref, k, fro):
+    for c in (cl if cl is not None else clusters(s_ref, k, fro)):
         if max(c) >= k:
             continue  # straddles k: sigma only
         if s_ref[c[0]] <= min_rel * s_ref[0]:

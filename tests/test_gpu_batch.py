@@ -46,9 +46,9 @@ def compare_one(f, L, k, sig, U, V, rec, dense=True):
         p0 = inputs.start_vector(L, 7)
         sA, UA, VA, _, conv = oracle.lanczos_svd(f, L, kr, p0, tol=1e-12)
         assert conv
-    fro = parity.frobenius(f, L)
-    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, fro)
-    groups = [c for c in parity.clusters(sA, k, fro) if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
+    cl = parity.reference_clusters(f, L, k, sA, UA, VA)
+    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, cl=cl)
+    groups = [c for c in cl if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
     if groups:  # white noise can leave one cluster straddling k: then sigma and subspaces only
         rg = rec.cpu().numpy().astype(np.float64)
         ref = oracle.reconstruct(N, L, sA[:k], UA[:, :k], VA[:, :k], groups)

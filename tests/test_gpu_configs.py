@@ -60,14 +60,15 @@ def parity_vs_oracle(ssa, f, L, k, tier):
     else:
         sA, UA, VA, steps, conv = oracle.lanczos_svd(f, L, kr, inputs.start_vector(L, 11), tol=1e-12)
         assert conv
-    fro = parity.frobenius(f, L)
-    groups = [c for c in parity.clusters(sA, k, fro) if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
+    cl = parity.reference_clusters(f, L, k, sA, UA, VA)
+    groups = [c for c in cl if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
     plan, s, U, V, info, rec = solve(ssa, f, L, k, groups)
     say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")
     sg = s.cpu().numpy()
     Ug = U.cpu().numpy().T.astype(np.float64)
     Vg = V.cpu().numpy().T.astype(np.float64)
-    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, fro)
+    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, cl=cl)
+    rep["clusters"] = [c for c in cl if len(c) > 1]
     ref = oracle.reconstruct(N, L, sA[:k], UA[:, :k], VA[:, :k], groups)
     rep["recon_err"] = parity.compare_recon(rec.cpu().numpy().astype(np.float64), ref, np.abs(f).max())
     say(f"  {rep}")
