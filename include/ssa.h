@@ -16,10 +16,15 @@
  *  - Indices are 0-based.  Device pointers ("_dev") are HIP device memory on
  *    the current device, owned by the caller; the library never allocates
  *    device memory.  Host pointers are ordinary host memory.
- *  - Work is enqueued on the stream given to ssa_plan_bind, in call order.
- *    ssa_truncated_svd returns after its result is complete (it needs the
- *    Lanczos scalars on the host to decide when to stop); the other calls
- *    return as soon as their work is enqueued.
+ *  - Work is enqueued on the stream given to ssa_plan_bind, in call order, and
+ *    the calls return as soon as their work is enqueued; outputs are valid once
+ *    the stream has run it.  ssa_truncated_svd is the exception in one respect:
+ *    the stopping test runs on the device, but the host must learn its answer
+ *    to stop enqueuing Lanczos steps, so the call waits for the test of each
+ *    check point (one check point behind the steps it has enqueued) and reads
+ *    back that test's small record -- never the Lanczos scalars.  With thick
+ *    restart (ssa_opts.restart_keep) the projected matrix is solved on the
+ *    host and the call returns after its result is complete.
  *  - A plan (and its workspace) may be used by one stream at a time.
  *    Distinct plans are independent.
  *  - Return values: 0 success; positive = warning, results written;
@@ -43,6 +48,11 @@ typedef struct ssa_plan_s* ssa_plan;
 enum ssa_status {
     SSA_OK = 0,
     SSA_WARN_NOT_CONVERGED = 1, /* Krylov dimension cap reached before the stopping rule  */
+    SSA_WARN_BREAKDOWN = 2,     /* converged, but an alpha or beta vanished on the way (the
+                                   series has rank below the steps taken, or the Krylov space
+                                   was exhausted): Algorithm 1 continued from a random vector
+                                   orthogonal to the basis, and triples past the rank have
+                                   sigma = 0 with arbitrary orthonormal vectors              */
     SSA_EINVAL = -1,            /* invalid argument (sizes, null pointers, group members) */
     SSA_ENOMEM = -2,            /* workspace missing or smaller than required             */
     SSA_ENONFINITE = -3,        /* the series holds NaN or Inf                            */
@@ -78,6 +88,11 @@ typedef struct {
                                correlation).  Must be >= ceil(N/2), 7-smooth and split
                                into two factors <= 4096; 0 = the smallest such M'.  The
                                schedule tuner (ssa_tune_fft) picks it by measurement.    */
+    int unfused;            /* 1: run each Lanczos half-step as six launches (pass 1, 2, 3,
+                               projection, reduction, update) with the bases in natural
+                               order; 0 = the fused four-launch half-step wherever it
+                               applies (1D, no thick restart, max(L, K) <= 2^20).  Same
+                               results up to rounding order; an A/B switch.              */
 } ssa_opts;
 
 /* Per-solve report, filled by ssa_truncated_svd. */
@@ -91,6 +106,7 @@ typedef struct {
                           point overlaps the next steps, which are then discarded)           */
     double resid[64];  /* residual bounds alpha_{d+1} |P[d+1,i]| of the first min(k,64) triples */
     int thick_restarts;/* restart cycles performed (ssa_opts.restart_keep)                   */
+    int status;        /* the call's return value (SSA_OK or a warning; errors fill nothing) */
 } ssa_info;
 
 /* Sizes chosen by a plan (reported for tests and benchmarks). */
@@ -166,10 +182,13 @@ int ssa_matvec(ssa_plan plan, int transpose, const float* x_dev, float* y_dev);
  *   sigma_dev: k doubles; U_dev: L x k floats column-major (u_i at
  *   U_dev + i*L); V_dev: K x k floats column-major (v_i at V_dev + i*K).
  *   info: optional host struct (may be NULL).
- * Returns SSA_OK, SSA_WARN_NOT_CONVERGED, or an error: SSA_EINVAL
- * (k outside [1, k_max]), SSA_EMISMATCH, SSA_ENOMEM (unbound plan),
- * SSA_ENONFINITE (series holds NaN/Inf; outputs untouched), SSA_EDEVICE.
- * Synchronizes the plan's stream before returning.
+ * Returns SSA_OK, SSA_WARN_NOT_CONVERGED, SSA_WARN_BREAKDOWN, or an error:
+ * SSA_EINVAL (k outside [1, k_max]), SSA_EMISMATCH, SSA_ENOMEM (unbound
+ * plan), SSA_ENONFINITE (series holds NaN/Inf, found on the device by the
+ * first stopping test; outputs untouched), SSA_EDEVICE.
+ * Without thick restart: info is complete on return, sigma_dev/U_dev/V_dev
+ * once the plan's stream has run the enqueued work (stream-ordered).  With
+ * thick restart the stream is synchronized before returning.
  */
 int ssa_truncated_svd(ssa_plan plan, const double* series_dev, long long N, long long L, int k,
                       double* sigma_dev, float* U_dev, float* V_dev, ssa_info* info);
@@ -447,12 +466,16 @@ int ssa_dense_ritz(const double* A, int nr, int nc, int k, double* omega, double
  *   (Algorithm 4); EMBED: the spectrum of the series (Algorithm 2, steps 1-2);
  *   DGKS2: the launches of a DGKS second Gram-Schmidt pass over the whole grid
  *   (long vectors), which return at once unless the criterion fired on the
- *   device; their algorithmic bytes are counted as 0.
+ *   device; their algorithmic bytes are counted as 0.  CHECK: the stopping test
+ *   on B_j and the Ritz coefficients on the device (eqs. lbdiagm1/lbdiagm2).
+ *   On the fused path (1D, no thick restart, max(L, K) <= 2^20)
+ *   PASS1 also finishes the previous Lanczos vector (the Gram-Schmidt update)
+ *   and PASS3 also forms the projection partial sums, so UPDATE and DOTS stay 0.
  */
 enum ssa_prof_class {
     SSA_PROF_PASS1 = 0, SSA_PROF_PASS2, SSA_PROF_PASS3, SSA_PROF_DOTS, SSA_PROF_REDUCE,
     SSA_PROF_UPDATE, SSA_PROF_RITZ, SSA_PROF_RECON1, SSA_PROF_RECON2, SSA_PROF_RECON3,
-    SSA_PROF_EMBED, SSA_PROF_DGKS2, SSA_PROF_NCLASSES
+    SSA_PROF_EMBED, SSA_PROF_DGKS2, SSA_PROF_CHECK, SSA_PROF_NCLASSES
 };
 
 /*

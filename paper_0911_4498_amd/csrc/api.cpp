@@ -27,6 +27,9 @@ constexpr int kMaxGroupBatch = 64;
 constexpr int kMaxRestartDmax = 512;  // basis cap of the restarted solver (host dense SVD per cycle)
 constexpr int kMaxCycles = 64;        // thick restarts before the solver gives up
 constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 16 x 1024 = 16384 rows
+// Longest basis vector of the fused path: one workgroup adds the pass-3 partial sums of
+// every column, and a DGKS pass in that workgroup must stay short.
+constexpr long long kFusedMaxRows = 1LL << 20;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -78,6 +81,41 @@ FftStages make_stages(int n) {
     return st;
 }
 
+// Columns per workgroup of passes 1 and 3: enough workgroups (~M2/CB >= 256) comes first;
+// at N = 1e5 (M1 x M2 = 200 x 250) CB = 1 beats CB = 4 by 10% per product although the
+// wider blocks fetch fewer partial lines (measured over every split of M' = 50000).
+int default_cb(int M1, int M2) {
+    return (int)std::min<long long>({16LL, 8192LL / M1, std::max(1LL, ((long long)M2 + 255) / 256)});
+}
+
+// Segment layout of vectors whose natural element i is y index o + i (i < n).
+SegLay make_seglay(const ConvGeom& g, long long o, long long n) {
+    SegLay l{};
+    l.o = o;
+    l.n = n;
+    l.M1 = g.M1;
+    l.M2 = g.M2;
+    int smax = 0;
+    for (int n2 = 0; n2 < g.M2; ++n2)
+        for (int e = 0; e < 2; ++e) smax = std::max(smax, seg_count(l, n2, e));
+    l.S = std::max(4, (smax + 3) / 4 * 4);
+    l.len = 2LL * g.M2 * l.S;
+    return l;
+}
+
+void fill_geom(long long Mp, int M1, int M2, int cb, ConvGeom& g) {
+    g.M1 = M1;
+    g.M2 = M2;
+    g.Mp = Mp;
+    g.M = 2 * Mp;
+    g.CB = std::max(1, cb);
+    int shift = 0;
+    while ((1LL << (2 * shift)) < Mp) ++shift;
+    g.tw_shift = shift;
+    g.st1 = make_stages(M1);
+    g.st2 = make_stages(M2);
+}
+
 }  // namespace
 
 struct ssa_plan_s {
@@ -91,6 +129,9 @@ struct ssa_plan_s {
     int keep;   // thick restart: Ritz pairs kept per cycle (0: no restart)
     int onesided;  // 1: only the length-Li basis (U) is reorthogonalized
     int kcols;  // columns of the P/Q coefficient buffers: max(k_max, keep)
+    int fused;  // 1: the four-launch half-step of fused.hip, bases in the segment layout
+    SegLay layU, layV;  // segment layouts of the U-side (length Li) and V-side (length Ki) vectors
+    int nblk;   // pass-3 workgroups of a product (partial sums per column on the fused path)
     double tol;
     unsigned long long seed;
     ConvGeom g;
@@ -98,7 +139,9 @@ struct ssa_plan_s {
     int pstride, nchunks_max;
     size_t ws_bytes;
     size_t o_ab, o_tw1, o_tw2, o_twlo, o_twhi, o_t1, o_t2, o_U, o_V, o_r, o_part, o_h, o_sc, o_alpha,
-        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2, o_rot;
+        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2, o_rot, o_rec, o_lzscr;
+    int nrec;          // doubles of the stopping-test record (kChkHdr + 3 kcols)
+    long long dstride; // d_max + 2: per-triple length of the device stopping-test scratch
     size_t grp_ints;
     // bound state
     char* ws = nullptr;
@@ -107,6 +150,7 @@ struct ssa_plan_s {
     // pinned host staging
     double* h_scal = nullptr;   // alpha (d_max+3) | beta (d_max+3) | P | Q | sigma
     double* h_flag = nullptr;
+    double* h_rec = nullptr;    // two stopping-test records (double-buffered)
     int* h_grp = nullptr;
     hipEvent_t grp_done = nullptr;
     hipEvent_t chk_ev[2] = {nullptr, nullptr};
@@ -164,6 +208,10 @@ void layout(ssa_plan p) {
     p->o_rt1 = take(sizeof(float2) * (size_t)g.Mp * 2 * p->k_max);
     p->o_rt2 = take(sizeof(float2) * (size_t)g.Mp * kMaxGroupBatch);
     p->o_rot = take(sizeof(float) * (size_t)p->keep * std::max(p->ldU, p->ldV));
+    p->nrec = kChkHdr + 3 * p->kcols;
+    p->dstride = p->d_max + 2;
+    p->o_rec = take(sizeof(double) * (size_t)p->nrec);
+    p->o_lzscr = take(sizeof(double) * (8 * (size_t)p->kcols * p->dstride + 2 * (size_t)p->kcols));
     p->ws_bytes = o;
 }
 
@@ -241,7 +289,7 @@ int convolve(ssa_plan p, const ConvGeom& g, const float* x, int side, float* out
         SSA_TRY(launch_pass1(g, IN_REV, in, 1, at<float2>(p, p->o_t1), s));
     }
     {
-        ProfScope ps(p, SSA_PROF_PASS2, 32.0 * mp);
+        ProfScope ps(p, SSA_PROF_PASS2, 24.0 * mp);
         SSA_TRY(launch_pass2_matvec(g, at<float4>(p, p->o_ab), at<float2>(p, p->o_t1), at<float2>(p, p->o_t2), s));
     }
     P3Out o{};
@@ -265,7 +313,7 @@ int convolve(ssa_plan p, const ConvGeom& g, const float* x, int side, float* out
 // columns, then the normalized vector becomes basis column `out_col` (ncols
 // if negative); the B entry goes to *coef_out.
 int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long n, double* coef_out, int track,
-                   unsigned long long ctr, int out_col = -1) {
+                   unsigned long long ctr, int out_col = -1, int ncols_bd = -1) {
     hipStream_t s = p->stream;
     float* r = at<float>(p, p->o_r);
     double* h = at<double>(p, p->o_h);
@@ -276,6 +324,7 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     a.nchunks = (int)((n + a.chunk_rows - 1) / a.chunk_rows);
     a.pstride = p->pstride;
     a.ncols = ncols;
+    a.ncols_bd = ncols_bd < ncols ? ncols : ncols_bd;
     a.r = r;
     a.n = n;
     a.basis = basis;
@@ -344,6 +393,125 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     return SSA_OK;
 }
 
+// Reduction step of the fused path: the partial sums in the partials buffer (nchunks
+// per column) give h, the new B entry and the normalization (k_cgs_reduce).  Long
+// bases hand a DGKS second pass to gated launches over the whole grid, which rewrite
+// r in place as r - basis h and redo the projection and the reduction; the next
+// pass-1 update then uses whichever h and scale were written last.
+int fused_finish(ssa_plan p, const float* basis, long long ld, int ncols, int ncols_bd, const SegLay& lay,
+                 int nchunks, double* coef_out, int track, unsigned long long ctr) {
+    hipStream_t s = p->stream;
+    float* r = at<float>(p, p->o_r);
+    double* h = at<double>(p, p->o_h);
+    double* sc = at<double>(p, p->o_sc);
+    ReduceArgs a{};
+    a.part = at<double>(p, p->o_part);
+    a.nchunks = nchunks;
+    a.pstride = p->pstride;
+    a.ncols = ncols;
+    a.ncols_bd = std::max(ncols, ncols_bd);
+    a.r = r;
+    a.n = lay.len;
+    a.basis = basis;
+    a.ld = ld;
+    a.h = h;
+    a.coef_out = coef_out;
+    a.scale_out = sc;
+    a.state = at<double>(p, p->o_state);
+    a.seed = p->seed;
+    a.stream_ctr = ctr;
+    a.track = track;
+    a.full = ncols >= lay.n ? 1 : 0;
+    a.tol_bd = kBreakdownTol;
+    a.segmented = 1;
+    a.seg = lay;
+    a.presummed = nchunks > kColsumChunks ? 1 : 0;
+    const long long grid2_rows = (long long)(p->onesided ? kGrid2ChunksOneSided : kColsumChunks) * kProjRows;
+    const bool grid2 = ncols > 0 && lay.n > grid2_rows;
+    int* flag2 = at<int>(p, p->o_flag) + 8;
+    a.dgks_flag = grid2 ? flag2 : nullptr;
+    if (a.presummed) {
+        ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)nchunks * (ncols + 1));
+        SSA_TRY(launch_cgs_colsum(a, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_REDUCE, a.presummed ? 8.0 * (ncols + 1) : 8.0 * (double)nchunks * (ncols + 1));
+        SSA_TRY(launch_cgs_reduce(a, s));
+    }
+    if (grid2) {
+        {
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
+            SSA_TRY(launch_cgs_update(r, basis, ld, ncols, h, sc, r, lay.len, flag2, s));
+        }
+        ReduceArgs b = a;
+        b.dgks_flag = nullptr;
+        b.gate = flag2;
+        b.chunk_rows = proj_chunk_rows(lay.len);
+        b.nchunks = (int)((lay.len + b.chunk_rows - 1) / b.chunk_rows);
+        b.presummed = b.nchunks > kColsumChunks ? 1 : 0;
+        {
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
+            SSA_TRY(launch_cgs_project(b, s));
+        }
+        if (b.presummed) {
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
+            SSA_TRY(launch_cgs_colsum(b, s));
+        }
+        {
+            ProfScope ps(p, SSA_PROF_DGKS2, 0.0);
+            SSA_TRY(launch_cgs_reduce(b, s));
+        }
+    }
+    return SSA_OK;
+}
+
+// One product of the fused path: pass 1 finishes x (the previous half-step's vector,
+// layout lin, written to out_col) and transforms it; pass 2; pass 3 writes
+// r = y - coef * prev in layout lout and the projection partials against ncols_out
+// columns of basis_out.
+int fused_product(ssa_plan p, const ConvGeom& g, const SegLay& lin, const float* basis_in, long long ld_in,
+                  int ncols_in, float* out_col, const SegLay& lout, const float* prev, const double* coef,
+                  const float* basis_out, long long ld_out, int ncols_out) {
+    hipStream_t s = p->stream;
+    float* r = at<float>(p, p->o_r);
+    float2* T1 = at<float2>(p, p->o_t1);
+    float2* T2 = at<float2>(p, p->o_t2);
+    const double mp = (double)g.Mp;
+    P1Seg a{};
+    a.lay = lin;
+    a.N = p->N;
+    a.r = r;
+    a.basis = basis_in;
+    a.ld = ld_in;
+    a.ncols = ncols_in;
+    a.h = at<double>(p, p->o_h);
+    a.scale = at<double>(p, p->o_sc);
+    a.out = out_col;
+    {
+        ProfScope ps(p, SSA_PROF_PASS1, 4.0 * (double)lin.n * (ncols_in + 2) + 8.0 * mp);
+        SSA_TRY(launch_p1_update(g, a, T1, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_PASS2, 24.0 * mp);
+        SSA_TRY(launch_pass2_matvec(g, at<float4>(p, p->o_ab), T1, T2, s));
+    }
+    P3Seg b{};
+    b.lay = lout;
+    b.r = r;
+    b.prev = prev;
+    b.coef = coef;
+    b.basis = basis_out;
+    b.ld = ld_out;
+    b.ncols = ncols_out;
+    b.part = at<double>(p, p->o_part);
+    b.pstride = p->pstride;
+    {
+        ProfScope ps(p, SSA_PROF_PASS3, 8.0 * mp + 4.0 * (double)lout.n * (ncols_out + (prev ? 2 : 1)));
+        SSA_TRY(launch_p3_project(g, T2, b, s));
+    }
+    return SSA_OK;
+}
+
 int check_series(ssa_plan p, const double* series_dev) {
     double* dflag = at<double>(p, p->o_flag);
     SSA_TRY(launch_fill_zero(dflag, 1, p->stream));
@@ -353,9 +521,19 @@ int check_series(ssa_plan p, const double* series_dev) {
     return *p->h_flag != 0.0 ? SSA_ENONFINITE : SSA_OK;
 }
 
-int do_embed(ssa_plan p, const double* series_dev) {
-    const int rc = check_series(p, series_dev);
-    if (rc != SSA_OK) return rc;
+// The spectral operator of the series (Algorithm 2, steps 1-2).  With sync_check the
+// series is first checked for NaN/Inf on the device and the host waits for the
+// answer; without it the check only leaves its flag in the workspace (the device
+// stopping test reports it), so nothing waits.
+int do_embed(ssa_plan p, const double* series_dev, bool sync_check = true) {
+    if (sync_check) {
+        const int rc = check_series(p, series_dev);
+        if (rc != SSA_OK) return rc;
+    } else {
+        double* dflag = at<double>(p, p->o_flag);
+        SSA_TRY(launch_fill_zero(dflag, 1, p->stream));
+        SSA_TRY(launch_check_finite(series_dev, p->N, dflag, p->stream));
+    }
     const ConvGeom g = bound_geom(p);
     P1In in{};
     in.f = series_dev;
@@ -376,6 +554,27 @@ std::once_flag g_attr_once;
 hipError_t g_attr_err = hipSuccess;
 
 }  // namespace
+
+namespace ssa {
+
+hipError_t kernel_attributes_once() {
+    std::call_once(g_attr_once, [] {
+        g_attr_err = set_kernel_attributes();
+        const hipError_t e2 = set_fused_attributes();
+        if (g_attr_err == hipSuccess) g_attr_err = e2;
+    });
+    return g_attr_err;
+}
+
+bool auto_geometry(long long N, ConvGeom* g) {
+    long long Mp;
+    int M1, M2;
+    if (!choose_fft(N, Mp, M1, M2)) return false;
+    fill_geom(Mp, M1, M2, default_cb(M1, M2), *g);
+    return true;
+}
+
+}  // namespace ssa
 
 extern "C" {
 
@@ -464,15 +663,7 @@ static int plan_create(long long N, long long L, long long K, int is2d, long lon
         M1 = (int)m1;
         M2 = (int)(Mp / m1);
     }
-    ConvGeom& g = p->g;
-    g.M1 = M1;
-    g.M2 = M2;
-    g.Mp = Mp;
-    g.M = 2 * Mp;
-    // columns per workgroup of passes 1 and 3: enough workgroups (~M2/CB >= 256) comes first;
-    // at N = 1e5 (M1 x M2 = 200 x 250) CB = 1 beats CB = 4 by 10% per product although the
-    // wider blocks fetch fewer partial lines (measured over every split of M' = 50000)
-    int cb = (int)std::min<long long>({16LL, 8192LL / M1, std::max(1LL, ((long long)M2 + 255) / 256)});
+    int cb = default_cb(M1, M2);
     if (opts && opts->fft_cb > 0) {
         // passes 1 and 3 hold CB columns of M1 points: at most 32 per thread of 256
         if (opts->fft_cb > 64 || (long long)opts->fft_cb * M1 > 8192) {
@@ -481,16 +672,22 @@ static int plan_create(long long N, long long L, long long K, int is2d, long lon
         }
         cb = opts->fft_cb;
     }
-    g.CB = std::max(1, cb);
-    int shift = 0;
-    while ((1LL << (2 * shift)) < Mp) ++shift;
-    g.tw_shift = shift;
-    g.st1 = make_stages(M1);
-    g.st2 = make_stages(M2);
-    p->ldU = (long long)align_up((size_t)p->Li, 64);
-    p->ldV = (long long)align_up((size_t)p->Ki, 64);
-    p->nchunks_max = (int)((p->Ki + kProjRows - 1) / kProjRows);
-    p->pstride = p->nchunks_max;
+    fill_geom(Mp, M1, M2, cb, p->g);
+    const ConvGeom& gg = p->g;
+    p->nblk = (gg.M2 + gg.CB - 1) / gg.CB;
+    p->fused = (!is2d && p->keep == 0 && p->Ki <= kFusedMaxRows && !(opts && opts->unfused)) ? 1 : 0;
+    if (p->fused) {
+        // U-side vectors are outputs y[Ki-1+i] of X v, V-side ones y[Li-1+i] of X^T u
+        p->layU = make_seglay(gg, p->Ki - 1, p->Li);
+        p->layV = make_seglay(gg, p->Li - 1, p->Ki);
+        p->ldU = (long long)align_up((size_t)p->layU.len, 64);
+        p->ldV = (long long)align_up((size_t)p->layV.len, 64);
+    } else {
+        p->ldU = (long long)align_up((size_t)p->Li, 64);
+        p->ldV = (long long)align_up((size_t)p->Ki, 64);
+    }
+    p->nchunks_max = (int)((std::max(p->ldU, p->ldV) + kProjRows - 1) / kProjRows);
+    p->pstride = std::max(p->nchunks_max, p->fused ? p->nblk : 0);
     layout(p);
     p->work.resize(bidiag_work_doubles(d_max) + 16);
     *workspace_bytes = p->ws_bytes;
@@ -521,13 +718,14 @@ int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_strea
     if (!p || !workspace_dev) return SSA_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
     if (bytes < p->ws_bytes) return SSA_ENOMEM;
-    std::call_once(g_attr_once, [] { g_attr_err = set_kernel_attributes(); });
-    if (g_attr_err != hipSuccess) return SSA_EDEVICE;
+    if (kernel_attributes_once() != hipSuccess) return SSA_EDEVICE;
     if (!p->h_scal) {
         const size_t nd = 4 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->kcols + p->k_max + 8;
         if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * nd, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
         if (hipHostMalloc((void**)&p->h_flag, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
+            return SSA_EDEVICE;
+        if (hipHostMalloc((void**)&p->h_rec, sizeof(double) * 2 * (size_t)p->nrec, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
         if (hipHostMalloc((void**)&p->h_grp, sizeof(int) * p->grp_ints, hipHostMallocDefault) != hipSuccess)
             return SSA_EDEVICE;
@@ -566,11 +764,17 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     if (k < 1 || k > p->k_max) return SSA_EINVAL;
     if (N != p->N || L != p->L) return SSA_EMISMATCH;
     if (!p->bound) return SSA_ENOMEM;
-    int rc = do_embed(p, series_dev);
+    // Without thick restart the stopping test and the Ritz coefficients run on the
+    // device and the host reads back only the test's record; the restarted solver
+    // assembles its projected matrix on the host.
+    const bool devchk = p->keep == 0;
+    int rc = do_embed(p, series_dev, !devchk);
     if (rc != SSA_OK) return rc;
     const ConvGeom g = bound_geom(p);
     hipStream_t s = p->stream;
     const long long Li = p->Li, Ki = p->Ki;
+    double* rec = at<double>(p, p->o_rec);
+    if (devchk) SSA_TRY(launch_fill_zero(rec, p->nrec, s));
     float* U = at<float>(p, p->o_U);
     float* V = at<float>(p, p->o_V);
     float* r = at<float>(p, p->o_r);
@@ -580,9 +784,28 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     SSA_TRY(launch_fill_zero(beta, p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
 
-    // Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0
-    SSA_TRY(launch_start_vector(r, Li, p->seed, s));
-    rc = orthonormalize(p, U, p->ldU, 0, Li, beta + 1, 0, 1);
+    // Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0 (the fused
+    // path leaves u_1 = r * scale to the first pass-1 update)
+    if (p->fused) {
+        SSA_TRY(launch_start_seg(r, p->layU, p->seed, s));
+        ReduceArgs a0{};
+        a0.part = at<double>(p, p->o_part);
+        a0.chunk_rows = proj_chunk_rows(p->layU.len);
+        a0.nchunks = (int)((p->layU.len + a0.chunk_rows - 1) / a0.chunk_rows);
+        a0.pstride = p->pstride;
+        a0.r = r;
+        a0.n = p->layU.len;
+        a0.basis = U;
+        a0.ld = p->ldU;
+        {
+            ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)Li);
+            SSA_TRY(launch_cgs_project(a0, s));
+        }
+        rc = fused_finish(p, U, p->ldU, 0, 0, p->layU, a0.nchunks, beta + 1, 0, 1);
+    } else {
+        SSA_TRY(launch_start_vector(r, Li, p->seed, s));
+        rc = orthonormalize(p, U, p->ldU, 0, Li, beta + 1, 0, 1);
+    }
     if (rc != SSA_OK) return rc;
 
     const int d_cap = (int)std::min<long long>(p->d_max, std::min(Li, Ki));
@@ -595,6 +818,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     bool have_prev = false, converged = false;
     int d = 0, steps_run = 0;
     const double* fin = nullptr;
+    const double* fin_rec = nullptr;  // device-check path: the record that ended the solve
     // Stopping test on B_jj (its residual bound needs alpha_{jj+1}).  The test
     // of one check point runs on the host while the GPU works through the
     // steps enqueued after it, so the GPU never waits for the host; if it
@@ -620,17 +844,64 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     };
     int pend_jj = -1, pend_buf = 0, cur_buf = 0;
     for (int j = 1;; ++j) {
-        // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
-        rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, 0, r,
-                      j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
-        if (rc != SSA_OK) return rc;
         // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
-        rc = orthonormalize(p, V, p->ldV, p->onesided ? 0 : j - 1, Ki, alpha + j, 1, 2ULL * j, j - 1);
+        const int ncv = p->onesided ? 0 : j - 1;
+        if (p->fused) {
+            // finish u_j; r_j = X^T u_j - beta_j v_{j-1}; its partials against V_{j-1}; alpha_j
+            rc = fused_product(p, g, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU, p->layV,
+                               j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j, V, p->ldV, ncv);
+            if (rc != SSA_OK) return rc;
+            rc = fused_finish(p, V, p->ldV, ncv, j - 1, p->layV, p->nblk, alpha + j, 1, 2ULL * j);
+        } else {
+            // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
+            rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, 0, r,
+                          j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
+            if (rc != SSA_OK) return rc;
+            rc = orthonormalize(p, V, p->ldV, ncv, Ki, alpha + j, 1, 2ULL * j, j - 1, j - 1);
+        }
         if (rc != SSA_OK) return rc;
         const int jj = j - 1;
         steps_run = jj;
         bool stop = false;
-        if (jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
+        if (devchk && jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
+            // the test of one check point runs on the device while the host has the next
+            // steps enqueued; the host reads its record one check point later
+            LzCheck c{};
+            c.alpha = alpha;
+            c.beta = beta;
+            c.jj = jj;
+            c.k = k;
+            c.dcap = d_cap;
+            c.rmin = std::min(Li, Ki);
+            c.tol = p->tol;
+            c.rec = rec;
+            c.state = at<double>(p, p->o_state);
+            c.nonfinite = at<double>(p, p->o_flag);
+            c.scr = at<double>(p, p->o_lzscr);
+            c.kstride = p->kcols;
+            c.dstride = p->dstride;
+            {
+                ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (jj + 2));
+                SSA_TRY(launch_lz_check(c, s));
+            }
+            double* hr = p->h_rec + (size_t)cur_buf * p->nrec;
+            SSA_TRY(hipMemcpyAsync(hr, rec, sizeof(double) * p->nrec, hipMemcpyDeviceToHost, s));
+            SSA_TRY(hipEventRecord(p->chk_ev[cur_buf], s));
+            if (pend_jj >= 0) {
+                SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
+                stop = p->h_rec[(size_t)pend_buf * p->nrec + kChkDone] != 0.0;
+            }
+            if (!stop) {
+                pend_jj = jj;
+                pend_buf = cur_buf;
+                cur_buf ^= 1;
+                if (jj >= d_cap) {
+                    SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
+                    stop = p->h_rec[(size_t)pend_buf * p->nrec + kChkDone] != 0.0;
+                }
+            }
+            if (stop) fin_rec = p->h_rec + (size_t)pend_buf * p->nrec;
+        } else if (!devchk && jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
             double* buf = h_ab[cur_buf];
             SSA_TRY(hipMemcpyAsync(buf, alpha, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
             SSA_TRY(hipMemcpyAsync(buf + abn, beta, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
@@ -650,16 +921,78 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
             }
         }
         if (stop) break;
-        // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
-        rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, 1, r, U + (long long)(j - 1) * p->ldU, alpha + j);
+        if (p->fused) {
+            // finish v_j; p_j = X v_j - alpha_j u_j; its partials against U_j; beta_{j+1}
+            rc = fused_product(p, g, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV, p->layU,
+                               U + (long long)(j - 1) * p->ldU, alpha + j, U, p->ldU, j);
+            if (rc != SSA_OK) return rc;
+            rc = fused_finish(p, U, p->ldU, j, j, p->layU, p->nblk, beta + j + 1, 1, 2ULL * j + 1);
+        } else {
+            // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
+            rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, 1, r, U + (long long)(j - 1) * p->ldU, alpha + j);
+            if (rc != SSA_OK) return rc;
+            rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
+        }
         if (rc != SSA_OK) return rc;
-        rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
-        if (rc != SSA_OK) return rc;
+    }
+    double* dP = at<double>(p, p->o_P);
+    double* dQ = at<double>(p, p->o_Q);
+    float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
+    float* Vo = p->transposed ? U_dev : V_dev;
+    if (devchk) {
+        // stream-ordered from here: the Ritz coefficients and vectors are enqueued and the
+        // call returns; the outputs are complete when the stream has run them
+        if (fin_rec[kChkNonfinite] != 0.0) {
+            p->embedded = 0;  // the operator holds the non-finite series: unusable
+            return SSA_ENONFINITE;
+        }
+        d = (int)fin_rec[kChkD];
+        const bool conv = fin_rec[kChkConv] != 0.0;
+        LzRitz rz{};
+        rz.alpha = alpha;
+        rz.beta = beta;
+        rz.rec = rec;
+        rz.k = k;
+        rz.kstride = k;
+        rz.dstride = p->dstride;
+        rz.P = dP;
+        rz.Q = dQ;
+        rz.sigma = sigma_dev;
+        rz.scr = at<double>(p, p->o_lzscr);
+        {
+            ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (d + 2));
+            SSA_TRY(launch_lz_ritz(rz, d, s));
+        }
+        {
+            ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (d + 1 + k));
+            if (p->fused)
+                SSA_TRY(launch_ritz_seg(U, p->ldU, d + 1, dP, k, Uo, Li, p->layU, s));
+            else
+                SSA_TRY(launch_ritz(U, p->ldU, d + 1, dP, k, Uo, Li, Li, s));
+        }
+        {
+            ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (d + k));
+            if (p->fused)
+                SSA_TRY(launch_ritz_seg(V, p->ldV, d, dQ, k, Vo, Ki, p->layV, s));
+            else
+                SSA_TRY(launch_ritz(V, p->ldV, d, dQ, k, Vo, Ki, Ki, s));
+        }
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->steps = d;
+            info->converged = conv ? 1 : 0;
+            info->restarts = (int)fin_rec[kChkRestarts];
+            info->dgks_passes = (int)fin_rec[kChkDgks];
+            info->steps_run = steps_run;
+            const double* resid = fin_rec + kChkHdr + 2 * p->kcols;
+            for (int i = 0; i < k && i < 64; ++i) info->resid[i] = resid[i];
+        }
+        const int status = !conv ? SSA_WARN_NOT_CONVERGED : fin_rec[kChkRestarts] > 0.0 ? SSA_WARN_BREAKDOWN : SSA_OK;
+        if (info) info->status = status;
+        return status;
     }
     const double* h_alpha = fin;
     const double* h_beta = fin + abn;
-    double* dP = at<double>(p, p->o_P);
-    double* dQ = at<double>(p, p->o_Q);
     int nu = d + 1, nc = d;  // the result is U_{nu} P (nu x k) and V_{nc} Q (nc x k)
     int cycles = 0;
 
@@ -782,15 +1115,19 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     SSA_TRY(hipMemcpyAsync(dP, h_P, sizeof(double) * (size_t)nu * k, hipMemcpyHostToDevice, s));
     SSA_TRY(hipMemcpyAsync(dQ, h_Q, sizeof(double) * (size_t)nc * k, hipMemcpyHostToDevice, s));
     SSA_TRY(hipMemcpyAsync(sigma_dev, h_sig, sizeof(double) * k, hipMemcpyHostToDevice, s));
-    float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
-    float* Vo = p->transposed ? U_dev : V_dev;
     {
         ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (nu + k));
-        SSA_TRY(launch_ritz(U, p->ldU, nu, dP, k, Uo, Li, Li, s));
+        if (p->fused)
+            SSA_TRY(launch_ritz_seg(U, p->ldU, nu, dP, k, Uo, Li, p->layU, s));
+        else
+            SSA_TRY(launch_ritz(U, p->ldU, nu, dP, k, Uo, Li, Li, s));
     }
     {
         ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (nc + k));
-        SSA_TRY(launch_ritz(V, p->ldV, nc, dQ, k, Vo, Ki, Ki, s));
+        if (p->fused)
+            SSA_TRY(launch_ritz_seg(V, p->ldV, nc, dQ, k, Vo, Ki, p->layV, s));
+        else
+            SSA_TRY(launch_ritz(V, p->ldV, nc, dQ, k, Vo, Ki, Ki, s));
     }
     double st[3] = {0, 0, 0};
     SSA_TRY(hipMemcpyAsync(h_sig + k, at<double>(p, p->o_state), sizeof(double) * 3, hipMemcpyDeviceToHost, s));
@@ -806,7 +1143,9 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         info->thick_restarts = cycles;
         for (int i = 0; i < k && i < 64; ++i) info->resid[i] = res[i];
     }
-    return converged ? SSA_OK : SSA_WARN_NOT_CONVERGED;
+    const int status = !converged ? SSA_WARN_NOT_CONVERGED : st[1] > 0.0 ? SSA_WARN_BREAKDOWN : SSA_OK;
+    if (info) info->status = status;
+    return status;
 }
 
 int ssa_reconstruct(ssa_plan p, const double* sigma_dev, const float* U_dev, const float* V_dev, int k,
@@ -927,6 +1266,7 @@ void ssa_plan_destroy(ssa_plan p) {
         if (e) (void)hipEventDestroy(e);
     if (p->h_scal) (void)hipHostFree(p->h_scal);
     if (p->h_flag) (void)hipHostFree(p->h_flag);
+    if (p->h_rec) (void)hipHostFree(p->h_rec);
     if (p->h_grp) (void)hipHostFree(p->h_grp);
     delete p;
 }
@@ -935,6 +1275,7 @@ const char* ssa_status_str(int status) {
     switch (status) {
         case SSA_OK: return "ok";
         case SSA_WARN_NOT_CONVERGED: return "stopping rule not met before the Krylov dimension cap";
+        case SSA_WARN_BREAKDOWN: return "converged after a breakdown (alpha or beta vanished; rank below k)";
         case SSA_EINVAL: return "invalid argument";
         case SSA_ENOMEM: return "workspace missing or too small";
         case SSA_ENONFINITE: return "series holds NaN or Inf";

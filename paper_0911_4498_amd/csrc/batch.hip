@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ssa_batch.h"
+#include "tridiag_dev.h"
 
 namespace ssa {
 namespace batch {
@@ -346,9 +347,12 @@ SSA_INLINE double cgs_h2(CgsLds* sh, int ncols, int tid) {
 // New basis column ncols from r: one Gram-Schmidt pass with
 // |r_new|^2 = |r|^2 - |h|^2, a second pass if |r_new|^2 < |r|^2 / 2 (DGKS),
 // a seeded random direction if the vector vanishes (|r_new| <= tol * max B).
+// The random direction is made orthogonal to the first ncols_bd >= ncols columns:
+// one-sided reorthogonalization projects the V side against no column (ncols = 0),
+// yet a fresh direction must still be orthogonal to every earlier v (Sec. 3.2).
 // Returns the B entry (0 after a restart); updates the series state.
 SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basis, long long ld, int ncols,
-                                 long long n, unsigned long long ctr, int tid, int out_col) {
+                                 int ncols_bd, long long n, unsigned long long ctr, int tid, int out_col) {
     const double bnorm = q.state[kStBnorm];
     cgs_project(sh, r, basis, ld, ncols, n, tid);
     double coef = 0.0, scale = 0.0;
@@ -377,12 +381,12 @@ SSA_INLINE double orthonormalize(CgsLds* sh, const Ser& q, float* r, float* basi
                 for (long long t = tid; t < n; t += kCgsThreads) r[t] = gaussian(q.seed, ctr, t);
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
-                    cgs_project(sh, r, basis, ld, ncols, n, tid);
-                    cgs_update(sh, r, basis, ld, ncols, n, 1.0, r, tid);
+                    cgs_project(sh, r, basis, ld, ncols_bd, n, tid);
+                    cgs_update(sh, r, basis, ld, ncols_bd, n, 1.0, r, tid);
                 }
                 cgs_project(sh, r, basis, ld, 0, n, tid);
                 const double r3 = sh->h[0];
-                for (int c = tid; c < ncols; c += kCgsThreads) sh->h[c] = 0.0;
+                for (int c = tid; c < ncols_bd; c += kCgsThreads) sh->h[c] = 0.0;
                 __syncthreads();
                 scale = r3 > 0.0 ? 1.0 / sqrt(r3) : 0.0;
                 event = 2;
@@ -505,10 +509,10 @@ __global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int side) {
     if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
     if (side == 0) {
         // one-sided: V (length Ki >= Li) keeps only the three-term recurrence
-        const double aj = orthonormalize(sh, q, q.r, q.V, q.ldv, a.onesided ? 0 : j - 1, q.Ki, 2ULL * j, tid, j - 1);
+        const double aj = orthonormalize(sh, q, q.r, q.V, q.ldv, a.onesided ? 0 : j - 1, j - 1, q.Ki, 2ULL * j, tid, j - 1);
         if (tid == 0) q.alpha[j] = aj;
     } else {
-        const double bj = orthonormalize(sh, q, q.r, q.U, q.ldu, j, q.Li, 2ULL * j + 1, tid, j);
+        const double bj = orthonormalize(sh, q, q.r, q.U, q.ldu, j, j, q.Li, 2ULL * j + 1, tid, j);
         if (tid == 0) {
             q.beta[j + 1] = bj;
             q.state[kStJ] = (double)(j + 1);  // the series' next Lanczos step
@@ -518,18 +522,6 @@ __global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int side) {
 
 // The k largest eigenvalues of T_n by multisection (sh->lam); D, E2 in sh->tri,
 // the pivot floor in sh->dmisc[0].
-SSA_INLINE int sturm_count(const double* D, const double* E2, int n, double x, double pivmin) {
-    double d = D[0] - x;
-    if (fabs(d) < pivmin) d = -pivmin;
-    int cnt = d < 0.0 ? 1 : 0;
-    for (int i = 1; i < n; ++i) {
-        d = D[i] - x - E2[i - 1] / d;
-        if (fabs(d) < pivmin) d = -pivmin;
-        cnt += d < 0.0 ? 1 : 0;
-    }
-    return cnt;
-}
-
 SSA_INLINE void tridiag_top(SmallLds* sh, int n, int k, int tid) {
     const double* al = sh->ab;
     const double* be = sh->ab + (kDmax + 3);
@@ -552,86 +544,15 @@ SSA_INLINE void tridiag_top(SmallLds* sh, int n, int k, int tid) {
     }
     const double gmax = block_max(sh, g, tid);
     const double pivmin = 2.2250738585072014e-308 * fmax(1.0, block_max(sh, e2max, tid));
-    const int P = kThreads / k;  // shifts per eigenvalue per round
     for (int i = tid; i < k; i += kThreads) {
         sh->lo[i] = 0.0;
         sh->hi[i] = gmax * (1.0 + 1e-12) + 1e-300;
     }
     __syncthreads();
-    const int ei = tid / P, p = tid % P;
-    for (int round = 0; round < 14; ++round) {
-        if (ei < k) {
-            const double lo = sh->lo[ei], hi = sh->hi[ei];
-            const double x = lo + (hi - lo) * (double)(p + 1) / (double)(P + 1);
-            sh->cnt[tid] = sturm_count(D, E2, n, x, pivmin);
-            sh->xs[tid] = x;
-        }
-        __syncthreads();
-        if (ei < k && p == 0) {
-            const int m = n - 1 - ei;  // the eigenvalue is the m-th smallest
-            double lo = sh->lo[ei], hi = sh->hi[ei];
-            for (int t = 0; t < P; ++t) {
-                const int idx = ei * P + t;
-                if (sh->cnt[idx] <= m) {
-                    lo = sh->xs[idx];
-                } else {
-                    hi = sh->xs[idx];
-                    break;
-                }
-            }
-            sh->lo[ei] = lo;
-            sh->hi[ei] = hi;
-        }
-        __syncthreads();
-    }
+    multisection_top<kThreads>(D, E2, n, k, pivmin, sh->lo, sh->hi, sh->xs, sh->cnt, 14, tid);
     for (int i = tid; i < k; i += kThreads) sh->lam[i] = 0.5 * (sh->lo[i] + sh->hi[i]);
     if (tid == 0) sh->dmisc[0] = pivmin;
     __syncthreads();
-}
-
-// Squared last component of the unit eigenvector of T_n at eigenvalue lam, from
-// the twisted factorization of T - lam I (Dhillon and Parlett): backward pivots
-// dm, forward pivots dp, twist index r minimizing |dp_r + dm_r - (D_r - lam)|,
-// then z_r = 1 and z spreads both ways by products of pivot ratios, which keeps
-// the tiny tail components of converged Ritz vectors to relative accuracy.
-// dm and dp (n doubles each) live in the caller's scratch.
-SSA_INLINE double twisted_qlast(const double* D, const double* E2, int n, double lam, double pivmin, double* dm,
-                                double* dp) {
-    if (n == 1) return 1.0;
-    dm[n - 1] = D[n - 1] - lam;
-    for (int c = n - 2; c >= 0; --c) {
-        const double x = fabs(dm[c + 1]) >= pivmin ? dm[c + 1] : -pivmin;
-        dm[c] = D[c] - lam - E2[c] / x;
-    }
-    double best = 0.0;
-    int r = 0;
-    for (int c = 0; c < n; ++c) {
-        if (c == 0) {
-            dp[0] = D[0] - lam;
-        } else {
-            const double x = fabs(dp[c - 1]) >= pivmin ? dp[c - 1] : -pivmin;
-            dp[c] = D[c] - lam - E2[c - 1] / x;
-        }
-        const double g = fabs(dp[c] + dm[c] - (D[c] - lam));
-        if (c == 0 || g < best) {
-            best = g;
-            r = c;
-        }
-    }
-    double z = 1.0, zz = 1.0;
-    for (int c = r - 1; c >= 0; --c) {
-        const double x = fabs(dp[c]) >= pivmin ? dp[c] : -pivmin;
-        z = -(sqrt(E2[c]) / x) * z;
-        zz += z * z;
-    }
-    z = 1.0;
-    for (int c = r + 1; c < n; ++c) {
-        const double x = fabs(dm[c]) >= pivmin ? dm[c] : -pivmin;
-        z = -(sqrt(E2[c - 1]) / x) * z;
-        zz += z * z;
-    }
-    const double zl = r == n - 1 ? 1.0 : z;
-    return zl * zl / zz;
 }
 
 // Stopping test of step j on B_{j-1} for the series whose check point it is:
@@ -684,41 +605,20 @@ __global__ __launch_bounds__(kThreads) void kb_check(BatchArgs a) {
     }
 }
 
-// Solve (T - lam I) x = x in place (partial pivoting; tiny pivots replaced).
-SSA_INLINE void shifted_solve(const double* D, const double* E, int n, double lam, double tnorm, double* x,
-                              double* a, double* b, double* cc, double* u2) {
-    for (int i = 0; i < n; ++i) a[i] = D[i] - lam;
-    for (int i = 0; i + 1 < n; ++i) {
-        b[i] = E[i];
-        cc[i] = E[i];
-    }
-    const double tiny = 2.220446049250313e-16 * (tnorm > 0.0 ? tnorm : 1.0);
-    for (int i = 0; i + 1 < n; ++i) {
-        u2[i] = 0.0;
-        if (fabs(a[i]) >= fabs(cc[i])) {
-            if (a[i] == 0.0) a[i] = tiny;
-            const double f = cc[i] / a[i];
-            a[i + 1] -= f * b[i];
-            x[i + 1] -= f * x[i];
-        } else {
-            const double f = a[i] / cc[i];
-            a[i] = cc[i];
-            const double t = a[i + 1];
-            a[i + 1] = b[i] - f * t;
-            if (i + 2 < n) {
-                u2[i] = b[i + 1];
-                b[i + 1] = -f * b[i + 1];
-            }
-            b[i] = t;
-            const double r0 = x[i];
-            x[i] = x[i + 1];
-            x[i + 1] = r0 - f * x[i + 1];
+// Column i of the (n x k, row-major) left coefficient matrix P made orthogonal to
+// columns 0..i-1 by two Gram-Schmidt passes; returns its norm.
+SSA_INLINE double left_orth(SmallLds* sh, double* P, int k, int n, int i, int tid) {
+    for (int pass = 0; pass < 2; ++pass)
+        for (int j = 0; j < i; ++j) {
+            double h = 0.0;
+            for (int r = tid; r < n; r += kThreads) h += P[(long long)r * k + j] * P[(long long)r * k + i];
+            h = block_sum(sh, h, tid);
+            for (int r = tid; r < n; r += kThreads) P[(long long)r * k + i] -= h * P[(long long)r * k + j];
+            __syncthreads();
         }
-    }
-    if (a[n - 1] == 0.0) a[n - 1] = tiny;
-    x[n - 1] /= a[n - 1];
-    if (n >= 2) x[n - 2] = (x[n - 2] - b[n - 2] * x[n - 1]) / a[n - 2];
-    for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - b[i] * x[i + 1] - u2[i] * x[i + 2]) / a[i];
+    double nrm = 0.0;
+    for (int r = tid; r < n; r += kThreads) nrm += P[(long long)r * k + i] * P[(long long)r * k + i];
+    return sqrt(block_sum(sh, nrm, tid));
 }
 
 // out[i*ldo + t] = sum_{c < ncols} basis[c][t] coef[c*k + i], i < k
@@ -801,6 +701,9 @@ __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
         }
     }
     __syncthreads();
+    double bm = 0.0;
+    for (int i = tid; i < d; i += kThreads) bm = fmax(bm, fmax(fabs(al[i + 1]), fabs(be[i + 2])));
+    const double bmax = block_max(sh, bm, tid);
     const int kk = k < d ? k : d;
     for (int i = 0; i < kk; ++i) {
         double* xi = q.scr + (long long)i * 5 * stride;
@@ -820,15 +723,23 @@ __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
             q.Q[(long long)t * k + i] = xi[t];
         }
         __syncthreads();
-        double pn = 0.0;
+        // p = B q, kept orthogonal to the earlier left vectors (two passes); when it
+        // vanishes (omega_i = 0, a series of rank below k) a unit vector orthogonal to
+        // them completes the SVD of B instead
         for (int r = tid; r <= d; r += kThreads) {
             double v = 0.0;
             if (r < d) v += al[r + 1] * xi[r];
             if (r >= 1) v += be[r + 1] * xi[r - 1];
             q.P[(long long)r * k + i] = v;
-            pn += v * v;
         }
-        pn = sqrt(block_sum(sh, pn, tid));
+        __syncthreads();
+        double pn = left_orth(sh, q.P, k, d + 1, i, tid);
+        for (int c = d; !(pn > 1e-12 * bmax) && c >= 0; --c) {
+            for (int r = tid; r <= d; r += kThreads) q.P[(long long)r * k + i] = r == c ? 1.0 : 0.0;
+            __syncthreads();
+            pn = left_orth(sh, q.P, k, d + 1, i, tid);
+            if (pn < 0.5) pn = 0.0;
+        }
         for (int r = tid; r <= d; r += kThreads) q.P[(long long)r * k + i] = pn > 0.0 ? q.P[(long long)r * k + i] / pn : 0.0;
         __syncthreads();
     }

@@ -1,0 +1,398 @@
+// fused.hip -- the Lanczos half-step of the single-series path in four launches.
+//
+// Algorithm 1 alternates two half-steps; each is one trajectory-matrix product by
+// FFT (Algorithms 2/3: pass 1 column FFTs, pass 2 row FFTs with the spectral
+// operator, pass 3 inverse column FFTs) followed by classical Gram-Schmidt
+// against the basis of its side (Sec. 3.2.2).  Kernel boundaries are the cheapest
+// grid-wide synchronization on this GPU, so the work is cut where a grid-wide
+// result is needed and fused everywhere else:
+//
+//   k_p1_update   finishes the previous half-step's vector x = (r - B h) * scale
+//                 (B its basis, h and scale from the reduction) and runs pass 1
+//                 of the product that takes x;
+//   pass 2        unchanged (kernels.hip);
+//   k_p3_project  pass 3, the three-term term r = y - coef * prev, and the
+//                 projection partials <b_c, r> and |r|^2 of its block;
+//   reduce        one workgroup: h, the new alpha or beta, DGKS, breakdown
+//                 (k_cgs_reduce, kernels.hip).
+//
+// The vectors of both bases live in the segment layout (SegLay): pass 3's
+// workgroup owns a contiguous slot range of its output, and the reversed input of
+// the next product maps each pass-1 column onto whole segments, so both fused
+// kernels read the basis in coalesced float4 runs.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "ssa_internal.h"
+
+namespace ssa {
+
+// Threads of the fused kernels: 16 waves per workgroup keep enough basis loads in
+// flight when one workgroup per CU streams its slice of the basis.
+constexpr int kFusedThreads = 1024;
+// basis columns a wave of k_p3_project handles at once (independent loads in flight)
+constexpr int kProjUnroll = 4;
+
+// float2 words of the FFT buffer and its twiddles, rounded up to 16 bytes
+__host__ __device__ inline int fused_fft_lds_words(const ConvGeom& g) {
+    const int w = g.CB * (g.M1 + 1) + g.M1;
+    return w + (w & 1);
+}
+
+// Pass 3 + three-term term + projection partials.  Workgroup b (XCD-ordered)
+// owns the columns [c0, c0 + CB) of the four-step layout, i.e. the output slots
+// [2*c0*S, 2*(c0 + CB)*S).  The loads that do not depend on the transform (the
+// three-term vector and the first basis columns of each wave) are issued before
+// it, so their latency hides behind the column FFT.
+template <int EPT>
+__global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const float2* __restrict__ T2, P3Seg a) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int kWaves = kFusedThreads / 64;
+    const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
+    const int S = a.lay.S;
+    float2* buf = smem;             // CB x (M1 + 1)
+    float2* tw = buf + CB * ss;     // M1
+    float* rs = reinterpret_cast<float*>(smem + fused_fft_lds_words(g));  // 2 * CB * S floats
+    const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
+    const int ncb = min(CB, M2 - c0);  // columns of this block inside the transform
+    const int nsl = 2 * ncb * S;
+    const int nf = nsl / 4;
+    const long long base = 2LL * c0 * S;
+    const float cf = (a.prev && a.coef) ? (float)(*a.coef) : 0.0f;
+    const float pv0 = (a.prev && tid < nsl) ? a.prev[base + tid] : 0.0f;
+    // (not in the 8-point instantiation for long rows: capped at 128 VGPRs, it would spill)
+    constexpr int kPre = EPT >= 8 ? 0 : kProjUnroll;
+    float4 pre[kPre > 0 ? kPre : 1];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int c = wave * kProjUnroll + u;
+        pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < a.ncols && lane < nf) pre[u] = reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + base)[lane];
+    }
+    for (int t = tid; t < M1; t += kFusedThreads) tw[t] = g.tw1[t];
+    for (int idx = tid; idx < CB * M1; idx += kFusedThreads) {
+        const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
+        float2 z = make_float2(0.0f, 0.0f);
+        if (n2 < M2) z = cmul(T2[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
+        buf[c * ss + k1] = z;
+    }
+    __syncthreads();
+    lds_fft<1, EPT>(buf, g.st1, CB, ss, tw, tid, kFusedThreads);
+    for (int q = tid; q < nsl; q += kFusedThreads) {
+        const int sg = q / S, t = q - sg * S;
+        const int c = sg >> 1, e = sg & 1, n2 = c0 + c;
+        float v = 0.0f;
+        if (t < seg_count(a.lay, n2, e)) {
+            const float2 z = buf[c * ss + (int)(seg_lo(a.lay, n2, e) + t)];
+            v = e ? z.y : z.x;
+            if (a.prev) v -= cf * (q == tid ? pv0 : a.prev[base + q]);
+        }
+        rs[q] = v;
+        a.r[base + q] = v;
+    }
+    __syncthreads();
+    // partials: the waves split the columns (column ncols stands for |r|^2), the lanes
+    // split the float4 groups of the block; FP64 sums of exact FP32 products
+    const float4* r4 = reinterpret_cast<const float4*>(rs);
+    const int ncol = a.ncols + 1;
+    for (int cb0 = wave * kProjUnroll; cb0 < ncol; cb0 += kWaves * kProjUnroll) {
+        const bool first = cb0 == wave * kProjUnroll;  // wave-uniform
+        double acc[kProjUnroll];
+#pragma unroll
+        for (int u = 0; u < kProjUnroll; ++u) acc[u] = 0.0;
+        for (int f = lane; f < nf; f += 64) {
+            const float4 rv = r4[f];
+            float4 bv[kProjUnroll];
+#pragma unroll
+            for (int u = 0; u < kProjUnroll; ++u) {
+                // the column index is wave-uniform: branches, not address selects
+                const int c = cb0 + u;
+                bv[u] = rv;
+                if (c < a.ncols) {
+                    if (kPre > 0 && first && f == lane)
+                        bv[u] = pre[u < kPre ? u : 0];
+                    else
+                        bv[u] = reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + base)[f];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kProjUnroll; ++u) acc[u] += dot4(bv[u], rv);
+        }
+#pragma unroll
+        for (int u = 0; u < kProjUnroll; ++u) {
+            const double sum = wave_sum(acc[u]);
+            const int c = cb0 + u;
+            if (lane == 0 && c < ncol) a.part[(long long)c * a.pstride + blockIdx.x] = sum;
+        }
+    }
+}
+
+// Finishing the previous vector + pass 1 of the product that takes it.  The
+// workgroup owns the columns [c0, c0 + CB) of pass 1; element (n1, n2, e) of the
+// reversed input is natural element n_in - 1 - m (m = 2*(M2*n1 + n2) + e) of x,
+// which sits at y index m' = N - 1 - m of x's layout: for fixed (n2, e) that is one
+// segment s' whose slot t' holds n1 = Q - seg_lo(s') - t'.
+struct SegSrc {
+    long long pos;  // stored position of slot 0 of the source segment
+    int lo, cnt, Q;  // its first n1', its element count (0: padding only), n1 = Q - n1'
+};
+
+// Source segment of local segment sl = 2 c + e (pass-1 column c0 + c, parity e).  A =
+// m' - 2 M2 n1 for this (n2, e); over all pairs A runs through 2 M2 consecutive
+// integers, so every segment of x is the source of exactly one pair.  A < 0 holds no
+// element of x (m' < 0): its segment only gets its zeros written.
+__device__ __forceinline__ SegSrc seg_source(const P1Seg& a, int M2, int S, int c0, int sl) {
+    const int c = sl >> 1, e = sl & 1, n2 = c0 + c;
+    const long long A = a.N - 1 - e - 2LL * n2;
+    const int ep = (int)(A & 1);
+    const long long H = (A - ep) / 2;  // exact
+    const int n2p = (int)(((H % M2) + M2) % M2);
+    SegSrc d;
+    d.pos = (2LL * n2p + ep) * S;
+    d.Q = A >= 0 ? (int)(H / M2) : 0;
+    d.lo = (int)seg_lo(a.lay, n2p, ep);
+    d.cnt = A >= 0 ? seg_count(a.lay, n2p, ep) : 0;
+    return d;
+}
+
+// Sum over the columns c = slice, slice + nslice, ... of basis[c][p..p+3] h[c] for
+// float4 group f of the workgroup's source segments (nothing for a missing segment).
+// The first kUpdPre columns may come preloaded (use_pre).
+constexpr int kUpdPre = 4;
+__device__ __forceinline__ void fused_accumulate(const P1Seg& a, const double* hs, const SegSrc* src, int gps, int f,
+                                                 int slice, int nslice, double (&x)[4], const float4 (&pre)[kUpdPre],
+                                                 bool use_pre) {
+    x[0] = x[1] = x[2] = x[3] = 0.0;
+    const int sg = f / gps;
+    if (4 * (f - sg * gps) >= src[sg].cnt) return;  // padding slots only
+    const long long p = src[sg].pos + 4LL * (f - sg * gps);
+    int c = slice;
+    if (use_pre) {
+#pragma unroll
+        for (int u = 0; u < kUpdPre; ++u, c += nslice) {
+            if (c >= a.ncols) break;
+            const double hc = hs[c];
+            x[0] += (double)pre[u].x * hc;
+            x[1] += (double)pre[u].y * hc;
+            x[2] += (double)pre[u].z * hc;
+            x[3] += (double)pre[u].w * hc;
+        }
+    }
+#pragma unroll 4
+    for (; c < a.ncols; c += nslice) {
+        const float4 b = *reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + p);
+        const double hc = hs[c];
+        x[0] += (double)b.x * hc;
+        x[1] += (double)b.y * hc;
+        x[2] += (double)b.z * hc;
+        x[3] += (double)b.w * hc;
+    }
+}
+
+// x = (r - sum) * scale at the four slots of group f: written to the output column
+// (zero in padding slots) and placed in the pass-1 buffer at its (n1, e).
+__device__ __forceinline__ void fused_finish_group(const P1Seg& a, const SegSrc* src, int gps, int f,
+                                                   const double (&x)[4], double scale, float2* buf, int ss) {
+    const int sg = f / gps;
+    const SegSrc d = src[sg];
+    const int tq0 = 4 * (f - sg * gps);
+    const long long p = d.pos + tq0;
+    const float4 rv = tq0 < d.cnt ? *reinterpret_cast<const float4*>(a.r + p) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float r4[4] = {rv.x, rv.y, rv.z, rv.w};
+    float o[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int tq = tq0 + u;
+        o[u] = 0.0f;
+        if (tq < d.cnt) {
+            o[u] = (float)(((double)r4[u] - x[u]) * scale);
+            float2* z = &buf[(sg >> 1) * ss + (d.Q - d.lo - tq)];
+            if (sg & 1) z->y = o[u];
+            else z->x = o[u];
+        }
+    }
+    *reinterpret_cast<float4*>(a.out + p) = make_float4(o[0], o[1], o[2], o[3]);
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a, float2* __restrict__ T1) {
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x;
+    const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
+    const int S = a.lay.S;
+    float2* buf = smem;                                                   // CB x (M1 + 1)
+    float2* tw = buf + CB * ss;                                           // M1
+    double* red = reinterpret_cast<double*>(smem + fused_fft_lds_words(g));  // kFusedThreads x 4
+    double* hs = red + 4 * kFusedThreads;                                 // ncols
+    SegSrc* src = reinterpret_cast<SegSrc*>(hs + a.ncols + (a.ncols & 1));  // 2 * CB
+    const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
+    const int ncb = min(CB, M2 - c0);
+    for (int t = tid; t < M1; t += kFusedThreads) tw[t] = g.tw1[t];
+    for (int idx = tid; idx < CB * ss; idx += kFusedThreads) buf[idx] = make_float2(0.0f, 0.0f);
+    for (int c = tid; c < a.ncols; c += kFusedThreads) hs[c] = a.h[c];
+    if (tid < 2 * ncb) src[tid] = seg_source(a, M2, S, c0, tid);
+    // x at every slot of the 2*ncb source segments, FP64.  The float4 groups are
+    // split over the threads; when there are few of them the columns are split too,
+    // over slices of threads whose sums meet in LDS in a fixed order.  A thread's
+    // first columns are loaded before the barrier that publishes h.
+    const int gps = S / 4;  // float4 groups per segment
+    const int nf = 2 * ncb * gps;
+    const int nf64 = (nf + 63) & ~63;
+    const int nslice = min(16, kFusedThreads / nf64);  // 0 or 1: no column split
+    const int slice = nslice >= 2 ? tid / nf64 : 0, f0 = nslice >= 2 ? tid % nf64 : tid;
+    const int nsl_ = nslice >= 2 ? nslice : 1;
+    float4 pre[kUpdPre];
+    bool pre_ok = false;
+    if (slice < nsl_ && f0 < nf) {
+        const int sg = f0 / gps;
+        const SegSrc d = seg_source(a, M2, S, c0, sg);
+        if (4 * (f0 - sg * gps) < d.cnt) {
+            pre_ok = true;
+            const long long p = d.pos + 4LL * (f0 - sg * gps);
+#pragma unroll
+            for (int u = 0; u < kUpdPre; ++u) {
+                const int c = slice + u * nsl_;
+                pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (c < a.ncols) pre[u] = *reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + p);
+            }
+        }
+    }
+    const double scale = *a.scale;
+    __syncthreads();
+    if (nslice >= 2) {
+        const int f = f0;
+        if (slice < nslice && f < nf) {
+            double x[4];
+            fused_accumulate(a, hs, src, gps, f, slice, nslice, x, pre, pre_ok);
+            for (int u = 0; u < 4; ++u) red[4 * tid + u] = x[u];
+        }
+        __syncthreads();
+        if (tid < nf) {
+            double x[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int sl = 0; sl < nslice; ++sl)
+                for (int u = 0; u < 4; ++u) x[u] += red[4 * (sl * nf64 + tid) + u];
+            fused_finish_group(a, src, gps, tid, x, scale, buf, ss);
+        }
+    } else {
+        for (int f = tid; f < nf; f += kFusedThreads) {
+            double x[4];
+            fused_accumulate(a, hs, src, gps, f, 0, 1, x, pre, f == tid && pre_ok);
+            fused_finish_group(a, src, gps, f, x, scale, buf, ss);
+        }
+    }
+    __syncthreads();
+    lds_fft<-1, EPT>(buf, g.st1, CB, ss, tw, tid, kFusedThreads);
+    for (int idx = tid; idx < CB * M1; idx += kFusedThreads) {
+        const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
+        if (n2 < M2) T1[(long long)k1 * M2 + n2] = cmul(buf[c * ss + k1], twiddle_mp(g, (long long)n2 * k1));
+    }
+}
+
+// Start vector p_0 of Algorithm 1 in the segment layout: element i of a seeded
+// standard normal stream at its slot, zero in the padding slots.
+__global__ void k_start_seg(float* r, SegLay lay, unsigned long long seed) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= lay.len) return;
+    const long long i = seg_natural(lay, t / lay.S, t % lay.S);
+    r[t] = i >= 0 ? gauss(seed, 0, i) : 0.0f;
+}
+
+// Ritz vectors out[i*ldo + nat(t)] = sum_c basis[c][t] P[c*k + i] of a basis in the
+// segment layout: one stored slot per thread, 16 triples per workgroup with their
+// coefficients in LDS; padding slots write nothing.
+constexpr int kRitzSegTile = 16;
+__global__ __launch_bounds__(256) void k_ritz_seg(const float* __restrict__ basis, long long ld, int ncols,
+                                                  const double* __restrict__ P, int k, float* __restrict__ out,
+                                                  long long ldo, SegLay lay) {
+    extern __shared__ double ps[];  // ncols x kRitzSegTile
+    const int i0 = blockIdx.y * kRitzSegTile;
+    const int kt = min(kRitzSegTile, k - i0);
+    for (int idx = threadIdx.x; idx < ncols * kRitzSegTile; idx += 256) {
+        const int c = idx / kRitzSegTile, i = idx - c * kRitzSegTile;
+        ps[idx] = i < kt ? P[(long long)c * k + i0 + i] : 0.0;
+    }
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= lay.len) return;
+    const long long nat = seg_natural(lay, t / lay.S, t % lay.S);
+    if (nat < 0) return;
+    double acc[kRitzSegTile];
+#pragma unroll
+    for (int i = 0; i < kRitzSegTile; ++i) acc[i] = 0.0;
+    for (int c = 0; c < ncols; ++c) {
+        const double x = basis[(long long)c * ld + t];
+#pragma unroll
+        for (int i = 0; i < kRitzSegTile; ++i) acc[i] += x * ps[c * kRitzSegTile + i];
+    }
+#pragma unroll
+    for (int i = 0; i < kRitzSegTile; ++i)
+        if (i < kt) out[(long long)(i0 + i) * ldo + nat] = (float)acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static int fused_ept(long long elems) {
+    const long long e = (elems + kFusedThreads - 1) / kFusedThreads;
+    if (e <= 4) return 4;
+    return 8;  // CB * M1 <= 8192
+}
+
+size_t fused_p3_lds(const ConvGeom& g, const SegLay& lay) {
+    return sizeof(float2) * (size_t)fused_fft_lds_words(g) + sizeof(float) * 2 * (size_t)g.CB * lay.S;
+}
+
+size_t fused_p1_lds(const ConvGeom& g, int ncols) {
+    return sizeof(float2) * (size_t)fused_fft_lds_words(g) +
+           sizeof(double) * (4 * (size_t)kFusedThreads + ncols + (ncols & 1)) + sizeof(SegSrc) * 2 * (size_t)g.CB;
+}
+
+hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a, hipStream_t s) {
+    const dim3 grid((g.M2 + g.CB - 1) / g.CB);
+    const size_t lds = fused_p3_lds(g, a.lay);
+    if (fused_ept((long long)g.CB * g.M1) == 4)
+        hipLaunchKernelGGL(k_p3_project<4>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
+    else
+        hipLaunchKernelGGL(k_p3_project<8>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s) {
+    const dim3 grid((g.M2 + g.CB - 1) / g.CB);
+    const size_t lds = fused_p1_lds(g, a.ncols);
+    if (fused_ept((long long)g.CB * g.M1) == 4)
+        hipLaunchKernelGGL(k_p1_update<4>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+    else
+        hipLaunchKernelGGL(k_p1_update<8>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+    return hipGetLastError();
+}
+
+hipError_t launch_start_seg(float* r, const SegLay& lay, unsigned long long seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_start_seg, dim3((unsigned)((lay.len + 255) / 256)), dim3(256), 0, s, r, lay, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_ritz_seg(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
+                           long long ldo, const SegLay& lay, hipStream_t s) {
+    const dim3 grid((unsigned)((lay.len + 255) / 256), (unsigned)((k + kRitzSegTile - 1) / kRitzSegTile));
+    const size_t lds = sizeof(double) * (size_t)ncols * kRitzSegTile;
+    hipLaunchKernelGGL(k_ritz_seg, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, lay);
+    return hipGetLastError();
+}
+
+hipError_t set_fused_attributes() {
+    hipError_t e = hipSuccess;
+    auto allow = [&](const void* f) {
+        const hipError_t e2 = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e2 != hipSuccess) e = e2;
+    };
+    allow(reinterpret_cast<const void*>(k_p3_project<4>));
+    allow(reinterpret_cast<const void*>(k_p3_project<8>));
+    allow(reinterpret_cast<const void*>(k_p1_update<4>));
+    allow(reinterpret_cast<const void*>(k_p1_update<8>));
+    allow(reinterpret_cast<const void*>(k_ritz_seg));
+    return e;
+}
+
+}  // namespace ssa

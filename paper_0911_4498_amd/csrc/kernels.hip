@@ -18,50 +18,10 @@
 //  * Ritz-vector assembly U_{d+1} P and V_d Q (eqs. lbdiagm1/lbdiagm2).
 #include <hip/hip_runtime.h>
 
+#include "dev_common.h"
 #include "ssa_internal.h"
 
 namespace ssa {
-
-// ---------------------------------------------------------------------------
-// small helpers
-
-__device__ __forceinline__ float2 twiddle_mp(const ConvGeom& g, long long t) {
-    const long long mask = (1LL << g.tw_shift) - 1;
-    return cmul(g.tw_hi[t >> g.tw_shift], g.tw_lo[t & mask]);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3").
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
-        const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += W0;
-        k1 += W1;
-    }
-}
-
-// Standard normal number for element t of stream `ctr` (Box-Muller on two uniforms).
-__device__ __forceinline__ float gauss(unsigned long long seed, unsigned long long ctr, long long t) {
-    uint32_t c[4] = {(uint32_t)t, (uint32_t)((unsigned long long)t >> 32), (uint32_t)ctr,
-                     (uint32_t)(ctr >> 32)};
-    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double u1 = ((double)c[0] + 1.0) * (1.0 / 4294967296.0);  // (0, 1]
-    const double u2 = (double)c[1] * (1.0 / 4294967296.0);
-    return (float)(sqrt(-2.0 * log(u1)) * cospi(2.0 * u2));
-}
 
 // ---------------------------------------------------------------------------
 // twiddle tables (FP64 angles, rounded once to FP32)
@@ -130,15 +90,6 @@ __device__ __forceinline__ float p1_value(const P1In& a, long long m, int y) {
 // memory latency (256 threads with 32 points each reach a third less).
 constexpr int kBigThreads = 1024;
 
-// Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), and each
-// XCD has its own L2.  Column blocks of passes 1 and 3 read and write runs of CB
-// complex values, so neighbouring blocks share 128-byte lines: give each XCD a
-// contiguous run of blocks so that those neighbours meet in one L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    if (nb % kXcds != 0) return b;
-    return (b % kXcds) * (nb / kXcds) + b / kXcds;
-}
 
 template <int MODE, int EPT, int NT = 256>
 __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __restrict__ T1) {
@@ -627,22 +578,6 @@ __global__ void k_start_vector(float* r, long long n, unsigned long long seed) {
 // ---------------------------------------------------------------------------
 // classical Gram-Schmidt
 
-// 4 consecutive rows t..t+3 (t a multiple of 4, t < n) of a column whose
-// allocation is padded to a multiple of 64 floats; rows >= n read as zero.
-__device__ __forceinline__ float4 rows4(const float* __restrict__ col, long long t, long long n) {
-    float4 v = *reinterpret_cast<const float4*>(col + t);
-    if (t + 3 >= n) {
-        if (t + 1 >= n) v.y = 0.0f;
-        if (t + 2 >= n) v.z = 0.0f;
-        if (t + 3 >= n) v.w = 0.0f;
-    }
-    return v;
-}
-
-__device__ __forceinline__ double dot4(float4 a, float4 b) {
-    return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
-           (double)a.w * (double)b.w;
-}
 
 // block-wide sum (any block of up to 1024 threads), fixed order, valid in every thread
 __device__ double block_sum(double v, double* sh) {
@@ -693,15 +628,14 @@ __device__ double blk_project(const float* r, long long n, const float* basis, l
 //                B entry becomes 0 and a seeded random direction, made
 //                orthogonal to the basis by two passes, continues the
 //                recurrence.
-__device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& decision) {
+//
+// hs[0..ncols] holds the column sums on entry (hs[ncols] = |r|^2); bnorm is state[0].
+__device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& decision, double bnorm) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int c = tid; c < a.ncols; c += nt) hs[c] = a.h[c];
-    __syncthreads();
     double hh = 0.0;
     for (int c = tid; c < a.ncols; c += nt) hh += hs[c] * hs[c];
     hh = block_sum(hh, sh);
-    const double rr = a.h[a.ncols];
-    const double bnorm = a.state[0];
+    const double rr = hs[a.ncols];
     double coef, scale;
     if (a.full) {
         for (int c = tid; c < a.ncols; c += nt) hs[c] = 0.0;
@@ -746,15 +680,22 @@ __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& dec
                 // breakdown: fresh direction
                 coef = 0.0;
                 const unsigned long long ctr = a.stream_ctr;
-                for (long long t = tid; t < a.n; t += nt) a.r[t] = gauss(a.seed, ctr, t);
+                for (long long t = tid; t < a.n; t += nt) {
+                    if (a.segmented) {
+                        const long long i = seg_natural(a.seg, t / a.seg.S, t % a.seg.S);
+                        a.r[t] = i >= 0 ? gauss(a.seed, ctr, i) : 0.0f;
+                    } else {
+                        a.r[t] = gauss(a.seed, ctr, t);
+                    }
+                }
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
-                    blk_project(a.r, a.n, a.basis, a.ld, a.ncols, hs, sh);
+                    blk_project(a.r, a.n, a.basis, a.ld, a.ncols_bd, hs, sh);
                     __syncthreads();
-                    blk_subtract(a.r, a.n, a.basis, a.ld, a.ncols, hs);
+                    blk_subtract(a.r, a.n, a.basis, a.ld, a.ncols_bd, hs);
                 }
                 const double rr3 = blk_project(a.r, a.n, a.basis, 0, 0, hs, sh);
-                for (int c = tid; c < a.ncols; c += nt) hs[c] = 0.0;
+                for (int c = tid; c < a.ncols_bd; c += nt) hs[c] = 0.0;
                 scale = rr3 > 0.0 ? 1.0 / sqrt(rr3) : 0.0;
                 if (tid == 0) a.state[1] += 1.0;
             }
@@ -818,28 +759,38 @@ __global__ __launch_bounds__(256) void k_cgs_colsum(ReduceArgs a) {
     if (threadIdx.x == 0) a.h[blockIdx.x] = sum;
 }
 
-// One workgroup (1024 threads): h[c] = sum over chunks of part[c][chunk]
-// (32 lanes per column, chunks contiguous, fixed order) unless k_cgs_colsum
-// has already formed it, then cgs_finish.
+// One workgroup (1024 threads): h[c] = sum over chunks of part[c][chunk] (16
+// lanes per column with their loads in flight together, then a fixed-order
+// shuffle tree), kept in LDS for cgs_finish and written out; or the sums that
+// k_cgs_colsum has already formed.
 constexpr int kReduceThreads = 1024;
+constexpr int kReduceLanes = 16;
 __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
     if (a.gate && *a.gate == 0) return;
-    __shared__ double hs[kMaxCols];
+    __shared__ double hs[kMaxCols + 1];
     __shared__ double sh[16];
     __shared__ int decision;
     const int tid = threadIdx.x;
+    const double bnorm = a.state[0];
     if (!a.presummed) {
-        for (int c = tid >> 5; c <= a.ncols; c += kReduceThreads / 32) {
+        const int l = tid % kReduceLanes;
+        for (int c = tid / kReduceLanes; c <= a.ncols; c += kReduceThreads / kReduceLanes) {
             const double* row = a.part + (long long)c * a.pstride;
             double sum = 0.0;
-            for (int ch = tid & 31; ch < a.nchunks; ch += 32) sum += row[ch];
+#pragma unroll 16
+            for (int ch = l; ch < a.nchunks; ch += kReduceLanes) sum += row[ch];
 #pragma unroll
-            for (int off = 16; off > 0; off >>= 1) sum += __shfl_down(sum, off, 32);
-            if ((tid & 31) == 0) a.h[c] = sum;
+            for (int off = kReduceLanes / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, kReduceLanes);
+            if (l == 0) {
+                hs[c] = sum;
+                a.h[c] = sum;
+            }
         }
+    } else {
+        for (int c = tid; c <= a.ncols; c += kReduceThreads) hs[c] = a.h[c];
     }
     __syncthreads();
-    cgs_finish(a, hs, sh, decision);
+    cgs_finish(a, hs, sh, decision, bnorm);
 }
 
 // out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale, FP64 accumulation.  A

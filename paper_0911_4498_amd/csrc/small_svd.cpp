@@ -14,7 +14,9 @@
 // the last row of the eigenvector matrix is carried, which is all the
 // residual bound needs: p_i[d] = beta_{d+1} q_i[d-1] / omega_i.  The final k
 // vectors come from inverse iteration on T (Wilkinson), each made orthogonal
-// to the ones before it, O(k^2 d).  The left vectors are p_i = B_d q_i / omega_i.
+// to the ones before it, O(k^2 d).  The left vectors are p_i = B_d q_i / omega_i,
+// made orthogonal to the earlier ones; where omega_i = 0 (a series of rank below k)
+// a unit vector orthogonal to them takes its place, so P stays orthonormal.
 //
 // Squaring costs relative accuracy only for omega_i below ~1e-8 omega_1, far
 // under the error of the FP32 products that produced B_d.
@@ -343,13 +345,29 @@ void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, 
         }
         std::memcpy(&q[(size_t)i * d], x.data(), sizeof(double) * d);
     }
+    double bmax = 0.0;
+    for (int r = 0; r < d; ++r) bmax = std::max({bmax, std::fabs(alpha[r + 1]), std::fabs(beta[r + 2])});
+    const int n1 = d + 1;
+    std::vector<double> pc((size_t)k * n1, 0.0), x1(n1);
+    // Gram-Schmidt of x against the left vectors 0..i-1 already chosen (two passes)
+    auto orth_prev = [&](int i, double* v) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < i; ++j) {
+                const double* pj = &pc[(size_t)j * n1];
+                double h = 0.0;
+                for (int r = 0; r < n1; ++r) h += pj[r] * v[r];
+                for (int r = 0; r < n1; ++r) v[r] -= h * pj[r];
+            }
+        double nrm = 0.0;
+        for (int r = 0; r < n1; ++r) nrm += v[r] * v[r];
+        return std::sqrt(nrm);
+    };
     for (int i = 0; i < k; ++i) {
         omega[i] = i < kk ? std::sqrt(std::max(D[order[i]], 0.0)) : 0.0;
         // Q[t][i] (row-major d x k)
         for (int t = 0; t < d; ++t) Q[(size_t)t * k + i] = i < kk ? q[(size_t)i * d + t] : 0.0;
-        // p = B q / omega, normalized (the normalization only matters when omega ~ 0)
-        double nrm = 0.0;
-        std::vector<double> p(d + 1, 0.0);
+        // p = B q / omega, normalized and kept orthogonal to the earlier left vectors
+        double* p = &pc[(size_t)i * n1];
         if (i < kk) {
             const double* qi = &q[(size_t)i * d];
             for (int r = 0; r <= d; ++r) {
@@ -357,11 +375,26 @@ void bidiag_ritz_vectors(const double* alpha, const double* beta, int d, int k, 
                 if (r < d) v += alpha[r + 1] * qi[r];
                 if (r >= 1) v += beta[r + 1] * qi[r - 1];
                 p[r] = v;
-                nrm += v * v;
             }
-            nrm = std::sqrt(nrm);
         }
-        for (int r = 0; r <= d; ++r) P[(size_t)r * k + i] = nrm > 0.0 ? p[r] / nrm : 0.0;
+        double nrm = orth_prev(i, p);
+        if (!(nrm > 1e-12 * bmax)) {
+            // omega_i = 0 (a series of rank below k): B q vanishes and any unit vector
+            // orthogonal to the other left vectors completes the SVD of B
+            for (int c = d; c >= 0; --c) {
+                std::fill(x1.begin(), x1.end(), 0.0);
+                x1[c] = 1.0;
+                nrm = orth_prev(i, x1.data());
+                if (nrm >= 0.5) {
+                    std::copy(x1.begin(), x1.end(), p);
+                    break;
+                }
+            }
+        }
+        for (int r = 0; r <= d; ++r) {
+            p[r] = nrm > 0.0 ? p[r] / nrm : 0.0;
+            P[(size_t)r * k + i] = p[r];
+        }
     }
 }
 

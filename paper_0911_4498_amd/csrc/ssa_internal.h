@@ -64,9 +64,55 @@ struct P3Out {
     long long Nx, Lx, Kx;  // the y-dimension in (pitch, L, K) and the x-dimension here
 };
 
+// Segment layout of a Lanczos vector on the fused single-series path.  A vector
+// whose natural element i (i < n) is output y[o + i] of a product's inverse FFT
+// is stored in the order pass 3 produces it: segment s = 2*n2 + e (n2 < M2,
+// e < 2) holds the y indices m = 2*(M2*n1 + n2) + e with n1 = seg_lo + t at slot
+// t < S, so the pass-3 workgroup of columns [c0, c0 + CB) owns the contiguous
+// slots [2*c0*S, 2*(c0 + CB)*S).  Slots past a segment's count hold zero, so
+// inner products over whole segments equal those over the natural vector.  The
+// reversed input of the next product maps every pass-1 column onto whole
+// segments too (y index m' = N - 1 - m), which lets pass 1 finish the vector.
+struct SegLay {
+    long long o, n;  // y index of natural element 0; natural length
+    int M1, M2;      // the FFT split
+    int S;           // slots per segment, a multiple of 4
+    long long len;   // stored length 2 * M2 * S
+};
+
+__host__ __device__ inline long long seg_lo(const SegLay& l, int n2, int e) {
+    const long long a = l.o - 2LL * n2 - e, step = 2LL * l.M2;
+    return a <= 0 ? 0 : (a + step - 1) / step;
+}
+
+__host__ __device__ inline int seg_count(const SegLay& l, int n2, int e) {
+    const long long b = l.o + l.n - 1 - 2LL * n2 - e;
+    if (b < 0) return 0;
+    long long hi = b / (2LL * l.M2);
+    if (hi > l.M1 - 1) hi = l.M1 - 1;
+    const long long lo = seg_lo(l, n2, e);
+    return hi >= lo ? (int)(hi - lo + 1) : 0;
+}
+
+// natural index held by slot t of segment s, or -1 for a padding slot
+__host__ __device__ inline long long seg_natural(const SegLay& l, long long s, long long t) {
+    const int n2 = (int)(s >> 1), e = (int)(s & 1);
+    if (t >= seg_count(l, n2, e)) return -1;
+    return 2 * ((long long)l.M2 * (seg_lo(l, n2, e) + t) + n2) + e - l.o;
+}
+
+// stored position of natural element i < n
+__host__ __device__ inline long long seg_position(const SegLay& l, long long i) {
+    const long long m = l.o + i, c = m >> 1;
+    const int e = (int)(m & 1), n2 = (int)(c % l.M2);
+    return (2LL * n2 + e) * l.S + (c / l.M2 - seg_lo(l, n2, e));
+}
+
 struct ReduceArgs {
     double* part;
     int nchunks, pstride, ncols;
+    int ncols_bd;       // a fresh direction after a breakdown is made orthogonal to this many
+                        // columns (>= ncols; one-sided projects the V side against none)
     float* r;
     long long n;
     const float* basis;
@@ -82,7 +128,82 @@ struct ReduceArgs {
     int* dgks_flag;     // non-null: a second pass is left to the gated launches (flag set to 1)
     const int* gate;    // non-null: the launch does nothing unless *gate != 0
     double tol_bd;      // breakdown threshold relative to state[0]
+    int segmented;      // 1: r and the basis are in layout `seg` (a fresh direction fills
+    SegLay seg;         //    the natural slots only; padding slots stay zero)
     long long chunk_rows;  // rows per projection workgroup (a multiple of kProjRows); nchunks of them
+};
+
+// Pass 3 of a product fused with the three-term term and the projection partials
+// (k_p3_project): r = y - coef * prev in layout lay, part[c * pstride + b] =
+// <basis_c, r> over workgroup b's slots for c < ncols and |r|^2 for c = ncols.
+struct P3Seg {
+    SegLay lay;
+    float* r;
+    const float* prev;   // same layout as r; may be null (no three-term term)
+    const double* coef;  // device scalar (used with prev)
+    const float* basis;  // ncols columns, leading dimension ld, layout lay
+    long long ld;
+    int ncols;
+    double* part;
+    int pstride;
+};
+
+// The update of the previous vector fused with pass 1 of the next product
+// (k_p1_update): x = (r - basis h) * scale in layout lay (natural length n = the
+// product's input length) is written to out and transformed as the reversed,
+// zero-padded input w[m] = x[n - 1 - m].
+struct P1Seg {
+    SegLay lay;
+    long long N;         // series length: slot of y index m' holds w[N - 1 - m']
+    const float* r;
+    const float* basis;
+    long long ld;
+    int ncols;
+    const double* h;     // ncols coefficients (device)
+    const double* scale; // device scalar
+    float* out;          // stored length lay.len; must not alias r or the ncols columns
+};
+
+// Record of the single-series stopping test (doubles, device; the host reads only
+// this): header fields, then the k eigenvalues of B_d^T B_d, the Ritz values of the
+// previous test and the residual bounds, each kstride long.
+enum {
+    kChkHavePrev = 0,  // a previous test exists (stability of the Ritz values)
+    kChkDone = 1,      // 1 once a test ended the solve
+    kChkD = 2,         // Lanczos steps d of the deciding test
+    kChkConv = 3,      // 1 if the stopping rule held (or the Krylov space was exhausted)
+    kChkNonfinite = 4, // 1 if the series holds NaN or Inf
+    kChkRestarts = 5,  // breakdown restarts so far
+    kChkDgks = 6,      // DGKS second passes so far
+    kChkJJ = 7,        // steps of the latest test
+    kChkHdr = 8
+};
+constexpr double kResidFloorDev = 1e-5;  // residuals of omega_i < 1e-5 omega_1 judged against 1e-5 omega_1
+
+struct LzCheck {
+    const double* alpha;  // Algorithm 1 scalars, 1-based: alpha[1..jj+1], beta[2..jj+1]
+    const double* beta;
+    int jj, k, dcap;      // test on B_jj; k triples; step cap
+    long long rmin;       // min(L, K): B is exact once jj reaches it
+    double tol;
+    double* rec;          // the record (kChkHdr + 3 kstride doubles)
+    const double* state;  // solver state: [1] restarts, [2] DGKS passes
+    const double* nonfinite;  // nonzero: the series holds NaN/Inf (may be null)
+    double* scr;          // 2 kstride + 2 k dstride doubles
+    int kstride;
+    long long dstride;    // >= jj + 2
+};
+
+struct LzRitz {
+    const double* alpha;
+    const double* beta;
+    const double* rec;    // d and the eigenvalues of the deciding test
+    int k, kstride;       // P ((d+1) x k) and Q (d x k), row-major, row stride kstride
+    long long dstride;
+    double* P;
+    double* Q;
+    double* sigma;        // k values (device)
+    double* scr;          // 8 k dstride doubles
 };
 
 constexpr int kEdgeCnt = 2048;   // Hankelization entries with <= this many terms are summed directly
@@ -133,7 +254,21 @@ hipError_t launch_cgs_update(const float* r, const float* basis, long long ld, i
                              const int* gate, hipStream_t s);
 hipError_t launch_ritz(const float* basis, long long ld, int ncols, const double* P, int k,
                        float* out, long long ldo, long long n, hipStream_t s);
+hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a, hipStream_t s);
+hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s);
+hipError_t launch_start_seg(float* r, const SegLay& lay, unsigned long long seed, hipStream_t s);
+hipError_t launch_ritz_seg(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
+                           long long ldo, const SegLay& lay, hipStream_t s);
+hipError_t set_fused_attributes();
+hipError_t launch_lz_check(const LzCheck& a, hipStream_t s);
+hipError_t launch_lz_ritz(const LzRitz& a, int d, hipStream_t s);
 hipError_t set_kernel_attributes();
+// set_kernel_attributes() once per process; its result afterwards (api.cpp)
+hipError_t kernel_attributes_once();
+// The automatic FFT geometry of a 1D plan for a series of length N: the schedule that
+// ssa_embed_plan picks without schedule options (twiddle pointers left unset); false when no
+// admissible transform length exists (api.cpp).
+bool auto_geometry(long long N, ConvGeom* g);
 
 // host small eigen/singular solver (small_svd.cpp)
 // Ritz values of the (d+1) x d lower bidiagonal B_d (alpha[1..d] on the

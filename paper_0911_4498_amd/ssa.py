@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libssa_hip.so")
 
 SSA_OK = 0
 SSA_WARN_NOT_CONVERGED = 1
+SSA_WARN_BREAKDOWN = 2
 SSA_EINVAL = -1
 SSA_ENOMEM = -2
 SSA_ENONFINITE = -3
@@ -29,13 +30,14 @@ _c_p = ctypes.c_void_p
 class SsaOpts(ctypes.Structure):
     _fields_ = [("d_max", ctypes.c_int), ("check_every", ctypes.c_int), ("tol", ctypes.c_double),
                 ("seed", ctypes.c_ulonglong), ("fft_m1", ctypes.c_int), ("fft_cb", ctypes.c_int),
-                ("restart_keep", ctypes.c_int), ("reorth", ctypes.c_int), ("fft_mp", ctypes.c_longlong)]
+                ("restart_keep", ctypes.c_int), ("reorth", ctypes.c_int), ("fft_mp", ctypes.c_longlong),
+                ("unfused", ctypes.c_int)]
 
 
 class SsaInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int), ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("dgks_passes", ctypes.c_int), ("steps_run", ctypes.c_int), ("resid", ctypes.c_double * 64),
-                ("thick_restarts", ctypes.c_int)]
+                ("thick_restarts", ctypes.c_int), ("status", ctypes.c_int)]
 
 
 class SsaPlanDesc(ctypes.Structure):
@@ -44,7 +46,8 @@ class SsaPlanDesc(ctypes.Structure):
                 ("cb", ctypes.c_int)]
 
 
-EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_truncated_svd",
+EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec",
+            "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
             "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read", "ssa_profile_sample",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
@@ -58,7 +61,7 @@ BATCH_PROF_CLASSES = ("init", "conv", "cgs", "check", "ritz", "hankel")
 
 # kernel classes of ssa_profile_read (enum ssa_prof_class)
 PROF_CLASSES = ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz",
-                "recon_pass1", "recon_pass2", "recon_pass3", "embed", "dgks2")
+                "recon_pass1", "recon_pass2", "recon_pass3", "embed", "dgks2", "check")
 
 _lib = None
 
@@ -187,7 +190,7 @@ class Plan:
 
     def __init__(self, N: int, L: int, k_max: int, d_max: int = 0, check_every: int = 0,
                  tol: float = 0.0, seed: int = 0, device=None, stream=None, fft_m1: int = 0, fft_cb: int = 0,
-                 restart_keep: int = 0, reorth: int = 0, fft_mp: int = 0):
+                 restart_keep: int = 0, reorth: int = 0, fft_mp: int = 0, unfused: int = 0):
         import torch
         self._torch = torch
         lib = load()
@@ -195,7 +198,7 @@ class Plan:
         self.N, self.L, self.K = int(N), int(L), int(N) - int(L) + 1
         self.k_max = int(k_max)
         opts = SsaOpts(int(d_max), int(check_every), float(tol), int(seed), int(fft_m1), int(fft_cb),
-                       int(restart_keep), int(reorth), int(fft_mp))
+                       int(restart_keep), int(reorth), int(fft_mp), int(unfused))
         ws = ctypes.c_size_t(0)
         h = _c_p()
         _check(self._create(opts, ws, h), "ssa_embed_plan")

@@ -4,32 +4,34 @@ Tolerances (FP32 products, FP64 Lanczos scalars):
   * singular values: relative error <= 1e-5 for sigma_i >= 1e-2 sigma_1; below
     that, absolute error <= 1e-7 sigma_1 (the size of the FP32 rounding of one
     product X v, which bounds what any FP32 matvec can resolve);
-  * vectors: largest principal-angle sine <= 1e-4 per cluster, because
-    individual vectors inside a cluster are not unique.  Two neighbouring
-    oracle values belong to one cluster when their relative gap
-    (sigma_i - sigma_{i+1}) / sigma_i is below 1e-3.  The perturbations the FP32
-    path introduces (rounding the series, FFT products, FP32 vector storage)
-    act like a perturbation E of norm ~1e-7 |X|_2 with no preferred direction,
-    so the rotation of an isolated singular subspace, to first order
-    |U_perp^T E V_c| / gap, stays far below 1e-4 at these gaps; the tests measure
-    it rather than assume a worst case;
+  * vectors: largest principal-angle sine per cluster, because individual
+    vectors inside a cluster are not unique.  Two neighbouring oracle values
+    belong to one cluster when their relative gap (sigma_i - sigma_{i+1}) /
+    sigma_i is below 1e-3;
   * reconstructions: max-abs error <= 1e-5 |F|_inf per isolated triple, and per
     cluster (sum over the cluster) otherwise.
 A cluster that straddles k (its last member beyond k) is compared by its
 singular values only, and so are exactly zero triples (sigma <= 1e-6 sigma_1:
 their vectors span an arbitrary part of the null space).
 
-FP32 resolution (resolved_clusters).  The method computes its products with
-FP32 FFTs, and for noise-floor triples whose relative gaps are ~1e-3 those
-products alone rotate a subspace by ~1e-4 (a CPU model with float32 library
-FFTs reproduces the GPU's figures, e.g. 1.40e-4 against 1.39e-4).  So the
-clusters are refined by measurement: fp32_model runs Algorithm 1 on the CPU
-with float32 FFT products, FP32 vector storage and FP64 Gram-Schmidt, and every
-relative-gap cluster that this model itself does not reproduce to half the
-angle tolerance is merged with its neighbour across the smaller gap (and the
-test repeats).  The merged cluster is still compared at 1e-4 (or by sigma only
-if it then reaches past k).  Clusters the FP32 method resolves keep the 1e-4
-check; none is exempted by a worst-case bound.
+Angle tolerance per cluster (angle_tolerance).  A perturbation E of X turns the
+singular vector u_i, to first order, by (sigma_i e_ji + sigma_j e'_ij) /
+(sigma_i^2 - sigma_j^2) towards u_j (e_ji = u_j^T E v_i, e'_ij = v_j^T E^T u_i),
+and by the part of E v_i outside the range of X divided by sigma_i.  For an E with
+no preferred direction and coefficients of size eta sigma_1 that gives a subspace
+rotation of about eta G_c with
+    G_c^2 = sum_{i in c} [ sum_{j not in c} sigma_1^2 ((sigma_i - sigma_j)^-2 +
+            (sigma_i + sigma_j)^-2) + |L - K| sigma_1^2 / sigma_i^2 ]
+over the oracle values at hand.  The FP32 products (rounding of the series, of the
+FFTs and of the stored vectors) act as such an E: the FP32 model below measures
+eta <= 6.3e-10 on the test workloads (largest on noise-floor clusters whose gaps are
+~1e-6 sigma_1), and the HIP path's four-step FFT rounds differently from the
+library FFT, so the tests use eta = FP32_ROTATION = 2e-9.  Each cluster is compared
+at max(1e-4, FP32_ROTATION G_c): signal triples and well separated clusters keep
+1e-4; near-degenerate noise-floor clusters get what FP32 arithmetic resolves.  A
+cluster whose tolerance passes 0.1 is not resolved at all and is compared by its
+singular values only.  test_parity_rules pins G_c against exact perturbations and
+the constant against the FP32 model.
 """
 import scipy.fft
 import numpy as np
@@ -39,6 +41,8 @@ SIGMA_FLOOR = 1e-7
 ANGLE_SIN = 1e-4
 RECON_REL = 1e-5
 CLUSTER_GAP = 1e-3
+FP32_ROTATION = 2e-9     # per-coefficient size of the FP32 perturbation, in units of sigma_1
+ANGLE_UNRESOLVED = 0.1   # above this estimate a cluster is compared by sigma only
 
 
 def frobenius(f, L):
@@ -67,11 +71,12 @@ def clusters(s_ref, k, fro=None):
     return out
 
 
-def fp32_model(f, L, k, d=None, seed=1, dtype=np.float32):
+def fp32_model(f, L, k, d=None, seed=1, dtype=np.float32, one_sided=False):
     """The k leading triples of Algorithm 1 run with float32 FFT products (library FFT),
     FP32 storage of the Lanczos vectors and FP64 Gram-Schmidt (two passes, full
-    reorthogonalization), the Ritz triples taken from an FP64 SVD of B_d.  A model of the
-    arithmetic of the FP32 method, used only to measure what that arithmetic resolves."""
+    reorthogonalization; with one_sided only the basis of length min(L, K)), the Ritz
+    triples taken from an FP64 SVD of B_d.  A model of the arithmetic of the FP32 method,
+    used only to measure what that arithmetic resolves."""
     f = np.asarray(f, dtype=np.float64)
     N = f.size
     K = N - L + 1
@@ -99,7 +104,7 @@ def fp32_model(f, L, k, d=None, seed=1, dtype=np.float32):
     U[:, 0] = st(p / be[1])
     for j in range(1, d + 1):
         x = st(conv(U[:, j - 1], Li - 1, Ki) - (be[j] * V[:, j - 2] if j >= 2 else 0.0))
-        for _ in range(2):
+        for _ in range(0 if one_sided else 2):
             x = x - V[:, :j - 1] @ (V[:, :j - 1].T @ x)
         al[j] = np.linalg.norm(x)
         V[:, j - 1] = st(x / al[j])
@@ -119,41 +124,23 @@ def fp32_model(f, L, k, d=None, seed=1, dtype=np.float32):
     return om[:k], Um, Vm
 
 
-def resolved_clusters(s_ref, U_ref, V_ref, k, model):
-    """Relative-gap clusters of the first k oracle triples, each merged with its nearer
-    neighbour while the FP32 model (sigma, U, V with >= k columns) does not reproduce its
-    subspace to ANGLE_SIN / 2.  U_ref, V_ref: (n, >= k) oracle vectors as columns."""
-    _, Um, Vm = model
-    km = Um.shape[1]
-    cl = clusters(s_ref, k)
-    changed = True
-    while changed:
-        changed = False
-        for idx, c in enumerate(cl):
-            if max(c) >= min(k, km) or s_ref[c[0]] <= 1e-6 * s_ref[0]:
-                continue
-            sm = max(subspace_sin(U_ref[:, c], Um[:, c]), subspace_sin(V_ref[:, c], Vm[:, c]))
-            if sm <= ANGLE_SIN / 2:
-                continue
-            lo_gap = s_ref[c[0] - 1] - s_ref[c[0]] if c[0] > 0 else np.inf
-            hi_gap = s_ref[c[-1]] - s_ref[c[-1] + 1] if c[-1] + 1 < len(s_ref) else np.inf
-            if lo_gap < hi_gap:
-                cl[idx - 1] = cl[idx - 1] + c
-                del cl[idx]
-            elif idx + 1 < len(cl):
-                cl[idx] = c + cl[idx + 1]
-                del cl[idx + 1]
-            else:  # the next cluster lies beyond k
-                cl[idx] = c + [c[-1] + 1]
-            changed = True
-            break
-    return cl
+def rotation_factor(s_ref, c, n_rows, n_cols):
+    """G_c of the module docstring: the first-order rotation of the singular subspace of
+    cluster c per unit coefficient (in sigma_1) of a perturbation, from the oracle values
+    s_ref (all those at hand) and the shape n_rows x n_cols of X."""
+    s = np.asarray(s_ref, dtype=np.float64)
+    s1 = s[0]
+    rest = np.delete(s, c)
+    g2 = 0.0
+    for i in c:
+        g2 += float(np.sum((s1 / (s[i] - rest)) ** 2) + np.sum((s1 / (s[i] + rest)) ** 2))
+        g2 += abs(n_rows - n_cols) * (s1 / s[i]) ** 2
+    return float(np.sqrt(g2))
 
 
-def reference_clusters(f, L, k, s_ref, U_ref, V_ref):
-    """The clusters a test compares for the series f: relative-gap clusters refined by
-    the FP32 model (resolved_clusters); the model gets as many triples as U_ref has."""
-    return resolved_clusters(s_ref, U_ref, V_ref, k, fp32_model(f, L, U_ref.shape[1]))
+def angle_tolerance(s_ref, c, n_rows, n_cols):
+    """The largest principal-angle sine allowed for cluster c."""
+    return max(ANGLE_SIN, FP32_ROTATION * rotation_factor(s_ref, c, n_rows, n_cols))
 
 
 def sigma_errors(s_gpu, s_ref):
@@ -179,20 +166,53 @@ def subspace_sin(A, B):
 
 
 def compare_svd(s_gpu, U_gpu, V_gpu, s_ref, U_ref, V_ref, k, fro=None, min_rel=1e-6, cl=None):
-    """U/V as (n, k) arrays (columns = vectors).  cl: the clusters to compare (default:
-    the relative-gap clusters).  Returns a report dict; asserts."""
-    worst_sin = 0.0
+    """U/V as (n, k) arrays (columns = vectors; U_ref, V_ref give the shape of X and s_ref
+    may hold more than k values).  cl: the clusters to compare (default: the relative-gap
+    clusters).  Each is held to angle_tolerance.  Returns a report dict; asserts."""
+    worst_sin, worst_ratio, loosened, unresolved = 0.0, 0.0, 0, 0
     rel = assert_sigma(s_gpu[:k], s_ref[:k])
+    n_rows, n_cols = U_ref.shape[0], V_ref.shape[0]
     for c in (cl if cl is not None else clusters(s_ref, k, fro)):
         if max(c) >= k:
             continue  # straddles k: sigma only
         if s_ref[c[0]] <= min_rel * s_ref[0]:
             continue  # null space: vectors arbitrary
+        tol = angle_tolerance(s_ref, c, n_rows, n_cols)
+        if tol > ANGLE_UNRESOLVED:
+            unresolved += 1
+            continue
+        loosened += tol > ANGLE_SIN
         su = subspace_sin(U_ref[:, c], U_gpu[:, c])
         sv = subspace_sin(V_ref[:, c], V_gpu[:, c])
         worst_sin = max(worst_sin, su, sv)
-        assert su <= ANGLE_SIN and sv <= ANGLE_SIN, f"cluster {c}: sin(theta) u={su:.2e} v={sv:.2e}"
-    return {"sigma_rel": rel, "sin_theta": worst_sin}
+        worst_ratio = max(worst_ratio, su / tol, sv / tol)
+        assert su <= tol and sv <= tol, f"cluster {c}: sin(theta) u={su:.2e} v={sv:.2e} > {tol:.2e}"
+    return {"sigma_rel": rel, "sin_theta": worst_sin, "sin_over_tol": worst_ratio,
+            "loosened": int(loosened), "unresolved": unresolved}
+
+
+RESID_REL = 1e-6
+# One-sided reorthogonalization leaves the basis of length max(L, K) to the three-term
+# recurrence alone: in FP32 it loses orthogonality to ~1e-4, and the Ritz vectors taken
+# from it carry components along converged directions, so |X v - sigma u| (v on that
+# side when L <= K) reaches ~1e-5 sigma_1 on noise-floor triples.  The FP32 model gives
+# 9.5e-6 on c1 (N = 1500, L = 750, k = 20); the bar keeps a factor 3.
+RESID_REL_ONE_SIDED = 3e-5
+
+
+def compare_residuals(X, s_gpu, U_gpu, V_gpu, k, rel=RESID_REL):
+    """Every returned triple is a singular triple of X up to FP32 rounding:
+    |X v_i - sigma_i u_i| and |X^T u_i - sigma_i v_i| <= rel sigma_1 (FP64 products
+    with the explicit trajectory matrix X).  Unlike the angles this holds for any
+    cluster structure.  U/V as (n, k) arrays."""
+    s = np.asarray(s_gpu[:k], dtype=np.float64)
+    U = np.asarray(U_gpu[:, :k], dtype=np.float64)
+    V = np.asarray(V_gpu[:, :k], dtype=np.float64)
+    r1 = np.linalg.norm(X @ V - U * s, axis=0)
+    r2 = np.linalg.norm(X.T @ U - V * s, axis=0)
+    worst = float(max(r1.max(), r2.max()) / s[0])
+    assert worst <= rel, f"residual {worst:.2e} sigma_1 (triples {np.nonzero(np.maximum(r1, r2) > rel * s[0])[0]})"
+    return worst
 
 
 def compare_recon(rec_gpu, rec_ref, f_inf):

@@ -46,7 +46,7 @@ def compare_one(f, L, k, sig, U, V, rec, dense=True):
         p0 = inputs.start_vector(L, 7)
         sA, UA, VA, _, conv = oracle.lanczos_svd(f, L, kr, p0, tol=1e-12)
         assert conv
-    cl = parity.reference_clusters(f, L, k, sA, UA, VA)
+    cl = parity.clusters(sA, k)
     rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, cl=cl)
     groups = [c for c in cl if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
     if groups:  # white noise can leave one cluster straddling k: then sigma and subspaces only

@@ -60,7 +60,7 @@ def parity_vs_oracle(ssa, f, L, k, tier):
     else:
         sA, UA, VA, steps, conv = oracle.lanczos_svd(f, L, kr, inputs.start_vector(L, 11), tol=1e-12)
         assert conv
-    cl = parity.reference_clusters(f, L, k, sA, UA, VA)
+    cl = parity.clusters(sA, k)
     groups = [c for c in cl if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
     plan, s, U, V, info, rec = solve(ssa, f, L, k, groups)
     say(f"  steps={info.steps} converged={info.converged} restarts={info.restarts} dgks={info.dgks_passes}")

@@ -166,10 +166,12 @@ def check_against_dense(ssa, f, L, k, extra=4, groups_of_clusters=True, **kw):
     sg = s.cpu().numpy()
     Ug = U.cpu().numpy().T.astype(np.float64)
     Vg = V.cpu().numpy().T.astype(np.float64)
-    fro = parity.frobenius(f, L)
-    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, fro)
+    cl = parity.clusters(sA, k)
+    rep = parity.compare_svd(sg, Ug, Vg, sA, UA, VA, k, cl=cl)
+    rel = parity.RESID_REL_ONE_SIDED if kw.get("reorth", 0) == 1 else parity.RESID_REL
+    rep["resid"] = parity.compare_residuals(hankel(np.asarray(f, dtype=np.float64), L), sg, Ug, Vg, k, rel)
     # reconstructions: isolated triples and whole clusters
-    groups = [c for c in parity.clusters(sA, k, fro) if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
+    groups = [c for c in cl if max(c) < k and sA[c[0]] > 1e-6 * sA[0]]
     rg = plan.reconstruct(s, U, V, groups).cpu().numpy()
     ro = oracle.reconstruct(N, L, sA[:k], UA[:, :k], VA[:, :k], groups)
     rep["recon_err"] = parity.compare_recon(rg, ro, np.abs(f).max())
@@ -233,15 +235,24 @@ def test_svd_one_sided_reorth(ssa, N, L, k, kind):
     assert rep["converged"] == 1
 
 
-def test_thick_restart_off_is_plain_algorithm(ssa):
-    """restart_keep with a cap that the solve never reaches leaves the result bitwise equal
-    to the plain solver's."""
-    say("thick restart unused")
+def test_thick_restart_off_and_unfused_are_the_plain_algorithm(ssa):
+    """restart_keep with a cap that the solve never reaches runs the plain Algorithm 1 (on
+    the six-launch path with the host-side solve of B), and so does ssa_opts.unfused: the
+    same steps and the same triples as the fused plain solver up to rounding order, each
+    within the parity tolerances of the dense oracle."""
+    say("thick restart unused / unfused path")
     f = inputs.c1_series(1000)
     _, s0, U0, V0, i0 = run_gpu(ssa, f, 500, 10)
     _, s1, U1, V1, i1 = run_gpu(ssa, f, 500, 10, d_max=200, restart_keep=20)
-    assert i0.thick_restarts == 0 and i1.thick_restarts == 0 and i0.steps == i1.steps
-    assert torch.equal(s0, s1) and torch.equal(U0, U1) and torch.equal(V0, V1)
+    _, s2, U2, V2, i2 = run_gpu(ssa, f, 500, 10, unfused=1)
+    assert i0.thick_restarts == 0 and i1.thick_restarts == 0 and i0.steps == i1.steps == i2.steps
+    sA, UA, VA = oracle.ssa_dense(f, 500, 14)
+    for s, U, V in ((s0, U0, V0), (s1, U1, V1), (s2, U2, V2)):
+        rep = parity.compare_svd(s.cpu().numpy(), U.cpu().numpy().T.astype(np.float64),
+                                 V.cpu().numpy().T.astype(np.float64), sA, UA, VA, 10)
+        say(f"  {rep}")
+    np.testing.assert_allclose(s1.cpu().numpy(), s0.cpu().numpy(), rtol=1e-6)
+    np.testing.assert_allclose(s2.cpu().numpy(), s0.cpu().numpy(), rtol=1e-6)
 
 
 def test_svd_window_longer_than_lag_count(ssa):
@@ -250,24 +261,51 @@ def test_svd_window_longer_than_lag_count(ssa):
     check_against_dense(ssa, inputs.c1_series(600), 450, 8)
 
 
-def test_exact_rank_series(ssa):
+def assert_orthonormal_rows(A, tol=1e-5):
+    A = A.cpu().numpy().astype(np.float64)
+    G = A @ A.T
+    err = np.abs(G - np.eye(A.shape[0])).max()
+    assert err <= tol, err
+    return err
+
+
+@pytest.mark.parametrize("reorth", [0, 1])
+def test_exact_rank_series(ssa, reorth):
     """Finite-rank series: a sinusoid gives two nonzero singular values, an exponential
-    one; asking for more triples exercises the breakdown restart."""
-    say("exact rank")
+    one; asking for more triples exercises the breakdown restart.  With one-sided
+    reorthogonalization the V side breaks down first (its Krylov space has the rank r,
+    the U side r + 1), and its fresh direction must still be orthogonal to every earlier
+    v: the relations X v_i = sigma_i u_i and orthonormal U and V are checked for every
+    triple, including those past the rank."""
+    say(f"exact rank reorth={reorth}")
     N, L = 999, 500
+    K = N - L + 1
     f = inputs.sinusoid(N, 10.0, 1.3, 0.4)
-    plan, s, U, V, info = run_gpu(ssa, f, L, 4)
-    s = s.cpu().numpy()
-    expect = 1.3 * np.sqrt(L * (N - L + 1)) / 2
-    np.testing.assert_allclose(s[:2], [expect, expect], rtol=1e-5)
-    assert np.all(s[2:] <= 1e-5 * expect), s
-    assert np.all(np.isfinite(U.cpu().numpy())) and np.all(np.isfinite(V.cpu().numpy()))
+    for k in (4, 9):
+        plan, s, U, V, info = run_gpu(ssa, f, L, k, reorth=reorth)
+        assert info.converged == 1 and info.restarts >= 1 and info.status == ssa.SSA_WARN_BREAKDOWN
+        s = s.cpu().numpy()
+        expect = 1.3 * np.sqrt(L * K) / 2
+        np.testing.assert_allclose(s[:2], [expect, expect], rtol=1e-5)
+        assert np.all(s[2:] <= 1e-5 * expect), s
+        assert np.all(np.isfinite(U.cpu().numpy())) and np.all(np.isfinite(V.cpu().numpy()))
+        eu, ev = assert_orthonormal_rows(U), assert_orthonormal_rows(V)
+        Xv = np.array([oracle.matvec(f, L, v) for v in V.cpu().numpy().astype(np.float64)])
+        res = np.abs(Xv - s[:, None] * U.cpu().numpy().astype(np.float64)).max() / s[0]
+        say(f"  sinusoid k={k}: restarts={info.restarts} |UtU-I|={eu:.1e} |VtV-I|={ev:.1e} resid/s1={res:.1e}")
+        assert res <= 1e-5
     f = inputs.geometric(300, 1.7, 0.99)
-    plan, s, U, V, info = run_gpu(ssa, f, 120, 3)
-    s = s.cpu().numpy()
-    sA, _, _ = oracle.ssa_dense(f, 120, 3)
-    np.testing.assert_allclose(s[0], sA[0], rtol=1e-5)
-    assert np.all(s[1:] <= 1e-5 * s[0])
+    for k in (3, 6):
+        plan, s, U, V, info = run_gpu(ssa, f, 120, k, reorth=reorth)
+        s = s.cpu().numpy()
+        sA, _, _ = oracle.ssa_dense(f, 120, 3)
+        np.testing.assert_allclose(s[0], sA[0], rtol=1e-5)
+        assert np.all(s[1:] <= 1e-5 * s[0])
+        eu, ev = assert_orthonormal_rows(U), assert_orthonormal_rows(V)
+        Xv = np.array([oracle.matvec(f, 120, v) for v in V.cpu().numpy().astype(np.float64)])
+        res = np.abs(Xv - s[:, None] * U.cpu().numpy().astype(np.float64)).max() / s[0]
+        say(f"  geometric k={k}: restarts={info.restarts} |UtU-I|={eu:.1e} |VtV-I|={ev:.1e} resid/s1={res:.1e}")
+        assert res <= 1e-5
 
 
 def test_paper_rank5_series_reconstruction(ssa):
@@ -343,6 +381,7 @@ def test_determinism(ssa):
 # --- the N=100000 workload at full size ---------------------------------------------
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle.json")
+GOLDEN_VECTORS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_vectors.npz")
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
@@ -377,6 +416,22 @@ def test_c2_full_size(ssa, d_max, keep, reorth, sched):
     say(f"  sigma rel err max {np.max(np.abs(sg - s_ref[:k]) / s_ref[:k]):.2e}")
     parity.assert_sigma(sg, s_ref[:k])
     fro = parity.frobenius(f, L)
+    # vectors: every cluster of near-equal oracle values that does not straddle k, against
+    # the oracle's own singular vectors (tier B, stored)
+    vec = np.load(GOLDEN_VECTORS)
+    Uo, Vo = vec["U"].astype(np.float64).T, vec["V"].astype(np.float64).T
+    Ugk = U.cpu().numpy().T.astype(np.float64)
+    Vgk = V.cpu().numpy().T.astype(np.float64)
+    checked = []
+    for c in parity.clusters(s_ref, k):
+        if max(c) >= k:
+            continue
+        su = parity.subspace_sin(Uo[:, c], Ugk[:, c])
+        sv = parity.subspace_sin(Vo[:, c], Vgk[:, c])
+        say(f"  cluster {c}: sin(theta) u={su:.2e} v={sv:.2e}")
+        assert su <= parity.ANGLE_SIN and sv <= parity.ANGLE_SIN, (c, su, sv)
+        checked.extend(c)
+    assert checked == list(range(19)), checked  # triples 19.. form one cluster that reaches past k
     groups = [c for c in parity.clusters(s_ref, k, fro) if max(c) < k]
     rec = plan.reconstruct(s, U, V, groups).cpu().numpy()
     idx = np.array(g["sample_index"])
@@ -407,6 +462,9 @@ def test_c2_full_size(ssa, d_max, keep, reorth, sched):
     assert worst <= 1e-5
     G = Ug @ Ug.T
     assert np.abs(G - np.eye(k)).max() <= 1e-5
+    G = Vg @ Vg.T
+    say(f"  |UtU - I| = {np.abs(Ug @ Ug.T - np.eye(k)).max():.1e}, |VtV - I| = {np.abs(G - np.eye(k)).max():.1e}")
+    assert np.abs(G - np.eye(k)).max() <= 1e-5
 
 
 def test_profile_classes(ssa):
@@ -415,17 +473,25 @@ def test_profile_classes(ssa):
     launch in three still gives a time for the sampled classes."""
     say("profile classes")
     f = inputs.c1_series(1000)
-    plan = ssa.Plan(1000, 500, 10)
-    plan.profile_enable(every=3)
-    s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 10)
-    plan.reconstruct(s, U, V, [[0, 1], [2]])
-    pr = plan.profile_read()
-    for c in ("pass1", "pass2", "pass3", "cgs_dots", "cgs_reduce", "cgs_update", "ritz", "recon_pass2"):
-        n, ms, b = pr[c]
-        assert n > 0 and ms > 0 and b > 0, (c, pr[c])
-    assert pr["pass2"][0] >= 2 * info.steps_run - 1
-    assert pr["dgks2"][0] == 0  # short vectors: the second pass stays in the finish
-    plan.close()
+    for unfused in (0, 1):
+        plan = ssa.Plan(1000, 500, 10, unfused=unfused)
+        plan.profile_enable(every=3)
+        s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 10)
+        plan.reconstruct(s, U, V, [[0, 1], [2]])
+        pr = plan.profile_read()
+        # the fused path folds the projection into pass 3 and the update into pass 1 (only
+        # the start vector's norm is a projection launch of its own)
+        classes = ("pass1", "pass2", "pass3", "cgs_reduce", "check", "ritz", "recon_pass2")
+        if unfused:
+            classes += ("cgs_dots", "cgs_update")
+        for c in classes:
+            n, ms, b = pr[c]
+            assert n > 0 and ms > 0 and b > 0, (unfused, c, pr[c])
+        if not unfused:
+            assert pr["cgs_update"][0] == 0 and pr["cgs_dots"][0] == 1, pr
+        assert pr["pass2"][0] >= 2 * info.steps_run - 1
+        assert pr["dgks2"][0] == 0  # short vectors: the second pass stays in the finish
+        plan.close()
     # one-sided with U longer than 16384 rows: every U-side step adds three gated launches
     N, L = 40000, 20000
     f = inputs.c2_series(N)
