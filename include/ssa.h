@@ -176,6 +176,29 @@ int ssa_embed(ssa_plan plan, const double* series_dev);
 int ssa_matvec(ssa_plan plan, int transpose, const float* x_dev, float* y_dev);
 
 /*
+ * ssa_matvec_static -- the product of ssa_matvec for callers that cannot
+ * allocate device memory or bind a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  One call computes the
+ * operator of the series (ssa_embed) and then y = X x (transpose = 0; x has
+ * K = N - L + 1 entries, y gets L) or y = X^T x (transpose = 1; x has L, y gets
+ * K), with the FFT schedule ssa_embed_plan picks without options, so y has the
+ * same bits as ssa_embed + ssa_matvec on such a plan.
+ *   series_dev: N doubles; x_dev, y_dev: FP32 device vectors, caller-owned.
+ *   hip_stream: hipStream_t as void* (NULL = the default stream).
+ * Every intermediate (twiddle tables, the series' spectral operator, two FFT
+ * buffers) lives in a static device array of the library, 16.25 MiB per GPU,
+ * held until the process ends; the call allocates nothing.  Limit: N <= 2^20.
+ * All calls on one GPU share that array and it keeps the last call's contents:
+ * calls that overlap on one GPU (different streams or threads) race and must be
+ * serialized by the caller.  The series is not checked for NaN/Inf (no host
+ * synchronization); non-finite input gives non-finite output.
+ * Asynchronous on hip_stream.  Errors: SSA_EINVAL (null pointers, N <= 2,
+ * L outside (1, N)), SSA_ENOMEM (N > 2^20), SSA_EDEVICE.
+ */
+int ssa_matvec_static(const double* series_dev, long long N, long long L, int transpose,
+                      const float* x_dev, float* y_dev, void* hip_stream);
+
+/*
  * ssa_truncated_svd -- Sec. 2.2 via Sec. 3 + 4: the k leading singular
  * triples of X, sigma descending.
  *   series_dev: N doubles (device).  N, L must equal the plan's.

@@ -46,7 +46,7 @@ class SsaPlanDesc(ctypes.Structure):
                 ("cb", ctypes.c_int)]
 
 
-EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec",
+EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed", "ssa_matvec", "ssa_matvec_static",
             "ssa_truncated_svd",
             "ssa_reconstruct", "ssa_plan_describe", "ssa_plan_destroy", "ssa_status_str",
             "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read", "ssa_profile_sample",
@@ -87,6 +87,7 @@ def load():
     lib.ssa_plan_bind.argtypes = [_c_p, _c_p, ctypes.c_size_t, _c_p]
     lib.ssa_embed.argtypes = [_c_p, _c_p]
     lib.ssa_matvec.argtypes = [_c_p, ctypes.c_int, _c_p, _c_p]
+    lib.ssa_matvec_static.argtypes = [_c_p, _c_ll, _c_ll, ctypes.c_int, _c_p, _c_p, _c_p]
     lib.ssa_truncated_svd.argtypes = [_c_p, _c_p, _c_ll, _c_ll, ctypes.c_int, _c_p, _c_p, _c_p,
                                       ctypes.POINTER(SsaInfo)]
     lib.ssa_reconstruct.argtypes = [_c_p, _c_p, _c_p, _c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_int, _c_p]
@@ -309,6 +310,26 @@ class Plan:
                                       ctypes.cast(mem_a, _c_p), m, out.data_ptr())
         _check(rc, "ssa_reconstruct")
         return out
+
+
+def matvec_static(f, L: int, x, transpose: bool = False, device=None, stream=None):
+    """X x (x has K entries) or X^T x (x has L entries) by ``ssa_matvec_static``: no plan and no
+    workspace, the library's static device array holds every intermediate.  FP32 on the device."""
+    import torch
+    lib = load()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    f = torch.as_tensor(f, dtype=torch.float64, device=dev).contiguous()
+    N, L = int(f.numel()), int(L)
+    K = N - L + 1
+    n_in, n_out = (L, K) if transpose else (K, L)
+    x = torch.as_tensor(x, dtype=torch.float32, device=dev).contiguous()
+    if x.numel() != n_in:
+        raise ValueError("vector length does not match")
+    y = torch.empty(max(n_out, 1), dtype=torch.float32, device=dev)
+    _check(lib.ssa_matvec_static(_c_p(f.data_ptr()), N, L, 1 if transpose else 0, _c_p(x.data_ptr()),
+                                 _c_p(y.data_ptr()), _c_p(st.cuda_stream)), "ssa_matvec_static")
+    return y[:n_out]
 
 
 def tune_fft(N: int, L: int, series=None, reps: int = 20, max_rows: int = 512, device=None, stream=None):

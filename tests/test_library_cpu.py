@@ -126,6 +126,20 @@ def test_status_codes_and_info_layout():
     assert re.search(r"SSA_WARN_BREAKDOWN\s*=\s*2", text)
 
 
+def test_matvec_static_host_checks():
+    """ssa_matvec_static rejects bad arguments and series beyond its static array (N > 2^20)
+    before it touches the device."""
+    lib = _built()
+    p8 = ctypes.c_void_p(256)
+    assert lib.ssa_matvec_static(None, 100, 40, 0, p8, p8, None) == ssa.SSA_EINVAL
+    assert lib.ssa_matvec_static(p8, 100, 40, 0, None, p8, None) == ssa.SSA_EINVAL
+    assert lib.ssa_matvec_static(p8, 100, 40, 0, p8, None, None) == ssa.SSA_EINVAL
+    assert lib.ssa_matvec_static(p8, 2, 1, 0, p8, p8, None) == ssa.SSA_EINVAL
+    assert lib.ssa_matvec_static(p8, 100, 100, 1, p8, p8, None) == ssa.SSA_EINVAL
+    assert lib.ssa_matvec_static(p8, 100, 1, 1, p8, p8, None) == ssa.SSA_EINVAL
+    assert lib.ssa_matvec_static(p8, (1 << 20) + 1, 1000, 0, p8, p8, None) == ssa.SSA_ENOMEM
+
+
 def test_fft_schedule_override():
     """ssa_opts.fft_m1 / fft_cb select the split of M' = M1*M2 and the columns per workgroup;
     invalid overrides are rejected."""
