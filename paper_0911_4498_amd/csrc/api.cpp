@@ -139,7 +139,8 @@ struct ssa_plan_s {
     int pstride, nchunks_max;
     size_t ws_bytes;
     size_t o_ab, o_tw1, o_tw2, o_twlo, o_twhi, o_t1, o_t2, o_U, o_V, o_r, o_part, o_h, o_sc, o_alpha,
-        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2, o_rot, o_rec, o_lzscr;
+        o_beta, o_state, o_P, o_Q, o_flag, o_grp, o_rt1, o_rt2, o_rot, o_rec, o_lzscr, o_snap;
+    int nsnap;         // half-steps with a state snapshot slot (2 doubles each)
     int nrec;          // doubles of the stopping-test record (kChkHdr + 3 kcols)
     long long dstride; // d_max + 2: per-triple length of the device stopping-test scratch
     size_t grp_ints;
@@ -154,6 +155,10 @@ struct ssa_plan_s {
     int* h_grp = nullptr;
     hipEvent_t grp_done = nullptr;
     hipEvent_t chk_ev[2] = {nullptr, nullptr};
+    // the stopping test runs on its own stream, beside the Lanczos steps
+    hipStream_t chk_stream = nullptr;
+    hipEvent_t ab_ev = nullptr;  // the scalars of the tested step are written
+    const double* stop_dev = nullptr;  // during a fused solve: the test's "done" flag
     std::vector<double> work;
     // optional per-kernel-class timing (HIP events around the launches of the
     // classes in prof_mask; launch counts and bytes are kept for all classes)
@@ -212,6 +217,8 @@ void layout(ssa_plan p) {
     p->dstride = p->d_max + 2;
     p->o_rec = take(sizeof(double) * (size_t)p->nrec);
     p->o_lzscr = take(sizeof(double) * (8 * (size_t)p->kcols * p->dstride + 2 * (size_t)p->kcols));
+    p->nsnap = 2 * p->d_max + 4;
+    p->o_snap = take(sizeof(double) * 2 * (size_t)p->nsnap);
     p->ws_bytes = o;
 }
 
@@ -240,10 +247,12 @@ struct ProfScope {
     int cls;
     double bytes;
     hipEvent_t e0 = nullptr;
-    ProfScope(ssa_plan p_, int cls_, double bytes_) : p(p_), cls(cls_), bytes(bytes_) {
+    hipStream_t st;
+    ProfScope(ssa_plan p_, int cls_, double bytes_, hipStream_t st_ = nullptr)
+        : p(p_), cls(cls_), bytes(bytes_), st(st_ ? st_ : p_->stream) {
         if (p->prof_on && (p->prof_mask >> cls & 1u) && p->prof_seen[cls]++ % p->prof_every == 0) {
             e0 = next_event(p);
-            if (e0) (void)hipEventRecord(e0, p->stream);
+            if (e0) (void)hipEventRecord(e0, st);
         }
     }
     ~ProfScope() {
@@ -252,7 +261,7 @@ struct ProfScope {
         if (p->prof_on && e0) {
             hipEvent_t e1 = next_event(p);
             if (e1) {
-                (void)hipEventRecord(e1, p->stream);
+                (void)hipEventRecord(e1, st);
                 p->prof_pairs[cls].push_back({e0, e1});
             }
         }
@@ -335,6 +344,7 @@ int orthonormalize(ssa_plan p, float* basis, long long ld, int ncols, long long 
     a.state = at<double>(p, p->o_state);
     a.seed = p->seed;
     a.stream_ctr = ctr;
+    a.snap = ctr < (unsigned long long)p->nsnap ? at<double>(p, p->o_snap) + 2 * ctr : nullptr;
     a.track = track;
     a.full = ncols >= n ? 1 : 0;
     a.tol_bd = kBreakdownTol;
@@ -420,12 +430,14 @@ int fused_finish(ssa_plan p, const float* basis, long long ld, int ncols, int nc
     a.state = at<double>(p, p->o_state);
     a.seed = p->seed;
     a.stream_ctr = ctr;
+    a.snap = ctr < (unsigned long long)p->nsnap ? at<double>(p, p->o_snap) + 2 * ctr : nullptr;
     a.track = track;
     a.full = ncols >= lay.n ? 1 : 0;
     a.tol_bd = kBreakdownTol;
     a.segmented = 1;
     a.seg = lay;
     a.presummed = nchunks > kColsumChunks ? 1 : 0;
+    a.stop = p->stop_dev;
     const long long grid2_rows = (long long)(p->onesided ? kGrid2ChunksOneSided : kColsumChunks) * kProjRows;
     const bool grid2 = ncols > 0 && lay.n > grid2_rows;
     int* flag2 = at<int>(p, p->o_flag) + 8;
@@ -562,6 +574,8 @@ hipError_t kernel_attributes_once() {
         g_attr_err = set_kernel_attributes();
         const hipError_t e2 = set_fused_attributes();
         if (g_attr_err == hipSuccess) g_attr_err = e2;
+        const hipError_t e3 = set_lz_attributes();
+        if (g_attr_err == hipSuccess) g_attr_err = e3;
     });
     return g_attr_err;
 }
@@ -732,6 +746,8 @@ int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_strea
         if (hipEventCreateWithFlags(&p->grp_done, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
         for (hipEvent_t& e : p->chk_ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
+        if (hipEventCreateWithFlags(&p->ab_ev, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
+        if (hipStreamCreateWithFlags(&p->chk_stream, hipStreamNonBlocking) != hipSuccess) return SSA_EDEVICE;
     }
     p->ws = static_cast<char*>(workspace_dev);
     p->stream = static_cast<hipStream_t>(hip_stream);
@@ -809,6 +825,18 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     if (rc != SSA_OK) return rc;
 
     const int d_cap = (int)std::min<long long>(p->d_max, std::min(Li, Ki));
+    // Steps enqueued after the deciding test (the host learns of it one test later) do
+    // no work on the fused path: its product and reduction kernels return at once once
+    // the test's record says done.  Those steps only write columns and scalars past d.
+    ConvGeom gl = g;
+    if (devchk && p->fused) {
+        gl.stop = rec + kChkDone;
+        p->stop_dev = gl.stop;
+    }
+    struct StopReset {
+        ssa_plan p;
+        ~StopReset() { p->stop_dev = nullptr; }
+    } stop_reset{p};
     const size_t abn = (size_t)(p->d_max + 3);
     double* h_ab[2] = {p->h_scal, p->h_scal + 2 * abn};  // alpha | beta, double-buffered
     double* h_P = p->h_scal + 4 * abn;
@@ -842,13 +870,13 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         }
         return false;
     };
-    int pend_jj = -1, pend_buf = 0, cur_buf = 0;
+    int pend_jj = -1, pend_buf = 0, cur_buf = 0, last_chk = -1;
     for (int j = 1;; ++j) {
         // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
         const int ncv = p->onesided ? 0 : j - 1;
         if (p->fused) {
             // finish u_j; r_j = X^T u_j - beta_j v_{j-1}; its partials against V_{j-1}; alpha_j
-            rc = fused_product(p, g, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU, p->layV,
+            rc = fused_product(p, gl, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU, p->layV,
                                j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j, V, p->ldV, ncv);
             if (rc != SSA_OK) return rc;
             rc = fused_finish(p, V, p->ldV, ncv, j - 1, p->layV, p->nblk, alpha + j, 1, 2ULL * j);
@@ -864,8 +892,12 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         steps_run = jj;
         bool stop = false;
         if (devchk && jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
-            // the test of one check point runs on the device while the host has the next
-            // steps enqueued; the host reads its record one check point later
+            // the test of one check point runs on the check stream, beside the next
+            // Lanczos steps (it reads only alpha/beta up to this step and the state
+            // snapshot of this step's reduction); the host reads its record one check
+            // point later
+            SSA_TRY(hipEventRecord(p->ab_ev, s));
+            SSA_TRY(hipStreamWaitEvent(p->chk_stream, p->ab_ev, 0));
             LzCheck c{};
             c.alpha = alpha;
             c.beta = beta;
@@ -875,18 +907,19 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
             c.rmin = std::min(Li, Ki);
             c.tol = p->tol;
             c.rec = rec;
-            c.state = at<double>(p, p->o_state);
+            c.snap = at<double>(p, p->o_snap) + 2 * (2 * (long long)j);  // the V half of step j
             c.nonfinite = at<double>(p, p->o_flag);
             c.scr = at<double>(p, p->o_lzscr);
             c.kstride = p->kcols;
             c.dstride = p->dstride;
             {
-                ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (jj + 2));
-                SSA_TRY(launch_lz_check(c, s));
+                ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (jj + 2), p->chk_stream);
+                SSA_TRY(launch_lz_check(c, p->chk_stream));
             }
             double* hr = p->h_rec + (size_t)cur_buf * p->nrec;
-            SSA_TRY(hipMemcpyAsync(hr, rec, sizeof(double) * p->nrec, hipMemcpyDeviceToHost, s));
-            SSA_TRY(hipEventRecord(p->chk_ev[cur_buf], s));
+            SSA_TRY(hipMemcpyAsync(hr, rec, sizeof(double) * p->nrec, hipMemcpyDeviceToHost, p->chk_stream));
+            SSA_TRY(hipEventRecord(p->chk_ev[cur_buf], p->chk_stream));
+            last_chk = cur_buf;
             if (pend_jj >= 0) {
                 SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
                 stop = p->h_rec[(size_t)pend_buf * p->nrec + kChkDone] != 0.0;
@@ -923,7 +956,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         if (stop) break;
         if (p->fused) {
             // finish v_j; p_j = X v_j - alpha_j u_j; its partials against U_j; beta_{j+1}
-            rc = fused_product(p, g, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV, p->layU,
+            rc = fused_product(p, gl, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV, p->layU,
                                U + (long long)(j - 1) * p->ldU, alpha + j, U, p->ldU, j);
             if (rc != SSA_OK) return rc;
             rc = fused_finish(p, U, p->ldU, j, j, p->layU, p->nblk, beta + j + 1, 1, 2ULL * j + 1);
@@ -942,6 +975,9 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     if (devchk) {
         // stream-ordered from here: the Ritz coefficients and vectors are enqueued and the
         // call returns; the outputs are complete when the stream has run them
+        // everything after this reads the record and the test's scratch, and the next
+        // call rewrites them: order the main stream after every test enqueued
+        SSA_TRY(hipStreamWaitEvent(s, p->chk_ev[last_chk], 0));
         if (fin_rec[kChkNonfinite] != 0.0) {
             p->embedded = 0;  // the operator holds the non-finite series: unusable
             return SSA_ENONFINITE;
@@ -1262,6 +1298,11 @@ void ssa_plan_destroy(ssa_plan p) {
         (void)hipEventDestroy(p->grp_done);
     }
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->chk_stream) {
+        (void)hipStreamSynchronize(p->chk_stream);
+        (void)hipStreamDestroy(p->chk_stream);
+    }
+    if (p->ab_ev) (void)hipEventDestroy(p->ab_ev);
     for (hipEvent_t e : p->chk_ev)
         if (e) (void)hipEventDestroy(e);
     if (p->h_scal) (void)hipHostFree(p->h_scal);

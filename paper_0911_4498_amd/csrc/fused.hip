@@ -46,6 +46,7 @@ __host__ __device__ inline int fused_fft_lds_words(const ConvGeom& g) {
 // it, so their latency hides behind the column FFT.
 template <int EPT>
 __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const float2* __restrict__ T2, P3Seg a) {
+    if (g.stop && *g.stop != 0.0) return;
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int kWaves = kFusedThreads / 64;
@@ -217,6 +218,7 @@ __device__ __forceinline__ void fused_finish_group(const P1Seg& a, const SegSrc*
 
 template <int EPT>
 __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a, float2* __restrict__ T1) {
+    if (g.stop && *g.stop != 0.0) return;
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x;
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
@@ -320,7 +322,18 @@ __global__ __launch_bounds__(256) void k_ritz_seg(const float* __restrict__ basi
     double acc[kRitzSegTile];
 #pragma unroll
     for (int i = 0; i < kRitzSegTile; ++i) acc[i] = 0.0;
-    for (int c = 0; c < ncols; ++c) {
+    // eight columns' loads in flight at a time: the loop is bound by their latency
+    int c = 0;
+    for (; c + 8 <= ncols; c += 8) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = basis[(long long)(c + u) * ld + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int i = 0; i < kRitzSegTile; ++i) acc[i] += (double)x[u] * ps[(c + u) * kRitzSegTile + i];
+    }
+    for (; c < ncols; ++c) {
         const double x = basis[(long long)c * ld + t];
 #pragma unroll
         for (int i = 0; i < kRitzSegTile; ++i) acc[i] += x * ps[c * kRitzSegTile + i];

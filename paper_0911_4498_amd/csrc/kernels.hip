@@ -186,6 +186,7 @@ template <int EPT, int NT = 256>
 __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
                                                       const float2* __restrict__ T1,
                                                       float2* __restrict__ T2) {
+    if (g.stop && *g.stop != 0.0) return;
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int M2 = g.M2;
@@ -525,6 +526,58 @@ __global__ __launch_bounds__(256) void k_recon_edges(const double* __restrict__ 
     out[(long long)grp * ldo + n] = (float)(acc / (double)(a1 - a0 + 1));
 }
 
+// The same sums for long series (min(L, K) > kEdgeCnt: the 2 kEdgeCnt positions of the
+// two ends), a tile of kEdgeTile positions per workgroup: the stretch of u_i and v_i the
+// tile needs is staged in LDS once per member, and kEdgeSlices threads share each
+// position's sum over a (a = a0 + slice, a0 + slice + kEdgeSlices, ...), meeting in a
+// fixed order at the end.
+constexpr int kEdgeTile = 16;
+constexpr int kEdgeSlices = 16;  // kEdgeTile * kEdgeSlices = 256 threads
+__global__ __launch_bounds__(256) void k_recon_edges_tiled(const double* __restrict__ sigma,
+                                                           const float* __restrict__ U, long long ldu,
+                                                           const float* __restrict__ V, long long ldv,
+                                                           const int* __restrict__ offs,
+                                                           const int* __restrict__ members, long long N,
+                                                           long long L, long long K, float* __restrict__ out,
+                                                           long long ldo) {
+    __shared__ float us[kEdgeCnt + kEdgeTile];
+    __shared__ float vs[kEdgeCnt + kEdgeTile];
+    __shared__ double red[kEdgeSlices][kEdgeTile];
+    const int grp = blockIdx.y, tid = threadIdx.x;
+    const int nl = tid % kEdgeTile, sl = tid / kEdgeTile;
+    const long long idx0 = (long long)blockIdx.x * kEdgeTile;  // tiles never straddle the two ends
+    const long long n0 = idx0 < kEdgeCnt ? idx0 : N - 2LL * kEdgeCnt + idx0;
+    const long long n = n0 + nl;
+    // the stretch of u and v the tile's positions read
+    const long long amin = n0 - K + 1 > 0 ? n0 - K + 1 : 0;
+    const long long amax = n0 + kEdgeTile - 1 < L - 1 ? n0 + kEdgeTile - 1 : L - 1;
+    const long long bmin = n0 - amax > 0 ? n0 - amax : 0;
+    const long long bmax = n0 + kEdgeTile - 1 - amin < K - 1 ? n0 + kEdgeTile - 1 - amin : K - 1;
+    const long long a0 = n - K + 1 > 0 ? n - K + 1 : 0;
+    const long long a1 = n < L - 1 ? n : L - 1;
+    double acc = 0.0;
+    for (int mi = offs[grp]; mi < offs[grp + 1]; ++mi) {
+        const int i = members[mi];
+        const float* u = U + (long long)i * ldu;
+        const float* v = V + (long long)i * ldv;
+        __syncthreads();  // the previous member's reads are done
+        for (long long a = amin + tid; a <= amax; a += 256) us[a - amin] = u[a];
+        for (long long b = bmin + tid; b <= bmax; b += 256) vs[b - bmin] = v[b];
+        __syncthreads();
+        double sum = 0.0;
+        for (long long a = a0 + sl; a <= a1; a += kEdgeSlices) sum += (double)us[a - amin] * (double)vs[n - a - bmin];
+        acc += sigma[i] * sum;
+    }
+    red[sl][nl] = acc;
+    __syncthreads();
+    if (sl == 0) {
+        double tot = 0.0;
+#pragma unroll
+        for (int q = 0; q < kEdgeSlices; ++q) tot += red[q][nl];
+        out[(long long)grp * ldo + n] = (float)(tot / (double)(a1 - a0 + 1));
+    }
+}
+
 // The same for a 2D array (Nx x Ny, window Lx x Ly, U and V compressed row by
 // row): every position whose count cnt_x(i) cnt_y(j) is at most kEdgeCnt is
 // recomputed as sum_i sigma_i sum_{a+c=i, b+d=j} U_i[a, b] V_i[c, d] / count.
@@ -767,6 +820,7 @@ constexpr int kReduceThreads = 1024;
 constexpr int kReduceLanes = 16;
 __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
     if (a.gate && *a.gate == 0) return;
+    if (a.stop && *a.stop != 0.0) return;
     __shared__ double hs[kMaxCols + 1];
     __shared__ double sh[16];
     __shared__ int decision;
@@ -791,6 +845,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
     }
     __syncthreads();
     cgs_finish(a, hs, sh, decision, bnorm);
+    if (a.snap && threadIdx.x == 0) {  // thread 0 made every state update
+        a.snap[0] = a.state[1];
+        a.snap[1] = a.state[2];
+    }
 }
 
 // out[t] = (r[t] - sum_c basis[c][t] h[c]) * scale, FP64 accumulation.  A
@@ -1050,8 +1108,14 @@ hipError_t launch_recon_edges(const double* sigma, const float* U, long long ldu
                               const int* offs, const int* members, int ng, long long N, long long L, long long K,
                               float* out, long long ldo, hipStream_t s) {
     const long long lmin = L < K ? L : K;
-    const long long ne = lmin <= kEdgeCnt ? N : 2LL * kEdgeCnt;
-    const dim3 grid((unsigned)((ne + 255) / 256), (unsigned)ng);
+    if (lmin > kEdgeCnt) {
+        static_assert(kEdgeCnt % kEdgeTile == 0, "edge tiles must not straddle the two ends");
+        const dim3 grid((unsigned)(2 * kEdgeCnt / kEdgeTile), (unsigned)ng);
+        hipLaunchKernelGGL(k_recon_edges_tiled, grid, dim3(256), 0, s, sigma, U, ldu, V, ldv, offs, members, N, L,
+                           K, out, ldo);
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)((N + 255) / 256), (unsigned)ng);
     hipLaunchKernelGGL(k_recon_edges, grid, dim3(256), 0, s, sigma, U, ldu, V, ldv, offs, members, N, L, K, out, ldo);
     return hipGetLastError();
 }

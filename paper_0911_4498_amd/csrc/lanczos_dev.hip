@@ -11,9 +11,10 @@
 //  * k_lz_decide applies the stopping rule and writes a small record, the only
 //    data the host reads back;
 //  * k_lz_invit (one workgroup per triple) turns the final eigenvalues into
-//    eigenvectors q_i by inverse iteration, and k_lz_orth (one wave) makes them
-//    orthonormal and forms P = B Q Omega^-1, completed to an orthonormal set where
-//    omega = 0.
+//    eigenvectors q_i by inverse iteration, and k_lz_orth makes them orthonormal
+//    and forms P = B Q Omega^-1, completed to an orthonormal set where omega = 0
+//    (the _lds versions hold every work array in LDS; the plain ones, for bases too
+//    long for that, work in global memory).
 // The Lanczos scalars never leave the device.
 #include <hip/hip_runtime.h>
 
@@ -149,8 +150,8 @@ __global__ void k_lz_decide(LzCheck a) {
     }
     rec[kChkHavePrev] = 1.0;
     rec[kChkJJ] = (double)n;
-    rec[kChkRestarts] = a.state[1];
-    rec[kChkDgks] = a.state[2];
+    rec[kChkRestarts] = a.snap[0];
+    rec[kChkDgks] = a.snap[1];
     const bool bad = a.nonfinite && *a.nonfinite != 0.0;
     if (bad) rec[kChkNonfinite] = 1.0;
     const bool exhausted = n >= a.rmin;
@@ -268,6 +269,254 @@ __global__ __launch_bounds__(64) void k_lz_orth(LzRitz a) {
     for (int i = lane; i < k; i += 64) a.sigma[i] = i < kk ? sqrt(fmax(lam[i], 0.0)) : 0.0;
 }
 
+// ---- the same Ritz coefficients with every work array in LDS ----------------------
+// One eigenvector solve is a chain of dependent divisions; with its arrays in global
+// memory each step also waits for a memory round trip.  These versions keep D, E, the
+// iterate and the factors in LDS and carry the running row in registers.
+
+constexpr int kInvitArrays = 8;           // D, E, x and the factor rows A, 1/A, Bv, U2, F
+constexpr size_t kRitzLdsMax = 64 * 1024; // larger bases take the global-memory kernels
+constexpr int kOrthThreads = 1024;
+constexpr int kOrthWaves = kOrthThreads / 64;
+
+size_t invit_lds_bytes(int d) { return (sizeof(double) * kInvitArrays + 1) * (size_t)d; }
+size_t orth_lds_bytes(int d, int k) {
+    const size_t kk = (size_t)(k < d ? k : d);
+    return sizeof(double) * (kk * (size_t)d + kk * (size_t)(d + 1) + (size_t)k + kOrthWaves + 2 * (size_t)(d + 2));
+}
+
+// LU factorization of T - lam I (T = diagonal D, off-diagonal E) with partial pivoting,
+// a zero pivot replaced by eps |T|: the elimination of shifted_solve with the row being
+// eliminated carried in registers.  Row i of U goes to A (pivot; RA = its reciprocal),
+// Bv and U2 (the fill-in of a row swap); F[i] is the multiplier and Sw[i] marks a swap.
+// The factors do not depend on the right-hand side, so every inverse-iteration step
+// reuses them (the same arithmetic as refactoring each time).
+__device__ __forceinline__ void tri_factor(const double* __restrict__ D, const double* __restrict__ E, int n,
+                                           double lam, double tnorm, double* __restrict__ A,
+                                           double* __restrict__ RA, double* __restrict__ Bv,
+                                           double* __restrict__ U2, double* __restrict__ F,
+                                           unsigned char* __restrict__ Sw) {
+    const double tiny = 2.220446049250313e-16 * (tnorm > 0.0 ? tnorm : 1.0);
+    double ai = D[0] - lam, bi = n > 1 ? E[0] : 0.0;
+#pragma unroll 4
+    for (int i = 0; i + 1 < n; ++i) {
+        const double ci = E[i];
+        const double an = D[i + 1] - lam;  // next row, not yet touched
+        const double bn = i + 2 < n ? E[i + 1] : 0.0;
+        if (fabs(ai) >= fabs(ci)) {
+            if (ai == 0.0) ai = tiny;
+            const double r = fast_rcp(ai);
+            const double f = ci * r;
+            A[i] = ai;
+            RA[i] = r;
+            Bv[i] = bi;
+            U2[i] = 0.0;
+            F[i] = f;
+            Sw[i] = 0;
+            ai = an - f * bi;
+            bi = bn;
+        } else {  // rows i and i + 1 swap
+            const double r = fast_rcp(ci);
+            const double f = ai * r;
+            A[i] = ci;
+            RA[i] = r;
+            Bv[i] = an;
+            U2[i] = bn;
+            F[i] = f;
+            Sw[i] = 1;
+            ai = bi - f * an;
+            bi = -f * bn;
+        }
+    }
+    if (ai == 0.0) ai = tiny;
+    A[n - 1] = ai;
+    RA[n - 1] = fast_rcp(ai);
+}
+
+// x <- (T - lam I)^{-1} x with the factors of tri_factor.
+__device__ __forceinline__ void tri_apply(int n, const double* __restrict__ RA, const double* __restrict__ Bv,
+                                          const double* __restrict__ U2, const double* __restrict__ F,
+                                          const unsigned char* __restrict__ Sw, double* __restrict__ x) {
+    double xi = x[0];
+#pragma unroll 4
+    for (int i = 0; i + 1 < n; ++i) {
+        const double xn = x[i + 1];
+        if (Sw[i]) {
+            x[i] = xn;
+            xi = xi - F[i] * xn;
+        } else {
+            x[i] = xi;
+            xi = xn - F[i] * xi;
+        }
+    }
+    double x1 = xi * RA[n - 1];  // x[i + 1] and x[i + 2] of the back substitution
+    x[n - 1] = x1;
+    if (n < 2) return;
+    double x2 = x1;
+    x1 = (x[n - 2] - Bv[n - 2] * x1) * RA[n - 2];
+    x[n - 2] = x1;
+#pragma unroll 4
+    for (int i = n - 3; i >= 0; --i) {
+        const double v = (x[i] - Bv[i] * x1 - U2[i] * x2) * RA[i];
+        x[i] = v;
+        x2 = x1;
+        x1 = v;
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Inverse iteration for Ritz triple i = blockIdx.x (one wave): 4 solves from the fixed
+// start of k_lz_invit, each normalized; the vector goes to scr + i * 5 * dstride.
+__global__ __launch_bounds__(64) void k_lz_invit_lds(LzRitz a) {
+    extern __shared__ double sm[];
+    const int d = (int)a.rec[kChkD], i = blockIdx.x, lane = threadIdx.x;
+    if (i >= d) return;
+    const double lam = a.rec[kChkHdr + i];
+    double* D = sm;
+    double* E = D + d;
+    double* x = E + d;
+    double* A = x + d;
+    double* RA = A + d;
+    double* Bv = RA + d;
+    double* U2 = Bv + d;
+    double* F = U2 + d;
+    unsigned char* Sw = reinterpret_cast<unsigned char*>(F + d);
+    double tn = 0.0;
+    for (int t = lane; t < d; t += 64) {
+        const double al = a.alpha[t + 1], be = a.beta[t + 2];
+        D[t] = al * al + be * be;
+        E[t] = t + 1 < d ? a.alpha[t + 2] * a.beta[t + 2] : 0.0;
+        tn = fmax(tn, fabs(D[t]) + 2.0 * fabs(E[t]));
+        x[t] = 1.0 + 0.5 * sin(0.7 * (t + 1) + 1.3 * (i + 1));
+    }
+    tn = wave_max(tn);
+    __syncthreads();
+    if (lane == 0) tri_factor(D, E, d, lam, tn, A, RA, Bv, U2, F, Sw);
+    __syncthreads();
+    for (int it = 0; it < 4; ++it) {
+        if (lane == 0) tri_apply(d, RA, Bv, U2, F, Sw, x);
+        __syncthreads();
+        double nrm = sqrt(wave_dot(x, x, d, lane));
+        const bool bad = !(nrm > 0.0) || !isfinite(nrm);
+        for (int t = lane; t < d; t += 64) x[t] = bad ? (t == i ? 1.0 : 0.0) : x[t] / nrm;
+        __syncthreads();
+    }
+    double* out = a.scr + (long long)i * 5 * a.dstride;
+    for (int t = lane; t < d; t += 64) out[t] = x[t];
+}
+
+// Sum over the workgroup in a fixed order (wave sums, then the kOrthWaves partials).
+__device__ __forceinline__ double orth_block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kOrthWaves; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// y -= sum_{p < m} <v_p, y> v_p, twice (classical Gram-Schmidt with one
+// reorthogonalization), for the m vectors v_p = V + p * len in LDS.
+__device__ __forceinline__ void orth_against(double* y, const double* V, int m, int len, double* hv) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int q = wave; q < m; q += kOrthWaves) {
+            const double h = wave_dot(V + (long long)q * len, y, len, lane);
+            if (lane == 0) hv[q] = h;
+        }
+        __syncthreads();
+        for (int t = tid; t < len; t += kOrthThreads) {
+            double v = y[t];
+            for (int q = 0; q < m; ++q) v -= hv[q] * V[(long long)q * len + t];
+            y[t] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// k_lz_orth with the vectors in LDS and the projections of one step in parallel.
+__global__ __launch_bounds__(kOrthThreads) void k_lz_orth_lds(LzRitz a) {
+    extern __shared__ double sm[];
+    const int tid = threadIdx.x, k = a.k;
+    const int d = (int)a.rec[kChkD];
+    const double* lam = a.rec + kChkHdr;
+    const int kk = k < d ? k : d;
+    double* Xq = sm;                        // kk vectors of length d
+    double* Pl = Xq + (long long)kk * d;    // kk vectors of length d + 1
+    double* hv = Pl + (long long)kk * (d + 1);
+    double* red = hv + k;
+    double* al = red + kOrthWaves;  // alpha[0 .. d+1], beta[0 .. d+1]
+    double* be = al + d + 2;
+    for (int t = tid; t < d + 2; t += kOrthThreads) {
+        al[t] = a.alpha[t];
+        be[t] = a.beta[t];
+    }
+    for (int i = 0; i < kk; ++i)
+        for (int t = tid; t < d; t += kOrthThreads) Xq[(long long)i * d + t] = a.scr[(long long)i * 5 * a.dstride + t];
+    __syncthreads();
+    double bm = 0.0;
+    for (int t = tid; t < d; t += kOrthThreads) bm = fmax(bm, fmax(fabs(al[t + 1]), fabs(be[t + 2])));
+    bm = wave_max(bm);
+    if ((tid & 63) == 0) red[tid >> 6] = bm;
+    __syncthreads();
+    double bmax = 0.0;
+    for (int w = 0; w < kOrthWaves; ++w) bmax = fmax(bmax, red[w]);
+    __syncthreads();
+    for (int i = 0; i < kk; ++i) {
+        double* xi = Xq + (long long)i * d;
+        orth_against(xi, Xq, i, d, hv);
+        double ss = 0.0;
+        for (int t = tid; t < d; t += kOrthThreads) ss += xi[t] * xi[t];
+        const double nrm = sqrt(orth_block_sum(ss, red));
+        for (int t = tid; t < d; t += kOrthThreads) {
+            const double v = nrm > 0.0 ? xi[t] / nrm : 0.0;
+            xi[t] = v;
+            a.Q[(long long)t * a.kstride + i] = v;
+        }
+        __syncthreads();
+        double* pi = Pl + (long long)i * (d + 1);
+        double pn = 0.0;
+        for (int c = d + 1;; --c) {  // c = d + 1: B q itself; then the unit vectors e_d, e_{d-1}, ...
+            for (int r = tid; r <= d; r += kOrthThreads) {
+                double v = 0.0;
+                if (c == d + 1) {
+                    if (r < d) v += al[r + 1] * xi[r];
+                    if (r >= 1) v += be[r + 1] * xi[r - 1];
+                } else {
+                    v = r == c ? 1.0 : 0.0;
+                }
+                pi[r] = v;
+            }
+            __syncthreads();
+            orth_against(pi, Pl, i, d + 1, hv);
+            double sp = 0.0;
+            for (int r = tid; r <= d; r += kOrthThreads) sp += pi[r] * pi[r];
+            pn = sqrt(orth_block_sum(sp, red));
+            if (c == d + 1 ? pn > 1e-12 * bmax : pn >= 0.5) break;
+            if (c == 0) {
+                pn = 0.0;
+                break;
+            }
+        }
+        for (int r = tid; r <= d; r += kOrthThreads) {
+            const double v = pn > 0.0 ? pi[r] / pn : 0.0;
+            pi[r] = v;
+            a.P[(long long)r * a.kstride + i] = v;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < k; i += kOrthThreads) a.sigma[i] = i < kk ? sqrt(fmax(lam[i], 0.0)) : 0.0;
+}
+
 hipError_t launch_lz_check(const LzCheck& a, hipStream_t s) {
     const size_t lds = sizeof(double) * (2 * (size_t)a.jj + kEigShifts + 8) + sizeof(int) * (kEigShifts + 4);
     hipLaunchKernelGGL(k_lz_eig, dim3((unsigned)a.k), dim3(kEigThreads), lds, s, a);
@@ -277,13 +526,29 @@ hipError_t launch_lz_check(const LzCheck& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// d: the dimension the deciding test recorded (the host read it from the record).
 hipError_t launch_lz_ritz(const LzRitz& a, int d, hipStream_t s) {
-    (void)d;
+    const size_t li = invit_lds_bytes(d), lo = orth_lds_bytes(d, a.k);
+    if (li <= kRitzLdsMax && lo <= kRitzLdsMax) {
+        hipLaunchKernelGGL(k_lz_invit_lds, dim3((unsigned)a.k), dim3(64), li, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_lz_orth_lds, dim3(1), dim3(kOrthThreads), lo, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_lz_invit, dim3((unsigned)a.k), dim3(64), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lz_orth, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t set_lz_attributes() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_lz_invit_lds),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRitzLdsMax);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(k_lz_orth_lds),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRitzLdsMax);
 }
 
 }  // namespace ssa

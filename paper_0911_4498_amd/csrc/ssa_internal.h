@@ -27,6 +27,7 @@ struct ConvGeom {
     const float2* tw2;  // W_{M2}^t, t < M2
     const float2* tw_lo;
     const float2* tw_hi;
+    const double* stop = nullptr;  // non-null: the product kernels return at once while *stop != 0
 };
 
 // pass-1 input modes
@@ -131,6 +132,8 @@ struct ReduceArgs {
     int segmented;      // 1: r and the basis are in layout `seg` (a fresh direction fills
     SegLay seg;         //    the natural slots only; padding slots stay zero)
     long long chunk_rows;  // rows per projection workgroup (a multiple of kProjRows); nchunks of them
+    double* snap;       // non-null: gets state[1], state[2] once this launch has updated them
+    const double* stop; // non-null: the launch does nothing while *stop != 0
 };
 
 // Pass 3 of a product fused with the three-term term and the projection partials
@@ -187,7 +190,7 @@ struct LzCheck {
     long long rmin;       // min(L, K): B is exact once jj reaches it
     double tol;
     double* rec;          // the record (kChkHdr + 3 kstride doubles)
-    const double* state;  // solver state: [1] restarts, [2] DGKS passes
+    const double* snap;   // restarts and DGKS passes after the last reduction before the test
     const double* nonfinite;  // nonzero: the series holds NaN/Inf (may be null)
     double* scr;          // 2 kstride + 2 k dstride doubles
     int kstride;
@@ -262,6 +265,7 @@ hipError_t launch_ritz_seg(const float* basis, long long ld, int ncols, const do
 hipError_t set_fused_attributes();
 hipError_t launch_lz_check(const LzCheck& a, hipStream_t s);
 hipError_t launch_lz_ritz(const LzRitz& a, int d, hipStream_t s);
+hipError_t set_lz_attributes();
 hipError_t set_kernel_attributes();
 // set_kernel_attributes() once per process; its result afterwards (api.cpp)
 hipError_t kernel_attributes_once();
