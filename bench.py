@@ -21,14 +21,17 @@ Prints one JSON line:
               counter runs (FETCH_SIZE, WRITE_SIZE; see
               paper_0911_4498_amd/pmc_traffic.py), null unless the summary in
               profiles/ was taken from the current library sources
+  served      a bounded served leg: --served-requests (120) requests of the
+              served-stream workload below at 100 req/s, p50/p99 latency
 With --workload many: the many-series workload instead (4096 series, N uniform
 in [2000, 20000], L = N/2, k = 16, seeded), solved together by the batched
 engine (ssa_batch_*); the JSON line also reports the single-series path on a
 sample of the same series, one series at a time, on the same GPU.
 With --workload served: a Poisson stream of requests (N log-uniform in
 [1e3, 1e6], L in {N/4, N/2}, k in [8, 32], seeded) at each of --rates;
-requests with N <= 20480 go to the continuous-batching server (ssa_server_*),
-longer ones to single-series plans on --long-workers (4) worker streams; reports p50/p99
+every request goes to the continuous-batching server (ssa_server_*): N <= 20480 to its
+batched engine, longer ones to its long path (single-series plans bound to regions of
+the same pool, --long-slots (4) at a time, one check interval per tick); reports p50/p99
 latency from arrival to complete outputs, and throughput.
 With --workload long: the very long series (N = 2^24, L = N/2, k = 50) through
 the single-series path with the basis capped by thick restart (--d-max,
@@ -39,7 +42,8 @@ array, k = 16.
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--pmc-copy]
                        [--workload single|many|served|hmatrix|realizations|long] [--reorth 0|1]
                        [--series S] [--sample S1] [--rates R1,R2] [--requests Q] [--slots S]
-                       [--pool-gb G] [--d-max D] [--restart-keep M]
+                       [--pool-gb G] [--long-slots S] [--served-requests Q] [--d-max D]
+                       [--restart-keep M]
 """
 import argparse
 import json
@@ -286,76 +290,44 @@ def cpu_baseline_many(host, Ns, k, info, ns):
     }
 
 
-def bench_served(args):
-    """Served stream: continuous batching for short requests, single-series plans for long ones."""
-    import queue
-    import threading
-
+def served_stream(args, nreq, rates, quiet=False):
+    """Served stream through ssa_server_*: requests with N <= 20480 go to the batched
+    engine, longer ones to the server's long path (single-series plans bound to regions
+    of the same pool, one check interval per tick).  Returns one result per rate."""
     import numpy as np
     import torch
 
     from paper_0911_4498_amd import inputs, ssa
     dev = torch.device("cuda:0")
-    nreq = args.requests
     n_small_max = 20480
-    print(f"# generating {nreq} requests", file=sys.stderr, flush=True)
+    log = (lambda *a: None) if quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    log(f"# generating {nreq} requests")
     reqs = []
     for r in range(nreq):
         f, N, L, k = inputs.c4_request(r)
         reqs.append((torch.tensor(f, device=dev), N, L, k))
-    small = [r for r in range(nreq) if reqs[r][1] <= n_small_max]
     torch.cuda.synchronize()  # request series resident before any stream uses them
     srv = ssa.Server(n_max=n_small_max, k_max=32, slots=args.slots, pool_bytes=int(args.pool_gb * 2**30), device=dev,
-                     reorth=args.reorth)
-    done_at = {}
-    lock = threading.Lock()
-    work = queue.Queue()
-
-    def worker():
-        stream = torch.cuda.Stream(device=dev)
-        groups_cache = {}
-        while True:
-            item = work.get()
-            if item is None:
-                return
-            r, t0 = item
-            f, N, L, k = reqs[r]
-            with torch.cuda.stream(stream):
-                plan = ssa.Plan(N, L, k, device=dev, stream=stream, reorth=args.reorth)
-                sg, U, V, info = plan.truncated_svd(f, k)
-                g = groups_cache.setdefault(k, [[i] for i in range(k)])
-                plan.reconstruct(sg, U, V, g)
-                stream.synchronize()
-                plan.close()
-            with lock:
-                done_at[r] = time.perf_counter() - t0
-
-    workers = [threading.Thread(target=worker, daemon=True) for _ in range(args.long_workers)]
-    for w in workers:
-        w.start()
+                     reorth=args.reorth, n_long_max=1 << 20, long_slots=args.long_slots)
 
     def run_stream(rate, ids):
         arrivals = inputs.c4_arrivals(rate, len(ids))
-        done_at.clear()
+        done_at = {}
+        outs = {}
         t0 = time.perf_counter()
         nxt = 0
-        keep = {}
         while len(done_at) < len(ids):
             now = time.perf_counter() - t0
             while nxt < len(ids) and arrivals[nxt] <= now:
                 r = ids[nxt]
                 f, N, L, k = reqs[r]
-                if N <= n_small_max:
-                    keep[r] = srv.submit(r, f, L, k, key=r)
-                else:
-                    work.put((r, t0))
+                outs[r] = srv.submit(r, f, L, k, key=r)
                 nxt += 1
             st = srv.status()
             if st["queued"] + st["active"] + st["finalizing"]:
                 for r, _ in srv.step():
-                    with lock:
-                        done_at[r] = time.perf_counter() - t0
-                    keep.pop(r, None)
+                    done_at[r] = time.perf_counter() - t0
+                    outs.pop(r, None)
             else:
                 time.sleep(min(1e-3, max(0.0, (arrivals[nxt] - now) if nxt < len(ids) else 1e-3)))
         lat = np.array([done_at[r] - arrivals[i] for i, r in enumerate(ids)])
@@ -373,18 +345,30 @@ def bench_served(args):
                 "eigentriples_per_s": triples / span}
 
     # warm-up: a few short and long requests, untimed
-    print("# warmup", file=sys.stderr, flush=True)
+    log("# served warmup")
+    small = [r for r in range(nreq) if reqs[r][1] <= n_small_max]
     run_stream(1000.0, small[:8] + [r for r in range(nreq) if r not in small][:2])
     results = []
-    for rate in [float(x) for x in args.rates.split(",")]:
-        print(f"# rate {rate:.0f} req/s", file=sys.stderr, flush=True)
+    for rate in rates:
+        log(f"# served rate {rate:.0f} req/s")
         res = run_stream(rate, list(range(nreq)))
-        print(f"#   p50 {res['p50_s']:.3f} s  p99 {res['p99_s']:.3f} s  short p50 {res['p50_short_s']:.3f} s "
-              f"p99 {res['p99_short_s']:.3f} s  {res['eigentriples_per_s']:.0f} eigentriples/s", file=sys.stderr,
-              flush=True)
+        log(f"#   p50 {res['p50_s']:.3f} s  p99 {res['p99_s']:.3f} s  short p50 {res['p50_short_s']:.3f} s "
+            f"p99 {res['p99_short_s']:.3f} s  long p50 {res['p50_long_s']:.3f} s  p99 {res['p99_long_s']:.3f} s  "
+            f"{res['eigentriples_per_s']:.0f} eigentriples/s")
         results.append(res)
-    for _ in workers:
-        work.put(None)
+    srv.close()
+    config = {"workload": f"Poisson stream of {nreq} requests per rate: N log-uniform in [1e3, 1e6], "
+                          "L in {N/4, N/2}, k in [8, 32], c3 signals (seeded)",
+              "short_path": f"continuous batching, N <= {n_small_max}, {args.slots} slots",
+              "long_path": f"server long path: single-series plans bound to pool regions, {args.long_slots} slots, "
+                           "one check interval per tick",
+              "pool_gib": args.pool_gb, "reorth": "one-sided" if args.reorth else "full"}
+    return results, config
+
+
+def bench_served(args):
+    """Served stream at each rate of --rates."""
+    results, config = served_stream(args, args.requests, [float(x) for x in args.rates.split(",")])
     best = results[-1]
     out = {
         "metric": "p50/p99 served-SSA latency",
@@ -399,12 +383,7 @@ def bench_served(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"Poisson stream of {nreq} requests per rate: N log-uniform in [1e3, 1e6], "
-                               "L in {N/4, N/2}, k in [8, 32], c3 signals (seeded)",
-                   "short_path": f"continuous batching, N <= {n_small_max}, {args.slots} slots, "
-                                 f"{args.pool_gb} GiB pool",
-                   "long_path": f"single-series plans, {args.long_workers} worker streams",
-                   "reorth": "one-sided" if args.reorth else "full", "parallelism": "single GPU"},
+        "config": {**config, "parallelism": "single GPU"},
         "rates": results,
     }
     print(json.dumps(out), flush=True)
@@ -598,8 +577,9 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="requests per rate (served stream)")
     ap.add_argument("--slots", type=int, default=256, help="server slots (served stream)")
     ap.add_argument("--pool-gb", type=float, default=24.0, help="server pool GiB (served stream)")
-    ap.add_argument("--long-workers", type=int, default=4,
-                    help="host threads, each with its own stream, for the long requests (served stream)")
+    ap.add_argument("--long-slots", type=int, default=4, help="server long-request slots (served stream)")
+    ap.add_argument("--served-requests", type=int, default=120,
+                    help="requests of the bounded served leg of the default run (0: none)")
     ap.add_argument("--series", type=int, default=4096, help="series of the many-series workload")
     ap.add_argument("--sample", type=int, default=256, help="series timed one at a time (many-series workload)")
     args = ap.parse_args()
@@ -631,6 +611,10 @@ def main():
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(f_np, int(round(out["lanczos_steps"])))
+    if args.served_requests > 0:
+        # a bounded served leg (the served-stream workload at one rate) beside the headline
+        results, scfg = served_stream(args, args.served_requests, [100.0])
+        out["served"] = {"metric": "p50/p99 served-SSA latency", **results[0], "config": scfg}
     print(json.dumps(out), flush=True)
 
 

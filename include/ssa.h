@@ -325,26 +325,55 @@ void ssa_batch_destroy(ssa_batch batch);
 /*
  * Continuous batching of SSA requests (served form).  A server owns a pool of
  * device memory (the caller's workspace, its HBM budget) and a number of
- * slots.  Submitted requests wait in a first-come-first-served queue and are
- * admitted, at the start of a tick, while a slot is free and the pool holds
- * their region.  A tick enqueues one Lanczos step (Algorithm 1 with the FFT
- * products and Gram-Schmidt of the batched path) for every admitted request,
- * sets up the newly admitted ones and finishes (Ritz triples, Algorithm 4) the
- * ones whose stopping test held in the previous tick.  Each request's Lanczos
- * state stays on the device between ticks.  A request gives the same result
- * whatever else is in flight (its key seeds its start vector).
+ * slots.  Submitted requests wait in one queue in arrival order and are
+ * admitted, at the start of a tick, while a slot of their class is free and the
+ * pool holds their region (a request whose class has no free slot lets later
+ * requests of the other class pass; one the pool cannot hold stops admission
+ * until it fits).  Every request's state stays in its pool region between ticks;
+ * storage is O(d (L + K)) per request (Sec. 3.3 on the cost of the bases).
+ * Short requests (N <= n_max) run on the batched engine: a tick enqueues one
+ * Lanczos step (Algorithm 1 with the FFT products and Gram-Schmidt of the
+ * batched path) for every admitted one, sets up the newly admitted ones and
+ * finishes (Ritz triples, Algorithm 4) the ones whose stopping test held in the
+ * previous tick.  Long requests (ssa_server_enable_long) run the single-series
+ * solver on a plan bound to their region, each on a stream of its own: a tick
+ * advances each by one check interval once its previous one has run, and
+ * enqueues its Ritz triples and Hankelization once its device stopping test has
+ * held.  A request gives the same result whatever else is in flight (its key
+ * seeds its start vector).
  */
 typedef struct ssa_server_s* ssa_server;
 
 /*
- * ssa_server_create -- requests of length 3 <= N <= n_max (n_max <= 20480),
- * k <= k_max <= 32, at most `slots` in flight; opts as for ssa_batch_plan.
+ * ssa_server_create -- batched requests of length 3 <= N <= n_max (n_max <=
+ * 20480), k <= k_max <= 32, at most `slots` of them in flight (longer ones:
+ * ssa_server_enable_long); opts as for ssa_batch_plan.
  * workspace_dev (256-byte aligned, `bytes` long) is the device pool; the
  * library allocates no device memory.  Errors: SSA_EINVAL, SSA_ENOMEM (pool
  * too small for the slot tables).
  */
 int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opts, void* workspace_dev,
                       size_t bytes, void* hip_stream, ssa_server* out);
+
+/*
+ * ssa_server_enable_long -- also serve requests with n_max < N <= n_long_max
+ * (n_long_max <= 2^24), at most long_slots at a time.  Each is planned at
+ * submission (ssa_embed_plan with the server's opts, its seed mixed with the
+ * request key) and takes a pool region of the plan's workspace size.  Creates
+ * one HIP stream, one event and a few pinned bytes per long slot.  Errors:
+ * SSA_EINVAL, SSA_ESTATE (already enabled), SSA_EDEVICE.
+ */
+int ssa_server_enable_long(ssa_server server, long long n_long_max, int long_slots);
+
+/*
+ * ssa_server_create_stub -- a server whose executor is a stub, for tests of the
+ * queue and of admission on machines without a GPU: no device memory, stream or
+ * HIP call; the pool is pool_bytes of bookkeeping only; every admitted request
+ * reports its test passed after `ticks` ticks and completes like a real one.
+ * Submitted pointers are never dereferenced.
+ */
+int ssa_server_create_stub(long long n_max, int k_max, int slots, const ssa_opts* opts, size_t pool_bytes,
+                           int ticks, ssa_server* out);
 
 /* ssa_server_request_bytes -- pool bytes a request of this shape occupies. */
 int ssa_server_request_bytes(ssa_server server, long long N, long long L, int k, size_t* bytes);
@@ -353,7 +382,9 @@ int ssa_server_request_bytes(ssa_server server, long long N, long long L, int k,
  * ssa_server_submit -- queue a request.  series_dev (N FP64 values) and the
  * outputs (sigma_dev: k doubles; U_dev: L*k floats, u_i at + i*L; V_dev:
  * K*k floats; recon_dev: N*k floats or NULL; info_dev: 4 ints or NULL: steps,
- * converged, restarts, DGKS passes) are device memory that must stay valid
+ * converged (-1 for a long request whose series holds NaN or Inf), restarts,
+ * DGKS passes) are device memory that must hold no pending work of other
+ * streams at submission (a long request is solved on a stream of its own) and stay valid
  * until `id` is reported complete by ssa_server_step.  Errors: SSA_EINVAL,
  * SSA_ENOMEM (the request alone exceeds the pool).
  */

@@ -159,6 +159,15 @@ struct ssa_plan_s {
     hipStream_t chk_stream = nullptr;
     hipEvent_t ab_ev = nullptr;  // the scalars of the tested step are written
     const double* stop_dev = nullptr;  // during a fused solve: the test's "done" flag
+    // a resumable solve on the device-test path (run_begin .. run_finish)
+    struct Run {
+        int active = 0, k = 0, j = 1, d_cap = 0;
+        int pend_jj = -1, pend_buf = 0, cur_buf = 0, last_chk = -1;
+        int steps_run = 0, stopped = 0;
+        const double* fin_rec = nullptr;  // pinned copy of the record that ended the solve
+    } run;
+    hipEvent_t run_ev = nullptr;  // the main stream has run every step enqueued so far
+    const ssa::PlanHost* lent = nullptr;  // host resources lent by the caller (not freed here)
     std::vector<double> work;
     // optional per-kernel-class timing (HIP events around the launches of the
     // classes in prof_mask; launch counts and bytes are kept for all classes)
@@ -562,6 +571,105 @@ int do_embed(ssa_plan p, const double* series_dev, bool sync_check = true) {
     return SSA_OK;
 }
 
+// One half of Lanczos step j (Algorithm 1).  The V half finishes u_j, forms r_j = X^T u_j -
+// beta_j v_{j-1}, orthogonalizes it against V (Sec. 3.2.2) and yields alpha_j; the U half
+// finishes v_j, forms p_j = X v_j - alpha_j u_j, orthogonalizes it against U and yields
+// beta_{j+1}.  gl is the geometry of the fused products (it may carry the early-exit
+// flag), g that of the unfused ones.
+int half_step(ssa_plan p, const ConvGeom& gl, const ConvGeom& g, int j, bool vhalf) {
+    float* U = at<float>(p, p->o_U);
+    float* V = at<float>(p, p->o_V);
+    float* r = at<float>(p, p->o_r);
+    double* alpha = at<double>(p, p->o_alpha);
+    double* beta = at<double>(p, p->o_beta);
+    const long long Li = p->Li, Ki = p->Ki;
+    // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
+    const int ncv = p->onesided ? 0 : j - 1;
+    int rc;
+    if (vhalf) {
+        if (p->fused) {
+            // finish u_j; r_j = X^T u_j - beta_j v_{j-1}; its partials against V_{j-1}; alpha_j
+            rc = fused_product(p, gl, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU, p->layV,
+                               j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j, V, p->ldV, ncv);
+            if (rc != SSA_OK) return rc;
+            rc = fused_finish(p, V, p->ldV, ncv, j - 1, p->layV, p->nblk, alpha + j, 1, 2ULL * j);
+        } else {
+            // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
+            rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, 0, r,
+                          j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
+            if (rc != SSA_OK) return rc;
+            rc = orthonormalize(p, V, p->ldV, ncv, Ki, alpha + j, 1, 2ULL * j, j - 1, j - 1);
+        }
+        if (rc != SSA_OK) return rc;
+    } else {
+        if (p->fused) {
+            // finish v_j; p_j = X v_j - alpha_j u_j; its partials against U_j; beta_{j+1}
+            rc = fused_product(p, gl, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV, p->layU,
+                               U + (long long)(j - 1) * p->ldU, alpha + j, U, p->ldU, j);
+            if (rc != SSA_OK) return rc;
+            rc = fused_finish(p, U, p->ldU, j, j, p->layU, p->nblk, beta + j + 1, 1, 2ULL * j + 1);
+        } else {
+            // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
+            rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, 1, r, U + (long long)(j - 1) * p->ldU, alpha + j);
+            if (rc != SSA_OK) return rc;
+            rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
+        }
+        if (rc != SSA_OK) return rc;
+    }
+    return SSA_OK;
+}
+
+// Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0 (the fused
+// path leaves u_1 = r * scale to the first pass-1 update); beta_1 = |p_0|.
+int start_vector(ssa_plan p) {
+    hipStream_t s = p->stream;
+    float* U = at<float>(p, p->o_U);
+    float* r = at<float>(p, p->o_r);
+    double* beta = at<double>(p, p->o_beta);
+    const long long Li = p->Li;
+    int rc;
+    if (p->fused) {
+        SSA_TRY(launch_start_seg(r, p->layU, p->seed, s));
+        ReduceArgs a0{};
+        a0.part = at<double>(p, p->o_part);
+        a0.chunk_rows = proj_chunk_rows(p->layU.len);
+        a0.nchunks = (int)((p->layU.len + a0.chunk_rows - 1) / a0.chunk_rows);
+        a0.pstride = p->pstride;
+        a0.r = r;
+        a0.n = p->layU.len;
+        a0.basis = U;
+        a0.ld = p->ldU;
+        {
+            ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)Li);
+            SSA_TRY(launch_cgs_project(a0, s));
+        }
+        rc = fused_finish(p, U, p->ldU, 0, 0, p->layU, a0.nchunks, beta + 1, 0, 1);
+    } else {
+        SSA_TRY(launch_start_vector(r, Li, p->seed, s));
+        rc = orthonormalize(p, U, p->ldU, 0, Li, beta + 1, 0, 1);
+    }
+    if (rc != SSA_OK) return rc;
+    return SSA_OK;
+}
+
+// Pinned doubles of a plan's scalar staging (alpha, beta, P, Q, sigma of the host-test path).
+size_t host_scal_doubles(int d_max, int kcols, int k_max) {
+    return 4 * (size_t)(d_max + 3) + (size_t)(2 * d_max + 1) * kcols + k_max + 8;
+}
+
+void use_host(ssa_plan p, const ssa::PlanHost& h) {
+    p->h_scal = h.h_scal;
+    p->h_flag = h.h_flag;
+    p->h_rec = h.h_rec;
+    p->h_grp = h.h_grp;
+    p->grp_done = h.grp_done;
+    p->chk_ev[0] = h.chk_ev[0];
+    p->chk_ev[1] = h.chk_ev[1];
+    p->ab_ev = h.ab_ev;
+    p->run_ev = h.run_ev;
+    p->chk_stream = h.chk_stream;
+}
+
 std::once_flag g_attr_once;
 hipError_t g_attr_err = hipSuccess;
 
@@ -586,6 +694,250 @@ bool auto_geometry(long long N, ConvGeom* g) {
     if (!choose_fft(N, Mp, M1, M2)) return false;
     fill_geom(Mp, M1, M2, default_cb(M1, M2), *g);
     return true;
+}
+
+}  // namespace ssa
+
+namespace ssa {
+
+// A solve on the device-test path (plans without thick restart), in resumable pieces:
+// run_begin embeds the series and enqueues the start vector; run_advance enqueues up to
+// max_steps Lanczos steps, launching the stopping test at its check points (on the check
+// stream) and waiting for the previous test's record at each; run_finish enqueues the Ritz
+// triples once a test has ended the solve.  ssa_truncated_svd runs the three in a row; the
+// served form advances many of them a check interval per tick.
+int host_alloc(PlanHost& h, size_t n_scal, size_t n_rec, size_t n_grp) {
+    h.n_scal = n_scal;
+    h.n_rec = n_rec;
+    h.n_grp = n_grp;
+    if (hipHostMalloc((void**)&h.h_scal, sizeof(double) * n_scal, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h.h_flag, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h.h_rec, sizeof(double) * n_rec, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h.h_grp, sizeof(int) * n_grp, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&h.grp_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h.chk_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h.chk_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h.ab_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h.run_ev, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&h.chk_stream, hipStreamNonBlocking) != hipSuccess)
+        return SSA_EDEVICE;
+    return SSA_OK;
+}
+
+void host_free(PlanHost& h) {
+    if (h.chk_stream) {
+        (void)hipStreamSynchronize(h.chk_stream);
+        (void)hipStreamDestroy(h.chk_stream);
+    }
+    if (h.grp_done) {
+        (void)hipEventSynchronize(h.grp_done);
+        (void)hipEventDestroy(h.grp_done);
+    }
+    for (hipEvent_t e : {h.chk_ev[0], h.chk_ev[1], h.ab_ev, h.run_ev})
+        if (e) (void)hipEventDestroy(e);
+    if (h.h_scal) (void)hipHostFree(h.h_scal);
+    if (h.h_flag) (void)hipHostFree(h.h_flag);
+    if (h.h_rec) (void)hipHostFree(h.h_rec);
+    if (h.h_grp) (void)hipHostFree(h.h_grp);
+    h = PlanHost{};
+}
+
+int host_alloc_for(PlanHost& h, int k_max, const ssa_opts* opts) {
+    const int d_max = std::min(opts && opts->d_max > 0 ? opts->d_max : 8 * k_max + 32, kMaxDmax);
+    const int kcols = std::max(k_max, opts ? opts->restart_keep : 0);
+    const size_t grp = (size_t)(kMaxGroupBatch + 1) + (size_t)kMaxGroupBatch * k_max;
+    return host_alloc(h, host_scal_doubles(d_max, kcols, k_max), 2 * (size_t)(kChkHdr + 3 * kcols), grp);
+}
+
+int plan_lend_host(ssa_plan p, const PlanHost& h) {
+    if (!p || p->h_scal || !h.h_scal) return SSA_ESTATE;  // before the plan's first bind
+    if (host_scal_doubles(p->d_max, p->kcols, p->k_max) > h.n_scal || 2 * (size_t)p->nrec > h.n_rec ||
+        p->grp_ints > h.n_grp)
+        return SSA_ENOMEM;
+    use_host(p, h);
+    p->lent = &h;
+    return SSA_OK;
+}
+
+int run_begin(ssa_plan p, const double* series_dev, int k) {
+    int rc = do_embed(p, series_dev, false);
+    if (rc != SSA_OK) return rc;
+    hipStream_t s = p->stream;
+    double* rec = at<double>(p, p->o_rec);
+    SSA_TRY(launch_fill_zero(rec, p->nrec, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_alpha), p->d_max + 3, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_beta), p->d_max + 3, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
+    rc = start_vector(p);
+    if (rc != SSA_OK) return rc;
+    p->run = decltype(p->run){};
+    p->run.active = 1;
+    p->run.k = k;
+    p->run.d_cap = (int)std::min<long long>(p->d_max, std::min(p->Li, p->Ki));
+    // Steps enqueued after the deciding test (the host learns of it one test later) do
+    // no work on the fused path: its product and reduction kernels return at once once
+    // the test's record says done.  Those steps only write columns and scalars past d.
+    p->stop_dev = p->fused ? rec + kChkDone : nullptr;
+    SSA_TRY(hipEventRecord(p->run_ev, s));
+    return SSA_OK;
+}
+
+int run_advance(ssa_plan p, int max_steps) {
+    auto& R = p->run;
+    if (!R.active) return SSA_ESTATE;
+    hipStream_t s = p->stream;
+    const ConvGeom g = bound_geom(p);
+    ConvGeom gl = g;
+    gl.stop = p->stop_dev;
+    const long long Li = p->Li, Ki = p->Ki;
+    double* rec = at<double>(p, p->o_rec);
+    double* alpha = at<double>(p, p->o_alpha);
+    double* beta = at<double>(p, p->o_beta);
+    const int k = R.k;
+    for (int n = 0; n < max_steps && !R.stopped; ++n) {
+        const int j = R.j;
+        int rc = half_step(p, gl, g, j, true);
+        if (rc != SSA_OK) return rc;
+        const int jj = j - 1;
+        R.steps_run = jj;
+        bool stop = false;
+        if (jj >= k && (jj % p->check_every == 0 || jj >= R.d_cap)) {
+            // the test of one check point runs on the check stream, beside the next
+            // Lanczos steps (it reads only alpha/beta up to this step and the state
+            // snapshot of this step's reduction); the host reads its record one check
+            // point later
+            SSA_TRY(hipEventRecord(p->ab_ev, s));
+            SSA_TRY(hipStreamWaitEvent(p->chk_stream, p->ab_ev, 0));
+            LzCheck c{};
+            c.alpha = alpha;
+            c.beta = beta;
+            c.jj = jj;
+            c.k = k;
+            c.dcap = R.d_cap;
+            c.rmin = std::min(Li, Ki);
+            c.tol = p->tol;
+            c.rec = rec;
+            c.snap = at<double>(p, p->o_snap) + 2 * (2 * (long long)j);  // the V half of step j
+            c.nonfinite = at<double>(p, p->o_flag);
+            c.scr = at<double>(p, p->o_lzscr);
+            c.kstride = p->kcols;
+            c.dstride = p->dstride;
+            {
+                ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (jj + 2), p->chk_stream);
+                SSA_TRY(launch_lz_check(c, p->chk_stream));
+            }
+            double* hr = p->h_rec + (size_t)R.cur_buf * p->nrec;
+            SSA_TRY(hipMemcpyAsync(hr, rec, sizeof(double) * p->nrec, hipMemcpyDeviceToHost, p->chk_stream));
+            SSA_TRY(hipEventRecord(p->chk_ev[R.cur_buf], p->chk_stream));
+            R.last_chk = R.cur_buf;
+            if (R.pend_jj >= 0) {
+                SSA_TRY(hipEventSynchronize(p->chk_ev[R.pend_buf]));
+                stop = p->h_rec[(size_t)R.pend_buf * p->nrec + kChkDone] != 0.0;
+            }
+            if (!stop) {
+                R.pend_jj = jj;
+                R.pend_buf = R.cur_buf;
+                R.cur_buf ^= 1;
+                if (jj >= R.d_cap) {
+                    SSA_TRY(hipEventSynchronize(p->chk_ev[R.pend_buf]));
+                    stop = p->h_rec[(size_t)R.pend_buf * p->nrec + kChkDone] != 0.0;
+                }
+            }
+            if (stop) R.fin_rec = p->h_rec + (size_t)R.pend_buf * p->nrec;
+        }
+        if (stop) {
+            R.stopped = 1;
+            break;
+        }
+        rc = half_step(p, gl, g, j, false);
+        if (rc != SSA_OK) return rc;
+        R.j = j + 1;
+    }
+    SSA_TRY(hipEventRecord(p->run_ev, s));
+    return SSA_OK;
+}
+
+int run_stopped(ssa_plan p) { return p->run.stopped; }
+
+// Every step and test enqueued so far has finished (no waiting).
+int run_idle(ssa_plan p) {
+    if (hipEventQuery(p->run_ev) != hipSuccess) return 0;
+    if (p->run.last_chk >= 0 && hipEventQuery(p->chk_ev[p->run.last_chk]) != hipSuccess) return 0;
+    return 1;
+}
+
+// The Ritz triples of a stopped run (stream-ordered: the call returns once they are
+// enqueued).  Also ends the run.
+int run_finish(ssa_plan p, double* sigma_dev, float* U_dev, float* V_dev, ssa_info* info) {
+    auto& R = p->run;
+    if (!R.active || !R.stopped) return SSA_ESTATE;
+    R.active = 0;
+    p->stop_dev = nullptr;
+    hipStream_t s = p->stream;
+    const int k = R.k;
+    const long long Li = p->Li, Ki = p->Ki;
+    float* U = at<float>(p, p->o_U);
+    float* V = at<float>(p, p->o_V);
+    double* rec = at<double>(p, p->o_rec);
+    double* alpha = at<double>(p, p->o_alpha);
+    double* beta = at<double>(p, p->o_beta);
+    double* dP = at<double>(p, p->o_P);
+    double* dQ = at<double>(p, p->o_Q);
+    float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
+    float* Vo = p->transposed ? U_dev : V_dev;
+    // Stream-ordered from here: the Ritz coefficients and vectors are enqueued and the
+    // call returns; the outputs are complete when the stream has run them.  Everything
+    // after this reads the record and the test's scratch, and the next solve rewrites
+    // them: order the main stream after every test enqueued.
+    SSA_TRY(hipStreamWaitEvent(s, p->chk_ev[R.last_chk], 0));
+    if (R.fin_rec[kChkNonfinite] != 0.0) {
+        p->embedded = 0;  // the operator holds the non-finite series: unusable
+        return SSA_ENONFINITE;
+    }
+    const int d = (int)R.fin_rec[kChkD];
+    const bool conv = R.fin_rec[kChkConv] != 0.0;
+    LzRitz rz{};
+    rz.alpha = alpha;
+    rz.beta = beta;
+    rz.rec = rec;
+    rz.k = k;
+    rz.kstride = k;
+    rz.dstride = p->dstride;
+    rz.P = dP;
+    rz.Q = dQ;
+    rz.sigma = sigma_dev;
+    rz.scr = at<double>(p, p->o_lzscr);
+    {
+        ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (d + 2));
+        SSA_TRY(launch_lz_ritz(rz, d, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (d + 1 + k));
+        if (p->fused)
+            SSA_TRY(launch_ritz_seg(U, p->ldU, d + 1, dP, k, Uo, Li, p->layU, s));
+        else
+            SSA_TRY(launch_ritz(U, p->ldU, d + 1, dP, k, Uo, Li, Li, s));
+    }
+    {
+        ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (d + k));
+        if (p->fused)
+            SSA_TRY(launch_ritz_seg(V, p->ldV, d, dQ, k, Vo, Ki, p->layV, s));
+        else
+            SSA_TRY(launch_ritz(V, p->ldV, d, dQ, k, Vo, Ki, Ki, s));
+    }
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->steps = d;
+        info->converged = conv ? 1 : 0;
+        info->restarts = (int)R.fin_rec[kChkRestarts];
+        info->dgks_passes = (int)R.fin_rec[kChkDgks];
+        info->steps_run = R.steps_run;
+        const double* resid = R.fin_rec + kChkHdr + 2 * p->kcols;
+        for (int i = 0; i < k && i < 64; ++i) info->resid[i] = resid[i];
+    }
+    const int status = !conv ? SSA_WARN_NOT_CONVERGED : R.fin_rec[kChkRestarts] > 0.0 ? SSA_WARN_BREAKDOWN : SSA_OK;
+    if (info) info->status = status;
+    return status;
 }
 
 }  // namespace ssa
@@ -734,20 +1086,14 @@ int ssa_plan_bind(ssa_plan p, void* workspace_dev, size_t bytes, void* hip_strea
     if (bytes < p->ws_bytes) return SSA_ENOMEM;
     if (kernel_attributes_once() != hipSuccess) return SSA_EDEVICE;
     if (!p->h_scal) {
-        const size_t nd = 4 * (size_t)(p->d_max + 3) + (size_t)(2 * p->d_max + 1) * p->kcols + p->k_max + 8;
-        if (hipHostMalloc((void**)&p->h_scal, sizeof(double) * nd, hipHostMallocDefault) != hipSuccess)
-            return SSA_EDEVICE;
-        if (hipHostMalloc((void**)&p->h_flag, sizeof(double) * 16, hipHostMallocDefault) != hipSuccess)
-            return SSA_EDEVICE;
-        if (hipHostMalloc((void**)&p->h_rec, sizeof(double) * 2 * (size_t)p->nrec, hipHostMallocDefault) != hipSuccess)
-            return SSA_EDEVICE;
-        if (hipHostMalloc((void**)&p->h_grp, sizeof(int) * p->grp_ints, hipHostMallocDefault) != hipSuccess)
-            return SSA_EDEVICE;
-        if (hipEventCreateWithFlags(&p->grp_done, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
-        for (hipEvent_t& e : p->chk_ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
-        if (hipEventCreateWithFlags(&p->ab_ev, hipEventDisableTiming) != hipSuccess) return SSA_EDEVICE;
-        if (hipStreamCreateWithFlags(&p->chk_stream, hipStreamNonBlocking) != hipSuccess) return SSA_EDEVICE;
+        ssa::PlanHost h;
+        const int rc = ssa::host_alloc(h, host_scal_doubles(p->d_max, p->kcols, p->k_max), 2 * (size_t)p->nrec,
+                                       p->grp_ints);
+        if (rc != SSA_OK) {
+            ssa::host_free(h);
+            return rc;
+        }
+        use_host(p, h);
     }
     p->ws = static_cast<char*>(workspace_dev);
     p->stream = static_cast<hipStream_t>(hip_stream);
@@ -782,15 +1128,22 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     if (!p->bound) return SSA_ENOMEM;
     // Without thick restart the stopping test and the Ritz coefficients run on the
     // device and the host reads back only the test's record; the restarted solver
-    // assembles its projected matrix on the host.
-    const bool devchk = p->keep == 0;
-    int rc = do_embed(p, series_dev, !devchk);
+    // (below) assembles its projected matrix on the host.
+    if (p->keep == 0) {
+        int rc = ssa::run_begin(p, series_dev, k);
+        while (rc == SSA_OK && !p->run.stopped) rc = ssa::run_advance(p, 1 << 30);
+        if (rc != SSA_OK) {
+            p->run.active = 0;
+            p->stop_dev = nullptr;
+            return rc;
+        }
+        return ssa::run_finish(p, sigma_dev, U_dev, V_dev, info);
+    }
+    int rc = do_embed(p, series_dev, true);
     if (rc != SSA_OK) return rc;
     const ConvGeom g = bound_geom(p);
     hipStream_t s = p->stream;
     const long long Li = p->Li, Ki = p->Ki;
-    double* rec = at<double>(p, p->o_rec);
-    if (devchk) SSA_TRY(launch_fill_zero(rec, p->nrec, s));
     float* U = at<float>(p, p->o_U);
     float* V = at<float>(p, p->o_V);
     float* r = at<float>(p, p->o_r);
@@ -800,43 +1153,10 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     SSA_TRY(launch_fill_zero(beta, p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
 
-    // Algorithm 1, first line: u_1 = p_0 / |p_0| with a seeded Gaussian p_0 (the fused
-    // path leaves u_1 = r * scale to the first pass-1 update)
-    if (p->fused) {
-        SSA_TRY(launch_start_seg(r, p->layU, p->seed, s));
-        ReduceArgs a0{};
-        a0.part = at<double>(p, p->o_part);
-        a0.chunk_rows = proj_chunk_rows(p->layU.len);
-        a0.nchunks = (int)((p->layU.len + a0.chunk_rows - 1) / a0.chunk_rows);
-        a0.pstride = p->pstride;
-        a0.r = r;
-        a0.n = p->layU.len;
-        a0.basis = U;
-        a0.ld = p->ldU;
-        {
-            ProfScope ps(p, SSA_PROF_DOTS, 4.0 * (double)Li);
-            SSA_TRY(launch_cgs_project(a0, s));
-        }
-        rc = fused_finish(p, U, p->ldU, 0, 0, p->layU, a0.nchunks, beta + 1, 0, 1);
-    } else {
-        SSA_TRY(launch_start_vector(r, Li, p->seed, s));
-        rc = orthonormalize(p, U, p->ldU, 0, Li, beta + 1, 0, 1);
-    }
+    rc = start_vector(p);
     if (rc != SSA_OK) return rc;
 
     const int d_cap = (int)std::min<long long>(p->d_max, std::min(Li, Ki));
-    // Steps enqueued after the deciding test (the host learns of it one test later) do
-    // no work on the fused path: its product and reduction kernels return at once once
-    // the test's record says done.  Those steps only write columns and scalars past d.
-    ConvGeom gl = g;
-    if (devchk && p->fused) {
-        gl.stop = rec + kChkDone;
-        p->stop_dev = gl.stop;
-    }
-    struct StopReset {
-        ssa_plan p;
-        ~StopReset() { p->stop_dev = nullptr; }
-    } stop_reset{p};
     const size_t abn = (size_t)(p->d_max + 3);
     double* h_ab[2] = {p->h_scal, p->h_scal + 2 * abn};  // alpha | beta, double-buffered
     double* h_P = p->h_scal + 4 * abn;
@@ -846,7 +1166,6 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
     bool have_prev = false, converged = false;
     int d = 0, steps_run = 0;
     const double* fin = nullptr;
-    const double* fin_rec = nullptr;  // device-check path: the record that ended the solve
     // Stopping test on B_jj (its residual bound needs alpha_{jj+1}).  The test
     // of one check point runs on the host while the GPU works through the
     // steps enqueued after it, so the GPU never waits for the host; if it
@@ -870,71 +1189,14 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         }
         return false;
     };
-    int pend_jj = -1, pend_buf = 0, cur_buf = 0, last_chk = -1;
+    int pend_jj = -1, pend_buf = 0, cur_buf = 0;
     for (int j = 1;; ++j) {
-        // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
-        const int ncv = p->onesided ? 0 : j - 1;
-        if (p->fused) {
-            // finish u_j; r_j = X^T u_j - beta_j v_{j-1}; its partials against V_{j-1}; alpha_j
-            rc = fused_product(p, gl, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU, p->layV,
-                               j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j, V, p->ldV, ncv);
-            if (rc != SSA_OK) return rc;
-            rc = fused_finish(p, V, p->ldV, ncv, j - 1, p->layV, p->nblk, alpha + j, 1, 2ULL * j);
-        } else {
-            // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
-            rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, 0, r,
-                          j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j);
-            if (rc != SSA_OK) return rc;
-            rc = orthonormalize(p, V, p->ldV, ncv, Ki, alpha + j, 1, 2ULL * j, j - 1, j - 1);
-        }
+        rc = half_step(p, g, g, j, true);
         if (rc != SSA_OK) return rc;
         const int jj = j - 1;
         steps_run = jj;
         bool stop = false;
-        if (devchk && jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
-            // the test of one check point runs on the check stream, beside the next
-            // Lanczos steps (it reads only alpha/beta up to this step and the state
-            // snapshot of this step's reduction); the host reads its record one check
-            // point later
-            SSA_TRY(hipEventRecord(p->ab_ev, s));
-            SSA_TRY(hipStreamWaitEvent(p->chk_stream, p->ab_ev, 0));
-            LzCheck c{};
-            c.alpha = alpha;
-            c.beta = beta;
-            c.jj = jj;
-            c.k = k;
-            c.dcap = d_cap;
-            c.rmin = std::min(Li, Ki);
-            c.tol = p->tol;
-            c.rec = rec;
-            c.snap = at<double>(p, p->o_snap) + 2 * (2 * (long long)j);  // the V half of step j
-            c.nonfinite = at<double>(p, p->o_flag);
-            c.scr = at<double>(p, p->o_lzscr);
-            c.kstride = p->kcols;
-            c.dstride = p->dstride;
-            {
-                ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (jj + 2), p->chk_stream);
-                SSA_TRY(launch_lz_check(c, p->chk_stream));
-            }
-            double* hr = p->h_rec + (size_t)cur_buf * p->nrec;
-            SSA_TRY(hipMemcpyAsync(hr, rec, sizeof(double) * p->nrec, hipMemcpyDeviceToHost, p->chk_stream));
-            SSA_TRY(hipEventRecord(p->chk_ev[cur_buf], p->chk_stream));
-            last_chk = cur_buf;
-            if (pend_jj >= 0) {
-                SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
-                stop = p->h_rec[(size_t)pend_buf * p->nrec + kChkDone] != 0.0;
-            }
-            if (!stop) {
-                pend_jj = jj;
-                pend_buf = cur_buf;
-                cur_buf ^= 1;
-                if (jj >= d_cap) {
-                    SSA_TRY(hipEventSynchronize(p->chk_ev[pend_buf]));
-                    stop = p->h_rec[(size_t)pend_buf * p->nrec + kChkDone] != 0.0;
-                }
-            }
-            if (stop) fin_rec = p->h_rec + (size_t)pend_buf * p->nrec;
-        } else if (!devchk && jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
+        if (jj >= k && (jj % p->check_every == 0 || jj >= d_cap)) {
             double* buf = h_ab[cur_buf];
             SSA_TRY(hipMemcpyAsync(buf, alpha, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
             SSA_TRY(hipMemcpyAsync(buf + abn, beta, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
@@ -954,79 +1216,13 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
             }
         }
         if (stop) break;
-        if (p->fused) {
-            // finish v_j; p_j = X v_j - alpha_j u_j; its partials against U_j; beta_{j+1}
-            rc = fused_product(p, gl, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV, p->layU,
-                               U + (long long)(j - 1) * p->ldU, alpha + j, U, p->ldU, j);
-            if (rc != SSA_OK) return rc;
-            rc = fused_finish(p, U, p->ldU, j, j, p->layU, p->nblk, beta + j + 1, 1, 2ULL * j + 1);
-        } else {
-            // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
-            rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, 1, r, U + (long long)(j - 1) * p->ldU, alpha + j);
-            if (rc != SSA_OK) return rc;
-            rc = orthonormalize(p, U, p->ldU, j, Li, beta + j + 1, 1, 2ULL * j + 1);
-        }
+        rc = half_step(p, g, g, j, false);
         if (rc != SSA_OK) return rc;
     }
     double* dP = at<double>(p, p->o_P);
     double* dQ = at<double>(p, p->o_Q);
     float* Uo = p->transposed ? V_dev : U_dev;  // internal U has length Li
     float* Vo = p->transposed ? U_dev : V_dev;
-    if (devchk) {
-        // stream-ordered from here: the Ritz coefficients and vectors are enqueued and the
-        // call returns; the outputs are complete when the stream has run them
-        // everything after this reads the record and the test's scratch, and the next
-        // call rewrites them: order the main stream after every test enqueued
-        SSA_TRY(hipStreamWaitEvent(s, p->chk_ev[last_chk], 0));
-        if (fin_rec[kChkNonfinite] != 0.0) {
-            p->embedded = 0;  // the operator holds the non-finite series: unusable
-            return SSA_ENONFINITE;
-        }
-        d = (int)fin_rec[kChkD];
-        const bool conv = fin_rec[kChkConv] != 0.0;
-        LzRitz rz{};
-        rz.alpha = alpha;
-        rz.beta = beta;
-        rz.rec = rec;
-        rz.k = k;
-        rz.kstride = k;
-        rz.dstride = p->dstride;
-        rz.P = dP;
-        rz.Q = dQ;
-        rz.sigma = sigma_dev;
-        rz.scr = at<double>(p, p->o_lzscr);
-        {
-            ProfScope ps(p, SSA_PROF_CHECK, 16.0 * (d + 2));
-            SSA_TRY(launch_lz_ritz(rz, d, s));
-        }
-        {
-            ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Li * (d + 1 + k));
-            if (p->fused)
-                SSA_TRY(launch_ritz_seg(U, p->ldU, d + 1, dP, k, Uo, Li, p->layU, s));
-            else
-                SSA_TRY(launch_ritz(U, p->ldU, d + 1, dP, k, Uo, Li, Li, s));
-        }
-        {
-            ProfScope ps(p, SSA_PROF_RITZ, 4.0 * (double)Ki * (d + k));
-            if (p->fused)
-                SSA_TRY(launch_ritz_seg(V, p->ldV, d, dQ, k, Vo, Ki, p->layV, s));
-            else
-                SSA_TRY(launch_ritz(V, p->ldV, d, dQ, k, Vo, Ki, Ki, s));
-        }
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->steps = d;
-            info->converged = conv ? 1 : 0;
-            info->restarts = (int)fin_rec[kChkRestarts];
-            info->dgks_passes = (int)fin_rec[kChkDgks];
-            info->steps_run = steps_run;
-            const double* resid = fin_rec + kChkHdr + 2 * p->kcols;
-            for (int i = 0; i < k && i < 64; ++i) info->resid[i] = resid[i];
-        }
-        const int status = !conv ? SSA_WARN_NOT_CONVERGED : fin_rec[kChkRestarts] > 0.0 ? SSA_WARN_BREAKDOWN : SSA_OK;
-        if (info) info->status = status;
-        return status;
-    }
     const double* h_alpha = fin;
     const double* h_beta = fin + abn;
     int nu = d + 1, nc = d;  // the result is U_{nu} P (nu x k) and V_{nc} Q (nc x k)
@@ -1293,16 +1489,23 @@ int ssa_plan_describe(ssa_plan p, ssa_plan_desc* d) {
 
 void ssa_plan_destroy(ssa_plan p) {
     if (!p) return;
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->lent) {  // the lender keeps its resources: only wait for this plan's work on them
+        if (p->grp_done) (void)hipEventSynchronize(p->grp_done);
+        if (p->chk_stream) (void)hipStreamSynchronize(p->chk_stream);
+        delete p;
+        return;
+    }
     if (p->grp_done) {
         (void)hipEventSynchronize(p->grp_done);
         (void)hipEventDestroy(p->grp_done);
     }
-    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->chk_stream) {
         (void)hipStreamSynchronize(p->chk_stream);
         (void)hipStreamDestroy(p->chk_stream);
     }
     if (p->ab_ev) (void)hipEventDestroy(p->ab_ev);
+    if (p->run_ev) (void)hipEventDestroy(p->run_ev);
     for (hipEvent_t e : p->chk_ev)
         if (e) (void)hipEventDestroy(e);
     if (p->h_scal) (void)hipHostFree(p->h_scal);

@@ -15,6 +15,7 @@
 #include <map>
 #include <new>
 #include <set>
+#include <thread>
 #include <vector>
 
 #include "ssa.h"
@@ -408,6 +409,8 @@ struct Request {
     float* V;
     float* recon;
     int* info;
+    ssa_plan plan = nullptr;  // long requests: the single-series plan, sized at submission
+    size_t bytes = 0;         // long requests: its workspace bytes
 };
 
 // First-fit allocator of byte ranges of the region pool (256-byte multiples).
@@ -420,6 +423,7 @@ struct Pool {
         if (bytes) free_[base] = bytes;
     }
     bool alloc(size_t bytes, size_t* at) {
+        bytes = align_up(bytes, 256);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second < bytes) continue;
             *at = it->first;
@@ -432,6 +436,7 @@ struct Pool {
         return false;
     }
     void release(size_t at, size_t bytes) {
+        bytes = align_up(bytes, 256);
         auto it = free_.emplace(at, bytes).first;
         auto nx = std::next(it);
         if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -455,17 +460,36 @@ struct Pool {
 
 enum SlotState { kFree = 0, kActive = 1, kFinalizing = 2 };
 
+// A request longer than the batched engine takes, solved on a plan bound to a pool region.
+struct LongSlot {
+    int state = kFree;
+    Request req{};
+    size_t reg = 0, bytes = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t fin_ev = nullptr;  // its Ritz triples and Hankelization have run
+    int* h_info = nullptr;        // pinned: the info ints, staged for the device copy
+    ssa::PlanHost host;           // lent to each plan the slot runs (nothing allocated per request)
+    int stub_left = 0;
+};
+
+// start-vector seed of a long request: a function of the server seed and the request key
+unsigned long long long_seed(unsigned long long seed, unsigned long long key) {
+    const unsigned long long z = seed ^ (key * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL);
+    return z ? z : 1ULL;
+}
+
 }  // namespace
 
 struct ssa_server_s {
     EngineCfg cfg;
+    ssa_opts opts{};  // as given at creation (the long requests' plans use it)
     int slots;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
     size_t o_tab, o_flags, o_lists;  // table, done flags, launch lists (device)
     Pool pool;
-    std::deque<Request> queue;
+    std::deque<Request> queue;         // both classes, in arrival order
     std::vector<int> state;            // SlotState per slot
     std::vector<Request> req;          // request per slot
     std::vector<size_t> reg, reg_bytes;
@@ -473,19 +497,98 @@ struct ssa_server_s {
     int* h_flags = nullptr;            // pinned: done flags read back after each tick
     int* h_lists = nullptr;            // pinned: launch lists (set-up | active | finalize)
     long long ticks = 0;
+    long long n_long_max = 0;          // 0: long requests are not served
+    std::vector<LongSlot> lslot;
+    int lrr = 0;                       // round-robin position among the long slots
+    int stub = 0;                      // stub executor: no device work, requests take stub_ticks ticks
+    int stub_ticks = 0;
+    std::vector<int> stub_left;        // short slots, stub executor
 };
 
-extern "C" {
+namespace {
 
-int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opts, void* workspace_dev, size_t bytes,
-                      void* hip_stream, ssa_server* out) {
+void destroy_long(ssa_server v) {
+    for (LongSlot& ls : v->lslot) {
+        if (ls.stream) (void)hipStreamSynchronize(ls.stream);
+        if (ls.req.plan) ssa_plan_destroy(ls.req.plan);
+        if (ls.fin_ev) (void)hipEventDestroy(ls.fin_ev);
+        if (ls.stream) (void)hipStreamDestroy(ls.stream);
+        if (ls.h_info) (void)hipHostFree(ls.h_info);
+        if (ls.host.h_scal) ssa::host_free(ls.host);
+    }
+    v->lslot.clear();
+}
+
+// Ritz triples, info and Hankelization of a long request whose stopping test held.
+int finish_long(ssa_server v, LongSlot& ls) {
+    const Request& r = ls.req;
+    ssa_info info{};
+    const int rc = ssa::run_finish(r.plan, r.sigma, r.U, r.V, &info);
+    int* hi = ls.h_info;
+    if (rc == SSA_ENONFINITE) {
+        hi[0] = 0;
+        hi[1] = -1;  // the series holds NaN or Inf: no triples
+        hi[2] = hi[3] = 0;
+    } else if (rc < 0) {
+        return rc;
+    } else {
+        hi[0] = info.steps;
+        hi[1] = info.converged;
+        hi[2] = info.restarts;
+        hi[3] = info.dgks_passes;
+        if (r.recon) {  // every triple alone, like the batched requests
+            std::vector<int> offs(r.k + 1), mem(r.k);
+            for (int i = 0; i <= r.k; ++i) offs[i] = i;
+            for (int i = 0; i < r.k; ++i) mem[i] = i;
+            const int rr = ssa_reconstruct(r.plan, r.sigma, r.U, r.V, r.k, offs.data(), mem.data(), r.k, r.recon);
+            if (rr != SSA_OK) return rr;
+        }
+    }
+    if (r.info && hipMemcpyAsync(r.info, hi, sizeof(int) * 4, hipMemcpyHostToDevice, ls.stream) != hipSuccess)
+        return SSA_EDEVICE;
+    if (hipEventRecord(ls.fin_ev, ls.stream) != hipSuccess) return SSA_EDEVICE;
+    return SSA_OK;
+}
+
+// One check interval more for active long requests whose previous interval has run (its
+// stopping test included: the interval then waits on nothing), and the finish for each
+// whose test held; at most `limit` of them, round robin.  *did: something was enqueued.
+int advance_long(ssa_server v, bool* did, int limit) {
+    *did = false;
+    const int n = (int)v->lslot.size();
+    for (int t = 0; t < n && limit > 0; ++t) {
+        LongSlot& ls = v->lslot[(v->lrr + t) % n];
+        if (ls.state != kActive) continue;
+        ssa_plan pl = ls.req.plan;
+        if (!ssa::run_idle(pl)) continue;  // still working through its previous interval
+        if (!ssa::run_stopped(pl)) {
+            const int rc = ssa::run_advance(pl, v->cfg.check_every);
+            if (rc != SSA_OK) return rc;
+            *did = true;
+        }
+        if (ssa::run_stopped(pl)) {
+            const int rc = finish_long(v, ls);
+            if (rc != SSA_OK) return rc;
+            ls.state = kFinalizing;
+            *did = true;
+        }
+        v->lrr = (v->lrr + t + 1) % n;
+        --limit;
+    }
+    return SSA_OK;
+}
+
+int server_create(long long n_max, int k_max, int slots, const ssa_opts* opts, void* workspace_dev, size_t bytes,
+                  void* hip_stream, int stub, int stub_ticks, ssa_server* out) {
     if (!out) return SSA_EINVAL;
     *out = nullptr;
-    if (!cfg_valid(n_max, k_max, opts) || slots < 1 || !workspace_dev) return SSA_EINVAL;
-    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256) return SSA_EINVAL;
+    if (!cfg_valid(n_max, k_max, opts) || slots < 1) return SSA_EINVAL;
+    if (!stub && (!workspace_dev || reinterpret_cast<uintptr_t>(workspace_dev) % 256)) return SSA_EINVAL;
+    if (stub && stub_ticks < 1) return SSA_EINVAL;
     ssa_server v = new (std::nothrow) ssa_server_s();
     if (!v) return SSA_EINVAL;
     v->cfg = make_cfg(n_max, k_max, opts);
+    if (opts) v->opts = *opts;
     v->slots = slots;
     v->o_tab = 0;
     v->o_flags = align_up(sizeof(BSeries) * (size_t)slots, 256);
@@ -503,12 +606,68 @@ int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opt
     v->req.assign(slots, Request{});
     v->reg.assign(slots, 0);
     v->reg_bytes.assign(slots, 0);
+    v->stub = stub;
+    v->stub_ticks = stub_ticks;
+    v->stub_left.assign(slots, 0);
     *out = v;
+    return SSA_OK;
+}
+
+// Workspace bytes and host plan of a long request (N above the batched engine's n_max).
+int long_plan(ssa_server v, long long N, long long L, int k, unsigned long long key, ssa_plan* plan,
+              size_t* bytes) {
+    if (v->n_long_max == 0 || N > v->n_long_max || N <= v->cfg.n_max) return SSA_EINVAL;
+    if (L <= 1 || L >= N || k < 1 || k > v->cfg.k_max || k > std::min(L, N - L + 1)) return SSA_EINVAL;
+    ssa_opts o = v->opts;
+    o.seed = long_seed(v->cfg.seed, key);
+    o.restart_keep = 0;
+    o.fft_m1 = o.fft_cb = 0;
+    o.fft_mp = 0;
+    return ssa_embed_plan(N, L, k, &o, bytes, plan);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssa_server_create(long long n_max, int k_max, int slots, const ssa_opts* opts, void* workspace_dev, size_t bytes,
+                      void* hip_stream, ssa_server* out) {
+    return server_create(n_max, k_max, slots, opts, workspace_dev, bytes, hip_stream, 0, 0, out);
+}
+
+int ssa_server_create_stub(long long n_max, int k_max, int slots, const ssa_opts* opts, size_t pool_bytes,
+                           int ticks, ssa_server* out) {
+    return server_create(n_max, k_max, slots, opts, nullptr, pool_bytes, nullptr, 1, ticks, out);
+}
+
+int ssa_server_enable_long(ssa_server v, long long n_long_max, int long_slots) {
+    if (!v || long_slots < 1 || n_long_max <= v->cfg.n_max || n_long_max > (1LL << 24)) return SSA_EINVAL;
+    if (!v->lslot.empty()) return SSA_ESTATE;
+    v->lslot.resize(long_slots);
+    v->n_long_max = n_long_max;
+    if (v->stub) return SSA_OK;
+    for (LongSlot& ls : v->lslot) {
+        if (hipStreamCreateWithFlags(&ls.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ls.fin_ev, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&ls.h_info, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess ||
+            ssa::host_alloc_for(ls.host, v->cfg.k_max, &v->opts) != SSA_OK) {
+            destroy_long(v);
+            v->n_long_max = 0;
+            return SSA_EDEVICE;
+        }
+    }
     return SSA_OK;
 }
 
 int ssa_server_request_bytes(ssa_server v, long long N, long long L, int k, size_t* bytes) {
     if (!v || !bytes) return SSA_EINVAL;
+    if (N > v->cfg.n_max) {
+        ssa_plan pl = nullptr;
+        const int rc = long_plan(v, N, L, k, 0, &pl, bytes);
+        if (pl) ssa_plan_destroy(pl);
+        if (rc == SSA_OK) *bytes = align_up(*bytes, 256);
+        return rc;
+    }
     BSeries t;
     const size_t b = layout_series(v->cfg, N, L, k, 0, t);
     if (b == 0) return SSA_EINVAL;
@@ -520,11 +679,28 @@ int ssa_server_submit(ssa_server v, long long id, unsigned long long key, const 
                       long long L, int k, double* sigma_dev, float* U_dev, float* V_dev, float* recon_dev,
                       int* info_dev) {
     if (!v || !series_dev || !sigma_dev || !U_dev || !V_dev) return SSA_EINVAL;
-    BSeries t;
-    const size_t bytes = layout_series(v->cfg, N, L, k, key, t);
-    if (bytes == 0) return SSA_EINVAL;
-    if (bytes > v->pool.size) return SSA_ENOMEM;  // could never be admitted
-    v->queue.push_back(Request{id, key, series_dev, N, L, k, sigma_dev, U_dev, V_dev, recon_dev, info_dev});
+    Request r{id, key, series_dev, N, L, k, sigma_dev, U_dev, V_dev, recon_dev, info_dev};
+    if (N > v->cfg.n_max) {
+        size_t bytes = 0;
+        ssa_plan pl = nullptr;
+        const int rc = long_plan(v, N, L, k, key, &pl, &bytes);
+        if (rc != SSA_OK) {
+            if (pl) ssa_plan_destroy(pl);
+            return rc;
+        }
+        if (align_up(bytes, 256) > v->pool.size) {  // could never be admitted
+            ssa_plan_destroy(pl);
+            return SSA_ENOMEM;
+        }
+        r.plan = pl;
+        r.bytes = bytes;
+    } else {
+        BSeries t;
+        const size_t bytes = layout_series(v->cfg, N, L, k, key, t);
+        if (bytes == 0) return SSA_EINVAL;
+        if (bytes > v->pool.size) return SSA_ENOMEM;
+    }
+    v->queue.push_back(r);
     return SSA_OK;
 }
 
@@ -532,15 +708,23 @@ int ssa_server_step(ssa_server v, long long* completed, int max_completed, int* 
     if (!v || !ncompleted || max_completed < 0 || (max_completed > 0 && !completed)) return SSA_EINVAL;
     *ncompleted = 0;
     hipStream_t st = v->stream;
-    if (!v->h_tab) {  // pinned staging, allocated at the first tick
-        if (hipHostMalloc((void**)&v->h_tab, sizeof(BSeries) * (size_t)v->slots, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&v->h_flags, sizeof(int) * (size_t)v->slots, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&v->h_lists, sizeof(int) * 3 * (size_t)v->slots, hipHostMallocDefault) !=
-                hipSuccess)
+    if (!v->h_tab) {  // staging, allocated at the first tick (pinned unless the executor is a stub)
+        if (v->stub) {
+            v->h_tab = new BSeries[v->slots];
+            v->h_flags = new int[v->slots];
+            v->h_lists = new int[3 * (size_t)v->slots];
+        } else if (hipHostMalloc((void**)&v->h_tab, sizeof(BSeries) * (size_t)v->slots, hipHostMallocDefault) !=
+                       hipSuccess ||
+                   hipHostMalloc((void**)&v->h_flags, sizeof(int) * (size_t)v->slots, hipHostMallocDefault) !=
+                       hipSuccess ||
+                   hipHostMalloc((void**)&v->h_lists, sizeof(int) * 3 * (size_t)v->slots, hipHostMallocDefault) !=
+                       hipSuccess) {
             return SSA_EDEVICE;
+        }
         std::memset(v->h_flags, 0, sizeof(int) * (size_t)v->slots);
     }
-    // 1. requests finalized in the previous tick are complete (every tick ends synchronized)
+    // 1. requests finalized in the previous tick are complete (every tick ends with the
+    //    batched stream synchronized; a long request when its own stream has run its finish)
     for (int s = 0; s < v->slots; ++s) {
         if (v->state[s] != kFinalizing) continue;
         if (*ncompleted >= max_completed) break;  // the rest are reported next time
@@ -548,6 +732,22 @@ int ssa_server_step(ssa_server v, long long* completed, int max_completed, int* 
         v->pool.release(v->reg[s], v->reg_bytes[s]);
         v->state[s] = kFree;
     }
+    for (LongSlot& ls : v->lslot) {
+        if (ls.state != kFinalizing) continue;
+        if (*ncompleted >= max_completed) break;
+        if (!v->stub && hipEventQuery(ls.fin_ev) != hipSuccess) continue;
+        completed[(*ncompleted)++] = ls.req.id;
+        v->pool.release(ls.reg, ls.bytes);
+        ssa_plan_destroy(ls.req.plan);
+        ls.req.plan = nullptr;
+        ls.state = kFree;
+    }
+    // 2. long requests: one check interval more for each whose last one has run; the
+    //    finish (Ritz triples, Hankelization) for each whose stopping test held: done
+    //    while the batched step below runs (stub: counted down here)
+    if (v->stub)
+        for (LongSlot& ls : v->lslot)
+            if (ls.state == kActive && --ls.stub_left <= 0) ls.state = kFinalizing;
     BatchArgs a{};
     a.tab = reinterpret_cast<const BSeries*>(v->ws + v->o_tab);
     a.ws = v->ws;
@@ -561,57 +761,100 @@ int ssa_server_step(ssa_server v, long long* completed, int max_completed, int* 
     int* l_act = v->h_lists + v->slots;
     int* l_fin = v->h_lists + 2 * v->slots;
     int n_init = 0, n_act = 0, n_fin = 0;
-    // 2. series the previous tick's stopping test finished: Ritz triples and Hankelization
+    // 3. batched series the previous tick's stopping test finished: Ritz triples and Hankelization
     for (int s = 0; s < v->slots; ++s)
         if (v->state[s] == kActive && v->h_flags[s]) l_fin[n_fin++] = s;
-    // 3. admission, first come first served, while a slot and pool memory are free
-    while (!v->queue.empty()) {
-        int s = -1;
-        for (int c = 0; c < v->slots; ++c)
-            if (v->state[c] == kFree) {
-                s = c;
-                break;
+    // 4. admission in arrival order: a request whose class has no free slot lets later
+    //    requests of the other class pass; one that the pool cannot hold stops admission
+    //    (nothing overtakes a request waiting for memory)
+    for (auto it = v->queue.begin(); it != v->queue.end();) {
+        const Request& r = *it;
+        if (r.plan) {
+            int ls_i = -1;
+            for (int c = 0; c < (int)v->lslot.size(); ++c)
+                if (v->lslot[c].state == kFree) {
+                    ls_i = c;
+                    break;
+                }
+            if (ls_i < 0) {
+                ++it;
+                continue;
             }
-        if (s < 0) break;
-        const Request r = v->queue.front();
-        BSeries t;
-        const size_t bytes = layout_series(v->cfg, r.N, r.L, r.k, r.key, t);
-        size_t at = 0;
-        if (!v->pool.alloc(bytes, &at)) break;
-        t.reg = (long long)at;
-        t.f = r.f;
-        t.sigma = r.sigma;
-        t.U = r.U;
-        t.V = r.V;
-        t.recon = r.recon;
-        t.info = r.info;
-        v->h_tab[s] = t;
-        SSA_TRY_HIP(hipMemcpyAsync(v->ws + v->o_tab + sizeof(BSeries) * (size_t)s, &v->h_tab[s], sizeof(BSeries),
-                                   hipMemcpyHostToDevice, st));
-        v->req[s] = r;
-        v->reg[s] = at;
-        v->reg_bytes[s] = bytes;
-        v->state[s] = kActive;
-        v->h_flags[s] = 0;
-        l_init[n_init++] = s;
-        v->queue.pop_front();
+            size_t at = 0;
+            if (!v->pool.alloc(r.bytes, &at)) break;
+            LongSlot& ls = v->lslot[ls_i];
+            ls.req = r;
+            ls.reg = at;
+            ls.bytes = r.bytes;
+            ls.state = kActive;
+            ls.stub_left = v->stub_ticks;
+            if (!v->stub) {
+                int rc = ssa::plan_lend_host(r.plan, ls.host);
+                if (rc == SSA_OK) rc = ssa_plan_bind(r.plan, v->ws + at, align_up(r.bytes, 256), ls.stream);
+                if (rc == SSA_OK) rc = ssa::run_begin(r.plan, r.f, r.k);
+                if (rc == SSA_OK) rc = ssa::run_advance(r.plan, v->cfg.check_every);
+                if (rc != SSA_OK) return rc;
+            }
+        } else {
+            int s = -1;
+            for (int c = 0; c < v->slots; ++c)
+                if (v->state[c] == kFree) {
+                    s = c;
+                    break;
+                }
+            if (s < 0) {
+                ++it;
+                continue;
+            }
+            BSeries t;
+            const size_t bytes = layout_series(v->cfg, r.N, r.L, r.k, r.key, t);
+            size_t at = 0;
+            if (!v->pool.alloc(bytes, &at)) break;
+            t.reg = (long long)at;
+            t.f = r.f;
+            t.sigma = r.sigma;
+            t.U = r.U;
+            t.V = r.V;
+            t.recon = r.recon;
+            t.info = r.info;
+            v->h_tab[s] = t;
+            if (!v->stub)
+                SSA_TRY_HIP(hipMemcpyAsync(v->ws + v->o_tab + sizeof(BSeries) * (size_t)s, &v->h_tab[s],
+                                           sizeof(BSeries), hipMemcpyHostToDevice, st));
+            v->req[s] = r;
+            v->reg[s] = at;
+            v->reg_bytes[s] = bytes;
+            v->state[s] = kActive;
+            v->h_flags[s] = 0;
+            v->stub_left[s] = v->stub_ticks;
+            l_init[n_init++] = s;
+        }
+        it = v->queue.erase(it);
     }
     for (int s = 0; s < v->slots; ++s)
         if (v->state[s] == kActive && !v->h_flags[s]) l_act[n_act++] = s;
+    for (int i = 0; i < n_fin; ++i) v->state[l_fin[i]] = kFinalizing;
+    if (v->stub) {  // no device work: a batched request's test holds after stub_ticks ticks
+        for (int i = 0; i < n_act; ++i) {
+            const int s = l_act[i];
+            if (--v->stub_left[s] <= 0) v->h_flags[s] = 1;
+        }
+        ++v->ticks;
+        return SSA_OK;
+    }
     SSA_TRY_HIP(hipMemcpyAsync(d_lists, v->h_lists, sizeof(int) * 3 * (size_t)v->slots, hipMemcpyHostToDevice, st));
     if (n_fin) {
         a.list = d_lists + 2 * v->slots;
         a.nseries = n_fin;
         SSA_TRY_HIP(launch_batch_ritz(a, st));
         SSA_TRY_HIP(launch_batch_hankel(a, st));
-        for (int i = 0; i < n_fin; ++i) v->state[l_fin[i]] = kFinalizing;
     }
     if (n_init) {
         a.list = d_lists;
         a.nseries = n_init;
         SSA_TRY_HIP(launch_batch_init(a, st));
     }
-    // 4. one Lanczos step of every active series; the stopping test runs where it is due
+    // 5. one Lanczos step of every active batched series; the stopping test runs where it is due
     if (n_act) {
         a.list = d_lists + v->slots;
         a.nseries = n_act;
@@ -622,7 +865,22 @@ int ssa_server_step(ssa_server v, long long* completed, int max_completed, int* 
         SSA_TRY_HIP(launch_batch_cgs(a, 1, st));
     }
     SSA_TRY_HIP(hipMemcpyAsync(v->h_flags, a.done_flags, sizeof(int) * (size_t)v->slots, hipMemcpyDeviceToHost, st));
-    SSA_TRY_HIP(hipStreamSynchronize(st));
+    // The tick ends when the batched stream has run.  Meanwhile the long requests keep
+    // their streams fed, one at a time so that the end of the batched step is seen soon
+    // (each advance is one whole check interval, so the sequence of tests, and with it
+    // the result, does not depend on timing).  With no batched work every long request
+    // gets its interval.
+    const bool batched = n_act + n_fin + n_init > 0;
+    for (;;) {
+        const hipError_t q = hipStreamQuery(st);
+        if (q != hipSuccess && q != hipErrorNotReady) return SSA_EDEVICE;
+        bool did = false;
+        if (q == hipSuccess && batched) break;
+        const int rc = advance_long(v, &did, q == hipSuccess ? (int)v->lslot.size() : 1);
+        if (rc != SSA_OK) return rc;
+        if (q == hipSuccess) break;
+        if (!did) std::this_thread::yield();
+    }
     ++v->ticks;
     return SSA_OK;
 }
@@ -634,6 +892,10 @@ int ssa_server_status(ssa_server v, int* queued, int* active, int* finalizing, s
         na += v->state[s] == kActive;
         nf += v->state[s] == kFinalizing;
     }
+    for (const LongSlot& ls : v->lslot) {
+        na += ls.state == kActive;
+        nf += ls.state == kFinalizing;
+    }
     if (queued) *queued = (int)v->queue.size();
     if (active) *active = na;
     if (finalizing) *finalizing = nf;
@@ -643,10 +905,19 @@ int ssa_server_status(ssa_server v, int* queued, int* active, int* finalizing, s
 
 void ssa_server_destroy(ssa_server v) {
     if (!v) return;
-    if (v->h_tab) (void)hipStreamSynchronize(v->stream);
-    if (v->h_tab) (void)hipHostFree(v->h_tab);
-    if (v->h_flags) (void)hipHostFree(v->h_flags);
-    if (v->h_lists) (void)hipHostFree(v->h_lists);
+    if (!v->stub && v->h_tab) (void)hipStreamSynchronize(v->stream);
+    destroy_long(v);
+    for (Request& r : v->queue)
+        if (r.plan) ssa_plan_destroy(r.plan);
+    if (v->stub) {
+        delete[] v->h_tab;
+        delete[] v->h_flags;
+        delete[] v->h_lists;
+    } else {
+        if (v->h_tab) (void)hipHostFree(v->h_tab);
+        if (v->h_flags) (void)hipHostFree(v->h_flags);
+        if (v->h_lists) (void)hipHostFree(v->h_lists);
+    }
     delete v;
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "fft_lds.h"
+#include "ssa.h"
 
 namespace ssa {
 
@@ -266,6 +267,39 @@ hipError_t set_fused_attributes();
 hipError_t launch_lz_check(const LzCheck& a, hipStream_t s);
 hipError_t launch_lz_ritz(const LzRitz& a, int d, hipStream_t s);
 hipError_t set_lz_attributes();
+
+// Resumable single-series solve on a bound plan without thick restart (api.cpp): begin
+// (embed, start vector), advance (up to max_steps Lanczos steps; the stopping test at its
+// check points), stopped (a test ended the solve), idle (every step and test enqueued so far
+// has run; no waiting), finish (Ritz triples; ends the run).  ssa_truncated_svd runs them
+// in a row; the served form advances each long request one check interval per tick.
+int run_begin(ssa_plan p, const double* series_dev, int k);
+
+// Host-side resources of a bound plan (pinned staging, events, the check stream).  A plan
+// allocates its own at its first bind; a caller that admits and retires many plans lends
+// one set instead (plan_lend_host before the bind), so that nothing is allocated or freed
+// per plan -- freeing pinned memory can wait for the whole device.
+struct PlanHost {
+    double* h_scal = nullptr;
+    size_t n_scal = 0;
+    double* h_flag = nullptr;
+    double* h_rec = nullptr;
+    size_t n_rec = 0;
+    int* h_grp = nullptr;
+    size_t n_grp = 0;
+    hipEvent_t grp_done = nullptr;
+    hipEvent_t chk_ev[2] = {nullptr, nullptr};
+    hipEvent_t ab_ev = nullptr, run_ev = nullptr;
+    hipStream_t chk_stream = nullptr;
+};
+int host_alloc(PlanHost& h, size_t n_scal, size_t n_rec, size_t n_grp);
+int host_alloc_for(PlanHost& h, int k_max, const ssa_opts* opts);  // enough for any plan with this k_max
+void host_free(PlanHost& h);
+int plan_lend_host(ssa_plan p, const PlanHost& h);
+int run_advance(ssa_plan p, int max_steps);
+int run_stopped(ssa_plan p);
+int run_idle(ssa_plan p);
+int run_finish(ssa_plan p, double* sigma_dev, float* U_dev, float* V_dev, ssa_info* info);
 hipError_t set_kernel_attributes();
 // set_kernel_attributes() once per process; its result afterwards (api.cpp)
 hipError_t kernel_attributes_once();

@@ -52,7 +52,7 @@ EXPORTED = ("ssa_embed_plan", "ssa_embed_plan_2d", "ssa_plan_bind", "ssa_embed",
             "ssa_bidiag_ritz", "ssa_dense_ritz", "ssa_profile_enable", "ssa_profile_read", "ssa_profile_sample",
             "ssa_batch_plan", "ssa_batch_workspace", "ssa_batch_bind", "ssa_batch_solve",
             "ssa_batch_profile_enable", "ssa_batch_profile_read", "ssa_batch_destroy",
-            "ssa_server_create", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
+            "ssa_server_create", "ssa_server_enable_long", "ssa_server_create_stub", "ssa_server_request_bytes", "ssa_server_submit", "ssa_server_step",
             "ssa_server_status", "ssa_server_destroy", "ssa_hmatrix_workspace", "ssa_hmatrix",
             "ssa_realizations_workspace", "ssa_realizations", "ssa_tune_workspace", "ssa_tune_fft")
 
@@ -114,6 +114,9 @@ def load():
     lib.ssa_batch_destroy.restype = None
     lib.ssa_server_create.argtypes = [_c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts), _c_p,
                                       ctypes.c_size_t, _c_p, ctypes.POINTER(_c_p)]
+    lib.ssa_server_enable_long.argtypes = [_c_p, _c_ll, ctypes.c_int]
+    lib.ssa_server_create_stub.argtypes = [_c_ll, ctypes.c_int, ctypes.c_int, ctypes.POINTER(SsaOpts), ctypes.c_size_t,
+                                           ctypes.c_int, ctypes.POINTER(_c_p)]
     lib.ssa_server_request_bytes.argtypes = [_c_p, _c_ll, _c_ll, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     lib.ssa_server_submit.argtypes = [_c_p, _c_ll, ctypes.c_ulonglong, _c_p, _c_ll, _c_ll, ctypes.c_int, _c_p, _c_p,
                                       _c_p, _c_p, _c_p]
@@ -514,11 +517,14 @@ class Batch:
 
 class Server:
     """Continuous batching of SSA requests (``ssa_server_*``): a device pool of
-    ``pool_bytes`` (the HBM budget), ``slots`` requests in flight, one Lanczos step of
-    every admitted request per tick."""
+    ``pool_bytes`` (the HBM budget), ``slots`` batched requests (N <= n_max) in flight,
+    one Lanczos step of every admitted one per tick; with ``long_slots`` > 0 also up to
+    that many longer requests (N <= n_long_max), each advanced one check interval per tick
+    on a plan bound to its pool region."""
 
     def __init__(self, n_max: int, k_max: int, slots: int, pool_bytes: int, d_max: int = 0,
-                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None, reorth: int = 0):
+                 check_every: int = 0, tol: float = 0.0, seed: int = 0, device=None, stream=None, reorth: int = 0,
+                 n_long_max: int = 0, long_slots: int = 0):
         import torch
         self._torch = torch
         lib = load()
@@ -532,8 +538,11 @@ class Server:
         _check(lib.ssa_server_create(int(n_max), int(k_max), int(slots), ctypes.byref(opts), base + (-base) % 256,
                                      int(pool_bytes), self.stream.cuda_stream, ctypes.byref(h)), "ssa_server_create")
         self._h = h
-        self.slots = int(slots)
+        self.slots = int(slots) + int(long_slots)
+        self.n_max = int(n_max)
         self._live = {}
+        if long_slots:
+            _check(lib.ssa_server_enable_long(h, int(n_long_max), int(long_slots)), "ssa_server_enable_long")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -566,6 +575,8 @@ class Server:
             "recon": torch.empty((k, N), dtype=torch.float32, device=self.device) if recon else None,
             "info": torch.zeros(4, dtype=torch.int32, device=self.device),
         }
+        if N > self.n_max:  # solved on a stream of its own: the inputs and outputs must be ready
+            torch.cuda.current_stream(self.device).synchronize()
         _check(self.lib.ssa_server_submit(self._h, int(rid), int(rid if key is None else key), f.data_ptr(), N,
                                           int(L), int(k), out["sigma"].data_ptr(), out["U"].data_ptr(),
                                           out["V"].data_ptr(), out["recon"].data_ptr() if recon else None,

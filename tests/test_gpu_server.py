@@ -83,3 +83,50 @@ def test_server_rejects_oversized_request(ssa):
         srv.submit(0, f, 700, 16)  # region larger than the whole pool
     with pytest.raises(ssa.SsaError):
         srv.submit(1, np.zeros(3000), 1000, 8)  # longer than n_max
+
+
+def run_mixed(ssa, reqs, long_slots, pool_bytes, slots=4):
+    """Serve (rid, f, L, k, key) requests, all submitted at once, on a server whose batched
+    engine takes N <= 1500; longer ones go to the long path."""
+    srv = ssa.Server(n_max=1500, k_max=16, slots=slots, pool_bytes=pool_bytes, n_long_max=1 << 17,
+                     long_slots=long_slots)
+    free0 = srv.status()["pool_free"]
+    for rid, f, L, k, key in reqs:
+        srv.submit(rid, f, L, k, key=key)
+    done, ticks = {}, 0
+    while len(done) < len(reqs):
+        for rid, out in srv.step():
+            done[rid] = out
+        ticks += 1
+        assert ticks < 20000
+    torch.cuda.synchronize()
+    st = srv.status()
+    say(f"mixed server: {len(reqs)} requests in {ticks} ticks, status {st}")
+    assert st["queued"] == 0 and st["active"] == 0 and st["finalizing"] == 0 and st["pool_free"] == free0
+    srv.close()
+    return done
+
+
+def test_long_request_same_bits_alone_and_in_the_mix(ssa):
+    """A request above the batched engine's n_max runs the single-series solver on a plan
+    bound to its pool region, advanced one check interval per tick.  It gives the same bits
+    served alone and served beside another long request and batched ones (its key seeds its
+    start vector), and agrees with the FP64 oracle."""
+    from paper_0911_4498_amd import inputs
+    fA, _, _ = inputs.c3_series(5, N=6000)
+    fB, _, _ = inputs.c3_series(6, N=60000)
+    series, Ls, ks = small_batch(6)
+    say("long request alone")
+    alone = run_mixed(ssa, [(0, fA, 3000, 12, 77)], long_slots=1, pool_bytes=1 << 30)[0]
+    say("long request in the mix")
+    mix = [(1, fB, 30000, 16, 78)] + [(10 + s, series[s], Ls[s], ks[s], 500 + s) for s in range(3)]
+    mix += [(0, fA, 3000, 12, 77)] + [(10 + s, series[s], Ls[s], ks[s], 500 + s) for s in range(3, 6)]
+    done = run_mixed(ssa, mix, long_slots=2, pool_bytes=1 << 30)
+    for key in ("sigma", "U", "V", "recon", "info"):
+        assert np.array_equal(done[0][key].cpu().numpy(), alone[key].cpu().numpy()), key
+    info = alone["info"].cpu().numpy()
+    say(f"long request: info {info}")
+    assert info[1] == 1
+    rep = compare_one(fA, 3000, 12, alone["sigma"], alone["U"], alone["V"], alone["recon"], dense=False)
+    say(f"long request against the oracle: {rep}")
+    assert done[1]["info"].cpu().numpy()[1] == 1
