@@ -61,6 +61,9 @@ CLASS_KERNEL = {"pass1": "k_pass1<0", "pass2": "k_pass2_matvec", "pass3": "k_pas
                 "cgs_dots": "k_cgs_project", "cgs_reduce": "k_cgs_reduce", "cgs_update": "k_cgs_update",
                 "ritz": "k_ritz", "recon_pass1": "k_pass1<2", "recon_pass2": "k_pass2_recon",
                 "recon_pass3": "k_pass3<1"}
+# on the fused half-step (the default single-series path) passes 1 and 3 carry the update
+# and the projection: their kernels are these
+CLASS_KERNEL_FUSED = {**CLASS_KERNEL, "pass1": "k_p1_update", "pass3": "k_p3_project"}
 
 
 def traffic_summary_path(cls, workload="c2"):
@@ -743,6 +746,7 @@ def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
+            "kernel_name": (CLASS_KERNEL if plan_kw.get("unfused") else CLASS_KERNEL_FUSED).get(dom, dom),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

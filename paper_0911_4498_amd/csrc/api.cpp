@@ -255,24 +255,33 @@ struct ProfScope {
     ssa_plan p;
     int cls;
     double bytes;
-    hipEvent_t e0 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t st;
+    // A timed launch gets the kernel's own start and end timestamps when its launcher
+    // goes through SSA_LAUNCH (it consumes ssa::g_launch_timing); otherwise the two
+    // events bracket the scope on the stream.
     ProfScope(ssa_plan p_, int cls_, double bytes_, hipStream_t st_ = nullptr)
         : p(p_), cls(cls_), bytes(bytes_), st(st_ ? st_ : p_->stream) {
         if (p->prof_on && (p->prof_mask >> cls & 1u) && p->prof_seen[cls]++ % p->prof_every == 0) {
             e0 = next_event(p);
-            if (e0) (void)hipEventRecord(e0, st);
+            e1 = e0 ? next_event(p) : nullptr;
+            if (e0 && e1) {
+                (void)hipEventRecord(e0, st);
+                ssa::g_launch_timing = {e0, e1};
+            } else {
+                e0 = e1 = nullptr;
+            }
         }
     }
     ~ProfScope() {
         p->prof_bytes[cls] += bytes;
         p->prof_count[cls] += 1;
         if (p->prof_on && e0) {
-            hipEvent_t e1 = next_event(p);
-            if (e1) {
+            if (ssa::g_launch_timing.start == e0) {  // no launch consumed them
+                ssa::g_launch_timing = {};
                 (void)hipEventRecord(e1, st);
-                p->prof_pairs[cls].push_back({e0, e1});
             }
+            p->prof_pairs[cls].push_back({e0, e1});
         }
     }
 };

@@ -365,9 +365,9 @@ hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a
     const dim3 grid((g.M2 + g.CB - 1) / g.CB);
     const size_t lds = fused_p3_lds(g, a.lay);
     if (fused_ept((long long)g.CB * g.M1) == 4)
-        hipLaunchKernelGGL(k_p3_project<4>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
+        SSA_LAUNCH(k_p3_project<4>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
     else
-        hipLaunchKernelGGL(k_p3_project<8>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
+        SSA_LAUNCH(k_p3_project<8>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
     return hipGetLastError();
 }
 
@@ -375,9 +375,9 @@ hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipSt
     const dim3 grid((g.M2 + g.CB - 1) / g.CB);
     const size_t lds = fused_p1_lds(g, a.ncols);
     if (fused_ept((long long)g.CB * g.M1) == 4)
-        hipLaunchKernelGGL(k_p1_update<4>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+        SSA_LAUNCH(k_p1_update<4>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
     else
-        hipLaunchKernelGGL(k_p1_update<8>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+        SSA_LAUNCH(k_p1_update<8>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
     return hipGetLastError();
 }
 
@@ -390,7 +390,7 @@ hipError_t launch_ritz_seg(const float* basis, long long ld, int ncols, const do
                            long long ldo, const SegLay& lay, hipStream_t s) {
     const dim3 grid((unsigned)((lay.len + 255) / 256), (unsigned)((k + kRitzSegTile - 1) / kRitzSegTile));
     const size_t lds = sizeof(double) * (size_t)ncols * kRitzSegTile;
-    hipLaunchKernelGGL(k_ritz_seg, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, lay);
+    SSA_LAUNCH(k_ritz_seg, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, lay);
     return hipGetLastError();
 }
 

@@ -23,6 +23,8 @@
 
 namespace ssa {
 
+thread_local LaunchTiming g_launch_timing;
+
 // ---------------------------------------------------------------------------
 // twiddle tables (FP64 angles, rounded once to FP32)
 
@@ -1036,9 +1038,9 @@ hipError_t launch_pass2_matvec(const ConvGeom& g, const float4* AB, const float2
     const dim3 grid(g.M1 / 2 + 1);
     const int ept = ept_for(2LL * g.M2, 256);
     if (pass_big(2LL * g.M2))
-        hipLaunchKernelGGL((k_pass2_matvec<8, kBigThreads>), grid, dim3(kBigThreads), lds_p2(g), s, g, AB, T1, T2);
+        SSA_LAUNCH((k_pass2_matvec<8, kBigThreads>), grid, dim3(kBigThreads), lds_p2(g), s, g, AB, T1, T2);
     else
-        SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_matvec<E>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2));
+        SSA_EPT_SWITCH(ept, SSA_LAUNCH((k_pass2_matvec<E>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2));
     return hipGetLastError();
 }
 
@@ -1157,7 +1159,7 @@ hipError_t launch_cgs_colsum(const ReduceArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_cgs_reduce(const ReduceArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_cgs_reduce, dim3(1), dim3(kReduceThreads), 0, s, a);
+    SSA_LAUNCH(k_cgs_reduce, dim3(1), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -7,8 +7,29 @@
 
 #include "fft_lds.h"
 #include "ssa.h"
+#include <hip/hip_ext.h>
 
 namespace ssa {
+
+// Timing of one launch by the kernel's own start and end timestamps, the ones a kernel
+// profiler reads (events recorded around a launch would also count its dispatch): the
+// library's profiler sets these for the next launch of a timed class, and SSA_LAUNCH hands
+// them to hipExtLaunchKernelGGL.  Host-thread local; a launch consumes them.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
+#define SSA_LAUNCH(kern, grid, block, shmem, stream, ...)                                              \
+    do {                                                                                               \
+        if (::ssa::g_launch_timing.start) {                                                            \
+            const ::ssa::LaunchTiming t_ = ::ssa::g_launch_timing;                                     \
+            ::ssa::g_launch_timing = {};                                                               \
+            hipExtLaunchKernelGGL(kern, grid, block, shmem, stream, t_.start, t_.stop, 0, __VA_ARGS__); \
+        } else {                                                                                       \
+            hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);                         \
+        }                                                                                              \
+    } while (0)
 
 // Geometry of the half-length complex FFT used for every real convolution of
 // length M: M' = M/2 = M1 * M2 points, "four-step" order.  Pass 1 transforms
