@@ -562,6 +562,8 @@ def main():
                     default="single")
     ap.add_argument("--s2-sizes", default="48x48,256x256,1024x1024", help="array sizes (2d workload)")
     ap.add_argument("--s2-oracle-max", type=int, default=600, help="largest Lx*Ly timed with the dense oracle")
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="Lanczos steps between stopping tests (single workload; 0: the library default, 4)")
     ap.add_argument("--unfused", type=int, choices=(0, 1), default=0,
                     help="1: six launches per Lanczos half-step instead of the fused four (A/B switch)")
     ap.add_argument("--reorth", type=int, choices=(0, 1), default=0,
@@ -609,7 +611,8 @@ def main():
                           "AR(1) noise (seed 1002); truncated SVD + 20 elementary reconstructions",
               "N": N, "L": L, "k": K_TRIPLES, "reorth": "one-sided" if args.reorth else "full",
               "parallelism": "single GPU"}
-    out = bench_plan(args, f_np, L, K_TRIPLES, {"reorth": args.reorth, "unfused": args.unfused},
+    out = bench_plan(args, f_np, L, K_TRIPLES,
+                     {"reorth": args.reorth, "unfused": args.unfused, "check_every": args.check_every},
                      "eigentriples/s (N=1e5, L=N/2, k=20)", config, traffic_per_launch)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle sample)", file=sys.stderr, flush=True)

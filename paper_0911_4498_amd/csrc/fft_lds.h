@@ -230,4 +230,36 @@ __device__ void lds_fft(float2* buf, const FftStages& st, int nseq, int sstride,
     lds_fft_tw<DIR, EPT>(buf, st, nseq, sstride, TableTw{tw}, tid, nthr);
 }
 
+// Radix sequences known at compile time.  A kernel instantiated with FftFixed<R...> inlines
+// exactly those stages (no run-time radix switch): its code is a fraction of the generic
+// one's, which matters when each launch is short and starts with cold instruction caches.
+// FftGeneric runs the sequence of the FftStages argument.
+struct FftGeneric {
+    static __host__ __device__ bool matches(const FftStages&) { return true; }
+};
+template <int... R>
+struct FftFixed {
+    static __host__ __device__ bool matches(const FftStages& st) {
+        constexpr int r[] = {R...};
+        if (st.nstages != (int)sizeof...(R)) return false;
+        for (int i = 0; i < (int)sizeof...(R); ++i)
+            if (st.radix[i] != r[i]) return false;
+        return true;
+    }
+};
+
+template <int DIR, int EPT>
+__device__ __forceinline__ void fft_run(FftGeneric, float2* buf, const FftStages& st, int nseq, int sstride,
+                                        const float2* __restrict__ tw, int tid, int nthr) {
+    lds_fft<DIR, EPT>(buf, st, nseq, sstride, tw, tid, nthr);
+}
+
+template <int DIR, int EPT, int... R>
+__device__ __forceinline__ void fft_run(FftFixed<R...>, float2* buf, const FftStages&, int nseq, int sstride,
+                                        const float2* __restrict__ tw, int tid, int nthr) {
+    constexpr int n = (R * ...);  // the length, and with it every stride and twiddle step, is a constant
+    int p = 1;
+    ((fft_stage<R, DIR, EPT>(buf, n, nseq, sstride, p, TableTw{tw}, tid, nthr), p *= R), ...);
+}
+
 }  // namespace ssa

@@ -44,7 +44,7 @@ __host__ __device__ inline int fused_fft_lds_words(const ConvGeom& g) {
 // [2*c0*S, 2*(c0 + CB)*S).  The loads that do not depend on the transform (the
 // three-term vector and the first basis columns of each wave) are issued before
 // it, so their latency hides behind the column FFT.
-template <int EPT>
+template <int EPT, typename F1 = FftGeneric>
 __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const float2* __restrict__ T2, P3Seg a) {
     if (g.stop && *g.stop != 0.0) return;
     extern __shared__ float2 smem[];
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
         buf[c * ss + k1] = z;
     }
     __syncthreads();
-    lds_fft<1, EPT>(buf, g.st1, CB, ss, tw, tid, kFusedThreads);
+    fft_run<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int q = tid; q < nsl; q += kFusedThreads) {
         const int sg = q / S, t = q - sg * S;
         const int c = sg >> 1, e = sg & 1, n2 = c0 + c;
@@ -216,7 +216,7 @@ __device__ __forceinline__ void fused_finish_group(const P1Seg& a, const SegSrc*
     *reinterpret_cast<float4*>(a.out + p) = make_float4(o[0], o[1], o[2], o[3]);
 }
 
-template <int EPT>
+template <int EPT, typename F1 = FftGeneric>
 __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a, float2* __restrict__ T1) {
     if (g.stop && *g.stop != 0.0) return;
     extern __shared__ float2 smem[];
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
         }
     }
     __syncthreads();
-    lds_fft<-1, EPT>(buf, g.st1, CB, ss, tw, tid, kFusedThreads);
+    fft_run<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int idx = tid; idx < CB * M1; idx += kFusedThreads) {
         const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
         if (n2 < M2) T1[(long long)k1 * M2 + n2] = cmul(buf[c * ss + k1], twiddle_mp(g, (long long)n2 * k1));
@@ -364,20 +364,28 @@ size_t fused_p1_lds(const ConvGeom& g, int ncols) {
 hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a, hipStream_t s) {
     const dim3 grid((g.M2 + g.CB - 1) / g.CB);
     const size_t lds = fused_p3_lds(g, a.lay);
-    if (fused_ept((long long)g.CB * g.M1) == 4)
-        SSA_LAUNCH(k_p3_project<4>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
-    else
+    if (fused_ept((long long)g.CB * g.M1) != 4)
         SSA_LAUNCH(k_p3_project<8>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
+    else if (FftPlanA::matches(g.st1))
+        SSA_LAUNCH((k_p3_project<4, FftPlanA>), grid, dim3(kFusedThreads), lds, s, g, T2, a);
+    else if (FftPlanB::matches(g.st1))
+        SSA_LAUNCH((k_p3_project<4, FftPlanB>), grid, dim3(kFusedThreads), lds, s, g, T2, a);
+    else
+        SSA_LAUNCH(k_p3_project<4>, grid, dim3(kFusedThreads), lds, s, g, T2, a);
     return hipGetLastError();
 }
 
 hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s) {
     const dim3 grid((g.M2 + g.CB - 1) / g.CB);
     const size_t lds = fused_p1_lds(g, a.ncols);
-    if (fused_ept((long long)g.CB * g.M1) == 4)
-        SSA_LAUNCH(k_p1_update<4>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
-    else
+    if (fused_ept((long long)g.CB * g.M1) != 4)
         SSA_LAUNCH(k_p1_update<8>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+    else if (FftPlanA::matches(g.st1))
+        SSA_LAUNCH((k_p1_update<4, FftPlanA>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
+    else if (FftPlanB::matches(g.st1))
+        SSA_LAUNCH((k_p1_update<4, FftPlanB>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
+    else
+        SSA_LAUNCH(k_p1_update<4>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
     return hipGetLastError();
 }
 

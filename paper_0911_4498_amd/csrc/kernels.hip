@@ -184,7 +184,7 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 }
 
 // pass 2 of a trajectory-matrix product: Q(k) = A(k) Z(k) + B(k) conj Z(M'-k)
-template <int EPT, int NT = 256>
+template <int EPT, int NT = 256, typename F2 = FftGeneric>
 __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
                                                       const float2* __restrict__ T1,
                                                       float2* __restrict__ T2) {
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         }
     }
     __syncthreads();
-    lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     int i = 0;
     for (int p = tid; p < rp.npairs; p += nthr, ++i) {
         int s0, e0, s1, e1;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         if (s0 != s1 || e0 != e1) buf[s1 * M2 + e1] = q1;
     }
     __syncthreads();
-    lds_fft<1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2, rp, M2, tid, nthr);
 }
 
@@ -1039,6 +1039,10 @@ hipError_t launch_pass2_matvec(const ConvGeom& g, const float4* AB, const float2
     const int ept = ept_for(2LL * g.M2, 256);
     if (pass_big(2LL * g.M2))
         SSA_LAUNCH((k_pass2_matvec<8, kBigThreads>), grid, dim3(kBigThreads), lds_p2(g), s, g, AB, T1, T2);
+    else if (ept == 4 && FftPlanB::matches(g.st2))
+        SSA_LAUNCH((k_pass2_matvec<4, 256, FftPlanB>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2);
+    else if (ept == 4 && FftPlanA::matches(g.st2))
+        SSA_LAUNCH((k_pass2_matvec<4, 256, FftPlanA>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2);
     else
         SSA_EPT_SWITCH(ept, SSA_LAUNCH((k_pass2_matvec<E>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2));
     return hipGetLastError();

@@ -52,6 +52,12 @@ struct ConvGeom {
     const double* stop = nullptr;  // non-null: the product kernels return at once while *stop != 0
 };
 
+// The radix sequences with kernels of their own (FftFixed, fft_lds.h): 200 = 8·5·5 and
+// 256 = 8·8·4, the two factors of the tuned split M' = 51200 of N = 1e5 series (the
+// schedule tuner's winner and runner-up).  Every other length runs the generic kernels.
+using FftPlanA = FftFixed<8, 5, 5>;
+using FftPlanB = FftFixed<8, 8, 4>;
+
 // pass-1 input modes
 enum { IN_REV = 0, IN_SERIES = 1, IN_VECS = 2 };
 // pass-3 output modes
