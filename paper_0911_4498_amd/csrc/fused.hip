@@ -39,6 +39,24 @@ __host__ __device__ inline int fused_fft_lds_words(const ConvGeom& g) {
     return w + (w & 1);
 }
 
+// 32-bit forms of seg_lo / seg_count for these kernels: a fused plan holds at most 2^20
+// rows, so every y index stays below 2^22, and a 32-bit division costs a fraction of the
+// 64-bit one (these sit at the head of each workgroup's dependence chain).
+__device__ __forceinline__ int seg_lo32(const SegLay& l, int n2, int e) {
+    const int a = (int)l.o - 2 * n2 - e;
+    const unsigned step = 2u * (unsigned)l.M2;
+    return a <= 0 ? 0 : (int)(((unsigned)a + step - 1u) / step);
+}
+
+__device__ __forceinline__ int seg_count32(const SegLay& l, int n2, int e) {
+    const int b = (int)(l.o + l.n) - 1 - 2 * n2 - e;
+    if (b < 0) return 0;
+    int hi = (int)((unsigned)b / (2u * (unsigned)l.M2));
+    if (hi > l.M1 - 1) hi = l.M1 - 1;
+    const int lo = seg_lo32(l, n2, e);
+    return hi >= lo ? hi - lo + 1 : 0;
+}
+
 // Pass 3 + three-term term + projection partials.  Workgroup b (XCD-ordered)
 // owns the columns [c0, c0 + CB) of the four-step layout, i.e. the output slots
 // [2*c0*S, 2*(c0 + CB)*S).  The loads that do not depend on the transform (the
@@ -84,8 +102,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
         const int sg = q / S, t = q - sg * S;
         const int c = sg >> 1, e = sg & 1, n2 = c0 + c;
         float v = 0.0f;
-        if (t < seg_count(a.lay, n2, e)) {
-            const float2 z = buf[c * ss + (int)(seg_lo(a.lay, n2, e) + t)];
+        if (t < seg_count32(a.lay, n2, e)) {
+            const float2 z = buf[c * ss + seg_lo32(a.lay, n2, e) + t];
             v = e ? z.y : z.x;
             if (a.prev) v -= cf * (q == tid ? pv0 : a.prev[base + q]);
         }
@@ -145,15 +163,21 @@ struct SegSrc {
 // element of x (m' < 0): its segment only gets its zeros written.
 __device__ __forceinline__ SegSrc seg_source(const P1Seg& a, int M2, int S, int c0, int sl) {
     const int c = sl >> 1, e = sl & 1, n2 = c0 + c;
-    const long long A = a.N - 1 - e - 2LL * n2;
-    const int ep = (int)(A & 1);
-    const long long H = (A - ep) / 2;  // exact
-    const int n2p = (int)(((H % M2) + M2) % M2);
+    const int A = (int)a.N - 1 - e - 2 * n2;  // N < 2^22 on the fused path
+    const int ep = A & 1;
+    const int H = (A - ep) / 2;  // exact
+    int n2p, Q = 0;
+    if (H >= 0) {
+        Q = (int)((unsigned)H / (unsigned)M2);
+        n2p = H - Q * M2;
+    } else {
+        n2p = ((H % M2) + M2) % M2;
+    }
     SegSrc d;
-    d.pos = (2LL * n2p + ep) * S;
-    d.Q = A >= 0 ? (int)(H / M2) : 0;
-    d.lo = (int)seg_lo(a.lay, n2p, ep);
-    d.cnt = A >= 0 ? seg_count(a.lay, n2p, ep) : 0;
+    d.pos = (long long)(2 * n2p + ep) * S;
+    d.Q = A >= 0 ? Q : 0;
+    d.lo = seg_lo32(a.lay, n2p, ep);
+    d.cnt = A >= 0 ? seg_count32(a.lay, n2p, ep) : 0;
     return d;
 }
 
@@ -412,6 +436,10 @@ hipError_t set_fused_attributes() {
     allow(reinterpret_cast<const void*>(k_p3_project<8>));
     allow(reinterpret_cast<const void*>(k_p1_update<4>));
     allow(reinterpret_cast<const void*>(k_p1_update<8>));
+    allow(reinterpret_cast<const void*>(k_p3_project<4, FftPlanA>));
+    allow(reinterpret_cast<const void*>(k_p3_project<4, FftPlanB>));
+    allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanA>));
+    allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanB>));
     allow(reinterpret_cast<const void*>(k_ritz_seg));
     return e;
 }

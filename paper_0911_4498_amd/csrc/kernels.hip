@@ -300,7 +300,7 @@ __global__ __launch_bounds__(NT) void k_pass2_embed(ConvGeom g, const float2* __
 // pairs live in registers, so NP is the smallest that covers the row (1 for rows of up
 // to 1024 points) rather than the largest (4 would spill them to scratch memory).
 constexpr int kReconThreads = 1024;
-template <int EPT, int NP>
+template <int EPT, int NP, typename F2 = FftGeneric>
 __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const float2* __restrict__ T1all,
                                                               int k, const double* __restrict__ sigma,
                                                               const int* __restrict__ offs,
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         __syncthreads();
         load_rows<EPT>(buf, T1all + (long long)tri * Mp, rp, M2, tid, nthr);
         __syncthreads();
-        lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+        fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             const int p = tid + i * nthr;
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         // v_i spectrum rows
         load_rows<EPT>(buf, T1all + (long long)(k + tri) * Mp, rp, M2, tid, nthr);
         __syncthreads();
-        lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+        fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             const int p = tid + i * nthr;
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         }
     }
     __syncthreads();
-    lds_fft<1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2all + (long long)blockIdx.y * Mp, rp, M2, tid, nthr);
 }
 
@@ -1067,7 +1067,13 @@ hipError_t launch_pass2_recon(const ConvGeom& g, const float2* T1all, int k, con
 #define SSA_RECON(NPV)                                                                                  \
     SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass2_recon<E, NPV>), grid, dim3(kReconThreads), lds_p2(g), s, g, \
                                            T1all, k, sigma, offs, members, g0, T2all))
-    if (np <= 1) {
+    if (np <= 1 && ept == 4 && FftPlanB::matches(g.st2)) {
+        hipLaunchKernelGGL((k_pass2_recon<4, 1, FftPlanB>), grid, dim3(kReconThreads), lds_p2(g), s, g, T1all, k,
+                           sigma, offs, members, g0, T2all);
+    } else if (np <= 1 && ept == 4 && FftPlanA::matches(g.st2)) {
+        hipLaunchKernelGGL((k_pass2_recon<4, 1, FftPlanA>), grid, dim3(kReconThreads), lds_p2(g), s, g, T1all, k,
+                           sigma, offs, members, g0, T2all);
+    } else if (np <= 1) {
         SSA_RECON(1);
     } else if (np <= 2) {
         SSA_RECON(2);
@@ -1217,6 +1223,8 @@ hipError_t set_kernel_attributes() {
     SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads>));
     SSA_ALLOW((k_pass2_matvec<8, kBigThreads>)); SSA_ALLOW((k_pass2_embed<8, kBigThreads>));
     SSA_ALLOW_EPT(k_pass2_matvec);
+    SSA_ALLOW((k_pass2_matvec<4, 256, FftPlanA>)); SSA_ALLOW((k_pass2_matvec<4, 256, FftPlanB>));
+    SSA_ALLOW((k_pass2_recon<4, 1, FftPlanA>)); SSA_ALLOW((k_pass2_recon<4, 1, FftPlanB>));
     SSA_ALLOW_EPT(k_pass2_embed);
 #define SSA_ALLOW_RECON(NPV)                                                                   \
     SSA_ALLOW((k_pass2_recon<4, NPV>)); SSA_ALLOW((k_pass2_recon<8, NPV>));                      \

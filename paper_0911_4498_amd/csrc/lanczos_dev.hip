@@ -276,7 +276,7 @@ __global__ __launch_bounds__(64) void k_lz_orth(LzRitz a) {
 
 constexpr int kInvitArrays = 8;           // D, E, x and the factor rows A, 1/A, Bv, U2, F
 constexpr size_t kRitzLdsMax = 64 * 1024; // larger bases take the global-memory kernels
-constexpr int kOrthThreads = 1024;
+constexpr int kOrthThreads = 256;  // few waves: the orthonormalization is a chain of short phases
 constexpr int kOrthWaves = kOrthThreads / 64;
 
 size_t invit_lds_bytes(int d) { return (sizeof(double) * kInvitArrays + 1) * (size_t)d; }
