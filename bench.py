@@ -564,8 +564,10 @@ def main():
     ap.add_argument("--s2-oracle-max", type=int, default=600, help="largest Lx*Ly timed with the dense oracle")
     ap.add_argument("--check-every", type=int, default=0,
                     help="Lanczos steps between stopping tests (single workload; 0: the library default, 4)")
-    ap.add_argument("--unfused", type=int, choices=(0, 1), default=0,
-                    help="1: six launches per Lanczos half-step instead of the fused four (A/B switch)")
+    ap.add_argument("--unfused", type=int, choices=(0, 1, 2), default=0,
+                    help="1: six launches per Lanczos half-step; 2: the fused four (the reduction as "
+                         "its own launch); 0: the fused path with each reduction folded into the next "
+                         "pass 1 where it applies (A/B switch)")
     ap.add_argument("--reorth", type=int, choices=(0, 1), default=0,
                     help="0: full reorthogonalization, 1: one-sided (single, many and served workloads)")
     ap.add_argument("--schedule", choices=("table", "tune", "auto"), default="table",
@@ -663,6 +665,7 @@ def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
     steps_seen = []
     steps_run = []
     cycles = []
+    launches = []
 
     def step():
         s, U, V, info = plan.truncated_svd(f, k)
@@ -670,6 +673,7 @@ def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
         steps_seen.append(info.steps)
         steps_run.append(info.steps_run)
         cycles.append(info.thick_restarts)
+        launches.append(info.half_step_launches)
         return info
 
     print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
@@ -744,12 +748,13 @@ def bench_plan(args, f_np, Lw, k, plan_kw, metric, config, traffic_fn):
         "lanczos_steps": float(np.mean(steps_seen[-args.steps:])),
         "lanczos_steps_run": float(np.mean(steps_run[-args.steps:])),
         "thick_restarts": float(np.mean(cycles[-args.steps:])),
+        "half_step_launches": sorted(set(launches[-args.steps:])),
         "matvecs_per_s": 2.0 * sum(steps_run[-args.steps:]) / t_timed,
         "hbm_gb_s_algorithmic": total_bytes / t_timed / 1e9,
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
-            "kernel_name": (CLASS_KERNEL if plan_kw.get("unfused") else CLASS_KERNEL_FUSED).get(dom, dom),
+            "kernel_name": (CLASS_KERNEL if plan_kw.get("unfused") == 1 else CLASS_KERNEL_FUSED).get(dom, dom),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

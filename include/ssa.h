@@ -90,9 +90,15 @@ typedef struct {
                                schedule tuner (ssa_tune_fft) picks it by measurement.    */
     int unfused;            /* 1: run each Lanczos half-step as six launches (pass 1, 2, 3,
                                projection, reduction, update) with the bases in natural
-                               order; 0 = the fused four-launch half-step wherever it
-                               applies (1D, no thick restart, max(L, K) <= 2^20).  Same
-                               results up to rounding order; an A/B switch.              */
+                               order; 2: the fused four-launch half-step (pass 1 with the
+                               update, pass 2, pass 3 with the projection, reduction);
+                               0 = fused wherever it applies (1D, no thick restart,
+                               max(L, K) <= 2^20), with each reduction folded into the
+                               next pass-1 launch (three launches) where pass 3 has at
+                               most 256 workgroups.  A folded solve that meets a DGKS
+                               pass or a breakdown restarts as four launches.  1 gives
+                               the same results up to rounding order, 2 the same bits as
+                               a folded solve that did not restart; an A/B switch.       */
 } ssa_opts;
 
 /* Per-solve report, filled by ssa_truncated_svd. */
@@ -107,6 +113,11 @@ typedef struct {
     double resid[64];  /* residual bounds alpha_{d+1} |P[d+1,i]| of the first min(k,64) triples */
     int thick_restarts;/* restart cycles performed (ssa_opts.restart_keep)                   */
     int status;        /* the call's return value (SSA_OK or a warning; errors fill nothing) */
+    int half_step_launches; /* launches per Lanczos half-step the result came from: 3 (each
+                          reduction folded into the next pass-1 launch), 4 (the reduction as
+                          its own launch; also where a folded solve met a DGKS pass or a
+                          breakdown and was restarted), or 6 (ssa_opts.unfused = 1, 2D,
+                          thick restart, max(L, K) > 2^20)                                   */
 } ssa_info;
 
 /* Sizes chosen by a plan (reported for tests and benchmarks). */

@@ -30,6 +30,9 @@ constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 1
 // Longest basis vector of the fused path: one workgroup adds the pass-3 partial sums of
 // every column, and a DGKS pass in that workgroup must stay short.
 constexpr long long kFusedMaxRows = 1LL << 20;
+// Most pass-3 workgroups (partial sums per column) with which each reduction is folded
+// into the next pass-1 update, where every workgroup adds all of them.
+constexpr int kFoldMaxChunks = 256;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -130,6 +133,9 @@ struct ssa_plan_s {
     int onesided;  // 1: only the length-Li basis (U) is reorthogonalized
     int kcols;  // columns of the P/Q coefficient buffers: max(k_max, keep)
     int fused;  // 1: the four-launch half-step of fused.hip, bases in the segment layout
+    int fold;   // 1: each reduction is folded into the next pass-1 update (three launches)
+    int fold_off = 0;  // this solve restarted without the fold (a DGKS pass or a breakdown)
+    int fell_back = 0; // ... and so it did
     SegLay layU, layV;  // segment layouts of the U-side (length Li) and V-side (length Ki) vectors
     int nblk;   // pass-3 workgroups of a product (partial sums per column on the fused path)
     double tol;
@@ -495,17 +501,33 @@ int fused_finish(ssa_plan p, const float* basis, long long ld, int ncols, int nc
     return SSA_OK;
 }
 
-// One product of the fused path: pass 1 finishes x (the previous half-step's vector,
-// layout lin, written to out_col) and transforms it; pass 2; pass 3 writes
-// r = y - coef * prev in layout lout and the projection partials against ncols_out
-// columns of basis_out.
-int fused_product(ssa_plan p, const ConvGeom& g, const SegLay& lin, const float* basis_in, long long ld_in,
-                  int ncols_in, float* out_col, const SegLay& lout, const float* prev, const double* coef,
-                  const float* basis_out, long long ld_out, int ncols_out) {
+// The reduction folded into the next pass-1 update: the partials of the last pass 3
+// (against ncols columns) give the B entry coef_out; ctr numbers the reduction as
+// fused_finish does.
+FoldRed fold_args(ssa_plan p, int ncols, const SegLay& lay, double* coef_out, unsigned long long ctr) {
+    FoldRed f{};
+    f.part = at<double>(p, p->o_part);
+    f.pstride = p->pstride;
+    f.nchunks = p->nblk;
+    f.coef_out = coef_out;
+    f.bn = at<double>(p, p->o_state) + 4;
+    f.par = (int)(ctr & 1);
+    f.track = 1;
+    f.full = ncols >= lay.n ? 1 : 0;
+    f.tol_bd = kBreakdownTol;
+    f.snap = ctr < (unsigned long long)p->nsnap ? at<double>(p, p->o_snap) + 2 * ctr : nullptr;
+    f.fail = at<double>(p, p->o_rec) + kChkDone;
+    return f;
+}
+
+// One product of the fused path, first launch: pass 1 finishes x (the previous
+// half-step's vector, layout lin, written to out_col; with fold, after the reduction
+// that gives its h and scale) and transforms it.
+int fused_pass1(ssa_plan p, const ConvGeom& g, const SegLay& lin, const float* basis_in, long long ld_in,
+                int ncols_in, float* out_col, const FoldRed* fold) {
     hipStream_t s = p->stream;
     float* r = at<float>(p, p->o_r);
     float2* T1 = at<float2>(p, p->o_t1);
-    float2* T2 = at<float2>(p, p->o_t2);
     const double mp = (double)g.Mp;
     P1Seg a{};
     a.lay = lin;
@@ -517,10 +539,24 @@ int fused_product(ssa_plan p, const ConvGeom& g, const SegLay& lin, const float*
     a.h = at<double>(p, p->o_h);
     a.scale = at<double>(p, p->o_sc);
     a.out = out_col;
+    if (fold) a.fold = *fold;
     {
-        ProfScope ps(p, SSA_PROF_PASS1, 4.0 * (double)lin.n * (ncols_in + 2) + 8.0 * mp);
+        const double red = fold ? 8.0 * (double)(ncols_in + 1) * fold->nchunks : 0.0;
+        ProfScope ps(p, SSA_PROF_PASS1, 4.0 * (double)lin.n * (ncols_in + 2) + 8.0 * mp + red);
         SSA_TRY(launch_p1_update(g, a, T1, s));
     }
+    return SSA_OK;
+}
+
+// The rest of the product: pass 2; pass 3 writes r = y - coef * prev in layout lout and
+// the projection partials against ncols_out columns of basis_out.
+int fused_pass23(ssa_plan p, const ConvGeom& g, const SegLay& lout, const float* prev, const double* coef,
+                 const float* basis_out, long long ld_out, int ncols_out) {
+    hipStream_t s = p->stream;
+    float* r = at<float>(p, p->o_r);
+    float2* T1 = at<float2>(p, p->o_t1);
+    float2* T2 = at<float2>(p, p->o_t2);
+    const double mp = (double)g.Mp;
     {
         ProfScope ps(p, SSA_PROF_PASS2, 24.0 * mp);
         SSA_TRY(launch_pass2_matvec(g, at<float4>(p, p->o_ab), T1, T2, s));
@@ -585,7 +621,12 @@ int do_embed(ssa_plan p, const double* series_dev, bool sync_check = true) {
 // finishes v_j, forms p_j = X v_j - alpha_j u_j, orthogonalizes it against U and yields
 // beta_{j+1}.  gl is the geometry of the fused products (it may carry the early-exit
 // flag), g that of the unfused ones.
-int half_step(ssa_plan p, const ConvGeom& gl, const ConvGeom& g, int j, bool vhalf) {
+//
+// On the folded path the reduction of each half-step runs inside the next one's pass-1
+// launch (not after the V half of step 1, whose pass 1 follows the start vector's own
+// reduction).  part 1 enqueues only that launch, part 2 the rest, 0 both: alpha_j comes
+// from the U half's first launch, and a stopping test of step j waits for it.
+int half_step(ssa_plan p, const ConvGeom& gl, const ConvGeom& g, int j, bool vhalf, int part = 0) {
     float* U = at<float>(p, p->o_U);
     float* V = at<float>(p, p->o_V);
     float* r = at<float>(p, p->o_r);
@@ -595,13 +636,23 @@ int half_step(ssa_plan p, const ConvGeom& gl, const ConvGeom& g, int j, bool vha
     // one-sided: V (length Ki >= Li) keeps only the three-term recurrence of pass 3
     const int ncv = p->onesided ? 0 : j - 1;
     int rc;
+    const bool folding = p->fused && p->fold && !p->fold_off;
     if (vhalf) {
         if (p->fused) {
-            // finish u_j; r_j = X^T u_j - beta_j v_{j-1}; its partials against V_{j-1}; alpha_j
-            rc = fused_product(p, gl, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU, p->layV,
-                               j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j, V, p->ldV, ncv);
+            // finish u_j (folded: after the reduction that yields beta_j); r_j = X^T u_j -
+            // beta_j v_{j-1}; its partials against V_{j-1}; alpha_j
+            if (part != 2) {
+                FoldRed f{};
+                if (folding && j >= 2) f = fold_args(p, j - 1, p->layU, beta + j, 2ULL * j - 1);
+                rc = fused_pass1(p, gl, p->layU, U, p->ldU, j - 1, U + (long long)(j - 1) * p->ldU,
+                                 f.part ? &f : nullptr);
+                if (rc != SSA_OK) return rc;
+            }
+            if (part == 1) return SSA_OK;
+            rc = fused_pass23(p, gl, p->layV, j >= 2 ? V + (long long)(j - 2) * p->ldV : nullptr, beta + j, V,
+                              p->ldV, ncv);
             if (rc != SSA_OK) return rc;
-            rc = fused_finish(p, V, p->ldV, ncv, j - 1, p->layV, p->nblk, alpha + j, 1, 2ULL * j);
+            if (!folding) rc = fused_finish(p, V, p->ldV, ncv, j - 1, p->layV, p->nblk, alpha + j, 1, 2ULL * j);
         } else {
             // r_j = X^T u_j - beta_j v_{j-1};  alpha_j = |r_j|;  v_j = r_j / alpha_j  (with FRO)
             rc = convolve(p, g, U + (long long)(j - 1) * p->ldU, 0, r,
@@ -612,11 +663,19 @@ int half_step(ssa_plan p, const ConvGeom& gl, const ConvGeom& g, int j, bool vha
         if (rc != SSA_OK) return rc;
     } else {
         if (p->fused) {
-            // finish v_j; p_j = X v_j - alpha_j u_j; its partials against U_j; beta_{j+1}
-            rc = fused_product(p, gl, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV, p->layU,
-                               U + (long long)(j - 1) * p->ldU, alpha + j, U, p->ldU, j);
+            // finish v_j (folded: after the reduction that yields alpha_j); p_j = X v_j -
+            // alpha_j u_j; its partials against U_j; beta_{j+1}
+            if (part != 2) {
+                FoldRed f{};
+                if (folding) f = fold_args(p, ncv, p->layV, alpha + j, 2ULL * j);
+                rc = fused_pass1(p, gl, p->layV, V, p->ldV, ncv, V + (long long)(j - 1) * p->ldV,
+                                 f.part ? &f : nullptr);
+                if (rc != SSA_OK) return rc;
+            }
+            if (part == 1) return SSA_OK;
+            rc = fused_pass23(p, gl, p->layU, U + (long long)(j - 1) * p->ldU, alpha + j, U, p->ldU, j);
             if (rc != SSA_OK) return rc;
-            rc = fused_finish(p, U, p->ldU, j, j, p->layU, p->nblk, beta + j + 1, 1, 2ULL * j + 1);
+            if (!folding) rc = fused_finish(p, U, p->ldU, j, j, p->layU, p->nblk, beta + j + 1, 1, 2ULL * j + 1);
         } else {
             // p_j = X v_j - alpha_j u_j;  beta_{j+1} = |p_j|;  u_{j+1} = p_j / beta_{j+1}
             rc = convolve(p, g, V + (long long)(j - 1) * p->ldV, 1, r, U + (long long)(j - 1) * p->ldU, alpha + j);
@@ -777,6 +836,8 @@ int run_begin(ssa_plan p, const double* series_dev, int k) {
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_alpha), p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_beta), p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
+    p->fold_off = 0;
+    p->fell_back = 0;
     rc = start_vector(p);
     if (rc != SSA_OK) return rc;
     p->run = decltype(p->run){};
@@ -788,6 +849,31 @@ int run_begin(ssa_plan p, const double* series_dev, int k) {
     // the test's record says done.  Those steps only write columns and scalars past d.
     p->stop_dev = p->fused ? rec + kChkDone : nullptr;
     SSA_TRY(hipEventRecord(p->run_ev, s));
+    return SSA_OK;
+}
+
+// A folded reduction met a DGKS pass or a breakdown (the record says kDoneFallback; every
+// launch after it returned at once): the solve starts over, same start vector, with the
+// reduction as its own launch.  Nothing waits on the host.
+int run_restart_unfolded(ssa_plan p) {
+    auto& R = p->run;
+    hipStream_t s = p->stream;
+    // the tests enqueued so far read and write the record: the reset comes after them
+    if (R.last_chk >= 0) SSA_TRY(hipStreamWaitEvent(s, p->chk_ev[R.last_chk], 0));
+    double* rec = at<double>(p, p->o_rec);
+    SSA_TRY(launch_fill_zero(rec, p->nrec, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_alpha), p->d_max + 3, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_beta), p->d_max + 3, s));
+    SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
+    p->fold_off = 1;
+    p->fell_back = 1;
+    const int rc = start_vector(p);
+    if (rc != SSA_OK) return rc;
+    R.j = 1;
+    R.pend_jj = -1;
+    R.steps_run = 0;
+    R.stopped = 0;
+    R.fin_rec = nullptr;
     return SSA_OK;
 }
 
@@ -805,12 +891,20 @@ int run_advance(ssa_plan p, int max_steps) {
     const int k = R.k;
     for (int n = 0; n < max_steps && !R.stopped; ++n) {
         const int j = R.j;
+        const bool folding = p->fused && p->fold && !p->fold_off;
         int rc = half_step(p, gl, g, j, true);
         if (rc != SSA_OK) return rc;
         const int jj = j - 1;
         R.steps_run = jj;
         bool stop = false;
-        if (jj >= k && (jj % p->check_every == 0 || jj >= R.d_cap)) {
+        double done = 0.0;
+        const bool test = jj >= k && (jj % p->check_every == 0 || jj >= R.d_cap);
+        if (test && folding) {
+            // alpha_j and the snapshot of its reduction come from the U half's first launch
+            rc = half_step(p, gl, g, j, false, 1);
+            if (rc != SSA_OK) return rc;
+        }
+        if (test) {
             // the test of one check point runs on the check stream, beside the next
             // Lanczos steps (it reads only alpha/beta up to this step and the state
             // snapshot of this step's reduction); the host reads its record one check
@@ -841,7 +935,8 @@ int run_advance(ssa_plan p, int max_steps) {
             R.last_chk = R.cur_buf;
             if (R.pend_jj >= 0) {
                 SSA_TRY(hipEventSynchronize(p->chk_ev[R.pend_buf]));
-                stop = p->h_rec[(size_t)R.pend_buf * p->nrec + kChkDone] != 0.0;
+                done = p->h_rec[(size_t)R.pend_buf * p->nrec + kChkDone];
+                stop = done != 0.0;
             }
             if (!stop) {
                 R.pend_jj = jj;
@@ -849,16 +944,22 @@ int run_advance(ssa_plan p, int max_steps) {
                 R.cur_buf ^= 1;
                 if (jj >= R.d_cap) {
                     SSA_TRY(hipEventSynchronize(p->chk_ev[R.pend_buf]));
-                    stop = p->h_rec[(size_t)R.pend_buf * p->nrec + kChkDone] != 0.0;
+                    done = p->h_rec[(size_t)R.pend_buf * p->nrec + kChkDone];
+                    stop = done != 0.0;
                 }
             }
             if (stop) R.fin_rec = p->h_rec + (size_t)R.pend_buf * p->nrec;
+        }
+        if (stop && done == kDoneFallback) {
+            rc = run_restart_unfolded(p);
+            if (rc != SSA_OK) return rc;
+            continue;
         }
         if (stop) {
             R.stopped = 1;
             break;
         }
-        rc = half_step(p, gl, g, j, false);
+        rc = half_step(p, gl, g, j, false, test && folding ? 2 : 0);
         if (rc != SSA_OK) return rc;
         R.j = j + 1;
     }
@@ -941,6 +1042,7 @@ int run_finish(ssa_plan p, double* sigma_dev, float* U_dev, float* V_dev, ssa_in
         info->restarts = (int)R.fin_rec[kChkRestarts];
         info->dgks_passes = (int)R.fin_rec[kChkDgks];
         info->steps_run = R.steps_run;
+        info->half_step_launches = !p->fused ? 6 : (p->fold && !p->fold_off) ? 3 : 4;
         const double* resid = R.fin_rec + kChkHdr + 2 * p->kcols;
         for (int i = 0; i < k && i < 64; ++i) info->resid[i] = resid[i];
     }
@@ -1050,7 +1152,10 @@ static int plan_create(long long N, long long L, long long K, int is2d, long lon
     fill_geom(Mp, M1, M2, cb, p->g);
     const ConvGeom& gg = p->g;
     p->nblk = (gg.M2 + gg.CB - 1) / gg.CB;
-    p->fused = (!is2d && p->keep == 0 && p->Ki <= kFusedMaxRows && !(opts && opts->unfused)) ? 1 : 0;
+    const int unfused = opts ? opts->unfused : 0;
+    p->fused = (!is2d && p->keep == 0 && p->Ki <= kFusedMaxRows && unfused != 1) ? 1 : 0;
+    // the fold: every pass-1 workgroup reads all partial sums, (ncols + 1) x nblk doubles
+    p->fold = (p->fused && unfused == 0 && p->nblk <= kFoldMaxChunks) ? 1 : 0;
     if (p->fused) {
         // U-side vectors are outputs y[Ki-1+i] of X v, V-side ones y[Li-1+i] of X^T u
         p->layU = make_seglay(gg, p->Ki - 1, p->Li);
@@ -1382,6 +1487,7 @@ int ssa_truncated_svd(ssa_plan p, const double* series_dev, long long N, long lo
         info->dgks_passes = (int)st[2];
         info->steps_run = steps_run;
         info->thick_restarts = cycles;
+        info->half_step_launches = 6;
         for (int i = 0; i < k && i < 64; ++i) info->resid[i] = res[i];
     }
     const int status = !converged ? SSA_WARN_NOT_CONVERGED : st[1] > 0.0 ? SSA_WARN_BREAKDOWN : SSA_OK;

@@ -64,7 +64,8 @@ __device__ __forceinline__ int seg_count32(const SegLay& l, int n2, int e) {
 // it, so their latency hides behind the column FFT.
 template <int EPT, typename F1 = FftGeneric>
 __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const float2* __restrict__ T2, P3Seg a) {
-    if (g.stop && *g.stop != 0.0) return;
+    // the early-exit flag is read here and tested once the loads below are in flight
+    const double stopv = g.stop ? *g.stop : 0.0;
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int kWaves = kFusedThreads / 64;
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
         if (n2 < M2) z = cmul(T2[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
         buf[c * ss + k1] = z;
     }
+    if (stopv != 0.0) return;
     __syncthreads();
     fft_run<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int q = tid; q < nsl; q += kFusedThreads) {
@@ -215,15 +217,22 @@ __device__ __forceinline__ void fused_accumulate(const P1Seg& a, const double* h
     }
 }
 
-// x = (r - sum) * scale at the four slots of group f: written to the output column
-// (zero in padding slots) and placed in the pass-1 buffer at its (n1, e).
+// The four slots of r in float4 group f of the source segments (zeros past the segment's
+// elements).
+__device__ __forceinline__ float4 fused_load_r(const P1Seg& a, const SegSrc& d, int gps, int f, int sg) {
+    const int tq0 = 4 * (f - sg * gps);
+    return tq0 < d.cnt ? *reinterpret_cast<const float4*>(a.r + d.pos + tq0) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// x = (r - sum) * scale at the four slots of group f (rv: r there): written to the
+// output column (zero in padding slots) and placed in the pass-1 buffer at its (n1, e).
 __device__ __forceinline__ void fused_finish_group(const P1Seg& a, const SegSrc* src, int gps, int f,
-                                                   const double (&x)[4], double scale, float2* buf, int ss) {
+                                                   const double (&x)[4], double scale, float2* buf, int ss,
+                                                   float4 rv) {
     const int sg = f / gps;
     const SegSrc d = src[sg];
     const int tq0 = 4 * (f - sg * gps);
     const long long p = d.pos + tq0;
-    const float4 rv = tq0 < d.cnt ? *reinterpret_cast<const float4*>(a.r + p) : make_float4(0.f, 0.f, 0.f, 0.f);
     const float r4[4] = {rv.x, rv.y, rv.z, rv.w};
     float o[4];
 #pragma unroll
@@ -240,9 +249,51 @@ __device__ __forceinline__ void fused_finish_group(const P1Seg& a, const SegSrc*
     *reinterpret_cast<float4*>(a.out + p) = make_float4(o[0], o[1], o[2], o[3]);
 }
 
-template <int EPT, typename F1 = FftGeneric>
+// The folded reduction, first part: hs[c] = sum over chunks of part[c][chunk] for c <=
+// ncols, in the reduction kernel's order (16 lanes per column, each adding its chunks in
+// sequence, then a shuffle tree).  Its loads are issued after the caller's.
+constexpr int kFoldLanes = 16;
+__device__ __forceinline__ void fold_sums(const FoldRed& f, int ncols, double* hs, int tid) {
+    const int l = tid % kFoldLanes;
+    for (int c = tid / kFoldLanes; c <= ncols; c += kFusedThreads / kFoldLanes) {
+        const double* row = f.part + (long long)c * f.pstride;
+        double sum = 0.0;
+#pragma unroll 16
+        for (int ch = l; ch < f.nchunks; ch += kFoldLanes) sum += row[ch];
+#pragma unroll
+        for (int off = kFoldLanes / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, kFoldLanes);
+        if (l == 0) hs[c] = sum;
+    }
+}
+
+// Second part (hs published): the new B entry and the normalization, the common case of
+// classical Gram-Schmidt (|r - B h|^2 = |r|^2 - |h|^2 >= |r|^2 / 2 and above the
+// breakdown threshold), the same arithmetic as the reduction kernel in every thread.
+// Returns false when the vector needs a DGKS pass or a fresh direction.
+__device__ __forceinline__ bool fold_finish(const FoldRed& f, int ncols, double* hs, double* sh, double bnorm,
+                                            double& coef, double& scale) {
+    const int tid = threadIdx.x;
+    double hh = 0.0;
+    for (int c = tid; c < ncols; c += kFusedThreads) hh += hs[c] * hs[c];
+    hh = block_sum(hh, sh);
+    const double rr = hs[ncols];
+    if (f.full) {
+        for (int c = tid; c < ncols; c += kFusedThreads) hs[c] = 0.0;
+        __syncthreads();
+        coef = 0.0;
+        scale = 0.0;
+        return true;
+    }
+    const double a2 = rr - hh;
+    if (!(a2 >= 0.5 * rr && sqrt(a2) > f.tol_bd * bnorm)) return false;
+    coef = sqrt(a2);
+    scale = 1.0 / coef;
+    return true;
+}
+
+template <int EPT, typename F1 = FftGeneric, bool FOLD = false>
 __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a, float2* __restrict__ T1) {
-    if (g.stop && *g.stop != 0.0) return;
+    const double stopv = g.stop ? *g.stop : 0.0;  // tested once the first loads are in flight
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x;
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
@@ -250,13 +301,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     float2* buf = smem;                                                   // CB x (M1 + 1)
     float2* tw = buf + CB * ss;                                           // M1
     double* red = reinterpret_cast<double*>(smem + fused_fft_lds_words(g));  // kFusedThreads x 4
-    double* hs = red + 4 * kFusedThreads;                                 // ncols
-    SegSrc* src = reinterpret_cast<SegSrc*>(hs + a.ncols + (a.ncols & 1));  // 2 * CB
+    double* hs = red + 4 * kFusedThreads;                                 // ncols + 1
+    SegSrc* src = reinterpret_cast<SegSrc*>(hs + ((a.ncols + 2) & ~1));   // 2 * CB
     const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
     const int ncb = min(CB, M2 - c0);
     for (int t = tid; t < M1; t += kFusedThreads) tw[t] = g.tw1[t];
     for (int idx = tid; idx < CB * ss; idx += kFusedThreads) buf[idx] = make_float2(0.0f, 0.0f);
-    for (int c = tid; c < a.ncols; c += kFusedThreads) hs[c] = a.h[c];
+    if constexpr (!FOLD)
+        for (int c = tid; c < a.ncols; c += kFusedThreads) hs[c] = a.h[c];
     if (tid < 2 * ncb) src[tid] = seg_source(a, M2, S, c0, tid);
     // x at every slot of the 2*ncb source segments, FP64.  The float4 groups are
     // split over the threads; when there are few of them the columns are split too,
@@ -270,6 +322,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     const int nsl_ = nslice >= 2 ? nslice : 1;
     float4 pre[kUpdPre];
     bool pre_ok = false;
+    // r at the group this thread finishes first (f = tid)
+    float4 rpre = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < nf) {
+        const int sg = tid / gps;
+        rpre = fused_load_r(a, seg_source(a, M2, S, c0, sg), gps, tid, sg);
+    }
     if (slice < nsl_ && f0 < nf) {
         const int sg = f0 / gps;
         const SegSrc d = seg_source(a, M2, S, c0, sg);
@@ -284,8 +342,31 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
             }
         }
     }
-    const double scale = *a.scale;
-    __syncthreads();
+    double scale;
+    if constexpr (FOLD) {
+        const double bnorm = a.fold.bn[a.fold.par];
+        fold_sums(a.fold, a.ncols, hs, tid);
+        if (stopv != 0.0) return;
+        __syncthreads();
+        double coef;
+        if (!fold_finish(a.fold, a.ncols, hs, red, bnorm, coef, scale)) {
+            // every workgroup takes this branch (same sums); a stopped solve is left alone
+            if (blockIdx.x == 0 && tid == 0) *a.fold.fail = kDoneFallback;
+            return;
+        }
+        if (blockIdx.x == 0 && tid == 0) {
+            *a.fold.coef_out = coef;
+            a.fold.bn[a.fold.par ^ 1] = (a.fold.track && coef > bnorm) ? coef : bnorm;
+            if (a.fold.snap) {
+                a.fold.snap[0] = 0.0;
+                a.fold.snap[1] = 0.0;
+            }
+        }
+    } else {
+        scale = *a.scale;
+        if (stopv != 0.0) return;
+        __syncthreads();
+    }
     if (nslice >= 2) {
         const int f = f0;
         if (slice < nslice && f < nf) {
@@ -298,13 +379,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
             double x[4] = {0.0, 0.0, 0.0, 0.0};
             for (int sl = 0; sl < nslice; ++sl)
                 for (int u = 0; u < 4; ++u) x[u] += red[4 * (sl * nf64 + tid) + u];
-            fused_finish_group(a, src, gps, tid, x, scale, buf, ss);
+            fused_finish_group(a, src, gps, tid, x, scale, buf, ss, rpre);
         }
     } else {
         for (int f = tid; f < nf; f += kFusedThreads) {
             double x[4];
             fused_accumulate(a, hs, src, gps, f, 0, 1, x, pre, f == tid && pre_ok);
-            fused_finish_group(a, src, gps, f, x, scale, buf, ss);
+            const float4 rv = f == tid ? rpre : fused_load_r(a, src[f / gps], gps, f, f / gps);
+            fused_finish_group(a, src, gps, f, x, scale, buf, ss, rv);
         }
     }
     __syncthreads();
@@ -382,7 +464,7 @@ size_t fused_p3_lds(const ConvGeom& g, const SegLay& lay) {
 
 size_t fused_p1_lds(const ConvGeom& g, int ncols) {
     return sizeof(float2) * (size_t)fused_fft_lds_words(g) +
-           sizeof(double) * (4 * (size_t)kFusedThreads + ncols + (ncols & 1)) + sizeof(SegSrc) * 2 * (size_t)g.CB;
+           sizeof(double) * (4 * (size_t)kFusedThreads + ((ncols + 2) & ~1)) + sizeof(SegSrc) * 2 * (size_t)g.CB;
 }
 
 hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a, hipStream_t s) {
@@ -399,17 +481,25 @@ hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a
     return hipGetLastError();
 }
 
-hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s) {
+template <bool FOLD>
+static void launch_p1_variant(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s) {
     const dim3 grid((g.M2 + g.CB - 1) / g.CB);
     const size_t lds = fused_p1_lds(g, a.ncols);
     if (fused_ept((long long)g.CB * g.M1) != 4)
-        SSA_LAUNCH(k_p1_update<8>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+        SSA_LAUNCH((k_p1_update<8, FftGeneric, FOLD>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
     else if (FftPlanA::matches(g.st1))
-        SSA_LAUNCH((k_p1_update<4, FftPlanA>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
+        SSA_LAUNCH((k_p1_update<4, FftPlanA, FOLD>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
     else if (FftPlanB::matches(g.st1))
-        SSA_LAUNCH((k_p1_update<4, FftPlanB>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
+        SSA_LAUNCH((k_p1_update<4, FftPlanB, FOLD>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
     else
-        SSA_LAUNCH(k_p1_update<4>, grid, dim3(kFusedThreads), lds, s, g, a, T1);
+        SSA_LAUNCH((k_p1_update<4, FftGeneric, FOLD>), grid, dim3(kFusedThreads), lds, s, g, a, T1);
+}
+
+hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s) {
+    if (a.fold.part)
+        launch_p1_variant<true>(g, a, T1, s);
+    else
+        launch_p1_variant<false>(g, a, T1, s);
     return hipGetLastError();
 }
 
@@ -440,6 +530,10 @@ hipError_t set_fused_attributes() {
     allow(reinterpret_cast<const void*>(k_p3_project<4, FftPlanB>));
     allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanA>));
     allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanB>));
+    allow(reinterpret_cast<const void*>(k_p1_update<4, FftGeneric, true>));
+    allow(reinterpret_cast<const void*>(k_p1_update<8, FftGeneric, true>));
+    allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanA, true>));
+    allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanB, true>));
     allow(reinterpret_cast<const void*>(k_ritz_seg));
     return e;
 }

@@ -188,7 +188,7 @@ template <int EPT, int NT = 256, typename F2 = FftGeneric>
 __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
                                                       const float2* __restrict__ T1,
                                                       float2* __restrict__ T2) {
-    if (g.stop && *g.stop != 0.0) return;
+    const double stopv = g.stop ? *g.stop : 0.0;  // tested once the row loads are in flight
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int M2 = g.M2;
@@ -211,6 +211,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
             pre1[i] = AB[(long long)rp.row(s1) * M2 + e1];
         }
     }
+    if (stopv != 0.0) return;
     __syncthreads();
     fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     int i = 0;
@@ -635,18 +636,6 @@ __global__ void k_start_vector(float* r, long long n, unsigned long long seed) {
 
 
 // block-wide sum (any block of up to 1024 threads), fixed order, valid in every thread
-__device__ double block_sum(double v, double* sh) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[w];
-    __syncthreads();
-    return s;
-}
-
 // r <- r - basis * h (h in LDS), one workgroup
 __device__ void blk_subtract(float* r, long long n, const float* basis, long long ld, int ncols,
                              const double* h) {
@@ -822,7 +811,9 @@ constexpr int kReduceThreads = 1024;
 constexpr int kReduceLanes = 16;
 __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
     if (a.gate && *a.gate == 0) return;
-    if (a.stop && *a.stop != 0.0) return;
+    // the early-exit flag is tested once the partial sums are loaded; a stopped launch
+    // writes nothing
+    const double stopv = a.stop ? *a.stop : 0.0;
     __shared__ double hs[kMaxCols + 1];
     __shared__ double sh[16];
     __shared__ int decision;
@@ -839,12 +830,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_cgs_reduce(ReduceArgs a) {
             for (int off = kReduceLanes / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, kReduceLanes);
             if (l == 0) {
                 hs[c] = sum;
-                a.h[c] = sum;
+                if (stopv == 0.0) a.h[c] = sum;
             }
         }
     } else {
         for (int c = tid; c <= a.ncols; c += kReduceThreads) hs[c] = a.h[c];
     }
+    if (stopv != 0.0) return;
     __syncthreads();
     cgs_finish(a, hs, sh, decision, bnorm);
     if (a.snap && threadIdx.x == 0) {  // thread 0 made every state update

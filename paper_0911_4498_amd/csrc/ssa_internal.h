@@ -183,6 +183,25 @@ struct P3Seg {
 // (k_p1_update): x = (r - basis h) * scale in layout lay (natural length n = the
 // product's input length) is written to out and transformed as the reversed,
 // zero-padded input w[m] = x[n - 1 - m].
+// The reduction step of the previous half-step folded into the pass-1 update (three
+// launches per half-step): every workgroup sums the same partials in the same fixed order
+// as the reduction kernel, so all of them reach that kernel's h, B entry and scale bit for
+// bit; workgroup 0 publishes the B entry.  A vector that needs a DGKS pass or a fresh
+// direction cannot be finished this way: the launch then marks the solve for a restart
+// with the reduction as its own launch and writes nothing else.
+struct FoldRed {
+    const double* part;  // part[c * pstride + chunk]: <basis_c, r> for c < ncols, |r|^2 for c = ncols
+    int pstride, nchunks;
+    double* coef_out;    // the new B entry (alpha_j or beta_{j+1})
+    double* bn;          // running max of the B entries in two slots: read bn[par], write bn[par ^ 1]
+    int par;
+    int track;           // 1: the entry counts in the running max
+    int full;            // 1: the basis already spans the whole space (zero vector)
+    double tol_bd;       // breakdown threshold relative to the running max
+    double* snap;        // non-null: restarts and DGKS passes after this reduction (none on this path)
+    double* fail;        // gets kDoneFallback when the restart is needed
+};
+
 struct P1Seg {
     SegLay lay;
     long long N;         // series length: slot of y index m' holds w[N - 1 - m']
@@ -190,9 +209,10 @@ struct P1Seg {
     const float* basis;
     long long ld;
     int ncols;
-    const double* h;     // ncols coefficients (device)
-    const double* scale; // device scalar
+    const double* h;     // ncols coefficients (device; not read when the reduction is folded in)
+    const double* scale; // device scalar (idem)
     float* out;          // stored length lay.len; must not alias r or the ncols columns
+    FoldRed fold;        // the folded reduction (fold.part non-null)
 };
 
 // Record of the single-series stopping test (doubles, device; the host reads only
@@ -200,7 +220,8 @@ struct P1Seg {
 // previous test and the residual bounds, each kstride long.
 enum {
     kChkHavePrev = 0,  // a previous test exists (stability of the Ritz values)
-    kChkDone = 1,      // 1 once a test ended the solve
+    kChkDone = 1,      // 1 once a test ended the solve; kDoneFallback once a folded
+                       // reduction asked for a restart with the reduction as its own launch
     kChkD = 2,         // Lanczos steps d of the deciding test
     kChkConv = 3,      // 1 if the stopping rule held (or the Krylov space was exhausted)
     kChkNonfinite = 4, // 1 if the series holds NaN or Inf
@@ -209,6 +230,7 @@ enum {
     kChkJJ = 7,        // steps of the latest test
     kChkHdr = 8
 };
+constexpr double kDoneFallback = 2.0;
 constexpr double kResidFloorDev = 1e-5;  // residuals of omega_i < 1e-5 omega_1 judged against 1e-5 omega_1
 
 struct LzCheck {

@@ -37,7 +37,7 @@ class SsaOpts(ctypes.Structure):
 class SsaInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int), ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("dgks_passes", ctypes.c_int), ("steps_run", ctypes.c_int), ("resid", ctypes.c_double * 64),
-                ("thick_restarts", ctypes.c_int), ("status", ctypes.c_int)]
+                ("thick_restarts", ctypes.c_int), ("status", ctypes.c_int), ("half_step_launches", ctypes.c_int)]
 
 
 class SsaPlanDesc(ctypes.Structure):

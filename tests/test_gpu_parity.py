@@ -473,33 +473,46 @@ def test_profile_classes(ssa):
     launch in three still gives a time for the sampled classes."""
     say("profile classes")
     f = inputs.c1_series(1000)
-    for unfused in (0, 1):
+    for unfused in (0, 2, 1):
         plan = ssa.Plan(1000, 500, 10, unfused=unfused)
         plan.profile_enable(every=3)
         s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 10)
         plan.reconstruct(s, U, V, [[0, 1], [2]])
         pr = plan.profile_read()
+        assert info.half_step_launches == {0: 3, 2: 4, 1: 6}[unfused], info.half_step_launches
         # the fused path folds the projection into pass 3 and the update into pass 1 (only
-        # the start vector's norm is a projection launch of its own)
+        # the start vector's norm is a projection launch of its own); folded, the reduction
+        # runs in the next pass 1 (only the start vector's is a launch of its own)
         classes = ("pass1", "pass2", "pass3", "cgs_reduce", "check", "ritz", "recon_pass2")
-        if unfused:
+        if unfused == 1:
             classes += ("cgs_dots", "cgs_update")
         for c in classes:
             n, ms, b = pr[c]
             assert n > 0 and ms > 0 and b > 0, (unfused, c, pr[c])
-        if not unfused:
+        if unfused != 1:
             assert pr["cgs_update"][0] == 0 and pr["cgs_dots"][0] == 1, pr
+        if unfused == 0:
+            assert pr["cgs_reduce"][0] == 1, pr
+        if unfused == 2:
+            assert pr["cgs_reduce"][0] >= 2 * info.steps_run, pr
         assert pr["pass2"][0] >= 2 * info.steps_run - 1
         assert pr["dgks2"][0] == 0  # short vectors: the second pass stays in the finish
         plan.close()
     # one-sided with U longer than 16384 rows: every U-side step adds three gated launches
     N, L = 40000, 20000
     f = inputs.c2_series(N)
-    plan = ssa.Plan(N, L, 8, reorth=1)
+    plan = ssa.Plan(N, L, 8, reorth=1, unfused=2)
     plan.profile_enable(every=3)
     s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 8)
     pr = plan.profile_read()
     say(f"  steps_run={info.steps_run} dgks={info.dgks_passes} dgks2 launches={pr['dgks2'][0]}")
     assert pr["dgks2"][0] >= 3 * (info.steps_run - 1) and pr["dgks2"][2] == 0.0
     assert pr["cgs_dots"][2] > 0
+    plan.close()
+    # folded, those launches are gone: a second pass would restart the solve unfolded
+    plan = ssa.Plan(N, L, 8, reorth=1)
+    plan.profile_enable(every=3)
+    s, U, V, info = plan.truncated_svd(torch.tensor(f, device="cuda"), 8)
+    pr = plan.profile_read()
+    assert info.half_step_launches == 3 and pr["dgks2"][0] == 0, (info.half_step_launches, pr["dgks2"])
     plan.close()
