@@ -30,9 +30,6 @@ constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 1
 // Longest basis vector of the fused path: one workgroup adds the pass-3 partial sums of
 // every column, and a DGKS pass in that workgroup must stay short.
 constexpr long long kFusedMaxRows = 1LL << 20;
-// Most pass-3 workgroups (partial sums per column) with which each reduction is folded
-// into the next pass-1 update, where every workgroup adds all of them.
-constexpr int kFoldMaxChunks = 256;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

@@ -35,6 +35,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
+// sum_c hs[c]^2 over ncols values in LDS, formed by every wave on its own (lane l adds
+// c = l, l + 64, ... in order, then an xor butterfly): every lane of every wave gets the
+// same bits (each butterfly stage adds the same two values, in either order), with no
+// barrier.
+__device__ __forceinline__ double sumsq_allwave(const double* hs, int ncols) {
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    for (int c = lane; c < ncols; c += 64) v += hs[c] * hs[c];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 // Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3").
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;

@@ -32,6 +32,8 @@ namespace ssa {
 constexpr int kFusedThreads = 1024;
 // basis columns a wave of k_p3_project handles at once (independent loads in flight)
 constexpr int kProjUnroll = 4;
+// pass-1 twiddles per thread in the preambles: M1 <= 4096
+constexpr int kTwPer = 4;
 
 // float2 words of the FFT buffer and its twiddles, rounded up to 16 bytes
 __host__ __device__ inline int fused_fft_lds_words(const ConvGeom& g) {
@@ -80,18 +82,53 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
     const int nf = nsl / 4;
     const long long base = 2LL * c0 * S;
     const float cf = (a.prev && a.coef) ? (float)(*a.coef) : 0.0f;
-    const float pv0 = (a.prev && tid < nsl) ? a.prev[base + tid] : 0.0f;
+    // (the loads below are unconditional at clamped, in-bounds positions: branches around
+    // them would make the compiler wait for each one in turn)
+    const float pv0 = a.prev ? a.prev[base + min(tid, nsl - 1)] : 0.0f;
     // (not in the 8-point instantiation for long rows: capped at 128 VGPRs, it would spill)
     constexpr int kPre = EPT >= 8 ? 0 : kProjUnroll;
     float4 pre[kPre > 0 ? kPre : 1];
 #pragma unroll
+    for (int u = 0; u < (kPre > 0 ? kPre : 1); ++u) pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
     for (int u = 0; u < kPre; ++u) {
-        const int c = wave * kProjUnroll + u;
-        pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (c < a.ncols && lane < nf) pre[u] = reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + base)[lane];
+        const int c = wave * kProjUnroll + u;  // wave-uniform
+        if (c < a.ncols) pre[u] = reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + base)[min(lane, nf - 1)];
     }
-    for (int t = tid; t < M1; t += kFusedThreads) tw[t] = g.tw1[t];
-    for (int idx = tid; idx < CB * M1; idx += kFusedThreads) {
+    // twiddles and the column elements (with their four-step twiddles) in batches of four
+    // per thread, each batch's loads issued before its LDS writes (at clamped positions)
+    // (a wave whose first index is past the data skips the load: a wave-uniform branch)
+    const int wave0 = tid & ~63;
+    float2 twv[kTwPer];
+#pragma unroll
+    for (int i = 0; i < kTwPer; ++i)
+        if (wave0 + i * kFusedThreads < M1) twv[i] = g.tw1[min(tid + i * kFusedThreads, M1 - 1)];
+    const int nz = CB * M1;  // <= EPT * kFusedThreads
+#pragma unroll
+    for (int b = 0; b < EPT; b += 4) {
+        float2 zv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (wave0 + (b + i) * kFusedThreads >= nz) continue;
+            const int idx = min(tid + (b + i) * kFusedThreads, nz - 1);
+            const int c = idx % CB, k1 = idx / CB, n2 = min(c0 + c, M2 - 1);
+            zv[i] = cmul(T2[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
+        }
+        if (b == 0) {
+#pragma unroll
+            for (int i = 0; i < kTwPer; ++i)
+                if (tid + i * kFusedThreads < M1) tw[tid + i * kFusedThreads] = twv[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + (b + i) * kFusedThreads;
+            if (idx < nz) {
+                const int c = idx % CB, k1 = idx / CB;
+                buf[c * ss + k1] = c0 + c < M2 ? zv[i] : make_float2(0.0f, 0.0f);
+            }
+        }
+    }
+    for (int idx = tid + EPT * kFusedThreads; idx < nz; idx += kFusedThreads) {  // (none when nz <= EPT * 1024)
         const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
         float2 z = make_float2(0.0f, 0.0f);
         if (n2 < M2) z = cmul(T2[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
@@ -125,17 +162,19 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
         for (int f = lane; f < nf; f += 64) {
             const float4 rv = r4[f];
             float4 bv[kProjUnroll];
+            if (kPre > 0 && first && f == lane) {  // wave-uniform
 #pragma unroll
-            for (int u = 0; u < kProjUnroll; ++u) {
-                // the column index is wave-uniform: branches, not address selects
-                const int c = cb0 + u;
-                bv[u] = rv;
-                if (c < a.ncols) {
-                    if (kPre > 0 && first && f == lane)
-                        bv[u] = pre[u < kPre ? u : 0];
-                    else
-                        bv[u] = reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + base)[f];
-                }
+                for (int u = 0; u < kProjUnroll; ++u) bv[u] = cb0 + u < a.ncols ? pre[u < kPre ? u : 0] : rv;
+            } else {
+                // all four loads in flight together: clamped (in-bounds) columns, then the
+                // columns past the basis take r itself (its |r|^2)
+                const int cmax = max(a.ncols - 1, 0);
+#pragma unroll
+                for (int u = 0; u < kProjUnroll; ++u)
+                    bv[u] = reinterpret_cast<const float4*>(a.basis + (long long)min(cb0 + u, cmax) * a.ld + base)[f];
+#pragma unroll
+                for (int u = 0; u < kProjUnroll; ++u)
+                    if (cb0 + u >= a.ncols) bv[u] = rv;
             }
 #pragma unroll
             for (int u = 0; u < kProjUnroll; ++u) acc[u] += dot4(bv[u], rv);
@@ -187,6 +226,8 @@ __device__ __forceinline__ SegSrc seg_source(const P1Seg& a, int M2, int S, int 
 // float4 group f of the workgroup's source segments (nothing for a missing segment).
 // The first kUpdPre columns may come preloaded (use_pre).
 constexpr int kUpdPre = 4;
+constexpr int kHPer = 2;   // h values per thread: ncols <= kMaxCols
+static_assert(kHPer * kFusedThreads >= kMaxCols, "h fits the preamble loads");
 __device__ __forceinline__ void fused_accumulate(const P1Seg& a, const double* hs, const SegSrc* src, int gps, int f,
                                                  int slice, int nslice, double (&x)[4], const float4 (&pre)[kUpdPre],
                                                  bool use_pre) {
@@ -206,14 +247,22 @@ __device__ __forceinline__ void fused_accumulate(const P1Seg& a, const double* h
             x[3] += (double)pre[u].w * hc;
         }
     }
-#pragma unroll 4
-    for (; c < a.ncols; c += nslice) {
-        const float4 b = *reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + p);
-        const double hc = hs[c];
-        x[0] += (double)b.x * hc;
-        x[1] += (double)b.y * hc;
-        x[2] += (double)b.z * hc;
-        x[3] += (double)b.w * hc;
+    // four columns' loads in flight at a time (clamped columns, unconditional loads), added
+    // in column order
+    for (; c < a.ncols; c += 4 * nslice) {
+        float4 b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            b[u] = *reinterpret_cast<const float4*>(a.basis + (long long)min(c + u * nslice, a.ncols - 1) * a.ld + p);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (c + u * nslice >= a.ncols) break;
+            const double hc = hs[c + u * nslice];
+            x[0] += (double)b[u].x * hc;
+            x[1] += (double)b[u].y * hc;
+            x[2] += (double)b[u].z * hc;
+            x[3] += (double)b[u].w * hc;
+        }
     }
 }
 
@@ -251,15 +300,37 @@ __device__ __forceinline__ void fused_finish_group(const P1Seg& a, const SegSrc*
 
 // The folded reduction, first part: hs[c] = sum over chunks of part[c][chunk] for c <=
 // ncols, in the reduction kernel's order (16 lanes per column, each adding its chunks in
-// sequence, then a shuffle tree).  Its loads are issued after the caller's.
+// sequence, then a shuffle tree).  The first 64 columns' loads (kFoldPer per lane) are
+// issued at the head of the kernel (fold_load), so the sums run while the basis loads
+// are in flight; further columns are loaded here.
 constexpr int kFoldLanes = 16;
-__device__ __forceinline__ void fold_sums(const FoldRed& f, int ncols, double* hs, int tid) {
+constexpr int kFoldPer = 16;  // chunks per lane: nchunks <= kFoldLanes * kFoldPer
+static_assert(kFoldLanes * kFoldPer == kFoldMaxChunks, "fold lanes cover the partials");
+__device__ __forceinline__ void fold_load(const FoldRed& f, int ncols, int tid, double (&pv)[kFoldPer]) {
+    // unconditional loads at clamped (in-bounds) rows and chunks; fold_sums adds only the
+    // valid ones
+    const int l = tid % kFoldLanes, c = min(tid / kFoldLanes, ncols);
+    if ((tid & ~63) / kFoldLanes > ncols) return;  // the wave's columns are all past ncols
+    const double* row = f.part + (long long)c * f.pstride;
+#pragma unroll
+    for (int i = 0; i < kFoldPer; ++i)
+        if (i * kFoldLanes < f.nchunks) pv[i] = row[min(l + i * kFoldLanes, f.nchunks - 1)];
+}
+
+__device__ __forceinline__ void fold_sums(const FoldRed& f, int ncols, double* hs, int tid,
+                                          const double (&pv)[kFoldPer]) {
     const int l = tid % kFoldLanes;
     for (int c = tid / kFoldLanes; c <= ncols; c += kFusedThreads / kFoldLanes) {
         const double* row = f.part + (long long)c * f.pstride;
         double sum = 0.0;
+        if (c < kFusedThreads / kFoldLanes) {
+#pragma unroll
+            for (int i = 0; i < kFoldPer; ++i)
+                if (l + i * kFoldLanes < f.nchunks) sum += pv[i];
+        } else {
 #pragma unroll 16
-        for (int ch = l; ch < f.nchunks; ch += kFoldLanes) sum += row[ch];
+            for (int ch = l; ch < f.nchunks; ch += kFoldLanes) sum += row[ch];
+        }
 #pragma unroll
         for (int off = kFoldLanes / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, kFoldLanes);
         if (l == 0) hs[c] = sum;
@@ -270,12 +341,10 @@ __device__ __forceinline__ void fold_sums(const FoldRed& f, int ncols, double* h
 // classical Gram-Schmidt (|r - B h|^2 = |r|^2 - |h|^2 >= |r|^2 / 2 and above the
 // breakdown threshold), the same arithmetic as the reduction kernel in every thread.
 // Returns false when the vector needs a DGKS pass or a fresh direction.
-__device__ __forceinline__ bool fold_finish(const FoldRed& f, int ncols, double* hs, double* sh, double bnorm,
-                                            double& coef, double& scale) {
+__device__ __forceinline__ bool fold_finish(const FoldRed& f, int ncols, double* hs, double bnorm, double& coef,
+                                            double& scale) {
     const int tid = threadIdx.x;
-    double hh = 0.0;
-    for (int c = tid; c < ncols; c += kFusedThreads) hh += hs[c] * hs[c];
-    hh = block_sum(hh, sh);
+    const double hh = sumsq_allwave(hs, ncols);
     const double rr = hs[ncols];
     if (f.full) {
         for (int c = tid; c < ncols; c += kFusedThreads) hs[c] = 0.0;
@@ -296,6 +365,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     const double stopv = g.stop ? *g.stop : 0.0;  // tested once the first loads are in flight
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x;
+    double pv[FOLD ? kFoldPer : 1];
+    double bnorm = 0.0;
+    if constexpr (FOLD) {
+        fold_load(a.fold, a.ncols, tid, pv);
+        bnorm = a.fold.bn[a.fold.par];
+    }
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
     const int S = a.lay.S;
     float2* buf = smem;                                                   // CB x (M1 + 1)
@@ -305,11 +380,21 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     SegSrc* src = reinterpret_cast<SegSrc*>(hs + ((a.ncols + 2) & ~1));   // 2 * CB
     const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
     const int ncb = min(CB, M2 - c0);
-    for (int t = tid; t < M1; t += kFusedThreads) tw[t] = g.tw1[t];
-    for (int idx = tid; idx < CB * ss; idx += kFusedThreads) buf[idx] = make_float2(0.0f, 0.0f);
-    if constexpr (!FOLD)
-        for (int c = tid; c < a.ncols; c += kFusedThreads) hs[c] = a.h[c];
-    if (tid < 2 * ncb) src[tid] = seg_source(a, M2, S, c0, tid);
+    // Every global load of the preamble is issued before the first LDS write: a write of
+    // a loaded value waits for all loads issued before it (the counter is in order).
+    const int wave0 = tid & ~63;  // (whole waves past the data skip their loads)
+    float2 twv[kTwPer];           // M1 <= kTwPer * kFusedThreads
+#pragma unroll
+    for (int i = 0; i < kTwPer; ++i)
+        if (wave0 + i * kFusedThreads < M1) twv[i] = g.tw1[min(tid + i * kFusedThreads, M1 - 1)];
+    double hv[FOLD ? 1 : kHPer];  // ncols <= kHPer * kFusedThreads
+    if constexpr (!FOLD) {
+        if (a.ncols > 0) {
+#pragma unroll
+            for (int i = 0; i < kHPer; ++i)
+                if (wave0 + i * kFusedThreads < a.ncols) hv[i] = a.h[min(tid + i * kFusedThreads, a.ncols - 1)];
+        }
+    }
     // x at every slot of the 2*ncb source segments, FP64.  The float4 groups are
     // split over the threads; when there are few of them the columns are split too,
     // over slices of threads whose sums meet in LDS in a fixed order.  A thread's
@@ -320,36 +405,52 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     const int nslice = min(16, kFusedThreads / nf64);  // 0 or 1: no column split
     const int slice = nslice >= 2 ? tid / nf64 : 0, f0 = nslice >= 2 ? tid % nf64 : tid;
     const int nsl_ = nslice >= 2 ? nslice : 1;
+    // r at the group this thread finishes first (f = tid) and the first kUpdPre columns of
+    // its accumulation group.  The loads are unconditional, at a group and a column clamped
+    // into bounds (unused values are never read): branches around them would make the
+    // compiler wait for each one in turn.
     float4 pre[kUpdPre];
-    bool pre_ok = false;
-    // r at the group this thread finishes first (f = tid)
-    float4 rpre = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (tid < nf) {
-        const int sg = tid / gps;
-        rpre = fused_load_r(a, seg_source(a, M2, S, c0, sg), gps, tid, sg);
-    }
-    if (slice < nsl_ && f0 < nf) {
-        const int sg = f0 / gps;
-        const SegSrc d = seg_source(a, M2, S, c0, sg);
-        if (4 * (f0 - sg * gps) < d.cnt) {
-            pre_ok = true;
-            const long long p = d.pos + 4LL * (f0 - sg * gps);
 #pragma unroll
-            for (int u = 0; u < kUpdPre; ++u) {
-                const int c = slice + u * nsl_;
-                pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (c < a.ncols) pre[u] = *reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + p);
-            }
+    for (int u = 0; u < kUpdPre; ++u) pre[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool pre_ok = false;
+    float4 rpre;  // read only where tid < nf, at the slots holding elements
+    {
+        const int f = min(tid, nf - 1), sg = f / gps;
+        const SegSrc d = seg_source(a, M2, S, c0, sg);
+        rpre = *reinterpret_cast<const float4*>(a.r + d.pos + 4 * (f - sg * gps));
+    }
+    if (a.ncols > 0) {
+        const bool mine = slice < nsl_ && f0 < nf;
+        const int f = mine ? f0 : 0, sg = f / gps;
+        const SegSrc d = seg_source(a, M2, S, c0, sg);
+        pre_ok = mine && 4 * (f - sg * gps) < d.cnt;
+        const long long p = d.pos + 4LL * (f - sg * gps);
+        // (clamped, not skipped: a branch around each load would have the compiler convert
+        // the value inside it, waiting for every load in turn)
+#pragma unroll
+        for (int u = 0; u < kUpdPre; ++u) {
+            const int c = min(slice + u * nsl_, a.ncols - 1);
+            pre[u] = *reinterpret_cast<const float4*>(a.basis + (long long)c * a.ld + p);
         }
     }
+    const double scale_in = FOLD ? 0.0 : *a.scale;
+#pragma unroll
+    for (int i = 0; i < kTwPer; ++i)
+        if (tid + i * kFusedThreads < M1) tw[tid + i * kFusedThreads] = twv[i];
+    for (int idx = tid; idx < CB * ss; idx += kFusedThreads) buf[idx] = make_float2(0.0f, 0.0f);
+    if constexpr (!FOLD) {
+#pragma unroll
+        for (int i = 0; i < kHPer; ++i)
+            if (tid + i * kFusedThreads < a.ncols) hs[tid + i * kFusedThreads] = hv[i];
+    }
+    if (tid < 2 * ncb) src[tid] = seg_source(a, M2, S, c0, tid);
     double scale;
     if constexpr (FOLD) {
-        const double bnorm = a.fold.bn[a.fold.par];
-        fold_sums(a.fold, a.ncols, hs, tid);
+        fold_sums(a.fold, a.ncols, hs, tid, pv);
         if (stopv != 0.0) return;
         __syncthreads();
         double coef;
-        if (!fold_finish(a.fold, a.ncols, hs, red, bnorm, coef, scale)) {
+        if (!fold_finish(a.fold, a.ncols, hs, bnorm, coef, scale)) {
             // every workgroup takes this branch (same sums); a stopped solve is left alone
             if (blockIdx.x == 0 && tid == 0) *a.fold.fail = kDoneFallback;
             return;
@@ -363,7 +464,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
             }
         }
     } else {
-        scale = *a.scale;
+        scale = scale_in;
         if (stopv != 0.0) return;
         __syncthreads();
     }

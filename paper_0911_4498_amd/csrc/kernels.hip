@@ -195,21 +195,40 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
     float2* buf = smem;
     float2* tw = smem + 2 * M2;
     const RowPair rp(blockIdx.x, g.M1, M2);
-    for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
-    load_rows<EPT>(buf, T1, rp, M2, tid, nthr);
-    // operator values of this thread's first kPre pairs, fetched before the FFT (not in the
-    // 1024-thread instantiation: capped at 128 VGPRs, it would spill)
+    // The first four row elements per thread, the first twiddle and the operator values
+    // of the first kPre pairs are loaded (at clamped, in-bounds positions) before any LDS
+    // write: a write of a loaded value waits for every load issued before it.
+    const int total = rp.nseq * M2;
+    const int wave0 = tid & ~63;  // (whole waves past the data skip their loads)
+    float2 rv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (wave0 + i * nthr >= total) continue;
+        const int idx = min(tid + i * nthr, total - 1);
+        const int s = idx / M2, k2 = idx - s * M2;
+        rv[i] = T1[(long long)rp.row(s) * M2 + k2];
+    }
+    const float2 tw0 = g.tw2[min(tid, M2 - 1)];
+    // (not in the 1024-thread instantiation: capped at 128 VGPRs, it would spill)
     constexpr int kPre = NT >= 1024 ? 0 : 2;
     float4 pre0[kPre > 0 ? kPre : 1], pre1[kPre > 0 ? kPre : 1];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
-        const int p = tid + i * nthr;
-        if (p < rp.npairs) {
-            int s0, e0, s1, e1;
-            rp.pair(p, M2, s0, e0, s1, e1);
-            pre0[i] = AB[(long long)rp.row(s0) * M2 + e0];
-            pre1[i] = AB[(long long)rp.row(s1) * M2 + e1];
-        }
+        if (wave0 + i * nthr >= rp.npairs) continue;
+        const int p = min(tid + i * nthr, rp.npairs - 1);
+        int s0, e0, s1, e1;
+        rp.pair(p, M2, s0, e0, s1, e1);
+        pre0[i] = AB[(long long)rp.row(s0) * M2 + e0];
+        pre1[i] = AB[(long long)rp.row(s1) * M2 + e1];
+    }
+    if (tid < M2) tw[tid] = tw0;
+    for (int t = tid + nthr; t < M2; t += nthr) tw[t] = g.tw2[t];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (tid + i * nthr < total) buf[tid + i * nthr] = rv[i];
+    for (int idx = tid + 4 * nthr; idx < total; idx += nthr) {
+        const int s = idx / M2, k2 = idx - s * M2;
+        buf[idx] = T1[(long long)rp.row(s) * M2 + k2];
     }
     if (stopv != 0.0) return;
     __syncthreads();
@@ -676,9 +695,7 @@ __device__ double blk_project(const float* r, long long n, const float* basis, l
 // hs[0..ncols] holds the column sums on entry (hs[ncols] = |r|^2); bnorm is state[0].
 __device__ void cgs_finish(const ReduceArgs& a, double* hs, double* sh, int& decision, double bnorm) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    double hh = 0.0;
-    for (int c = tid; c < a.ncols; c += nt) hh += hs[c] * hs[c];
-    hh = block_sum(hh, sh);
+    const double hh = sumsq_allwave(hs, a.ncols);  // as the pass-1 launches that fold this step
     const double rr = hs[a.ncols];
     double coef, scale;
     if (a.full) {

@@ -189,6 +189,9 @@ struct P3Seg {
 // bit; workgroup 0 publishes the B entry.  A vector that needs a DGKS pass or a fresh
 // direction cannot be finished this way: the launch then marks the solve for a restart
 // with the reduction as its own launch and writes nothing else.
+// Most pass-3 workgroups (partial sums per column) with which each reduction is folded
+// into the next pass-1 update, where every workgroup adds all of them.
+constexpr int kFoldMaxChunks = 256;
 struct FoldRed {
     const double* part;  // part[c * pstride + chunk]: <basis_c, r> for c < ncols, |r|^2 for c = ncols
     int pstride, nchunks;
