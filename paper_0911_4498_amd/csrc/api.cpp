@@ -30,6 +30,11 @@ constexpr int kGrid2ChunksOneSided = 16;  // one-sided: grid second pass above 1
 // Longest basis vector of the fused path: one workgroup adds the pass-3 partial sums of
 // every column, and a DGKS pass in that workgroup must stay short.
 constexpr long long kFusedMaxRows = 1LL << 20;
+// Columns (with |r|^2) up to which the folded reduction sums the partials inside every
+// pass-1 workgroup; beyond, k_fold_sums adds them first.  Measured at N = 1e5: each
+// column costs the pass-1 launch about 0.09 us, the extra launch about 8 us with its gap
+// (a threshold of 32 or 88 columns made that solve 4% and 2% slower).
+constexpr int kFoldInlineCols = 160;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -514,6 +519,10 @@ FoldRed fold_args(ssa_plan p, int ncols, const SegLay& lay, double* coef_out, un
     f.tol_bd = kBreakdownTol;
     f.snap = ctr < (unsigned long long)p->nsnap ? at<double>(p, p->o_snap) + 2 * ctr : nullptr;
     f.fail = at<double>(p, p->o_rec) + kChkDone;
+    // many columns: their sums run as a launch of their own (k_fold_sums), which costs less
+    // than every pass-1 workgroup fetching all partials
+    f.presummed = ncols + 1 > kFoldInlineCols ? 1 : 0;
+    f.hsum = at<double>(p, p->o_h);
     return f;
 }
 
@@ -537,8 +546,12 @@ int fused_pass1(ssa_plan p, const ConvGeom& g, const SegLay& lin, const float* b
     a.scale = at<double>(p, p->o_sc);
     a.out = out_col;
     if (fold) a.fold = *fold;
+    if (fold && fold->presummed) {
+        ProfScope ps(p, SSA_PROF_REDUCE, 8.0 * (double)(ncols_in + 1) * fold->nchunks);
+        SSA_TRY(launch_fold_sums(*fold, ncols_in, s));
+    }
     {
-        const double red = fold ? 8.0 * (double)(ncols_in + 1) * fold->nchunks : 0.0;
+        const double red = fold ? 8.0 * (double)(ncols_in + 1) * (fold->presummed ? 1 : fold->nchunks) : 0.0;
         ProfScope ps(p, SSA_PROF_PASS1, 4.0 * (double)lin.n * (ncols_in + 2) + 8.0 * mp + red);
         SSA_TRY(launch_p1_update(g, a, T1, s));
     }

@@ -15,6 +15,16 @@ namespace ssa {
 
 constexpr int kMaxStages = 16;
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also makes the
+// workgroup's earlier global stores visible to it, which on this GPU waits for every
+// store in flight to complete; the kernels that use this barrier never read global
+// memory that another thread of the workgroup wrote in the same launch.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 struct FftStages {
     int n;
     int nstages;
@@ -189,7 +199,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstr
             for (int r = 0; r < R; ++r) v[i][r] = x[r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int b = tid + i * nthr;
@@ -202,7 +212,7 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstr
             for (int r = 0; r < R; ++r) dst[r * p] = v[i][r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // Full transform.  Requires n * nseq <= EPT * nthr.  Ends synchronized.

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
         buf[c * ss + k1] = z;
     }
     if (stopv != 0.0) return;
-    __syncthreads();
+    lds_barrier();
     fft_run<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int q = tid; q < nsl; q += kFusedThreads) {
         const int sg = q / S, t = q - sg * S;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
         rs[q] = v;
         a.r[base + q] = v;
     }
-    __syncthreads();
+    lds_barrier();
     // partials: the waves split the columns (column ncols stands for |r|^2), the lanes
     // split the float4 groups of the block; FP64 sums of exact FP32 products
     const float4* r4 = reinterpret_cast<const float4*>(rs);
@@ -227,7 +227,7 @@ __device__ __forceinline__ SegSrc seg_source(const P1Seg& a, int M2, int S, int 
 // The first kUpdPre columns may come preloaded (use_pre).
 constexpr int kUpdPre = 4;
 constexpr int kHPer = 2;   // h values per thread: ncols <= kMaxCols
-static_assert(kHPer * kFusedThreads >= kMaxCols, "h fits the preamble loads");
+static_assert(kHPer * kFusedThreads >= 1024 + 1, "h and |r|^2 fit the preamble loads (ncols <= d_max <= 1024)");
 __device__ __forceinline__ void fused_accumulate(const P1Seg& a, const double* hs, const SegSrc* src, int gps, int f,
                                                  int slice, int nslice, double (&x)[4], const float4 (&pre)[kUpdPre],
                                                  bool use_pre) {
@@ -337,6 +337,30 @@ __device__ __forceinline__ void fold_sums(const FoldRed& f, int ncols, double* h
     }
 }
 
+// The same column sums as a launch of their own, for many columns (the pass-1 launch then
+// reads ncols + 1 doubles): a wave sums four columns in fold_sums' order, so the bits are
+// the same.  Each pass-1 workgroup would otherwise fetch all (ncols + 1) * nchunks partials
+// through its own CU, whose outstanding misses bound the rate; spread over many workgroups
+// each CU fetches a few columns.
+__global__ __launch_bounds__(64) void k_fold_sums(FoldRed f, int ncols) {
+    if (*f.fail != 0.0) return;  // the solve has stopped (the test's done flag)
+    const int lane = threadIdx.x, l = lane % kFoldLanes;
+    const int c = blockIdx.x * (64 / kFoldLanes) + lane / kFoldLanes;
+    if (c > ncols) return;  // whole 16-lane groups
+    const double* row = f.part + (long long)c * f.pstride;
+    double pv[kFoldPer];
+#pragma unroll
+    for (int i = 0; i < kFoldPer; ++i)
+        if (i * kFoldLanes < f.nchunks) pv[i] = row[min(l + i * kFoldLanes, f.nchunks - 1)];
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < kFoldPer; ++i)
+        if (l + i * kFoldLanes < f.nchunks) sum += pv[i];
+#pragma unroll
+    for (int off = kFoldLanes / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off, kFoldLanes);
+    if (l == 0) f.hsum[c] = sum;
+}
+
 // Second part (hs published): the new B entry and the normalization, the common case of
 // classical Gram-Schmidt (|r - B h|^2 = |r|^2 - |h|^2 >= |r|^2 / 2 and above the
 // breakdown threshold), the same arithmetic as the reduction kernel in every thread.
@@ -348,7 +372,7 @@ __device__ __forceinline__ bool fold_finish(const FoldRed& f, int ncols, double*
     const double rr = hs[ncols];
     if (f.full) {
         for (int c = tid; c < ncols; c += kFusedThreads) hs[c] = 0.0;
-        __syncthreads();
+        lds_barrier();
         coef = 0.0;
         scale = 0.0;
         return true;
@@ -367,8 +391,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     const int tid = threadIdx.x;
     double pv[FOLD ? kFoldPer : 1];
     double bnorm = 0.0;
+    const bool presummed = FOLD && a.fold.presummed;
     if constexpr (FOLD) {
-        fold_load(a.fold, a.ncols, tid, pv);
+        if (!presummed) fold_load(a.fold, a.ncols, tid, pv);
         bnorm = a.fold.bn[a.fold.par];
     }
     const int CB = g.CB, M1 = g.M1, M2 = g.M2, ss = M1 + 1;
@@ -387,13 +412,14 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
 #pragma unroll
     for (int i = 0; i < kTwPer; ++i)
         if (wave0 + i * kFusedThreads < M1) twv[i] = g.tw1[min(tid + i * kFusedThreads, M1 - 1)];
-    double hv[FOLD ? 1 : kHPer];  // ncols <= kHPer * kFusedThreads
-    if constexpr (!FOLD) {
-        if (a.ncols > 0) {
+    // h (ncols values), or with presummed column sums h and |r|^2 (ncols + 1)
+    double hv[kHPer];  // ncols + 1 <= kHPer * kFusedThreads
+    const int nh = FOLD ? (presummed ? a.ncols + 1 : 0) : a.ncols;
+    const double* hsrc = FOLD ? a.fold.hsum : a.h;
+    if (nh > 0) {
 #pragma unroll
-            for (int i = 0; i < kHPer; ++i)
-                if (wave0 + i * kFusedThreads < a.ncols) hv[i] = a.h[min(tid + i * kFusedThreads, a.ncols - 1)];
-        }
+        for (int i = 0; i < kHPer; ++i)
+            if (wave0 + i * kFusedThreads < nh) hv[i] = hsrc[min(tid + i * kFusedThreads, nh - 1)];
     }
     // x at every slot of the 2*ncb source segments, FP64.  The float4 groups are
     // split over the threads; when there are few of them the columns are split too,
@@ -438,17 +464,15 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     for (int i = 0; i < kTwPer; ++i)
         if (tid + i * kFusedThreads < M1) tw[tid + i * kFusedThreads] = twv[i];
     for (int idx = tid; idx < CB * ss; idx += kFusedThreads) buf[idx] = make_float2(0.0f, 0.0f);
-    if constexpr (!FOLD) {
 #pragma unroll
-        for (int i = 0; i < kHPer; ++i)
-            if (tid + i * kFusedThreads < a.ncols) hs[tid + i * kFusedThreads] = hv[i];
-    }
+    for (int i = 0; i < kHPer; ++i)
+        if (tid + i * kFusedThreads < nh) hs[tid + i * kFusedThreads] = hv[i];
     if (tid < 2 * ncb) src[tid] = seg_source(a, M2, S, c0, tid);
     double scale;
     if constexpr (FOLD) {
-        fold_sums(a.fold, a.ncols, hs, tid, pv);
+        if (!presummed) fold_sums(a.fold, a.ncols, hs, tid, pv);
         if (stopv != 0.0) return;
-        __syncthreads();
+        lds_barrier();
         double coef;
         if (!fold_finish(a.fold, a.ncols, hs, bnorm, coef, scale)) {
             // every workgroup takes this branch (same sums); a stopped solve is left alone
@@ -466,7 +490,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
     } else {
         scale = scale_in;
         if (stopv != 0.0) return;
-        __syncthreads();
+        lds_barrier();
     }
     if (nslice >= 2) {
         const int f = f0;
@@ -475,7 +499,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
             fused_accumulate(a, hs, src, gps, f, slice, nslice, x, pre, pre_ok);
             for (int u = 0; u < 4; ++u) red[4 * tid + u] = x[u];
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < nf) {
             double x[4] = {0.0, 0.0, 0.0, 0.0};
             for (int sl = 0; sl < nslice; ++sl)
@@ -490,7 +514,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
             fused_finish_group(a, src, gps, f, x, scale, buf, ss, rv);
         }
     }
-    __syncthreads();
+    lds_barrier();
     fft_run<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int idx = tid; idx < CB * M1; idx += kFusedThreads) {
         const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
@@ -508,46 +532,61 @@ __global__ void k_start_seg(float* r, SegLay lay, unsigned long long seed) {
 }
 
 // Ritz vectors out[i*ldo + nat(t)] = sum_c basis[c][t] P[c*k + i] of a basis in the
-// segment layout: one stored slot per thread, 16 triples per workgroup with their
-// coefficients in LDS; padding slots write nothing.
-constexpr int kRitzSegTile = 16;
-__global__ __launch_bounds__(256) void k_ritz_seg(const float* __restrict__ basis, long long ld, int ncols,
-                                                  const double* __restrict__ P, int k, float* __restrict__ out,
-                                                  long long ldo, SegLay lay) {
-    extern __shared__ double ps[];  // ncols x kRitzSegTile
+// segment layout: 64 stored slots and TILE triples per workgroup (the smallest tile that
+// holds k, so that k <= 32 takes one pass over the basis), with the coefficients in LDS;
+// its four waves take every fourth column (eight loads in flight each) and wave 0 adds
+// the four partial sums in a fixed order.  Padding slots write nothing.
+constexpr int kRitzSegWaves = 4;
+template <int kRitzSegTile>
+__global__ __launch_bounds__(64 * kRitzSegWaves) void k_ritz_seg(const float* __restrict__ basis, long long ld,
+                                                                 int ncols, const double* __restrict__ P, int k,
+                                                                 float* __restrict__ out, long long ldo, SegLay lay) {
+    extern __shared__ double ps[];  // ncols x kRitzSegTile, then (waves - 1) x 64 x kRitzSegTile
+    double* red = ps + (long long)ncols * kRitzSegTile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.y * kRitzSegTile;
     const int kt = min(kRitzSegTile, k - i0);
-    for (int idx = threadIdx.x; idx < ncols * kRitzSegTile; idx += 256) {
+    for (int idx = tid; idx < ncols * kRitzSegTile; idx += 64 * kRitzSegWaves) {
         const int c = idx / kRitzSegTile, i = idx - c * kRitzSegTile;
         ps[idx] = i < kt ? P[(long long)c * k + i0 + i] : 0.0;
     }
-    __syncthreads();
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= lay.len) return;
-    const long long nat = seg_natural(lay, t / lay.S, t % lay.S);
-    if (nat < 0) return;
+    lds_barrier();
+    const long long t = (long long)blockIdx.x * 64 + lane;
+    const bool valid = t < lay.len;
+    const long long tc = valid ? t : 0;  // in-bounds slot for the loads of the tail lanes
     double acc[kRitzSegTile];
 #pragma unroll
     for (int i = 0; i < kRitzSegTile; ++i) acc[i] = 0.0;
-    // eight columns' loads in flight at a time: the loop is bound by their latency
-    int c = 0;
-    for (; c + 8 <= ncols; c += 8) {
+    constexpr int kStep = kRitzSegWaves;
+    int c = wave;
+    for (; c + 7 * kStep < ncols; c += 8 * kStep) {
         float x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = basis[(long long)(c + u) * ld + t];
+        for (int u = 0; u < 8; ++u) x[u] = basis[(long long)(c + u * kStep) * ld + tc];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int i = 0; i < kRitzSegTile; ++i) acc[i] += (double)x[u] * ps[(c + u) * kRitzSegTile + i];
+            for (int i = 0; i < kRitzSegTile; ++i) acc[i] += (double)x[u] * ps[(c + u * kStep) * kRitzSegTile + i];
     }
-    for (; c < ncols; ++c) {
-        const double x = basis[(long long)c * ld + t];
+    for (; c < ncols; c += kStep) {
+        const double x = basis[(long long)c * ld + tc];
 #pragma unroll
         for (int i = 0; i < kRitzSegTile; ++i) acc[i] += x * ps[c * kRitzSegTile + i];
     }
+    if (wave > 0) {
 #pragma unroll
-    for (int i = 0; i < kRitzSegTile; ++i)
-        if (i < kt) out[(long long)(i0 + i) * ldo + nat] = (float)acc[i];
+        for (int i = 0; i < kRitzSegTile; ++i) red[((wave - 1) * 64 + lane) * kRitzSegTile + i] = acc[i];
+    }
+    lds_barrier();
+    if (wave != 0 || !valid) return;
+    const long long nat = seg_natural(lay, t / lay.S, t % lay.S);
+    if (nat < 0) return;
+#pragma unroll
+    for (int i = 0; i < kRitzSegTile; ++i) {
+        double v = acc[i];
+        for (int w = 1; w < kRitzSegWaves; ++w) v += red[((w - 1) * 64 + lane) * kRitzSegTile + i];
+        if (i < kt) out[(long long)(i0 + i) * ldo + nat] = (float)v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -604,17 +643,35 @@ hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipSt
     return hipGetLastError();
 }
 
+hipError_t launch_fold_sums(const FoldRed& f, int ncols, hipStream_t s) {
+    const int per = 64 / kFoldLanes;
+    SSA_LAUNCH(k_fold_sums, dim3((unsigned)((ncols + per) / per)), dim3(64), 0, s, f, ncols);
+    return hipGetLastError();
+}
+
 hipError_t launch_start_seg(float* r, const SegLay& lay, unsigned long long seed, hipStream_t s) {
     hipLaunchKernelGGL(k_start_seg, dim3((unsigned)((lay.len + 255) / 256)), dim3(256), 0, s, r, lay, seed);
     return hipGetLastError();
 }
 
+template <int TILE>
+static hipError_t launch_ritz_seg_t(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
+                                    long long ldo, const SegLay& lay, hipStream_t s) {
+    const dim3 grid((unsigned)((lay.len + 63) / 64), (unsigned)((k + TILE - 1) / TILE));
+    const size_t lds = sizeof(double) * ((size_t)ncols + (kRitzSegWaves - 1) * 64) * TILE;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    SSA_LAUNCH(k_ritz_seg<TILE>, grid, dim3(64 * kRitzSegWaves), lds, s, basis, ld, ncols, P, k, out, ldo, lay);
+    return hipGetLastError();
+}
+
 hipError_t launch_ritz_seg(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
                            long long ldo, const SegLay& lay, hipStream_t s) {
-    const dim3 grid((unsigned)((lay.len + 255) / 256), (unsigned)((k + kRitzSegTile - 1) / kRitzSegTile));
-    const size_t lds = sizeof(double) * (size_t)ncols * kRitzSegTile;
-    SSA_LAUNCH(k_ritz_seg, grid, dim3(256), lds, s, basis, ld, ncols, P, k, out, ldo, lay);
-    return hipGetLastError();
+    if (k <= 8) return launch_ritz_seg_t<8>(basis, ld, ncols, P, k, out, ldo, lay, s);
+    if (k <= 12) return launch_ritz_seg_t<12>(basis, ld, ncols, P, k, out, ldo, lay, s);
+    if (k <= 16) return launch_ritz_seg_t<16>(basis, ld, ncols, P, k, out, ldo, lay, s);
+    if (k <= 20) return launch_ritz_seg_t<20>(basis, ld, ncols, P, k, out, ldo, lay, s);
+    if (k <= 24) return launch_ritz_seg_t<24>(basis, ld, ncols, P, k, out, ldo, lay, s);
+    return launch_ritz_seg_t<32>(basis, ld, ncols, P, k, out, ldo, lay, s);
 }
 
 hipError_t set_fused_attributes() {
@@ -635,7 +692,12 @@ hipError_t set_fused_attributes() {
     allow(reinterpret_cast<const void*>(k_p1_update<8, FftGeneric, true>));
     allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanA, true>));
     allow(reinterpret_cast<const void*>(k_p1_update<4, FftPlanB, true>));
-    allow(reinterpret_cast<const void*>(k_ritz_seg));
+    allow(reinterpret_cast<const void*>(k_ritz_seg<8>));
+    allow(reinterpret_cast<const void*>(k_ritz_seg<12>));
+    allow(reinterpret_cast<const void*>(k_ritz_seg<16>));
+    allow(reinterpret_cast<const void*>(k_ritz_seg<20>));
+    allow(reinterpret_cast<const void*>(k_ritz_seg<24>));
+    allow(reinterpret_cast<const void*>(k_ritz_seg<32>));
     return e;
 }
 

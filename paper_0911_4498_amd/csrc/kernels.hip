@@ -86,6 +86,47 @@ __device__ __forceinline__ float p1_value(const P1In& a, long long m, int y) {
     }
 }
 
+// Element m of input y as a position to load: the float (or, for the series, double) at
+// *pf / *pd when ok, else the value 0 (pf / pd then point at an element that exists, so
+// the load can be issued unconditionally: loads under a branch would be waited for one
+// at a time).
+template <int MODE>
+__device__ __forceinline__ bool p1_where(const P1In& a, long long m, int y, const float*& pf, const double*& pd) {
+    if constexpr (MODE == IN_REV) {
+        long long j = a.n_in - 1 - m;
+        bool ok = m < a.n_in;
+        if (a.pitch && ok) {
+            j = compress_index(j, a.pitch, a.win);
+            ok = j >= 0;
+        }
+        pf = a.x + (ok ? j : 0);
+        return ok;
+    } else if constexpr (MODE == IN_SERIES) {
+        const bool ok = m < a.N;
+        pd = a.f + (ok ? m : 0);
+        return ok;
+    } else {
+        const bool isu = y < a.nu;
+        bool ok = m < (isu ? a.lenu : a.lenv);
+        long long j = m;
+        if (a.pitch && ok) {
+            j = compress_index(m, a.pitch, isu ? a.wu : a.wv);
+            ok = j >= 0;
+        }
+        if (!ok) j = 0;
+        pf = isu ? a.U + (long long)y * a.ldu + j : a.V + (long long)(y - a.nu) * a.ldv + j;
+        return ok;
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ float p1_load(const float* pf, const double* pd) {
+    if constexpr (MODE == IN_SERIES)
+        return (float)*pd;
+    else
+        return *pf;
+}
+
 // Threads of a workgroup of the FFT passes whose rows hold more than 2048
 // points in total (up to 8192: 8 per thread).  Such a workgroup needs 64-96
 // KB of LDS, so it is alone on its CU; the 16 waves are what hides the
@@ -102,8 +143,44 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
     float2* tw = smem + CB * ss;
     const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
     const int y = blockIdx.y;
-    for (int t = tid; t < M1; t += nthr) tw[t] = g.tw1[t];
-    for (int idx = tid; idx < CB * M1; idx += nthr) {
+    // the first four elements per thread (two values each) and the first twiddle are
+    // loaded before any LDS write; whole waves past the data skip their loads
+    const int nz = CB * M1, wave0 = tid & ~63;
+    // positions first, then the loads (all unconditional, at clamped positions), then the
+    // zeros: branches between them would have each load waited for in turn
+    const float* fp[4][2];
+    const double* dp[4][2];
+    bool okv[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = min(tid + i * nthr, nz - 1);
+        const int c = idx % CB, n1 = idx / CB, n2 = min(c0 + c, M2 - 1);
+        const long long n = (long long)M2 * n1 + n2;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            fp[i][e] = nullptr;
+            dp[i][e] = nullptr;
+            okv[i][e] = p1_where<MODE>(a, 2 * n + e, y, fp[i][e], dp[i][e]) && c0 + c < M2 && tid + i * nthr < nz;
+        }
+    }
+    float zr[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) zr[i][e] = p1_load<MODE>(fp[i][e], dp[i][e]);
+    float2 zv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zv[i] = make_float2(okv[i][0] ? zr[i][0] : 0.0f, okv[i][1] ? zr[i][1] : 0.0f);
+    (void)wave0;
+    const float2 tw0 = g.tw1[min(tid, M1 - 1)];
+    if (tid < M1) tw[tid] = tw0;
+    for (int t = tid + nthr; t < M1; t += nthr) tw[t] = g.tw1[t];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = tid + i * nthr;
+        if (idx < nz) buf[(idx % CB) * ss + idx / CB] = zv[i];
+    }
+    for (int idx = tid + 4 * nthr; idx < nz; idx += nthr) {
         const int c = idx % CB, n1 = idx / CB, n2 = c0 + c;
         float2 z = make_float2(0.0f, 0.0f);
         if (n2 < M2) {
@@ -119,11 +196,13 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
     float2 wpre[kPre > 0 ? kPre : 1];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
-        const int idx = tid + i * nthr;
-        const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
-        wpre[i] = (idx < CB * M1 && n2 < M2) ? twiddle_mp(g, (long long)n2 * k1) : make_float2(1.0f, 0.0f);
+        // clamped, unconditional loads; the value is used only where idx < CB * M1 and
+        // n2 < M2
+        const int idx = min(tid + i * nthr, nz - 1);
+        const int c = idx % CB, k1 = idx / CB, n2 = min(c0 + c, M2 - 1);
+        wpre[i] = twiddle_mp(g, (long long)n2 * k1);
     }
-    __syncthreads();
+    lds_barrier();
     lds_fft<-1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
     float2* out = T1 + (long long)y * g.Mp;
     int i = 0;
@@ -231,7 +310,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         buf[idx] = T1[(long long)rp.row(s) * M2 + k2];
     }
     if (stopv != 0.0) return;
-    __syncthreads();
+    lds_barrier();
     fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     int i = 0;
     for (int p = tid; p < rp.npairs; p += nthr, ++i) {
@@ -245,7 +324,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         buf[s0 * M2 + e0] = q0;
         if (s0 != s1 || e0 != e1) buf[s1 * M2 + e1] = q1;
     }
-    __syncthreads();
+    lds_barrier();
     fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2, rp, M2, tid, nthr);
 }
@@ -282,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_pass2_embed(ConvGeom g, const float2* __
     const RowPair rp(blockIdx.x, M1, M2);
     for (int t = tid; t < M2; t += nthr) tw[t] = g.tw2[t];
     load_rows<EPT>(buf, T1, rp, M2, tid, nthr);
-    __syncthreads();
+    lds_barrier();
     lds_fft<-1, EPT>(buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     const double invMp = 1.0 / (double)g.Mp;
     for (int idx = tid; idx < rp.nseq * M2; idx += nthr) {
@@ -364,9 +443,9 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         const int tri = members[mi];
         const double sg = sigma[tri];
         // u_i spectrum rows
-        __syncthreads();
+        lds_barrier();
         load_rows<EPT>(buf, T1all + (long long)tri * Mp, rp, M2, tid, nthr);
-        __syncthreads();
+        lds_barrier();
         fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -378,10 +457,10 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
                 zu1[i] = buf[s1 * M2 + e1];
             }
         }
-        __syncthreads();
+        lds_barrier();
         // v_i spectrum rows
         load_rows<EPT>(buf, T1all + (long long)(k + tri) * Mp, rp, M2, tid, nthr);
-        __syncthreads();
+        lds_barrier();
         fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -413,7 +492,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     const double invMp = 1.0 / (double)Mp;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -437,7 +516,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2all + (long long)blockIdx.y * Mp, rp, M2, tid, nthr);
 }
@@ -491,14 +570,31 @@ __global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restri
     const int c0 = xcd_block(blockIdx.x, gridDim.x) * CB;
     const int y = blockIdx.y;
     const float2* in = T2 + (long long)y * g.Mp;
-    for (int t = tid; t < M1; t += nthr) tw[t] = g.tw1[t];
-    for (int idx = tid; idx < CB * M1; idx += nthr) {
+    // the first four elements per thread (with their twiddles) and the first pass twiddle
+    // are loaded, at clamped positions, before any LDS write
+    const int nz = CB * M1;
+    float2 zv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = min(tid + i * nthr, nz - 1);
+        const int c = idx % CB, k1 = idx / CB, n2 = min(c0 + c, M2 - 1);
+        zv[i] = cmul(in[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
+    }
+    const float2 tw0 = g.tw1[min(tid, M1 - 1)];
+    if (tid < M1) tw[tid] = tw0;
+    for (int t = tid + nthr; t < M1; t += nthr) tw[t] = g.tw1[t];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = tid + i * nthr;
+        if (idx < nz) buf[(idx % CB) * ss + idx / CB] = c0 + idx % CB < M2 ? zv[i] : make_float2(0.0f, 0.0f);
+    }
+    for (int idx = tid + 4 * nthr; idx < nz; idx += nthr) {
         const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
         float2 z = make_float2(0.0f, 0.0f);
         if (n2 < M2) z = cmul(in[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
         buf[c * ss + k1] = z;
     }
-    __syncthreads();
+    lds_barrier();
     lds_fft<1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
     float coef = 0.0f;
     if constexpr (MODE == OUT_SLICE) {

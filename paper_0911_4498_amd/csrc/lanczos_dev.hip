@@ -416,11 +416,11 @@ __device__ __forceinline__ double orth_block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
+    lds_barrier();
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kOrthWaves; ++w) s += red[w];
-    __syncthreads();
+    lds_barrier();
     return s;
 }
 
@@ -433,13 +433,24 @@ __device__ __forceinline__ void orth_against(double* y, const double* V, int m, 
             const double h = wave_dot(V + (long long)q * len, y, len, lane);
             if (lane == 0) hv[q] = h;
         }
-        __syncthreads();
+        lds_barrier();
         for (int t = tid; t < len; t += kOrthThreads) {
             double v = y[t];
-            for (int q = 0; q < m; ++q) v -= hv[q] * V[(long long)q * len + t];
+            int q = 0;
+            // four terms' loads ahead of their (in-order) subtractions
+            for (; q + 4 <= m; q += 4) {
+                const double h0 = hv[q], h1 = hv[q + 1], h2 = hv[q + 2], h3 = hv[q + 3];
+                const double w0 = V[(long long)q * len + t], w1 = V[(long long)(q + 1) * len + t];
+                const double w2 = V[(long long)(q + 2) * len + t], w3 = V[(long long)(q + 3) * len + t];
+                v -= h0 * w0;
+                v -= h1 * w1;
+                v -= h2 * w2;
+                v -= h3 * w3;
+            }
+            for (; q < m; ++q) v -= hv[q] * V[(long long)q * len + t];
             y[t] = v;
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -462,15 +473,15 @@ __global__ __launch_bounds__(kOrthThreads) void k_lz_orth_lds(LzRitz a) {
     }
     for (int i = 0; i < kk; ++i)
         for (int t = tid; t < d; t += kOrthThreads) Xq[(long long)i * d + t] = a.scr[(long long)i * 5 * a.dstride + t];
-    __syncthreads();
+    lds_barrier();
     double bm = 0.0;
     for (int t = tid; t < d; t += kOrthThreads) bm = fmax(bm, fmax(fabs(al[t + 1]), fabs(be[t + 2])));
     bm = wave_max(bm);
     if ((tid & 63) == 0) red[tid >> 6] = bm;
-    __syncthreads();
+    lds_barrier();
     double bmax = 0.0;
     for (int w = 0; w < kOrthWaves; ++w) bmax = fmax(bmax, red[w]);
-    __syncthreads();
+    lds_barrier();
     for (int i = 0; i < kk; ++i) {
         double* xi = Xq + (long long)i * d;
         orth_against(xi, Xq, i, d, hv);
@@ -482,7 +493,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_lz_orth_lds(LzRitz a) {
             xi[t] = v;
             a.Q[(long long)t * a.kstride + i] = v;
         }
-        __syncthreads();
+        lds_barrier();
         double* pi = Pl + (long long)i * (d + 1);
         double pn = 0.0;
         for (int c = d + 1;; --c) {  // c = d + 1: B q itself; then the unit vectors e_d, e_{d-1}, ...
@@ -496,7 +507,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_lz_orth_lds(LzRitz a) {
                 }
                 pi[r] = v;
             }
-            __syncthreads();
+            lds_barrier();
             orth_against(pi, Pl, i, d + 1, hv);
             double sp = 0.0;
             for (int r = tid; r <= d; r += kOrthThreads) sp += pi[r] * pi[r];
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(kOrthThreads) void k_lz_orth_lds(LzRitz a) {
             pi[r] = v;
             a.P[(long long)r * a.kstride + i] = v;
         }
-        __syncthreads();
+        lds_barrier();
     }
     for (int i = tid; i < k; i += kOrthThreads) a.sigma[i] = i < kk ? sqrt(fmax(lam[i], 0.0)) : 0.0;
 }

@@ -203,6 +203,8 @@ struct FoldRed {
     double tol_bd;       // breakdown threshold relative to the running max
     double* snap;        // non-null: restarts and DGKS passes after this reduction (none on this path)
     double* fail;        // gets kDoneFallback when the restart is needed
+    int presummed;       // 1: k_fold_sums has written the column sums to hsum (ncols + 1 doubles)
+    double* hsum;
 };
 
 struct P1Seg {
@@ -312,6 +314,7 @@ hipError_t launch_ritz(const float* basis, long long ld, int ncols, const double
                        float* out, long long ldo, long long n, hipStream_t s);
 hipError_t launch_p3_project(const ConvGeom& g, const float2* T2, const P3Seg& a, hipStream_t s);
 hipError_t launch_p1_update(const ConvGeom& g, const P1Seg& a, float2* T1, hipStream_t s);
+hipError_t launch_fold_sums(const FoldRed& f, int ncols, hipStream_t s);
 hipError_t launch_start_seg(float* r, const SegLay& lay, unsigned long long seed, hipStream_t s);
 hipError_t launch_ritz_seg(const float* basis, long long ld, int ncols, const double* P, int k, float* out,
                            long long ldo, const SegLay& lay, hipStream_t s);

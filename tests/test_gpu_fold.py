@@ -62,6 +62,18 @@ def test_fold_same_bits_as_four_launches(ssa, N, L, k, reorth):
     same_bits(a, b)
 
 
+def test_fold_many_columns_same_bits(ssa):
+    """Past 160 columns the partials are summed by a launch of their own before pass 1
+    (same order, same bits)."""
+    f = inputs.c2_series(20000)
+    # (one stopping test, at the step cap: the run takes all 240 steps)
+    a = solve(ssa, f, 10000, 16, d_max=240, tol=1e-30, check_every=1000)
+    b = solve(ssa, f, 10000, 16, d_max=240, tol=1e-30, check_every=1000, unfused=2)
+    say(f"  steps {a[3].steps} run {a[3].steps_run} launches {a[3].half_step_launches}")
+    assert a[3].half_step_launches == 3 and a[3].steps_run > 200
+    same_bits(a, b)
+
+
 @pytest.mark.parametrize("check_every", [1, 3])
 def test_fold_same_bits_any_check_interval(ssa, check_every):
     """The stopping test of step j waits for the U half's first launch (it yields alpha_j);
