@@ -165,6 +165,23 @@ struct TwoLevelTw {  // W(t) = hi[t >> shift] * lo[t & mask]; two tables of ~sqr
     }
 };
 
+// W(t) for t < n from a table of the first n/4 entries (n divisible by 4), with
+// W(t + n/4) = -i W(t): a quarter of the LDS of the full table.
+struct QuarterTableTw {
+    const float2* tw;
+    int quarter;  // n / 4
+    __device__ __forceinline__ float2 operator()(int t) const {
+        const int q = (t >= quarter) + (t >= 2 * quarter) + (t >= 3 * quarter);
+        const float2 w = tw[t - q * quarter];
+        switch (q) {
+            case 0: return w;
+            case 1: return make_float2(w.y, -w.x);
+            case 2: return make_float2(-w.x, -w.y);
+            default: return make_float2(-w.y, w.x);
+        }
+    }
+};
+
 // One Stockham stage of radix R over nseq sequences of length n.
 // p = product of the radices of earlier stages; tw(t) = e^{-2 pi i t / n}.
 template <int R, int DIR, int EPT, typename TW>
@@ -270,6 +287,17 @@ __device__ __forceinline__ void fft_run(FftFixed<R...>, float2* buf, const FftSt
     constexpr int n = (R * ...);  // the length, and with it every stride and twiddle step, is a constant
     int p = 1;
     ((fft_stage<R, DIR, EPT>(buf, n, nseq, sstride, p, TableTw{tw}, tid, nthr), p *= R), ...);
+}
+
+// The same with the twiddles from a quarter table (tw holds W(t) for t < n/4).
+template <int DIR, int EPT, int... R>
+__device__ __forceinline__ void fft_run_quarter(FftFixed<R...>, float2* buf, int nseq, int sstride,
+                                                const float2* __restrict__ tw, int tid, int nthr) {
+    constexpr int n = (R * ...);
+    static_assert(n % 4 == 0, "quarter table needs n divisible by 4");
+    const QuarterTableTw q{tw, n / 4};
+    int p = 1;
+    ((fft_stage<R, DIR, EPT>(buf, n, nseq, sstride, p, q, tid, nthr), p *= R), ...);
 }
 
 }  // namespace ssa

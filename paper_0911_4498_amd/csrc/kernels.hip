@@ -134,7 +134,9 @@ __device__ __forceinline__ float p1_load(const float* pf, const double* pd) {
 constexpr int kBigThreads = 1024;
 
 
-template <int MODE, int EPT, int NT = 256>
+// QTW: the twiddle table in LDS is a quarter table (fixed-radix long rows, F1 = FftFixed), so
+// that two workgroups share a CU's LDS.
+template <int MODE, int EPT, int NT = 256, typename F1 = FftGeneric, bool QTW = false>
 __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __restrict__ T1) {
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -172,9 +174,10 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
 #pragma unroll
     for (int i = 0; i < 4; ++i) zv[i] = make_float2(okv[i][0] ? zr[i][0] : 0.0f, okv[i][1] ? zr[i][1] : 0.0f);
     (void)wave0;
-    const float2 tw0 = g.tw1[min(tid, M1 - 1)];
-    if (tid < M1) tw[tid] = tw0;
-    for (int t = tid + nthr; t < M1; t += nthr) tw[t] = g.tw1[t];
+    const int ntw = QTW ? M1 / 4 : M1;  // entries of the twiddle table
+    const float2 tw0 = g.tw1[min(tid, ntw - 1)];
+    if (tid < ntw) tw[tid] = tw0;
+    for (int t = tid + nthr; t < ntw; t += nthr) tw[t] = g.tw1[t];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int idx = tid + i * nthr;
@@ -203,7 +206,10 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
         wpre[i] = twiddle_mp(g, (long long)n2 * k1);
     }
     lds_barrier();
-    lds_fft<-1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
+    if constexpr (QTW)
+        fft_run_quarter<-1, EPT>(F1{}, buf, CB, ss, tw, tid, nthr);
+    else
+        fft_run<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, nthr);
     float2* out = T1 + (long long)y * g.Mp;
     int i = 0;
     for (int idx = tid; idx < CB * M1; idx += nthr, ++i) {
@@ -263,7 +269,7 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 }
 
 // pass 2 of a trajectory-matrix product: Q(k) = A(k) Z(k) + B(k) conj Z(M'-k)
-template <int EPT, int NT = 256, typename F2 = FftGeneric>
+template <int EPT, int NT = 256, typename F2 = FftGeneric, bool QTW = false>
 __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* __restrict__ AB,
                                                       const float2* __restrict__ T1,
                                                       float2* __restrict__ T2) {
@@ -287,7 +293,8 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         const int s = idx / M2, k2 = idx - s * M2;
         rv[i] = T1[(long long)rp.row(s) * M2 + k2];
     }
-    const float2 tw0 = g.tw2[min(tid, M2 - 1)];
+    const int ntw = QTW ? M2 / 4 : M2;  // entries of the twiddle table
+    const float2 tw0 = g.tw2[min(tid, ntw - 1)];
     // (not in the 1024-thread instantiation: capped at 128 VGPRs, it would spill)
     constexpr int kPre = NT >= 1024 ? 0 : 2;
     float4 pre0[kPre > 0 ? kPre : 1], pre1[kPre > 0 ? kPre : 1];
@@ -300,8 +307,8 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         pre0[i] = AB[(long long)rp.row(s0) * M2 + e0];
         pre1[i] = AB[(long long)rp.row(s1) * M2 + e1];
     }
-    if (tid < M2) tw[tid] = tw0;
-    for (int t = tid + nthr; t < M2; t += nthr) tw[t] = g.tw2[t];
+    if (tid < ntw) tw[tid] = tw0;
+    for (int t = tid + nthr; t < ntw; t += nthr) tw[t] = g.tw2[t];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         if (tid + i * nthr < total) buf[tid + i * nthr] = rv[i];
@@ -311,7 +318,10 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
     }
     if (stopv != 0.0) return;
     lds_barrier();
-    fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    if constexpr (QTW)
+        fft_run_quarter<-1, EPT>(F2{}, buf, rp.nseq, M2, tw, tid, nthr);
+    else
+        fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     int i = 0;
     for (int p = tid; p < rp.npairs; p += nthr, ++i) {
         int s0, e0, s1, e1;
@@ -325,7 +335,10 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
         if (s0 != s1 || e0 != e1) buf[s1 * M2 + e1] = q1;
     }
     lds_barrier();
-    fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    if constexpr (QTW)
+        fft_run_quarter<1, EPT>(F2{}, buf, rp.nseq, M2, tw, tid, nthr);
+    else
+        fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2, rp, M2, tid, nthr);
 }
 
@@ -560,7 +573,7 @@ __device__ __forceinline__ void p3_emit(const P3Out& o, long long m, float val, 
     }
 }
 
-template <int MODE, int EPT, int NT = 256>
+template <int MODE, int EPT, int NT = 256, typename F1 = FftGeneric, bool QTW = false>
 __global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restrict__ T2, P3Out o) {
     extern __shared__ float2 smem[];
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -580,9 +593,10 @@ __global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restri
         const int c = idx % CB, k1 = idx / CB, n2 = min(c0 + c, M2 - 1);
         zv[i] = cmul(in[(long long)k1 * M2 + n2], cconj(twiddle_mp(g, (long long)n2 * k1)));
     }
-    const float2 tw0 = g.tw1[min(tid, M1 - 1)];
-    if (tid < M1) tw[tid] = tw0;
-    for (int t = tid + nthr; t < M1; t += nthr) tw[t] = g.tw1[t];
+    const int ntw = QTW ? M1 / 4 : M1;  // entries of the twiddle table
+    const float2 tw0 = g.tw1[min(tid, ntw - 1)];
+    if (tid < ntw) tw[tid] = tw0;
+    for (int t = tid + nthr; t < ntw; t += nthr) tw[t] = g.tw1[t];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int idx = tid + i * nthr;
@@ -595,7 +609,10 @@ __global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restri
         buf[c * ss + k1] = z;
     }
     lds_barrier();
-    lds_fft<1, EPT>(buf, g.st1, CB, ss, tw, tid, nthr);
+    if constexpr (QTW)
+        fft_run_quarter<1, EPT>(F1{}, buf, CB, ss, tw, tid, nthr);
+    else
+        fft_run<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, nthr);
     float coef = 0.0f;
     if constexpr (MODE == OUT_SLICE) {
         if (o.coef) coef = (float)(*o.coef);
@@ -1091,6 +1108,10 @@ static bool pass_big(long long elems) { return elems > 2048; }
 
 static size_t lds_p13(const ConvGeom& g) { return sizeof(float2) * ((size_t)g.CB * (g.M1 + 1) + g.M1); }
 static size_t lds_p2(const ConvGeom& g) { return sizeof(float2) * (3 * (size_t)g.M2); }
+// with quarter twiddle tables (the fixed-radix long-row kernels): under 80 KB, so that two
+// workgroups share a CU
+static size_t lds_p13q(const ConvGeom& g) { return sizeof(float2) * ((size_t)g.CB * (g.M1 + 1) + g.M1 / 4); }
+static size_t lds_p2q(const ConvGeom& g) { return sizeof(float2) * (2 * (size_t)g.M2 + g.M2 / 4); }
 
 #define SSA_EPT_SWITCH(ept, EXPR)             \
     switch (ept) {                            \
@@ -1120,7 +1141,9 @@ hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, f
     const int ept = ept_for(elems, 256);
     const dim3 big(kBigThreads);
     if (mode == IN_REV) {
-        if (pass_big(elems))
+        if (pass_big(elems) && FftPlanC::matches(g.st1))
+            hipLaunchKernelGGL((k_pass1<IN_REV, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, in, T1);
+        else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass1<IN_REV, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
         else
             SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_REV, E>), grid, dim3(256), lds, s, g, in, T1));
@@ -1130,7 +1153,9 @@ hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, f
         else
             SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_SERIES, E>), grid, dim3(256), lds, s, g, in, T1));
     } else {
-        if (pass_big(elems))
+        if (pass_big(elems) && FftPlanC::matches(g.st1))
+            hipLaunchKernelGGL((k_pass1<IN_VECS, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, in, T1);
+        else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass1<IN_VECS, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
         else
             SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass1<IN_VECS, E>), grid, dim3(256), lds, s, g, in, T1));
@@ -1142,7 +1167,11 @@ hipError_t launch_pass2_matvec(const ConvGeom& g, const float4* AB, const float2
                                hipStream_t s) {
     const dim3 grid(g.M1 / 2 + 1);
     const int ept = ept_for(2LL * g.M2, 256);
-    if (pass_big(2LL * g.M2))
+    if (pass_big(2LL * g.M2) && FftPlanD::matches(g.st2))
+        SSA_LAUNCH((k_pass2_matvec<8, kBigThreads, FftPlanD, true>), grid, dim3(kBigThreads), lds_p2q(g), s, g, AB, T1, T2);
+    else if (pass_big(2LL * g.M2) && FftPlanC::matches(g.st2))
+        SSA_LAUNCH((k_pass2_matvec<8, kBigThreads, FftPlanC, true>), grid, dim3(kBigThreads), lds_p2q(g), s, g, AB, T1, T2);
+    else if (pass_big(2LL * g.M2))
         SSA_LAUNCH((k_pass2_matvec<8, kBigThreads>), grid, dim3(kBigThreads), lds_p2(g), s, g, AB, T1, T2);
     else if (ept == 4 && FftPlanB::matches(g.st2))
         SSA_LAUNCH((k_pass2_matvec<4, 256, FftPlanB>), grid, dim3(256), lds_p2(g), s, g, AB, T1, T2);
@@ -1197,12 +1226,16 @@ hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3O
     const int ept = ept_for(elems, 256);
     const dim3 big(kBigThreads);
     if (mode == OUT_SLICE) {
-        if (pass_big(elems))
+        if (pass_big(elems) && FftPlanC::matches(g.st1))
+            hipLaunchKernelGGL((k_pass3<OUT_SLICE, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, T2, o);
+        else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass3<OUT_SLICE, 8, kBigThreads>), grid, big, lds, s, g, T2, o);
         else
             SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_SLICE, E>), grid, dim3(256), lds, s, g, T2, o));
     } else {
-        if (pass_big(elems))
+        if (pass_big(elems) && FftPlanC::matches(g.st1))
+            hipLaunchKernelGGL((k_pass3<OUT_HANKEL, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, T2, o);
+        else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass3<OUT_HANKEL, 8, kBigThreads>), grid, big, lds, s, g, T2, o);
         else
             SSA_EPT_SWITCH(ept, hipLaunchKernelGGL((k_pass3<OUT_HANKEL, E>), grid, dim3(256), lds, s, g, T2, o));
@@ -1327,6 +1360,12 @@ hipError_t set_kernel_attributes() {
     SSA_ALLOW((k_pass1<IN_VECS, 8, kBigThreads>));
     SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads>));
     SSA_ALLOW((k_pass2_matvec<8, kBigThreads>)); SSA_ALLOW((k_pass2_embed<8, kBigThreads>));
+    SSA_ALLOW((k_pass1<IN_REV, 8, kBigThreads, FftPlanC, true>));
+    SSA_ALLOW((k_pass1<IN_VECS, 8, kBigThreads, FftPlanC, true>));
+    SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads, FftPlanC, true>));
+    SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads, FftPlanC, true>));
+    SSA_ALLOW((k_pass2_matvec<8, kBigThreads, FftPlanC, true>));
+    SSA_ALLOW((k_pass2_matvec<8, kBigThreads, FftPlanD, true>));
     SSA_ALLOW_EPT(k_pass2_matvec);
     SSA_ALLOW((k_pass2_matvec<4, 256, FftPlanA>)); SSA_ALLOW((k_pass2_matvec<4, 256, FftPlanB>));
     SSA_ALLOW((k_pass2_recon<4, 1, FftPlanA>)); SSA_ALLOW((k_pass2_recon<4, 1, FftPlanB>));

@@ -57,6 +57,9 @@ struct ConvGeom {
 // schedule tuner's winner and runner-up).  Every other length runs the generic kernels.
 using FftPlanA = FftFixed<8, 5, 5>;
 using FftPlanB = FftFixed<8, 8, 4>;
+// the long-row passes of N = 2^22 .. 2^24 (M1 or M2 = 2048 and 4096)
+using FftPlanC = FftFixed<8, 8, 8, 4>;
+using FftPlanD = FftFixed<8, 8, 8, 8>;
 
 // pass-1 input modes
 enum { IN_REV = 0, IN_SERIES = 1, IN_VECS = 2 };
