@@ -1143,6 +1143,8 @@ hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, f
     if (mode == IN_REV) {
         if (pass_big(elems) && FftPlanC::matches(g.st1))
             hipLaunchKernelGGL((k_pass1<IN_REV, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, in, T1);
+        else if (pass_big(elems) && FftPlanD::matches(g.st1))
+            hipLaunchKernelGGL((k_pass1<IN_REV, 8, kBigThreads, FftPlanD, true>), grid, big, lds_p13q(g), s, g, in, T1);
         else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass1<IN_REV, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
         else
@@ -1155,6 +1157,8 @@ hipError_t launch_pass1(const ConvGeom& g, int mode, const P1In& in, int nvec, f
     } else {
         if (pass_big(elems) && FftPlanC::matches(g.st1))
             hipLaunchKernelGGL((k_pass1<IN_VECS, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, in, T1);
+        else if (pass_big(elems) && FftPlanD::matches(g.st1))
+            hipLaunchKernelGGL((k_pass1<IN_VECS, 8, kBigThreads, FftPlanD, true>), grid, big, lds_p13q(g), s, g, in, T1);
         else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass1<IN_VECS, 8, kBigThreads>), grid, big, lds, s, g, in, T1);
         else
@@ -1228,6 +1232,8 @@ hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3O
     if (mode == OUT_SLICE) {
         if (pass_big(elems) && FftPlanC::matches(g.st1))
             hipLaunchKernelGGL((k_pass3<OUT_SLICE, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, T2, o);
+        else if (pass_big(elems) && FftPlanD::matches(g.st1))
+            hipLaunchKernelGGL((k_pass3<OUT_SLICE, 8, kBigThreads, FftPlanD, true>), grid, big, lds_p13q(g), s, g, T2, o);
         else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass3<OUT_SLICE, 8, kBigThreads>), grid, big, lds, s, g, T2, o);
         else
@@ -1235,6 +1241,8 @@ hipError_t launch_pass3(const ConvGeom& g, int mode, const float2* T2, const P3O
     } else {
         if (pass_big(elems) && FftPlanC::matches(g.st1))
             hipLaunchKernelGGL((k_pass3<OUT_HANKEL, 8, kBigThreads, FftPlanC, true>), grid, big, lds_p13q(g), s, g, T2, o);
+        else if (pass_big(elems) && FftPlanD::matches(g.st1))
+            hipLaunchKernelGGL((k_pass3<OUT_HANKEL, 8, kBigThreads, FftPlanD, true>), grid, big, lds_p13q(g), s, g, T2, o);
         else if (pass_big(elems))
             hipLaunchKernelGGL((k_pass3<OUT_HANKEL, 8, kBigThreads>), grid, big, lds, s, g, T2, o);
         else
@@ -1361,6 +1369,10 @@ hipError_t set_kernel_attributes() {
     SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads>)); SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads>));
     SSA_ALLOW((k_pass2_matvec<8, kBigThreads>)); SSA_ALLOW((k_pass2_embed<8, kBigThreads>));
     SSA_ALLOW((k_pass1<IN_REV, 8, kBigThreads, FftPlanC, true>));
+    SSA_ALLOW((k_pass1<IN_REV, 8, kBigThreads, FftPlanD, true>));
+    SSA_ALLOW((k_pass1<IN_VECS, 8, kBigThreads, FftPlanD, true>));
+    SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads, FftPlanD, true>));
+    SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads, FftPlanD, true>));
     SSA_ALLOW((k_pass1<IN_VECS, 8, kBigThreads, FftPlanC, true>));
     SSA_ALLOW((k_pass3<OUT_SLICE, 8, kBigThreads, FftPlanC, true>));
     SSA_ALLOW((k_pass3<OUT_HANKEL, 8, kBigThreads, FftPlanC, true>));

@@ -205,6 +205,17 @@ def test_ragged_long_series_tails(ssa):
     certify(ssa, f, L, k, sampled_rows=128, recon_positions=128, d_max=40, fft_mp=2 ** 21, fft_m1=2048, fft_cb=4)
 
 
+def test_long_columns_of_4096_points(ssa):
+    """N = 2^22 with the split M' = 2^21 = 4096 x 512, CB = 2: passes 1 and 3 run the
+    fixed-radix 8-8-8-8 column kernels with the quarter twiddle table.  Certificates on
+    sampled rows."""
+    N = 2 ** 22
+    L, k = N // 2, 4
+    say(f"4096-point columns: N={N} L={L} k={k} d_max=24 M'=2^21 (4096 x 512) CB=2")
+    f = inputs.c5_series(N)
+    certify(ssa, f, L, k, sampled_rows=64, recon_positions=64, d_max=24, fft_mp=2 ** 21, fft_m1=4096, fft_cb=2)
+
+
 def test_one_sided_second_passes_run_on_the_whole_grid(ssa):
     """Request 6 of the served stream (N = 241251, L = N/2, k = 13) with one-sided
     reorthogonalization: the U-side Gram-Schmidt often removes most of the vector, so DGKS
