@@ -137,7 +137,6 @@ struct ssa_plan_s {
     int fused;  // 1: the four-launch half-step of fused.hip, bases in the segment layout
     int fold;   // 1: each reduction is folded into the next pass-1 update (three launches)
     int fold_off = 0;  // this solve restarted without the fold (a DGKS pass or a breakdown)
-    int fell_back = 0; // ... and so it did
     SegLay layU, layV;  // segment layouts of the U-side (length Li) and V-side (length Ki) vectors
     int nblk;   // pass-3 workgroups of a product (partial sums per column on the fused path)
     double tol;
@@ -847,7 +846,6 @@ int run_begin(ssa_plan p, const double* series_dev, int k) {
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_beta), p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
     p->fold_off = 0;
-    p->fell_back = 0;
     rc = start_vector(p);
     if (rc != SSA_OK) return rc;
     p->run = decltype(p->run){};
@@ -876,7 +874,6 @@ int run_restart_unfolded(ssa_plan p) {
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_beta), p->d_max + 3, s));
     SSA_TRY(launch_fill_zero(at<double>(p, p->o_state), 8, s));
     p->fold_off = 1;
-    p->fell_back = 1;
     const int rc = start_vector(p);
     if (rc != SSA_OK) return rc;
     R.j = 1;

@@ -1211,6 +1211,12 @@ hipError_t launch_pass2_recon(const ConvGeom& g, const float2* T1all, int k, con
     } else if (np <= 1 && ept == 4 && FftPlanA::matches(g.st2)) {
         hipLaunchKernelGGL((k_pass2_recon<4, 1, FftPlanA>), grid, dim3(kReconThreads), lds_p2(g), s, g, T1all, k,
                            sigma, offs, members, g0, T2all);
+    } else if (np == 4 && ept == 8 && FftPlanD::matches(g.st2)) {
+        hipLaunchKernelGGL((k_pass2_recon<8, 4, FftPlanD>), grid, dim3(kReconThreads), lds_p2(g), s, g, T1all, k,
+                           sigma, offs, members, g0, T2all);
+    } else if (np == 2 && ept == 4 && FftPlanC::matches(g.st2)) {
+        hipLaunchKernelGGL((k_pass2_recon<4, 2, FftPlanC>), grid, dim3(kReconThreads), lds_p2(g), s, g, T1all, k,
+                           sigma, offs, members, g0, T2all);
     } else if (np <= 1) {
         SSA_RECON(1);
     } else if (np <= 2) {
@@ -1381,6 +1387,7 @@ hipError_t set_kernel_attributes() {
     SSA_ALLOW_EPT(k_pass2_matvec);
     SSA_ALLOW((k_pass2_matvec<4, 256, FftPlanA>)); SSA_ALLOW((k_pass2_matvec<4, 256, FftPlanB>));
     SSA_ALLOW((k_pass2_recon<4, 1, FftPlanA>)); SSA_ALLOW((k_pass2_recon<4, 1, FftPlanB>));
+    SSA_ALLOW((k_pass2_recon<8, 4, FftPlanD>)); SSA_ALLOW((k_pass2_recon<4, 2, FftPlanC>));
     SSA_ALLOW_EPT(k_pass2_embed);
 #define SSA_ALLOW_RECON(NPV)                                                                   \
     SSA_ALLOW((k_pass2_recon<4, NPV>)); SSA_ALLOW((k_pass2_recon<8, NPV>));                      \
