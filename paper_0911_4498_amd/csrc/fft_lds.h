@@ -182,9 +182,18 @@ struct QuarterTableTw {
     }
 };
 
-// One Stockham stage of radix R over nseq sequences of length n.
+// Ordering of LDS accesses within one wave (the wave's LDS instructions complete in issue
+// order; this keeps the compiler from moving them across it).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// One Stockham stage of radix R over nseq sequences of length n.  WAVE: the transform
+// belongs to one wave (tid = lane, nthr = 64), whose stages need no workgroup barrier.
 // p = product of the radices of earlier stages; tw(t) = e^{-2 pi i t / n}.
-template <int R, int DIR, int EPT, typename TW>
+template <int R, int DIR, int EPT, typename TW, bool WAVE = false>
 __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstride, int p,
                                           const TW& tw, int tid, int nthr) {
     constexpr int NB = (EPT + R - 1) / R;
@@ -216,7 +225,10 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstr
             for (int r = 0; r < R; ++r) v[i][r] = x[r];
         }
     }
-    lds_barrier();
+    if constexpr (WAVE)
+        wave_lds_sync();
+    else
+        lds_barrier();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int b = tid + i * nthr;
@@ -229,7 +241,10 @@ __device__ __forceinline__ void fft_stage(float2* buf, int n, int nseq, int sstr
             for (int r = 0; r < R; ++r) dst[r * p] = v[i][r];
         }
     }
-    lds_barrier();
+    if constexpr (WAVE)
+        wave_lds_sync();
+    else
+        lds_barrier();
 }
 
 // Full transform.  Requires n * nseq <= EPT * nthr.  Ends synchronized.
@@ -262,10 +277,13 @@ __device__ void lds_fft(float2* buf, const FftStages& st, int nseq, int sstride,
 // one's, which matters when each launch is short and starts with cold instruction caches.
 // FftGeneric runs the sequence of the FftStages argument.
 struct FftGeneric {
+    static constexpr bool kFixed = false;
     static __host__ __device__ bool matches(const FftStages&) { return true; }
 };
 template <int... R>
 struct FftFixed {
+    static constexpr bool kFixed = true;
+    static constexpr int kLength = (R * ...);
     static __host__ __device__ bool matches(const FftStages& st) {
         constexpr int r[] = {R...};
         if (st.nstages != (int)sizeof...(R)) return false;
@@ -287,6 +305,35 @@ __device__ __forceinline__ void fft_run(FftFixed<R...>, float2* buf, const FftSt
     constexpr int n = (R * ...);  // the length, and with it every stride and twiddle step, is a constant
     int p = 1;
     ((fft_stage<R, DIR, EPT>(buf, n, nseq, sstride, p, TableTw{tw}, tid, nthr), p *= R), ...);
+}
+
+// One transform of a fixed length by one wave (lane < 64; at most 4 points per lane, so
+// n <= 256), with no workgroup barrier between its stages: the caller synchronizes the
+// workgroup before other waves read the result.
+template <int DIR, int... R>
+__device__ __forceinline__ void fft_run_wave(FftFixed<R...>, float2* buf, const float2* __restrict__ tw, int lane) {
+    constexpr int n = (R * ...);
+    static_assert(n <= 256, "one wave, four points per lane");
+    int p = 1;
+    ((fft_stage<R, DIR, 4, TableTw, true>(buf, n, 1, n, p, TableTw{tw}, lane, 64), p *= R), ...);
+}
+
+// nseq transforms of a fixed length of at most 256 points, one per wave (nseq <= waves),
+// or the workgroup-wide transform otherwise; ends synchronized.
+template <int DIR, int EPT, typename F>
+__device__ __forceinline__ void fft_run_waves(F f, float2* buf, const FftStages& st, int nseq, int sstride,
+                                              const float2* __restrict__ tw, int tid, int nthr) {
+    if constexpr (F::kFixed) {
+        if constexpr (F::kLength <= 256) {
+            if (nseq <= nthr / 64) {
+                const int wave = tid >> 6;
+                if (wave < nseq) fft_run_wave<DIR>(f, buf + (long long)wave * sstride, tw, tid & 63);
+                lds_barrier();
+                return;
+            }
+        }
+    }
+    fft_run<DIR, EPT>(f, buf, st, nseq, sstride, tw, tid, nthr);
 }
 
 // The same with the twiddles from a quarter table (tw holds W(t) for t < n/4).

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p3_project(ConvGeom g, const 
     }
     if (stopv != 0.0) return;
     lds_barrier();
-    fft_run<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
+    fft_run_waves<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int q = tid; q < nsl; q += kFusedThreads) {
         const int sg = q / S, t = q - sg * S;
         const int c = sg >> 1, e = sg & 1, n2 = c0 + c;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_p1_update(ConvGeom g, P1Seg a
         }
     }
     lds_barrier();
-    fft_run<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
+    fft_run_waves<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, kFusedThreads);
     for (int idx = tid; idx < CB * M1; idx += kFusedThreads) {
         const int c = idx % CB, k1 = idx / CB, n2 = c0 + c;
         if (n2 < M2) T1[(long long)k1 * M2 + n2] = cmul(buf[c * ss + k1], twiddle_mp(g, (long long)n2 * k1));

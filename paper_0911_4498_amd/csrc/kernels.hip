@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NT) void k_pass1(ConvGeom g, P1In a, float2* __rest
     if constexpr (QTW)
         fft_run_quarter<-1, EPT>(F1{}, buf, CB, ss, tw, tid, nthr);
     else
-        fft_run<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, nthr);
+        fft_run_waves<-1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, nthr);
     float2* out = T1 + (long long)y * g.Mp;
     int i = 0;
     for (int idx = tid; idx < CB * M1; idx += nthr, ++i) {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
     if constexpr (QTW)
         fft_run_quarter<-1, EPT>(F2{}, buf, rp.nseq, M2, tw, tid, nthr);
     else
-        fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+        fft_run_waves<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     int i = 0;
     for (int p = tid; p < rp.npairs; p += nthr, ++i) {
         int s0, e0, s1, e1;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_pass2_matvec(ConvGeom g, const float4* _
     if constexpr (QTW)
         fft_run_quarter<1, EPT>(F2{}, buf, rp.nseq, M2, tw, tid, nthr);
     else
-        fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+        fft_run_waves<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2, rp, M2, tid, nthr);
 }
 
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         lds_barrier();
         load_rows<EPT>(buf, T1all + (long long)tri * Mp, rp, M2, tid, nthr);
         lds_barrier();
-        fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+        fft_run_waves<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             const int p = tid + i * nthr;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         // v_i spectrum rows
         load_rows<EPT>(buf, T1all + (long long)(k + tri) * Mp, rp, M2, tid, nthr);
         lds_barrier();
-        fft_run<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+        fft_run_waves<-1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             const int p = tid + i * nthr;
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(kReconThreads) void k_pass2_recon(ConvGeom g, const
         }
     }
     lds_barrier();
-    fft_run<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
+    fft_run_waves<1, EPT>(F2{}, buf, g.st2, rp.nseq, M2, tw, tid, nthr);
     store_rows<EPT>(buf, T2all + (long long)blockIdx.y * Mp, rp, M2, tid, nthr);
 }
 
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(NT) void k_pass3(ConvGeom g, const float2* __restri
     if constexpr (QTW)
         fft_run_quarter<1, EPT>(F1{}, buf, CB, ss, tw, tid, nthr);
     else
-        fft_run<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, nthr);
+        fft_run_waves<1, EPT>(F1{}, buf, g.st1, CB, ss, tw, tid, nthr);
     float coef = 0.0f;
     if constexpr (MODE == OUT_SLICE) {
         if (o.coef) coef = (float)(*o.coef);
