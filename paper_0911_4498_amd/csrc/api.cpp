@@ -134,7 +134,7 @@ struct ssa_plan_s {
     int keep;   // thick restart: Ritz pairs kept per cycle (0: no restart)
     int onesided;  // 1: only the length-Li basis (U) is reorthogonalized
     int kcols;  // columns of the P/Q coefficient buffers: max(k_max, keep)
-    int fused;  // 1: the four-launch half-step of fused.hip, bases in the segment layout
+    int fused;  // 1: the fused half-step of fused.hip (three or four launches), bases in the segment layout
     int fold;   // 1: each reduction is folded into the next pass-1 update (three launches)
     int fold_off = 0;  // this solve restarted without the fold (a DGKS pass or a breakdown)
     SegLay layU, layV;  // segment layouts of the U-side (length Li) and V-side (length Ki) vectors

@@ -1,4 +1,5 @@
-// fused.hip -- the Lanczos half-step of the single-series path in four launches.
+// fused.hip -- the Lanczos half-step of the single-series path in three launches
+// (four with the reduction as its own launch).
 //
 // Algorithm 1 alternates two half-steps; each is one trajectory-matrix product by
 // FFT (Algorithms 2/3: pass 1 column FFTs, pass 2 row FFTs with the spectral
@@ -7,14 +8,17 @@
 // grid-wide synchronization on this GPU, so the work is cut where a grid-wide
 // result is needed and fused everywhere else:
 //
-//   k_p1_update   finishes the previous half-step's vector x = (r - B h) * scale
-//                 (B its basis, h and scale from the reduction) and runs pass 1
-//                 of the product that takes x;
+//   k_p1_update   the reduction of the previous half-step (every workgroup sums the
+//                 partials itself: h, the new alpha or beta, the normalization; a
+//                 DGKS pass or a breakdown sends the solve back to the four-launch
+//                 form), then finishes that half-step's vector x = (r - B h) * scale
+//                 (B its basis) and runs pass 1 of the product that takes x;
 //   pass 2        unchanged (kernels.hip);
 //   k_p3_project  pass 3, the three-term term r = y - coef * prev, and the
-//                 projection partials <b_c, r> and |r|^2 of its block;
-//   reduce        one workgroup: h, the new alpha or beta, DGKS, breakdown
-//                 (k_cgs_reduce, kernels.hip).
+//                 projection partials <b_c, r> and |r|^2 of its block.
+//
+// In the four-launch form a single workgroup does the reduction in between
+// (k_cgs_reduce, kernels.hip: DGKS, breakdown) and k_p1_update reads h and scale.
 //
 // The vectors of both bases live in the segment layout (SegLay): pass 3's
 // workgroup owns a contiguous slot range of its output, and the reversed input of
