@@ -29,10 +29,10 @@ engine (ssa_batch_*); the JSON line also reports the single-series path on a
 sample of the same series, one series at a time, on the same GPU.
 With --workload served: a Poisson stream of requests (N log-uniform in
 [1e3, 1e6], L in {N/4, N/2}, k in [8, 32], seeded) at each of --rates;
-every request goes to the continuous-batching server (ssa_server_*): N <= 20480 to its
-batched engine, longer ones to its long path (single-series plans bound to regions of
-the same pool, --long-slots (4) at a time, one check interval per tick); reports p50/p99
-latency from arrival to complete outputs, and throughput.
+every request goes to the continuous-batching server (ssa_server_*): N <= --batched-n-max
+(8192) to its batched engine, longer ones to its long path (single-series plans bound to
+regions of the same pool, --long-slots (4) at a time, one check interval per tick);
+reports p50/p99 latency from arrival to complete outputs, and throughput.
 With --workload long: the very long series (N = 2^24, L = N/2, k = 50) through
 the single-series path with the basis capped by thick restart (--d-max,
 --restart-keep); suggested --steps 2 --warmup 1.
@@ -294,15 +294,15 @@ def cpu_baseline_many(host, Ns, k, info, ns):
 
 
 def served_stream(args, nreq, rates, quiet=False):
-    """Served stream through ssa_server_*: requests with N <= 20480 go to the batched
-    engine, longer ones to the server's long path (single-series plans bound to regions
-    of the same pool, one check interval per tick).  Returns one result per rate."""
+    """Served stream through ssa_server_*: requests with N <= args.batched_n_max go to the
+    batched engine, longer ones to the server's long path (single-series plans bound to
+    regions of the same pool, one check interval per tick).  Returns one result per rate."""
     import numpy as np
     import torch
 
     from paper_0911_4498_amd import inputs, ssa
     dev = torch.device("cuda:0")
-    n_small_max = 20480
+    n_small_max = args.batched_n_max
     log = (lambda *a: None) if quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     log(f"# generating {nreq} requests")
     reqs = []
@@ -585,6 +585,9 @@ def main():
     ap.add_argument("--slots", type=int, default=256, help="server slots (served stream)")
     ap.add_argument("--pool-gb", type=float, default=24.0, help="server pool GiB (served stream)")
     ap.add_argument("--long-slots", type=int, default=4, help="server long-request slots (served stream)")
+    ap.add_argument("--batched-n-max", type=int, default=8192,
+                    help="longest series the server's batched engine takes (served stream; longer ones "
+                         "take its single-series path; the engine allows up to 20480)")
     ap.add_argument("--served-requests", type=int, default=120,
                     help="requests of the bounded served leg of the default run (0: none)")
     ap.add_argument("--series", type=int, default=4096, help="series of the many-series workload")
