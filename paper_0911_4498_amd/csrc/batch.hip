@@ -212,31 +212,93 @@ SSA_INLINE void load_twiddles(Lds* sh, const Ser& q, int tid) {
 
 // r = X x or X^T x (x: n_in entries in HBM) minus coef * prev, written to r_out
 // (n_out entries); the product is y[n_in - 1 + t] of the circular convolution.
+// Each phase issues all of a thread's global loads before it uses the first of them
+// (at clamped, in-bounds positions; values past the data are replaced by zeros), so
+// a phase waits for HBM once rather than once per loop iteration.  The twiddle tables
+// are loaded here as well.
+constexpr int kConvPts = kMaxMp / kFftThreads;              // input points per thread
+constexpr int kConvPtBatch = 5;                              // input points whose loads fly together
+constexpr int kConvPairs = (kMaxMp / 2) / kFftThreads + 1;  // bin pairs per thread
+constexpr int kConvPairBatch = 3;                            // bin pairs whose operator loads fly together
+constexpr int kConvOutBatch = 10;                            // outputs whose prev loads fly together
+static_assert(kMaxMp % kFftThreads == 0 && kTwTab <= kFftThreads && 2 * kMaxMp < (1 << 30),
+              "convolve's load layout");
 SSA_INLINE void convolve(Lds* sh, const Ser& q, const float* x, long long n_in, long long n_out, const float* prev,
                          double coef, float* r_out, int tid) {
     float2* buf = sh->buf;
-    for (int n = tid; n < q.Mp; n += kFftThreads) {
-        const long long m0 = 2LL * n, m1 = m0 + 1;
-        buf[n] = make_float2(m0 < n_in ? x[n_in - 1 - m0] : 0.0f, m1 < n_in ? x[n_in - 1 - m1] : 0.0f);
+    const int wave0 = tid & ~63;  // (whole waves past the data skip their loads)
+    const int nin = (int)n_in;    // <= 2 M'
+    float2 th = make_float2(0.0f, 0.0f), tl = th;
+    if (wave0 < kTwTab) {
+        th = q.tw[min(tid, kTwTab - 1)];
+        tl = q.tw[kTwTab + min(tid, kTwTab - 1)];
+    }
+    // the reversed input w[m] = x[n_in - 1 - m], packed w[2n] + i w[2n+1] at buf[n]
+    for (int b = 0; b < kConvPts && wave0 + b * kFftThreads < q.Mp; b += kConvPtBatch) {
+        float x0[kConvPtBatch], x1[kConvPtBatch];
+#pragma unroll
+        for (int i = 0; i < kConvPtBatch; ++i) {
+            x0[i] = 0.0f;
+            x1[i] = 0.0f;
+            if (wave0 + (b + i) * kFftThreads >= q.Mp) continue;
+            const int m0 = 2 * (tid + (b + i) * kFftThreads);
+            x0[i] = x[max(nin - 1 - m0, 0)];
+            x1[i] = x[max(nin - 2 - m0, 0)];
+        }
+        if (b == 0 && tid < kTwTab) {
+            sh->tw_hi[tid] = th;
+            sh->tw_lo[tid] = tl;
+        }
+#pragma unroll
+        for (int i = 0; i < kConvPtBatch; ++i) {
+            const int n = tid + (b + i) * kFftThreads, m0 = 2 * n;
+            if (n < q.Mp) buf[n] = make_float2(m0 < nin ? x0[i] : 0.0f, m0 + 1 < nin ? x1[i] : 0.0f);
+        }
     }
     __syncthreads();
     fft<-1>(sh, q, tid);
     // Q(k) = A(k) Z(k) + B(k) conj Z(M'-k), for the bin pair (k, M'-k) owned by one thread
-    for (int k = tid; k <= q.Mp / 2; k += kFftThreads) {
-        const int kp = k == 0 ? 0 : q.Mp - k;
-        const float2 z0 = buf[k], z1 = buf[kp];
-        const float4 o0 = q.AB[k], o1 = q.AB[kp];
-        const float2 q0 = cadd(cmul(make_float2(o0.x, o0.y), z0), cmul(make_float2(o0.z, o0.w), cconj(z1)));
-        const float2 q1 = cadd(cmul(make_float2(o1.x, o1.y), z1), cmul(make_float2(o1.z, o1.w), cconj(z0)));
-        buf[k] = q0;
-        if (kp != k) buf[kp] = q1;
+    const int half = q.Mp / 2;
+    for (int b = 0; b < kConvPairs && wave0 + b * kFftThreads <= half; b += kConvPairBatch) {
+        float4 o0[kConvPairBatch], o1[kConvPairBatch];
+#pragma unroll
+        for (int i = 0; i < kConvPairBatch; ++i) {
+            o0[i] = o1[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (wave0 + (b + i) * kFftThreads > half) continue;
+            const int k = min(tid + (b + i) * kFftThreads, half);
+            o0[i] = q.AB[k];
+            o1[i] = q.AB[k == 0 ? 0 : q.Mp - k];
+        }
+#pragma unroll
+        for (int i = 0; i < kConvPairBatch; ++i) {
+            const int k = tid + (b + i) * kFftThreads;
+            if (k > half) continue;
+            const int kp = k == 0 ? 0 : q.Mp - k;
+            const float2 z0 = buf[k], z1 = buf[kp];
+            const float2 q0 = cadd(cmul(make_float2(o0[i].x, o0[i].y), z0), cmul(make_float2(o0[i].z, o0[i].w), cconj(z1)));
+            const float2 q1 = cadd(cmul(make_float2(o1[i].x, o1[i].y), z1), cmul(make_float2(o1[i].z, o1[i].w), cconj(z0)));
+            buf[k] = q0;
+            if (kp != k) buf[kp] = q1;
+        }
     }
     __syncthreads();
     fft<1>(sh, q, tid);
     const float cf = (float)coef;
-    for (long long t = tid; t < n_out; t += kFftThreads) {
-        const float y = getr(buf, n_in - 1 + t);
-        r_out[t] = prev ? y - cf * prev[t] : y;
+    for (long long t0 = 0; t0 < n_out; t0 += (long long)kConvOutBatch * kFftThreads) {
+        float pv[kConvOutBatch];
+#pragma unroll
+        for (int i = 0; i < kConvOutBatch; ++i) {
+            pv[i] = 0.0f;
+            if (!prev || t0 + wave0 + i * kFftThreads >= n_out) continue;
+            pv[i] = prev[min(t0 + tid + i * kFftThreads, n_out - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < kConvOutBatch; ++i) {
+            const long long t = t0 + tid + i * kFftThreads;
+            if (t >= n_out) continue;
+            const float y = getr(buf, n_in - 1 + t);
+            r_out[t] = prev ? y - cf * pv[i] : y;
+        }
     }
 }
 
@@ -490,7 +552,6 @@ __global__ __launch_bounds__(kFftThreads) void kb_conv(BatchArgs a, int side) {
     const Ser q = load_series(a, s);
     const int j = (int)q.state[kStJ];
     if (q.state[kStDone] != 0.0 || j - 1 > q.dcap) return;
-    load_twiddles(sh, q, tid);
     if (side == 0)
         convolve(sh, q, q.U + (long long)(j - 1) * q.ldu, q.Li, q.Ki,
                  j >= 2 ? q.V + (long long)(j - 2) * q.ldv : nullptr, q.beta[j], q.r, tid);
