@@ -561,7 +561,8 @@ __global__ __launch_bounds__(kFftThreads) void kb_conv(BatchArgs a, int side) {
 }
 
 // Gram-Schmidt part: side 0: v_j and alpha_j;  side 1: u_{j+1} and beta_{j+1}.
-__global__ __launch_bounds__(kCgsThreads) void kb_cgs(BatchArgs a, int side) {
+// (six waves per SIMD: at most 80 VGPRs, no spills, three workgroups per CU)
+__global__ __launch_bounds__(kCgsThreads, 6) void kb_cgs(BatchArgs a, int side) {
     extern __shared__ char lds[];
     CgsLds* sh = reinterpret_cast<CgsLds*>(lds);
     const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
