@@ -323,7 +323,8 @@ int convolve(ssa_plan p, const ConvGeom& g, const float* x, int side, float* out
         SSA_TRY(launch_pass1(g, IN_REV, in, 1, at<float2>(p, p->o_t1), s));
     }
     {
-        ProfScope ps(p, SSA_PROF_PASS2, 24.0 * mp);
+        // T1 in (8 B a point), the spectral operator (A, B: 16 B a point), T2 out (8 B)
+        ProfScope ps(p, SSA_PROF_PASS2, 32.0 * mp);
         SSA_TRY(launch_pass2_matvec(g, at<float4>(p, p->o_ab), at<float2>(p, p->o_t1), at<float2>(p, p->o_t2), s));
     }
     P3Out o{};
@@ -567,7 +568,7 @@ int fused_pass23(ssa_plan p, const ConvGeom& g, const SegLay& lout, const float*
     float2* T2 = at<float2>(p, p->o_t2);
     const double mp = (double)g.Mp;
     {
-        ProfScope ps(p, SSA_PROF_PASS2, 24.0 * mp);
+        ProfScope ps(p, SSA_PROF_PASS2, 32.0 * mp);  // T1, the operator (16 B a point), T2
         SSA_TRY(launch_pass2_matvec(g, at<float4>(p, p->o_ab), T1, T2, s));
     }
     P3Seg b{};
