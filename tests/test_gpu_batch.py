@@ -145,6 +145,25 @@ def test_batch_c3_series_match_oracle(ssa, s):
     say(f"   {rep}")
 
 
+@pytest.mark.parametrize("N,L", [(20480, 10240), (20479, 5000)])
+def test_batch_longest_series_match_oracle(ssa, N, L):
+    """The longest series the batched engine holds (M' = 10240 points in LDS: every load
+    batch of the product kernel in use), with L = N/2 and an odd N with L < K, against the
+    tier-B oracle, in a batch with three short series."""
+    f, _, _ = inputs.c3_series(7, N=N)
+    others = [inputs.c3_series(t, N=900)[0] for t in range(3)]
+    b = ssa.Batch(n_max=20480, k_max=16, max_series=8)
+    say(f"longest series: N={N} L={L}: solving in a batch of four")
+    out = b.solve([f] + others, [L] + [450] * 3, [8] * 4)
+    info = out["info"].cpu().numpy()
+    say(f"longest series: N={N} steps={info[0, 0]} conv={info[0, 1]}")
+    rep = compare_one(f, L, 8, out["sigma"][0], out["U"][0], out["V"][0], out["recon"][0], dense=False)
+    say(f"   {rep}")
+    for s in range(1, 4):
+        rep = compare_one(others[s - 1], 450, 8, out["sigma"][s], out["U"][s], out["V"][s], out["recon"][s])
+        say(f"   short series {s}: {rep}")
+
+
 def test_batch_full_many_series_workload(ssa):
     """The many-series workload exactly as the benchmark launches it: 4096 series (N uniform in
     [2000, 20000], L = N/2, k = 16) in one batch.  Three sampled series against the oracle
