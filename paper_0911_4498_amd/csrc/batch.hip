@@ -829,10 +829,19 @@ __global__ __launch_bounds__(kThreads) void kb_ritz(BatchArgs a) {
 // Elementary series of every triple (Algorithm 4): g = sigma (u * v) / cnt,
 // the linear convolution by a packed-real FFT; the spectrum of u waits in the
 // region's scratch while v is transformed.  Entries whose antidiagonal has at
-// most kEdge terms are summed directly (FP64 sums of exact FP32 products).
+// most kEdge terms are summed directly (FP64 sums of exact FP32 products, in
+// ascending order of the u index).  When L and K both exceed kEdge those entries
+// sit at the two ends of the series and read only the first and last kEdge
+// entries of u and v, which are staged in LDS once the product is done.
+struct HankelLds {
+    Lds fft;
+    float edge[4][kEdge];  // u head, u tail, v head, v tail
+};
+
 __global__ __launch_bounds__(kFftThreads) void kb_hankel(BatchArgs a) {
     extern __shared__ char lds[];
-    Lds* sh = reinterpret_cast<Lds*>(lds);
+    HankelLds* hl = reinterpret_cast<HankelLds*>(lds);
+    Lds* sh = &hl->fft;
     const int tid = threadIdx.x, s = a.list ? a.list[blockIdx.x] : (int)blockIdx.x;
     const Ser q = load_series(a, s);
     const BSeries& b = a.tab[s];
@@ -843,6 +852,7 @@ __global__ __launch_bounds__(kFftThreads) void kb_hankel(BatchArgs a) {
     const long long N = q.N, L = b.L, K = N - b.L + 1;
     const int Mp = q.Mp;
     const double M = 2.0 * Mp;
+    const bool staged = L > kEdge && K > kEdge;  // (uniform)
     for (int i = 0; i < q.k; ++i) {
         const double sigma = b.sigma[i];
         const float* u = b.U + (long long)i * L;
@@ -894,15 +904,40 @@ __global__ __launch_bounds__(kFftThreads) void kb_hankel(BatchArgs a) {
         }
         __syncthreads();
         fft<1>(sh, q, tid);
+        if (staged) {
+            float ev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if ((tid & ~63) < kEdge) {  // (whole waves past the edges skip the loads)
+                const int t = min(tid, kEdge - 1);
+                ev[0] = u[t];
+                ev[1] = u[L - kEdge + t];
+                ev[2] = v[t];
+                ev[3] = v[K - kEdge + t];
+            }
+            if (tid < kEdge) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) hl->edge[e][tid] = ev[e];
+            }
+            __syncthreads();
+        }
         for (long long m = tid; m < N; m += kFftThreads) {
             long long cnt = m + 1;
             if (L < cnt) cnt = L;
             if (K < cnt) cnt = K;
             if (N - m < cnt) cnt = N - m;
             if (cnt <= kEdge) {
-                const long long a0 = m - K + 1 > 0 ? m - K + 1 : 0, a1 = m < L - 1 ? m : L - 1;
                 double acc = 0.0;
-                for (long long t = a0; t <= a1; ++t) acc += (double)u[t] * (double)v[m - t];
+                if (staged && m < kEdge) {  // u[0 .. m] against v[m .. 0]
+                    const int mm = (int)m;
+                    for (int t = 0; t <= mm; ++t) acc += (double)hl->edge[0][t] * (double)hl->edge[2][mm - t];
+                } else if (staged) {  // u[m - K + 1 .. L - 1] (the last cnt of u) against v[K - 1 .. m - L + 1]
+                    // u[L - kEdge + j] = tail[j]; its partner v[m - L + kEdge - j] = vtail[2 kEdge - cnt - 1 - j]
+                    const int c = (int)cnt;
+                    for (int j = kEdge - c; j < kEdge; ++j)
+                        acc += (double)hl->edge[1][j] * (double)hl->edge[3][2 * kEdge - c - 1 - j];
+                } else {
+                    const long long a0 = m - K + 1 > 0 ? m - K + 1 : 0, a1 = m < L - 1 ? m : L - 1;
+                    for (long long t = a0; t <= a1; ++t) acc += (double)u[t] * (double)v[m - t];
+                }
                 out[m] = (float)(sigma * acc / (double)cnt);
             } else {
                 out[m] = getr(buf, m) / (float)cnt;
@@ -916,20 +951,20 @@ __global__ __launch_bounds__(kFftThreads) void kb_hankel(BatchArgs a) {
 
 }  // namespace batch
 
-static hipError_t allow_lds(const void* f) {
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(batch::Lds));
+static hipError_t allow_lds(const void* f, size_t bytes = sizeof(batch::Lds)) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 static hipError_t batch_attributes() {
     static hipError_t err = [] {
         hipError_t e = hipSuccess;
         for (const void* f : {reinterpret_cast<const void*>(batch::kb_init), reinterpret_cast<const void*>(batch::kb_conv),
-                              reinterpret_cast<const void*>(batch::kb_check), reinterpret_cast<const void*>(batch::kb_ritz),
-                              reinterpret_cast<const void*>(batch::kb_hankel)}) {
+                              reinterpret_cast<const void*>(batch::kb_check), reinterpret_cast<const void*>(batch::kb_ritz)}) {
             const hipError_t e2 = allow_lds(f);
             if (e2 != hipSuccess) e = e2;
         }
-        return e;
+        const hipError_t e3 = allow_lds(reinterpret_cast<const void*>(batch::kb_hankel), sizeof(batch::HankelLds));
+        return e != hipSuccess ? e : e3;
     }();
     return err;
 }
@@ -963,7 +998,7 @@ hipError_t launch_batch_ritz(const BatchArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_batch_hankel(const BatchArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(batch::kb_hankel, dim3(a.nseries), dim3(batch::kFftThreads), sizeof(batch::Lds), s, a);
+    hipLaunchKernelGGL(batch::kb_hankel, dim3(a.nseries), dim3(batch::kFftThreads), sizeof(batch::HankelLds), s, a);
     return hipGetLastError();
 }
 
